@@ -1,0 +1,239 @@
+"""The QFlow method (singles and doubles, N=1 Trotter) in plain FP64.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Steps, in the order the paper states them:
+
+* Reference quantities of the closed-shell determinant Phi that fills the
+  occupied orbitals O = {0..N_o-1} ("Numerical Implementation", first index
+  paragraph): Fock matrix f, reference energy E_ref, orbital energies eps=diag f.
+* sigma = T - T^dagger with T = T1 + T2 over singles and doubles (Eq. (1)),
+  split per active space into sigma_int(i) (amplitudes whose indices all lie in
+  the space) and sigma_ext(i) = sigma - sigma_int(i) (Eq. (3)).
+* The downfolded Hamiltonian of Eq. (6) at N=1, where G = exp(sigma_ext)
+  (Eq. (7)).  Its similarity transform is expanded as
+      Hbar = H + [H_N, sigma_ext]_2 + 1/2 [[F_N, sigma_ext]_2, sigma_ext]_2
+  (commutators truncated to 0-, 1- and 2-body parts; F_N the normal-ordered
+  Fock operator), then restricted to the orbitals of the space: the projector
+  P + Q_int(i) keeps Phi and every determinant excited inside the space.
+* E(i) is the lowest eigenvalue of that active-space matrix (Eq. (5) with the
+  exact active-space ground state standing in for the UCCSD-VQE solver), with
+  the eigenvector's reference coefficient made positive.
+* The eigenvector is mapped back to amplitudes by intermediate-normalised
+  cluster analysis: T1 = C1, T2 = C2 - T1^2/2 (in spin orbitals).
+* Each amplitude is written by the first space in Delta-epsilon order that
+  reaches it (ownership; amplitudes no space reaches take a residual Jacobi
+  step t <- t - R/Delta with R = <X|Hbar(sigma)|Phi>).
+* One macro-iteration is a Jacobi sweep: every space reads the pool as it was
+  at the end of the previous sweep (the barrier at the end of each sweep).
+* The flow energy is the unweighted mean of E(i) over the spaces.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import so
+from .cas import basis
+
+
+# ----------------------------------------------------------------------------
+# reference quantities
+# ----------------------------------------------------------------------------
+
+def reference(h: np.ndarray, eri: np.ndarray, o: int):
+    """f_pq = h_pq + sum_k [2(pq|kk) - (pk|kq)], E_ref = sum_k (h_kk + f_kk),
+    eps_p = f_pp (k runs over the occupied orbitals of Phi)."""
+    k = np.arange(o)
+    f = h + 2.0 * eri[:, :, k, k].sum(axis=2) - eri[:, k, k, :].sum(axis=1)
+    e_ref = float(np.sum(h[k, k] + f[k, k]))
+    return f, e_ref, np.diag(f).copy()
+
+
+def mp2_guess(f, eri, o):
+    """t_ij^ab = (ia|jb)/(e_i+e_j-e_a-e_b), t_i^a = f_ia/(e_i-e_a)."""
+    e = np.diag(f)
+    eo, ev = e[:o], e[o:]
+    t1 = f[:o, o:] / (eo[:, None] - ev[None, :])
+    iajb = eri[:o, o:, :o, o:]                    # (ia|jb) as [i,a,j,b]
+    t2 = iajb.transpose(0, 2, 1, 3) / (eo[:, None, None, None] + eo[None, :, None, None]
+                                        - ev[None, None, :, None] - ev[None, None, None, :])
+    return t1, t2
+
+
+class Problem:
+    def __init__(self, h, eri, o):
+        self.h, self.eri, self.o = h, eri, o
+        self.n = h.shape[0]
+        self.v = self.n - o
+        self.f, self.e_ref, self.eps = reference(h, eri, o)
+        self.bl = so.Blocks(self.n, o)
+        self.H = so.Hamiltonian(self.f, eri, self.e_ref)
+        self.HN = so.Hamiltonian(self.f, eri, 0.0)
+        self.F = so.Fock(self.f)
+
+
+class Sum(so.Op):
+    def __init__(self, terms):
+        self.terms = terms
+
+    def zero(self):
+        return sum(w * A.zero() for w, A in self.terms)
+
+    def one(self, I, J):
+        return sum(w * A.one(I, J) for w, A in self.terms)
+
+    def two(self, I, J, K, L):
+        return sum(w * A.two(I, J, K, L) for w, A in self.terms)
+
+
+def hbar(pb: Problem, t1, t2, mask=None) -> so.Op:
+    """H + [H_N, s]_2 + 1/2 [[F_N, s]_2, s]_2 with s = sigma (mask None) or
+    s = sigma_ext of the space whose spatial orbitals are `mask`."""
+    S = so.Cluster(pb.bl, t1, t2, mask)
+    Y = so.Commutator(pb.F, S, pb.bl)
+    return Sum([(1.0, pb.H), (1.0, so.Commutator(pb.HN, S, pb.bl)),
+                (0.5, so.Commutator(Y, S, pb.bl))])
+
+
+def spin_orbitals(orbs):
+    return np.array([2 * P + s for P in orbs for s in (0, 1)], dtype=np.int64)
+
+
+# ----------------------------------------------------------------------------
+# per active space
+# ----------------------------------------------------------------------------
+
+def heff(pb: Problem, t1, t2, orbs):
+    """Normal-ordered (x0, x1, x2) of Eq. (6) at N=1 for the space `orbs`
+    (sorted spatial orbitals, occupied first), in its local spin orbitals."""
+    Hb = hbar(pb, t1, t2, mask=orbs)
+    return so.restrict(Hb, spin_orbitals(orbs), pb.bl)
+
+
+def heff_spatial(x0, x1, x2):
+    """Spin-free view of a singlet operator restricted to a space: x0, the
+    alpha-alpha one-body block and the alpha-beta two-body block
+    x2[P alpha, Q beta, R alpha, S beta]."""
+    return x0, x1[0::2, 0::2].copy(), x2[0::2, 1::2, 0::2, 1::2].copy()
+
+
+def cas_matrix(x0, x1, x2, n_occ):
+    na = x1.shape[0] // 2
+    return basis(n_occ, na).matrix(x0, x1, x2)
+
+
+def solve_cas(x0, x1, x2, n_occ):
+    """Lowest eigenpair of the active-space matrix; reference weight > 0."""
+    B = basis(n_occ, x1.shape[0] // 2)
+    Hc = B.matrix(x0, x1, x2)
+    w, U = np.linalg.eigh(Hc)
+    c = U[:, 0].copy()
+    if c[B.iref] < 0:
+        c = -c
+    return float(w[0]), c, Hc
+
+
+def cluster_analysis(c, n_occ, n_vir):
+    """Intermediate-normalised cluster amplitudes of c (local indices).
+
+    C_i^a = <Phi| i+ a |c>/c_Phi and C_ij^ab = <Phi| i+ j+ b a |c>/c_Phi are the
+    coefficients of a+ i Phi and a+ b+ j i Phi; T1 = C1 and
+    T2 = C2 - (C_i^a C_j^b - C_i^b C_j^a).  Returns spatial t1[i,a] (alpha)
+    and t2[i,j,a,b] (i,a alpha; j,b beta)."""
+    na = n_occ + n_vir
+    B = basis(n_occ, na)
+    c0 = c[B.iref]
+    occ = [2 * P + s for P in range(n_occ) for s in (0, 1)]
+    vir = [2 * P + s for P in range(n_occ, na) for s in (0, 1)]
+    M = 2 * na
+    C1 = np.zeros((M, M))
+    for i in occ:
+        for a in vir:
+            C1[i, a] = B.overlap_string([(i, 1), (a, 0)], c) / c0
+    t1 = np.zeros((n_occ, n_vir))
+    t2 = np.zeros((n_occ, n_occ, n_vir, n_vir))
+    for I in range(n_occ):
+        for A in range(n_vir):
+            t1[I, A] = C1[2 * I, 2 * (n_occ + A)]
+    for I in range(n_occ):
+        for J in range(n_occ):
+            for A in range(n_vir):
+                for Bv in range(n_vir):
+                    i, j = 2 * I, 2 * J + 1
+                    a, b = 2 * (n_occ + A), 2 * (n_occ + Bv) + 1
+                    c2 = B.overlap_string([(i, 1), (j, 1), (b, 0), (a, 0)], c) / c0
+                    t2[I, J, A, Bv] = c2 - (C1[i, a] * C1[j, b] - C1[i, b] * C1[j, a])
+    return t1, t2
+
+
+def solve_space(pb: Problem, t1, t2, orbs, n_occ):
+    x0, x1, x2 = heff(pb, t1, t2, orbs)
+    E, c, _ = solve_cas(x0, x1, x2, n_occ)
+    B = basis(n_occ, len(orbs))
+    c0 = c[B.iref]
+    lt1, lt2 = cluster_analysis(c, n_occ, len(orbs) - n_occ)
+    return dict(E=E, c0=c0, t1=lt1, t2=lt2, x=(x0, x1, x2), c=c)
+
+
+# ----------------------------------------------------------------------------
+# global residual
+# ----------------------------------------------------------------------------
+
+def residual(pb: Problem, t1, t2, occ=None, vir=None):
+    """R1[i,a] = <Phi_i^a|Hbar(sigma)|Phi> and
+    R2[i,j,a,b] = <Phi_{i alpha j beta}^{a alpha b beta}|Hbar(sigma)|Phi>,
+    E0 = <Phi|Hbar(sigma)|Phi>.  occ/vir optionally restrict the output to
+    subsets of spatial occupied / virtual orbitals (absolute indices)."""
+    o, n = pb.o, pb.n
+    occ = np.arange(o) if occ is None else np.asarray(occ)
+    vir = np.arange(o, n) if vir is None else np.asarray(vir)
+    Hb = hbar(pb, t1, t2)
+    Ia, Ib = ("o", 2 * occ), ("o", 2 * occ + 1)
+    Aa, Ab = ("v", 2 * vir), ("v", 2 * vir + 1)
+    R1 = Hb.one(Aa, Ia).T.copy()
+    R2 = Hb.two(Aa, Ab, Ia, Ib).transpose(2, 3, 0, 1).copy()
+    return R1, R2, Hb.zero()
+
+
+# ----------------------------------------------------------------------------
+# one macro-iteration
+# ----------------------------------------------------------------------------
+
+REF_WEIGHT_MIN = 0.1
+
+
+def flow_step(pb: Problem, t1, t2, spaces, owner1, owner2, unowned="residual"):
+    """One Jacobi macro-iteration.  spaces: list of (occ tuple, vir tuple) of
+    absolute spatial orbitals, in Delta-epsilon order.  owner1[i,a] and
+    owner2[i,j,a,b] hold the owning space index or -1.  Returns new (t1, t2),
+    per-space energies, the mean energy and per-space solutions."""
+    o = pb.o
+    sols = []
+    for (occ, vir) in spaces:
+        orbs = tuple(occ) + tuple(vir)
+        sols.append(solve_space(pb, t1, t2, orbs, len(occ)))
+    E = np.array([s["E"] for s in sols])
+    nt1, nt2 = t1.copy(), t2.copy()
+    if unowned == "residual" and (np.any(owner1 < 0) or np.any(owner2 < 0)):
+        R1, R2, _ = residual(pb, t1, t2)
+        e = pb.eps
+        d1 = e[o:][None, :] - e[:o][:, None]
+        d2 = (e[o:][None, None, :, None] + e[o:][None, None, None, :]
+              - e[:o][:, None, None, None] - e[:o][None, :, None, None])
+        nt1 = np.where(owner1 < 0, t1 - R1 / d1, nt1)
+        nt2 = np.where(owner2 < 0, t2 - R2 / d2, nt2)
+    for k, (occ, vir) in enumerate(spaces):
+        s = sols[k]
+        if abs(s["c0"]) < REF_WEIGHT_MIN:
+            continue
+        for I, i in enumerate(occ):
+            for A, a in enumerate(vir):
+                if owner1[i, a - o] == k:
+                    nt1[i, a - o] = s["t1"][I, A]
+        for I, i in enumerate(occ):
+            for J, j in enumerate(occ):
+                for A, a in enumerate(vir):
+                    for B, b in enumerate(vir):
+                        if owner2[i, j, a - o, b - o] == k:
+                            nt2[i, j, a - o, b - o] = s["t2"][I, J, A, B]
+    return nt1, nt2, E, float(np.mean(E)), sols
