@@ -1,0 +1,185 @@
+/*
+ * qflow.h -- C ABI of libqflow, the GPU hot path of singles-and-doubles
+ * Quantum Flow (QFlow) with N=1 Trotter downfolding, for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Conventions shared by every call
+ *   - Orbitals are spatial, 0-based, occupied first: O = {0..n_occ-1},
+ *     V = {n_occ..n_orb-1} (the index sets of the paper's "Numerical
+ *     Implementation" section).  o = n_occ, v = n_orb - n_occ.
+ *   - Arrays are row-major FP64 unless stated.  t1 is [o][v] (t_i^a with
+ *     a relative to n_occ), t2 is [o][o][v][v] with t2[i][j][a][b] =
+ *     t2[j][i][b][a]; they define sigma = T - T^dagger, T = sum t1 E_ai +
+ *     1/2 sum t2 E_ai E_bj (the anti-Hermitian operator of Eq. (1)).
+ *   - "device" pointers are HIP device memory owned by the caller (for
+ *     example a torch tensor's data_ptr()); "host" pointers are ordinary
+ *     host memory.  The library never frees caller memory and keeps no
+ *     caller pointer after a call returns.
+ *   - Calls enqueue work on the context's stream and return; only
+ *     qflow_load_integrals and qflow_flow_step synchronise that stream.
+ *   - Every call returns a qflow_status.  Argument errors are detected
+ *     before any work is enqueued; the message is available from
+ *     qflow_last_error.  Device errors surface as QFLOW_E_DEVICE at the next
+ *     synchronising call.  Per-space failures never fail a batch: they are
+ *     reported in the status arrays.  No call exits, aborts or throws.
+ *   - A context is not thread safe; use one context per stream.
+ */
+#ifndef QFLOW_H
+#define QFLOW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qflow_ctx qflow_ctx;
+
+/* One active space (Eq. (3) partition): n_o occupied then n_v virtual
+ * absolute orbital indices in orb[], each group ascending.  Supported sizes:
+ * n_o == n_v, 2 <= n_o <= 4 (at most 4900 determinants). */
+typedef struct {
+  int32_t n_o, n_v;
+  int32_t orb[8];
+} qflow_space;
+
+typedef enum {
+  QFLOW_OK = 0,
+  QFLOW_E_INVALID_ARG = -1,
+  QFLOW_E_SYMMETRY = -2,      /* integrals not real 8-fold symmetric / not finite */
+  QFLOW_E_OOM = -3,
+  QFLOW_E_DEVICE = -4,
+  QFLOW_E_NOT_CONVERGED = -5, /* per-space status: eigensolver hit max_iter */
+  QFLOW_E_REF_WEIGHT = -6,    /* per-space status: |c_Phi| < 0.1 */
+  QFLOW_E_STATE = -7,         /* call order violated (e.g. no integrals loaded) */
+  QFLOW_E_UNSUPPORTED = -8
+} qflow_status;
+
+/* Arithmetic of the residual contractions (ladder intermediates). */
+typedef enum { QFLOW_FP64 = 0, QFLOW_FP32 = 1, QFLOW_BF16X3 = 2 } qflow_precision;
+
+/* flow_step flags: low 4 bits = qflow_precision. */
+enum {
+  QFLOW_UNOWNED_FROZEN = 1 << 4 /* amplitudes no space owns keep their value */
+};
+
+/* Create a context on HIP device `device`; hip_stream is a hipStream_t to
+ * enqueue on, or NULL for a stream the context creates.  *out is NULL on
+ * failure. */
+int qflow_create(qflow_ctx** out, int device, void* hip_stream);
+
+/* Release every resource of ctx; NULL is accepted.  Idempotent per pointer. */
+int qflow_destroy(qflow_ctx* ctx);
+
+/* Text of the last error on ctx (never NULL; "" if none). */
+const char* qflow_last_error(const qflow_ctx* ctx);
+
+/* Load the Hamiltonian H of Eq. (1): h[n][n] (device) and chemist-order
+ * two-electron integrals eri[n][n][n][n] = (pq|rs) (device).  Checks that h
+ * is symmetric and eri 8-fold symmetric to sym_tol (absolute) and finite
+ * (QFLOW_E_SYMMETRY otherwise), then builds the Fock matrix of Phi
+ * f_pq = h_pq + sum_k [2(pq|kk) - (pk|kq)], E_ref = sum_k (h_kk + f_kk),
+ * eps_p = f_pp, and the device layouts of the integrals.  n_orb <= 128,
+ * 1 <= n_occ < n_orb.  Synchronises the stream. */
+int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const double* h,
+                         const double* eri, double sym_tol);
+
+/* Reference quantities of the loaded Hamiltonian: *e_ref (host), eps[n_orb]
+ * (host, may be NULL), fock[n_orb*n_orb] (host, may be NULL). */
+int qflow_reference(qflow_ctx* ctx, double* e_ref, double* eps, double* fock);
+
+/* MP2 first-order amplitudes t2 = (ia|jb)/(e_i+e_j-e_a-e_b) and
+ * t1 = f_ia/(e_i-e_a) into t1, t2 (device). */
+int qflow_mp2_guess(qflow_ctx* ctx, double* t1, double* t2);
+
+/* Global residual of the transformed Hamiltonian
+ *   Hbar(sigma) = H + [H_N, sigma]_2 + 1/2 [[F_N, sigma]_2, sigma]_2
+ * (the N=1 similarity transform of Eqs. (6)-(7) with every amplitude
+ * external, commutators kept to two-body rank):
+ *   r1[i][a] = <Phi_i^a|Hbar|Phi>, r2[i][j][a][b] = <Phi_{i alpha j beta}^{a alpha b beta}|Hbar|Phi>,
+ *   *e0 = <Phi|Hbar|Phi>.
+ * t1, t2, r1, r2, e0 are device pointers; precision selects the arithmetic
+ * of the ladder contractions. */
+int qflow_residual(qflow_ctx* ctx, const double* t1, const double* t2, double* r1, double* r2,
+                   double* e0, int precision);
+
+/* Number of doubles the CAS-form Hamiltonian of one space occupies:
+ * 1 + na^2 + na^4 with na = n_o + n_v. */
+int64_t qflow_heff_size(const qflow_space* space);
+
+/* Downfolded Hamiltonian of every space (Eq. (6) at N=1, G = exp(sigma_ext),
+ * sigma_ext = sigma minus the amplitudes whose indices all lie in the space,
+ * Eq. (3)), restricted to the space's orbitals and written relative to the
+ * empty active space: at heff + heff_off[k] (device buffer; heff_off host,
+ * K+1 entries, each block qflow_heff_size long) the layout is
+ *   [Ec, h[na][na], g[na][na][na][na]] with g in chemist order (pq|rs),
+ * local orbital order = spaces[k].orb.  spaces is a host array. */
+int qflow_build_heff(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const double* t1,
+                     const double* t2, double* heff, const int64_t* heff_off, int precision);
+
+/* Number of doubles of the local amplitudes of one space:
+ * n_o*n_v + (n_o*n_v)^2. */
+int64_t qflow_amp_size(const qflow_space* space);
+
+/* Lowest eigenpair of every space's CAS matrix (determinants with n_o alpha
+ * and n_o beta electrons in the space's orbitals: the span of P + Q_int of
+ * Eq. (6)), by Davidson iteration in FP64 from the reference determinant.
+ * Outputs (device): energy[K] (the E(i) of Eq. (5), eigenvalue reading),
+ * c0[K] (reference coefficient of the normalised eigenvector, made >= 0),
+ * amp + amp_off[k] (amp_off host, K+1 entries): the intermediate-normalised
+ * cluster amplitudes t1[n_o][n_v] then t2[n_o][n_o][n_v][n_v] (local
+ * indices; t2[i][j][a][b] pairs i,a alpha with j,b beta), iters[K],
+ * status[K] (QFLOW_OK, QFLOW_E_NOT_CONVERGED, QFLOW_E_REF_WEIGHT).
+ * Converged when the residual norm of the normalised Ritz vector is < tol. */
+int qflow_solve_active_batch(qflow_ctx* ctx, int32_t K, const qflow_space* spaces,
+                             const double* heff, const int64_t* heff_off, double* energy,
+                             double* c0, double* amp, const int64_t* amp_off, int32_t* iters,
+                             int32_t* status, double tol, int32_t max_iter);
+
+/* One QFlow macro-iteration (a Jacobi sweep: every space reads the pool as
+ * it was on entry, then the pool is updated once, as with the end-of-sweep
+ * barrier of the parallel implementation):
+ *   1. build every space's downfolded Hamiltonian from (t1, t2),
+ *   2. solve every space,
+ *   3. write each amplitude from the space that owns it (owner1[o][v],
+ *      owner2[o][o][v][v] device int32 arrays, -1 = unowned, owner2
+ *      pair-symmetric); spaces whose status is not QFLOW_OK leave their
+ *      amplitudes unchanged,
+ *   4. unowned amplitudes take t <- t - R/Delta (Delta = eps_a - eps_i,
+ *      eps_a + eps_b - eps_i - eps_j) unless QFLOW_UNOWNED_FROZEN.
+ * t1, t2 (device) are updated in place.  energy[K] (device) receives E(i);
+ * *e_mean (host) = mean_i E(i), *max_dt (host) = max |t_new - t_old|.
+ * Synchronises the stream. */
+int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const int32_t* owner1,
+                    const int32_t* owner2, double* t1, double* t2, double* energy, double* e_mean,
+                    double* max_dt, int32_t flags);
+
+/* Per-stage device times of the last qflow_flow_step in milliseconds, in
+ * the order: intermediates (Yg), ladder contractions, residual, build_heff,
+ * solve, update.  n is the capacity of ms (host). Returns the count written. */
+int qflow_last_timings(const qflow_ctx* ctx, float* ms, int n);
+
+/* Algorithm 1 (coverage-driven active-space sampling), host only.
+ * Draws (Otilde, Vtilde) of sizes (no, nv) from {0..No-1} and
+ * {No..No+Nv-1} without replacement by partial Fisher-Yates shuffles driven
+ * by the uniforms u[0..n_u) (one per swap), discards candidates that cover
+ * no remaining (o1<o2, v1<v2) tuple, stops when every tuple is covered or
+ * after `cap` accepted spaces (cap <= 0: no cap), and sorts the result by
+ * Delta eps = sum eps_v - sum eps_o ascending (stable; ties by orbital
+ * lists).  eps: host, No+Nv entries.  out: host, capacity `max_out`.
+ * *K_out = spaces written, *used = uniforms consumed.  QFLOW_E_INVALID_ARG
+ * if the uniforms or the output capacity run out. */
+int qflow_sample_spaces(int32_t No, int32_t Nv, int32_t no, int32_t nv, const double* eps,
+                        const double* u, int64_t n_u, int32_t cap, qflow_space* out,
+                        double* delta_eps, int32_t max_out, int32_t* K_out, int64_t* used);
+
+/* Ownership (host): owner1[i][a], owner2[i][j][a][b] = index of the first
+ * space in list order that reaches the amplitude, or -1. */
+int qflow_build_owners(int32_t No, int32_t Nv, int32_t K, const qflow_space* spaces,
+                       int32_t* owner1, int32_t* owner2);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QFLOW_H */

@@ -117,6 +117,24 @@ def heff_spatial(x0, x1, x2):
     return x0, x1[0::2, 0::2].copy(), x2[0::2, 1::2, 0::2, 1::2].copy()
 
 
+def cas_integrals(x0, x1, x2, n_occ):
+    """The space's operator relative to the empty active space,
+    Ec + sum h_pq p+ q + 1/4 sum g_pqrs p+ q+ s r (spin orbitals), from its
+    normal-ordered form: with k, l over the active occupied spin orbitals,
+    {p+ q} = p+ q - d_pq n_p and the two-body contractions give
+        h_pq = x1_pq - sum_k x2_pkqk,
+        Ec   = x0 - sum_k x1_kk + 1/2 sum_kl x2_klkl.
+    Returns the spin-free (Ec, h[P,Q], g[P,Q,R,S] = (PQ|RS)) with
+    h = alpha-alpha block and (PQ|RS) = <P alpha R beta | Q alpha S beta>."""
+    occ = np.arange(2 * n_occ)
+    h = x1 - np.einsum("pkqk->pq", x2[:, occ][:, :, :, occ])
+    ec = x0 - np.trace(x1[np.ix_(occ, occ)]) + 0.5 * np.einsum(
+        "klkl->", x2[np.ix_(occ, occ, occ, occ)])
+    hs = h[0::2, 0::2]
+    g = x2[0::2, 1::2, 0::2, 1::2].transpose(0, 2, 1, 3)
+    return float(ec), hs.copy(), g.copy()
+
+
 def cas_matrix(x0, x1, x2, n_occ):
     na = x1.shape[0] // 2
     return basis(n_occ, na).matrix(x0, x1, x2)

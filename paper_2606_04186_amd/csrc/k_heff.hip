@@ -1,0 +1,162 @@
+// Per-space downfolded Hamiltonians in CAS form.
+//
+// For space A with tau = the amplitudes inside A and s = sigma - tau,
+//   Hbar|_A = H + [H,sigma] - [H,tau]
+//           + 1/2 ([Yg,sigma] - [Yg,tau] - [Ft,sigma] + [Ft,tau]),
+// Yg = [F,sigma], Ft = [F,tau].  Three kernels accumulate the H, Yg and Ft
+// groups of terms into the normal-ordered block (x0, x1[na^2], x2[na^4]) of
+// each space, held in the output slot itself; a fourth rewrites the slot in
+// CAS form (Ec, h, g) relative to the empty active space.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "kcommon.h"
+#include "kernels.h"
+#include "qflow_cas.h"
+#include "qflow_eval.h"
+
+namespace qf {
+
+namespace {
+
+// Active-set description shared by the block.
+__device__ void load_active(const SpaceDev& sp, Active& A) {
+  for (int p = threadIdx.x; p < kMaxOrb; p += blockDim.x) A.pos[p] = -1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    A.na = sp.na;
+    A.nocc = sp.nocc;
+    for (int a = 0; a < sp.na; ++a) {
+      A.orb[a] = sp.orb[a];
+      A.pos[sp.orb[a]] = (int8_t)a;
+    }
+  }
+  __syncthreads();
+}
+
+// Slot layout while accumulating: [x0, x1 (na^2), x2 (na^4)].
+// part 0: H + [H,sigma] - [H,tau]         (initialises the slot)
+// part 1: + 1/2 ([Yg,sigma] - [Yg,tau])
+// part 2: + 1/2 ([Ft,tau] - [Ft,sigma])
+template <int PART>
+__global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __restrict__ scal,
+                                                   const SpaceDev* __restrict__ spaces,
+                                                   const int64_t* __restrict__ heff_off,
+                                                   double* heff) {
+  __shared__ Active A;
+  const int k = blockIdx.x;
+  const SpaceDev sp = spaces[k];
+  load_active(sp, A);
+  const int na = sp.na, n = g.n, o = g.o, v = n - o;
+  const int n2 = na * na, n4 = n2 * n2;
+  double* slot = heff + heff_off[k];
+  const Sigma s{g.t1, g.t2, n, o, v};
+  const Tau tau{s, &A};
+  const int task = blockIdx.y * blockDim.x + threadIdx.x;
+  if (task > n4 + n2) return;
+  int p = 0, q = 0, r = 0, t = 0;
+  if (task < n4) {
+    const int d = task % na, c = task / na % na, b = task / n2 % na, a = task / (n2 * na);
+    p = A.orb[a];
+    q = A.orb[b];
+    r = A.orb[c];
+    t = A.orb[d];
+  } else if (task < n4 + n2) {
+    const int e = task - n4;
+    p = A.orb[e / na];
+    q = A.orb[e % na];
+  }
+  double* dst = (task < n4) ? slot + 1 + n2 + task : (task < n4 + n2 ? slot + 1 + (task - n4) : slot);
+  if constexpr (PART == 0) {
+    const DenseOp H{g.f, g.V, g.L, n, o};
+    const auto cs = make_comm(H, s, n, o);
+    const auto ct = make_comm(H, tau, n, o);
+    double x;
+    if (task < n4)
+      x = H.two(p, q, r, t) + cs.c2(p, q, r, t) - ct.c2(p, q, r, t);
+    else if (task < n4 + n2)
+      x = H.one(p, q) + cs.c1(p, q) - ct.c1(p, q);
+    else
+      x = scal[3] + scal[0] - ct.c0();
+    *dst = x;
+  } else if constexpr (PART == 1) {
+    const DenseOp Y{g.y1, g.y2, g.LY, n, o};
+    const auto cs = make_comm(Y, s, n, o);
+    const auto ct = make_comm(Y, tau, n, o);
+    double x;
+    if (task < n4)
+      x = cs.c2(p, q, r, t) - ct.c2(p, q, r, t);
+    else if (task < n4 + n2)
+      x = cs.c1(p, q) - ct.c1(p, q);
+    else
+      x = scal[1] - ct.c0();
+    *dst += 0.5 * x;
+  } else {
+    const FtauOp F{g.f, tau, n, o};
+    const auto cs = make_comm(F, s, n, o);
+    const auto ct = make_comm(F, tau, n, o);
+    double x;
+    if (task < n4)
+      x = ct.c2(p, q, r, t) - cs.c2(p, q, r, t);
+    else if (task < n4 + n2)
+      x = ct.c1(p, q) - cs.c1(p, q);
+    else
+      x = ct.c0() - cs.c0();
+    *dst += 0.5 * x;
+  }
+}
+
+// Rewrite each slot from normal order to CAS form:
+//   Ec = x0 - 2 sum_k x1_kk + sum_kl (2 x2_klkl - x2_kllk)
+//   h_pq = x1_pq - sum_k (2 x2_pkqk - x2_pkkq),  g(pq|rs) = x2_prqs
+__global__ __launch_bounds__(256) void k_heff_cas(const SpaceDev* __restrict__ spaces,
+                                                  const int64_t* __restrict__ heff_off,
+                                                  double* heff) {
+  extern __shared__ double sm[];
+  const int k = blockIdx.x;
+  const SpaceDev sp = spaces[k];
+  const int na = sp.na, ne = sp.nocc, n2 = na * na, n4 = n2 * n2;
+  double* slot = heff + heff_off[k];
+  for (int e = threadIdx.x; e < 1 + n2 + n4; e += blockDim.x) sm[e] = slot[e];
+  __syncthreads();
+  const double* x1 = sm + 1;
+  const double* x2 = sm + 1 + n2;
+  for (int e = threadIdx.x; e < n4; e += blockDim.x) {
+    const int s = e % na, r = e / na % na, q = e / n2 % na, p = e / (n2 * na);
+    slot[1 + n2 + e] = x2[((p * na + r) * na + q) * na + s];
+  }
+  for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+    const int p = e / na, q = e % na;
+    double h = x1[e];
+    for (int kk = 0; kk < ne; ++kk)
+      h -= 2.0 * x2[((p * na + kk) * na + q) * na + kk] - x2[((p * na + kk) * na + kk) * na + q];
+    slot[1 + e] = h;
+  }
+  if (threadIdx.x == 0) {
+    double ec = sm[0];
+    for (int kk = 0; kk < ne; ++kk) ec -= 2.0 * x1[kk * na + kk];
+    for (int kk = 0; kk < ne; ++kk)
+      for (int l = 0; l < ne; ++l)
+        ec += 2.0 * x2[((kk * na + l) * na + kk) * na + l] - x2[((kk * na + l) * na + l) * na + kk];
+    slot[0] = ec;
+  }
+}
+
+}  // namespace
+
+void launch_heff(const double* f, const double* V, const double* y1, const double* y2,
+                 const double* L, const double* LY, const double* t1, const double* t2, int n,
+                 int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
+                 int K, int na_max, double* heff, hipStream_t st) {
+  GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o};
+  const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
+  dim3 grid(K, (tasks + kBlock - 1) / kBlock);
+  k_heff_part<0><<<grid, kBlock, 0, st>>>(g, scal, spaces, heff_off, heff);
+  k_heff_part<1><<<grid, kBlock, 0, st>>>(g, scal, spaces, heff_off, heff);
+  k_heff_part<2><<<grid, kBlock, 0, st>>>(g, scal, spaces, heff_off, heff);
+  const size_t lds = (size_t)tasks * sizeof(double);
+  k_heff_cas<<<K, kBlock, lds, st>>>(spaces, heff_off, heff);
+}
+
+}  // namespace qf

@@ -1,0 +1,267 @@
+// Integral preparation, the [F,sigma] intermediate and the pool update.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "kcommon.h"
+#include "kernels.h"
+#include "qflow_cas.h"
+#include "qflow_eval.h"
+
+namespace qf {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// integral preparation
+// ---------------------------------------------------------------------------
+
+__global__ void k_sym_check(const double* __restrict__ h, const double* __restrict__ eri, int n,
+                            double* partial) {
+  const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+  double m = 0.0;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n4;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int s = (int)(idx % n), r = (int)(idx / n % n), q = (int)(idx / n2 % n),
+              p = (int)(idx / (n2 * n));
+    const double x = eri[idx];
+    if (!isfinite(x)) m = INFINITY;
+    m = fmax(m, fabs(x - eri[(((size_t)q * n + p) * n + r) * n + s]));
+    m = fmax(m, fabs(x - eri[(((size_t)p * n + q) * n + s) * n + r]));
+    m = fmax(m, fabs(x - eri[(((size_t)r * n + s) * n + p) * n + q]));
+    if (idx < n2) {
+      const double y = h[idx];
+      if (!isfinite(y)) m = INFINITY;
+      m = fmax(m, fabs(y - h[(idx % n) * n + idx / n]));
+    }
+  }
+  __shared__ double red[kBlock / 64];
+  m = wave_max(m);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = red[0];
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) x = fmax(x, red[w]);
+    partial[blockIdx.x] = x;
+  }
+}
+
+__global__ void k_fock(const double* __restrict__ h, const double* __restrict__ eri, int n, int o,
+                       double* f) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int p = idx / n, q = idx % n;
+  double x = h[idx];
+  for (int k = 0; k < o; ++k)
+    x += 2.0 * eri[(((size_t)p * n + q) * n + k) * n + k] - eri[(((size_t)p * n + k) * n + k) * n + q];
+  f[idx] = x;
+}
+
+// V[p][q][r][s] = (pr|qs); W[(pq)][(cd)] = V[p][q][o+c][o+d]
+__global__ void k_repack(const double* __restrict__ eri, int n, int o, double* V, double* W) {
+  const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+  const int v = n - o;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n4;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int s = (int)(idx % n), r = (int)(idx / n % n), q = (int)(idx / n2 % n),
+              p = (int)(idx / (n2 * n));
+    const double x = eri[(((size_t)p * n + r) * n + q) * n + s];
+    V[idx] = x;
+    if (r >= o && s >= o) W[((size_t)p * n + q) * v * v + (size_t)(r - o) * v + (s - o)] = x;
+  }
+}
+
+__global__ void k_mp2(const double* __restrict__ f, const double* __restrict__ V, int n, int o,
+                      double* t1, double* t2) {
+  const int v = n - o;
+  const size_t nt2 = (size_t)o * o * v * v;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nt2 + (size_t)o * v;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    if (idx < nt2) {
+      const int b = (int)(idx % v), a = (int)(idx / v % v), j = (int)(idx / v / v % o),
+                i = (int)(idx / v / v / o);
+      const double den = f[i * n + i] + f[j * n + j] - f[(o + a) * n + o + a] - f[(o + b) * n + o + b];
+      t2[idx] = V[(((size_t)i * n + j) * n + o + a) * n + o + b] / den;
+    } else {
+      const size_t k = idx - nt2;
+      const int i = (int)(k / v), a = (int)(k % v);
+      t1[k] = f[i * n + o + a] / (f[i * n + i] - f[(o + a) * n + o + a]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Yg = [F_N, sigma] (dense two-body, one-body, zero-body) and its
+// virtual-virtual block in ladder layout
+// ---------------------------------------------------------------------------
+
+__global__ void k_yg2(const double* __restrict__ f, const double* __restrict__ t1,
+                      const double* __restrict__ t2, int n, int o, double* y2, double* wy) {
+  const int v = n - o;
+  Yg Y{f, Sigma{t1, t2, n, o, v}, n, o};
+  const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n4;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int s = (int)(idx % n), r = (int)(idx / n % n), q = (int)(idx / n2 % n),
+              p = (int)(idx / (n2 * n));
+    const double x = Y.two(p, q, r, s);
+    y2[idx] = x;
+    if (r >= o && s >= o) wy[((size_t)p * n + q) * v * v + (size_t)(r - o) * v + (s - o)] = x;
+  }
+}
+
+__global__ void k_yg1(const double* __restrict__ f, const double* __restrict__ t1,
+                      const double* __restrict__ t2, int n, int o, double* y1, double* scal) {
+  const int v = n - o;
+  Yg Y{f, Sigma{t1, t2, n, o, v}, n, o};
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n * n) y1[idx] = Y.one(idx / n, idx % n);
+  if (idx == 0) scal[2] = Y.zero();
+}
+
+__global__ void k_fill(double* x, size_t count, double value) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    x[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// pool update
+// ---------------------------------------------------------------------------
+
+__global__ void k_update(const double* __restrict__ t1, const double* __restrict__ t2,
+                         const double* __restrict__ r1, const double* __restrict__ r2,
+                         const double* __restrict__ f, const int32_t* __restrict__ owner1,
+                         const int32_t* __restrict__ owner2, int n, int o, int step,
+                         double* t1n, double* t2n) {
+  const int v = n - o;
+  const size_t nt2 = (size_t)o * o * v * v, tot = nt2 + (size_t)o * v;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    if (idx < nt2) {
+      double x = t2[idx];
+      if (step && owner2[idx] < 0) {
+        const int b = (int)(idx % v), a = (int)(idx / v % v), j = (int)(idx / v / v % o),
+                  i = (int)(idx / v / v / o);
+        const double den = f[(o + a) * n + o + a] + f[(o + b) * n + o + b] - f[i * n + i] - f[j * n + j];
+        x -= r2[idx] / den;
+      }
+      t2n[idx] = x;
+    } else {
+      const size_t e = idx - nt2;
+      double x = t1[e];
+      if (step && owner1[e] < 0) {
+        const int i = (int)(e / v), a = (int)(e % v);
+        x -= r1[e] / (f[(o + a) * n + o + a] - f[i * n + i]);
+      }
+      t1n[e] = x;
+    }
+  }
+}
+
+__global__ void k_scatter_owned(const SpaceDev* __restrict__ spaces, const double* __restrict__ amp,
+                                const int64_t* __restrict__ amp_off,
+                                const int32_t* __restrict__ status,
+                                const int32_t* __restrict__ owner1,
+                                const int32_t* __restrict__ owner2, int n, int o, double* t1n,
+                                double* t2n) {
+  const int k = blockIdx.x;
+  if (status[k] != 0) return;
+  const SpaceDev sp = spaces[k];
+  const int ne = sp.nocc, nv = sp.na - sp.nocc, v = n - o;
+  const double* x = amp + amp_off[k];
+  const int nt1 = ne * nv;
+  for (int e = threadIdx.x; e < nt1 + nt1 * nt1; e += blockDim.x) {
+    if (e < nt1) {
+      const int i = sp.orb[e / nv], a = sp.orb[ne + e % nv] - o;
+      if (owner1[i * v + a] == k) t1n[i * v + a] = x[e];
+    } else {
+      const int q = e - nt1;
+      const int b = q % nv, a = q / nv % nv, j = q / (nv * nv) % ne, i = q / (nv * nv * ne);
+      const int I = sp.orb[i], J = sp.orb[j], Av = sp.orb[ne + a] - o, Bv = sp.orb[ne + b] - o;
+      const size_t g = (((size_t)I * o + J) * v + Av) * v + Bv;
+      if (owner2[g] == k) t2n[g] = x[e];
+    }
+  }
+}
+
+// out[0] = mean energy (fixed summation order), out[1] = max |t_new - t_old|
+__global__ __launch_bounds__(1024) void k_finish(const double* __restrict__ energy, int K,
+                                                 const double* __restrict__ t1,
+                                                 const double* __restrict__ t2,
+                                                 const double* __restrict__ t1n,
+                                                 const double* __restrict__ t2n, int o, int v,
+                                                 double* out) {
+  __shared__ double red[16];
+  const size_t nt2 = (size_t)o * o * v * v, nt1 = (size_t)o * v;
+  double m = 0.0;
+  for (size_t i = threadIdx.x; i < nt2; i += blockDim.x) m = fmax(m, fabs(t2n[i] - t2[i]));
+  for (size_t i = threadIdx.x; i < nt1; i += blockDim.x) m = fmax(m, fabs(t1n[i] - t1[i]));
+  m = wave_max(m);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) x = fmax(x, red[w]);
+    double e = 0.0;
+    for (int k = 0; k < K; ++k) e += energy[k];
+    out[0] = (K > 0) ? e / K : 0.0;
+    out[1] = x;
+  }
+}
+
+}  // namespace
+
+void launch_sym_check(const double* h, const double* eri, int n, double* partial, int nblocks,
+                      hipStream_t st) {
+  k_sym_check<<<nblocks, kBlock, 0, st>>>(h, eri, n, partial);
+}
+
+void launch_fock(const double* h, const double* eri, int n, int o, double* f, hipStream_t st) {
+  k_fock<<<grid_for((size_t)n * n), kBlock, 0, st>>>(h, eri, n, o, f);
+}
+
+void launch_repack(const double* eri, int n, int o, double* V, double* W, hipStream_t st) {
+  const size_t n4 = (size_t)n * n * n * n;
+  k_repack<<<grid_for(n4, kBlock, 65536), kBlock, 0, st>>>(eri, n, o, V, W);
+}
+
+void launch_mp2(const double* f, const double* V, int n, int o, double* t1, double* t2,
+                hipStream_t st) {
+  const size_t v = n - o;
+  k_mp2<<<grid_for(o * o * v * v + o * v, kBlock, 65536), kBlock, 0, st>>>(f, V, n, o, t1, t2);
+}
+
+void launch_yg(const double* f, const double* t1, const double* t2, int n, int o, double* y1,
+               double* y2, double* wy, double* scal, hipStream_t st) {
+  const size_t n4 = (size_t)n * n * n * n;
+  k_yg2<<<grid_for(n4, kBlock, 65536), kBlock, 0, st>>>(f, t1, t2, n, o, y2, wy);
+  k_yg1<<<grid_for((size_t)n * n), kBlock, 0, st>>>(f, t1, t2, n, o, y1, scal);
+}
+
+void launch_fill(double* x, size_t count, double value, hipStream_t st) {
+  k_fill<<<grid_for(count, kBlock, 65536), kBlock, 0, st>>>(x, count, value);
+}
+
+void launch_update(const double* t1, const double* t2, const double* r1, const double* r2,
+                   const double* f, const int32_t* owner1, const int32_t* owner2, int n, int o,
+                   bool unowned_step, double* t1n, double* t2n, hipStream_t st) {
+  const size_t v = n - o;
+  k_update<<<grid_for(o * o * v * v + o * v, kBlock, 65536), kBlock, 0, st>>>(
+      t1, t2, r1, r2, f, owner1, owner2, n, o, unowned_step ? 1 : 0, t1n, t2n);
+}
+
+void launch_scatter_owned(const SpaceDev* spaces, const double* amp, const int64_t* amp_off,
+                          const int32_t* status, const int32_t* owner1, const int32_t* owner2,
+                          int n, int o, int K, double* t1n, double* t2n, hipStream_t st) {
+  k_scatter_owned<<<K, kBlock, 0, st>>>(spaces, amp, amp_off, status, owner1, owner2, n, o, t1n,
+                                         t2n);
+}
+
+void launch_finish(const double* energy, int K, const double* t1, const double* t2,
+                   const double* t1n, const double* t2n, int o, int v, double* out2,
+                   hipStream_t st) {
+  k_finish<<<1, 1024, 0, st>>>(energy, K, t1, t2, t1n, t2n, o, v, out2);
+}
+
+}  // namespace qf

@@ -1,0 +1,77 @@
+// Global residual of the transformed Hamiltonian.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "kcommon.h"
+#include "kernels.h"
+#include "qflow_cas.h"
+#include "qflow_eval.h"
+
+namespace qf {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// residual of Hbar(sigma)
+// ---------------------------------------------------------------------------
+
+__global__ void k_residual2(GlobalOps g, double* r2) {
+  const int n = g.n, o = g.o, v = n - o;
+  const Sigma s{g.t1, g.t2, n, o, v};
+  const DenseOp H{g.f, g.V, g.L, n, o};
+  const DenseOp Y{g.y1, g.y2, g.LY, n, o};
+  const auto cH = make_comm(H, s, n, o);
+  const auto cY = make_comm(Y, s, n, o);
+  const size_t tot = (size_t)o * o * v * v;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int b = (int)(idx % v), a = (int)(idx / v % v), j = (int)(idx / v / v % o),
+              i = (int)(idx / v / v / o);
+    const int pa = o + a, pb = o + b;
+    r2[idx] = H.two(pa, pb, i, j) + cH.c2(pa, pb, i, j) + 0.5 * cY.c2(pa, pb, i, j);
+  }
+}
+
+__global__ void k_residual1(GlobalOps g, double* r1) {
+  const int n = g.n, o = g.o, v = n - o;
+  const Sigma s{g.t1, g.t2, n, o, v};
+  const DenseOp H{g.f, g.V, g.L, n, o};
+  const DenseOp Y{g.y1, g.y2, g.LY, n, o};
+  const auto cH = make_comm(H, s, n, o);
+  const auto cY = make_comm(Y, s, n, o);
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= o * v) return;
+  const int i = idx / v, a = idx % v;
+  r1[idx] = H.one(o + a, i) + cH.c1(o + a, i) + 0.5 * cY.c1(o + a, i);
+}
+
+// scal[0] = [H_N,sigma]_0, scal[1] = [Yg,sigma]_0 (scal[3] = E_ref, set at load)
+__global__ void k_residual0(GlobalOps g, double* scal, double* e0) {
+  const int n = g.n, o = g.o, v = n - o;
+  const Sigma s{g.t1, g.t2, n, o, v};
+  const DenseOp H{g.f, g.V, g.L, n, o};
+  const DenseOp Y{g.y1, g.y2, g.LY, n, o};
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double zh = make_comm(H, s, n, o).c0();
+    const double zy = make_comm(Y, s, n, o).c0();
+    scal[0] = zh;
+    scal[1] = zy;
+    if (e0) *e0 = scal[3] + zh + 0.5 * zy;
+  }
+}
+
+}  // namespace
+
+void launch_residual(const double* f, const double* V, const double* y1, const double* y2,
+                     const double* L, const double* LY, const double* t1, const double* t2,
+                     int n, int o, double* scal, double* r1, double* r2, double* e0,
+                     hipStream_t st) {
+  GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o};
+  const size_t v = n - o;
+  k_residual2<<<grid_for(o * o * v * v, kBlock, 65536), kBlock, 0, st>>>(g, r2);
+  k_residual1<<<grid_for(o * v), kBlock, 0, st>>>(g, r1);
+  k_residual0<<<1, 64, 0, st>>>(g, scal, e0);
+}
+
+}  // namespace qf

@@ -1,0 +1,35 @@
+// Helpers shared by the libqflow kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stddef.h>
+
+namespace qf {
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(size_t work, int block = kBlock, size_t cap = 1u << 20) {
+  size_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+__device__ inline double wave_sum(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+__device__ inline double wave_max(double x) {
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+// Operands of the global commutator evaluations.
+struct GlobalOps {
+  const double *f, *V, *y1, *y2, *L, *LY, *t1, *t2;
+  int n, o;
+};
+
+}  // namespace qf

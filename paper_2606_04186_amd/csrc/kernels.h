@@ -1,0 +1,76 @@
+// Launch wrappers of the libqflow kernels (all enqueue on `st`).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qflow_cas.h"
+
+namespace qf {
+
+struct SpaceDev {            // device copy of one active space
+  int na, nocc;
+  int orb[8];
+};
+
+// integral preparation
+void launch_sym_check(const double* h, const double* eri, int n, double* partial, int nblocks,
+                      hipStream_t st);
+void launch_fock(const double* h, const double* eri, int n, int o, double* f, hipStream_t st);
+void launch_repack(const double* eri, int n, int o, double* V, double* W, hipStream_t st);
+void launch_mp2(const double* f, const double* V, int n, int o, double* t1, double* t2,
+                hipStream_t st);
+
+// intermediates of one amplitude set
+void launch_yg(const double* f, const double* t1, const double* t2, int n, int o, double* y1,
+               double* y2, double* wy, double* scal, hipStream_t st);
+void launch_fill(double* x, size_t count, double value, hipStream_t st);
+// C[M][N] = sum_k A[m][k] B[n][k], FP64 matrix cores
+void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int N, int K,
+                        hipStream_t st);
+
+// residual of Hbar(sigma)
+void launch_residual(const double* f, const double* V, const double* y1, const double* y2,
+                     const double* L, const double* LY, const double* t1, const double* t2,
+                     int n, int o, double* scal, double* r1, double* r2, double* e0,
+                     hipStream_t st);
+
+// per-space downfolded Hamiltonians in CAS form
+void launch_heff(const double* f, const double* V, const double* y1, const double* y2,
+                 const double* L, const double* LY, const double* t1, const double* t2, int n,
+                 int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
+                 int K, int na_max, double* heff, hipStream_t st);
+
+// per-space Davidson eigensolver and cluster analysis
+struct DavidsonArgs {
+  const SpaceDev* spaces;
+  const Strings* strings;     // one table per size class, indexed by nocc-2
+  const double* heff;
+  const int64_t* heff_off;
+  double* work;               // per space: 2*maxsub*D doubles
+  const int64_t* work_off;
+  double* energy;
+  double* c0;
+  double* amp;
+  const int64_t* amp_off;
+  int32_t* iters;
+  int32_t* status;
+  double tol;
+  int max_iter;
+  int maxsub;
+  int K;
+};
+void launch_davidson(const DavidsonArgs& a, int lds_doubles, hipStream_t st);
+
+// pool update
+void launch_update(const double* t1, const double* t2, const double* r1, const double* r2,
+                   const double* f, const int32_t* owner1, const int32_t* owner2, int n, int o,
+                   bool unowned_step, double* t1n, double* t2n, hipStream_t st);
+void launch_scatter_owned(const SpaceDev* spaces, const double* amp, const int64_t* amp_off,
+                          const int32_t* status, const int32_t* owner1, const int32_t* owner2,
+                          int n, int o, int K, double* t1n, double* t2n, hipStream_t st);
+void launch_finish(const double* energy, int K, const double* t1, const double* t2,
+                   const double* t1n, const double* t2n, int o, int v, double* out2,
+                   hipStream_t st);
+
+}  // namespace qf

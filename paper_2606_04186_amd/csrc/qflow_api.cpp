@@ -1,0 +1,542 @@
+// libqflow host runtime: context, device workspaces and the C ABI of
+// include/qflow.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qflow.h"
+#include "kernels.h"
+#include "qflow_cas.h"
+
+namespace qf {
+bool build_strings(int na, int ne, Strings* S);
+}
+
+using qf::SpaceDev;
+
+namespace {
+
+constexpr int kMaxSub = 12;        // Davidson subspace before restart
+constexpr int kStages = 6;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct qflow_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  // problem
+  int n = 0, o = 0, v = 0;
+  bool loaded = false;
+  double e_ref = 0.0;
+  std::vector<double> fock;
+  // device state
+  DevBuf f, V, W, y1, y2, wy, L, LY, scal, r1, r2, t1n, t2n;
+  DevBuf heff, heff_off, amp, amp_off, work, work_off, energy, c0, iters, status, spaces,
+      strings, out2, partial;
+  // host mirror of the last uploaded space list
+  std::vector<qflow_space> last_spaces;
+  std::vector<int64_t> h_heff_off, h_amp_off, h_work_off;
+  int lds_davidson = 0;
+  int na_max = 0;
+  hipEvent_t ev[kStages + 1] = {};
+  float stage_ms[kStages] = {};
+  bool timed = false;
+};
+
+namespace {
+
+int fail(qflow_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define QF_HIP(call)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(ctx, QFLOW_E_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+int ensure(qflow_ctx* ctx, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return QFLOW_OK;
+  if (b.p) {
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail(ctx, QFLOW_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.bytes = bytes;
+  return QFLOW_OK;
+}
+
+template <class T>
+T* P(DevBuf& b) {
+  return static_cast<T*>(b.p);
+}
+
+#define QF_TRY(expr)            \
+  do {                          \
+    int r_ = (expr);            \
+    if (r_ != QFLOW_OK) return r_; \
+  } while (0)
+
+int na_of(const qflow_space& s) { return s.n_o + s.n_v; }
+
+int check_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
+  if (K < 0) return fail(ctx, QFLOW_E_INVALID_ARG, "K < 0");
+  if (K > 0 && !spaces) return fail(ctx, QFLOW_E_INVALID_ARG, "spaces is NULL");
+  for (int k = 0; k < K; ++k) {
+    const qflow_space& s = spaces[k];
+    if (s.n_o < 2 || s.n_o > 4 || s.n_v != s.n_o)
+      return fail(ctx, QFLOW_E_UNSUPPORTED,
+                  "space " + std::to_string(k) + ": only (2,2), (3,3) and (4,4) spaces");
+    for (int a = 0; a < na_of(s); ++a) {
+      const int p = s.orb[a];
+      const bool occ = a < s.n_o;
+      if (p < 0 || p >= ctx->n || (occ && p >= ctx->o) || (!occ && p < ctx->o))
+        return fail(ctx, QFLOW_E_INVALID_ARG, "space " + std::to_string(k) + ": bad orbital");
+      if (a > 0 && a != s.n_o && s.orb[a - 1] >= p)
+        return fail(ctx, QFLOW_E_INVALID_ARG,
+                    "space " + std::to_string(k) + ": orbitals not ascending");
+    }
+  }
+  return QFLOW_OK;
+}
+
+bool same_spaces(const qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
+  return (int)ctx->last_spaces.size() == K &&
+         (K == 0 || std::memcmp(ctx->last_spaces.data(), spaces, sizeof(qflow_space) * K) == 0);
+}
+
+// Upload the space list (and its derived offsets) when it changed.
+int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
+  if (same_spaces(ctx, K, spaces) && ctx->spaces.p) return QFLOW_OK;
+  std::vector<SpaceDev> dev(std::max(K, 1));
+  ctx->h_heff_off.assign(K + 1, 0);
+  ctx->h_amp_off.assign(K + 1, 0);
+  ctx->h_work_off.assign(K + 1, 0);
+  int lds = 0, na_max = 0;
+  for (int k = 0; k < K; ++k) {
+    const qflow_space& s = spaces[k];
+    dev[k].na = na_of(s);
+    dev[k].nocc = s.n_o;
+    for (int a = 0; a < 8; ++a) dev[k].orb[a] = a < dev[k].na ? s.orb[a] : 0;
+    const int na = dev[k].na;
+    const int64_t nt1 = (int64_t)s.n_o * s.n_v;
+    ctx->h_heff_off[k + 1] = ctx->h_heff_off[k] + qflow_heff_size(&s);
+    ctx->h_amp_off[k + 1] = ctx->h_amp_off[k] + nt1 + nt1 * nt1;
+    int64_t ns = 1;
+    for (int i = 0; i < s.n_o; ++i) ns = ns * (na - i) / (i + 1);
+    const int64_t D = ns * ns;
+    ctx->h_work_off[k + 1] = ctx->h_work_off[k] + 2 * kMaxSub * D;
+    const int need = na * na * na * na + (int)(ns * ns) + 4 * (int)D + 3 * kMaxSub * kMaxSub +
+                     kMaxSub + 4;
+    lds = std::max(lds, need);
+    na_max = std::max(na_max, na);
+  }
+  if ((size_t)lds * sizeof(double) > 160 * 1024)
+    return fail(ctx, QFLOW_E_UNSUPPORTED, "active space too large for the LDS-resident solver");
+  ctx->lds_davidson = lds;
+  ctx->na_max = na_max;
+  QF_TRY(ensure(ctx, ctx->spaces, sizeof(SpaceDev) * std::max(K, 1)));
+  QF_TRY(ensure(ctx, ctx->heff_off, sizeof(int64_t) * (K + 1)));
+  QF_TRY(ensure(ctx, ctx->amp_off, sizeof(int64_t) * (K + 1)));
+  QF_TRY(ensure(ctx, ctx->work_off, sizeof(int64_t) * (K + 1)));
+  QF_TRY(ensure(ctx, ctx->work, sizeof(double) * std::max<int64_t>(ctx->h_work_off[K], 1)));
+  QF_TRY(ensure(ctx, ctx->heff, sizeof(double) * std::max<int64_t>(ctx->h_heff_off[K], 1)));
+  QF_TRY(ensure(ctx, ctx->amp, sizeof(double) * std::max<int64_t>(ctx->h_amp_off[K], 1)));
+  QF_TRY(ensure(ctx, ctx->energy, sizeof(double) * std::max(K, 1)));
+  QF_TRY(ensure(ctx, ctx->c0, sizeof(double) * std::max(K, 1)));
+  QF_TRY(ensure(ctx, ctx->iters, sizeof(int32_t) * std::max(K, 1)));
+  QF_TRY(ensure(ctx, ctx->status, sizeof(int32_t) * std::max(K, 1)));
+  QF_HIP(hipMemcpyAsync(ctx->spaces.p, dev.data(), sizeof(SpaceDev) * std::max(K, 1),
+                        hipMemcpyHostToDevice, ctx->stream));
+  QF_HIP(hipMemcpyAsync(ctx->heff_off.p, ctx->h_heff_off.data(), sizeof(int64_t) * (K + 1),
+                        hipMemcpyHostToDevice, ctx->stream));
+  QF_HIP(hipMemcpyAsync(ctx->amp_off.p, ctx->h_amp_off.data(), sizeof(int64_t) * (K + 1),
+                        hipMemcpyHostToDevice, ctx->stream));
+  QF_HIP(hipMemcpyAsync(ctx->work_off.p, ctx->h_work_off.data(), sizeof(int64_t) * (K + 1),
+                        hipMemcpyHostToDevice, ctx->stream));
+  // the host vectors must outlive the asynchronous copies
+  QF_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->last_spaces.assign(spaces, spaces + K);
+  return QFLOW_OK;
+}
+
+int require_loaded(qflow_ctx* ctx) {
+  if (!ctx) return QFLOW_E_INVALID_ARG;
+  if (!ctx->loaded) return fail(ctx, QFLOW_E_STATE, "no integrals loaded");
+  return QFLOW_OK;
+}
+
+// Yg = [F,sigma] and the ladder intermediates L = W t2^T, LY = WY t2^T
+int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
+  if (precision != QFLOW_FP64)
+    return fail(ctx, QFLOW_E_UNSUPPORTED, "only QFLOW_FP64 contractions are available");
+  const int n = ctx->n, o = ctx->o, v = ctx->v;
+  qf::launch_yg(P<double>(ctx->f), t1, t2, n, o, P<double>(ctx->y1), P<double>(ctx->y2),
+                P<double>(ctx->wy), P<double>(ctx->scal), ctx->stream);
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
+  qf::launch_gemm_nt_f64(P<double>(ctx->W), t2, P<double>(ctx->L), n * n, o * o, v * v,
+                         ctx->stream);
+  qf::launch_gemm_nt_f64(P<double>(ctx->wy), t2, P<double>(ctx->LY), n * n, o * o, v * v,
+                         ctx->stream);
+  QF_HIP(hipGetLastError());
+  return QFLOW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qflow_create(qflow_ctx** out, int device, void* hip_stream) {
+  if (!out) return QFLOW_E_INVALID_ARG;
+  *out = nullptr;
+  qflow_ctx* ctx = new (std::nothrow) qflow_ctx();
+  if (!ctx) return QFLOW_E_OOM;
+  ctx->device = device;
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    delete ctx;
+    return QFLOW_E_DEVICE;
+  }
+  if (hip_stream) {
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreate(&ctx->stream) != hipSuccess) {
+      delete ctx;
+      return QFLOW_E_DEVICE;
+    }
+    ctx->own_stream = true;
+  }
+  for (auto& ev : ctx->ev)
+    if (hipEventCreate(&ev) != hipSuccess) {
+      qflow_destroy(ctx);
+      return QFLOW_E_DEVICE;
+    }
+  std::vector<qf::Strings> tabs(3);
+  for (int s = 0; s < 3; ++s) qf::build_strings(2 * (s + 2), s + 2, &tabs[s]);
+  if (ensure(ctx, ctx->strings, sizeof(qf::Strings) * 3) != QFLOW_OK ||
+      hipMemcpy(ctx->strings.p, tabs.data(), sizeof(qf::Strings) * 3, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      ensure(ctx, ctx->scal, sizeof(double) * 8) != QFLOW_OK ||
+      ensure(ctx, ctx->out2, sizeof(double) * 2) != QFLOW_OK) {
+    qflow_destroy(ctx);
+    return QFLOW_E_DEVICE;
+  }
+  *out = ctx;
+  return QFLOW_OK;
+}
+
+int qflow_destroy(qflow_ctx* ctx) {
+  if (!ctx) return QFLOW_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  DevBuf* bufs[] = {&ctx->f,      &ctx->V,        &ctx->W,      &ctx->y1,       &ctx->y2,
+                    &ctx->wy,     &ctx->L,        &ctx->LY,     &ctx->scal,     &ctx->r1,
+                    &ctx->r2,     &ctx->t1n,      &ctx->t2n,    &ctx->heff,     &ctx->heff_off,
+                    &ctx->amp,    &ctx->amp_off,  &ctx->work,   &ctx->work_off, &ctx->energy,
+                    &ctx->c0,     &ctx->iters,    &ctx->status, &ctx->spaces,   &ctx->strings,
+                    &ctx->out2,   &ctx->partial};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  for (auto& ev : ctx->ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return QFLOW_OK;
+}
+
+const char* qflow_last_error(const qflow_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const double* h,
+                         const double* eri, double sym_tol) {
+  if (!ctx) return QFLOW_E_INVALID_ARG;
+  if (!h || !eri) return fail(ctx, QFLOW_E_INVALID_ARG, "h or eri is NULL");
+  if (n_orb < 2 || n_orb > 128 || n_occ < 1 || n_occ >= n_orb)
+    return fail(ctx, QFLOW_E_INVALID_ARG, "need 1 <= n_occ < n_orb <= 128");
+  if (!(sym_tol >= 0.0)) return fail(ctx, QFLOW_E_INVALID_ARG, "sym_tol must be >= 0");
+  QF_HIP(hipSetDevice(ctx->device));
+  ctx->loaded = false;
+  const int n = n_orb, o = n_occ, v = n - o;
+  const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+  ctx->n = n;
+  ctx->o = o;
+  ctx->v = v;
+  const int nblk = 1024;
+  QF_TRY(ensure(ctx, ctx->partial, sizeof(double) * nblk));
+  qf::launch_sym_check(h, eri, n, P<double>(ctx->partial), nblk, ctx->stream);
+  std::vector<double> part(nblk);
+  QF_HIP(hipMemcpyAsync(part.data(), ctx->partial.p, sizeof(double) * nblk,
+                        hipMemcpyDeviceToHost, ctx->stream));
+  QF_HIP(hipStreamSynchronize(ctx->stream));
+  double asym = 0.0;
+  for (double x : part) asym = std::max(asym, std::isnan(x) ? INFINITY : x);
+  if (!(asym <= sym_tol))
+    return fail(ctx, QFLOW_E_SYMMETRY,
+                "integrals not finite or not symmetric: max deviation " + std::to_string(asym));
+  QF_TRY(ensure(ctx, ctx->f, sizeof(double) * n2));
+  QF_TRY(ensure(ctx, ctx->V, sizeof(double) * n4));
+  QF_TRY(ensure(ctx, ctx->W, sizeof(double) * n2 * v * v));
+  QF_TRY(ensure(ctx, ctx->y1, sizeof(double) * n2));
+  QF_TRY(ensure(ctx, ctx->y2, sizeof(double) * n4));
+  QF_TRY(ensure(ctx, ctx->wy, sizeof(double) * n2 * v * v));
+  QF_TRY(ensure(ctx, ctx->L, sizeof(double) * n2 * o * o));
+  QF_TRY(ensure(ctx, ctx->LY, sizeof(double) * n2 * o * o));
+  QF_TRY(ensure(ctx, ctx->r1, sizeof(double) * o * v));
+  QF_TRY(ensure(ctx, ctx->r2, sizeof(double) * (size_t)o * o * v * v));
+  QF_TRY(ensure(ctx, ctx->t1n, sizeof(double) * o * v));
+  QF_TRY(ensure(ctx, ctx->t2n, sizeof(double) * (size_t)o * o * v * v));
+  qf::launch_fock(h, eri, n, o, P<double>(ctx->f), ctx->stream);
+  qf::launch_repack(eri, n, o, P<double>(ctx->V), P<double>(ctx->W), ctx->stream);
+  QF_HIP(hipGetLastError());
+  ctx->fock.assign(n2, 0.0);
+  std::vector<double> hh(n2);
+  QF_HIP(hipMemcpyAsync(ctx->fock.data(), ctx->f.p, sizeof(double) * n2, hipMemcpyDeviceToHost,
+                        ctx->stream));
+  QF_HIP(hipMemcpyAsync(hh.data(), h, sizeof(double) * n2, hipMemcpyDeviceToHost, ctx->stream));
+  QF_HIP(hipStreamSynchronize(ctx->stream));
+  double e = 0.0;
+  for (int k = 0; k < o; ++k) e += hh[(size_t)k * n + k] + ctx->fock[(size_t)k * n + k];
+  ctx->e_ref = e;
+  double sc[8] = {0, 0, 0, e, 0, 0, 0, 0};
+  QF_HIP(hipMemcpy(ctx->scal.p, sc, sizeof(sc), hipMemcpyHostToDevice));
+  ctx->loaded = true;
+  ctx->last_spaces.clear();
+  return QFLOW_OK;
+}
+
+int qflow_reference(qflow_ctx* ctx, double* e_ref, double* eps, double* fock) {
+  QF_TRY(require_loaded(ctx));
+  if (e_ref) *e_ref = ctx->e_ref;
+  const int n = ctx->n;
+  if (eps)
+    for (int p = 0; p < n; ++p) eps[p] = ctx->fock[(size_t)p * n + p];
+  if (fock) std::memcpy(fock, ctx->fock.data(), sizeof(double) * n * n);
+  return QFLOW_OK;
+}
+
+int qflow_mp2_guess(qflow_ctx* ctx, double* t1, double* t2) {
+  QF_TRY(require_loaded(ctx));
+  if (!t1 || !t2) return fail(ctx, QFLOW_E_INVALID_ARG, "t1 or t2 is NULL");
+  qf::launch_mp2(P<double>(ctx->f), P<double>(ctx->V), ctx->n, ctx->o, t1, t2, ctx->stream);
+  QF_HIP(hipGetLastError());
+  return QFLOW_OK;
+}
+
+int qflow_residual(qflow_ctx* ctx, const double* t1, const double* t2, double* r1, double* r2,
+                   double* e0, int precision) {
+  QF_TRY(require_loaded(ctx));
+  if (!t1 || !t2 || !r1 || !r2 || !e0)
+    return fail(ctx, QFLOW_E_INVALID_ARG, "NULL array argument");
+  QF_TRY(prepare(ctx, t1, t2, precision));
+  qf::launch_residual(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
+                      P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), t1, t2, ctx->n,
+                      ctx->o, P<double>(ctx->scal), r1, r2, e0, ctx->stream);
+  QF_HIP(hipGetLastError());
+  return QFLOW_OK;
+}
+
+int64_t qflow_heff_size(const qflow_space* s) {
+  if (!s) return 0;
+  const int64_t na = s->n_o + s->n_v;
+  return 1 + na * na + na * na * na * na;
+}
+
+int64_t qflow_amp_size(const qflow_space* s) {
+  if (!s) return 0;
+  const int64_t nt1 = (int64_t)s->n_o * s->n_v;
+  return nt1 + nt1 * nt1;
+}
+
+namespace {
+
+int check_offsets(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const int64_t* off,
+                  int64_t (*size)(const qflow_space*), const char* what) {
+  if (!off) return fail(ctx, QFLOW_E_INVALID_ARG, std::string(what) + " is NULL");
+  for (int k = 0; k < K; ++k)
+    if (off[k] < 0 || off[k + 1] - off[k] < size(&spaces[k]))
+      return fail(ctx, QFLOW_E_INVALID_ARG,
+                  std::string(what) + ": block " + std::to_string(k) + " too small");
+  return QFLOW_OK;
+}
+
+int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, double* heff,
+             const int64_t* heff_off_dev) {
+  // zero-body parts of [H_N, sigma] and [Yg, sigma] (scal[0], scal[1])
+  qf::launch_residual(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
+                      P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), t1, t2, ctx->n,
+                      ctx->o, P<double>(ctx->scal), P<double>(ctx->r1), P<double>(ctx->r2),
+                      nullptr, ctx->stream);
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[3], ctx->stream));
+  if (K > 0)
+    qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1), P<double>(ctx->y2),
+                    P<double>(ctx->L), P<double>(ctx->LY), t1, t2, ctx->n, ctx->o,
+                    P<double>(ctx->scal), P<SpaceDev>(ctx->spaces), heff_off_dev, K,
+                    ctx->na_max, heff, ctx->stream);
+  QF_HIP(hipGetLastError());
+  return QFLOW_OK;
+}
+
+int run_solve(qflow_ctx* ctx, int32_t K, const double* heff, const int64_t* heff_off_dev,
+              double* energy, double* c0, double* amp, const int64_t* amp_off_dev,
+              int32_t* iters, int32_t* status, double tol, int32_t max_iter) {
+  if (K == 0) return QFLOW_OK;
+  qf::DavidsonArgs a;
+  a.spaces = P<SpaceDev>(ctx->spaces);
+  a.strings = P<qf::Strings>(ctx->strings);
+  a.heff = heff;
+  a.heff_off = heff_off_dev;
+  a.work = P<double>(ctx->work);
+  a.work_off = P<int64_t>(ctx->work_off);
+  a.energy = energy;
+  a.c0 = c0;
+  a.amp = amp;
+  a.amp_off = amp_off_dev;
+  a.iters = iters;
+  a.status = status;
+  a.tol = tol;
+  a.max_iter = max_iter;
+  a.maxsub = kMaxSub;
+  a.K = K;
+  qf::launch_davidson(a, ctx->lds_davidson, ctx->stream);
+  QF_HIP(hipGetLastError());
+  return QFLOW_OK;
+}
+
+}  // namespace
+
+int qflow_build_heff(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const double* t1,
+                     const double* t2, double* heff, const int64_t* heff_off, int precision) {
+  QF_TRY(require_loaded(ctx));
+  QF_TRY(check_spaces(ctx, K, spaces));
+  if (!t1 || !t2 || !heff) return fail(ctx, QFLOW_E_INVALID_ARG, "NULL array argument");
+  QF_TRY(check_offsets(ctx, K, spaces, heff_off, qflow_heff_size, "heff_off"));
+  QF_TRY(upload_spaces(ctx, K, spaces));
+  DevBuf off;
+  QF_TRY(ensure(ctx, off, sizeof(int64_t) * (K + 1)));
+  hipError_t e = hipMemcpy(off.p, heff_off, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice);
+  int r = (e == hipSuccess) ? prepare(ctx, t1, t2, precision)
+                            : fail(ctx, QFLOW_E_DEVICE, "heff_off upload failed");
+  if (r == QFLOW_OK) r = run_heff(ctx, K, t1, t2, heff, P<int64_t>(off));
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(off.p);
+  return r;
+}
+
+int qflow_solve_active_batch(qflow_ctx* ctx, int32_t K, const qflow_space* spaces,
+                             const double* heff, const int64_t* heff_off, double* energy,
+                             double* c0, double* amp, const int64_t* amp_off, int32_t* iters,
+                             int32_t* status, double tol, int32_t max_iter) {
+  QF_TRY(require_loaded(ctx));
+  QF_TRY(check_spaces(ctx, K, spaces));
+  if (!heff || !energy || !c0 || !amp || !iters || !status)
+    return fail(ctx, QFLOW_E_INVALID_ARG, "NULL array argument");
+  if (!(tol > 0.0) || max_iter < 1) return fail(ctx, QFLOW_E_INVALID_ARG, "bad tol or max_iter");
+  QF_TRY(check_offsets(ctx, K, spaces, heff_off, qflow_heff_size, "heff_off"));
+  QF_TRY(check_offsets(ctx, K, spaces, amp_off, qflow_amp_size, "amp_off"));
+  QF_TRY(upload_spaces(ctx, K, spaces));
+  DevBuf off;
+  QF_TRY(ensure(ctx, off, sizeof(int64_t) * 2 * (K + 1)));
+  int64_t* d_hoff = P<int64_t>(off);
+  int64_t* d_aoff = d_hoff + (K + 1);
+  int r = QFLOW_OK;
+  if (hipMemcpy(d_hoff, heff_off, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(d_aoff, amp_off, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice) != hipSuccess)
+    r = fail(ctx, QFLOW_E_DEVICE, "offset upload failed");
+  if (r == QFLOW_OK)
+    r = run_solve(ctx, K, heff, d_hoff, energy, c0, amp, d_aoff, iters, status, tol, max_iter);
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(off.p);
+  return r;
+}
+
+int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const int32_t* owner1,
+                    const int32_t* owner2, double* t1, double* t2, double* energy,
+                    double* e_mean, double* max_dt, int32_t flags) {
+  QF_TRY(require_loaded(ctx));
+  QF_TRY(check_spaces(ctx, K, spaces));
+  if (!owner1 || !owner2 || !t1 || !t2 || !e_mean || !max_dt || (K > 0 && !energy))
+    return fail(ctx, QFLOW_E_INVALID_ARG, "NULL argument");
+  QF_TRY(upload_spaces(ctx, K, spaces));
+  const int precision = flags & 15;
+  const bool step = !(flags & QFLOW_UNOWNED_FROZEN);
+  const int n = ctx->n, o = ctx->o, v = ctx->v;
+  hipStream_t st = ctx->stream;
+  ctx->timed = true;
+  QF_HIP(hipEventRecord(ctx->ev[0], st));
+  int r = prepare(ctx, t1, t2, precision);
+  if (r != QFLOW_OK) {
+    ctx->timed = false;
+    return r;
+  }
+  QF_HIP(hipEventRecord(ctx->ev[2], st));
+  r = run_heff(ctx, K, t1, t2, P<double>(ctx->heff), P<int64_t>(ctx->heff_off));
+  if (r != QFLOW_OK) {
+    ctx->timed = false;
+    return r;
+  }
+  QF_HIP(hipEventRecord(ctx->ev[4], st));
+  r = run_solve(ctx, K, P<double>(ctx->heff), P<int64_t>(ctx->heff_off), P<double>(ctx->energy),
+                P<double>(ctx->c0), P<double>(ctx->amp), P<int64_t>(ctx->amp_off),
+                P<int32_t>(ctx->iters), P<int32_t>(ctx->status), 1e-10, 200);
+  ctx->timed = false;
+  if (r != QFLOW_OK) return r;
+  QF_HIP(hipEventRecord(ctx->ev[5], st));
+  qf::launch_update(t1, t2, P<double>(ctx->r1), P<double>(ctx->r2), P<double>(ctx->f), owner1,
+                    owner2, n, o, step, P<double>(ctx->t1n), P<double>(ctx->t2n), st);
+  if (K > 0)
+    qf::launch_scatter_owned(P<SpaceDev>(ctx->spaces), P<double>(ctx->amp),
+                             P<int64_t>(ctx->amp_off), P<int32_t>(ctx->status), owner1, owner2,
+                             n, o, K, P<double>(ctx->t1n), P<double>(ctx->t2n), st);
+  qf::launch_finish(P<double>(ctx->energy), K, t1, t2, P<double>(ctx->t1n), P<double>(ctx->t2n),
+                    o, v, P<double>(ctx->out2), st);
+  QF_HIP(hipGetLastError());
+  QF_HIP(hipMemcpyAsync(t1, ctx->t1n.p, sizeof(double) * o * v, hipMemcpyDeviceToDevice, st));
+  QF_HIP(hipMemcpyAsync(t2, ctx->t2n.p, sizeof(double) * (size_t)o * o * v * v,
+                        hipMemcpyDeviceToDevice, st));
+  if (K > 0)
+    QF_HIP(hipMemcpyAsync(energy, ctx->energy.p, sizeof(double) * K, hipMemcpyDeviceToDevice, st));
+  QF_HIP(hipEventRecord(ctx->ev[6], st));
+  double out[2];
+  QF_HIP(hipMemcpyAsync(out, ctx->out2.p, sizeof(out), hipMemcpyDeviceToHost, st));
+  QF_HIP(hipStreamSynchronize(st));
+  *e_mean = out[0];
+  *max_dt = out[1];
+  // stage times: Yg | ladder GEMMs | residual | heff | solve | update
+  const int pairs[kStages][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}};
+  for (int s = 0; s < kStages; ++s) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[pairs[s][0]], ctx->ev[pairs[s][1]]) != hipSuccess)
+      ms = -1.f;
+    ctx->stage_ms[s] = ms;
+  }
+  return QFLOW_OK;
+}
+
+int qflow_last_timings(const qflow_ctx* ctx, float* ms, int n) {
+  if (!ctx || !ms) return 0;
+  const int c = std::min(n, kStages);
+  for (int s = 0; s < c; ++s) ms[s] = ctx->stage_ms[s];
+  return c;
+}
+
+}  // extern "C"

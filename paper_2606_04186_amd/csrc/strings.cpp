@@ -1,0 +1,65 @@
+// Host construction of the determinant-string tables used by the active-space
+// CI kernels (layout documented in qflow_cas.h).
+#include <cstring>
+#include <vector>
+
+#include "qflow_cas.h"
+
+namespace qf {
+
+static int popc(unsigned x) { return __builtin_popcount(x); }
+
+// sign of a+_p a_q acting on string J (bitmask); requires q in J and
+// (p not in J or p == q)
+static int repl_sign(unsigned J, int p, int q) {
+  int s = (popc(J & ((1u << q) - 1u)) & 1) ? -1 : 1;
+  unsigned Jp = J & ~(1u << q);
+  s *= (popc(Jp & ((1u << p) - 1u)) & 1) ? -1 : 1;
+  return s;
+}
+
+bool build_strings(int na, int ne, Strings* S) {
+  if (na > 8 || ne > 4 || ne < 1 || ne >= na) return false;
+  std::memset(S, 0, sizeof(Strings));
+  std::vector<unsigned> strs;
+  for (unsigned m = 0; m < (1u << na); ++m)
+    if (popc(m) == ne) strs.push_back(m);
+  if ((int)strs.size() > kMaxStr) return false;
+  S->na = na;
+  S->ne = ne;
+  S->nstr = (int)strs.size();
+  S->nrep = ne * (1 + na - ne);
+  auto index = [&](unsigned m) {
+    for (size_t k = 0; k < strs.size(); ++k)
+      if (strs[k] == m) return (int)k;
+    return -1;
+  };
+  for (int I = 0; I < S->nstr; ++I) {
+    unsigned mI = strs[I];
+    int e = 0, o = 0;
+    for (int p = 0; p < na; ++p)
+      if (mI >> p & 1u) S->occ[I][o++] = (uint8_t)p;
+    for (int p = 0; p < na; ++p) {
+      if (!(mI >> p & 1u)) continue;
+      for (int q = 0; q < na; ++q) {
+        if (q != p && (mI >> q & 1u)) continue;
+        unsigned J = (q == p) ? mI : ((mI & ~(1u << p)) | (1u << q));
+        S->src[I][e] = (int16_t)index(J);
+        S->pq[I][e] = (int16_t)(p * na + q);
+        S->sgn[I][e] = (int8_t)repl_sign(J, p, q);
+        ++e;
+      }
+    }
+  }
+  unsigned ref = (1u << ne) - 1u;
+  for (int i = 0; i < ne; ++i)
+    for (int a = ne; a < na; ++a) {
+      if (a - ne >= 4) continue;
+      unsigned J = (ref & ~(1u << i)) | (1u << a);
+      S->exc_str[i][a - ne] = (int16_t)index(J);
+      S->exc_sgn[i][a - ne] = (int8_t)repl_sign(ref, a, i);
+    }
+  return true;
+}
+
+}  // namespace qf

@@ -1,0 +1,261 @@
+"""HIP path against the CPU oracle, element by element, through the C ABI.
+
+Tolerances are for FP64 arithmetic that differs from the oracle only in
+summation order (about 1e-15 relative per operation): residual and integral
+elements to 1e-11 absolute, energies to 1e-9 Eh (the FP64 target is 1e-8 Eh),
+amplitudes to 1e-8 (the eigensolver stops at a residual norm of 1e-10).
+"""
+import numpy as np
+import pytest
+
+import synth
+from bruteforce import sector_hamiltonian
+from oracle import qflow, sampling
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def problem(n, o, seed, stress=True):
+    if stress:
+        h, eri = synth.gen_integrals(n, o, 2 * n, seed, b_std=0.04, off_std=0.03)
+    else:
+        h, eri = synth.gen_integrals(n, o, 2 * n, seed)
+    return h, eri
+
+
+def context(h, eri, o):
+    import paper_2606_04186_amd as qf
+    ctx = qf.Context(0)
+    ctx.load_integrals(dev(h), dev(eri), o)
+    return ctx
+
+
+CASES = [(8, 3, 101), (24, 4, 102), (40, 5, 103)]
+
+
+@pytest.mark.parametrize("n,o,seed", CASES)
+def test_reference_and_mp2(n, o, seed):
+    _need_gpu()
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    ctx = context(h, eri, o)
+    e_ref, eps, f = ctx.reference()
+    assert abs(e_ref - pb.e_ref) < 1e-11
+    assert np.abs(f - pb.f).max() < 1e-13
+    v = n - o
+    t1, t2 = torch.zeros(o, v, dtype=torch.float64, device="cuda"), \
+        torch.zeros(o, o, v, v, dtype=torch.float64, device="cuda")
+    ctx.mp2_guess(t1, t2)
+    r1, r2 = qflow.mp2_guess(pb.f, eri, o)
+    assert np.abs(host(t1) - r1).max() < 1e-12
+    assert np.abs(host(t2) - r2).max() < 1e-13
+
+
+@pytest.mark.parametrize("n,o,seed", CASES)
+def test_residual_matches_oracle(n, o, seed):
+    _need_gpu()
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    v = n - o
+    t1, t2 = synth.random_amplitudes(o, v, seed + 7, scale=0.05)
+    ctx = context(h, eri, o)
+    r1 = torch.zeros(o, v, dtype=torch.float64, device="cuda")
+    r2 = torch.zeros(o, o, v, v, dtype=torch.float64, device="cuda")
+    e0 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.residual(dev(t1), dev(t2), r1, r2, e0)
+    torch.cuda.synchronize()
+    R1, R2, E0 = qflow.residual(pb, t1, t2)
+    assert np.abs(host(r1) - R1).max() < 1e-11
+    assert np.abs(host(r2) - R2).max() < 1e-11
+    assert abs(host(e0)[0] - E0) < 1e-10
+
+
+def _spaces_for(n, o, K, seed, eps):
+    if n == 8:
+        return [(s[0], s[1]) for s in sampling.enumerate_spaces(3, 5, 3, 3, eps)]
+    S = sampling.algorithm1(o, n - o, 3, 3, eps, synth.Stream(seed), cap=K)
+    return [(s[0], s[1]) for s in S]
+
+
+@pytest.mark.parametrize("n,o,seed,K", [(8, 3, 111, 10), (24, 4, 112, 12), (40, 5, 113, 6)])
+def test_heff_matches_oracle(n, o, seed, K):
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    v = n - o
+    t1, t2 = synth.random_amplitudes(o, v, seed + 1, scale=0.05)
+    lists = _spaces_for(n, o, K, seed, pb.eps)
+    sp = qf.make_spaces(lists)
+    off = qf.api.offsets(sp, qf.heff_size)
+    heff = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
+    ctx = context(h, eri, o)
+    ctx.build_heff(sp, dev(t1), dev(t2), heff, off)
+    torch.cuda.synchronize()
+    out = host(heff)
+    for k, (occ, vir) in enumerate(lists):
+        x = qflow.heff(pb, t1, t2, tuple(occ) + tuple(vir))
+        ec, hs, g = qflow.cas_integrals(*x, len(occ))
+        na = len(occ) + len(vir)
+        blk = out[off[k]:off[k + 1]]
+        assert abs(blk[0] - ec) < 1e-10, k
+        assert np.abs(blk[1:1 + na * na].reshape(na, na) - hs).max() < 1e-11, k
+        assert np.abs(blk[1 + na * na:].reshape(na, na, na, na) - g).max() < 1e-11, k
+
+
+@pytest.mark.parametrize("n,o,seed,K,start", [(8, 3, 121, 10, "random"), (24, 4, 122, 8, "mp2"),
+                                               (24, 4, 123, 4, "random")])
+def test_solve_matches_dense_eigensolver(n, o, seed, K, start):
+    """Energies always; reference weight and amplitudes where the space's
+    ground state keeps a reference weight >= 0.1 (else the status must be
+    QFLOW_E_REF_WEIGHT, as it is for large random pools on 24 orbitals)."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    v = n - o
+    if start == "mp2":
+        t1, t2 = qflow.mp2_guess(pb.f, eri, o)
+    else:
+        t1, t2 = synth.random_amplitudes(o, v, seed + 1, scale=0.05)
+    lists = _spaces_for(n, o, K, seed, pb.eps)
+    sp = qf.make_spaces(lists)
+    hoff = qf.api.offsets(sp, qf.heff_size)
+    aoff = qf.api.offsets(sp, qf.amp_size)
+    K = len(lists)
+    heff = torch.zeros(int(hoff[-1]), dtype=torch.float64, device="cuda")
+    amp = torch.zeros(int(aoff[-1]), dtype=torch.float64, device="cuda")
+    energy = torch.zeros(K, dtype=torch.float64, device="cuda")
+    c0 = torch.zeros(K, dtype=torch.float64, device="cuda")
+    iters = torch.zeros(K, dtype=torch.int32, device="cuda")
+    status = torch.zeros(K, dtype=torch.int32, device="cuda")
+    ctx = context(h, eri, o)
+    ctx.build_heff(sp, dev(t1), dev(t2), heff, hoff)
+    ctx.solve_active_batch(sp, heff, hoff, energy, c0, amp, aoff, iters, status)
+    torch.cuda.synchronize()
+    E, C0, A, st = host(energy), host(c0), host(amp), host(status)
+    for k, (occ, vir) in enumerate(lists):
+        s = qflow.solve_space(pb, t1, t2, tuple(occ) + tuple(vir), len(occ))
+        assert abs(E[k] - s["E"]) < 1e-9
+        if s["c0"] < 0.1:
+            assert st[k] == -6
+            continue
+        assert st[k] == 0
+        assert abs(C0[k] - s["c0"]) < 1e-8
+        nt1 = len(occ) * len(vir)
+        blk = A[aoff[k]:aoff[k + 1]]
+        assert np.abs(blk[:nt1] - s["t1"].reshape(-1)).max() < 1e-8
+        assert np.abs(blk[nt1:] - s["t2"].reshape(-1)).max() < 1e-8
+
+
+def _flow_parity(n, o, seed, K, iters, start, flags=0):
+    import paper_2606_04186_amd as qf
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    v = n - o
+    lists = _spaces_for(n, o, K, seed, pb.eps)
+    o1, o2 = sampling.ownership(o, v, lists)
+    if start == "zero":
+        t1, t2 = np.zeros((o, v)), np.zeros((o, o, v, v))
+    else:
+        t1, t2 = qflow.mp2_guess(pb.f, eri, o)
+    sp = qf.make_spaces(lists)
+    ctx = context(h, eri, o)
+    g1, g2 = dev(t1), dev(t2)
+    energy = torch.zeros(len(lists), dtype=torch.float64, device="cuda")
+    d1, d2 = dev(o1, torch.int32), dev(o2, torch.int32)
+    for it in range(iters):
+        em, _ = ctx.flow_step(sp, d1, d2, g1, g2, energy, flags)
+        t1, t2, E, Em, _s = qflow.flow_step(
+            pb, t1, t2, lists, o1, o2, unowned="frozen" if flags else "residual")
+        assert abs(em - Em) < 1e-9, it
+        assert np.abs(host(energy) - E).max() < 1e-9, it
+        assert np.abs(host(g1) - t1).max() < 1e-8, it
+        assert np.abs(host(g2) - t2).max() < 1e-8, it
+
+
+def test_flow_step_matches_oracle_eight_orbitals():
+    _need_gpu()
+    _flow_parity(8, 3, 131, 10, 3, "zero")
+
+
+def test_flow_step_matches_oracle_partial_coverage():
+    """Partial coverage: unowned amplitudes take the residual step."""
+    _need_gpu()
+    _flow_parity(24, 4, 132, 12, 2, "mp2")
+
+
+def test_flow_step_frozen_unowned():
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    _flow_parity(24, 4, 133, 6, 1, "mp2", flags=qf.UNOWNED_FROZEN)
+
+
+def test_whole_space_equals_fci():
+    """One (3,3) space holding all six orbitals: the flow energy is the FCI
+    energy for any amplitude pool."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    n, o = 6, 3
+    h, eri = problem(n, o, 141)
+    H, _ = sector_hamiltonian(h, eri, n, o, o)
+    e_fci = np.linalg.eigvalsh(H)[0]
+    lists = [((0, 1, 2), (3, 4, 5))]
+    o1, o2 = sampling.ownership(o, 3, lists)
+    t1, t2 = synth.random_amplitudes(o, 3, 142, scale=0.05)
+    ctx = context(h, eri, o)
+    g1, g2 = dev(t1), dev(t2)
+    energy = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        em, _ = ctx.flow_step(qf.make_spaces(lists), dev(o1, torch.int32), dev(o2, torch.int32),
+                              g1, g2, energy)
+        assert abs(em - e_fci) < 1e-10
+
+
+def test_symmetry_and_argument_errors():
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    n, o = 8, 3
+    h, eri = problem(n, o, 151)
+    ctx = qf.Context(0)
+    bad = eri.copy()
+    bad[0, 1, 2, 3] += 1e-6
+    with pytest.raises(qf.QFlowError) as e:
+        ctx.load_integrals(dev(h), dev(bad), o)
+    assert e.value.code == -2
+    bad = eri.copy()
+    bad[1, 1, 1, 1] = np.nan
+    with pytest.raises(qf.QFlowError) as e:
+        ctx.load_integrals(dev(h), dev(bad), o)
+    assert e.value.code == -2
+    with pytest.raises(qf.QFlowError) as e:
+        ctx.residual(dev(np.zeros((o, 5))), dev(np.zeros((o, o, 5, 5))),
+                     dev(np.zeros((o, 5))), dev(np.zeros((o, o, 5, 5))), dev(np.zeros(1)))
+    assert e.value.code == -7   # nothing loaded
+    ctx.load_integrals(dev(h), dev(eri), o)
+    sp = qf.make_spaces([((0, 1, 2), (3, 4, 9))])   # orbital 9 out of range
+    heff = torch.zeros(2000, dtype=torch.float64, device="cuda")
+    with pytest.raises(qf.QFlowError) as e:
+        ctx.build_heff(sp, dev(np.zeros((o, 5))), dev(np.zeros((o, o, 5, 5))), heff,
+                       np.array([0, 1333], dtype=np.int64))
+    assert e.value.code == -1
+    sp = qf.make_spaces([((0, 1), (3, 4, 5))])       # (2,3) not supported
+    with pytest.raises(qf.QFlowError) as e:
+        ctx.build_heff(sp, dev(np.zeros((o, 5))), dev(np.zeros((o, o, 5, 5))), heff,
+                       np.array([0, 1333], dtype=np.int64))
+    assert e.value.code == -8

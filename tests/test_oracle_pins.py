@@ -322,3 +322,19 @@ def test_residual_iteration_reaches_zero_residual():
                         - e[:o][:, None, None, None] - e[:o][None, :, None, None])
     R1, R2, _ = qflow.residual(pb, t1, t2)
     assert max(np.abs(R1).max(), np.abs(R2).max()) < 1e-10
+
+
+def test_cas_integrals_reproduce_space_spectrum():
+    """The vacuum-form integrals of a space, fed to a brute-force determinant
+    Hamiltonian, give the spectrum of the space's normal-ordered operator."""
+    n, o = 6, 3
+    h, eri = small_problem(n, o, 55)
+    pb = qflow.Problem(h, eri, o)
+    t1, t2 = synth.random_amplitudes(o, n - o, 56, scale=0.1)
+    orbs = (0, 2, 3, 5)
+    x = qflow.heff(pb, t1, t2, orbs)
+    ec, hs, g = qflow.cas_integrals(*x, 2)
+    Hb, _ = sector_hamiltonian(hs, g, 4, 2, 2, e_core=ec)
+    w1 = np.linalg.eigvalsh(Hb)
+    w2 = np.linalg.eigvalsh(qflow.cas_matrix(*x, 2))
+    assert np.abs(w1 - w2).max() < 1e-12
