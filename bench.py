@@ -1,0 +1,160 @@
+"""Throughput of the QFlow hot path on one MI355X.
+
+One step = one QFlow macro-iteration (qflow_flow_step): the [F,sigma]
+intermediate, the ladder contractions, the global residual, every active
+space's downfolded Hamiltonian, the batched Davidson solves, cluster analysis
+and the pool update, on the 114-orbital workload (13 occupied, 101 virtual,
+4096 (6e,6o) active spaces drawn by Algorithm 1, MP2 start, synthetic
+integrals).  Inputs are resident in HBM before the timed region.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4]
+                    [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c4")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-spaces", type=int, default=1)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of the path is a design note, not a measured configuration.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2606_04186_amd as qf
+    import synth
+
+    cfg = synth.CONFIGS[args.config]
+    n, o, K = cfg["n"], cfg["o"], cfg["K"]
+    v = n - o
+    print(f"[bench] generating {args.config}: n={n} o={o} L={cfg['L']} K={K}", file=sys.stderr,
+          flush=True)
+    h, eri = synth.config_integrals(args.config)
+    dev = torch.device("cuda:0")
+    ctx = qf.Context(0)
+    ctx.load_integrals(torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev), o)
+    e_ref, eps, _ = ctx.reference()
+    u = synth.sampling_stream(args.config).uniform(64 * K)
+    no, nv = cfg["sizes"][0]
+    spaces, _, _ = qf.sample_spaces(o, v, no, nv, eps, u, cap=K)
+    assert len(spaces) == K
+    o1, o2 = qf.build_owners(o, v, spaces)
+    d1 = torch.from_numpy(o1).to(dev)
+    d2 = torch.from_numpy(o2).to(dev)
+    t1 = torch.zeros(o, v, dtype=torch.float64, device=dev)
+    t2 = torch.zeros(o, o, v, v, dtype=torch.float64, device=dev)
+    ctx.mp2_guess(t1, t2)
+    energy = torch.zeros(K, dtype=torch.float64, device=dev)
+    print("[bench] warmup", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        ctx.flow_step(spaces, d1, d2, t1, t2, energy)
+    stages = []
+    e_means = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        em, dt = ctx.flow_step(spaces, d1, d2, t1, t2, energy)
+        stages.append(ctx.last_timings())
+        e_means.append(em)
+        print(f"[bench] step {k} E_mean {em:.10f} max|dt| {dt:.3e} {stages[-1]}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1_ = time.perf_counter()
+    ms = (t1_ - t0) * 1e3 / args.steps
+    st = {key: float(np.mean([s[key] for s in stages])) for key in stages[0]}
+
+    # dominant kernel and its roofline
+    dom = max(st, key=st.get)
+    ladder_flops = 2.0 * (n * n) * (o * o) * (v * v)        # one ladder contraction
+    if dom in ("ladder_h", "ladder_yg"):
+        achieved = ladder_flops / (st[dom] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved,
+                "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None}
+    else:
+        roof = {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None,
+                "frac": None, "traffic": None}
+    ladder = {"kernel": "ladder_h", "tflops": ladder_flops / (st["ladder_h"] * 1e-3) / 1e12,
+              "frac_fp64_mfma": ladder_flops / (st["ladder_h"] * 1e-3) / 1e12
+              / FP64_MFMA_PEAK_TFLOPS}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(h, eri, o, spaces, args.cpu_sample_spaces, K)
+
+    out = {
+        "metric": "QFlow macro-iterations/s (114 orbitals, FP64 path)",
+        "value": 1e3 / ms,
+        "unit": "macro-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {n} orbitals ({o} occ, {v} virt), K={K} "
+                               f"({no},{nv}) active spaces, MP2 start",
+                   "n_orb": n, "n_occ": o, "K": K, "space": [no, nv],
+                   "e_ref": e_ref, "e_mean_last": e_means[-1]},
+        "stage_ms": st,
+        "ladder": ladder,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(h, eri, o, spaces, m, K):
+    """The oracle on a bounded sample: the full per-space work (downfolded
+    Hamiltonian, CAS eigenproblem, cluster analysis) of the first m spaces,
+    scaled to one macro-iteration of K spaces.  The oracle's global residual
+    and update are not in the sample, so the figure is an upper bound on its
+    rate."""
+    from oracle import qflow
+    pb = qflow.Problem(h, eri, o)
+    t1, t2 = qflow.mp2_guess(pb.f, eri, o)
+    t0 = time.perf_counter()
+    for s in spaces[:m]:
+        orbs = tuple(int(x) for x in s["orb"][: s["n_o"] + s["n_v"]])
+        qflow.solve_space(pb, t1, t2, orbs, int(s["n_o"]))
+    dt = (time.perf_counter() - t0) / m
+    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    return {"value": 1.0 / (dt * K), "unit": "macro-iterations/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{m} of {K} active spaces (H_eff + CAS eigenproblem + cluster analysis), "
+                      f"{dt:.1f} s each, scaled by K; residual and update excluded"}
+
+
+if __name__ == "__main__":
+    main()

@@ -154,9 +154,11 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
                     const int32_t* owner2, double* t1, double* t2, double* energy, double* e_mean,
                     double* max_dt, int32_t flags);
 
-/* Per-stage device times of the last qflow_flow_step in milliseconds, in
- * the order: intermediates (Yg), ladder contractions, residual, build_heff,
- * solve, update.  n is the capacity of ms (host). Returns the count written. */
+/* Per-stage device times of the last qflow_flow_step in milliseconds (HIP
+ * events on the context's stream), in the order: [F,sigma] intermediate,
+ * ladder contraction of H_N, ladder contraction of [F,sigma], residual,
+ * build_heff, solve, update.  n is the capacity of ms (host).  Returns the
+ * count written. */
 int qflow_last_timings(const qflow_ctx* ctx, float* ms, int n);
 
 /* Algorithm 1 (coverage-driven active-space sampling), host only.

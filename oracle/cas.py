@@ -22,12 +22,7 @@ import numpy as np
 
 
 def _popcount_below(bits: np.ndarray, p: int) -> np.ndarray:
-    x = bits & ((1 << p) - 1)
-    c = np.zeros_like(x)
-    while np.any(x):
-        c += x & 1
-        x = x >> 1
-    return c
+    return np.bitwise_count(bits & ((1 << p) - 1)).astype(np.int64)
 
 
 def _apply(ops, dets: np.ndarray):

@@ -62,6 +62,11 @@ class Blocks:
         return out
 
 
+def _es(spec, *ops):
+    """np.einsum with a BLAS-backed contraction order."""
+    return np.einsum(spec, *ops, optimize=True)
+
+
 def spin_delta(I, J):
     return (np.asarray(I)[:, None] % 2 == np.asarray(J)[None, :] % 2).astype(float)
 
@@ -150,27 +155,40 @@ class Cluster(Op):
     def nz2(self, a, b, c, d):
         return (a == b == "v" and c == d == "o") or (a == b == "o" and c == d == "v")
 
+    def _full(self):
+        """Dense spin-orbital t1[2o,2v] and antisymmetric t2[2o,2o,2v,2v]
+        (built once; slices are cut from them)."""
+        if getattr(self, "_so", None) is None:
+            o, v = self.o, self.t1.shape[1]
+            i = np.arange(2 * o)
+            a = np.arange(2 * o, 2 * (o + v))
+            I, A = i // 2, a // 2 - o
+            t1 = self.t1[np.ix_(I, A)] * spin_delta(i, a)
+            d = self.t2[np.ix_(I, I, A, A)]
+            d = d * spin_delta(i, a)[:, None, :, None] * spin_delta(i, a)[None, :, None, :]
+            e = self.t2[np.ix_(I, I, A, A)].transpose(1, 0, 2, 3)
+            e = e * spin_delta(i, a)[None, :, :, None] * spin_delta(i, a)[:, None, None, :]
+            self._so = (t1, d - e)
+        return self._so
+
     def _t1(self, i, a):
         """spin-orbital t_{i,a}: i occupied, a virtual (arrays)."""
-        I, A = i // 2, a // 2 - self.o
-        x = self.t1[np.ix_(I, A)] * spin_delta(i, a)
+        o2 = 2 * self.o
+        x = self._full()[0][np.ix_(i, a - o2)]
         if self.mask is not None:
-            x = x * ~(self.mask[I][:, None] & self.mask[a // 2][None, :])
+            mi, ma = np.nonzero(self.mask[i // 2])[0], np.nonzero(self.mask[a // 2])[0]
+            x[np.ix_(mi, ma)] = 0.0
         return x
 
     def _t2(self, i, j, a, b):
-        """spin-orbital t_{ij}^{ab} (antisymmetric), shape [i,j,a,b]."""
-        I, J, A, B = i // 2, j // 2, a // 2 - self.o, b // 2 - self.o
-        d = self.t2[np.ix_(I, J, A, B)]
-        d = d * spin_delta(i, a)[:, None, :, None] * spin_delta(j, b)[None, :, None, :]
-        e = self.t2[np.ix_(J, I, A, B)].transpose(1, 0, 2, 3)
-        e = e * spin_delta(j, a)[None, :, :, None] * spin_delta(i, b)[:, None, None, :]
-        x = d - e
+        """spin-orbital t_{ij}^{ab} (antisymmetric), shape [i,j,a,b]:
+        t2[i,j,a,b] for opposite spins, t2[i,j,a,b] - t2[i,j,b,a] for equal."""
+        o2 = 2 * self.o
+        x = self._full()[1][np.ix_(i, j, a - o2, b - o2)]
         if self.mask is not None:
             m = self.mask
-            inside = (m[I][:, None, None, None] & m[J][None, :, None, None]
-                      & m[a // 2][None, None, :, None] & m[b // 2][None, None, None, :])
-            x = x * ~inside
+            sub = [np.nonzero(m[k // 2])[0] for k in (i, j, a, b)]
+            x[np.ix_(*sub)] = 0.0      # amplitudes with every index in the space
         return x
 
     def one(self, I, J):
@@ -200,12 +218,12 @@ def comm0(A: Op, B: Op, bl: Blocks) -> float:
     # sum_tu (n_t - n_u) A_tu B_ut : only (t,u) in (o,v) or (v,o) survive
     for (T, U, w) in ((O, V, 1.0), (V, O, -1.0)):
         if A.nz1(T[0], U[0]) and B.nz1(U[0], T[0]):
-            z += w * np.einsum("tu,ut->", A.one(T, U), B.one(U, T))
+            z += w * _es("tu,ut->", A.one(T, U), B.one(U, T))
     # 1/4 sum n_t n_u nb_w nb_x (A_tuwx B_wxtu - B_tuwx A_wxtu)
     if A.nz2("o", "o", "v", "v") and B.nz2("v", "v", "o", "o"):
-        z += 0.25 * np.einsum("tuwx,wxtu->", A.two(O, O, V, V), B.two(V, V, O, O))
+        z += 0.25 * _es("tuwx,wxtu->", A.two(O, O, V, V), B.two(V, V, O, O))
     if B.nz2("o", "o", "v", "v") and A.nz2("v", "v", "o", "o"):
-        z -= 0.25 * np.einsum("tuwx,wxtu->", B.two(O, O, V, V), A.two(V, V, O, O))
+        z -= 0.25 * _es("tuwx,wxtu->", B.two(O, O, V, V), A.two(V, V, O, O))
     return float(z)
 
 
@@ -219,11 +237,11 @@ def _comm1_ordered(A: Op, B: Op, P, Q, bl: Blocks) -> np.ndarray:
             out += A.one(P, T) @ B.one(T, Q)
     for (T, U, w) in ((O, V, 1.0), (V, O, -1.0)):
         if A.nz1(T[0], U[0]) and B.nz2(U[0], P[0], T[0], Q[0]):
-            out += w * np.einsum("tu,uptq->pq", A.one(T, U), B.two(U, P, T, Q))
+            out += w * _es("tu,uptq->pq", A.one(T, U), B.two(U, P, T, Q))
     # (t,u occupied, w virtual) and (t,u virtual, w occupied)
     for (T, W) in ((O, V), (V, O)):
         if A.nz2(W[0], P[0], T[0], T[0]) and B.nz2(T[0], T[0], W[0], Q[0]):
-            out += 0.5 * np.einsum("wptu,tuwq->pq", A.two(W, P, T, T), B.two(T, T, W, Q))
+            out += 0.5 * _es("wptu,tuwq->pq", A.two(W, P, T, T), B.two(T, T, W, Q))
     return out
 
 
@@ -240,9 +258,9 @@ def _g1(A, B, P, Q, R, S, bl):
     out = _z(P, Q, R, S)
     for T in (("o", bl.O), ("v", bl.V)):
         if A.nz1(P[0], T[0]) and B.nz2(T[0], Q[0], R[0], S[0]):
-            out += np.einsum("pt,tqrs->pqrs", A.one(P, T), B.two(T, Q, R, S))
+            out += _es("pt,tqrs->pqrs", A.one(P, T), B.two(T, Q, R, S))
         if B.nz1(P[0], T[0]) and A.nz2(T[0], Q[0], R[0], S[0]):
-            out -= np.einsum("pt,tqrs->pqrs", B.one(P, T), A.two(T, Q, R, S))
+            out -= _es("pt,tqrs->pqrs", B.one(P, T), A.two(T, Q, R, S))
     return out
 
 
@@ -251,9 +269,9 @@ def _g2(A, B, P, Q, R, S, bl):
     out = _z(P, Q, R, S)
     for T in (("o", bl.O), ("v", bl.V)):
         if A.nz1(T[0], R[0]) and B.nz2(P[0], Q[0], T[0], S[0]):
-            out += np.einsum("tr,pqts->pqrs", A.one(T, R), B.two(P, Q, T, S))
+            out += _es("tr,pqts->pqrs", A.one(T, R), B.two(P, Q, T, S))
         if B.nz1(T[0], R[0]) and A.nz2(P[0], Q[0], T[0], S[0]):
-            out -= np.einsum("tr,pqts->pqrs", B.one(T, R), A.two(P, Q, T, S))
+            out -= _es("tr,pqts->pqrs", B.one(T, R), A.two(P, Q, T, S))
     return out
 
 
@@ -262,9 +280,9 @@ def _ph(A, B, P, Q, R, S, bl):
     O, V = ("o", bl.O), ("v", bl.V)
     out = _z(P, Q, R, S)
     if A.nz2(P[0], "o", "v", R[0]) and B.nz2("v", Q[0], "o", S[0]):
-        out -= np.einsum("putr,tqus->pqrs", A.two(P, O, V, R), B.two(V, Q, O, S))
+        out -= _es("putr,tqus->pqrs", A.two(P, O, V, R), B.two(V, Q, O, S))
     if B.nz2(P[0], "o", "v", R[0]) and A.nz2("v", Q[0], "o", S[0]):
-        out += np.einsum("putr,tqus->pqrs", B.two(P, O, V, R), A.two(V, Q, O, S))
+        out += _es("putr,tqus->pqrs", B.two(P, O, V, R), A.two(V, Q, O, S))
     return out
 
 
@@ -278,9 +296,9 @@ def comm2(A: Op, B: Op, P, Q, R, S, bl: Blocks) -> np.ndarray:
     # 1/2 sum_tu (1 - n_t - n_u)(...): only t,u in the same block survive
     for (T, w) in ((V, 0.5), (O, -0.5)):
         if A.nz2(P[0], Q[0], T[0], T[0]) and B.nz2(T[0], T[0], R[0], S[0]):
-            out += w * np.einsum("pqtu,turs->pqrs", A.two(P, Q, T, T), B.two(T, T, R, S))
+            out += w * _es("pqtu,turs->pqrs", A.two(P, Q, T, T), B.two(T, T, R, S))
         if B.nz2(P[0], Q[0], T[0], T[0]) and A.nz2(T[0], T[0], R[0], S[0]):
-            out -= w * np.einsum("pqtu,turs->pqrs", B.two(P, Q, T, T), A.two(T, T, R, S))
+            out -= w * _es("pqtu,turs->pqrs", B.two(P, Q, T, T), A.two(T, T, R, S))
     # (1-P_pq)(1-P_rs) X_pqrs
     out += (_ph(A, B, P, Q, R, S, bl)
             - _ph(A, B, Q, P, R, S, bl).transpose(1, 0, 2, 3)

@@ -184,10 +184,13 @@ class Context:
                                           ctypes.byref(md), flags))
         return em.value, md.value
 
+    STAGES = ("yg", "ladder_h", "ladder_yg", "residual", "heff", "solve", "update")
+
     def last_timings(self):
-        ms = np.zeros(6, dtype=np.float32)
-        c = lib().qflow_last_timings(self.h, _ptr(ms), 6)
-        return ms[:c]
+        """Per-stage device milliseconds of the last flow_step (STAGES order)."""
+        ms = np.zeros(len(self.STAGES), dtype=np.float32)
+        c = lib().qflow_last_timings(self.h, _ptr(ms), len(self.STAGES))
+        return dict(zip(self.STAGES, ms[:c].tolist()))
 
 
 def sample_spaces(No, Nv, no, nv, eps, uniforms, cap=0, max_out=None):

@@ -84,7 +84,6 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f64(const double* __restrict__ 
 
 void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int N, int K,
                         hipStream_t st) {
-  launch_fill(C, (size_t)M * N, 0.0, st);
   int kchunk = (K + 1) / 2;
   kchunk = (kchunk + kGemmBK - 1) / kGemmBK * kGemmBK;
   const int splits = (K + kchunk - 1) / kchunk;

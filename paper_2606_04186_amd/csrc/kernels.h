@@ -25,7 +25,7 @@ void launch_mp2(const double* f, const double* V, int n, int o, double* t1, doub
 void launch_yg(const double* f, const double* t1, const double* t2, int n, int o, double* y1,
                double* y2, double* wy, double* scal, hipStream_t st);
 void launch_fill(double* x, size_t count, double value, hipStream_t st);
-// C[M][N] = sum_k A[m][k] B[n][k], FP64 matrix cores
+// C[M][N] += sum_k A[m][k] B[n][k], FP64 matrix cores (C must hold zeros)
 void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int N, int K,
                         hipStream_t st);
 
