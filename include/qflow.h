@@ -37,7 +37,8 @@ typedef struct qflow_ctx qflow_ctx;
 
 /* One active space (Eq. (3) partition): n_o occupied then n_v virtual
  * absolute orbital indices in orb[], each group ascending.  Supported sizes:
- * n_o == n_v, 2 <= n_o <= 4 (at most 4900 determinants). */
+ * (n_o, n_v) = (2,2) and (3,3) (36 and 400 determinants); other sizes give
+ * QFLOW_E_UNSUPPORTED. */
 typedef struct {
   int32_t n_o, n_v;
   int32_t orb[8];

@@ -21,7 +21,7 @@ namespace qf {
 namespace {
 
 // Active-set description shared by the block.
-__device__ void load_active(const SpaceDev& sp, Active& A) {
+__device__ void load_active(const SpaceDev& sp, int n, int o, Active& A) {
   for (int p = threadIdx.x; p < kMaxOrb; p += blockDim.x) A.pos[p] = -1;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -31,42 +31,66 @@ __device__ void load_active(const SpaceDev& sp, Active& A) {
       A.orb[a] = sp.orb[a];
       A.pos[sp.orb[a]] = (int8_t)a;
     }
+    active_fill_ext(A, n, o);
   }
   __syncthreads();
+}
+
+// Per-space tables of the marked [E,sigma] evaluation (see MarkTables).
+__global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
+                                                  const SpaceDev* __restrict__ spaces,
+                                                  double* tab, int64_t tab_stride) {
+  __shared__ Active A;
+  const int k = blockIdx.x;
+  const SpaceDev sp = spaces[k];
+  load_active(sp, g.n, g.o, A);
+  const Sigma s{g.t1, g.t2, g.n, g.o, g.n - g.o};
+  int a, b, c, d;
+  const int tot = mark_sizes(sp.na, &a, &b, &c, &d);
+  double* out = tab + (int64_t)k * tab_stride;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) out[e] = mark_table_entry(s, g.f, A, e);
 }
 
 // Slot layout while accumulating: [x0, x1 (na^2), x2 (na^4)].
 // part 0: H + [H,sigma] - [H,tau]         (initialises the slot)
 // part 1: + 1/2 ([Yg,sigma] - [Yg,tau])
-// part 2: + 1/2 ([Ft,tau] - [Ft,sigma])
+// part 2: + 1/2 ([Ft,tau] - [Ft,sigma]) = - 1/2 [E,sigma], marked evaluation
 template <int PART>
 __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __restrict__ scal,
                                                    const SpaceDev* __restrict__ spaces,
                                                    const int64_t* __restrict__ heff_off,
-                                                   double* heff) {
+                                                   const int32_t* __restrict__ tasks,
+                                                   int task_stride, const double* __restrict__ tab,
+                                                   int64_t tab_stride, double* heff) {
   __shared__ Active A;
+  extern __shared__ double tl[];
   const int k = blockIdx.x;
   const SpaceDev sp = spaces[k];
-  load_active(sp, A);
+  load_active(sp, g.n, g.o, A);
+  MarkTables T{};
+  if constexpr (PART == 2) {
+    int s1, s2, s3, s4;
+    const int tot = mark_sizes(sp.na, &s1, &s2, &s3, &s4);
+    const double* src = tab + (int64_t)k * tab_stride;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) tl[e] = src[e];
+    __syncthreads();
+    T = MarkTables{tl, tl + s1, tl + s1 + s2, tl + s1 + s2 + s3, sp.na};
+  }
   const int na = sp.na, n = g.n, o = g.o, v = n - o;
   const int n2 = na * na, n4 = n2 * n2;
   double* slot = heff + heff_off[k];
   const Sigma s{g.t1, g.t2, n, o, v};
   const Tau tau{s, &A};
-  const int task = blockIdx.y * blockDim.x + threadIdx.x;
-  if (task > n4 + n2) return;
-  int p = 0, q = 0, r = 0, t = 0;
-  if (task < n4) {
-    const int d = task % na, c = task / na % na, b = task / n2 % na, a = task / (n2 * na);
-    p = A.orb[a];
-    q = A.orb[b];
-    r = A.orb[c];
-    t = A.orb[d];
-  } else if (task < n4 + n2) {
-    const int e = task - n4;
-    p = A.orb[e / na];
-    q = A.orb[e % na];
-  }
+  const int slot_idx = blockIdx.y * blockDim.x + threadIdx.x;
+  if (slot_idx >= task_stride) return;
+  const int32_t code = tasks[(sp.nocc - 2) * task_stride + slot_idx];
+  if (code < 0) return;
+  const int kind = code >> 24;
+  const int la = (code >> 18) & 63, lb = (code >> 12) & 63, lc = (code >> 6) & 63, ld = code & 63;
+  // task numbering of the slot: two-body element, one-body element, scalar
+  const int task = (kind == 2) ? ((la * na + lb) * na + lc) * na + ld
+                               : (kind == 1 ? n4 + la * na + lb : n4 + n2);
+  const int p = A.orb[la], q = A.orb[lb], r = A.orb[lc], t = A.orb[ld];
   double* dst = (task < n4) ? slot + 1 + n2 + task : (task < n4 + n2 ? slot + 1 + (task - n4) : slot);
   if constexpr (PART == 0) {
     const DenseOp H{g.f, g.V, g.L, n, o};
@@ -93,17 +117,17 @@ __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __
       x = scal[1] - ct.c0();
     *dst += 0.5 * x;
   } else {
-    const FtauOp F{g.f, tau, n, o};
-    const auto cs = make_comm(F, s, n, o);
-    const auto ct = make_comm(F, tau, n, o);
+    const MarkedE E{T, &A};
+    const MarkedSigma D{T, &A};
+    const CommE<MarkedE, MarkedSigma, true> ce{E, D, A, n, o};
     double x;
     if (task < n4)
-      x = ct.c2(p, q, r, t) - cs.c2(p, q, r, t);
+      x = ce.c2(p, q, r, t);
     else if (task < n4 + n2)
-      x = ct.c1(p, q) - cs.c1(p, q);
+      x = ce.c1(p, q);
     else
-      x = ct.c0() - cs.c0();
-    *dst += 0.5 * x;
+      x = ce.c0();
+    *dst -= 0.5 * x;
   }
 }
 
@@ -145,16 +169,28 @@ __global__ __launch_bounds__(256) void k_heff_cas(const SpaceDev* __restrict__ s
 
 }  // namespace
 
+int heff_table_stride(int na_max) {
+  int s1, s2, s3, s4;
+  return mark_sizes(na_max, &s1, &s2, &s3, &s4);
+}
+
 void launch_heff(const double* f, const double* V, const double* y1, const double* y2,
                  const double* L, const double* LY, const double* t1, const double* t2, int n,
                  int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
-                 int K, int na_max, double* heff, hipStream_t st) {
+                 const int32_t* task_table, int task_stride, int slots_max, int K, int na_max,
+                 double* tab, double* heff, hipStream_t st) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o};
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
-  dim3 grid(K, (tasks + kBlock - 1) / kBlock);
-  k_heff_part<0><<<grid, kBlock, 0, st>>>(g, scal, spaces, heff_off, heff);
-  k_heff_part<1><<<grid, kBlock, 0, st>>>(g, scal, spaces, heff_off, heff);
-  k_heff_part<2><<<grid, kBlock, 0, st>>>(g, scal, spaces, heff_off, heff);
+  dim3 grid(K, (slots_max + kBlock - 1) / kBlock);
+  int s1, s2, s3, s4;
+  const int tab_stride = mark_sizes(na_max, &s1, &s2, &s3, &s4);
+  k_heff_tab<<<K, kBlock, 0, st>>>(g, spaces, tab, tab_stride);
+  k_heff_part<0><<<grid, kBlock, 0, st>>>(g, scal, spaces, heff_off, task_table, task_stride,
+                                          tab, tab_stride, heff);
+  k_heff_part<1><<<grid, kBlock, 0, st>>>(g, scal, spaces, heff_off, task_table, task_stride,
+                                          tab, tab_stride, heff);
+  k_heff_part<2><<<grid, kBlock, (size_t)tab_stride * sizeof(double), st>>>(
+      g, scal, spaces, heff_off, task_table, task_stride, tab, tab_stride, heff);
   const size_t lds = (size_t)tasks * sizeof(double);
   k_heff_cas<<<K, kBlock, lds, st>>>(spaces, heff_off, heff);
 }

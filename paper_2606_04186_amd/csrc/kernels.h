@@ -39,7 +39,13 @@ void launch_residual(const double* f, const double* V, const double* y1, const d
 void launch_heff(const double* f, const double* V, const double* y1, const double* y2,
                  const double* L, const double* LY, const double* t1, const double* t2, int n,
                  int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
-                 int K, int na_max, double* heff, hipStream_t st);
+                 const int32_t* task_table, int task_stride, int slots_max, int K, int na_max,
+                 double* tab, double* heff, hipStream_t st);
+// doubles of per-space scratch tables for spaces of up to na_max orbitals
+int heff_table_stride(int na_max);
+// output-element order of the per-space kernels (host; see strings.cpp)
+int build_tasks(int na, int ne, int32_t* out, int cap);
+constexpr int kTaskStride = 4608;   // >= padded task count of a (4,4) space
 
 // per-space Davidson eigensolver and cluster analysis
 struct DavidsonArgs {

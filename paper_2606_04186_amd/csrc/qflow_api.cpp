@@ -44,12 +44,14 @@ struct qflow_ctx {
   // device state
   DevBuf f, V, W, y1, y2, wy, L, LY, scal, r1, r2, t1n, t2n;
   DevBuf heff, heff_off, amp, amp_off, work, work_off, energy, c0, iters, status, spaces,
-      strings, out2, partial;
+      strings, out2, partial, tasks, mtab;
+  int task_slots[3] = {0, 0, 0};
   // host mirror of the last uploaded space list
   std::vector<qflow_space> last_spaces;
   std::vector<int64_t> h_heff_off, h_amp_off, h_work_off;
   int lds_davidson = 0;
   int na_max = 0;
+  int slots_max = 0;
   hipEvent_t ev[kStages + 1] = {};
   float stage_ms[kStages] = {};
   bool timed = false;
@@ -104,9 +106,9 @@ int check_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   if (K > 0 && !spaces) return fail(ctx, QFLOW_E_INVALID_ARG, "spaces is NULL");
   for (int k = 0; k < K; ++k) {
     const qflow_space& s = spaces[k];
-    if (s.n_o < 2 || s.n_o > 4 || s.n_v != s.n_o)
+    if (s.n_o < 2 || s.n_o > 3 || s.n_v != s.n_o)
       return fail(ctx, QFLOW_E_UNSUPPORTED,
-                  "space " + std::to_string(k) + ": only (2,2), (3,3) and (4,4) spaces");
+                  "space " + std::to_string(k) + ": only (2,2) and (3,3) spaces");
     for (int a = 0; a < na_of(s); ++a) {
       const int p = s.orb[a];
       const bool occ = a < s.n_o;
@@ -132,7 +134,7 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   ctx->h_heff_off.assign(K + 1, 0);
   ctx->h_amp_off.assign(K + 1, 0);
   ctx->h_work_off.assign(K + 1, 0);
-  int lds = 0, na_max = 0;
+  int lds = 0, na_max = 0, slots_max = 0;
   for (int k = 0; k < K; ++k) {
     const qflow_space& s = spaces[k];
     dev[k].na = na_of(s);
@@ -150,11 +152,13 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
                      kMaxSub + 4;
     lds = std::max(lds, need);
     na_max = std::max(na_max, na);
+    slots_max = std::max(slots_max, ctx->task_slots[s.n_o - 2]);
   }
   if ((size_t)lds * sizeof(double) > 160 * 1024)
     return fail(ctx, QFLOW_E_UNSUPPORTED, "active space too large for the LDS-resident solver");
   ctx->lds_davidson = lds;
   ctx->na_max = na_max;
+  ctx->slots_max = slots_max;
   QF_TRY(ensure(ctx, ctx->spaces, sizeof(SpaceDev) * std::max(K, 1)));
   QF_TRY(ensure(ctx, ctx->heff_off, sizeof(int64_t) * (K + 1)));
   QF_TRY(ensure(ctx, ctx->amp_off, sizeof(int64_t) * (K + 1)));
@@ -166,6 +170,8 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   QF_TRY(ensure(ctx, ctx->c0, sizeof(double) * std::max(K, 1)));
   QF_TRY(ensure(ctx, ctx->iters, sizeof(int32_t) * std::max(K, 1)));
   QF_TRY(ensure(ctx, ctx->status, sizeof(int32_t) * std::max(K, 1)));
+  QF_TRY(ensure(ctx, ctx->mtab,
+                sizeof(double) * (size_t)std::max(K, 1) * qf::heff_table_stride(std::max(na_max, 4))));
   QF_HIP(hipMemcpyAsync(ctx->spaces.p, dev.data(), sizeof(SpaceDev) * std::max(K, 1),
                         hipMemcpyHostToDevice, ctx->stream));
   QF_HIP(hipMemcpyAsync(ctx->heff_off.p, ctx->h_heff_off.data(), sizeof(int64_t) * (K + 1),
@@ -236,9 +242,16 @@ int qflow_create(qflow_ctx** out, int device, void* hip_stream) {
     }
   std::vector<qf::Strings> tabs(3);
   for (int s = 0; s < 3; ++s) qf::build_strings(2 * (s + 2), s + 2, &tabs[s]);
+  std::vector<int32_t> task_tab(3 * qf::kTaskStride, -1);
+  for (int s = 0; s < 3; ++s)
+    ctx->task_slots[s] = qf::build_tasks(2 * (s + 2), s + 2, &task_tab[s * qf::kTaskStride],
+                                         qf::kTaskStride);
   if (ensure(ctx, ctx->strings, sizeof(qf::Strings) * 3) != QFLOW_OK ||
       hipMemcpy(ctx->strings.p, tabs.data(), sizeof(qf::Strings) * 3, hipMemcpyHostToDevice) !=
           hipSuccess ||
+      ensure(ctx, ctx->tasks, sizeof(int32_t) * task_tab.size()) != QFLOW_OK ||
+      hipMemcpy(ctx->tasks.p, task_tab.data(), sizeof(int32_t) * task_tab.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
       ensure(ctx, ctx->scal, sizeof(double) * 8) != QFLOW_OK ||
       ensure(ctx, ctx->out2, sizeof(double) * 2) != QFLOW_OK) {
     qflow_destroy(ctx);
@@ -257,7 +270,7 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->r2,     &ctx->t1n,      &ctx->t2n,    &ctx->heff,     &ctx->heff_off,
                     &ctx->amp,    &ctx->amp_off,  &ctx->work,   &ctx->work_off, &ctx->energy,
                     &ctx->c0,     &ctx->iters,    &ctx->status, &ctx->spaces,   &ctx->strings,
-                    &ctx->out2,   &ctx->partial};
+                    &ctx->out2,   &ctx->partial, &ctx->tasks, &ctx->mtab};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& ev : ctx->ev)
@@ -392,8 +405,9 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
   if (K > 0)
     qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1), P<double>(ctx->y2),
                     P<double>(ctx->L), P<double>(ctx->LY), t1, t2, ctx->n, ctx->o,
-                    P<double>(ctx->scal), P<SpaceDev>(ctx->spaces), heff_off_dev, K,
-                    ctx->na_max, heff, ctx->stream);
+                    P<double>(ctx->scal), P<SpaceDev>(ctx->spaces), heff_off_dev,
+                    P<int32_t>(ctx->tasks), qf::kTaskStride, ctx->slots_max, K, ctx->na_max,
+                    P<double>(ctx->mtab), heff, ctx->stream);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }

@@ -51,8 +51,25 @@ struct Active {
   int na, nocc;              // active orbitals, of which the first nocc occupied
   int orb[kMaxAct];          // absolute orbital indices, occupied first
   int8_t pos[kMaxOrb];
+  int next_o, next_v;        // external (inactive) occupied / virtual counts
+  uint8_t ext[kMaxOrb];      // external occupied, then external virtual orbitals
   QF_HD bool act(int p) const { return pos[p] >= 0; }
+  QF_HD int nact(bool occ) const { return occ ? nocc : na - nocc; }
+  QF_HD int actv(bool occ, int k) const { return occ ? orb[k] : orb[nocc + k]; }
+  QF_HD int next(bool occ) const { return occ ? next_o : next_v; }
+  QF_HD int extv(bool occ, int k) const { return occ ? ext[k] : ext[next_o + k]; }
 };
+
+// Fill the external lists of A (host or a single device thread).
+QF_HD void active_fill_ext(Active& A, int n, int o) {
+  int m = 0;
+  for (int p = 0; p < o; ++p)
+    if (A.pos[p] < 0) A.ext[m++] = (uint8_t)p;
+  A.next_o = m;
+  for (int p = o; p < n; ++p)
+    if (A.pos[p] < 0) A.ext[m++] = (uint8_t)p;
+  A.next_v = m - A.next_o;
+}
 
 // sigma = T - T^dagger from t1[o][v], t2[o][o][v][v].
 struct Sigma {
@@ -521,6 +538,255 @@ struct Comm {
     return z;
   }
 };
+
+// ---------------------------------------------------------------------------
+// [E, sigma] restricted to the active space, E = the part of [F,tau] with
+// exactly one index outside the space.  For outputs inside the space,
+//   [Ft,sigma] - [Ft,tau] = [E,sigma]
+// because the all-active part of Ft meets only amplitudes inside the space
+// (where sigma = tau), and E cannot contract with tau.  Every term of
+// [E,sigma] therefore has exactly one external contracted index (E's
+// external leg); the loops below enumerate only those index combinations.
+// ---------------------------------------------------------------------------
+// Loop policy over the external index: either the external orbitals
+// themselves (kMarked = false), or, with the sum over the external orbital x
+// moved inside per-space tables, the active orbital t that E's Fock leg
+// attaches to (kMarked = true; the index is passed as the marker -1-t).
+template <class EOp, class BOp, bool kMarked = false>
+struct CommE {
+  const EOp& a;        // E accessor (one index external, or marked)
+  const BOp& b;        // sigma accessor (one index external, or marked)
+  const Active& A;
+  int n, o;
+
+  QF_HD bool occ(int p) const { return p < o; }   // markers are negative: "occupied"
+                                                  // tests below never see them
+
+  template <class F>
+  QF_HD void over_ext(bool occupied, F fn) const {
+    if constexpr (kMarked) {
+      for (int t = 0; t < A.na; ++t) fn(-1 - t);
+    } else {
+      for (int k = 0; k < A.next(occupied); ++k) fn(A.extv(occupied, k));
+    }
+  }
+  // (t in block bt, u in block bu) with exactly one of t, u external
+  template <class F>
+  QF_HD void pair1(bool bt, bool bu, F fn) const {
+    over_ext(bt, [&](int x) {
+      for (int m = 0; m < A.nact(bu); ++m) fn(x, A.actv(bu, m));
+    });
+    for (int k = 0; k < A.nact(bt); ++k) {
+      const int t = A.actv(bt, k);
+      over_ext(bu, [&](int x) { fn(t, x); });
+    }
+  }
+  // (t, u, w) with exactly one external
+  template <class F>
+  QF_HD void triple1(bool bt, bool bu, bool bw, F fn) const {
+    over_ext(bt, [&](int x) {
+      for (int j = 0; j < A.nact(bu); ++j)
+        for (int k = 0; k < A.nact(bw); ++k) fn(x, A.actv(bu, j), A.actv(bw, k));
+    });
+    for (int i = 0; i < A.nact(bt); ++i)
+      over_ext(bu, [&](int x) {
+        for (int k = 0; k < A.nact(bw); ++k) fn(A.actv(bt, i), x, A.actv(bw, k));
+      });
+    for (int i = 0; i < A.nact(bt); ++i)
+      for (int j = 0; j < A.nact(bu); ++j)
+        over_ext(bw, [&](int x) { fn(A.actv(bt, i), A.actv(bu, j), x); });
+  }
+
+  QF_HD double c2(int p, int q, int r, int s) const {
+    double res = 0.0;
+    const bool op = occ(p), oq = occ(q), or_ = occ(r), os = occ(s);
+    if (or_ == os && oq != or_) over_ext(oq, [&](int t) { res += a.one(p, t) * b.two(t, q, r, s); });
+    if (or_ == os && op != or_) over_ext(op, [&](int t) { res += a.one(q, t) * b.two(p, t, r, s); });
+    if (op == oq && os != op) over_ext(os, [&](int t) { res -= a.one(t, r) * b.two(p, q, t, s); });
+    if (op == oq && or_ != op) over_ext(or_, [&](int t) { res -= a.one(t, s) * b.two(p, q, r, t); });
+    over_ext(!op, [&](int t) { res -= b.one(p, t) * a.two(t, q, r, s); });
+    over_ext(!oq, [&](int t) { res -= b.one(q, t) * a.two(p, t, r, s); });
+    over_ext(!or_, [&](int t) { res += b.one(t, r) * a.two(p, q, t, s); });
+    over_ext(!os, [&](int t) { res += b.one(t, s) * a.two(p, q, r, t); });
+    if (or_ && os) pair1(false, false, [&](int t, int u) { res += a.two(p, q, t, u) * b.two(t, u, r, s); });
+    if (!or_ && !os) pair1(true, true, [&](int t, int u) { res -= a.two(p, q, t, u) * b.two(t, u, r, s); });
+    if (!op && !oq) pair1(true, true, [&](int t, int u) { res += b.two(p, q, t, u) * a.two(t, u, r, s); });
+    if (op && oq) pair1(false, false, [&](int t, int u) { res -= b.two(p, q, t, u) * a.two(t, u, r, s); });
+    res += xa(p, q, r, s) - xb(p, q, r, s) - xc(p, q, r, s) + xa(q, p, s, r);
+    return res;
+  }
+  QF_HD double xa(int p, int q, int r, int s) const {
+    double x = 0.0;
+    if (!occ(q) && occ(s))
+      pair1(false, true, [&](int t, int u) {
+        x += (2.0 * a.two(p, u, r, t) - a.two(p, u, t, r)) * b.two(t, q, u, s)
+           - a.two(p, u, r, t) * b.two(t, q, s, u);
+      });
+    if (occ(p) && !occ(r))
+      pair1(false, true, [&](int t, int u) {
+        x += (b.two(p, u, t, r) - 2.0 * b.two(p, u, r, t)) * a.two(t, q, u, s)
+           + b.two(p, u, r, t) * a.two(t, q, s, u);
+      });
+    return x;
+  }
+  QF_HD double xb(int p, int q, int r, int s) const {
+    double x = 0.0;
+    if (!occ(p) && occ(s)) pair1(false, true, [&](int t, int u) { x += a.two(q, u, t, r) * b.two(t, p, s, u); });
+    if (occ(q) && !occ(r)) pair1(false, true, [&](int t, int u) { x -= b.two(q, u, t, r) * a.two(t, p, s, u); });
+    return x;
+  }
+  QF_HD double xc(int p, int q, int r, int s) const {
+    double x = 0.0;
+    if (!occ(q) && occ(r)) pair1(false, true, [&](int t, int u) { x += a.two(p, u, t, s) * b.two(t, q, r, u); });
+    if (occ(p) && !occ(s)) pair1(false, true, [&](int t, int u) { x -= b.two(p, u, t, s) * a.two(t, q, r, u); });
+    return x;
+  }
+
+  QF_HD double c1(int p, int q) const {
+    double res = 0.0;
+    const bool op = occ(p), oq = occ(q);
+    over_ext(!oq, [&](int t) { res += a.one(p, t) * b.one(t, q); });
+    over_ext(!op, [&](int t) { res -= b.one(p, t) * a.one(t, q); });
+    if (!op && oq)
+      pair1(true, false, [&](int t, int u) { res += a.one(t, u) * (2.0 * b.two(u, p, t, q) - b.two(u, p, q, t)); });
+    if (op && !oq)
+      pair1(false, true, [&](int t, int u) { res -= a.one(t, u) * (2.0 * b.two(u, p, t, q) - b.two(u, p, q, t)); });
+    pair1(true, false, [&](int t, int u) {
+      res -= b.one(t, u) * (2.0 * a.two(u, p, t, q) - a.two(u, p, q, t));
+      res += b.one(u, t) * (2.0 * a.two(t, p, u, q) - a.two(t, p, q, u));
+    });
+    // (t,u occupied, w virtual) and (t,u virtual, w occupied), one external
+    if (!oq || !op)
+      triple1(true, true, false, [&](int t, int u, int w) {
+        if (!oq) res += a.two(w, p, t, u) * (2.0 * b.two(t, u, w, q) - b.two(t, u, q, w));
+        if (!op) res -= b.two(w, p, t, u) * (2.0 * a.two(t, u, w, q) - a.two(t, u, q, w));
+      });
+    if (oq || op)
+      triple1(false, false, true, [&](int t, int u, int w) {
+        if (oq) res += a.two(w, p, t, u) * (2.0 * b.two(t, u, w, q) - b.two(t, u, q, w));
+        if (op) res -= b.two(w, p, t, u) * (2.0 * a.two(t, u, w, q) - a.two(t, u, q, w));
+      });
+    return res;
+  }
+
+  QF_HD double c0() const {
+    double z = 0.0;
+    pair1(true, false, [&](int t, int u) {
+      z += 2.0 * (a.one(t, u) * b.one(u, t) - a.one(u, t) * b.one(t, u));
+    });
+    // (t,u occupied; w,x virtual) with exactly one external among the four
+    auto term = [&](int t, int u, int w, int x) {
+      z += a.two(t, u, w, x) * (2.0 * b.two(w, x, t, u) - b.two(w, x, u, t))
+         - b.two(t, u, w, x) * (2.0 * a.two(w, x, t, u) - a.two(w, x, u, t));
+    };
+    triple1(true, true, false, [&](int t, int u, int w) {
+      for (int m = 0; m < A.nact(false); ++m) term(t, u, w, A.actv(false, m));
+    });
+    for (int i = 0; i < A.nact(true); ++i)
+      for (int j = 0; j < A.nact(true); ++j)
+        for (int k = 0; k < A.nact(false); ++k)
+          over_ext(false, [&](int x) {
+            term(A.actv(true, i), A.actv(true, j), A.actv(false, k), x);
+          });
+    return z;
+  }
+};
+
+// Per-space tables for the marked evaluation of [E,sigma] (na local
+// orbitals, local index = position in the space):
+//   tau1[a][b], tau2[a][b][c][d]  sigma restricted to the space,
+//   D1[j][t][a]   = sum_{x outside} f[x][t] sigma1 with x in slot j, a in the other,
+//   D2[j][t][abc] = sum_{x outside} f[x][t] sigma2 with x in slot j, (a,b,c) in the
+//                   other slots in order.
+// With E's external leg x in slot k, E = sgn_k sum_t f[x][t] tau(t in slot k)
+// (sgn = +1 for creator slots 0,1 and -1 for annihilator slots 2,3 of the
+// two-body part; +1 / -1 for slots 0 / 1 of the one-body part), so every
+// product E * sigma summed over x becomes sum_t sgn_k tau(..t..) D_j(t; ..).
+struct MarkTables {
+  const double* tau1;
+  const double* tau2;
+  const double* D1;
+  const double* D2;
+  int na;
+};
+
+QF_HD int mark_sizes(int na, int* tau1, int* tau2, int* d1, int* d2) {
+  *tau1 = na * na;
+  *tau2 = na * na * na * na;
+  *d1 = 2 * na * na;
+  *d2 = 4 * na * na * na * na;
+  return *tau1 + *tau2 + *d1 + *d2;
+}
+
+struct MarkedE {
+  MarkTables T;
+  const Active* A;
+  QF_HD int loc(int p) const { return A->pos[p]; }
+  QF_HD double one(int p, int q) const {
+    const int na = T.na;
+    if (p < 0) return T.tau1[(-1 - p) * na + loc(q)];
+    return -T.tau1[loc(p) * na + (-1 - q)];
+  }
+  QF_HD double two(int p, int q, int r, int s) const {
+    const int na = T.na;
+    int i0, i1, i2, i3;
+    double sg = 1.0;
+    if (p < 0) { i0 = -1 - p; i1 = loc(q); i2 = loc(r); i3 = loc(s); }
+    else if (q < 0) { i0 = loc(p); i1 = -1 - q; i2 = loc(r); i3 = loc(s); }
+    else if (r < 0) { i0 = loc(p); i1 = loc(q); i2 = -1 - r; i3 = loc(s); sg = -1.0; }
+    else { i0 = loc(p); i1 = loc(q); i2 = loc(r); i3 = -1 - s; sg = -1.0; }
+    return sg * T.tau2[((i0 * na + i1) * na + i2) * na + i3];
+  }
+};
+
+struct MarkedSigma {
+  MarkTables T;
+  const Active* A;
+  QF_HD int loc(int p) const { return A->pos[p]; }
+  QF_HD double one(int p, int q) const {
+    const int na = T.na;
+    if (p < 0) return T.D1[(0 * na + (-1 - p)) * na + loc(q)];
+    return T.D1[(1 * na + (-1 - q)) * na + loc(p)];
+  }
+  QF_HD double two(int p, int q, int r, int s) const {
+    const int na = T.na, n3 = na * na * na;
+    int j, t, a, b, c;
+    if (p < 0) { j = 0; t = -1 - p; a = loc(q); b = loc(r); c = loc(s); }
+    else if (q < 0) { j = 1; t = -1 - q; a = loc(p); b = loc(r); c = loc(s); }
+    else if (r < 0) { j = 2; t = -1 - r; a = loc(p); b = loc(q); c = loc(s); }
+    else { j = 3; t = -1 - s; a = loc(p); b = loc(q); c = loc(r); }
+    return T.D2[(j * na + t) * n3 + (a * na + b) * na + c];
+  }
+};
+
+// Fill the tables of one space; element e of the concatenated
+// [tau1 | tau2 | D1 | D2] block (lets a block of threads share the work).
+QF_HD double mark_table_entry(const Sigma& s, const double* f, const Active& A, int e) {
+  const int na = A.na, n = s.n, n2 = na * na, n3 = n2 * na, n4 = n3 * na;
+  if (e < n2) return s.one(A.orb[e / na], A.orb[e % na]);
+  e -= n2;
+  if (e < n4)
+    return s.two(A.orb[e / n3], A.orb[e / n2 % na], A.orb[e / na % na], A.orb[e % na]);
+  e -= n4;
+  auto extern_sum = [&](auto val) {
+    double acc = 0.0;
+    for (int k = 0; k < A.next_o + A.next_v; ++k) acc += val((int)A.ext[k]);
+    return acc;
+  };
+  if (e < 2 * n2) {
+    const int j = e / n2, t = A.orb[e / na % na], a = A.orb[e % na];
+    return extern_sum([&](int x) { return f[x * n + t] * (j == 0 ? s.one(x, a) : s.one(a, x)); });
+  }
+  e -= 2 * n2;
+  const int j = e / (na * n3), t = A.orb[e / n3 % na];
+  const int a = A.orb[e / n2 % na], b = A.orb[e / na % na], c = A.orb[e % na];
+  return extern_sum([&](int x) {
+    double sv = (j == 0) ? s.two(x, a, b, c)
+              : (j == 1) ? s.two(a, x, b, c)
+              : (j == 2) ? s.two(a, b, x, c) : s.two(a, b, c, x);
+    return f[x * n + t] * sv;
+  });
+}
 
 template <class AOp, class BOp>
 QF_HD Comm<AOp, BOp> make_comm(const AOp& a, const BOp& b, int n, int o) {

@@ -62,4 +62,46 @@ bool build_strings(int na, int ne, Strings* S) {
   return true;
 }
 
+// Output-element order for the per-space Hamiltonian kernels: two-body
+// elements grouped by their occupied/virtual pattern, then one-body elements,
+// then the scalar; every group is padded with idle entries (-1) to a multiple
+// of the 64-lane wavefront so that a wavefront evaluates one pattern (one set
+// of terms).  Entry = kind << 24 | a << 18 | b << 12 | c << 6 | d with kind
+// 2, 1, 0 for two-, one- and zero-body.
+int build_tasks(int na, int ne, int32_t* out, int cap) {
+  int m = 0;
+  auto pad = [&]() {
+    while (m % 64) {
+      if (m >= cap) return false;
+      out[m++] = -1;
+    }
+    return true;
+  };
+  for (int pat = 0; pat < 16; ++pat) {
+    for (int a = 0; a < na; ++a)
+      for (int b = 0; b < na; ++b)
+        for (int c = 0; c < na; ++c)
+          for (int d = 0; d < na; ++d) {
+            const int bits = ((a < ne) << 3) | ((b < ne) << 2) | ((c < ne) << 1) | (d < ne);
+            if (bits != pat) continue;
+            if (m >= cap) return -1;
+            out[m++] = (2 << 24) | (a << 18) | (b << 12) | (c << 6) | d;
+          }
+    if (!pad()) return -1;
+  }
+  for (int pat = 0; pat < 4; ++pat) {
+    for (int a = 0; a < na; ++a)
+      for (int b = 0; b < na; ++b) {
+        if ((((a < ne) << 1) | (b < ne)) != pat) continue;
+        if (m >= cap) return -1;
+        out[m++] = (1 << 24) | (a << 18) | (b << 12);
+      }
+    if (!pad()) return -1;
+  }
+  if (m >= cap) return -1;
+  out[m++] = 0;
+  if (!pad()) return -1;
+  return m;
+}
+
 }  // namespace qf
