@@ -210,6 +210,71 @@ __global__ __launch_bounds__(1024) void k_finish(const double* __restrict__ ener
   }
 }
 
+// ---------------------------------------------------------------------------
+// ring intermediates: operand packing and the o^2 v one-body contraction
+// ---------------------------------------------------------------------------
+
+// K index of the ring contractions: k = u * v + (t - o), u occupied, t virtual.
+// Aa[(a,b)][k]      = 2 X[a,u,b,t] - X[a,u,t,b],  Aa[(a,b)][ov + k] = -X[a,u,b,t]
+// A22[(a,b)][k]     = X[a,u,t,b]
+__global__ void k_pack_ring_A(const double* __restrict__ X, int n, int o, double* Aa,
+                              double* A22) {
+  const int v = n - o;
+  const size_t ov = (size_t)o * v, rows = (size_t)n * n;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < rows * ov;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t row = idx / ov, k = idx % ov;
+    const int a = (int)(row / n), b = (int)(row % n), u = (int)(k / v), t = o + (int)(k % v);
+    const double x1 = X[(((size_t)a * n + u) * n + b) * n + t];
+    const double x2 = X[(((size_t)a * n + u) * n + t) * n + b];
+    Aa[row * 2 * ov + k] = 2.0 * x1 - x2;
+    Aa[row * 2 * ov + ov + k] = -x1;
+    A22[row * ov + k] = x2;
+  }
+}
+
+// Ta[(g,d)][k] = t2[u,d,t,g], Ta[(g,d)][ov + k] = t2[d,u,t,g], T22[(g,d)][k] = t2[d,u,t,g]
+// with row (g,d) = (g - o) * o + d.
+__global__ void k_pack_ring_T(const double* __restrict__ t2, int o, int v, double* Ta,
+                              double* T22) {
+  const size_t ov = (size_t)o * v;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ov * ov;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t row = idx / ov, k = idx % ov;
+    const int g = (int)(row / o), d = (int)(row % o), u = (int)(k / v), t = (int)(k % v);
+    const double s1 = t2[(((size_t)u * o + d) * v + t) * v + g];
+    const double s2 = t2[(((size_t)d * o + u) * v + t) * v + g];
+    Ta[row * 2 * ov + k] = s1;
+    Ta[row * 2 * ov + ov + k] = s2;
+    T22[row * ov + k] = s2;
+  }
+}
+
+// J1[p][q] = - sum_{t,u occ, w virt} X[w,p,t,u] (2 t2[t,u,w,q] - t2[t,u,q,w])
+// J2[q][p] = - sum_{t,u occ, w virt} t2[t,u,w,p] (2 X[t,u,w,q] - X[t,u,q,w])
+// (p virtual in J2, q virtual in J1; the other index runs over all orbitals)
+__global__ void k_ring_j(const double* __restrict__ X, const double* __restrict__ t2, int n,
+                         int o, double* J1, double* J2) {
+  const int v = n - o;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * n * v) return;
+  const int which = idx / (n * v), e = idx % (n * v);
+  const int p = e / v, q = o + e % v;
+  double s = 0.0;
+  for (int t = 0; t < o; ++t)
+    for (int u = 0; u < o; ++u)
+      for (int w = o; w < n; ++w) {
+        const size_t tu = ((size_t)t * o + u) * v;
+        if (which == 0)
+          s += X[(((size_t)w * n + p) * n + t) * n + u] *
+               (2.0 * t2[(tu + (w - o)) * v + (q - o)] - t2[(tu + (q - o)) * v + (w - o)]);
+        else
+          s += t2[(tu + (w - o)) * v + (q - o)] *
+               (2.0 * X[(((size_t)t * n + u) * n + w) * n + p] - X[(((size_t)t * n + u) * n + p) * n + w]);
+      }
+  (which == 0 ? J1 : J2)[e] = -s;
+}
+
 }  // namespace
 
 void launch_sym_check(const double* h, const double* eri, int n, double* partial, int nblocks,
@@ -237,6 +302,21 @@ void launch_yg(const double* f, const double* t1, const double* t2, int n, int o
   const size_t n4 = (size_t)n * n * n * n;
   k_yg2<<<grid_for(n4, kBlock, 65536), kBlock, 0, st>>>(f, t1, t2, n, o, y2, wy);
   k_yg1<<<grid_for((size_t)n * n), kBlock, 0, st>>>(f, t1, t2, n, o, y1, scal);
+}
+
+void launch_pack_ring_A(const double* X, int n, int o, double* Aa, double* A22, hipStream_t st) {
+  const size_t work = (size_t)n * n * o * (n - o);
+  k_pack_ring_A<<<grid_for(work, kBlock, 65536), kBlock, 0, st>>>(X, n, o, Aa, A22);
+}
+
+void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22, hipStream_t st) {
+  const size_t ov = (size_t)o * v;
+  k_pack_ring_T<<<grid_for(ov * ov, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, Ta, T22);
+}
+
+void launch_ring_j(const double* X, const double* t2, int n, int o, double* J1, double* J2,
+                   hipStream_t st) {
+  k_ring_j<<<grid_for((size_t)2 * n * (n - o), 64), 64, 0, st>>>(X, t2, n, o, J1, J2);
 }
 
 void launch_fill(double* x, size_t count, double value, hipStream_t st) {

@@ -25,19 +25,28 @@ void launch_mp2(const double* f, const double* V, int n, int o, double* t1, doub
 void launch_yg(const double* f, const double* t1, const double* t2, int n, int o, double* y1,
                double* y2, double* wy, double* scal, hipStream_t st);
 void launch_fill(double* x, size_t count, double value, hipStream_t st);
+// ring intermediates (layouts in qflow_eval.h, DenseOp)
+void launch_pack_ring_A(const double* X, int n, int o, double* Aa, double* A22, hipStream_t st);
+void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22, hipStream_t st);
+void launch_ring_j(const double* X, const double* t2, int n, int o, double* J1, double* J2,
+                   hipStream_t st);
 // C[M][N] += sum_k A[m][k] B[n][k], FP64 matrix cores (C must hold zeros)
 void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int N, int K,
                         hipStream_t st);
 
 // residual of Hbar(sigma)
+struct RingOps {            // Ga, G22, J1, J2 of H_N and of Yg
+  const double *ga_h, *g22_h, *j1_h, *j2_h, *ga_y, *g22_y, *j1_y, *j2_y;
+};
 void launch_residual(const double* f, const double* V, const double* y1, const double* y2,
-                     const double* L, const double* LY, const double* t1, const double* t2,
-                     int n, int o, double* scal, double* r1, double* r2, double* e0,
-                     hipStream_t st);
+                     const double* L, const double* LY, const RingOps& rings, const double* t1,
+                     const double* t2, int n, int o, double* scal, double* r1, double* r2,
+                     double* e0, hipStream_t st);
 
 // per-space downfolded Hamiltonians in CAS form
 void launch_heff(const double* f, const double* V, const double* y1, const double* y2,
-                 const double* L, const double* LY, const double* t1, const double* t2, int n,
+                 const double* L, const double* LY, const RingOps& rings, const double* t1,
+                 const double* t2, int n,
                  int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
                  const int32_t* task_table, int task_stride, int slots_max, int K, int na_max,
                  double* tab, double* heff, hipStream_t st);

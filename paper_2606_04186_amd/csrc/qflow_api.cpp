@@ -22,7 +22,7 @@ using qf::SpaceDev;
 namespace {
 
 constexpr int kMaxSub = 12;        // Davidson subspace before restart
-constexpr int kStages = 7;
+constexpr int kStages = 8;
 
 struct DevBuf {
   void* p = nullptr;
@@ -43,6 +43,8 @@ struct qflow_ctx {
   std::vector<double> fock;
   // device state
   DevBuf f, V, W, y1, y2, wy, L, LY, scal, r1, r2, t1n, t2n;
+  // ring intermediates: packed operands (H constant, Yg per step) and outputs
+  DevBuf ra_h, r22_h, ra_y, r22_y, rta, rt22, ga_h, g22_h, ga_y, g22_y, jh, jy;
   DevBuf heff, heff_off, amp, amp_off, work, work_off, energy, c0, iters, status, spaces,
       strings, out2, partial, tasks, mtab;
   int task_slots[3] = {0, 0, 0};
@@ -192,11 +194,20 @@ int require_loaded(qflow_ctx* ctx) {
   return QFLOW_OK;
 }
 
-// Yg = [F,sigma] and the ladder intermediates L = W t2^T, LY = WY t2^T
+qf::RingOps rings_of(qflow_ctx* ctx) {
+  const size_t nv = (size_t)ctx->n * ctx->v;
+  return qf::RingOps{P<double>(ctx->ga_h), P<double>(ctx->g22_h), P<double>(ctx->jh),
+                     P<double>(ctx->jh) + nv,  P<double>(ctx->ga_y), P<double>(ctx->g22_y),
+                     P<double>(ctx->jy),       P<double>(ctx->jy) + nv};
+}
+
+// Yg = [F,sigma], the ladder intermediates L = W t2^T, LY = WY t2^T and the
+// ring intermediates (Ga, G22 by matrix cores; J1, J2) of H_N and Yg
 int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   if (precision != QFLOW_FP64)
     return fail(ctx, QFLOW_E_UNSUPPORTED, "only QFLOW_FP64 contractions are available");
   const int n = ctx->n, o = ctx->o, v = ctx->v;
+  const size_t n2 = (size_t)n * n, ov = (size_t)o * v;
   qf::launch_yg(P<double>(ctx->f), t1, t2, n, o, P<double>(ctx->y1), P<double>(ctx->y2),
                 P<double>(ctx->wy), P<double>(ctx->scal), ctx->stream);
   qf::launch_fill(P<double>(ctx->L), (size_t)n * n * o * o, 0.0, ctx->stream);
@@ -207,6 +218,26 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
   qf::launch_gemm_nt_f64(P<double>(ctx->wy), t2, P<double>(ctx->LY), n * n, o * o, v * v,
                          ctx->stream);
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[3], ctx->stream));
+  hipStream_t st = ctx->stream;
+  qf::launch_pack_ring_T(t2, o, v, P<double>(ctx->rta), P<double>(ctx->rt22), st);
+  qf::launch_pack_ring_A(P<double>(ctx->y2), n, o, P<double>(ctx->ra_y), P<double>(ctx->r22_y), st);
+  qf::launch_fill(P<double>(ctx->ga_h), n2 * ov, 0.0, st);
+  qf::launch_fill(P<double>(ctx->g22_h), n2 * ov, 0.0, st);
+  qf::launch_fill(P<double>(ctx->ga_y), n2 * ov, 0.0, st);
+  qf::launch_fill(P<double>(ctx->g22_y), n2 * ov, 0.0, st);
+  qf::launch_gemm_nt_f64(P<double>(ctx->ra_h), P<double>(ctx->rta), P<double>(ctx->ga_h),
+                         (int)n2, (int)ov, (int)(2 * ov), st);
+  qf::launch_gemm_nt_f64(P<double>(ctx->r22_h), P<double>(ctx->rt22), P<double>(ctx->g22_h),
+                         (int)n2, (int)ov, (int)ov, st);
+  qf::launch_gemm_nt_f64(P<double>(ctx->ra_y), P<double>(ctx->rta), P<double>(ctx->ga_y),
+                         (int)n2, (int)ov, (int)(2 * ov), st);
+  qf::launch_gemm_nt_f64(P<double>(ctx->r22_y), P<double>(ctx->rt22), P<double>(ctx->g22_y),
+                         (int)n2, (int)ov, (int)ov, st);
+  qf::launch_ring_j(P<double>(ctx->V), t2, n, o, P<double>(ctx->jh),
+                    P<double>(ctx->jh) + (size_t)n * v, st);
+  qf::launch_ring_j(P<double>(ctx->y2), t2, n, o, P<double>(ctx->jy),
+                    P<double>(ctx->jy) + (size_t)n * v, st);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -265,7 +296,10 @@ int qflow_destroy(qflow_ctx* ctx) {
   if (!ctx) return QFLOW_OK;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  DevBuf* bufs[] = {&ctx->f,      &ctx->V,        &ctx->W,      &ctx->y1,       &ctx->y2,
+  DevBuf* bufs[] = {&ctx->ra_h,   &ctx->r22_h,    &ctx->ra_y,   &ctx->r22_y,    &ctx->rta,
+                    &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
+                    &ctx->jh,     &ctx->jy,
+                    &ctx->f,      &ctx->V,        &ctx->W,      &ctx->y1,       &ctx->y2,
                     &ctx->wy,     &ctx->L,        &ctx->LY,     &ctx->scal,     &ctx->r1,
                     &ctx->r2,     &ctx->t1n,      &ctx->t2n,    &ctx->heff,     &ctx->heff_off,
                     &ctx->amp,    &ctx->amp_off,  &ctx->work,   &ctx->work_off, &ctx->energy,
@@ -320,8 +354,23 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->r2, sizeof(double) * (size_t)o * o * v * v));
   QF_TRY(ensure(ctx, ctx->t1n, sizeof(double) * o * v));
   QF_TRY(ensure(ctx, ctx->t2n, sizeof(double) * (size_t)o * o * v * v));
+  const size_t ov = (size_t)o * v;
+  QF_TRY(ensure(ctx, ctx->ra_h, sizeof(double) * n2 * 2 * ov));
+  QF_TRY(ensure(ctx, ctx->r22_h, sizeof(double) * n2 * ov));
+  QF_TRY(ensure(ctx, ctx->ra_y, sizeof(double) * n2 * 2 * ov));
+  QF_TRY(ensure(ctx, ctx->r22_y, sizeof(double) * n2 * ov));
+  QF_TRY(ensure(ctx, ctx->rta, sizeof(double) * ov * 2 * ov));
+  QF_TRY(ensure(ctx, ctx->rt22, sizeof(double) * ov * ov));
+  QF_TRY(ensure(ctx, ctx->ga_h, sizeof(double) * n2 * ov));
+  QF_TRY(ensure(ctx, ctx->g22_h, sizeof(double) * n2 * ov));
+  QF_TRY(ensure(ctx, ctx->ga_y, sizeof(double) * n2 * ov));
+  QF_TRY(ensure(ctx, ctx->g22_y, sizeof(double) * n2 * ov));
+  QF_TRY(ensure(ctx, ctx->jh, sizeof(double) * 2 * n * v));
+  QF_TRY(ensure(ctx, ctx->jy, sizeof(double) * 2 * n * v));
   qf::launch_fock(h, eri, n, o, P<double>(ctx->f), ctx->stream);
   qf::launch_repack(eri, n, o, P<double>(ctx->V), P<double>(ctx->W), ctx->stream);
+  qf::launch_pack_ring_A(P<double>(ctx->V), n, o, P<double>(ctx->ra_h), P<double>(ctx->r22_h),
+                         ctx->stream);
   QF_HIP(hipGetLastError());
   ctx->fock.assign(n2, 0.0);
   std::vector<double> hh(n2);
@@ -364,8 +413,8 @@ int qflow_residual(qflow_ctx* ctx, const double* t1, const double* t2, double* r
     return fail(ctx, QFLOW_E_INVALID_ARG, "NULL array argument");
   QF_TRY(prepare(ctx, t1, t2, precision));
   qf::launch_residual(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
-                      P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), t1, t2, ctx->n,
-                      ctx->o, P<double>(ctx->scal), r1, r2, e0, ctx->stream);
+                      P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx),
+                      t1, t2, ctx->n, ctx->o, P<double>(ctx->scal), r1, r2, e0, ctx->stream);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -398,13 +447,13 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
              const int64_t* heff_off_dev) {
   // zero-body parts of [H_N, sigma] and [Yg, sigma] (scal[0], scal[1])
   qf::launch_residual(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
-                      P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), t1, t2, ctx->n,
-                      ctx->o, P<double>(ctx->scal), P<double>(ctx->r1), P<double>(ctx->r2),
-                      nullptr, ctx->stream);
-  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
+                      P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx),
+                      t1, t2, ctx->n, ctx->o, P<double>(ctx->scal), P<double>(ctx->r1),
+                      P<double>(ctx->r2), nullptr, ctx->stream);
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
   if (K > 0)
     qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1), P<double>(ctx->y2),
-                    P<double>(ctx->L), P<double>(ctx->LY), t1, t2, ctx->n, ctx->o,
+                    P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx), t1, t2, ctx->n, ctx->o,
                     P<double>(ctx->scal), P<SpaceDev>(ctx->spaces), heff_off_dev,
                     P<int32_t>(ctx->tasks), qf::kTaskStride, ctx->slots_max, K, ctx->na_max,
                     P<double>(ctx->mtab), heff, ctx->stream);
@@ -505,19 +554,19 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
     ctx->timed = false;
     return r;
   }
-  QF_HIP(hipEventRecord(ctx->ev[3], st));
+  QF_HIP(hipEventRecord(ctx->ev[4], st));
   r = run_heff(ctx, K, t1, t2, P<double>(ctx->heff), P<int64_t>(ctx->heff_off));
   if (r != QFLOW_OK) {
     ctx->timed = false;
     return r;
   }
-  QF_HIP(hipEventRecord(ctx->ev[5], st));
+  QF_HIP(hipEventRecord(ctx->ev[6], st));
   r = run_solve(ctx, K, P<double>(ctx->heff), P<int64_t>(ctx->heff_off), P<double>(ctx->energy),
                 P<double>(ctx->c0), P<double>(ctx->amp), P<int64_t>(ctx->amp_off),
                 P<int32_t>(ctx->iters), P<int32_t>(ctx->status), 1e-10, 200);
   ctx->timed = false;
   if (r != QFLOW_OK) return r;
-  QF_HIP(hipEventRecord(ctx->ev[6], st));
+  QF_HIP(hipEventRecord(ctx->ev[7], st));
   qf::launch_update(t1, t2, P<double>(ctx->r1), P<double>(ctx->r2), P<double>(ctx->f), owner1,
                     owner2, n, o, step, P<double>(ctx->t1n), P<double>(ctx->t2n), st);
   if (K > 0)
@@ -532,14 +581,14 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
                         hipMemcpyDeviceToDevice, st));
   if (K > 0)
     QF_HIP(hipMemcpyAsync(energy, ctx->energy.p, sizeof(double) * K, hipMemcpyDeviceToDevice, st));
-  QF_HIP(hipEventRecord(ctx->ev[7], st));
+  QF_HIP(hipEventRecord(ctx->ev[8], st));
   double out[2];
   QF_HIP(hipMemcpyAsync(out, ctx->out2.p, sizeof(out), hipMemcpyDeviceToHost, st));
   QF_HIP(hipStreamSynchronize(st));
   *e_mean = out[0];
   *max_dt = out[1];
-  // stage times: Yg | ladder GEMM (H) | ladder GEMM (Yg) | residual | heff | solve | update
-  const int pairs[kStages][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7}};
+  // stage times: Yg | ladder GEMM (H) | ladder GEMM (Yg) | rings | residual | heff | solve | update
+  const int pairs[kStages][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7}, {7, 8}};
   for (int s = 0; s < kStages; ++s) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ctx->ev[pairs[s][0]], ctx->ev[pairs[s][1]]) != hipSuccess)

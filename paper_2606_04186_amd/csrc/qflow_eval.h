@@ -117,7 +117,14 @@ struct Tau {
 // the "A" operators
 // ---------------------------------------------------------------------------
 
-// Dense operator with a ladder intermediate L[(pq)][(ij)] (H_N, or Yg).
+// Dense operator A (H_N, or Yg) with its global contractions against sigma:
+//   L[(pq)][(ij)]       = sum_{c,d virtual} A[p,q,c,d] t2[i,j,c,d]       (ladder)
+//   Ga[(ab)][(g d)]     = sum_{u occ, t virt} (2 A[a,u,b,t] - A[a,u,t,b]) t2[u,d,t,g]
+//                                           - A[a,u,b,t] t2[d,u,t,g]      (rings)
+//   G22[(ab)][(g d)]    = sum_{u occ, t virt} A[a,u,t,b] t2[d,u,t,g]
+//   J1[p][q]            = - sum_{t,u occ, w virt} A[w,p,t,u] (2 t2[t,u,w,q] - t2[t,u,q,w])
+//   J2[q][p]            = - sum_{t,u occ, w virt} t2[t,u,w,p] (2 A[t,u,w,q] - A[t,u,q,w])
+// (g, q, p in J virtual; column index of Ga/G22 = (g - o) * o + d).
 struct DenseOp {
   static constexpr bool kHasL = true;
   static constexpr bool kSparse3 = false;
@@ -125,6 +132,10 @@ struct DenseOp {
   const double* x2;   // [n][n][n][n]
   const double* L;    // [n*n][o*o]
   int n, o;
+  const double* Ga = nullptr;    // [n*n][v*o]
+  const double* G22 = nullptr;   // [n*n][v*o]
+  const double* J1 = nullptr;    // [n][v]
+  const double* J2 = nullptr;    // [n][v]
   QF_HD double one(int p, int q) const { return x1[p * n + q]; }
   QF_HD double two(int p, int q, int r, int s) const {
     return x2[(((size_t)p * n + q) * n + r) * n + s];
@@ -132,6 +143,14 @@ struct DenseOp {
   QF_HD double lad(int p, int q, int i, int j) const {
     return L[((size_t)p * n + q) * o * o + i * o + j];
   }
+  QF_HD double ga(int a, int b, int g, int d) const {
+    return Ga[((size_t)a * n + b) * (size_t)(n - o) * o + (size_t)(g - o) * o + d];
+  }
+  QF_HD double g22(int a, int b, int g, int d) const {
+    return G22[((size_t)a * n + b) * (size_t)(n - o) * o + (size_t)(g - o) * o + d];
+  }
+  QF_HD double j1(int p, int q) const { return J1[p * (n - o) + (q - o)]; }
+  QF_HD double j2(int q, int p) const { return J2[q * (n - o) + (p - o)]; }
   QF_HD bool act(int) const { return true; }
 };
 
@@ -202,8 +221,13 @@ struct Comm {
   const AOp& a;
   const BOp& b;
   int n, o;
+  // Work split: every contraction loop runs over indices ln, ln+nl, ...; the
+  // caller sums the partial results of the nl lanes (nl = 1: one evaluator
+  // does everything).  Terms without a loop are taken by lane 0.
+  int ln = 0, nl = 1;
 
   QF_HD bool occ(int p) const { return p < o; }
+  QF_HD bool lead() const { return ln == 0; }
   static constexpr bool kUseL = AOp::kHasL && BOp::kFull;
   static constexpr bool kRestrict = AOp::kSparse3 && BOp::kFull;
 
@@ -211,44 +235,32 @@ struct Comm {
   template <class F>
   QF_HD void over_block(bool occupied, F fn) const {
     if (occupied)
-      for (int k = 0; k < b.nocc(); ++k) fn(b.occ(k));
+      for (int k = ln; k < b.nocc(); k += nl) fn(b.occ(k));
     else
-      for (int k = 0; k < b.nvir(); ++k) fn(b.vir(k));
+      for (int k = ln; k < b.nvir(); k += nl) fn(b.vir(k));
+  }
+  // pairs (t in block bt, u in block bu), t fastest
+  template <class F>
+  QF_HD void over_pair(bool bt, bool bu, F fn) const {
+    const int nt = bt ? b.nocc() : b.nvir(), nu = bu ? b.nocc() : b.nvir();
+    for (int k = ln; k < nt * nu; k += nl) {
+      const int it = k % nt, iu = k / nt;
+      fn(bt ? b.occ(it) : b.vir(it), bu ? b.occ(iu) : b.vir(iu));
+    }
   }
 
   // sum_{t,u virtual} A[p,q,t,u] B[t,u,r,s]  (r,s occupied)
   QF_HD double ladder_vv(int p, int q, int r, int s) const {
     if constexpr (kUseL) {
-      return a.lad(p, q, r, s);
+      return lead() ? a.lad(p, q, r, s) : 0.0;
     } else {
       double x = 0.0;
-      if constexpr (kRestrict) {
-        // A needs >= 3 active indices among (p,q,t,u)
-        int npq = (int)a.act(p) + (int)a.act(q);
-        if (npq == 0) return 0.0;
-        for (int k = 0; k < b.nvir(); ++k) {
-          int t = b.vir(k);
-          bool at = a.act(t);
-          if (npq + (int)at < 2) continue;
-          if (npq + (int)at >= 3) {
-            for (int m = 0; m < b.nvir(); ++m) {
-              int u = b.vir(m);
-              x += a.two(p, q, t, u) * b.two(t, u, r, s);
-            }
-          } else {
-            for (int m = 0; m < b.nvir(); ++m) {
-              int u = b.vir(m);
-              if (a.act(u)) x += a.two(p, q, t, u) * b.two(t, u, r, s);
-            }
-          }
+      over_pair(false, false, [&](int t, int u) {
+        if constexpr (kRestrict) {
+          if ((int)a.act(p) + (int)a.act(q) + (int)a.act(t) + (int)a.act(u) < 3) return;
         }
-      } else {
-        for (int k = 0; k < b.nvir(); ++k)
-          for (int m = 0; m < b.nvir(); ++m) {
-            int t = b.vir(k), u = b.vir(m);
-            x += a.two(p, q, t, u) * b.two(t, u, r, s);
-          }
-      }
+        x += a.two(p, q, t, u) * b.two(t, u, r, s);
+      });
       return x;
     }
   }
@@ -257,28 +269,15 @@ struct Comm {
   QF_HD double ladder_vv_rev(int p, int q, int r, int s) const {
     if constexpr (kUseL) {
       // B[p,q,c,d] = -t2[p,q,c,d]; A[c,d,r,s] = A[r,s,c,d] (Hermitian)
-      return -a.lad(r, s, p, q);
+      return lead() ? -a.lad(r, s, p, q) : 0.0;
     } else {
       double x = 0.0;
-      if constexpr (kRestrict) {
-        int nrs = (int)a.act(r) + (int)a.act(s);
-        if (nrs == 0) return 0.0;
-        for (int k = 0; k < b.nvir(); ++k) {
-          int t = b.vir(k);
-          bool at = a.act(t);
-          if (nrs + (int)at < 2) continue;
-          for (int m = 0; m < b.nvir(); ++m) {
-            int u = b.vir(m);
-            if (nrs + (int)at >= 3 || a.act(u)) x += b.two(p, q, t, u) * a.two(t, u, r, s);
-          }
+      over_pair(false, false, [&](int t, int u) {
+        if constexpr (kRestrict) {
+          if ((int)a.act(r) + (int)a.act(s) + (int)a.act(t) + (int)a.act(u) < 3) return;
         }
-      } else {
-        for (int k = 0; k < b.nvir(); ++k)
-          for (int m = 0; m < b.nvir(); ++m) {
-            int t = b.vir(k), u = b.vir(m);
-            x += b.two(p, q, t, u) * a.two(t, u, r, s);
-          }
-      }
+        x += b.two(p, q, t, u) * a.two(t, u, r, s);
+      });
       return x;
     }
   }
@@ -305,43 +304,32 @@ struct Comm {
     over_block(!os, [&](int t) { res += b.one(t, s) * a.two(p, q, r, t); });
     // ladders: sum_tu (1 - n_t - n_u)(A_pqtu B_turs - B_pqtu A_turs)
     if (or_ && os) res += ladder_vv(p, q, r, s);
-    if (!or_ && !os) {
-      double x = 0.0;
-      for (int k = 0; k < b.nocc(); ++k)
-        for (int m = 0; m < b.nocc(); ++m) {
-          int t = b.occ(k), u = b.occ(m);
-          x += a.two(p, q, t, u) * b.two(t, u, r, s);
-        }
-      res -= x;
-    }
-    if (!op && !oq) {
-      double x = 0.0;
-      for (int k = 0; k < b.nocc(); ++k)
-        for (int m = 0; m < b.nocc(); ++m) {
-          int t = b.occ(k), u = b.occ(m);
-          x += b.two(p, q, t, u) * a.two(t, u, r, s);
-        }
-      res += x;
-    }
+    if (!or_ && !os)
+      over_pair(true, true, [&](int t, int u) { res -= a.two(p, q, t, u) * b.two(t, u, r, s); });
+    if (!op && !oq)
+      over_pair(true, true, [&](int t, int u) { res += b.two(p, q, t, u) * a.two(t, u, r, s); });
     if (op && oq) res -= ladder_vv_rev(p, q, r, s);
     // particle-hole terms: Xa(p,q,r,s) - Xb - Xc + Xa(q,p,s,r)
     res += xa(p, q, r, s) - xb(p, q, r, s) - xc(p, q, r, s) + xa(q, p, s, r);
     return res;
   }
 
-  // sum over t virtual, u occupied, both contracted with B
+  // sum over t virtual, u occupied, both contracted with B (t fastest)
   template <class F>
   QF_HD void over_vo(F fn) const {
-    for (int k = 0; k < b.nvir(); ++k) {
-      int t = b.vir(k);
-      for (int m = 0; m < b.nocc(); ++m) fn(t, b.occ(m));
-    }
+    over_pair(false, true, fn);
   }
 
   // Xa = sum_{t v, u o} [ -A_putr B_tqus + 2 A_purt B_tqus - A_purt B_tqsu
   //                       + B_putr A_tqus - 2 B_purt A_tqus + B_purt A_tqsu ]
   QF_HD double xa(int p, int q, int r, int s) const {
     double x = 0.0;
+    if constexpr (kUseL) {
+      if (!lead()) return 0.0;
+      if (!occ(q) && occ(s)) x += a.ga(p, r, q, s);
+      if (occ(p) && !occ(r)) x += a.ga(s, q, r, p);
+      return x;
+    }
     if (!occ(q) && occ(s))
       over_vo([&](int t, int u) {
         x += (2.0 * a.two(p, u, r, t) - a.two(p, u, t, r)) * b.two(t, q, u, s)
@@ -357,6 +345,12 @@ struct Comm {
   // Xb = sum_{t v, u o} [A_qutr B_tpsu - B_qutr A_tpsu]
   QF_HD double xb(int p, int q, int r, int s) const {
     double x = 0.0;
+    if constexpr (kUseL) {
+      if (!lead()) return 0.0;
+      if (!occ(p) && occ(s)) x += a.g22(q, r, p, s);
+      if (occ(q) && !occ(r)) x += a.g22(s, p, r, q);
+      return x;
+    }
     if (!occ(p) && occ(s))
       over_vo([&](int t, int u) { x += a.two(q, u, t, r) * b.two(t, p, s, u); });
     if (occ(q) && !occ(r))
@@ -366,6 +360,12 @@ struct Comm {
   // Xc = sum_{t v, u o} [A_puts B_tqru - B_puts A_tqru]
   QF_HD double xc(int p, int q, int r, int s) const {
     double x = 0.0;
+    if constexpr (kUseL) {
+      if (!lead()) return 0.0;
+      if (!occ(q) && occ(r)) x += a.g22(p, s, q, r);
+      if (occ(p) && !occ(s)) x += a.g22(r, q, s, p);
+      return x;
+    }
     if (!occ(q) && occ(r))
       over_vo([&](int t, int u) { x += a.two(p, u, t, s) * b.two(t, q, r, u); });
     if (occ(p) && !occ(s))
@@ -382,43 +382,37 @@ struct Comm {
     over_block(!op, [&](int t) { res -= b.one(p, t) * a.one(t, q); });
     // sum_tu (n_t - n_u) [A_tu (2 B_uptq - B_upqt) - B_tu (2 A_uptq - A_upqt)]
     if (!op && oq)   // t occupied, u virtual
-      for (int k = 0; k < b.nocc(); ++k)
-        for (int m = 0; m < b.nvir(); ++m) {
-          int t = b.occ(k), u = b.vir(m);
-          res += a.one(t, u) * (2.0 * b.two(u, p, t, q) - b.two(u, p, q, t));
-        }
+      over_pair(true, false, [&](int t, int u) {
+        res += a.one(t, u) * (2.0 * b.two(u, p, t, q) - b.two(u, p, q, t));
+      });
     if (op && !oq)   // t virtual, u occupied (sign -1)
-      for (int k = 0; k < b.nvir(); ++k)
-        for (int m = 0; m < b.nocc(); ++m) {
-          int t = b.vir(k), u = b.occ(m);
-          res -= a.one(t, u) * (2.0 * b.two(u, p, t, q) - b.two(u, p, q, t));
-        }
-    for (int k = 0; k < b.nocc(); ++k)
-      for (int m = 0; m < b.nvir(); ++m) {
-        int t = b.occ(k), u = b.vir(m);
-        res -= b.one(t, u) * (2.0 * a.two(u, p, t, q) - a.two(u, p, q, t));
-        res += b.one(u, t) * (2.0 * a.two(t, p, u, q) - a.two(t, p, q, u));
-      }
+      over_pair(false, true, [&](int t, int u) {
+        res -= a.one(t, u) * (2.0 * b.two(u, p, t, q) - b.two(u, p, q, t));
+      });
+    over_pair(true, false, [&](int t, int u) {
+      res -= b.one(t, u) * (2.0 * a.two(u, p, t, q) - a.two(u, p, q, t));
+      res += b.one(u, t) * (2.0 * a.two(t, p, u, q) - a.two(t, p, q, u));
+    });
     // sum_tuw (n_t n_u nb_w + nb_t nb_u n_w)
     //      [A_wptu (2 B_tuwq - B_tuqw) - B_wptu (2 A_tuwq - A_tuqw)]
     // (t,u occupied, w virtual): B_tuwq needs q virtual, B_wptu needs p virtual
-    if (!oq || !op) {
-      double x = 0.0;
-      for (int k = 0; k < b.nocc(); ++k)
-        for (int l = 0; l < b.nocc(); ++l) {
-          int t = b.occ(k), u = b.occ(l);
-          if constexpr (kRestrict) {
-            int c = (int)a.act(t) + (int)a.act(u) + (int)a.act(p) + (int)a.act(q);
-            if (c < 1) continue;
-          }
-          for (int m = 0; m < b.nvir(); ++m) {
-            int w = b.vir(m);
-            if (!oq) x += a.two(w, p, t, u) * (2.0 * b.two(t, u, w, q) - b.two(t, u, q, w));
-            if (!op) x -= b.two(w, p, t, u) * (2.0 * a.two(t, u, w, q) - a.two(t, u, q, w));
-          }
+    if constexpr (kUseL) {
+      if (lead()) {
+        if (!oq) res += a.j1(p, q);
+        if (!op) res += a.j2(q, p);
+      }
+    } else if (!oq || !op)
+      over_pair(true, true, [&](int t, int u) {
+        if constexpr (kRestrict) {
+          int c = (int)a.act(t) + (int)a.act(u) + (int)a.act(p) + (int)a.act(q);
+          if (c < 1) return;
         }
-      res += x;
-    }
+        for (int m = 0; m < b.nvir(); ++m) {
+          int w = b.vir(m);
+          if (!oq) res += a.two(w, p, t, u) * (2.0 * b.two(t, u, w, q) - b.two(t, u, q, w));
+          if (!op) res -= b.two(w, p, t, u) * (2.0 * a.two(t, u, w, q) - a.two(t, u, q, w));
+        }
+      });
     // (t,u virtual, w occupied): B_tuwq needs q occupied, B_wptu needs p occupied
     if (oq) res += c1_vvo(p, q);
     if (op) res += c1_vvo_rev(p, q);
@@ -427,117 +421,76 @@ struct Comm {
 
   // sum_{w o; t,u v} A_wptu (2 B_tuwq - B_tuqw), q occupied
   QF_HD double c1_vvo(int p, int q) const {
+    double x = 0.0;
     if constexpr (kUseL) {
-      double x = 0.0;
-      for (int w = 0; w < o; ++w) x += 2.0 * a.lad(w, p, w, q) - a.lad(w, p, q, w);
-      return x;
+      for (int w = ln; w < o; w += nl) x += 2.0 * a.lad(w, p, w, q) - a.lad(w, p, q, w);
     } else {
-      double x = 0.0;
-      for (int m = 0; m < b.nocc(); ++m) {
-        int w = b.occ(m);
-        for (int k = 0; k < b.nvir(); ++k) {
-          int t = b.vir(k);
+      over_pair(false, false, [&](int t, int u) {
+        for (int m = 0; m < b.nocc(); ++m) {
+          const int w = b.occ(m);
           if constexpr (kRestrict) {
-            // A[w,p,t,u] needs at least three active indices
-            int c3 = (int)a.act(w) + (int)a.act(p) + (int)a.act(t);
-            if (c3 < 2) continue;
-            if (c3 == 2) {
-              for (int l = 0; l < b.nvir(); ++l) {
-                int u = b.vir(l);
-                if (a.act(u))
-                  x += a.two(w, p, t, u) * (2.0 * b.two(t, u, w, q) - b.two(t, u, q, w));
-              }
-              continue;
-            }
+            if ((int)a.act(w) + (int)a.act(p) + (int)a.act(t) + (int)a.act(u) < 3) continue;
           }
-          for (int l = 0; l < b.nvir(); ++l) {
-            int u = b.vir(l);
-            x += a.two(w, p, t, u) * (2.0 * b.two(t, u, w, q) - b.two(t, u, q, w));
-          }
+          x += a.two(w, p, t, u) * (2.0 * b.two(t, u, w, q) - b.two(t, u, q, w));
         }
-      }
-      return x;
+      });
     }
+    return x;
   }
 
   // - sum_{w o; t,u v} B_wptu (2 A_tuwq - A_tuqw), p occupied
   QF_HD double c1_vvo_rev(int p, int q) const {
+    double x = 0.0;
     if constexpr (kUseL) {
       // B_wptu = -t2[w,p,t,u]; A_tuwq = A_wqtu (Hermitian)
-      double x = 0.0;
-      for (int w = 0; w < o; ++w) x += 2.0 * a.lad(w, q, w, p) - a.lad(q, w, w, p);
-      return x;
+      for (int w = ln; w < o; w += nl) x += 2.0 * a.lad(w, q, w, p) - a.lad(q, w, w, p);
     } else {
-      double x = 0.0;
-      for (int m = 0; m < b.nocc(); ++m) {
-        int w = b.occ(m);
-        for (int k = 0; k < b.nvir(); ++k) {
-          int t = b.vir(k);
+      over_pair(false, false, [&](int t, int u) {
+        for (int m = 0; m < b.nocc(); ++m) {
+          const int w = b.occ(m);
           if constexpr (kRestrict) {
-            // A[t,u,w,q] needs at least three active indices
-            int c3 = (int)a.act(w) + (int)a.act(q) + (int)a.act(t);
-            if (c3 < 2) continue;
-            if (c3 == 2) {
-              for (int l = 0; l < b.nvir(); ++l) {
-                int u = b.vir(l);
-                if (a.act(u))
-                  x -= b.two(w, p, t, u) * (2.0 * a.two(t, u, w, q) - a.two(t, u, q, w));
-              }
-              continue;
-            }
+            if ((int)a.act(w) + (int)a.act(q) + (int)a.act(t) + (int)a.act(u) < 3) continue;
           }
-          for (int l = 0; l < b.nvir(); ++l) {
-            int u = b.vir(l);
-            x -= b.two(w, p, t, u) * (2.0 * a.two(t, u, w, q) - a.two(t, u, q, w));
-          }
+          x -= b.two(w, p, t, u) * (2.0 * a.two(t, u, w, q) - a.two(t, u, q, w));
         }
-      }
-      return x;
+      });
     }
+    return x;
   }
 
   // ----- zero-body part -----
   QF_HD double c0() const {
     double z = 0.0;
     // 2 sum_tu (n_t - n_u) A_tu B_ut
-    for (int k = 0; k < b.nocc(); ++k)
-      for (int m = 0; m < b.nvir(); ++m) {
-        int t = b.occ(k), u = b.vir(m);
-        z += 2.0 * (a.one(t, u) * b.one(u, t) - a.one(u, t) * b.one(t, u));
-      }
+    over_pair(true, false, [&](int t, int u) {
+      z += 2.0 * (a.one(t, u) * b.one(u, t) - a.one(u, t) * b.one(t, u));
+    });
     // sum_{tu o, wx v} [A_tuwx (2 B_wxtu - B_wxut) - B_tuwx (2 A_wxtu - A_wxut)]
     if constexpr (kUseL) {
-      for (int t = 0; t < o; ++t)
-        for (int u = 0; u < o; ++u)
-          z += 4.0 * a.lad(t, u, t, u) - a.lad(t, u, u, t) - a.lad(u, t, t, u);
+      over_pair(true, true, [&](int t, int u) {
+        z += 4.0 * a.lad(t, u, t, u) - a.lad(t, u, u, t) - a.lad(u, t, t, u);
+      });
     } else {
-      for (int k = 0; k < b.nocc(); ++k)
-        for (int l = 0; l < b.nocc(); ++l)
-          for (int m = 0; m < b.nvir(); ++m) {
-            int t = b.occ(k), u = b.occ(l), w = b.vir(m);
+      over_pair(true, true, [&](int t, int u) {
+        for (int m = 0; m < b.nvir(); ++m)
+          for (int r = 0; r < b.nvir(); ++r) {
+            const int w = b.vir(m), x = b.vir(r);
             if constexpr (kRestrict) {
-              int c = (int)a.act(t) + (int)a.act(u) + (int)a.act(w);
-              if (c < 2) continue;
-              if (c == 2) {
-                for (int r = 0; r < b.nvir(); ++r) {
-                  int x = b.vir(r);
-                  if (!a.act(x)) continue;
-                  z += a.two(t, u, w, x) * (2.0 * b.two(w, x, t, u) - b.two(w, x, u, t))
-                     - b.two(t, u, w, x) * (2.0 * a.two(w, x, t, u) - a.two(w, x, u, t));
-                }
-                continue;
-              }
+              if ((int)a.act(t) + (int)a.act(u) + (int)a.act(w) + (int)a.act(x) < 3) continue;
             }
-            for (int r = 0; r < b.nvir(); ++r) {
-              int x = b.vir(r);
-              z += a.two(t, u, w, x) * (2.0 * b.two(w, x, t, u) - b.two(w, x, u, t))
-                 - b.two(t, u, w, x) * (2.0 * a.two(w, x, t, u) - a.two(w, x, u, t));
-            }
+            z += a.two(t, u, w, x) * (2.0 * b.two(w, x, t, u) - b.two(w, x, u, t))
+               - b.two(t, u, w, x) * (2.0 * a.two(w, x, t, u) - a.two(w, x, u, t));
           }
+      });
     }
     return z;
   }
 };
+
+template <class AOp, class BOp>
+QF_HD Comm<AOp, BOp> make_comm_split(const AOp& a, const BOp& b, int n, int o, int ln, int nl) {
+  return Comm<AOp, BOp>{a, b, n, o, ln, nl};
+}
 
 // ---------------------------------------------------------------------------
 // [E, sigma] restricted to the active space, E = the part of [F,tau] with
