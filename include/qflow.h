@@ -157,8 +157,9 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
 
 /* Per-stage device times of the last qflow_flow_step in milliseconds (HIP
  * events on the context's stream), in the order: [F,sigma] intermediate,
- * ladder contraction of H_N, ladder contraction of [F,sigma], ring
- * contractions, residual, build_heff, solve, update.  n is the capacity of ms (host).  Returns the
+ * ladder contraction of H_N, ladder contraction of [F,sigma], ring operand
+ * packing, ring contractions (four matrix-core GEMMs), one-body ring terms,
+ * residual, build_heff, solve, update.  n is the capacity of ms (host).  Returns the
  * count written. */
 int qflow_last_timings(const qflow_ctx* ctx, float* ms, int n);
 

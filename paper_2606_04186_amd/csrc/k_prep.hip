@@ -253,26 +253,29 @@ __global__ void k_pack_ring_T(const double* __restrict__ t2, int o, int v, doubl
 // J1[p][q] = - sum_{t,u occ, w virt} X[w,p,t,u] (2 t2[t,u,w,q] - t2[t,u,q,w])
 // J2[q][p] = - sum_{t,u occ, w virt} t2[t,u,w,p] (2 X[t,u,w,q] - X[t,u,q,w])
 // (p virtual in J2, q virtual in J1; the other index runs over all orbitals)
-__global__ void k_ring_j(const double* __restrict__ X, const double* __restrict__ t2, int n,
-                         int o, double* J1, double* J2) {
+__global__ __launch_bounds__(256) void k_ring_j(const double* __restrict__ X,
+                                                const double* __restrict__ t2, int n, int o,
+                                                double* J1, double* J2) {
+  // one wavefront per output; lanes split the (t,u,w) sum, u fastest
   const int v = n - o;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x % 64;
+  const int idx = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   if (idx >= 2 * n * v) return;
   const int which = idx / (n * v), e = idx % (n * v);
   const int p = e / v, q = o + e % v;
   double s = 0.0;
-  for (int t = 0; t < o; ++t)
-    for (int u = 0; u < o; ++u)
-      for (int w = o; w < n; ++w) {
-        const size_t tu = ((size_t)t * o + u) * v;
-        if (which == 0)
-          s += X[(((size_t)w * n + p) * n + t) * n + u] *
-               (2.0 * t2[(tu + (w - o)) * v + (q - o)] - t2[(tu + (q - o)) * v + (w - o)]);
-        else
-          s += t2[(tu + (w - o)) * v + (q - o)] *
-               (2.0 * X[(((size_t)t * n + u) * n + w) * n + p] - X[(((size_t)t * n + u) * n + p) * n + w]);
-      }
-  (which == 0 ? J1 : J2)[e] = -s;
+  for (int k = lane; k < o * o * v; k += 64) {
+    const int u = k % o, t = k / o % o, w = o + k / (o * o);
+    const size_t tu = ((size_t)t * o + u) * v;
+    if (which == 0)
+      s += X[(((size_t)w * n + p) * n + t) * n + u] *
+           (2.0 * t2[(tu + (w - o)) * v + (q - o)] - t2[(tu + (q - o)) * v + (w - o)]);
+    else
+      s += t2[(tu + (w - o)) * v + (q - o)] *
+           (2.0 * X[(((size_t)t * n + u) * n + w) * n + p] - X[(((size_t)t * n + u) * n + p) * n + w]);
+  }
+  s = wave_sum(s);
+  if (lane == 0) (which == 0 ? J1 : J2)[e] = -s;
 }
 
 }  // namespace
@@ -316,7 +319,7 @@ void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22,
 
 void launch_ring_j(const double* X, const double* t2, int n, int o, double* J1, double* J2,
                    hipStream_t st) {
-  k_ring_j<<<grid_for((size_t)2 * n * (n - o), 64), 64, 0, st>>>(X, t2, n, o, J1, J2);
+  k_ring_j<<<grid_for((size_t)2 * n * (n - o) * 64), kBlock, 0, st>>>(X, t2, n, o, J1, J2);
 }
 
 void launch_fill(double* x, size_t count, double value, hipStream_t st) {

@@ -33,17 +33,21 @@ __global__ void k_residual2(GlobalOps g, double* r2) {
   }
 }
 
-__global__ void k_residual1(GlobalOps g, double* r1) {
+// one wavefront per output (lanes split the contraction loops)
+__global__ __launch_bounds__(256) void k_residual1(GlobalOps g, double* r1) {
   const int n = g.n, o = g.o, v = n - o;
+  const int lane = threadIdx.x % 64;
   const Sigma s{g.t1, g.t2, n, o, v};
   const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h};
   const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y};
-  const auto cH = make_comm(H, s, n, o);
-  const auto cY = make_comm(Y, s, n, o);
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const auto cH = make_comm_split(H, s, n, o, lane, 64);
+  const auto cY = make_comm_split(Y, s, n, o, lane, 64);
+  const int idx = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   if (idx >= o * v) return;
   const int i = idx / v, a = idx % v;
-  r1[idx] = H.one(o + a, i) + cH.c1(o + a, i) + 0.5 * cY.c1(o + a, i);
+  double x = cH.c1(o + a, i) + 0.5 * cY.c1(o + a, i);
+  x = wave_sum(x);
+  if (lane == 0) r1[idx] = H.one(o + a, i) + x;
 }
 
 // scal[0] = [H_N,sigma]_0, scal[1] = [Yg,sigma]_0 (scal[3] = E_ref, set at load)
@@ -71,7 +75,7 @@ void launch_residual(const double* f, const double* V, const double* y1, const d
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y};
   const size_t v = n - o;
   k_residual2<<<grid_for(o * o * v * v, kBlock, 65536), kBlock, 0, st>>>(g, r2);
-  k_residual1<<<grid_for(o * v), kBlock, 0, st>>>(g, r1);
+  k_residual1<<<grid_for(o * v * 64), kBlock, 0, st>>>(g, r1);
   k_residual0<<<1, 64, 0, st>>>(g, scal, e0);
 }
 

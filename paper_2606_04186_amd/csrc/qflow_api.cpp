@@ -22,7 +22,7 @@ using qf::SpaceDev;
 namespace {
 
 constexpr int kMaxSub = 12;        // Davidson subspace before restart
-constexpr int kStages = 8;
+constexpr int kStages = 10;
 
 struct DevBuf {
   void* p = nullptr;
@@ -226,6 +226,7 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   qf::launch_fill(P<double>(ctx->g22_h), n2 * ov, 0.0, st);
   qf::launch_fill(P<double>(ctx->ga_y), n2 * ov, 0.0, st);
   qf::launch_fill(P<double>(ctx->g22_y), n2 * ov, 0.0, st);
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
   qf::launch_gemm_nt_f64(P<double>(ctx->ra_h), P<double>(ctx->rta), P<double>(ctx->ga_h),
                          (int)n2, (int)ov, (int)(2 * ov), st);
   qf::launch_gemm_nt_f64(P<double>(ctx->r22_h), P<double>(ctx->rt22), P<double>(ctx->g22_h),
@@ -234,6 +235,7 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
                          (int)n2, (int)ov, (int)(2 * ov), st);
   qf::launch_gemm_nt_f64(P<double>(ctx->r22_y), P<double>(ctx->rt22), P<double>(ctx->g22_y),
                          (int)n2, (int)ov, (int)ov, st);
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
   qf::launch_ring_j(P<double>(ctx->V), t2, n, o, P<double>(ctx->jh),
                     P<double>(ctx->jh) + (size_t)n * v, st);
   qf::launch_ring_j(P<double>(ctx->y2), t2, n, o, P<double>(ctx->jy),
@@ -450,7 +452,7 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
                       P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx),
                       t1, t2, ctx->n, ctx->o, P<double>(ctx->scal), P<double>(ctx->r1),
                       P<double>(ctx->r2), nullptr, ctx->stream);
-  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[7], ctx->stream));
   if (K > 0)
     qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1), P<double>(ctx->y2),
                     P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx), t1, t2, ctx->n, ctx->o,
@@ -554,19 +556,19 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
     ctx->timed = false;
     return r;
   }
-  QF_HIP(hipEventRecord(ctx->ev[4], st));
+  QF_HIP(hipEventRecord(ctx->ev[6], st));
   r = run_heff(ctx, K, t1, t2, P<double>(ctx->heff), P<int64_t>(ctx->heff_off));
   if (r != QFLOW_OK) {
     ctx->timed = false;
     return r;
   }
-  QF_HIP(hipEventRecord(ctx->ev[6], st));
+  QF_HIP(hipEventRecord(ctx->ev[8], st));
   r = run_solve(ctx, K, P<double>(ctx->heff), P<int64_t>(ctx->heff_off), P<double>(ctx->energy),
                 P<double>(ctx->c0), P<double>(ctx->amp), P<int64_t>(ctx->amp_off),
                 P<int32_t>(ctx->iters), P<int32_t>(ctx->status), 1e-10, 200);
   ctx->timed = false;
   if (r != QFLOW_OK) return r;
-  QF_HIP(hipEventRecord(ctx->ev[7], st));
+  QF_HIP(hipEventRecord(ctx->ev[9], st));
   qf::launch_update(t1, t2, P<double>(ctx->r1), P<double>(ctx->r2), P<double>(ctx->f), owner1,
                     owner2, n, o, step, P<double>(ctx->t1n), P<double>(ctx->t2n), st);
   if (K > 0)
@@ -581,14 +583,19 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
                         hipMemcpyDeviceToDevice, st));
   if (K > 0)
     QF_HIP(hipMemcpyAsync(energy, ctx->energy.p, sizeof(double) * K, hipMemcpyDeviceToDevice, st));
-  QF_HIP(hipEventRecord(ctx->ev[8], st));
+  QF_HIP(hipEventRecord(ctx->ev[10], st));
   double out[2];
   QF_HIP(hipMemcpyAsync(out, ctx->out2.p, sizeof(out), hipMemcpyDeviceToHost, st));
   QF_HIP(hipStreamSynchronize(st));
   *e_mean = out[0];
   *max_dt = out[1];
-  // stage times: Yg | ladder GEMM (H) | ladder GEMM (Yg) | rings | residual | heff | solve | update
-  const int pairs[kStages][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7}, {7, 8}};
+  // stage times: Yg | ladder GEMM (H) | ladder GEMM (Yg) | ring packing | ring GEMMs | J |
+  // residual | heff | solve | update
+  int pairs[kStages][2];
+  for (int s = 0; s < kStages; ++s) {
+    pairs[s][0] = s;
+    pairs[s][1] = s + 1;
+  }
   for (int s = 0; s < kStages; ++s) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ctx->ev[pairs[s][0]], ctx->ev[pairs[s][1]]) != hipSuccess)
