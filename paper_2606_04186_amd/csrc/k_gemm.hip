@@ -1,4 +1,4 @@
-// FP64 ladder contraction on matrix cores.
+// FP64 contractions on matrix cores (ladder and ring intermediates).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -31,7 +31,8 @@ constexpr int kGemmNT = 11;   // column tiles of 16 -> N <= 176
 
 __global__ __launch_bounds__(256) void k_gemm_nt_f64(const double* __restrict__ A,
                                                      const double* __restrict__ B, double* C,
-                                                     int M, int N, int K, int kchunk) {
+                                                     int M, int N, int K, int kchunk,
+                                                     int to_slices) {
   __shared__ double As[kGemmBM][kGemmBK + 1];
   __shared__ double Bs[kGemmNT * 16][kGemmBK + 1];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -75,12 +76,36 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f64(const double* __restrict__ 
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = m0 + wave * 16 + lane / 16 + 4 * i;
-      if (row < M && col < N) atomicAdd(&C[(size_t)row * N + col], acc[t][i]);
+      if (row >= M || col >= N) continue;
+      if (to_slices)
+        C[((size_t)blockIdx.y * M + row) * N + col] = acc[t][i];
+      else
+        atomicAdd(&C[(size_t)row * N + col], acc[t][i]);
     }
   }
 }
 
+__global__ __launch_bounds__(256) void k_sum_slices(const double* __restrict__ part, int splits,
+                                                    size_t count, double scale, double* C) {
+  const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  double s = 0.0;
+  for (int i = 0; i < splits; ++i) s += part[(size_t)i * count + e];
+  C[e] = scale * s;
+}
+
 }  // namespace
+
+void launch_gemm_nt_f64_splitk(const double* A, const double* B, double* part, double* C, int M,
+                               int N, int K, double scale, hipStream_t st) {
+  int kchunk = (K + kMaxSplits - 1) / kMaxSplits;
+  kchunk = (kchunk + kGemmBK - 1) / kGemmBK * kGemmBK;
+  const int splits = (K + kchunk - 1) / kchunk;
+  dim3 grid((M + kGemmBM - 1) / kGemmBM, splits, (N + kGemmNT * 16 - 1) / (kGemmNT * 16));
+  k_gemm_nt_f64<<<grid, 256, 0, st>>>(A, B, part, M, N, K, kchunk, 1);
+  const size_t count = (size_t)M * N;
+  k_sum_slices<<<grid_for(count), kBlock, 0, st>>>(part, splits, count, scale, C);
+}
 
 void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int N, int K,
                         hipStream_t st) {
@@ -88,7 +113,7 @@ void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int 
   kchunk = (kchunk + kGemmBK - 1) / kGemmBK * kGemmBK;
   const int splits = (K + kchunk - 1) / kchunk;
   dim3 grid((M + kGemmBM - 1) / kGemmBM, splits, (N + kGemmNT * 16 - 1) / (kGemmNT * 16));
-  k_gemm_nt_f64<<<grid, 256, 0, st>>>(A, B, C, M, N, K, kchunk);
+  k_gemm_nt_f64<<<grid, 256, 0, st>>>(A, B, C, M, N, K, kchunk, 0);
 }
 
 }  // namespace qf

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __
     T = MarkTables{tl, tl + s1, tl + s1 + s2, tl + s1 + s2 + s3, sp.na};
   }
   const int na = sp.na, n = g.n, o = g.o, v = n - o;
-  const int n2 = na * na, n4 = n2 * n2;
+  const int n2 = na * na;
   double* slot = heff + heff_off[k];
   const Sigma s{g.t1, g.t2, n, o, v};
   const Tau tau{s, &A};
@@ -87,47 +87,69 @@ __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __
   if (code < 0) return;
   const int kind = code >> 24;
   const int la = (code >> 18) & 63, lb = (code >> 12) & 63, lc = (code >> 6) & 63, ld = code & 63;
-  // task numbering of the slot: two-body element, one-body element, scalar
-  const int task = (kind == 2) ? ((la * na + lb) * na + lc) * na + ld
-                               : (kind == 1 ? n4 + la * na + lb : n4 + n2);
   const int p = A.orb[la], q = A.orb[lb], r = A.orb[lc], t = A.orb[ld];
-  double* dst = (task < n4) ? slot + 1 + n2 + task : (task < n4 + n2 ? slot + 1 + (task - n4) : slot);
+  // distinct slot positions of the task's symmetry orbit (see build_tasks)
+  int d0, d1 = -1, d2 = -1, d3 = -1;
+  if (kind == 2) {
+    d0 = ((la * na + lb) * na + lc) * na + ld;
+    const int i1 = ((lb * na + la) * na + ld) * na + lc;
+    const int i2 = ((lc * na + ld) * na + la) * na + lb;
+    const int i3 = ((ld * na + lc) * na + lb) * na + la;
+    if (i1 != d0) d1 = i1;
+    if (i2 != d0 && i2 != i1) d2 = i2;
+    if (i3 != d0 && i3 != i1 && i3 != i2) d3 = i3;
+    d0 += 1 + n2;
+    if (d1 >= 0) d1 += 1 + n2;
+    if (d2 >= 0) d2 += 1 + n2;
+    if (d3 >= 0) d3 += 1 + n2;
+  } else if (kind == 1) {
+    d0 = 1 + la * na + lb;
+    if (la != lb) d1 = 1 + lb * na + la;
+  } else {
+    d0 = 0;
+  }
+  auto emit = [&](double x, double scale, bool init) {
+    const int ds[4] = {d0, d1, d2, d3};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (ds[i] >= 0) slot[ds[i]] = init ? x : slot[ds[i]] + scale * x;
+  };
   if constexpr (PART == 0) {
     const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h};
     const auto cs = make_comm(H, s, n, o);
     const auto ct = make_comm(H, tau, n, o);
     double x;
-    if (task < n4)
+    if (kind == 2)
       x = H.two(p, q, r, t) + cs.c2(p, q, r, t) - ct.c2(p, q, r, t);
-    else if (task < n4 + n2)
+    else if (kind == 1)
       x = H.one(p, q) + cs.c1(p, q) - ct.c1(p, q);
     else
       x = scal[3] + scal[0] - ct.c0();
-    *dst = x;
+    emit(x, 1.0, true);
   } else if constexpr (PART == 1) {
     const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y};
     const auto cs = make_comm(Y, s, n, o);
     const auto ct = make_comm(Y, tau, n, o);
     double x;
-    if (task < n4)
+    if (kind == 2)
       x = cs.c2(p, q, r, t) - ct.c2(p, q, r, t);
-    else if (task < n4 + n2)
+    else if (kind == 1)
       x = cs.c1(p, q) - ct.c1(p, q);
     else
       x = scal[1] - ct.c0();
-    *dst += 0.5 * x;
+    emit(x, 0.5, false);
   } else {
     const MarkedE E{T, &A};
     const MarkedSigma D{T, &A};
     const CommE<MarkedE, MarkedSigma, true> ce{E, D, A, n, o};
     double x;
-    if (task < n4)
+    if (kind == 2)
       x = ce.c2(p, q, r, t);
-    else if (task < n4 + n2)
+    else if (kind == 1)
       x = ce.c1(p, q);
     else
       x = ce.c0();
-    *dst -= 0.5 * x;
+    emit(x, -0.5, false);
   }
 }
 

@@ -253,29 +253,40 @@ __global__ void k_pack_ring_T(const double* __restrict__ t2, int o, int v, doubl
 // J1[p][q] = - sum_{t,u occ, w virt} X[w,p,t,u] (2 t2[t,u,w,q] - t2[t,u,q,w])
 // J2[q][p] = - sum_{t,u occ, w virt} t2[t,u,w,p] (2 X[t,u,w,q] - X[t,u,q,w])
 // (p virtual in J2, q virtual in J1; the other index runs over all orbitals)
-__global__ __launch_bounds__(256) void k_ring_j(const double* __restrict__ X,
-                                                const double* __restrict__ t2, int n, int o,
-                                                double* J1, double* J2) {
-  // one wavefront per output; lanes split the (t,u,w) sum, u fastest
+// Operands of the one-body ring terms as K-contiguous matrices over
+// k = (t*o + u)*v + (w - o), t and u occupied, w virtual:
+//   J1[p][q] = - sum_k X[w,p,t,u] (2 t2[t,u,w,q] - t2[t,u,q,w])
+//   J2[p][q] = - sum_k (2 X[t,u,w,p] - X[t,u,p,w]) t2[t,u,w,q]
+// A1[p][k] = X[w,p,t,u], A2[p][k] = 2 X[t,u,w,p] - X[t,u,p,w] (n rows each),
+// B1[q][k] = 2 t2[t,u,w,q] - t2[t,u,q,w], B2[q][k] = t2[t,u,w,q] (v rows each).
+__global__ __launch_bounds__(256) void k_pack_j_A(const double* __restrict__ X, int n, int o,
+                                                  double* A1, double* A2) {
   const int v = n - o;
-  const int lane = threadIdx.x % 64;
-  const int idx = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-  if (idx >= 2 * n * v) return;
-  const int which = idx / (n * v), e = idx % (n * v);
-  const int p = e / v, q = o + e % v;
-  double s = 0.0;
-  for (int k = lane; k < o * o * v; k += 64) {
-    const int u = k % o, t = k / o % o, w = o + k / (o * o);
-    const size_t tu = ((size_t)t * o + u) * v;
-    if (which == 0)
-      s += X[(((size_t)w * n + p) * n + t) * n + u] *
-           (2.0 * t2[(tu + (w - o)) * v + (q - o)] - t2[(tu + (q - o)) * v + (w - o)]);
-    else
-      s += t2[(tu + (w - o)) * v + (q - o)] *
-           (2.0 * X[(((size_t)t * n + u) * n + w) * n + p] - X[(((size_t)t * n + u) * n + p) * n + w]);
+  const size_t K = (size_t)o * o * v;
+  const size_t total = (size_t)n * K;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int p = (int)(e / K);
+    const int k = (int)(e % K);
+    const int w = o + k % v, u = k / v % o, t = k / (v * o);
+    A1[e] = X[(((size_t)w * n + p) * n + t) * n + u];
+    A2[e] = 2.0 * X[(((size_t)t * n + u) * n + w) * n + p] - X[(((size_t)t * n + u) * n + p) * n + w];
   }
-  s = wave_sum(s);
-  if (lane == 0) (which == 0 ? J1 : J2)[e] = -s;
+}
+
+__global__ __launch_bounds__(256) void k_pack_j_B(const double* __restrict__ t2, int o, int v,
+                                                  double* B1, double* B2) {
+  const size_t K = (size_t)o * o * v;
+  const size_t total = (size_t)v * K;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int q = (int)(e / K);
+    const int k = (int)(e % K);
+    const int w = k % v, tu = k / v;   // w relative to o
+    const double x = t2[((size_t)tu * v + w) * v + q];
+    B1[e] = 2.0 * x - t2[((size_t)tu * v + q) * v + w];
+    B2[e] = x;
+  }
 }
 
 }  // namespace
@@ -317,9 +328,14 @@ void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22,
   k_pack_ring_T<<<grid_for(ov * ov, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, Ta, T22);
 }
 
-void launch_ring_j(const double* X, const double* t2, int n, int o, double* J1, double* J2,
-                   hipStream_t st) {
-  k_ring_j<<<grid_for((size_t)2 * n * (n - o) * 64), kBlock, 0, st>>>(X, t2, n, o, J1, J2);
+void launch_pack_j_A(const double* X, int n, int o, double* A1, double* A2, hipStream_t st) {
+  const size_t total = (size_t)n * o * o * (n - o);
+  k_pack_j_A<<<grid_for(total, kBlock, 65536), kBlock, 0, st>>>(X, n, o, A1, A2);
+}
+
+void launch_pack_j_B(const double* t2, int o, int v, double* B1, double* B2, hipStream_t st) {
+  const size_t total = (size_t)v * o * o * v;
+  k_pack_j_B<<<grid_for(total, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, B1, B2);
 }
 
 void launch_fill(double* x, size_t count, double value, hipStream_t st) {

@@ -45,6 +45,9 @@ struct qflow_ctx {
   DevBuf f, V, W, y1, y2, wy, L, LY, scal, r1, r2, t1n, t2n;
   // ring intermediates: packed operands (H constant, Yg per step) and outputs
   DevBuf ra_h, r22_h, ra_y, r22_y, rta, rt22, ga_h, g22_h, ga_y, g22_y, jh, jy;
+  // one-body ring terms: packed operands (A of H constant, A of Yg and B per
+  // step) and the split-K slices
+  DevBuf ja_h, ja_y, jb, jpart;
   DevBuf heff, heff_off, amp, amp_off, work, work_off, energy, c0, iters, status, spaces,
       strings, out2, partial, tasks, mtab;
   int task_slots[3] = {0, 0, 0};
@@ -236,10 +239,23 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   qf::launch_gemm_nt_f64(P<double>(ctx->r22_y), P<double>(ctx->rt22), P<double>(ctx->g22_y),
                          (int)n2, (int)ov, (int)ov, st);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
-  qf::launch_ring_j(P<double>(ctx->V), t2, n, o, P<double>(ctx->jh),
-                    P<double>(ctx->jh) + (size_t)n * v, st);
-  qf::launch_ring_j(P<double>(ctx->y2), t2, n, o, P<double>(ctx->jy),
-                    P<double>(ctx->jy) + (size_t)n * v, st);
+  // one-body ring terms J1, J2 of H_N and Yg
+  const size_t kj = (size_t)o * o * v;
+  double* b1 = P<double>(ctx->jb);
+  double* b2 = b1 + (size_t)v * kj;
+  qf::launch_pack_j_B(t2, o, v, b1, b2, st);
+  qf::launch_pack_j_A(P<double>(ctx->y2), n, o, P<double>(ctx->ja_y),
+                      P<double>(ctx->ja_y) + (size_t)n * kj, st);
+  const struct {
+    DevBuf* a;
+    DevBuf* j;
+  } jops[2] = {{&ctx->ja_h, &ctx->jh}, {&ctx->ja_y, &ctx->jy}};
+  for (const auto& op : jops)
+    for (int which = 0; which < 2; ++which)
+      qf::launch_gemm_nt_f64_splitk(P<double>(*op.a) + which * (size_t)n * kj,
+                                    which == 0 ? b1 : b2, P<double>(ctx->jpart),
+                                    P<double>(*op.j) + which * (size_t)n * v, n, v, (int)kj,
+                                    -1.0, st);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -300,7 +316,8 @@ int qflow_destroy(qflow_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   DevBuf* bufs[] = {&ctx->ra_h,   &ctx->r22_h,    &ctx->ra_y,   &ctx->r22_y,    &ctx->rta,
                     &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
-                    &ctx->jh,     &ctx->jy,
+                    &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
+                    &ctx->jpart,
                     &ctx->f,      &ctx->V,        &ctx->W,      &ctx->y1,       &ctx->y2,
                     &ctx->wy,     &ctx->L,        &ctx->LY,     &ctx->scal,     &ctx->r1,
                     &ctx->r2,     &ctx->t1n,      &ctx->t2n,    &ctx->heff,     &ctx->heff_off,
@@ -369,10 +386,17 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->g22_y, sizeof(double) * n2 * ov));
   QF_TRY(ensure(ctx, ctx->jh, sizeof(double) * 2 * n * v));
   QF_TRY(ensure(ctx, ctx->jy, sizeof(double) * 2 * n * v));
+  const size_t kj = (size_t)o * o * v;
+  QF_TRY(ensure(ctx, ctx->ja_h, sizeof(double) * 2 * n * kj));
+  QF_TRY(ensure(ctx, ctx->ja_y, sizeof(double) * 2 * n * kj));
+  QF_TRY(ensure(ctx, ctx->jb, sizeof(double) * 2 * v * kj));
+  QF_TRY(ensure(ctx, ctx->jpart, sizeof(double) * qf::kMaxSplits * n * v));
   qf::launch_fock(h, eri, n, o, P<double>(ctx->f), ctx->stream);
   qf::launch_repack(eri, n, o, P<double>(ctx->V), P<double>(ctx->W), ctx->stream);
   qf::launch_pack_ring_A(P<double>(ctx->V), n, o, P<double>(ctx->ra_h), P<double>(ctx->r22_h),
                          ctx->stream);
+  qf::launch_pack_j_A(P<double>(ctx->V), n, o, P<double>(ctx->ja_h),
+                      P<double>(ctx->ja_h) + (size_t)n * o * o * v, ctx->stream);
   QF_HIP(hipGetLastError());
   ctx->fock.assign(n2, 0.0);
   std::vector<double> hh(n2);

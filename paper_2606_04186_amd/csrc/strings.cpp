@@ -68,6 +68,16 @@ bool build_strings(int na, int ne, Strings* S) {
 // of the 64-lane wavefront so that a wavefront evaluates one pattern (one set
 // of terms).  Entry = kind << 24 | a << 18 | b << 12 | c << 6 | d with kind
 // 2, 1, 0 for two-, one- and zero-body.
+// The downfolded operator is Hermitian and spin-free, so its two-body block
+// obeys x2_pqrs = x2_qpsr = x2_rspq = x2_srqp and its one-body block is
+// symmetric.  Only the lexicographically smallest member of each such orbit
+// is a task; the kernels write every distinct member.
+static bool canonical2(int a, int b, int c, int d) {
+  const int key = ((a * 64 + b) * 64 + c) * 64 + d;
+  return key <= ((b * 64 + a) * 64 + d) * 64 + c && key <= ((c * 64 + d) * 64 + a) * 64 + b &&
+         key <= ((d * 64 + c) * 64 + b) * 64 + a;
+}
+
 int build_tasks(int na, int ne, int32_t* out, int cap) {
   int m = 0;
   auto pad = [&]() {
@@ -83,7 +93,7 @@ int build_tasks(int na, int ne, int32_t* out, int cap) {
         for (int c = 0; c < na; ++c)
           for (int d = 0; d < na; ++d) {
             const int bits = ((a < ne) << 3) | ((b < ne) << 2) | ((c < ne) << 1) | (d < ne);
-            if (bits != pat) continue;
+            if (bits != pat || !canonical2(a, b, c, d)) continue;
             if (m >= cap) return -1;
             out[m++] = (2 << 24) | (a << 18) | (b << 12) | (c << 6) | d;
           }
@@ -91,7 +101,7 @@ int build_tasks(int na, int ne, int32_t* out, int cap) {
   }
   for (int pat = 0; pat < 4; ++pat) {
     for (int a = 0; a < na; ++a)
-      for (int b = 0; b < na; ++b) {
+      for (int b = a; b < na; ++b) {
         if ((((a < ne) << 1) | (b < ne)) != pat) continue;
         if (m >= cap) return -1;
         out[m++] = (1 << 24) | (a << 18) | (b << 12);
