@@ -159,7 +159,7 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
  * events on the context's stream), in the order: [F,sigma] intermediate,
  * ladder contraction of H_N, ladder contraction of [F,sigma], ring operand
  * packing, ring contractions (four matrix-core GEMMs), one-body ring terms,
- * residual, build_heff, solve, update.  n is the capacity of ms (host).  Returns the
+ * sigma1 applied to the two-body parts, residual, build_heff, solve, update.  n is the capacity of ms (host).  Returns the
  * count written. */
 int qflow_last_timings(const qflow_ctx* ctx, float* ms, int n);
 

@@ -184,8 +184,8 @@ class Context:
                                           ctypes.byref(md), flags))
         return em.value, md.value
 
-    STAGES = ("yg", "ladder_h", "ladder_yg", "ring_pack", "ring_gemm", "ring_j", "residual",
-              "heff", "solve", "update")
+    STAGES = ("yg", "ladder_h", "ladder_yg", "ring_pack", "ring_gemm", "ring_j", "sigma1_x",
+              "residual", "heff", "solve", "update")
 
     def last_timings(self):
         """Per-stage device milliseconds of the last flow_step (STAGES order)."""

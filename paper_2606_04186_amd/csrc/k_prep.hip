@@ -253,6 +253,55 @@ __global__ void k_pack_ring_T(const double* __restrict__ t2, int o, int v, doubl
 // J1[p][q] = - sum_{t,u occ, w virt} X[w,p,t,u] (2 t2[t,u,w,q] - t2[t,u,q,w])
 // J2[q][p] = - sum_{t,u occ, w virt} t2[t,u,w,p] (2 X[t,u,w,q] - X[t,u,q,w])
 // (p virtual in J2, q virtual in J1; the other index runs over all orbitals)
+// Z(p,q,r,s) = sum_t sigma1(p,t) X(t,q,r,s): the one-body part of sigma
+// (t1) applied to the first index of a two-body operator.  With X Hermitian
+// and pair symmetric and sigma1 anti-Hermitian, the four terms of
+// [X, sigma1]_2 are -(Z_pqrs + Z_qpsr + Z_rspq + Z_srqp).
+// sigma1(a,i) = t1[i][a], sigma1(i,a) = -t1[i][a].  One thread per column
+// c = (q,r,s); t1 is staged in LDS and read by broadcast.
+constexpr int kZChunk = 16;
+
+__global__ __launch_bounds__(256) void k_sigma1_x(const double* __restrict__ X,
+                                                  const double* __restrict__ t1, int n, int o,
+                                                  double* Z) {
+  __shared__ double ts[64 * 64];
+  const int v = n - o;
+  for (int e = threadIdx.x; e < o * v; e += blockDim.x) ts[e] = t1[e];
+  __syncthreads();
+  const size_t n3 = (size_t)n * n * n;
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n3) return;
+  // p occupied: Z[p][c] = -sum_{t virtual} t1[p][t-o] X[t][c]
+  for (int p0 = 0; p0 < o; p0 += kZChunk) {
+    double acc[kZChunk];
+#pragma unroll
+    for (int i = 0; i < kZChunk; ++i) acc[i] = 0.0;
+    for (int t = o; t < n; ++t) {
+      const double x = X[(size_t)t * n3 + c];
+#pragma unroll
+      for (int i = 0; i < kZChunk; ++i)
+        if (p0 + i < o) acc[i] -= ts[(p0 + i) * v + (t - o)] * x;
+    }
+#pragma unroll
+    for (int i = 0; i < kZChunk; ++i)
+      if (p0 + i < o) Z[(size_t)(p0 + i) * n3 + c] = acc[i];
+  }
+  // p virtual: Z[p][c] = sum_{t occupied} t1[t][p-o] X[t][c]
+  for (int t0 = 0; t0 < o; t0 += kZChunk) {
+    double xo[kZChunk];
+#pragma unroll
+    for (int i = 0; i < kZChunk; ++i) xo[i] = (t0 + i < o) ? X[(size_t)(t0 + i) * n3 + c] : 0.0;
+    for (int p = o; p < n; ++p) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < kZChunk; ++i)
+        if (t0 + i < o) acc += ts[(t0 + i) * v + (p - o)] * xo[i];
+      double* z = Z + (size_t)p * n3 + c;
+      *z = (t0 == 0) ? acc : *z + acc;
+    }
+  }
+}
+
 // Operands of the one-body ring terms as K-contiguous matrices over
 // k = (t*o + u)*v + (w - o), t and u occupied, w virtual:
 //   J1[p][q] = - sum_k X[w,p,t,u] (2 t2[t,u,w,q] - t2[t,u,q,w])
@@ -326,6 +375,11 @@ void launch_pack_ring_A(const double* X, int n, int o, double* Aa, double* A22, 
 void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22, hipStream_t st) {
   const size_t ov = (size_t)o * v;
   k_pack_ring_T<<<grid_for(ov * ov, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, Ta, T22);
+}
+
+void launch_sigma1_x(const double* X, const double* t1, int n, int o, double* Z, hipStream_t st) {
+  const size_t n3 = (size_t)n * n * n;
+  k_sigma1_x<<<(unsigned)((n3 + kBlock - 1) / kBlock), kBlock, 0, st>>>(X, t1, n, o, Z);
 }
 
 void launch_pack_j_A(const double* X, int n, int o, double* A1, double* A2, hipStream_t st) {

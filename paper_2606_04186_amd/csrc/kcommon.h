@@ -31,6 +31,7 @@ struct GlobalOps {
   const double *f, *V, *y1, *y2, *L, *LY, *t1, *t2;
   int n, o;
   const double *ga_h, *g22_h, *j1_h, *j2_h, *ga_y, *g22_y, *j1_y, *j2_y;
+  const double *z_h, *z_y;
 };
 
 }  // namespace qf

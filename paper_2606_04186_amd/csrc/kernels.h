@@ -28,6 +28,8 @@ void launch_fill(double* x, size_t count, double value, hipStream_t st);
 // ring intermediates (layouts in qflow_eval.h, DenseOp)
 void launch_pack_ring_A(const double* X, int n, int o, double* Aa, double* A22, hipStream_t st);
 void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22, hipStream_t st);
+// Z = sigma1 X over the first index (k_prep.hip, k_sigma1_x); n^4 doubles
+void launch_sigma1_x(const double* X, const double* t1, int n, int o, double* Z, hipStream_t st);
 // one-body ring operands (layouts in k_prep.hip, k_pack_j_A / k_pack_j_B)
 void launch_pack_j_A(const double* X, int n, int o, double* A1, double* A2, hipStream_t st);
 void launch_pack_j_B(const double* t2, int o, int v, double* B1, double* B2, hipStream_t st);
@@ -43,8 +45,9 @@ void launch_gemm_nt_f64_splitk(const double* A, const double* B, double* part, d
                                int N, int K, double scale, hipStream_t st);
 
 // residual of Hbar(sigma)
-struct RingOps {            // Ga, G22, J1, J2 of H_N and of Yg
+struct RingOps {            // Ga, G22, J1, J2, Z of H_N and of Yg
   const double *ga_h, *g22_h, *j1_h, *j2_h, *ga_y, *g22_y, *j1_y, *j2_y;
+  const double *z_h, *z_y;
 };
 void launch_residual(const double* f, const double* V, const double* y1, const double* y2,
                      const double* L, const double* LY, const RingOps& rings, const double* t1,

@@ -22,7 +22,7 @@ using qf::SpaceDev;
 namespace {
 
 constexpr int kMaxSub = 12;        // Davidson subspace before restart
-constexpr int kStages = 10;
+constexpr int kStages = 11;
 
 struct DevBuf {
   void* p = nullptr;
@@ -48,6 +48,8 @@ struct qflow_ctx {
   // one-body ring terms: packed operands (A of H constant, A of Yg and B per
   // step) and the split-K slices
   DevBuf ja_h, ja_y, jb, jpart;
+  // Z = sigma1 X (first index) of H_N and Yg, n^4 each
+  DevBuf z_h, z_y;
   DevBuf heff, heff_off, amp, amp_off, work, work_off, energy, c0, iters, status, spaces,
       strings, out2, partial, tasks, mtab;
   int task_slots[3] = {0, 0, 0};
@@ -201,7 +203,8 @@ qf::RingOps rings_of(qflow_ctx* ctx) {
   const size_t nv = (size_t)ctx->n * ctx->v;
   return qf::RingOps{P<double>(ctx->ga_h), P<double>(ctx->g22_h), P<double>(ctx->jh),
                      P<double>(ctx->jh) + nv,  P<double>(ctx->ga_y), P<double>(ctx->g22_y),
-                     P<double>(ctx->jy),       P<double>(ctx->jy) + nv};
+                     P<double>(ctx->jy),       P<double>(ctx->jy) + nv,
+                     P<double>(ctx->z_h),      P<double>(ctx->z_y)};
 }
 
 // Yg = [F,sigma], the ladder intermediates L = W t2^T, LY = WY t2^T and the
@@ -256,6 +259,10 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
                                     which == 0 ? b1 : b2, P<double>(ctx->jpart),
                                     P<double>(*op.j) + which * (size_t)n * v, n, v, (int)kj,
                                     -1.0, st);
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[6], ctx->stream));
+  // Z = sigma1 X of H_N and Yg
+  qf::launch_sigma1_x(P<double>(ctx->V), t1, n, o, P<double>(ctx->z_h), st);
+  qf::launch_sigma1_x(P<double>(ctx->y2), t1, n, o, P<double>(ctx->z_y), st);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -317,7 +324,7 @@ int qflow_destroy(qflow_ctx* ctx) {
   DevBuf* bufs[] = {&ctx->ra_h,   &ctx->r22_h,    &ctx->ra_y,   &ctx->r22_y,    &ctx->rta,
                     &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
                     &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
-                    &ctx->jpart,
+                    &ctx->jpart,  &ctx->z_h,      &ctx->z_y,
                     &ctx->f,      &ctx->V,        &ctx->W,      &ctx->y1,       &ctx->y2,
                     &ctx->wy,     &ctx->L,        &ctx->LY,     &ctx->scal,     &ctx->r1,
                     &ctx->r2,     &ctx->t1n,      &ctx->t2n,    &ctx->heff,     &ctx->heff_off,
@@ -391,6 +398,8 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->ja_y, sizeof(double) * 2 * n * kj));
   QF_TRY(ensure(ctx, ctx->jb, sizeof(double) * 2 * v * kj));
   QF_TRY(ensure(ctx, ctx->jpart, sizeof(double) * qf::kMaxSplits * n * v));
+  QF_TRY(ensure(ctx, ctx->z_h, sizeof(double) * n4));
+  QF_TRY(ensure(ctx, ctx->z_y, sizeof(double) * n4));
   qf::launch_fock(h, eri, n, o, P<double>(ctx->f), ctx->stream);
   qf::launch_repack(eri, n, o, P<double>(ctx->V), P<double>(ctx->W), ctx->stream);
   qf::launch_pack_ring_A(P<double>(ctx->V), n, o, P<double>(ctx->ra_h), P<double>(ctx->r22_h),
@@ -476,7 +485,7 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
                       P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx),
                       t1, t2, ctx->n, ctx->o, P<double>(ctx->scal), P<double>(ctx->r1),
                       P<double>(ctx->r2), nullptr, ctx->stream);
-  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[7], ctx->stream));
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[8], ctx->stream));
   if (K > 0)
     qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1), P<double>(ctx->y2),
                     P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx), t1, t2, ctx->n, ctx->o,
@@ -580,19 +589,19 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
     ctx->timed = false;
     return r;
   }
-  QF_HIP(hipEventRecord(ctx->ev[6], st));
+  QF_HIP(hipEventRecord(ctx->ev[7], st));
   r = run_heff(ctx, K, t1, t2, P<double>(ctx->heff), P<int64_t>(ctx->heff_off));
   if (r != QFLOW_OK) {
     ctx->timed = false;
     return r;
   }
-  QF_HIP(hipEventRecord(ctx->ev[8], st));
+  QF_HIP(hipEventRecord(ctx->ev[9], st));
   r = run_solve(ctx, K, P<double>(ctx->heff), P<int64_t>(ctx->heff_off), P<double>(ctx->energy),
                 P<double>(ctx->c0), P<double>(ctx->amp), P<int64_t>(ctx->amp_off),
                 P<int32_t>(ctx->iters), P<int32_t>(ctx->status), 1e-10, 200);
   ctx->timed = false;
   if (r != QFLOW_OK) return r;
-  QF_HIP(hipEventRecord(ctx->ev[9], st));
+  QF_HIP(hipEventRecord(ctx->ev[10], st));
   qf::launch_update(t1, t2, P<double>(ctx->r1), P<double>(ctx->r2), P<double>(ctx->f), owner1,
                     owner2, n, o, step, P<double>(ctx->t1n), P<double>(ctx->t2n), st);
   if (K > 0)
@@ -607,14 +616,14 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
                         hipMemcpyDeviceToDevice, st));
   if (K > 0)
     QF_HIP(hipMemcpyAsync(energy, ctx->energy.p, sizeof(double) * K, hipMemcpyDeviceToDevice, st));
-  QF_HIP(hipEventRecord(ctx->ev[10], st));
+  QF_HIP(hipEventRecord(ctx->ev[11], st));
   double out[2];
   QF_HIP(hipMemcpyAsync(out, ctx->out2.p, sizeof(out), hipMemcpyDeviceToHost, st));
   QF_HIP(hipStreamSynchronize(st));
   *e_mean = out[0];
   *max_dt = out[1];
   // stage times: Yg | ladder GEMM (H) | ladder GEMM (Yg) | ring packing | ring GEMMs | J |
-  // residual | heff | solve | update
+  // Z | residual | heff | solve | update
   int pairs[kStages][2];
   for (int s = 0; s < kStages; ++s) {
     pairs[s][0] = s;

@@ -136,6 +136,7 @@ struct DenseOp {
   const double* G22 = nullptr;   // [n*n][v*o]
   const double* J1 = nullptr;    // [n][v]
   const double* J2 = nullptr;    // [n][v]
+  const double* Z = nullptr;     // [n][n][n][n], sum_t sigma1(p,t) x2(t,q,r,s)
   QF_HD double one(int p, int q) const { return x1[p * n + q]; }
   QF_HD double two(int p, int q, int r, int s) const {
     return x2[(((size_t)p * n + q) * n + r) * n + s];
@@ -151,6 +152,9 @@ struct DenseOp {
   }
   QF_HD double j1(int p, int q) const { return J1[p * (n - o) + (q - o)]; }
   QF_HD double j2(int q, int p) const { return J2[q * (n - o) + (p - o)]; }
+  QF_HD double z(int p, int q, int r, int s) const {
+    return Z[(((size_t)p * n + q) * n + r) * n + s];
+  }
   QF_HD bool act(int) const { return true; }
 };
 
@@ -298,10 +302,16 @@ struct Comm {
       over_block(or_, [&](int t) { res -= a.one(t, s) * b.two(p, q, r, t); });
     // one-body B x two-body A:
     //   - sum_t [B_pt A_tqrs + B_qt A_ptrs - B_tr A_pqts - B_ts A_pqrt]
-    over_block(!op, [&](int t) { res -= b.one(p, t) * a.two(t, q, r, s); });
-    over_block(!oq, [&](int t) { res -= b.one(q, t) * a.two(p, t, r, s); });
-    over_block(!or_, [&](int t) { res += b.one(t, r) * a.two(p, q, t, s); });
-    over_block(!os, [&](int t) { res += b.one(t, s) * a.two(p, q, r, t); });
+    // = -(Z_pqrs + Z_qpsr + Z_rspq + Z_srqp) with Z = B A over the first index
+    // (A Hermitian and pair symmetric, B anti-Hermitian)
+    if constexpr (kUseL) {
+      if (lead()) res -= a.z(p, q, r, s) + a.z(q, p, s, r) + a.z(r, s, p, q) + a.z(s, r, q, p);
+    } else {
+      over_block(!op, [&](int t) { res -= b.one(p, t) * a.two(t, q, r, s); });
+      over_block(!oq, [&](int t) { res -= b.one(q, t) * a.two(p, t, r, s); });
+      over_block(!or_, [&](int t) { res += b.one(t, r) * a.two(p, q, t, s); });
+      over_block(!os, [&](int t) { res += b.one(t, s) * a.two(p, q, r, t); });
+    }
     // ladders: sum_tu (1 - n_t - n_u)(A_pqtu B_turs - B_pqtu A_turs)
     if (or_ && os) res += ladder_vv(p, q, r, s);
     if (!or_ && !os)
