@@ -36,19 +36,53 @@ __device__ void load_active(const SpaceDev& sp, int n, int o, Active& A) {
   __syncthreads();
 }
 
-// Per-space tables of the marked [E,sigma] evaluation (see MarkTables).
+// Per-space tables of the marked [E,sigma] evaluation (see MarkTables and
+// mark_table_entry).  The two-body tables D_j(t;a,b,c) = sum_{x external}
+// f[x][t] sigma(.. x in slot j ..) vanish unless b and c share a class and a
+// is in the other one, and x then runs over the externals of a's class.  D_0
+// and D_1 are summed directly; anti-Hermiticity of sigma gives the others:
+// D_2(t;a,b,c) = -D_0(t;c,a,b), D_3(t;a,b,c) = -D_1(t;c,a,b).
 __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
                                                   const SpaceDev* __restrict__ spaces,
                                                   double* tab, int64_t tab_stride) {
   __shared__ Active A;
+  constexpr int kNa = 6;   // largest supported space, (3,3)
+  __shared__ double d01[2 * kNa * kNa * kNa * kNa];
   const int k = blockIdx.x;
   const SpaceDev sp = spaces[k];
   load_active(sp, g.n, g.o, A);
-  const Sigma s{g.t1, g.t2, g.n, g.o, g.n - g.o};
-  int a, b, c, d;
-  const int tot = mark_sizes(sp.na, &a, &b, &c, &d);
+  const int n = g.n;
+  const Sigma s{g.t1, g.t2, n, g.o, n - g.o};
+  int s1, s2, s3, s4;
+  mark_sizes(sp.na, &s1, &s2, &s3, &s4);
+  const int na = sp.na, nocc = sp.nocc, n2 = na * na, n3 = n2 * na, n4 = n3 * na;
+  if (na > kNa) return;   // the host admits (2,2) and (3,3) spaces only
   double* out = tab + (int64_t)k * tab_stride;
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) out[e] = mark_table_entry(s, g.f, A, e);
+  // tau1, tau2, D1
+  for (int e = threadIdx.x; e < s1 + s2 + s3; e += blockDim.x)
+    out[e] = mark_table_entry(s, g.f, A, e);
+  // D_0, D_1
+  for (int e = threadIdx.x; e < 2 * n4; e += blockDim.x) {
+    const int j = e / n4, t = e / n3 % na, a = e / n2 % na, b = e / na % na, c = e % na;
+    const bool ao = a < nocc, bo = b < nocc, co = c < nocc;
+    double acc = 0.0;
+    if (bo == co && ao != bo) {
+      const int ft = A.orb[t], pa = A.orb[a], pb = A.orb[b], pc = A.orb[c];
+      const int m = A.next(ao);
+      for (int i = 0; i < m; ++i) {
+        const int x = A.extv(ao, i);
+        acc += g.f[x * n + ft] * (j == 0 ? s.two(x, pa, pb, pc) : s.two(pa, x, pb, pc));
+      }
+    }
+    d01[e] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 4 * n4; e += blockDim.x) {
+    const int j = e / n4, r = e % n4;
+    const int t = r / n3, a = r / n2 % na, b = r / na % na, c = r % na;
+    const double x = (j < 2) ? d01[r + j * n4] : -d01[(j - 2) * n4 + ((t * na + c) * na + a) * na + b];
+    out[s1 + s2 + s3 + e] = x;
+  }
 }
 
 // Slot layout while accumulating: [x0, x1 (na^2), x2 (na^4)].

@@ -110,13 +110,23 @@ __global__ void k_yg2(const double* __restrict__ f, const double* __restrict__ t
   }
 }
 
-__global__ void k_yg1(const double* __restrict__ f, const double* __restrict__ t1,
-                      const double* __restrict__ t2, int n, int o, double* y1, double* scal) {
+// one wavefront per element of y1; the last wavefront computes the scalar
+__global__ __launch_bounds__(256) void k_yg1(const double* __restrict__ f,
+                                             const double* __restrict__ t1,
+                                             const double* __restrict__ t2, int n, int o,
+                                             double* y1, double* scal) {
   const int v = n - o;
-  Yg Y{f, Sigma{t1, t2, n, o, v}, n, o};
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < n * n) y1[idx] = Y.one(idx / n, idx % n);
-  if (idx == 0) scal[2] = Y.zero();
+  const int lane = threadIdx.x % 64;
+  const int idx = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (idx > n * n) return;
+  Yg Y{f, Sigma{t1, t2, n, o, v}, n, o, lane, 64};
+  const double x = wave_sum(idx < n * n ? Y.one(idx / n, idx % n) : Y.zero());
+  if (lane == 0) {
+    if (idx < n * n)
+      y1[idx] = x;
+    else
+      scal[2] = x;
+  }
 }
 
 __global__ void k_fill(double* x, size_t count, double value) {
@@ -186,27 +196,46 @@ __global__ void k_scatter_owned(const SpaceDev* __restrict__ spaces, const doubl
 }
 
 // out[0] = mean energy (fixed summation order), out[1] = max |t_new - t_old|
-__global__ __launch_bounds__(1024) void k_finish(const double* __restrict__ energy, int K,
-                                                 const double* __restrict__ t1,
-                                                 const double* __restrict__ t2,
-                                                 const double* __restrict__ t1n,
-                                                 const double* __restrict__ t2n, int o, int v,
-                                                 double* out) {
-  __shared__ double red[16];
+// max |t_new - t_old| in two passes: per-block maxima, then one block
+// combines them and forms the mean energy.
+constexpr int kFinishBlocks = kFinishParts;
+
+__global__ __launch_bounds__(256) void k_dt_max(const double* __restrict__ t1,
+                                                const double* __restrict__ t2,
+                                                const double* __restrict__ t1n,
+                                                const double* __restrict__ t2n, int o, int v,
+                                                double* part) {
+  __shared__ double red[4];
   const size_t nt2 = (size_t)o * o * v * v, nt1 = (size_t)o * v;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
   double m = 0.0;
-  for (size_t i = threadIdx.x; i < nt2; i += blockDim.x) m = fmax(m, fabs(t2n[i] - t2[i]));
-  for (size_t i = threadIdx.x; i < nt1; i += blockDim.x) m = fmax(m, fabs(t1n[i] - t1[i]));
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nt2; i += stride)
+    m = fmax(m, fabs(t2n[i] - t2[i]));
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nt1; i += stride)
+    m = fmax(m, fabs(t1n[i] - t1[i]));
   m = wave_max(m);
   if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = m;
   __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void k_finish(const double* __restrict__ energy, int K,
+                                                const double* __restrict__ part, int nparts,
+                                                double* out) {
+  __shared__ double rm[4], re[4];
+  double m = 0.0, e = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmax(m, part[i]);
+  for (int k = threadIdx.x; k < K; k += blockDim.x) e += energy[k];
+  m = wave_max(m);
+  e = wave_sum(e);
+  if (threadIdx.x % 64 == 0) {
+    rm[threadIdx.x / 64] = m;
+    re[threadIdx.x / 64] = e;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    double x = 0.0;
-    for (int w = 0; w < (int)(blockDim.x / 64); ++w) x = fmax(x, red[w]);
-    double e = 0.0;
-    for (int k = 0; k < K; ++k) e += energy[k];
-    out[0] = (K > 0) ? e / K : 0.0;
-    out[1] = x;
+    out[0] = (K > 0) ? (re[0] + re[1] + re[2] + re[3]) / K : 0.0;
+    out[1] = fmax(fmax(rm[0], rm[1]), fmax(rm[2], rm[3]));
   }
 }
 
@@ -364,7 +393,7 @@ void launch_yg(const double* f, const double* t1, const double* t2, int n, int o
                double* y2, double* wy, double* scal, hipStream_t st) {
   const size_t n4 = (size_t)n * n * n * n;
   k_yg2<<<grid_for(n4, kBlock, 65536), kBlock, 0, st>>>(f, t1, t2, n, o, y2, wy);
-  k_yg1<<<grid_for((size_t)n * n), kBlock, 0, st>>>(f, t1, t2, n, o, y1, scal);
+  k_yg1<<<grid_for(((size_t)n * n + 1) * 64), kBlock, 0, st>>>(f, t1, t2, n, o, y1, scal);
 }
 
 void launch_pack_ring_A(const double* X, int n, int o, double* Aa, double* A22, hipStream_t st) {
@@ -412,9 +441,10 @@ void launch_scatter_owned(const SpaceDev* spaces, const double* amp, const int64
 }
 
 void launch_finish(const double* energy, int K, const double* t1, const double* t2,
-                   const double* t1n, const double* t2n, int o, int v, double* out2,
-                   hipStream_t st) {
-  k_finish<<<1, 1024, 0, st>>>(energy, K, t1, t2, t1n, t2n, o, v, out2);
+                   const double* t1n, const double* t2n, int o, int v, double* part,
+                   double* out2, hipStream_t st) {
+  k_dt_max<<<kFinishBlocks, kBlock, 0, st>>>(t1, t2, t1n, t2n, o, v, part);
+  k_finish<<<1, kBlock, 0, st>>>(energy, K, part, kFinishBlocks, out2);
 }
 
 }  // namespace qf

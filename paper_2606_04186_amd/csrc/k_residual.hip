@@ -50,15 +50,17 @@ __global__ __launch_bounds__(256) void k_residual1(GlobalOps g, double* r1) {
   if (lane == 0) r1[idx] = H.one(o + a, i) + x;
 }
 
-// scal[0] = [H_N,sigma]_0, scal[1] = [Yg,sigma]_0 (scal[3] = E_ref, set at load)
-__global__ void k_residual0(GlobalOps g, double* scal, double* e0) {
+// scal[0] = [H_N,sigma]_0, scal[1] = [Yg,sigma]_0 (scal[3] = E_ref, set at
+// load); one wavefront, lanes split the contraction loops
+__global__ __launch_bounds__(64) void k_residual0(GlobalOps g, double* scal, double* e0) {
   const int n = g.n, o = g.o, v = n - o;
+  const int lane = threadIdx.x;
   const Sigma s{g.t1, g.t2, n, o, v};
   const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.z_h};
   const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y};
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const double zh = make_comm(H, s, n, o).c0();
-    const double zy = make_comm(Y, s, n, o).c0();
+  const double zh = wave_sum(make_comm_split(H, s, n, o, lane, 64).c0());
+  const double zy = wave_sum(make_comm_split(Y, s, n, o, lane, 64).c0());
+  if (lane == 0) {
     scal[0] = zh;
     scal[1] = zy;
     if (e0) *e0 = scal[3] + zh + 0.5 * zy;

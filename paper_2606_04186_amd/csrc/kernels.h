@@ -95,8 +95,11 @@ void launch_update(const double* t1, const double* t2, const double* r1, const d
 void launch_scatter_owned(const SpaceDev* spaces, const double* amp, const int64_t* amp_off,
                           const int32_t* status, const int32_t* owner1, const int32_t* owner2,
                           int n, int o, int K, double* t1n, double* t2n, hipStream_t st);
+// mean energy and max |t_new - t_old| into out2[0..1]; part holds
+// kFinishParts doubles of scratch
+constexpr int kFinishParts = 512;
 void launch_finish(const double* energy, int K, const double* t1, const double* t2,
-                   const double* t1n, const double* t2n, int o, int v, double* out2,
-                   hipStream_t st);
+                   const double* t1n, const double* t2n, int o, int v, double* part,
+                   double* out2, hipStream_t st);
 
 }  // namespace qf

@@ -50,6 +50,7 @@ struct qflow_ctx {
   DevBuf ja_h, ja_y, jb, jpart;
   // Z = sigma1 X (first index) of H_N and Yg, n^4 each
   DevBuf z_h, z_y;
+  DevBuf dtpart;   // per-block maxima of |t_new - t_old|
   DevBuf heff, heff_off, amp, amp_off, work, work_off, energy, c0, iters, status, spaces,
       strings, out2, partial, tasks, mtab;
   int task_slots[3] = {0, 0, 0};
@@ -324,7 +325,7 @@ int qflow_destroy(qflow_ctx* ctx) {
   DevBuf* bufs[] = {&ctx->ra_h,   &ctx->r22_h,    &ctx->ra_y,   &ctx->r22_y,    &ctx->rta,
                     &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
                     &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
-                    &ctx->jpart,  &ctx->z_h,      &ctx->z_y,
+                    &ctx->jpart,  &ctx->z_h,      &ctx->z_y,      &ctx->dtpart,
                     &ctx->f,      &ctx->V,        &ctx->W,      &ctx->y1,       &ctx->y2,
                     &ctx->wy,     &ctx->L,        &ctx->LY,     &ctx->scal,     &ctx->r1,
                     &ctx->r2,     &ctx->t1n,      &ctx->t2n,    &ctx->heff,     &ctx->heff_off,
@@ -400,6 +401,7 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->jpart, sizeof(double) * qf::kMaxSplits * n * v));
   QF_TRY(ensure(ctx, ctx->z_h, sizeof(double) * n4));
   QF_TRY(ensure(ctx, ctx->z_y, sizeof(double) * n4));
+  QF_TRY(ensure(ctx, ctx->dtpart, sizeof(double) * qf::kFinishParts));
   qf::launch_fock(h, eri, n, o, P<double>(ctx->f), ctx->stream);
   qf::launch_repack(eri, n, o, P<double>(ctx->V), P<double>(ctx->W), ctx->stream);
   qf::launch_pack_ring_A(P<double>(ctx->V), n, o, P<double>(ctx->ra_h), P<double>(ctx->r22_h),
@@ -609,7 +611,7 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
                              P<int64_t>(ctx->amp_off), P<int32_t>(ctx->status), owner1, owner2,
                              n, o, K, P<double>(ctx->t1n), P<double>(ctx->t2n), st);
   qf::launch_finish(P<double>(ctx->energy), K, t1, t2, P<double>(ctx->t1n), P<double>(ctx->t2n),
-                    o, v, P<double>(ctx->out2), st);
+                    o, v, P<double>(ctx->dtpart), P<double>(ctx->out2), st);
   QF_HIP(hipGetLastError());
   QF_HIP(hipMemcpyAsync(t1, ctx->t1n.p, sizeof(double) * o * v, hipMemcpyDeviceToDevice, st));
   QF_HIP(hipMemcpyAsync(t2, ctx->t2n.p, sizeof(double) * (size_t)o * o * v * v,

@@ -761,13 +761,21 @@ struct Yg {
   const double* f;
   Sigma s;
   int n, o;
+  // lane split of the contraction loops (as in Comm); the caller sums lanes
+  int ln = 0, nl = 1;
   QF_HD bool occ(int p) const { return p < o; }
   template <class F>
   QF_HD void over_block(bool occupied, F fn) const {
     if (occupied)
-      for (int t = 0; t < o; ++t) fn(t);
+      for (int t = ln; t < o; t += nl) fn(t);
     else
-      for (int t = o; t < n; ++t) fn(t);
+      for (int t = o + ln; t < n; t += nl) fn(t);
+  }
+  // (t occupied, u virtual) pairs, split over lanes
+  template <class F>
+  QF_HD void over_ov(F fn) const {
+    const int v = n - o;
+    for (int k = ln; k < o * v; k += nl) fn(k / v, o + k % v);
   }
   QF_HD double two(int p, int q, int r, int s_) const {
     double res = 0.0;
@@ -787,20 +795,20 @@ struct Yg {
     over_block(!occ(q), [&](int t) { res += f[p * n + t] * s.one(t, q); });
     over_block(!occ(p), [&](int t) { res -= s.one(p, t) * f[t * n + q]; });
     if (!occ(p) && occ(q))
-      for (int t = 0; t < o; ++t)
-        for (int u = o; u < n; ++u)
-          res += f[t * n + u] * (2.0 * s.two(u, p, t, q) - s.two(u, p, q, t));
+      over_ov([&](int t, int u) {
+        res += f[t * n + u] * (2.0 * s.two(u, p, t, q) - s.two(u, p, q, t));
+      });
     if (occ(p) && !occ(q))
-      for (int t = o; t < n; ++t)
-        for (int u = 0; u < o; ++u)
-          res -= f[t * n + u] * (2.0 * s.two(u, p, t, q) - s.two(u, p, q, t));
+      over_ov([&](int u, int t) {
+        res -= f[t * n + u] * (2.0 * s.two(u, p, t, q) - s.two(u, p, q, t));
+      });
     return res;
   }
   QF_HD double zero() const {
     double z = 0.0;
-    for (int t = 0; t < o; ++t)
-      for (int u = o; u < n; ++u)
-        z += 2.0 * (f[t * n + u] * s.one(u, t) - f[u * n + t] * s.one(t, u));
+    over_ov([&](int t, int u) {
+      z += 2.0 * (f[t * n + u] * s.one(u, t) - f[u * n + t] * s.one(t, u));
+    });
     return z;
   }
 };
