@@ -1,119 +1,168 @@
-// FP64 contractions on matrix cores (ladder and ring intermediates).
+// FP64 contractions on matrix cores (ladder, ring and one-body ring
+// intermediates): C[M][N] = scale * sum_k A[m][k] B[n][k], both operands
+// K-contiguous (row-major A[M][K], B[N][K]).
 #include <hip/hip_runtime.h>
 
-#include <math.h>
+#include <algorithm>
 
 #include "kcommon.h"
 #include "kernels.h"
-#include "qflow_cas.h"
-#include "qflow_eval.h"
 
 namespace qf {
 
 namespace {
 
 // ---------------------------------------------------------------------------
-// FP64 matrix-core GEMM  C[M][N] += sum_k A[m][k] B[n][k]
-//
 // v_mfma_f64_16x16x4f64 operand layout (wave64): lane l supplies A[l%16][l/16]
 // and B[l/16][l%16] (k = l/16), and holds D[l/16 + 4*i][l%16] in element i.
-// A workgroup of four waves owns 64 rows and up to 176 columns (blockIdx.z
-// selects the column block); each wave computes 16 rows x 176 columns.  The K range is split in two halves over
-// blockIdx.y; both halves add into C (zeroed beforehand), and since exactly
-// two terms are added to zero the result does not depend on their order.
+//
+// A workgroup of four waves (2 x 2) owns a (32*TM) x (32*TN) tile of C; each
+// wave computes TM x TN MFMA tiles of 16 x 16.  K advances in steps of 16:
+// the next step's operands are loaded into registers while the matrix cores
+// work on the current one from LDS.  Rows of the LDS tiles are padded to 18
+// doubles, which keeps the operand reads of a half-wave on distinct banks.
+//
+// blockIdx.x = column tile (fastest, so the workgroups that share a row tile
+// of A run together), blockIdx.y = row tile, blockIdx.z = K split.  With one
+// split C is written directly; with several, split z writes slice z of C
+// (C + z*M*N) and k_sum_slices adds the slices in order.
 // ---------------------------------------------------------------------------
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGemmBM = 64;
-constexpr int kGemmBK = 16;
-constexpr int kGemmNT = 11;   // column tiles of 16 -> N <= 176
+constexpr int kBK = 16;
+constexpr int kLD = kBK + 2;
 
-__global__ __launch_bounds__(256) void k_gemm_nt_f64(const double* __restrict__ A,
-                                                     const double* __restrict__ B, double* C,
-                                                     int M, int N, int K, int kchunk,
-                                                     int to_slices) {
-  __shared__ double As[kGemmBM][kGemmBK + 1];
-  __shared__ double Bs[kGemmNT * 16][kGemmBK + 1];
+template <int TM, int TN>
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ A,
+                                                  const double* __restrict__ B,
+                                                  double* __restrict__ C, int M, int N, int K,
+                                                  int kchunk, int to_slices, double scale) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int LA = BM * kBK / 256, LB = BN * kBK / 256;
+  __shared__ double As[BM * kLD];
+  __shared__ double Bs[BN * kLD];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int m0 = blockIdx.x * kGemmBM;
-  const int n0 = blockIdx.z * kGemmNT * 16;
-  const int ks = blockIdx.y * kchunk;
+  const int wm = wave / 2, wn = wave % 2;
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
+  const int ks = blockIdx.z * kchunk;
   const int ke = min(K, ks + kchunk);
-  const int ntiles = min(kGemmNT, (N - n0 + 15) / 16);
-  d4 acc[kGemmNT];
+  double ra[LA], rb[LB];
+  auto load = [&](int k0) {
 #pragma unroll
-  for (int t = 0; t < kGemmNT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = ks; k0 < ke; k0 += kGemmBK) {
-    for (int e = threadIdx.x; e < kGemmBM * kGemmBK; e += 256) {
-      const int r = e / kGemmBK, c = e % kGemmBK;
-      const int gm = m0 + r, gk = k0 + c;
-      As[r][c] = (gm < M && gk < ke) ? A[(size_t)gm * K + gk] : 0.0;
+    for (int i = 0; i < LA; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int gm = m0 + e / kBK, gk = k0 + e % kBK;
+      ra[i] = (gm < M && gk < ke) ? A[(size_t)gm * K + gk] : 0.0;
     }
-    for (int e = threadIdx.x; e < ntiles * 16 * kGemmBK; e += 256) {
-      const int r = e / kGemmBK, c = e % kGemmBK;
-      const int gk = k0 + c;
-      Bs[r][c] = (n0 + r < N && gk < ke) ? B[(size_t)(n0 + r) * K + gk] : 0.0;
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int gn = n0 + e / kBK, gk = k0 + e % kBK;
+      rb[i] = (gn < N && gk < ke) ? B[(size_t)gn * K + gk] : 0.0;
+    }
+  };
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  if (ks < ke) load(ks);
+  for (int k0 = ks; k0 < ke; k0 += kBK) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      As[(e / kBK) * kLD + e % kBK] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      Bs[(e / kBK) * kLD + e % kBK] = rb[i];
     }
     __syncthreads();
+    if (k0 + kBK < ke) load(k0 + kBK);
 #pragma unroll
-    for (int kk = 0; kk < kGemmBK; kk += 4) {
-      const double a = As[wave * 16 + lane % 16][kk + lane / 16];
+    for (int kk = 0; kk < kBK; kk += 4) {
+      double a[TM], b[TN];
 #pragma unroll
-      for (int t = 0; t < kGemmNT; ++t) {
-        if (t < ntiles) {
-          const double b = Bs[t * 16 + lane % 16][kk + lane / 16];
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
-        }
+      for (int i = 0; i < TM; ++i)
+        a[i] = As[(wm * 16 * TM + i * 16 + lane % 16) * kLD + kk + lane / 16];
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        b[j] = Bs[(wn * 16 * TN + j * 16 + lane % 16) * kLD + kk + lane / 16];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* out = to_slices ? C + (size_t)blockIdx.z * M * N : C;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + wn * 16 * TN + j * 16 + lane % 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 16 * TM + i * 16 + lane / 16 + 4 * r;
+        if (row < M && col < N) out[(size_t)row * N + col] = scale * acc[i][j][r];
       }
     }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int t = 0; t < kGemmNT; ++t) {
-    if (t >= ntiles) continue;
-    const int col = n0 + t * 16 + lane % 16;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = m0 + wave * 16 + lane / 16 + 4 * i;
-      if (row >= M || col >= N) continue;
-      if (to_slices)
-        C[((size_t)blockIdx.y * M + row) * N + col] = acc[t][i];
-      else
-        atomicAdd(&C[(size_t)row * N + col], acc[t][i]);
-    }
-  }
 }
 
 __global__ __launch_bounds__(256) void k_sum_slices(const double* __restrict__ part, int splits,
-                                                    size_t count, double scale, double* C) {
+                                                    size_t count, double* C) {
   const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (e >= count) return;
   double s = 0.0;
   for (int i = 0; i < splits; ++i) s += part[(size_t)i * count + e];
-  C[e] = scale * s;
+  C[e] = s;
+}
+
+template <int TM, int TN>
+void launch_tiles(const double* A, const double* B, double* C, double* part, size_t part_cap,
+                  int M, int N, int K, double scale, hipStream_t st) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  const int tiles_n = (N + BN - 1) / BN, tiles_m = (M + BM - 1) / BM;
+  const long tiles = (long)tiles_n * tiles_m;
+  // split K until about four workgroups per compute unit are available,
+  // keeping at least eight K steps per split and the slices within `part`
+  constexpr long kTarget = 4 * 256;
+  const size_t mn = (size_t)M * N;
+  int splits = 1;
+  if (tiles < kTarget && part != nullptr) {
+    splits = (int)((kTarget + tiles - 1) / tiles);
+    splits = std::min(splits, std::max(1, K / (8 * kBK)));
+    splits = (int)std::min<size_t>((size_t)splits, part_cap / mn);
+    splits = std::min(splits, kMaxSplits);
+    splits = std::max(splits, 1);
+  }
+  int kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + kBK - 1) / kBK * kBK;
+  splits = (K + kchunk - 1) / kchunk;
+  if (splits <= 1) {
+    dim3 grid(tiles_n, tiles_m, 1);
+    k_gemm_f64<TM, TN><<<grid, 256, 0, st>>>(A, B, C, M, N, K, K > 0 ? K : kBK, 0, scale);
+    return;
+  }
+  dim3 grid(tiles_n, tiles_m, splits);
+  k_gemm_f64<TM, TN><<<grid, 256, 0, st>>>(A, B, part, M, N, K, kchunk, 1, scale);
+  k_sum_slices<<<grid_for(mn), kBlock, 0, st>>>(part, splits, mn, C);
 }
 
 }  // namespace
 
-void launch_gemm_nt_f64_splitk(const double* A, const double* B, double* part, double* C, int M,
-                               int N, int K, double scale, hipStream_t st) {
-  int kchunk = (K + kMaxSplits - 1) / kMaxSplits;
-  kchunk = (kchunk + kGemmBK - 1) / kGemmBK * kGemmBK;
-  const int splits = (K + kchunk - 1) / kchunk;
-  dim3 grid((M + kGemmBM - 1) / kGemmBM, splits, (N + kGemmNT * 16 - 1) / (kGemmNT * 16));
-  k_gemm_nt_f64<<<grid, 256, 0, st>>>(A, B, part, M, N, K, kchunk, 1);
-  const size_t count = (size_t)M * N;
-  k_sum_slices<<<grid_for(count), kBlock, 0, st>>>(part, splits, count, scale, C);
-}
-
 void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int N, int K,
-                        hipStream_t st) {
-  int kchunk = (K + 1) / 2;
-  kchunk = (kchunk + kGemmBK - 1) / kGemmBK * kGemmBK;
-  const int splits = (K + kchunk - 1) / kchunk;
-  dim3 grid((M + kGemmBM - 1) / kGemmBM, splits, (N + kGemmNT * 16 - 1) / (kGemmNT * 16));
-  k_gemm_nt_f64<<<grid, 256, 0, st>>>(A, B, C, M, N, K, kchunk, 0);
+                        double scale, double* part, size_t part_cap, hipStream_t st) {
+  if (M <= 0 || N <= 0) return;
+  // 128 x 96 tiles when they pad N less than 128 x 128 tiles do
+  const long pad4 = (long)((N + 127) / 128) * 128, pad3 = (long)((N + 95) / 96) * 96;
+  if (pad3 < pad4)
+    launch_tiles<4, 3>(A, B, C, part, part_cap, M, N, K, scale, st);
+  else
+    launch_tiles<4, 4>(A, B, C, part, part_cap, M, N, K, scale, st);
 }
 
 }  // namespace qf

@@ -33,16 +33,14 @@ void launch_sigma1_x(const double* X, const double* t1, int n, int o, double* Z,
 // one-body ring operands (layouts in k_prep.hip, k_pack_j_A / k_pack_j_B)
 void launch_pack_j_A(const double* X, int n, int o, double* A1, double* A2, hipStream_t st);
 void launch_pack_j_B(const double* t2, int o, int v, double* B1, double* B2, hipStream_t st);
-// C[M][N] += sum_k A[m][k] B[n][k], FP64 matrix cores (C must hold zeros)
-void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int N, int K,
-                        hipStream_t st);
-// C[M][N] = scale * sum_k A[m][k] B[n][k] with the K range split over up to
-// kMaxSplits workgroup columns; each split writes its own slice of `part`
-// (kMaxSplits*M*N doubles) and a second kernel sums the slices in order, so
-// the result is deterministic.
+// C[M][N] = scale * sum_k A[m][k] B[n][k] on the FP64 matrix cores.  When
+// the tile grid alone cannot fill the chip the K range is split; each split
+// writes its own M*N slice of `part` (capacity part_cap doubles, may be NULL
+// for no split) and the slices are summed in a fixed order, so the result is
+// deterministic.
 constexpr int kMaxSplits = 128;
-void launch_gemm_nt_f64_splitk(const double* A, const double* B, double* part, double* C, int M,
-                               int N, int K, double scale, hipStream_t st);
+void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int N, int K,
+                        double scale, double* part, size_t part_cap, hipStream_t st);
 
 // residual of Hbar(sigma)
 struct RingOps {            // Ga, G22, J1, J2, Z of H_N and of Yg

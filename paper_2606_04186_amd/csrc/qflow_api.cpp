@@ -47,7 +47,8 @@ struct qflow_ctx {
   DevBuf ra_h, r22_h, ra_y, r22_y, rta, rt22, ga_h, g22_h, ga_y, g22_y, jh, jy;
   // one-body ring terms: packed operands (A of H constant, A of Yg and B per
   // step) and the split-K slices
-  DevBuf ja_h, ja_y, jb, jpart;
+  DevBuf ja_h, ja_y, jb;
+  DevBuf gpart;   // split-K slices of the matrix-core contractions
   // Z = sigma1 X (first index) of H_N and Yg, n^4 each
   DevBuf z_h, z_y;
   DevBuf dtpart;   // per-block maxima of |t_new - t_old|
@@ -217,31 +218,27 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   const size_t n2 = (size_t)n * n, ov = (size_t)o * v;
   qf::launch_yg(P<double>(ctx->f), t1, t2, n, o, P<double>(ctx->y1), P<double>(ctx->y2),
                 P<double>(ctx->wy), P<double>(ctx->scal), ctx->stream);
-  qf::launch_fill(P<double>(ctx->L), (size_t)n * n * o * o, 0.0, ctx->stream);
-  qf::launch_fill(P<double>(ctx->LY), (size_t)n * n * o * o, 0.0, ctx->stream);
+  double* part = P<double>(ctx->gpart);
+  const size_t pcap = ctx->gpart.bytes / sizeof(double);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
-  qf::launch_gemm_nt_f64(P<double>(ctx->W), t2, P<double>(ctx->L), n * n, o * o, v * v,
-                         ctx->stream);
+  qf::launch_gemm_nt_f64(P<double>(ctx->W), t2, P<double>(ctx->L), n * n, o * o, v * v, 1.0, part,
+                         pcap, ctx->stream);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
-  qf::launch_gemm_nt_f64(P<double>(ctx->wy), t2, P<double>(ctx->LY), n * n, o * o, v * v,
-                         ctx->stream);
+  qf::launch_gemm_nt_f64(P<double>(ctx->wy), t2, P<double>(ctx->LY), n * n, o * o, v * v, 1.0,
+                         part, pcap, ctx->stream);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[3], ctx->stream));
   hipStream_t st = ctx->stream;
   qf::launch_pack_ring_T(t2, o, v, P<double>(ctx->rta), P<double>(ctx->rt22), st);
   qf::launch_pack_ring_A(P<double>(ctx->y2), n, o, P<double>(ctx->ra_y), P<double>(ctx->r22_y), st);
-  qf::launch_fill(P<double>(ctx->ga_h), n2 * ov, 0.0, st);
-  qf::launch_fill(P<double>(ctx->g22_h), n2 * ov, 0.0, st);
-  qf::launch_fill(P<double>(ctx->ga_y), n2 * ov, 0.0, st);
-  qf::launch_fill(P<double>(ctx->g22_y), n2 * ov, 0.0, st);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
   qf::launch_gemm_nt_f64(P<double>(ctx->ra_h), P<double>(ctx->rta), P<double>(ctx->ga_h),
-                         (int)n2, (int)ov, (int)(2 * ov), st);
+                         (int)n2, (int)ov, (int)(2 * ov), 1.0, part, pcap, st);
   qf::launch_gemm_nt_f64(P<double>(ctx->r22_h), P<double>(ctx->rt22), P<double>(ctx->g22_h),
-                         (int)n2, (int)ov, (int)ov, st);
+                         (int)n2, (int)ov, (int)ov, 1.0, part, pcap, st);
   qf::launch_gemm_nt_f64(P<double>(ctx->ra_y), P<double>(ctx->rta), P<double>(ctx->ga_y),
-                         (int)n2, (int)ov, (int)(2 * ov), st);
+                         (int)n2, (int)ov, (int)(2 * ov), 1.0, part, pcap, st);
   qf::launch_gemm_nt_f64(P<double>(ctx->r22_y), P<double>(ctx->rt22), P<double>(ctx->g22_y),
-                         (int)n2, (int)ov, (int)ov, st);
+                         (int)n2, (int)ov, (int)ov, 1.0, part, pcap, st);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
   // one-body ring terms J1, J2 of H_N and Yg
   const size_t kj = (size_t)o * o * v;
@@ -256,10 +253,9 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   } jops[2] = {{&ctx->ja_h, &ctx->jh}, {&ctx->ja_y, &ctx->jy}};
   for (const auto& op : jops)
     for (int which = 0; which < 2; ++which)
-      qf::launch_gemm_nt_f64_splitk(P<double>(*op.a) + which * (size_t)n * kj,
-                                    which == 0 ? b1 : b2, P<double>(ctx->jpart),
-                                    P<double>(*op.j) + which * (size_t)n * v, n, v, (int)kj,
-                                    -1.0, st);
+      qf::launch_gemm_nt_f64(P<double>(*op.a) + which * (size_t)n * kj, which == 0 ? b1 : b2,
+                             P<double>(*op.j) + which * (size_t)n * v, n, v, (int)kj, -1.0, part,
+                             pcap, st);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[6], ctx->stream));
   // Z = sigma1 X of H_N and Yg
   qf::launch_sigma1_x(P<double>(ctx->V), t1, n, o, P<double>(ctx->z_h), st);
@@ -325,7 +321,7 @@ int qflow_destroy(qflow_ctx* ctx) {
   DevBuf* bufs[] = {&ctx->ra_h,   &ctx->r22_h,    &ctx->ra_y,   &ctx->r22_y,    &ctx->rta,
                     &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
                     &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
-                    &ctx->jpart,  &ctx->z_h,      &ctx->z_y,      &ctx->dtpart,
+                    &ctx->gpart,  &ctx->z_h,      &ctx->z_y,      &ctx->dtpart,
                     &ctx->f,      &ctx->V,        &ctx->W,      &ctx->y1,       &ctx->y2,
                     &ctx->wy,     &ctx->L,        &ctx->LY,     &ctx->scal,     &ctx->r1,
                     &ctx->r2,     &ctx->t1n,      &ctx->t2n,    &ctx->heff,     &ctx->heff_off,
@@ -398,7 +394,9 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->ja_h, sizeof(double) * 2 * n * kj));
   QF_TRY(ensure(ctx, ctx->ja_y, sizeof(double) * 2 * n * kj));
   QF_TRY(ensure(ctx, ctx->jb, sizeof(double) * 2 * v * kj));
-  QF_TRY(ensure(ctx, ctx->jpart, sizeof(double) * qf::kMaxSplits * n * v));
+  // split-K slices: up to 8 of the ladder output (n^2 o^2) or 128 of J (n v)
+  QF_TRY(ensure(ctx, ctx->gpart,
+                sizeof(double) * std::max(8 * n2 * o * o, (size_t)qf::kMaxSplits * n * v)));
   QF_TRY(ensure(ctx, ctx->z_h, sizeof(double) * n4));
   QF_TRY(ensure(ctx, ctx->z_y, sizeof(double) * n4));
   QF_TRY(ensure(ctx, ctx->dtpart, sizeof(double) * qf::kFinishParts));
