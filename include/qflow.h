@@ -81,7 +81,8 @@ const char* qflow_last_error(const qflow_ctx* ctx);
  * (QFLOW_E_SYMMETRY otherwise), then builds the Fock matrix of Phi
  * f_pq = h_pq + sum_k [2(pq|kk) - (pk|kq)], E_ref = sum_k (h_kk + f_kk),
  * eps_p = f_pp, and the device layouts of the integrals.  n_orb <= 128,
- * 1 <= n_occ < n_orb.  Synchronises the stream. */
+ * 1 <= n_occ < n_orb, n_occ <= 64 (QFLOW_E_INVALID_ARG otherwise).
+ * Synchronises the stream. */
 int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const double* h,
                          const double* eri, double sym_tol);
 

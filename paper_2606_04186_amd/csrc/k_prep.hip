@@ -95,18 +95,93 @@ __global__ void k_mp2(const double* __restrict__ f, const double* __restrict__ V
 // virtual-virtual block in ladder layout
 // ---------------------------------------------------------------------------
 
-__global__ void k_yg2(const double* __restrict__ f, const double* __restrict__ t1,
-                      const double* __restrict__ t2, int n, int o, double* y2, double* wy) {
+// ---------------------------------------------------------------------------
+// U = [G, sigma_2]_2 for a Hermitian one-body G (G = f gives the two-body part
+// of Yg = [F_N, sigma]; G = y1 the one-body-times-two-body part of
+// [Yg, sigma]).  With sigma(a,b,i,j) = t2[i,j,a,b] = -sigma(i,j,a,b):
+//   U_pqrs = [r~s, q!~r] sum_{t~q} G_pt sigma_tqrs + [r~s, p!~r] sum_{t~p} G_qt sigma_ptrs
+//          - [p~q, s!~p] sum_{t~s} G_tr sigma_pqts - [p~q, r!~p] sum_{t~r} G_ts sigma_pqrt
+// (~ = same occupied/virtual class).  The sums over virtual t are four
+// matrix-core GEMMs over K = v with A1[p][t] = G[p][o+t], A2[p][t] = G[o+t][p]:
+//   P1 = A1 t2T^T, P2 = A1 t2^T, P3 = A2 t2T^T, P4 = A2 t2^T   ([n][o*o*v] each)
+// where t2 is read as [(i,j,a)][b] and t2T[i][j][b][a] = t2[i][j][a][b]; the
+// sums over occupied t (length o) are done while assembling.
+// ---------------------------------------------------------------------------
+
+__global__ void k_pack_onebody(const double* __restrict__ g, int n, int o, double* A1,
+                               double* A2) {
   const int v = n - o;
-  Yg Y{f, Sigma{t1, t2, n, o, v}, n, o};
-  const size_t n2 = (size_t)n * n, n4 = n2 * n2;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n4;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const int s = (int)(idx % n), r = (int)(idx / n % n), q = (int)(idx / n2 % n),
-              p = (int)(idx / (n2 * n));
-    const double x = Y.two(p, q, r, s);
-    y2[idx] = x;
-    if (r >= o && s >= o) wy[((size_t)p * n + q) * v * v + (size_t)(r - o) * v + (s - o)] = x;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * v) return;
+  const int p = e / v, t = e % v;
+  A1[e] = g[p * n + o + t];
+  A2[e] = g[(o + t) * n + p];
+}
+
+__global__ void k_pack_t2T(const double* __restrict__ t2, int o, int v, double* t2T) {
+  const size_t tot = (size_t)o * o * v * v;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t ij = e / ((size_t)v * v);
+    const int b = (int)(e / v % v), a = (int)(e % v);
+    t2T[e] = t2[(ij * v + a) * v + b];
+  }
+}
+
+// One workgroup per (p,q): the row U[p][q][:][:] (contiguous), and its
+// virtual-virtual part in ladder layout when wv is given.
+__global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restrict__ g,
+                                                         const double* __restrict__ t2,
+                                                         const double* __restrict__ P, int n,
+                                                         int o, double* U, double* wv) {
+  __shared__ double tpq[64 * 64];
+  const int v = n - o;
+  const int p = blockIdx.x / n, q = blockIdx.x % n;
+  const bool op = p < o, oq = q < o;
+  const size_t ov2 = (size_t)o * o * v, nv = (size_t)n * ov2;
+  const double* P1 = P;
+  const double* P2 = P + nv;
+  const double* P3 = P + 2 * nv;
+  const double* P4 = P + 3 * nv;
+  if (!op && !oq) {
+    // sigma_pq.. needs t2[t][u][p][q] for occupied t, u
+    for (int e = threadIdx.x; e < o * o; e += blockDim.x)
+      tpq[e] = t2[((size_t)e * v + (p - o)) * v + (q - o)];
+    __syncthreads();
+  }
+  const size_t row = ((size_t)p * n + q) * n * n;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int r = e / n, s_ = e % n;
+    const bool or_ = r < o, os = s_ < o;
+    double x = 0.0;
+    if (or_ == os) {
+      if (or_) {   // r, s occupied
+        const size_t rs = ((size_t)r * o + s_) * v;
+        if (!oq) x += P1[(size_t)p * ov2 + rs + (q - o)];
+        if (!op) x += P2[(size_t)q * ov2 + rs + (p - o)];
+      } else {     // r, s virtual
+        const size_t rs = (size_t)(r - o) * v + (s_ - o);
+        if (oq)
+          for (int t = 0; t < o; ++t) x -= g[p * n + t] * t2[((size_t)t * o + q) * v * v + rs];
+        if (op)
+          for (int t = 0; t < o; ++t) x -= g[q * n + t] * t2[((size_t)p * o + t) * v * v + rs];
+      }
+    }
+    if (op == oq) {
+      if (op) {    // p, q occupied
+        const size_t pq = ((size_t)p * o + q) * v;
+        if (!os) x += P3[(size_t)r * ov2 + pq + (s_ - o)];
+        if (!or_) x += P4[(size_t)s_ * ov2 + pq + (r - o)];
+      } else {     // p, q virtual
+        if (os)
+          for (int t = 0; t < o; ++t) x -= g[t * n + r] * tpq[t * o + s_];
+        if (or_)
+          for (int t = 0; t < o; ++t) x -= g[t * n + s_] * tpq[r * o + t];
+      }
+    }
+    U[row + e] = x;
+    if (wv && !or_ && !os)
+      wv[((size_t)p * n + q) * v * v + (size_t)(r - o) * v + (s_ - o)] = x;
   }
 }
 
@@ -389,10 +464,23 @@ void launch_mp2(const double* f, const double* V, int n, int o, double* t1, doub
   k_mp2<<<grid_for(o * o * v * v + o * v, kBlock, 65536), kBlock, 0, st>>>(f, V, n, o, t1, t2);
 }
 
-void launch_yg(const double* f, const double* t1, const double* t2, int n, int o, double* y1,
-               double* y2, double* wy, double* scal, hipStream_t st) {
-  const size_t n4 = (size_t)n * n * n * n;
-  k_yg2<<<grid_for(n4, kBlock, 65536), kBlock, 0, st>>>(f, t1, t2, n, o, y2, wy);
+void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12, double* t2T,
+                   bool pack_t2T, double* P, double* part, size_t part_cap, double* U,
+                   double* wv, hipStream_t st) {
+  const int v = n - o;
+  const size_t nv = (size_t)n * v, ov2 = (size_t)o * o * v;
+  k_pack_onebody<<<grid_for(nv), kBlock, 0, st>>>(g, n, o, A12, A12 + nv);
+  if (pack_t2T)
+    k_pack_t2T<<<grid_for((size_t)o * o * v * v, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, t2T);
+  const double* Bs[4] = {t2T, t2, t2T, t2};
+  for (int i = 0; i < 4; ++i)
+    launch_gemm_nt_f64(A12 + (i < 2 ? 0 : nv), Bs[i], P + i * n * ov2, n, (int)ov2, v, 1.0, part,
+                       part_cap, st);
+  k_sigma2_assemble<<<n * n, kBlock, 0, st>>>(g, t2, P, n, o, U, wv);
+}
+
+void launch_yg1(const double* f, const double* t1, const double* t2, int n, int o, double* y1,
+                double* scal, hipStream_t st) {
   k_yg1<<<grid_for(((size_t)n * n + 1) * 64), kBlock, 0, st>>>(f, t1, t2, n, o, y1, scal);
 }
 

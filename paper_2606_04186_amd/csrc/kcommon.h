@@ -32,6 +32,7 @@ struct GlobalOps {
   int n, o;
   const double *ga_h, *g22_h, *j1_h, *j2_h, *ga_y, *g22_y, *j1_y, *j2_y;
   const double *z_h, *z_y;
+  const double *u_h, *u_y;   // [x1, sigma_2]_2 of H_N (= two-body of Yg) and of Yg
 };
 
 }  // namespace qf

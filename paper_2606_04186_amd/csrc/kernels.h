@@ -22,8 +22,16 @@ void launch_mp2(const double* f, const double* V, int n, int o, double* t1, doub
                 hipStream_t st);
 
 // intermediates of one amplitude set
-void launch_yg(const double* f, const double* t1, const double* t2, int n, int o, double* y1,
-               double* y2, double* wy, double* scal, hipStream_t st);
+// U = [G, sigma_2]_2 (dense n^4) for a Hermitian one-body G, and its
+// virtual-virtual rows in ladder layout into wv when wv is not NULL
+// (k_prep.hip).  Scratch: A12 2*n*v, t2T o*o*v*v (packed here when
+// pack_t2T), P 4*n*o*o*v doubles.
+void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12, double* t2T,
+                   bool pack_t2T, double* P, double* part, size_t part_cap, double* U,
+                   double* wv, hipStream_t st);
+// y1 = one-body part of [F_N, sigma], scal[2] = its scalar part
+void launch_yg1(const double* f, const double* t1, const double* t2, int n, int o, double* y1,
+                double* scal, hipStream_t st);
 void launch_fill(double* x, size_t count, double value, hipStream_t st);
 // ring intermediates (layouts in qflow_eval.h, DenseOp)
 void launch_pack_ring_A(const double* X, int n, int o, double* Aa, double* A22, hipStream_t st);
@@ -43,9 +51,10 @@ void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int 
                         double scale, double* part, size_t part_cap, hipStream_t st);
 
 // residual of Hbar(sigma)
-struct RingOps {            // Ga, G22, J1, J2, Z of H_N and of Yg
+struct RingOps {            // Ga, G22, J1, J2, Z, U of H_N and of Yg
   const double *ga_h, *g22_h, *j1_h, *j2_h, *ga_y, *g22_y, *j1_y, *j2_y;
   const double *z_h, *z_y;
+  const double *u_h, *u_y;   // [x1, sigma_2]_2 of H_N (= two-body of Yg) and of Yg
 };
 void launch_residual(const double* f, const double* V, const double* y1, const double* y2,
                      const double* L, const double* LY, const RingOps& rings, const double* t1,

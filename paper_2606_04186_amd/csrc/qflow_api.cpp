@@ -52,6 +52,9 @@ struct qflow_ctx {
   // Z = sigma1 X (first index) of H_N and Yg, n^4 each
   DevBuf z_h, z_y;
   DevBuf dtpart;   // per-block maxima of |t_new - t_old|
+  // [G, sigma_2]_2 scratch (packed one-body, transposed t2, GEMM outputs)
+  // and U_Y = [y1, sigma_2]_2
+  DevBuf a12, t2T, sp, u_y;
   DevBuf heff, heff_off, amp, amp_off, work, work_off, energy, c0, iters, status, spaces,
       strings, out2, partial, tasks, mtab;
   int task_slots[3] = {0, 0, 0};
@@ -206,7 +209,8 @@ qf::RingOps rings_of(qflow_ctx* ctx) {
   return qf::RingOps{P<double>(ctx->ga_h), P<double>(ctx->g22_h), P<double>(ctx->jh),
                      P<double>(ctx->jh) + nv,  P<double>(ctx->ga_y), P<double>(ctx->g22_y),
                      P<double>(ctx->jy),       P<double>(ctx->jy) + nv,
-                     P<double>(ctx->z_h),      P<double>(ctx->z_y)};
+                     P<double>(ctx->z_h),      P<double>(ctx->z_y),
+                     P<double>(ctx->y2),       P<double>(ctx->u_y)};
 }
 
 // Yg = [F,sigma], the ladder intermediates L = W t2^T, LY = WY t2^T and the
@@ -216,10 +220,18 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
     return fail(ctx, QFLOW_E_UNSUPPORTED, "only QFLOW_FP64 contractions are available");
   const int n = ctx->n, o = ctx->o, v = ctx->v;
   const size_t n2 = (size_t)n * n, ov = (size_t)o * v;
-  qf::launch_yg(P<double>(ctx->f), t1, t2, n, o, P<double>(ctx->y1), P<double>(ctx->y2),
-                P<double>(ctx->wy), P<double>(ctx->scal), ctx->stream);
   double* part = P<double>(ctx->gpart);
   const size_t pcap = ctx->gpart.bytes / sizeof(double);
+  // Yg = [F_N, sigma]: one-body and scalar, two-body (+ its ladder slab), and
+  // U_Y = [y1, sigma_2]_2 (the one-body part of Yg against sigma's two-body)
+  qf::launch_yg1(P<double>(ctx->f), t1, t2, n, o, P<double>(ctx->y1), P<double>(ctx->scal),
+                 ctx->stream);
+  qf::launch_sigma2(P<double>(ctx->f), t2, n, o, P<double>(ctx->a12), P<double>(ctx->t2T), true,
+                    P<double>(ctx->sp), part, pcap, P<double>(ctx->y2), P<double>(ctx->wy),
+                    ctx->stream);
+  qf::launch_sigma2(P<double>(ctx->y1), t2, n, o, P<double>(ctx->a12), P<double>(ctx->t2T),
+                    false, P<double>(ctx->sp), part, pcap, P<double>(ctx->u_y), nullptr,
+                    ctx->stream);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
   qf::launch_gemm_nt_f64(P<double>(ctx->W), t2, P<double>(ctx->L), n * n, o * o, v * v, 1.0, part,
                          pcap, ctx->stream);
@@ -322,6 +334,7 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
                     &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
                     &ctx->gpart,  &ctx->z_h,      &ctx->z_y,      &ctx->dtpart,
+                    &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->u_y,
                     &ctx->f,      &ctx->V,        &ctx->W,      &ctx->y1,       &ctx->y2,
                     &ctx->wy,     &ctx->L,        &ctx->LY,     &ctx->scal,     &ctx->r1,
                     &ctx->r2,     &ctx->t1n,      &ctx->t2n,    &ctx->heff,     &ctx->heff_off,
@@ -343,8 +356,8 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
                          const double* eri, double sym_tol) {
   if (!ctx) return QFLOW_E_INVALID_ARG;
   if (!h || !eri) return fail(ctx, QFLOW_E_INVALID_ARG, "h or eri is NULL");
-  if (n_orb < 2 || n_orb > 128 || n_occ < 1 || n_occ >= n_orb)
-    return fail(ctx, QFLOW_E_INVALID_ARG, "need 1 <= n_occ < n_orb <= 128");
+  if (n_orb < 2 || n_orb > 128 || n_occ < 1 || n_occ >= n_orb || n_occ > 64)
+    return fail(ctx, QFLOW_E_INVALID_ARG, "need 1 <= n_occ < n_orb <= 128 and n_occ <= 64");
   if (!(sym_tol >= 0.0)) return fail(ctx, QFLOW_E_INVALID_ARG, "sym_tol must be >= 0");
   QF_HIP(hipSetDevice(ctx->device));
   ctx->loaded = false;
@@ -400,6 +413,10 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->z_h, sizeof(double) * n4));
   QF_TRY(ensure(ctx, ctx->z_y, sizeof(double) * n4));
   QF_TRY(ensure(ctx, ctx->dtpart, sizeof(double) * qf::kFinishParts));
+  QF_TRY(ensure(ctx, ctx->a12, sizeof(double) * 2 * n * v));
+  QF_TRY(ensure(ctx, ctx->t2T, sizeof(double) * o * o * v * v));
+  QF_TRY(ensure(ctx, ctx->sp, sizeof(double) * 4 * n * o * o * v));
+  QF_TRY(ensure(ctx, ctx->u_y, sizeof(double) * n4));
   qf::launch_fock(h, eri, n, o, P<double>(ctx->f), ctx->stream);
   qf::launch_repack(eri, n, o, P<double>(ctx->V), P<double>(ctx->W), ctx->stream);
   qf::launch_pack_ring_A(P<double>(ctx->V), n, o, P<double>(ctx->ra_h), P<double>(ctx->r22_h),

@@ -137,6 +137,7 @@ struct DenseOp {
   const double* J1 = nullptr;    // [n][v]
   const double* J2 = nullptr;    // [n][v]
   const double* Z = nullptr;     // [n][n][n][n], sum_t sigma1(p,t) x2(t,q,r,s)
+  const double* U = nullptr;     // [n][n][n][n], [x1, sigma_2]_2
   QF_HD double one(int p, int q) const { return x1[p * n + q]; }
   QF_HD double two(int p, int q, int r, int s) const {
     return x2[(((size_t)p * n + q) * n + r) * n + s];
@@ -154,6 +155,9 @@ struct DenseOp {
   QF_HD double j2(int q, int p) const { return J2[q * (n - o) + (p - o)]; }
   QF_HD double z(int p, int q, int r, int s) const {
     return Z[(((size_t)p * n + q) * n + r) * n + s];
+  }
+  QF_HD double u(int p, int q, int r, int s) const {
+    return U[(((size_t)p * n + q) * n + r) * n + s];
   }
   QF_HD bool act(int) const { return true; }
 };
@@ -292,14 +296,18 @@ struct Comm {
     const bool op = occ(p), oq = occ(q), or_ = occ(r), os = occ(s);
     // one-body A x two-body B:
     //   sum_t [A_pt B_tqrs + A_qt B_ptrs - A_tr B_pqts - A_ts B_pqrt]
-    if (or_ == os && oq != or_)
-      over_block(oq, [&](int t) { res += a.one(p, t) * b.two(t, q, r, s); });
-    if (or_ == os && op != or_)
-      over_block(op, [&](int t) { res += a.one(q, t) * b.two(p, t, r, s); });
-    if (op == oq && os != op)
-      over_block(os, [&](int t) { res -= a.one(t, r) * b.two(p, q, t, s); });
-    if (op == oq && or_ != op)
-      over_block(or_, [&](int t) { res -= a.one(t, s) * b.two(p, q, r, t); });
+    if constexpr (kUseL) {
+      if (lead()) res += a.u(p, q, r, s);   // precomputed [A_1, B_2]_2
+    } else {
+      if (or_ == os && oq != or_)
+        over_block(oq, [&](int t) { res += a.one(p, t) * b.two(t, q, r, s); });
+      if (or_ == os && op != or_)
+        over_block(op, [&](int t) { res += a.one(q, t) * b.two(p, t, r, s); });
+      if (op == oq && os != op)
+        over_block(os, [&](int t) { res -= a.one(t, r) * b.two(p, q, t, s); });
+      if (op == oq && or_ != op)
+        over_block(or_, [&](int t) { res -= a.one(t, s) * b.two(p, q, r, t); });
+    }
     // one-body B x two-body A:
     //   - sum_t [B_pt A_tqrs + B_qt A_ptrs - B_tr A_pqts - B_ts A_pqrt]
     // = -(Z_pqrs + Z_qpsr + Z_rspq + Z_srqp) with Z = B A over the first index

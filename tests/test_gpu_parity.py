@@ -243,6 +243,10 @@ def test_symmetry_and_argument_errors():
     with pytest.raises(qf.QFlowError) as e:
         ctx.load_integrals(dev(h), dev(bad), o)
     assert e.value.code == -2
+    # more than 64 occupied orbitals is rejected before the integrals are read
+    with pytest.raises(qf.QFlowError) as e:
+        ctx.load_integrals(dev(np.eye(66)), dev(np.zeros(1)), 65)
+    assert e.value.code == -1
     with pytest.raises(qf.QFlowError) as e:
         ctx.residual(dev(np.zeros((o, 5))), dev(np.zeros((o, o, 5, 5))),
                      dev(np.zeros((o, 5))), dev(np.zeros((o, o, 5, 5))), dev(np.zeros(1)))
