@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __
     if (kind == 2)
       x = H.two(p, q, r, t) + cs.c2(p, q, r, t) - ct.c2(p, q, r, t);
     else if (kind == 1)
-      x = H.one(p, q) + cs.c1(p, q) - ct.c1(p, q);
+      x = H.one(p, q) + g.c1_h[p * n + q] - ct.c1(p, q);
     else
       x = scal[3] + scal[0] - ct.c0();
     emit(x, 1.0, true);
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __
     if (kind == 2)
       x = cs.c2(p, q, r, t) - ct.c2(p, q, r, t);
     else if (kind == 1)
-      x = cs.c1(p, q) - ct.c1(p, q);
+      x = g.c1_y[p * n + q] - ct.c1(p, q);
     else
       x = scal[1] - ct.c0();
     emit(x, 0.5, false);
@@ -238,7 +238,7 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
                  double* tab, double* heff, hipStream_t st) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
-              rings.z_h,  rings.z_y, rings.u_h, rings.u_y};
+              rings.z_h,  rings.z_y, rings.u_h, rings.u_y, rings.c1_h, rings.c1_y};
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
   dim3 grid(K, (slots_max + kBlock - 1) / kBlock);
   int s1, s2, s3, s4;

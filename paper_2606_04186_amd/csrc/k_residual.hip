@@ -33,21 +33,33 @@ __global__ void k_residual2(GlobalOps g, double* r2) {
   }
 }
 
-// one wavefront per output (lanes split the contraction loops)
-__global__ __launch_bounds__(256) void k_residual1(GlobalOps g, double* r1) {
+// one-body parts of [H_N, sigma] and [Yg, sigma] for all (p,q): one wavefront
+// per element, lanes split the contraction loops
+__global__ __launch_bounds__(256) void k_comm1(GlobalOps g, double* c1h, double* c1y) {
   const int n = g.n, o = g.o, v = n - o;
   const int lane = threadIdx.x % 64;
-  const Sigma s{g.t1, g.t2, n, o, v};
-  const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.z_h, g.u_h};
-  const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, g.u_y};
-  const auto cH = make_comm_split(H, s, n, o, lane, 64);
-  const auto cY = make_comm_split(Y, s, n, o, lane, 64);
   const int idx = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-  if (idx >= o * v) return;
-  const int i = idx / v, a = idx % v;
-  double x = cH.c1(o + a, i) + 0.5 * cY.c1(o + a, i);
+  if (idx >= 2 * n * n) return;
+  const int which = idx / (n * n), e = idx % (n * n);
+  const Sigma s{g.t1, g.t2, n, o, v};
+  double x;
+  if (which == 0) {
+    const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.z_h, g.u_h};
+    x = make_comm_split(H, s, n, o, lane, 64).c1(e / n, e % n);
+  } else {
+    const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, g.u_y};
+    x = make_comm_split(Y, s, n, o, lane, 64).c1(e / n, e % n);
+  }
   x = wave_sum(x);
-  if (lane == 0) r1[idx] = H.one(o + a, i) + x;
+  if (lane == 0) (which == 0 ? c1h : c1y)[e] = x;
+}
+
+__global__ void k_residual1(GlobalOps g, double* r1) {
+  const int n = g.n, o = g.o, v = n - o;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= o * v) return;
+  const int i = idx / v, a = o + idx % v;
+  r1[idx] = g.f[a * n + i] + g.c1_h[a * n + i] + 0.5 * g.c1_y[a * n + i];
 }
 
 // scal[0] = [H_N,sigma]_0, scal[1] = [Yg,sigma]_0 (scal[3] = E_ref, set at
@@ -71,14 +83,15 @@ __global__ __launch_bounds__(64) void k_residual0(GlobalOps g, double* scal, dou
 
 void launch_residual(const double* f, const double* V, const double* y1, const double* y2,
                      const double* L, const double* LY, const RingOps& rings, const double* t1,
-                     const double* t2, int n, int o, double* scal, double* r1, double* r2,
-                     double* e0, hipStream_t st) {
+                     const double* t2, int n, int o, double* scal, double* c1h, double* c1y,
+                     double* r1, double* r2, double* e0, hipStream_t st) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
-              rings.z_h,  rings.z_y, rings.u_h, rings.u_y};
+              rings.z_h,  rings.z_y, rings.u_h, rings.u_y, rings.c1_h, rings.c1_y};
   const size_t v = n - o;
+  k_comm1<<<grid_for((size_t)2 * n * n * 64), kBlock, 0, st>>>(g, c1h, c1y);
   k_residual2<<<grid_for(o * o * v * v, kBlock, 65536), kBlock, 0, st>>>(g, r2);
-  k_residual1<<<grid_for(o * v * 64), kBlock, 0, st>>>(g, r1);
+  k_residual1<<<grid_for(o * v), kBlock, 0, st>>>(g, r1);
   k_residual0<<<1, 64, 0, st>>>(g, scal, e0);
 }
 

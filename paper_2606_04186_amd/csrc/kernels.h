@@ -51,15 +51,19 @@ void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int 
                         double scale, double* part, size_t part_cap, hipStream_t st);
 
 // residual of Hbar(sigma)
-struct RingOps {            // Ga, G22, J1, J2, Z, U of H_N and of Yg
+struct RingOps {            // global intermediates of H_N and of Yg
   const double *ga_h, *g22_h, *j1_h, *j2_h, *ga_y, *g22_y, *j1_y, *j2_y;
   const double *z_h, *z_y;
   const double *u_h, *u_y;   // [x1, sigma_2]_2 of H_N (= two-body of Yg) and of Yg
+  const double *c1_h, *c1_y; // [n][n] one-body parts of [H_N, sigma] and [Yg, sigma]
 };
+// One-body parts of [H_N, sigma] and [Yg, sigma] for every (p,q) into
+// c1h, c1y ([n][n] each; the buffers RingOps.c1_h / c1_y point to), then the
+// residual r1, r2 and the zero-body parts (scal[0], scal[1], e0).
 void launch_residual(const double* f, const double* V, const double* y1, const double* y2,
                      const double* L, const double* LY, const RingOps& rings, const double* t1,
-                     const double* t2, int n, int o, double* scal, double* r1, double* r2,
-                     double* e0, hipStream_t st);
+                     const double* t2, int n, int o, double* scal, double* c1h, double* c1y,
+                     double* r1, double* r2, double* e0, hipStream_t st);
 
 // per-space downfolded Hamiltonians in CAS form
 void launch_heff(const double* f, const double* V, const double* y1, const double* y2,

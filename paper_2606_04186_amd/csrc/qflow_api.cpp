@@ -55,6 +55,7 @@ struct qflow_ctx {
   // [G, sigma_2]_2 scratch (packed one-body, transposed t2, GEMM outputs)
   // and U_Y = [y1, sigma_2]_2
   DevBuf a12, t2T, sp, u_y;
+  DevBuf c1h, c1y;   // one-body parts of [H_N, sigma] and [Yg, sigma], [n][n]
   DevBuf heff, heff_off, amp, amp_off, work, work_off, energy, c0, iters, status, spaces,
       strings, out2, partial, tasks, mtab;
   int task_slots[3] = {0, 0, 0};
@@ -210,7 +211,8 @@ qf::RingOps rings_of(qflow_ctx* ctx) {
                      P<double>(ctx->jh) + nv,  P<double>(ctx->ga_y), P<double>(ctx->g22_y),
                      P<double>(ctx->jy),       P<double>(ctx->jy) + nv,
                      P<double>(ctx->z_h),      P<double>(ctx->z_y),
-                     P<double>(ctx->y2),       P<double>(ctx->u_y)};
+                     P<double>(ctx->y2),       P<double>(ctx->u_y),
+                     P<double>(ctx->c1h),      P<double>(ctx->c1y)};
 }
 
 // Yg = [F,sigma], the ladder intermediates L = W t2^T, LY = WY t2^T and the
@@ -334,7 +336,8 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
                     &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
                     &ctx->gpart,  &ctx->z_h,      &ctx->z_y,      &ctx->dtpart,
-                    &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->u_y,
+                    &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->u_y,      &ctx->c1h,
+                    &ctx->c1y,
                     &ctx->f,      &ctx->V,        &ctx->W,      &ctx->y1,       &ctx->y2,
                     &ctx->wy,     &ctx->L,        &ctx->LY,     &ctx->scal,     &ctx->r1,
                     &ctx->r2,     &ctx->t1n,      &ctx->t2n,    &ctx->heff,     &ctx->heff_off,
@@ -417,6 +420,8 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->t2T, sizeof(double) * o * o * v * v));
   QF_TRY(ensure(ctx, ctx->sp, sizeof(double) * 4 * n * o * o * v));
   QF_TRY(ensure(ctx, ctx->u_y, sizeof(double) * n4));
+  QF_TRY(ensure(ctx, ctx->c1h, sizeof(double) * n2));
+  QF_TRY(ensure(ctx, ctx->c1y, sizeof(double) * n2));
   qf::launch_fock(h, eri, n, o, P<double>(ctx->f), ctx->stream);
   qf::launch_repack(eri, n, o, P<double>(ctx->V), P<double>(ctx->W), ctx->stream);
   qf::launch_pack_ring_A(P<double>(ctx->V), n, o, P<double>(ctx->ra_h), P<double>(ctx->r22_h),
@@ -466,7 +471,8 @@ int qflow_residual(qflow_ctx* ctx, const double* t1, const double* t2, double* r
   QF_TRY(prepare(ctx, t1, t2, precision));
   qf::launch_residual(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
                       P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx),
-                      t1, t2, ctx->n, ctx->o, P<double>(ctx->scal), r1, r2, e0, ctx->stream);
+                      t1, t2, ctx->n, ctx->o, P<double>(ctx->scal), P<double>(ctx->c1h),
+                      P<double>(ctx->c1y), r1, r2, e0, ctx->stream);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -500,7 +506,8 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
   // zero-body parts of [H_N, sigma] and [Yg, sigma] (scal[0], scal[1])
   qf::launch_residual(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
                       P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx),
-                      t1, t2, ctx->n, ctx->o, P<double>(ctx->scal), P<double>(ctx->r1),
+                      t1, t2, ctx->n, ctx->o, P<double>(ctx->scal), P<double>(ctx->c1h),
+                      P<double>(ctx->c1y), P<double>(ctx->r1),
                       P<double>(ctx->r2), nullptr, ctx->stream);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[8], ctx->stream));
   if (K > 0)
