@@ -16,17 +16,23 @@ namespace {
 // batched Davidson: one wavefront per space
 // ---------------------------------------------------------------------------
 
-// Lowest eigenpair of the symmetric m x m matrix A (row-major, destroyed) by
-// cyclic Jacobi rotations; V (m x m) receives eigenvectors.
+// Lowest eigenpair of the symmetric m x m matrix A (LDS, row-major,
+// destroyed) by cyclic Jacobi rotations, one wavefront: lane k applies each
+// rotation to row/column k.  V (LDS, m x m) receives the eigenvectors; every
+// lane gets theta, and y[0..m) (LDS) the eigenvector.
 __device__ void jacobi_lowest(double* A, double* V, int m, double* theta, double* y) {
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) V[i * m + j] = (i == j) ? 1.0 : 0.0;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < m * m; e += 64) V[e] = (e / m == e % m) ? 1.0 : 0.0;
+  __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int i = 0; i < m; ++i) {
-      dia += A[i * m + i] * A[i * m + i];
-      for (int j = i + 1; j < m; ++j) off += A[i * m + j] * A[i * m + j];
+    for (int e = lane; e < m * m; e += 64) {
+      const int i = e / m, j = e % m;
+      if (i == j) dia += A[e] * A[e];
+      else if (j > i) off += A[e] * A[e];
     }
+    off = wave_sum(off);
+    dia = wave_sum(dia);
     if (off <= 1e-32 * (dia + 1e-300)) break;
     for (int p = 0; p < m; ++p)
       for (int q = p + 1; q < m; ++q) {
@@ -35,62 +41,138 @@ __device__ void jacobi_lowest(double* A, double* V, int m, double* theta, double
         const double th = (A[q * m + q] - A[p * m + p]) / (2.0 * apq);
         const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
         const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < m; ++k) {
-          const double akp = A[k * m + p], akq = A[k * m + q];
-          A[k * m + p] = c * akp - s * akq;
-          A[k * m + q] = s * akp + c * akq;
+        __syncthreads();
+        if (lane < m) {
+          const double akp = A[lane * m + p], akq = A[lane * m + q];
+          A[lane * m + p] = c * akp - s * akq;
+          A[lane * m + q] = s * akp + c * akq;
         }
-        for (int k = 0; k < m; ++k) {
-          const double apk = A[p * m + k], aqk = A[q * m + k];
-          A[p * m + k] = c * apk - s * aqk;
-          A[q * m + k] = s * apk + c * aqk;
+        __syncthreads();
+        if (lane < m) {
+          const double apk = A[p * m + lane], aqk = A[q * m + lane];
+          A[p * m + lane] = c * apk - s * aqk;
+          A[q * m + lane] = s * apk + c * aqk;
+          const double vkp = V[lane * m + p], vkq = V[lane * m + q];
+          V[lane * m + p] = c * vkp - s * vkq;
+          V[lane * m + q] = s * vkp + c * vkq;
         }
-        for (int k = 0; k < m; ++k) {
-          const double vkp = V[k * m + p], vkq = V[k * m + q];
-          V[k * m + p] = c * vkp - s * vkq;
-          V[k * m + q] = s * vkp + c * vkq;
-        }
+        __syncthreads();
       }
   }
   int best = 0;
   for (int i = 1; i < m; ++i)
     if (A[i * m + i] < A[best * m + best]) best = i;
   *theta = A[best * m + best];
-  for (int i = 0; i < m; ++i) y[i] = V[i * m + best];
+  for (int i = lane; i < m; i += 64) y[i] = V[i * m + best];
+  __syncthreads();
 }
 
-__global__ __launch_bounds__(64) void k_davidson(DavidsonArgs a) {
-  extern __shared__ double sm[];
-  const int k = blockIdx.x;
+constexpr int binom(int n, int k) { return k == 0 ? 1 : binom(n - 1, k - 1) * n / k; }
+
+// Replacement lists of one size class packed for LDS: src | pq << 8 | (sgn > 0) << 16.
+__device__ inline int rep_src(int r) { return r & 255; }
+__device__ inline int rep_pq(int r) { return (r >> 8) & 255; }
+__device__ inline double rep_sgn(int r) { return (r >> 16) ? 1.0 : -1.0; }
+
+// One space of NA orbitals and NE electrons per spin, one wavefront.
+//
+// sigma = H c is evaluated with lane l < G*NS owning beta string Ib = l % NS
+// and the alpha strings Ia = l / NS, l / NS + G, ... (G = 64 / NS); the
+// lane keeps the replacement list of its Ib in registers.
+template <int NA, int NE>
+__device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp, double* sm) {
+  constexpr int NS = binom(NA, NE), NR = NE * (1 + NA - NE), D = NS * NS;
+  constexpr int N2 = NA * NA, N4 = N2 * N2;
+  constexpr int G = 64 / NS, NT = (NS + G - 1) / G;
   const int lane = threadIdx.x;
-  const SpaceDev sp = a.spaces[k];
   const Strings& S = a.strings[sp.nocc - 2];
-  const int na = S.na, ns = S.nstr, D = ns * ns, MS = a.maxsub;
+  const int MS = a.maxsub;
   const double* hin = a.heff + a.heff_off[k];
   const double Ec = hin[0];
   const double* h = hin + 1;
-  double* g = sm;                       // na^4
-  double* Hs = g + na * na * na * na;   // ns^2
-  double* dg = Hs + ns * ns;            // D
+  double* g = sm;                       // N4
+  double* Hs = g + N4;                  // NS^2
+  double* dg = Hs + NS * NS;            // D
   double* xv = dg + D;                  // D  Ritz vector / sigma staging
   double* hx = xv + D;                  // D
   double* rv = hx + D;                  // D
-  double* G = rv + D;                   // MS^2
-  double* Aw = G + MS * MS;             // MS^2
+  double* Gm = rv + D;                  // MS^2
+  double* Aw = Gm + MS * MS;            // MS^2
   double* Vw = Aw + MS * MS;            // MS^2
   double* yv = Vw + MS * MS;            // MS
   double* misc = yv + MS;               // 4
+  int* rep = reinterpret_cast<int*>(misc + 4);   // NS*NR
   double* bb = a.work + a.work_off[k];  // MS x D
   double* ss = bb + (size_t)MS * D;     // MS x D
-  for (int e = lane; e < na * na * na * na; e += 64) g[e] = hin[1 + na * na + e];
-  __syncthreads();
-  for (int e = lane; e < ns * ns; e += 64) Hs[e] = same_spin_element(S, h, g, e / ns, e % ns);
-  __syncthreads();
-  for (int e = lane; e < D; e += 64) {
-    dg[e] = cas_diag(S, Hs, g, Ec, e / ns, e % ns);
-    bb[e] = (e == 0) ? 1.0 : 0.0;
+  for (int e = lane; e < N4; e += 64) g[e] = hin[1 + N2 + e];
+  for (int e = lane; e < NS * NR; e += 64) {
+    const int I = e / NR, f = e % NR;
+    rep[e] = S.src[I][f] | (S.pq[I][f] << 8) | ((S.sgn[I][f] > 0) << 16);
   }
   __syncthreads();
+  // same-spin string Hamiltonian Hs[I][J] = <I| sum k_pq E_pq + 1/2 sum g E_pq E_rs |J>,
+  // k_pq = h_pq - 1/2 sum_r g(pr|rq)
+  for (int e = lane; e < NS * NS; e += 64) {
+    const int I = e / NS, J = e % NS;
+    double x = 0.0;
+    for (int f = 0; f < NR; ++f) {
+      const int r = rep[I * NR + f];
+      if (rep_src(r) == J) {
+        const int p = rep_pq(r) / NA, q = rep_pq(r) % NA;
+        double kk = h[p * NA + q];
+        for (int t = 0; t < NA; ++t) kk -= 0.5 * g[((p * NA + t) * NA + t) * NA + q];
+        x += rep_sgn(r) * kk;
+      }
+      const int Kst = rep_src(r);
+      for (int f2 = 0; f2 < NR; ++f2) {
+        const int r2 = rep[Kst * NR + f2];
+        if (rep_src(r2) == J) x += 0.5 * rep_sgn(r) * rep_sgn(r2) * g[rep_pq(r) * N2 + rep_pq(r2)];
+      }
+    }
+    Hs[e] = x;
+  }
+  __syncthreads();
+  for (int e = lane; e < D; e += 64) {
+    dg[e] = cas_diag(S, Hs, g, Ec, e / NS, e % NS);
+    bb[e] = (e == 0) ? 1.0 : 0.0;
+  }
+  // this lane's beta replacement list
+  const bool active = lane < G * NS;
+  const int ib = lane % NS, grp = lane / NS;
+  int jb[NR], rs[NR];
+  double sb[NR];
+#pragma unroll
+  for (int f = 0; f < NR; ++f) {
+    const int r = active ? rep[ib * NR + f] : 0;
+    jb[f] = rep_src(r);
+    rs[f] = rep_pq(r);
+    sb[f] = rep_sgn(r);
+  }
+  __syncthreads();
+  // sigma of c (LDS) into out (global), one value per (Ia, Ib)
+  auto sigma = [&](const double* c, double* out) {
+    if (!active) return;
+#pragma unroll 1
+    for (int t = 0; t < NT; ++t) {
+      const int ia = grp + t * G;
+      if (ia >= NS) break;
+      double x = Ec * c[ia * NS + ib];
+#pragma unroll
+      for (int J = 0; J < NS; ++J)
+        x += Hs[ia * NS + J] * c[J * NS + ib] + Hs[ib * NS + J] * c[ia * NS + J];
+#pragma unroll
+      for (int e = 0; e < NR; ++e) {
+        const int r = rep[ia * NR + e];
+        const double* gr = g + rep_pq(r) * N2;
+        const double* cr = c + rep_src(r) * NS;
+        double acc = 0.0;
+#pragma unroll
+        for (int f = 0; f < NR; ++f) acc += sb[f] * gr[rs[f]] * cr[jb[f]];
+        x += rep_sgn(r) * acc;
+      }
+      out[ia * NS + ib] = x;
+    }
+  };
   int m = 1, it = 0;
   bool conv = false;
   double theta = 0.0;
@@ -100,25 +182,21 @@ __global__ __launch_bounds__(64) void k_davidson(DavidsonArgs a) {
     for (int e = lane; e < D; e += 64) xv[e] = bn[e];
     __syncthreads();
     double* sn = ss + (size_t)(m - 1) * D;
-    for (int e = lane; e < D; e += 64) sn[e] = cas_sigma(S, Hs, g, Ec, xv, e / ns, e % ns);
+    sigma(xv, sn);
     __syncthreads();
     for (int i = 0; i < m; ++i) {
       double d = 0.0;
       for (int e = lane; e < D; e += 64) d += bb[(size_t)i * D + e] * sn[e];
       d = wave_sum(d);
       if (lane == 0) {
-        G[i * MS + (m - 1)] = d;
-        G[(m - 1) * MS + i] = d;
+        Gm[i * MS + (m - 1)] = d;
+        Gm[(m - 1) * MS + i] = d;
       }
     }
     __syncthreads();
-    if (lane == 0) {
-      for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) Aw[i * m + j] = G[i * MS + j];
-      jacobi_lowest(Aw, Vw, m, &misc[0], yv);
-    }
+    for (int e = lane; e < m * m; e += 64) Aw[e] = Gm[(e / m) * MS + e % m];
     __syncthreads();
-    theta = misc[0];
+    jacobi_lowest(Aw, Vw, m, &theta, yv);
     double rn = 0.0;
     for (int e = lane; e < D; e += 64) {
       double x = 0.0, y = 0.0;
@@ -143,7 +221,7 @@ __global__ __launch_bounds__(64) void k_davidson(DavidsonArgs a) {
         bb[e] = xv[e];
         ss[e] = hx[e];
       }
-      if (lane == 0) G[0] = theta;
+      if (lane == 0) Gm[0] = theta;
       m = 1;
       __syncthreads();
     }
@@ -188,22 +266,32 @@ __global__ __launch_bounds__(64) void k_davidson(DavidsonArgs a) {
     a.status[k] = st;
   }
   // intermediate-normalised cluster amplitudes
-  const int nv = na - S.ne, ne = S.ne;
+  constexpr int nv = NA - NE, ne = NE;
   double* amp = a.amp + a.amp_off[k];
   const double inv = (c0 > 0.0) ? sgn / c0 : 0.0;
   for (int e = lane; e < ne * nv; e += 64) {
     const int i = e / nv, b = e % nv;
-    amp[e] = S.exc_sgn[i][b] * xv[S.exc_str[i][b] * ns] * inv;
+    amp[e] = S.exc_sgn[i][b] * xv[S.exc_str[i][b] * NS] * inv;
   }
-  const int nt1 = ne * nv;
+  constexpr int nt1 = ne * nv;
   for (int e = lane; e < nt1 * nt1; e += 64) {
     const int b = e % nv, av = e / nv % nv, j = e / (nv * nv) % ne, i = e / (nv * nv * ne);
-    const double ta = S.exc_sgn[i][av] * xv[S.exc_str[i][av] * ns] * inv;
-    const double tb = S.exc_sgn[j][b] * xv[S.exc_str[j][b] * ns] * inv;
+    const double ta = S.exc_sgn[i][av] * xv[S.exc_str[i][av] * NS] * inv;
+    const double tb = S.exc_sgn[j][b] * xv[S.exc_str[j][b] * NS] * inv;
     const double c2 = S.exc_sgn[i][av] * S.exc_sgn[j][b] *
-                      xv[S.exc_str[i][av] * ns + S.exc_str[j][b]] * inv;
+                      xv[S.exc_str[i][av] * NS + S.exc_str[j][b]] * inv;
     amp[nt1 + e] = c2 - ta * tb;
   }
+}
+
+__global__ __launch_bounds__(64) void k_davidson(DavidsonArgs a) {
+  extern __shared__ double sm[];
+  const int k = blockIdx.x;
+  const SpaceDev sp = a.spaces[k];
+  if (sp.nocc == 3)
+    davidson_space<6, 3>(a, k, sp, sm);
+  else
+    davidson_space<4, 2>(a, k, sp, sm);
 }
 
 }  // namespace
