@@ -162,8 +162,10 @@ __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restric
       } else {     // r, s virtual
         const size_t rs = (size_t)(r - o) * v + (s_ - o);
         if (oq)
+#pragma unroll 4
           for (int t = 0; t < o; ++t) x -= g[p * n + t] * t2[((size_t)t * o + q) * v * v + rs];
         if (op)
+#pragma unroll 4
           for (int t = 0; t < o; ++t) x -= g[q * n + t] * t2[((size_t)p * o + t) * v * v + rs];
       }
     }
@@ -362,25 +364,37 @@ __global__ void k_pack_ring_T(const double* __restrict__ t2, int o, int v, doubl
 // and pair symmetric and sigma1 anti-Hermitian, the four terms of
 // [X, sigma1]_2 are -(Z_pqrs + Z_qpsr + Z_rspq + Z_srqp).
 // sigma1(a,i) = t1[i][a], sigma1(i,a) = -t1[i][a].  One thread per column
-// c = (q,r,s); t1 is staged in LDS and read by broadcast.
+// c = (q,r,s); t1 is staged in LDS (o*v doubles) and read by broadcast.
 constexpr int kZChunk = 16;
 
 __global__ __launch_bounds__(256) void k_sigma1_x(const double* __restrict__ X,
                                                   const double* __restrict__ t1, int n, int o,
                                                   double* Z) {
-  __shared__ double ts[64 * 64];
+  extern __shared__ double ts[];   // t1, o*v
   const int v = n - o;
   for (int e = threadIdx.x; e < o * v; e += blockDim.x) ts[e] = t1[e];
   __syncthreads();
   const size_t n3 = (size_t)n * n * n;
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n3) return;
-  // p occupied: Z[p][c] = -sum_{t virtual} t1[p][t-o] X[t][c]
+  // p occupied: Z[p][c] = -sum_{t virtual} t1[p][t-o] X[t][c]; the column of
+  // X is read eight rows at a time to keep several loads in flight
   for (int p0 = 0; p0 < o; p0 += kZChunk) {
     double acc[kZChunk];
 #pragma unroll
     for (int i = 0; i < kZChunk; ++i) acc[i] = 0.0;
-    for (int t = o; t < n; ++t) {
+    int t = o;
+    for (; t + 8 <= n; t += 8) {
+      double x[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) x[j] = X[(size_t)(t + j) * n3 + c];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int i = 0; i < kZChunk; ++i)
+          if (p0 + i < o) acc[i] -= ts[(p0 + i) * v + (t + j - o)] * x[j];
+    }
+    for (; t < n; ++t) {
       const double x = X[(size_t)t * n3 + c];
 #pragma unroll
       for (int i = 0; i < kZChunk; ++i)
@@ -404,6 +418,27 @@ __global__ __launch_bounds__(256) void k_sigma1_x(const double* __restrict__ X,
       *z = (t0 == 0) ? acc : *z + acc;
     }
   }
+}
+
+// Operands of the occupied-occupied ladder Lo[(a,b)][(i,j)] =
+// sum_{t,u occupied} t2[t,u,a,b] X(t,u,i,j):  T[(a,b)][(t,u)] = t2[t,u,a,b]
+// (v*v rows) and Xo[(i,j)][(t,u)] = X[t,u,i,j] (o*o rows).
+__global__ void k_pack_t2_vvoo(const double* __restrict__ t2, int o, int v, double* T) {
+  const size_t oo = (size_t)o * o, tot = oo * v * v;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t ab = e / oo, tu = e % oo;
+    T[e] = t2[tu * v * v + ab];
+  }
+}
+
+__global__ void k_pack_x_oooo(const double* __restrict__ X, int n, int o, double* Xo) {
+  const int oo = o * o;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= oo * oo) return;
+  const int ij = e / oo, tu = e % oo;
+  const int i = ij / o, j = ij % o, t = tu / o, u = tu % o;
+  Xo[e] = X[(((size_t)t * n + u) * n + i) * n + j];
 }
 
 // Operands of the one-body ring terms as K-contiguous matrices over
@@ -496,7 +531,16 @@ void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22,
 
 void launch_sigma1_x(const double* X, const double* t1, int n, int o, double* Z, hipStream_t st) {
   const size_t n3 = (size_t)n * n * n;
-  k_sigma1_x<<<(unsigned)((n3 + kBlock - 1) / kBlock), kBlock, 0, st>>>(X, t1, n, o, Z);
+  k_sigma1_x<<<(unsigned)((n3 + kBlock - 1) / kBlock), kBlock,
+               (size_t)o * (n - o) * sizeof(double), st>>>(X, t1, n, o, Z);
+}
+
+void launch_pack_t2_vvoo(const double* t2, int o, int v, double* T, hipStream_t st) {
+  k_pack_t2_vvoo<<<grid_for((size_t)o * o * v * v, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, T);
+}
+
+void launch_pack_x_oooo(const double* X, int n, int o, double* Xo, hipStream_t st) {
+  k_pack_x_oooo<<<grid_for((size_t)o * o * o * o), kBlock, 0, st>>>(X, n, o, Xo);
 }
 
 void launch_pack_j_A(const double* X, int n, int o, double* A1, double* A2, hipStream_t st) {

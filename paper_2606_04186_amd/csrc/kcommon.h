@@ -34,6 +34,7 @@ struct GlobalOps {
   const double *z_h, *z_y;
   const double *u_h, *u_y;   // [x1, sigma_2]_2 of H_N (= two-body of Yg) and of Yg
   const double *c1_h, *c1_y; // [n][n] one-body parts of [H_N, sigma] and [Yg, sigma]
+  const double *lo_h, *lo_y; // [v*v][o*o] occupied-occupied ladders
 };
 
 }  // namespace qf

@@ -38,6 +38,9 @@ void launch_pack_ring_A(const double* X, int n, int o, double* Aa, double* A22, 
 void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22, hipStream_t st);
 // Z = sigma1 X over the first index (k_prep.hip, k_sigma1_x); n^4 doubles
 void launch_sigma1_x(const double* X, const double* t1, int n, int o, double* Z, hipStream_t st);
+// operands of the occupied-occupied ladder Lo (k_prep.hip)
+void launch_pack_t2_vvoo(const double* t2, int o, int v, double* T, hipStream_t st);
+void launch_pack_x_oooo(const double* X, int n, int o, double* Xo, hipStream_t st);
 // one-body ring operands (layouts in k_prep.hip, k_pack_j_A / k_pack_j_B)
 void launch_pack_j_A(const double* X, int n, int o, double* A1, double* A2, hipStream_t st);
 void launch_pack_j_B(const double* t2, int o, int v, double* B1, double* B2, hipStream_t st);
@@ -56,6 +59,7 @@ struct RingOps {            // global intermediates of H_N and of Yg
   const double *z_h, *z_y;
   const double *u_h, *u_y;   // [x1, sigma_2]_2 of H_N (= two-body of Yg) and of Yg
   const double *c1_h, *c1_y; // [n][n] one-body parts of [H_N, sigma] and [Yg, sigma]
+  const double *lo_h, *lo_y; // [v*v][o*o] occupied-occupied ladders
 };
 // One-body parts of [H_N, sigma] and [Yg, sigma] for every (p,q) into
 // c1h, c1y ([n][n] each; the buffers RingOps.c1_h / c1_y point to), then the

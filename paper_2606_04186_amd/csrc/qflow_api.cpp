@@ -56,6 +56,9 @@ struct qflow_ctx {
   // and U_Y = [y1, sigma_2]_2
   DevBuf a12, t2T, sp, u_y;
   DevBuf c1h, c1y;   // one-body parts of [H_N, sigma] and [Yg, sigma], [n][n]
+  // occupied-occupied ladders: packed t2 [v*v][o*o], X_oooo of H (constant)
+  // and Yg [o*o][o*o], outputs Lo of H and Yg [v*v][o*o]
+  DevBuf lo_t, lo_xh, lo_xy, lo_h, lo_y;
   DevBuf heff, heff_off, amp, amp_off, work, work_off, energy, c0, iters, status, spaces,
       strings, out2, partial, tasks, mtab;
   int task_slots[3] = {0, 0, 0};
@@ -213,7 +216,8 @@ qf::RingOps rings_of(qflow_ctx* ctx) {
                      P<double>(ctx->jy),       P<double>(ctx->jy) + nv,
                      P<double>(ctx->z_h),      P<double>(ctx->z_y),
                      P<double>(ctx->y2),       P<double>(ctx->u_y),
-                     P<double>(ctx->c1h),      P<double>(ctx->c1y)};
+                     P<double>(ctx->c1h),      P<double>(ctx->c1y),
+                     P<double>(ctx->lo_h),     P<double>(ctx->lo_y)};
 }
 
 // Yg = [F,sigma], the ladder intermediates L = W t2^T, LY = WY t2^T and the
@@ -271,6 +275,13 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
       qf::launch_gemm_nt_f64(P<double>(*op.a) + which * (size_t)n * kj, which == 0 ? b1 : b2,
                              P<double>(*op.j) + which * (size_t)n * v, n, v, (int)kj, -1.0, part,
                              pcap, st);
+  // occupied-occupied ladders Lo of H_N and Yg
+  qf::launch_pack_t2_vvoo(t2, o, v, P<double>(ctx->lo_t), st);
+  qf::launch_pack_x_oooo(P<double>(ctx->y2), n, o, P<double>(ctx->lo_xy), st);
+  qf::launch_gemm_nt_f64(P<double>(ctx->lo_t), P<double>(ctx->lo_xh), P<double>(ctx->lo_h), v * v,
+                         o * o, o * o, 1.0, part, pcap, st);
+  qf::launch_gemm_nt_f64(P<double>(ctx->lo_t), P<double>(ctx->lo_xy), P<double>(ctx->lo_y), v * v,
+                         o * o, o * o, 1.0, part, pcap, st);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[6], ctx->stream));
   // Z = sigma1 X of H_N and Yg
   qf::launch_sigma1_x(P<double>(ctx->V), t1, n, o, P<double>(ctx->z_h), st);
@@ -338,7 +349,8 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
                     &ctx->gpart,  &ctx->z_h,      &ctx->z_y,      &ctx->dtpart,
                     &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->u_y,      &ctx->c1h,
-                    &ctx->c1y,
+                    &ctx->c1y,    &ctx->lo_t,     &ctx->lo_xh,  &ctx->lo_xy,    &ctx->lo_h,
+                    &ctx->lo_y,
                     &ctx->f,      &ctx->V,        &ctx->W,      &ctx->y1,       &ctx->y2,
                     &ctx->wy,     &ctx->L,        &ctx->LY,     &ctx->scal,     &ctx->r1,
                     &ctx->r2,     &ctx->t1n,      &ctx->t2n,    &ctx->heff,     &ctx->heff_off,
@@ -423,12 +435,18 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->u_y, sizeof(double) * n4));
   QF_TRY(ensure(ctx, ctx->c1h, sizeof(double) * n2));
   QF_TRY(ensure(ctx, ctx->c1y, sizeof(double) * n2));
+  QF_TRY(ensure(ctx, ctx->lo_t, sizeof(double) * o * o * v * v));
+  QF_TRY(ensure(ctx, ctx->lo_xh, sizeof(double) * o * o * o * o));
+  QF_TRY(ensure(ctx, ctx->lo_xy, sizeof(double) * o * o * o * o));
+  QF_TRY(ensure(ctx, ctx->lo_h, sizeof(double) * o * o * v * v));
+  QF_TRY(ensure(ctx, ctx->lo_y, sizeof(double) * o * o * v * v));
   qf::launch_fock(h, eri, n, o, P<double>(ctx->f), ctx->stream);
   qf::launch_repack(eri, n, o, P<double>(ctx->V), P<double>(ctx->W), ctx->stream);
   qf::launch_pack_ring_A(P<double>(ctx->V), n, o, P<double>(ctx->ra_h), P<double>(ctx->r22_h),
                          ctx->stream);
   qf::launch_pack_j_A(P<double>(ctx->V), n, o, P<double>(ctx->ja_h),
                       P<double>(ctx->ja_h) + (size_t)n * o * o * v, ctx->stream);
+  qf::launch_pack_x_oooo(P<double>(ctx->V), n, o, P<double>(ctx->lo_xh), ctx->stream);
   QF_HIP(hipGetLastError());
   ctx->fock.assign(n2, 0.0);
   std::vector<double> hh(n2);

@@ -138,6 +138,7 @@ struct DenseOp {
   const double* J2 = nullptr;    // [n][v]
   const double* Z = nullptr;     // [n][n][n][n], sum_t sigma1(p,t) x2(t,q,r,s)
   const double* U = nullptr;     // [n][n][n][n], [x1, sigma_2]_2
+  const double* Lo = nullptr;    // [v*v][o*o], sum_{tu occ} t2[t,u,a,b] x2(t,u,i,j)
   QF_HD double one(int p, int q) const { return x1[p * n + q]; }
   QF_HD double two(int p, int q, int r, int s) const {
     return x2[(((size_t)p * n + q) * n + r) * n + s];
@@ -158,6 +159,10 @@ struct DenseOp {
   }
   QF_HD double u(int p, int q, int r, int s) const {
     return U[(((size_t)p * n + q) * n + r) * n + s];
+  }
+  QF_HD double lo(int a, int b, int i, int j) const {
+    const int v = n - o;
+    return Lo[((size_t)(a - o) * v + (b - o)) * o * o + i * o + j];
   }
   QF_HD bool act(int) const { return true; }
 };
@@ -322,10 +327,30 @@ struct Comm {
     }
     // ladders: sum_tu (1 - n_t - n_u)(A_pqtu B_turs - B_pqtu A_turs)
     if (or_ && os) res += ladder_vv(p, q, r, s);
-    if (!or_ && !os)
-      over_pair(true, true, [&](int t, int u) { res -= a.two(p, q, t, u) * b.two(t, u, r, s); });
-    if (!op && !oq)
-      over_pair(true, true, [&](int t, int u) { res += b.two(p, q, t, u) * a.two(t, u, r, s); });
+    // (the occupied-occupied / virtual-virtual cases are the precomputed Lo,
+    // using A_pqtu = A_tupq)
+    if (!or_ && !os) {
+      bool done = false;
+      if constexpr (kUseL) {
+        if (op && oq) {
+          if (lead()) res += a.lo(r, s, p, q);
+          done = true;
+        }
+      }
+      if (!done)
+        over_pair(true, true, [&](int t, int u) { res -= a.two(p, q, t, u) * b.two(t, u, r, s); });
+    }
+    if (!op && !oq) {
+      bool done = false;
+      if constexpr (kUseL) {
+        if (or_ && os) {
+          if (lead()) res += a.lo(p, q, r, s);
+          done = true;
+        }
+      }
+      if (!done)
+        over_pair(true, true, [&](int t, int u) { res += b.two(p, q, t, u) * a.two(t, u, r, s); });
+    }
     if (op && oq) res -= ladder_vv_rev(p, q, r, s);
     // particle-hole terms: Xa(p,q,r,s) - Xb - Xc + Xa(q,p,s,r)
     res += xa(p, q, r, s) - xb(p, q, r, s) - xc(p, q, r, s) + xa(q, p, s, r);
