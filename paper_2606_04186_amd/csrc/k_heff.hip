@@ -161,7 +161,8 @@ __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __
       x = scal[3] + scal[0] - ct.c0();
     emit(x, 1.0, true);
   } else if constexpr (PART == 1) {
-    const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, g.u_y, g.lo_y};
+    const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, nullptr, g.lo_y,
+                   Sigma2Lazy{g.y1, g.t2, g.s2p, g.s2q, n, o}};
     const auto cs = make_comm(Y, s, n, o);
     const auto ct = make_comm(Y, tau, n, o);
     double x;
@@ -238,7 +239,7 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
                  double* tab, double* heff, hipStream_t st) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
-              rings.z_h,  rings.z_y, rings.u_h, rings.u_y, rings.c1_h, rings.c1_y,
+              rings.z_h,  rings.z_y, rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
               rings.lo_h, rings.lo_y};
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
   dim3 grid(K, (slots_max + kBlock - 1) / kBlock);

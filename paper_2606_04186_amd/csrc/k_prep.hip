@@ -104,8 +104,11 @@ __global__ void k_mp2(const double* __restrict__ f, const double* __restrict__ V
 // (~ = same occupied/virtual class).  The sums over virtual t are four
 // matrix-core GEMMs over K = v with A1[p][t] = G[p][o+t], A2[p][t] = G[o+t][p]:
 //   P1 = A1 t2T^T, P2 = A1 t2^T, P3 = A2 t2T^T, P4 = A2 t2^T   ([n][o*o*v] each)
-// where t2 is read as [(i,j,a)][b] and t2T[i][j][b][a] = t2[i][j][a][b]; the
-// sums over occupied t (length o) are done while assembling.
+// where t2 is read as [(i,j,a)][b] and t2T[i][j][b][a] = t2[i][j][a][b].  The
+// sums over occupied t with r, s virtual are two GEMMs over K = o with
+// Ao[p][t] = G[p][t] (t occupied), scaled by -1:
+//   Q1 = -Ao Tq^T, Tq[(q,a,b)][t] = t2[t][q][a][b];  Q2 = -Ao Tp^T, Tp[(p,a,b)][t] = t2[p][t][a][b]
+// ([n][o*v*v] each); those with p, q virtual are done while assembling.
 // ---------------------------------------------------------------------------
 
 __global__ void k_pack_onebody(const double* __restrict__ g, int n, int o, double* A1,
@@ -116,6 +119,27 @@ __global__ void k_pack_onebody(const double* __restrict__ g, int n, int o, doubl
   const int p = e / v, t = e % v;
   A1[e] = g[p * n + o + t];
   A2[e] = g[(o + t) * n + p];
+}
+
+__global__ void k_pack_onebody_occ(const double* __restrict__ g, int n, int o, double* Ao) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * o) return;
+  Ao[e] = g[(e / o) * n + e % o];
+}
+
+// Tq[(q,a,b)][t] = t2[t][q][a][b], Tp[(p,a,b)][t] = t2[p][t][a][b]
+__global__ void k_pack_t2_occ(const double* __restrict__ t2, int o, int v, double* Tq,
+                              double* Tp) {
+  const size_t vv = (size_t)v * v, tot = (size_t)o * o * vv;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int t = (int)(e % o);
+    const size_t row = e / o;
+    const int i = (int)(row / vv);
+    const size_t ab = row % vv;
+    Tq[e] = t2[((size_t)t * o + i) * vv + ab];
+    Tp[e] = t2[((size_t)i * o + t) * vv + ab];
+  }
 }
 
 __global__ void k_pack_t2T(const double* __restrict__ t2, int o, int v, double* t2T) {
@@ -132,7 +156,8 @@ __global__ void k_pack_t2T(const double* __restrict__ t2, int o, int v, double* 
 // virtual-virtual part in ladder layout when wv is given.
 __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restrict__ g,
                                                          const double* __restrict__ t2,
-                                                         const double* __restrict__ P, int n,
+                                                         const double* __restrict__ P,
+                                                         const double* __restrict__ Q, int n,
                                                          int o, double* U, double* wv) {
   __shared__ double tpq[64 * 64];
   const int v = n - o;
@@ -143,6 +168,9 @@ __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restric
   const double* P2 = P + nv;
   const double* P3 = P + 2 * nv;
   const double* P4 = P + 3 * nv;
+  const size_t ovv = (size_t)o * v * v;
+  const double* Q1 = Q;
+  const double* Q2 = Q + (size_t)n * ovv;
   if (!op && !oq) {
     // sigma_pq.. needs t2[t][u][p][q] for occupied t, u
     for (int e = threadIdx.x; e < o * o; e += blockDim.x)
@@ -161,12 +189,8 @@ __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restric
         if (!op) x += P2[(size_t)q * ov2 + rs + (p - o)];
       } else {     // r, s virtual
         const size_t rs = (size_t)(r - o) * v + (s_ - o);
-        if (oq)
-#pragma unroll 4
-          for (int t = 0; t < o; ++t) x -= g[p * n + t] * t2[((size_t)t * o + q) * v * v + rs];
-        if (op)
-#pragma unroll 4
-          for (int t = 0; t < o; ++t) x -= g[q * n + t] * t2[((size_t)p * o + t) * v * v + rs];
+        if (oq) x += Q1[(size_t)p * ovv + (size_t)q * v * v + rs];
+        if (op) x += Q2[(size_t)q * ovv + (size_t)p * v * v + rs];
       }
     }
     if (op == oq) {
@@ -500,18 +524,28 @@ void launch_mp2(const double* f, const double* V, int n, int o, double* t1, doub
 }
 
 void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12, double* t2T,
-                   bool pack_t2T, double* P, double* part, size_t part_cap, double* U,
+                   bool pack_t2, double* P, double* Q, double* part, size_t part_cap, double* U,
                    double* wv, hipStream_t st) {
   const int v = n - o;
-  const size_t nv = (size_t)n * v, ov2 = (size_t)o * o * v;
+  const size_t nv = (size_t)n * v, ov2 = (size_t)o * o * v, ovv = (size_t)o * v * v;
+  const size_t o2v2 = (size_t)o * ovv;
+  // scratch layout: A12 = [A1 | A2 | Ao], t2T = [t2T | Tq | Tp]
+  double* Ao = A12 + 2 * nv;
+  double* Tq = t2T + o2v2;
+  double* Tp = Tq + o2v2;
   k_pack_onebody<<<grid_for(nv), kBlock, 0, st>>>(g, n, o, A12, A12 + nv);
-  if (pack_t2T)
-    k_pack_t2T<<<grid_for((size_t)o * o * v * v, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, t2T);
+  k_pack_onebody_occ<<<grid_for((size_t)n * o), kBlock, 0, st>>>(g, n, o, Ao);
+  if (pack_t2) {
+    k_pack_t2T<<<grid_for(o2v2, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, t2T);
+    k_pack_t2_occ<<<grid_for(o2v2, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, Tq, Tp);
+  }
   const double* Bs[4] = {t2T, t2, t2T, t2};
   for (int i = 0; i < 4; ++i)
     launch_gemm_nt_f64(A12 + (i < 2 ? 0 : nv), Bs[i], P + i * n * ov2, n, (int)ov2, v, 1.0, part,
                        part_cap, st);
-  k_sigma2_assemble<<<n * n, kBlock, 0, st>>>(g, t2, P, n, o, U, wv);
+  launch_gemm_nt_f64(Ao, Tq, Q, n, (int)ovv, o, -1.0, part, part_cap, st);
+  launch_gemm_nt_f64(Ao, Tp, Q + (size_t)n * ovv, n, (int)ovv, o, -1.0, part, part_cap, st);
+  if (U) k_sigma2_assemble<<<n * n, kBlock, 0, st>>>(g, t2, P, Q, n, o, U, wv);
 }
 
 void launch_yg1(const double* f, const double* t1, const double* t2, int n, int o, double* y1,

@@ -20,7 +20,8 @@ __global__ void k_residual2(GlobalOps g, double* r2) {
   const int n = g.n, o = g.o, v = n - o;
   const Sigma s{g.t1, g.t2, n, o, v};
   const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.z_h, g.u_h, g.lo_h};
-  const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, g.u_y, g.lo_y};
+  const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, nullptr, g.lo_y,
+                   Sigma2Lazy{g.y1, g.t2, g.s2p, g.s2q, n, o}};
   const auto cH = make_comm(H, s, n, o);
   const auto cY = make_comm(Y, s, n, o);
   const size_t tot = (size_t)o * o * v * v;
@@ -47,7 +48,8 @@ __global__ __launch_bounds__(256) void k_comm1(GlobalOps g, double* c1h, double*
     const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.z_h, g.u_h, g.lo_h};
     x = make_comm_split(H, s, n, o, lane, 64).c1(e / n, e % n);
   } else {
-    const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, g.u_y, g.lo_y};
+    const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, nullptr, g.lo_y,
+                   Sigma2Lazy{g.y1, g.t2, g.s2p, g.s2q, n, o}};
     x = make_comm_split(Y, s, n, o, lane, 64).c1(e / n, e % n);
   }
   x = wave_sum(x);
@@ -69,7 +71,8 @@ __global__ __launch_bounds__(64) void k_residual0(GlobalOps g, double* scal, dou
   const int lane = threadIdx.x;
   const Sigma s{g.t1, g.t2, n, o, v};
   const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.z_h, g.u_h, g.lo_h};
-  const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, g.u_y, g.lo_y};
+  const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, nullptr, g.lo_y,
+                   Sigma2Lazy{g.y1, g.t2, g.s2p, g.s2q, n, o}};
   const double zh = wave_sum(make_comm_split(H, s, n, o, lane, 64).c0());
   const double zy = wave_sum(make_comm_split(Y, s, n, o, lane, 64).c0());
   if (lane == 0) {
@@ -87,7 +90,7 @@ void launch_residual(const double* f, const double* V, const double* y1, const d
                      double* r1, double* r2, double* e0, hipStream_t st) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
-              rings.z_h,  rings.z_y, rings.u_h, rings.u_y, rings.c1_h, rings.c1_y,
+              rings.z_h,  rings.z_y, rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
               rings.lo_h, rings.lo_y};
   const size_t v = n - o;
   k_comm1<<<grid_for((size_t)2 * n * n * 64), kBlock, 0, st>>>(g, c1h, c1y);

@@ -32,7 +32,8 @@ struct GlobalOps {
   int n, o;
   const double *ga_h, *g22_h, *j1_h, *j2_h, *ga_y, *g22_y, *j1_y, *j2_y;
   const double *z_h, *z_y;
-  const double *u_h, *u_y;   // [x1, sigma_2]_2 of H_N (= two-body of Yg) and of Yg
+  const double *u_h;         // [x1, sigma_2]_2 of H_N (= two-body of Yg), dense
+  const double *s2p, *s2q;   // compact parts of [y1, sigma_2]_2 (Sigma2Lazy)
   const double *c1_h, *c1_y; // [n][n] one-body parts of [H_N, sigma] and [Yg, sigma]
   const double *lo_h, *lo_y; // [v*v][o*o] occupied-occupied ladders
 };

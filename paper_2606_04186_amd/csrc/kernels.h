@@ -24,10 +24,11 @@ void launch_mp2(const double* f, const double* V, int n, int o, double* t1, doub
 // intermediates of one amplitude set
 // U = [G, sigma_2]_2 (dense n^4) for a Hermitian one-body G, and its
 // virtual-virtual rows in ladder layout into wv when wv is not NULL
-// (k_prep.hip).  Scratch: A12 2*n*v, t2T o*o*v*v (packed here when
-// pack_t2T), P 4*n*o*o*v doubles.
+// (k_prep.hip).  With U NULL only the compact parts P and Q are formed
+// (read through Sigma2Lazy).  Scratch: A12 2*n*v + n*o, t2T 3*o*o*v*v (packed from t2
+// here when pack_t2), P 4*n*o*o*v and Q 2*n*o*v*v doubles.
 void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12, double* t2T,
-                   bool pack_t2T, double* P, double* part, size_t part_cap, double* U,
+                   bool pack_t2, double* P, double* Q, double* part, size_t part_cap, double* U,
                    double* wv, hipStream_t st);
 // y1 = one-body part of [F_N, sigma], scal[2] = its scalar part
 void launch_yg1(const double* f, const double* t1, const double* t2, int n, int o, double* y1,
@@ -57,7 +58,8 @@ void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int 
 struct RingOps {            // global intermediates of H_N and of Yg
   const double *ga_h, *g22_h, *j1_h, *j2_h, *ga_y, *g22_y, *j1_y, *j2_y;
   const double *z_h, *z_y;
-  const double *u_h, *u_y;   // [x1, sigma_2]_2 of H_N (= two-body of Yg) and of Yg
+  const double *u_h;         // [x1, sigma_2]_2 of H_N (= two-body of Yg), dense
+  const double *s2p, *s2q;   // compact parts of [y1, sigma_2]_2 (Sigma2Lazy)
   const double *c1_h, *c1_y; // [n][n] one-body parts of [H_N, sigma] and [Yg, sigma]
   const double *lo_h, *lo_y; // [v*v][o*o] occupied-occupied ladders
 };

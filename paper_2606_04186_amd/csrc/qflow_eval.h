@@ -117,6 +117,50 @@ struct Tau {
 // the "A" operators
 // ---------------------------------------------------------------------------
 
+// U = [G, sigma_2]_2 of a Hermitian one-body G evaluated from the compact
+// contractions of the K = v and K = o GEMMs (P1..P4, Q1, Q2; layouts as in
+// launch_sigma2) instead of a dense n^4 array.  Zero unless r,s or p,q share
+// a class; the p,q-virtual cases with r or s occupied are o-term sums.
+struct Sigma2Lazy {
+  const double* g;    // G [n][n]
+  const double* t2;
+  const double* P;    // [4][n][o*o*v]
+  const double* Q;    // [2][n][o*v*v]
+  int n, o;
+  QF_HD double operator()(int p, int q, int r, int s) const {
+    const int v = n - o;
+    const bool op = p < o, oq = q < o, or_ = r < o, os = s < o;
+    const size_t ov2 = (size_t)o * o * v, nv = (size_t)n * ov2;
+    const size_t vv = (size_t)v * v, ovv = (size_t)o * vv;
+    double x = 0.0;
+    if (or_ == os) {
+      if (or_) {
+        const size_t rs = ((size_t)r * o + s) * v;
+        if (!oq) x += P[(size_t)p * ov2 + rs + (q - o)];
+        if (!op) x += P[nv + (size_t)q * ov2 + rs + (p - o)];
+      } else {
+        const size_t rs = (size_t)(r - o) * v + (s - o);
+        if (oq) x += Q[(size_t)p * ovv + (size_t)q * vv + rs];
+        if (op) x += Q[(size_t)n * ovv + (size_t)q * ovv + (size_t)p * vv + rs];
+      }
+    }
+    if (op == oq) {
+      if (op) {
+        const size_t pq = ((size_t)p * o + q) * v;
+        if (!os) x += P[2 * nv + (size_t)r * ov2 + pq + (s - o)];
+        if (!or_) x += P[3 * nv + (size_t)s * ov2 + pq + (r - o)];
+      } else {
+        const size_t ab = (size_t)(p - o) * v + (q - o);
+        if (os)
+          for (int t = 0; t < o; ++t) x -= g[t * n + r] * t2[((size_t)t * o + s) * vv + ab];
+        if (or_)
+          for (int t = 0; t < o; ++t) x -= g[t * n + s] * t2[((size_t)r * o + t) * vv + ab];
+      }
+    }
+    return x;
+  }
+};
+
 // Dense operator A (H_N, or Yg) with its global contractions against sigma:
 //   L[(pq)][(ij)]       = sum_{c,d virtual} A[p,q,c,d] t2[i,j,c,d]       (ladder)
 //   Ga[(ab)][(g d)]     = sum_{u occ, t virt} (2 A[a,u,b,t] - A[a,u,t,b]) t2[u,d,t,g]
@@ -137,8 +181,9 @@ struct DenseOp {
   const double* J1 = nullptr;    // [n][v]
   const double* J2 = nullptr;    // [n][v]
   const double* Z = nullptr;     // [n][n][n][n], sum_t sigma1(p,t) x2(t,q,r,s)
-  const double* U = nullptr;     // [n][n][n][n], [x1, sigma_2]_2
+  const double* U = nullptr;     // [n][n][n][n], [x1, sigma_2]_2; when NULL, Ul is used
   const double* Lo = nullptr;    // [v*v][o*o], sum_{tu occ} t2[t,u,a,b] x2(t,u,i,j)
+  Sigma2Lazy Ul{};
   QF_HD double one(int p, int q) const { return x1[p * n + q]; }
   QF_HD double two(int p, int q, int r, int s) const {
     return x2[(((size_t)p * n + q) * n + r) * n + s];
@@ -158,7 +203,7 @@ struct DenseOp {
     return Z[(((size_t)p * n + q) * n + r) * n + s];
   }
   QF_HD double u(int p, int q, int r, int s) const {
-    return U[(((size_t)p * n + q) * n + r) * n + s];
+    return U ? U[(((size_t)p * n + q) * n + r) * n + s] : Ul(p, q, r, s);
   }
   QF_HD double lo(int a, int b, int i, int j) const {
     const int v = n - o;
