@@ -68,10 +68,24 @@ __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
     double acc = 0.0;
     if (bo == co && ao != bo) {
       const int ft = A.orb[t], pa = A.orb[a], pb = A.orb[b], pc = A.orb[c];
-      const int m = A.next(ao);
-      for (int i = 0; i < m; ++i) {
-        const int x = A.extv(ao, i);
-        acc += g.f[x * n + ft] * (j == 0 ? s.two(x, pa, pb, pc) : s.two(pa, x, pb, pc));
+      if (ao) {
+        // x over the occupied externals
+        const int m = A.next(true);
+        for (int i = 0; i < m; ++i) {
+          const int x = A.extv(true, i);
+          acc += g.f[x * n + ft] * (j == 0 ? s.two(x, pa, pb, pc) : s.two(pa, x, pb, pc));
+        }
+      } else {
+        // x over all virtuals is P3 (slot 0) / P4 (slot 1) of [F, sigma_2]
+        // (sum_x f[x][t] t2[b][c][x][a] and sum_x f[x][t] t2[b][c][a][x]),
+        // less the active virtuals
+        const int v = n - g.o;
+        const size_t ov2 = (size_t)g.o * g.o * v, nv = (size_t)n * ov2;
+        acc = g.pf[(2 + j) * nv + (size_t)ft * ov2 + ((size_t)pb * g.o + pc) * v + (pa - g.o)];
+        for (int i = nocc; i < na; ++i) {
+          const int x = A.orb[i];
+          acc -= g.f[x * n + ft] * (j == 0 ? s.two(x, pa, pb, pc) : s.two(pa, x, pb, pc));
+        }
       }
     }
     d01[e] = acc;
@@ -240,7 +254,7 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
               rings.z_h,  rings.z_y, rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
-              rings.lo_h, rings.lo_y};
+              rings.lo_h, rings.lo_y, rings.pf};
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
   dim3 grid(K, (slots_max + kBlock - 1) / kBlock);
   int s1, s2, s3, s4;

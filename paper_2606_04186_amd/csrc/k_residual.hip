@@ -91,7 +91,7 @@ void launch_residual(const double* f, const double* V, const double* y1, const d
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
               rings.z_h,  rings.z_y, rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
-              rings.lo_h, rings.lo_y};
+              rings.lo_h, rings.lo_y, rings.pf};
   const size_t v = n - o;
   k_comm1<<<grid_for((size_t)2 * n * n * 64), kBlock, 0, st>>>(g, c1h, c1y);
   k_residual2<<<grid_for(o * o * v * v, kBlock, 65536), kBlock, 0, st>>>(g, r2);

@@ -36,6 +36,7 @@ struct GlobalOps {
   const double *s2p, *s2q;   // compact parts of [y1, sigma_2]_2 (Sigma2Lazy)
   const double *c1_h, *c1_y; // [n][n] one-body parts of [H_N, sigma] and [Yg, sigma]
   const double *lo_h, *lo_y; // [v*v][o*o] occupied-occupied ladders
+  const double *pf;          // compact parts P1..P4 of [F, sigma_2] (launch_sigma2)
 };
 
 }  // namespace qf

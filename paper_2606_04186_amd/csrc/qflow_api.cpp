@@ -54,7 +54,7 @@ struct qflow_ctx {
   DevBuf dtpart;   // per-block maxima of |t_new - t_old|
   // [G, sigma_2]_2 scratch (packed one-body, transposed t2, GEMM outputs)
   // and U_Y = [y1, sigma_2]_2
-  DevBuf a12, t2T, sp, sq;
+  DevBuf a12, t2T, sp, sq, sp_f;   // sp_f keeps the [F, sigma_2] parts
   DevBuf c1h, c1y;   // one-body parts of [H_N, sigma] and [Yg, sigma], [n][n]
   // occupied-occupied ladders: packed t2 [v*v][o*o], X_oooo of H (constant)
   // and Yg [o*o][o*o], outputs Lo of H and Yg [v*v][o*o]
@@ -217,7 +217,8 @@ qf::RingOps rings_of(qflow_ctx* ctx) {
                      P<double>(ctx->z_h),      P<double>(ctx->z_y),
                      P<double>(ctx->y2),       P<double>(ctx->sp),       P<double>(ctx->sq),
                      P<double>(ctx->c1h),      P<double>(ctx->c1y),
-                     P<double>(ctx->lo_h),     P<double>(ctx->lo_y)};
+                     P<double>(ctx->lo_h),     P<double>(ctx->lo_y),
+                     P<double>(ctx->sp_f)};
 }
 
 // Yg = [F,sigma], the ladder intermediates L = W t2^T, LY = WY t2^T and the
@@ -235,7 +236,7 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   qf::launch_yg1(P<double>(ctx->f), t1, t2, n, o, P<double>(ctx->y1), P<double>(ctx->scal),
                  ctx->stream);
   qf::launch_sigma2(P<double>(ctx->f), t2, n, o, P<double>(ctx->a12), P<double>(ctx->t2T), true,
-                    P<double>(ctx->sp), P<double>(ctx->sq), part, pcap, P<double>(ctx->y2),
+                    P<double>(ctx->sp_f), P<double>(ctx->sq), part, pcap, P<double>(ctx->y2),
                     P<double>(ctx->wy), ctx->stream);
   qf::launch_sigma2(P<double>(ctx->y1), t2, n, o, P<double>(ctx->a12), P<double>(ctx->t2T),
                     false, P<double>(ctx->sp), P<double>(ctx->sq), part, pcap, nullptr, nullptr,
@@ -349,7 +350,7 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
                     &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
                     &ctx->gpart,  &ctx->z_h,      &ctx->z_y,      &ctx->dtpart,
-                    &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->sq,
+                    &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->sq,       &ctx->sp_f,
                     &ctx->c1h,
                     &ctx->c1y,    &ctx->lo_t,     &ctx->lo_xh,  &ctx->lo_xy,    &ctx->lo_h,
                     &ctx->lo_y,
@@ -435,6 +436,7 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->t2T, sizeof(double) * 3 * o * o * v * v));
   QF_TRY(ensure(ctx, ctx->sp, sizeof(double) * 4 * n * o * o * v));
   QF_TRY(ensure(ctx, ctx->sq, sizeof(double) * 2 * n * o * v * v));
+  QF_TRY(ensure(ctx, ctx->sp_f, sizeof(double) * 4 * n * o * o * v));
   QF_TRY(ensure(ctx, ctx->c1h, sizeof(double) * n2));
   QF_TRY(ensure(ctx, ctx->c1y, sizeof(double) * n2));
   QF_TRY(ensure(ctx, ctx->lo_t, sizeof(double) * o * o * v * v));
