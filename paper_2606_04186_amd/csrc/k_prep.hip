@@ -391,27 +391,33 @@ __global__ void k_pack_ring_T(const double* __restrict__ t2, int o, int v, doubl
 // c = (q,r,s); t1 is staged in LDS (o*v doubles) and read by broadcast.
 constexpr int kZChunk = 16;
 
+// W adjacent columns per thread (W = 2: 16-byte loads and stores; the host
+// picks W = 2 when n^3 is even).
+template <int W>
 __global__ __launch_bounds__(256) void k_sigma1_x(const double* __restrict__ X,
                                                   const double* __restrict__ t1, int n, int o,
                                                   double* Z) {
+  typedef double vw __attribute__((ext_vector_type(W)));
   extern __shared__ double ts[];   // t1, o*v
   const int v = n - o;
   for (int e = threadIdx.x; e < o * v; e += blockDim.x) ts[e] = t1[e];
   __syncthreads();
   const size_t n3 = (size_t)n * n * n;
-  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t c = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * W;
   if (c >= n3) return;
+  auto ld = [&](int t) { return *reinterpret_cast<const vw*>(X + (size_t)t * n3 + c); };
+  auto st = [&](int p, vw x) { *reinterpret_cast<vw*>(Z + (size_t)p * n3 + c) = x; };
   // p occupied: Z[p][c] = -sum_{t virtual} t1[p][t-o] X[t][c]; the column of
   // X is read eight rows at a time to keep several loads in flight
   for (int p0 = 0; p0 < o; p0 += kZChunk) {
-    double acc[kZChunk];
+    vw acc[kZChunk];
 #pragma unroll
-    for (int i = 0; i < kZChunk; ++i) acc[i] = 0.0;
+    for (int i = 0; i < kZChunk; ++i) acc[i] = vw(0.0);
     int t = o;
     for (; t + 8 <= n; t += 8) {
-      double x[8];
+      vw x[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) x[j] = X[(size_t)(t + j) * n3 + c];
+      for (int j = 0; j < 8; ++j) x[j] = ld(t + j);
 #pragma unroll
       for (int j = 0; j < 8; ++j)
 #pragma unroll
@@ -419,27 +425,27 @@ __global__ __launch_bounds__(256) void k_sigma1_x(const double* __restrict__ X,
           if (p0 + i < o) acc[i] -= ts[(p0 + i) * v + (t + j - o)] * x[j];
     }
     for (; t < n; ++t) {
-      const double x = X[(size_t)t * n3 + c];
+      const vw x = ld(t);
 #pragma unroll
       for (int i = 0; i < kZChunk; ++i)
         if (p0 + i < o) acc[i] -= ts[(p0 + i) * v + (t - o)] * x;
     }
 #pragma unroll
     for (int i = 0; i < kZChunk; ++i)
-      if (p0 + i < o) Z[(size_t)(p0 + i) * n3 + c] = acc[i];
+      if (p0 + i < o) st(p0 + i, acc[i]);
   }
   // p virtual: Z[p][c] = sum_{t occupied} t1[t][p-o] X[t][c]
   for (int t0 = 0; t0 < o; t0 += kZChunk) {
-    double xo[kZChunk];
+    vw xo[kZChunk];
 #pragma unroll
-    for (int i = 0; i < kZChunk; ++i) xo[i] = (t0 + i < o) ? X[(size_t)(t0 + i) * n3 + c] : 0.0;
+    for (int i = 0; i < kZChunk; ++i) xo[i] = (t0 + i < o) ? ld(t0 + i) : vw(0.0);
     for (int p = o; p < n; ++p) {
-      double acc = 0.0;
+      vw acc = vw(0.0);
 #pragma unroll
       for (int i = 0; i < kZChunk; ++i)
         if (t0 + i < o) acc += ts[(t0 + i) * v + (p - o)] * xo[i];
-      double* z = Z + (size_t)p * n3 + c;
-      *z = (t0 == 0) ? acc : *z + acc;
+      if (t0 > 0) acc += *reinterpret_cast<const vw*>(Z + (size_t)p * n3 + c);
+      st(p, acc);
     }
   }
 }
@@ -565,8 +571,11 @@ void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22,
 
 void launch_sigma1_x(const double* X, const double* t1, int n, int o, double* Z, hipStream_t st) {
   const size_t n3 = (size_t)n * n * n;
-  k_sigma1_x<<<(unsigned)((n3 + kBlock - 1) / kBlock), kBlock,
-               (size_t)o * (n - o) * sizeof(double), st>>>(X, t1, n, o, Z);
+  const size_t lds = (size_t)o * (n - o) * sizeof(double);
+  if (n3 % 2 == 0)
+    k_sigma1_x<2><<<(unsigned)((n3 / 2 + kBlock - 1) / kBlock), kBlock, lds, st>>>(X, t1, n, o, Z);
+  else
+    k_sigma1_x<1><<<(unsigned)((n3 + kBlock - 1) / kBlock), kBlock, lds, st>>>(X, t1, n, o, Z);
 }
 
 void launch_pack_t2_vvoo(const double* t2, int o, int v, double* T, hipStream_t st) {

@@ -46,14 +46,62 @@ __global__ __launch_bounds__(256) void k_comm1(GlobalOps g, double* c1h, double*
   double x;
   if (which == 0) {
     const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.z_h, g.u_h, g.lo_h};
-    x = make_comm_split(H, s, n, o, lane, 64).c1(e / n, e % n);
+    auto c = make_comm_split(H, s, n, o, lane, 64);
+    c.ring1 = false;
+    x = c.c1(e / n, e % n);
   } else {
     const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, nullptr, g.lo_y,
                    Sigma2Lazy{g.y1, g.t2, g.s2p, g.s2q, n, o}};
-    x = make_comm_split(Y, s, n, o, lane, 64).c1(e / n, e % n);
+    auto c = make_comm_split(Y, s, n, o, lane, 64);
+    c.ring1 = false;
+    x = c.c1(e / n, e % n);
   }
   x = wave_sum(x);
   if (lane == 0) (which == 0 ? c1h : c1y)[e] = x;
+}
+
+// The sigma1 x X_2 part of the one-body commutator for all (p,q):
+//   R[p][q] = sum_{t occ, u vir} t1[t][u] (2 X_uptq - X_upqt + 2 X_tpuq - X_tpqu)
+// (X pair symmetric, X_pqrs = X_qpsr).
+// Block (p, chunk of u, operator), one thread per q; chunk partials go to
+// part[op][chunk][n][n] and are added in a fixed order by k_comm1_sum.
+constexpr int kRingChunk = 8;
+
+__global__ __launch_bounds__(128) void k_comm1_ring(const double* __restrict__ X0,
+                                                    const double* __restrict__ X1,
+                                                    const double* __restrict__ t1, int n, int o,
+                                                    double* part) {
+  const int v = n - o;
+  const int nch = (v + kRingChunk - 1) / kRingChunk;
+  const int p = blockIdx.x, ch = blockIdx.y, op = blockIdx.z;
+  const int q = threadIdx.x;
+  const double* X = op == 0 ? X0 : X1;
+  const size_t n2 = (size_t)n * n, n3 = n2 * n;
+  double acc = 0.0;
+  if (q < n) {
+    const int u0 = o + ch * kRingChunk, u1 = min(n, u0 + kRingChunk);
+    for (int u = u0; u < u1; ++u)
+      for (int t = 0; t < o; ++t) {
+        const double w = t1[t * v + (u - o)];
+        // X_upqt = X_putq and X_tpqu = X_ptuq (pair symmetry): all four reads
+        // run along q
+        const double x = 2.0 * X[u * n3 + p * n2 + (size_t)t * n + q] - X[p * n3 + u * n2 + (size_t)t * n + q] +
+                         2.0 * X[t * n3 + p * n2 + (size_t)u * n + q] - X[p * n3 + t * n2 + (size_t)u * n + q];
+        acc += w * x;
+      }
+    part[(((size_t)op * nch + ch) * n + p) * n + q] = acc;
+  }
+}
+
+__global__ void k_comm1_sum(const double* __restrict__ part, int n, int nch, double* c1h,
+                            double* c1y) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n2 = n * n;
+  if (e >= 2 * n2) return;
+  const int op = e / n2, pq = e % n2;
+  double s = 0.0;
+  for (int c = 0; c < nch; ++c) s += part[((size_t)op * nch + c) * n2 + pq];
+  (op == 0 ? c1h : c1y)[pq] += s;
 }
 
 __global__ void k_residual1(GlobalOps g, double* r1) {
@@ -87,13 +135,16 @@ __global__ __launch_bounds__(64) void k_residual0(GlobalOps g, double* scal, dou
 void launch_residual(const double* f, const double* V, const double* y1, const double* y2,
                      const double* L, const double* LY, const RingOps& rings, const double* t1,
                      const double* t2, int n, int o, double* scal, double* c1h, double* c1y,
-                     double* r1, double* r2, double* e0, hipStream_t st) {
+                     double* part, double* r1, double* r2, double* e0, hipStream_t st) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
               rings.z_h,  rings.z_y, rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
               rings.lo_h, rings.lo_y, rings.pf};
   const size_t v = n - o;
   k_comm1<<<grid_for((size_t)2 * n * n * 64), kBlock, 0, st>>>(g, c1h, c1y);
+  const int nch = (int)((v + kRingChunk - 1) / kRingChunk);
+  k_comm1_ring<<<dim3(n, nch, 2), 128, 0, st>>>(V, y2, t1, n, o, part);
+  k_comm1_sum<<<grid_for((size_t)2 * n * n), kBlock, 0, st>>>(part, n, nch, c1h, c1y);
   k_residual2<<<grid_for(o * o * v * v, kBlock, 65536), kBlock, 0, st>>>(g, r2);
   k_residual1<<<grid_for(o * v), kBlock, 0, st>>>(g, r1);
   k_residual0<<<1, 64, 0, st>>>(g, scal, e0);

@@ -66,11 +66,12 @@ struct RingOps {            // global intermediates of H_N and of Yg
 };
 // One-body parts of [H_N, sigma] and [Yg, sigma] for every (p,q) into
 // c1h, c1y ([n][n] each; the buffers RingOps.c1_h / c1_y point to), then the
-// residual r1, r2 and the zero-body parts (scal[0], scal[1], e0).
+// residual r1, r2 and the zero-body parts (scal[0], scal[1], e0).  part:
+// scratch of 2*ceil(v/8)*n*n doubles.
 void launch_residual(const double* f, const double* V, const double* y1, const double* y2,
                      const double* L, const double* LY, const RingOps& rings, const double* t1,
                      const double* t2, int n, int o, double* scal, double* c1h, double* c1y,
-                     double* r1, double* r2, double* e0, hipStream_t st);
+                     double* part, double* r1, double* r2, double* e0, hipStream_t st);
 
 // per-space downfolded Hamiltonians in CAS form
 void launch_heff(const double* f, const double* V, const double* y1, const double* y2,

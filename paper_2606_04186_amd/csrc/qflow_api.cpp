@@ -427,8 +427,10 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->ja_y, sizeof(double) * 2 * n * kj));
   QF_TRY(ensure(ctx, ctx->jb, sizeof(double) * 2 * v * kj));
   // split-K slices: up to 8 of the ladder output (n^2 o^2) or 128 of J (n v)
+  // (also the one-body ring partials, 2*ceil(v/8)*n^2)
   QF_TRY(ensure(ctx, ctx->gpart,
-                sizeof(double) * std::max(8 * n2 * o * o, (size_t)qf::kMaxSplits * n * v)));
+                sizeof(double) * std::max({8 * n2 * o * o, (size_t)qf::kMaxSplits * n * v,
+                                           2 * (size_t)((v + 7) / 8) * n2})));
   QF_TRY(ensure(ctx, ctx->z_h, sizeof(double) * n4));
   QF_TRY(ensure(ctx, ctx->z_y, sizeof(double) * n4));
   QF_TRY(ensure(ctx, ctx->dtpart, sizeof(double) * qf::kFinishParts));
@@ -495,7 +497,7 @@ int qflow_residual(qflow_ctx* ctx, const double* t1, const double* t2, double* r
   qf::launch_residual(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
                       P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx),
                       t1, t2, ctx->n, ctx->o, P<double>(ctx->scal), P<double>(ctx->c1h),
-                      P<double>(ctx->c1y), r1, r2, e0, ctx->stream);
+                      P<double>(ctx->c1y), P<double>(ctx->gpart), r1, r2, e0, ctx->stream);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -530,7 +532,7 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
   qf::launch_residual(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
                       P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx),
                       t1, t2, ctx->n, ctx->o, P<double>(ctx->scal), P<double>(ctx->c1h),
-                      P<double>(ctx->c1y), P<double>(ctx->r1),
+                      P<double>(ctx->c1y), P<double>(ctx->gpart), P<double>(ctx->r1),
                       P<double>(ctx->r2), nullptr, ctx->stream);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[8], ctx->stream));
   if (K > 0)

@@ -283,6 +283,9 @@ struct Comm {
   // caller sums the partial results of the nl lanes (nl = 1: one evaluator
   // does everything).  Terms without a loop are taken by lane 0.
   int ln = 0, nl = 1;
+  // false: leave out the sigma1 x A_2 part of the one-body element (the
+  // caller evaluates it for all (p,q) at once)
+  bool ring1 = true;
 
   QF_HD bool occ(int p) const { return p < o; }
   QF_HD bool lead() const { return ln == 0; }
@@ -477,10 +480,11 @@ struct Comm {
       over_pair(false, true, [&](int t, int u) {
         res -= a.one(t, u) * (2.0 * b.two(u, p, t, q) - b.two(u, p, q, t));
       });
-    over_pair(true, false, [&](int t, int u) {
-      res -= b.one(t, u) * (2.0 * a.two(u, p, t, q) - a.two(u, p, q, t));
-      res += b.one(u, t) * (2.0 * a.two(t, p, u, q) - a.two(t, p, q, u));
-    });
+    if (ring1)
+      over_pair(true, false, [&](int t, int u) {
+        res -= b.one(t, u) * (2.0 * a.two(u, p, t, q) - a.two(u, p, q, t));
+        res += b.one(u, t) * (2.0 * a.two(t, p, u, q) - a.two(t, p, q, u));
+      });
     // sum_tuw (n_t n_u nb_w + nb_t nb_u n_w)
     //      [A_wptu (2 B_tuwq - B_tuqw) - B_wptu (2 A_tuwq - A_tuqw)]
     // (t,u occupied, w virtual): B_tuwq needs q virtual, B_wptu needs p virtual
