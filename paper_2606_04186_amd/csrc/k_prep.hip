@@ -67,7 +67,8 @@ __global__ void k_repack(const double* __restrict__ eri, int n, int o, double* V
               p = (int)(idx / (n2 * n));
     const double x = eri[(((size_t)p * n + r) * n + q) * n + s];
     V[idx] = x;
-    if (r >= o && s >= o) W[((size_t)p * n + q) * v * v + (size_t)(r - o) * v + (s - o)] = x;
+    if (r >= o && s >= o && p <= q)
+      W[tri_row(p, q, n) * v * v + (size_t)(r - o) * v + (s - o)] = x;
   }
 }
 
@@ -152,8 +153,9 @@ __global__ void k_pack_t2T(const double* __restrict__ t2, int o, int v, double* 
   }
 }
 
-// One workgroup per (p,q): the row U[p][q][:][:] (contiguous), and its
-// virtual-virtual part in ladder layout when wv is given.
+// One workgroup per (p,q): the row U[p][q][:][:] (contiguous), and, for
+// p <= q, its virtual-virtual part in ladder layout (row tri_row(p,q)) when
+// wv is given.
 __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restrict__ g,
                                                          const double* __restrict__ t2,
                                                          const double* __restrict__ P,
@@ -206,8 +208,8 @@ __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restric
       }
     }
     U[row + e] = x;
-    if (wv && !or_ && !os)
-      wv[((size_t)p * n + q) * v * v + (size_t)(r - o) * v + (s_ - o)] = x;
+    if (wv && !or_ && !os && p <= q)
+      wv[tri_row(p, q, n) * v * v + (size_t)(r - o) * v + (s_ - o)] = x;
   }
 }
 

@@ -242,10 +242,11 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
                     false, P<double>(ctx->sp), P<double>(ctx->sq), part, pcap, nullptr, nullptr,
                     ctx->stream);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
-  qf::launch_gemm_nt_f64(P<double>(ctx->W), t2, P<double>(ctx->L), n * n, o * o, v * v, 1.0, part,
+  const int npair = n * (n + 1) / 2;   // ladder rows p <= q
+  qf::launch_gemm_nt_f64(P<double>(ctx->W), t2, P<double>(ctx->L), npair, o * o, v * v, 1.0, part,
                          pcap, ctx->stream);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
-  qf::launch_gemm_nt_f64(P<double>(ctx->wy), t2, P<double>(ctx->LY), n * n, o * o, v * v, 1.0,
+  qf::launch_gemm_nt_f64(P<double>(ctx->wy), t2, P<double>(ctx->LY), npair, o * o, v * v, 1.0,
                          part, pcap, ctx->stream);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[3], ctx->stream));
   hipStream_t st = ctx->stream;
@@ -381,7 +382,7 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_HIP(hipSetDevice(ctx->device));
   ctx->loaded = false;
   const int n = n_orb, o = n_occ, v = n - o;
-  const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+  const size_t n2 = (size_t)n * n, n4 = n2 * n2, n2p = (size_t)n * (n + 1) / 2;
   ctx->n = n;
   ctx->o = o;
   ctx->v = v;
@@ -399,12 +400,12 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
                 "integrals not finite or not symmetric: max deviation " + std::to_string(asym));
   QF_TRY(ensure(ctx, ctx->f, sizeof(double) * n2));
   QF_TRY(ensure(ctx, ctx->V, sizeof(double) * n4));
-  QF_TRY(ensure(ctx, ctx->W, sizeof(double) * n2 * v * v));
+  QF_TRY(ensure(ctx, ctx->W, sizeof(double) * n2p * v * v));
   QF_TRY(ensure(ctx, ctx->y1, sizeof(double) * n2));
   QF_TRY(ensure(ctx, ctx->y2, sizeof(double) * n4));
-  QF_TRY(ensure(ctx, ctx->wy, sizeof(double) * n2 * v * v));
-  QF_TRY(ensure(ctx, ctx->L, sizeof(double) * n2 * o * o));
-  QF_TRY(ensure(ctx, ctx->LY, sizeof(double) * n2 * o * o));
+  QF_TRY(ensure(ctx, ctx->wy, sizeof(double) * n2p * v * v));
+  QF_TRY(ensure(ctx, ctx->L, sizeof(double) * n2p * o * o));
+  QF_TRY(ensure(ctx, ctx->LY, sizeof(double) * n2p * o * o));
   QF_TRY(ensure(ctx, ctx->r1, sizeof(double) * o * v));
   QF_TRY(ensure(ctx, ctx->r2, sizeof(double) * (size_t)o * o * v * v));
   QF_TRY(ensure(ctx, ctx->t1n, sizeof(double) * o * v));

@@ -71,6 +71,9 @@ QF_HD void active_fill_ext(Active& A, int n, int o) {
   A.next_v = m - A.next_o;
 }
 
+// Row of the ordered pair (p,q), p <= q, among the n(n+1)/2 such pairs.
+QF_HD size_t tri_row(int p, int q, int n) { return (size_t)p * (2 * n - p + 1) / 2 + (q - p); }
+
 // sigma = T - T^dagger from t1[o][v], t2[o][o][v][v].
 struct Sigma {
   static constexpr bool kFull = true;
@@ -174,7 +177,7 @@ struct DenseOp {
   static constexpr bool kSparse3 = false;
   const double* x1;   // [n][n]
   const double* x2;   // [n][n][n][n]
-  const double* L;    // [n*n][o*o]
+  const double* L;    // [n(n+1)/2][o*o], rows p <= q
   int n, o;
   const double* Ga = nullptr;    // [n*n][v*o]
   const double* G22 = nullptr;   // [n*n][v*o]
@@ -188,8 +191,11 @@ struct DenseOp {
   QF_HD double two(int p, int q, int r, int s) const {
     return x2[(((size_t)p * n + q) * n + r) * n + s];
   }
+  // L holds the rows p <= q only (packed, tri_row); L[(q,p)][(j,i)] = L[(p,q)][(i,j)]
+  // by the pair symmetry of A and t2
   QF_HD double lad(int p, int q, int i, int j) const {
-    return L[((size_t)p * n + q) * o * o + i * o + j];
+    return p <= q ? L[tri_row(p, q, n) * o * o + i * o + j]
+                  : L[tri_row(q, p, n) * o * o + j * o + i];
   }
   QF_HD double ga(int a, int b, int g, int d) const {
     return Ga[((size_t)a * n + b) * (size_t)(n - o) * o + (size_t)(g - o) * o + d];
