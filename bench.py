@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-spaces", type=int, default=1)
+    ap.add_argument("--cpu-sample-spaces", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB mebibytes device to device once before the steps "
                          "(reference dispatch for the HBM traffic counters)")
@@ -103,9 +103,9 @@ def main():
     ms = (t1_ - t0) * 1e3 / args.steps
     st = {key: float(np.mean([s[key] for s in stages])) for key in stages[0]}
 
-    # Roofline of the matrix-core GEMM kernel (k_gemm_nt_f64, six launches per
-    # step: two ladders, two Ga rings, two G22 rings).  Algorithmic flops per
-    # step over its event-timed duration inside the timed region.
+    # Roofline of the matrix-core GEMM kernel k_gemm_f64 over its ladder and
+    # ring launches (six per step: two ladders, two Ga rings, two G22 rings):
+    # algorithmic flops per step over their HIP-event time in the timed region.
     ov = o * v
     f_ladder = 2.0 * (n * (n + 1) // 2) * (o * o) * (v * v)   # rows p <= q
     f_ga = 2.0 * (n * n) * ov * (2 * ov)
@@ -113,10 +113,10 @@ def main():
     gemm_flops = 2 * f_ladder + 2 * f_ga + 2 * f_g22
     gemm_ms = st["ladder_h"] + st["ladder_yg"] + st["ring_gemm"]
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
-    roof = {"kernel": "k_gemm_nt_f64 (ladders + rings)", "bound": "mfma", "achieved": achieved,
-            "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
-            "flop_per_step": gemm_flops, "ms_per_step": gemm_ms}
+    roof = {"kernel": "k_gemm_f64", "scope": "ladder and ring launches, six per step",
+            "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
+            "traffic": gemm_traffic(), "flop_per_step": gemm_flops, "ms_per_step": gemm_ms}
     ladder = {"kernel": "ladder_h", "tflops": f_ladder / (st["ladder_h"] * 1e-3) / 1e12,
               "frac_fp64_mfma": f_ladder / (st["ladder_h"] * 1e-3) / 1e12
               / FP64_MFMA_PEAK_TFLOPS}
@@ -150,6 +150,27 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def gemm_traffic():
+    """HBM bytes per step of the six ladder and ring GEMM launches, from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in
+    profiles/k_gemm_f64_c4_traffic.md (scaled by a device copy of known size);
+    None when the GEMM source has changed since those counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_gemm_f64_c4_traffic.md")
+    src = os.path.join(ROOT, "paper_2606_04186_amd", "csrc", "k_gemm.hip")
+    try:
+        text = open(path).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_b = re.search(r"traffic_bytes_per_step: (\d+)", text)
+    m_h = re.search(r"k_gemm.hip sha256: ([0-9a-f]+)", text)
+    if not m_b or not m_h or m_h.group(1) != digest:
+        return None
+    return int(m_b.group(1))
 
 
 def cpu_baseline(h, eri, o, spaces, m, K):
