@@ -8,9 +8,13 @@ and the pool update, on the 114-orbital workload (13 occupied, 101 virtual,
 integrals).  Inputs are resident in HBM before the timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4]
-                    [--no-cpu-baseline]
+                    [--precision both|fp64|fp32] [--no-cpu-baseline]
 
-Prints one JSON line.
+By default both paths run from the same MP2 start: plain FP64, and the mixed
+one (the ladder and ring contractions with FP32 operands on the FP32 matrix
+cores, FP64 sums; everything else FP64).  `value` is the mixed path's rate when
+its mean and per-space energies stay within 1e-6 Eh of the FP64 path's,
+otherwise the FP64 rate; both are in `modes`.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -27,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
 def parse():
@@ -35,6 +40,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c4")
+    ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both",
+                    help="both: time the FP64 path and the mixed path (FP32 ladder and ring "
+                         "products, FP64 sums) from the same start and report the mixed one "
+                         "when its energies are within 1e-6 Eh of FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-spaces", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -74,7 +83,6 @@ def main():
     d2 = torch.from_numpy(o2).to(dev)
     t1 = torch.zeros(o, v, dtype=torch.float64, device=dev)
     t2 = torch.zeros(o, o, v, v, dtype=torch.float64, device=dev)
-    ctx.mp2_guess(t1, t2)
     energy = torch.zeros(K, dtype=torch.float64, device=dev)
     if args.copy_calibration > 0:
         nb = args.copy_calibration << 20
@@ -85,23 +93,43 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] copied {nb} bytes device to device", file=sys.stderr, flush=True)
         del src, dst
-    print("[bench] warmup", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        ctx.flow_step(spaces, d1, d2, t1, t2, energy)
-    stages = []
-    e_means = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        em, dt = ctx.flow_step(spaces, d1, d2, t1, t2, energy)
-        stages.append(ctx.last_timings())
-        e_means.append(em)
-        print(f"[bench] step {k} E_mean {em:.10f} max|dt| {dt:.3e} {stages[-1]}",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1_ = time.perf_counter()
-    ms = (t1_ - t0) * 1e3 / args.steps
-    st = {key: float(np.mean([s[key] for s in stages])) for key in stages[0]}
+
+    def run_path(precision):
+        """W untimed and K timed macro-iterations from the MP2 start."""
+        ctx.mp2_guess(t1, t2)
+        tag = {qf.FP64: "fp64", qf.FP32: "fp32"}[precision]
+        print(f"[bench] {tag}: warmup", file=sys.stderr, flush=True)
+        for _ in range(args.warmup):
+            ctx.flow_step(spaces, d1, d2, t1, t2, energy, precision)
+        stages, e_means = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            em, dt = ctx.flow_step(spaces, d1, d2, t1, t2, energy, precision)
+            stages.append(ctx.last_timings())
+            e_means.append(em)
+            print(f"[bench] {tag} step {k} E_mean {em:.10f} max|dt| {dt:.3e} {stages[-1]}",
+                  file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        st = {key: float(np.mean([s_[key] for s_ in stages])) for key in stages[0]}
+        return {"ms": ms, "stage_ms": st, "e_mean": e_means[-1],
+                "energy": energy.detach().cpu().numpy().copy()}
+
+    runs = {}
+    if args.precision in ("fp64", "both"):
+        runs["fp64"] = run_path(qf.FP64)
+    if args.precision in ("fp32", "both"):
+        runs["fp32"] = run_path(qf.FP32)
+    d_mean = d_space = None
+    if len(runs) == 2:
+        d_mean = abs(runs["fp32"]["e_mean"] - runs["fp64"]["e_mean"])
+        d_space = float(np.abs(runs["fp32"]["energy"] - runs["fp64"]["energy"]).max())
+    # the reported path: the mixed one when it holds |dE| < 1e-6 Eh against FP64
+    use = "fp32" if "fp32" in runs and (d_mean is None or (d_mean < 1e-6 and d_space < 1e-6)) \
+        else "fp64"
+    ms, st = runs[use]["ms"], runs[use]["stage_ms"]
+    peak = FP32_MFMA_PEAK_TFLOPS if use == "fp32" else FP64_MFMA_PEAK_TFLOPS
 
     # Roofline of the matrix-core GEMM kernel k_gemm_f64 over its ladder and
     # ring launches (six per step: two ladders, two Ga rings, two G22 rings):
@@ -113,13 +141,21 @@ def main():
     gemm_flops = 2 * f_ladder + 2 * f_ga + 2 * f_g22
     gemm_ms = st["ladder_h"] + st["ladder_yg"] + st["ring_gemm"]
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
-    roof = {"kernel": "k_gemm_f64", "scope": "ladder and ring launches, six per step",
-            "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
-            "traffic": gemm_traffic(), "flop_per_step": gemm_flops, "ms_per_step": gemm_ms}
-    ladder = {"kernel": "ladder_h", "tflops": f_ladder / (st["ladder_h"] * 1e-3) / 1e12,
-              "frac_fp64_mfma": f_ladder / (st["ladder_h"] * 1e-3) / 1e12
-              / FP64_MFMA_PEAK_TFLOPS}
+    roof = {"kernel": "k_gemm_f64" if use == "fp64" else "k_gemm_f32",
+            "scope": "ladder and ring launches, six per step",
+            "bound": "mfma", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": gemm_traffic() if use == "fp64" else None,
+            "flop_per_step": gemm_flops, "ms_per_step": gemm_ms}
+    modes = {}
+    for key, r in runs.items():
+        mms = r["stage_ms"]["ladder_h"] + r["stage_ms"]["ladder_yg"] + r["stage_ms"]["ring_gemm"]
+        modes[key] = {"value": 1e3 / r["ms"], "ms_per_step": r["ms"], "e_mean": r["e_mean"],
+                      "residual_gemm_tflops": gemm_flops / (mms * 1e-3) / 1e12,
+                      "stage_ms": r["stage_ms"]}
+    if d_mean is not None:
+        modes["abs_dE_mean"] = d_mean
+        modes["abs_dE_max_space"] = d_space
     dominant = max(st, key=st.get)
 
     cpu = None
@@ -127,7 +163,7 @@ def main():
         cpu = cpu_baseline(h, eri, o, spaces, args.cpu_sample_spaces, K)
 
     out = {
-        "metric": "QFlow macro-iterations/s (114 orbitals, FP64 path)",
+        "metric": "QFlow macro-iterations/s at 114 orbitals, mixed vs FP64, |dE| < 1e-6 Eh",
         "value": 1e3 / ms,
         "unit": "macro-iterations/s",
         "n_gpus": 1,
@@ -137,15 +173,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if use == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {n} orbitals ({o} occ, {v} virt), K={K} "
                                f"({no},{nv}) active spaces, MP2 start",
                    "n_orb": n, "n_occ": o, "K": K, "space": [no, nv],
-                   "e_ref": e_ref, "e_mean_last": e_means[-1]},
+                   "precision": ("FP32 ladder and ring products with FP64 sums; FP64 "
+                                 "elsewhere") if use == "fp32" else "FP64",
+                   "e_ref": e_ref, "e_mean_last": runs[use]["e_mean"]},
+        "modes": modes,
         "stage_ms": st,
         "dominant_stage": dominant,
-        "ladder": ladder,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -112,6 +112,118 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
     }
 }
 
+// FP32 operands: v_mfma_f32_16x16x4f32 has the same A/B lane layout, and
+// lane l holds D[4*(l/16) + i][l%16] in element i.  Products are summed in
+// FP32 over 64 consecutive k (four K steps), then added into FP64
+// accumulators, so the rounding of long sums stays at the FP64 level.
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int kFlush = 4;   // K steps per FP32 partial sum
+
+template <int TM, int TN>
+__global__ __launch_bounds__(256, 2) void k_gemm_f32(const float* __restrict__ A,
+                                                     const float* __restrict__ B,
+                                                     double* __restrict__ C, int M, int N, int K,
+                                                     int kchunk, int to_slices, double scale) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int LA = BM * kBK / 256, LB = BN * kBK / 256;
+  __shared__ float As[BM * kLD];
+  __shared__ float Bs[BN * kLD];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
+  const int ks = blockIdx.z * kchunk;
+  const int ke = min(K, ks + kchunk);
+  float ra[LA], rb[LB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int gm = m0 + e / kBK, gk = k0 + e % kBK;
+      ra[i] = (gm < M && gk < ke) ? A[(size_t)gm * K + gk] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int gn = n0 + e / kBK, gk = k0 + e % kBK;
+      rb[i] = (gn < N && gk < ke) ? B[(size_t)gn * K + gk] : 0.f;
+    }
+  };
+  f4 acc[TM][TN];
+  d4 acc64[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      acc64[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  auto flush = [&]() {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+        acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+  if (ks < ke) load(ks);
+  int step = 0;
+  for (int k0 = ks; k0 < ke; k0 += kBK) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      As[(e / kBK) * kLD + e % kBK] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      Bs[(e / kBK) * kLD + e % kBK] = rb[i];
+    }
+    __syncthreads();
+    if (k0 + kBK < ke) load(k0 + kBK);
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += 4) {
+      float a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        a[i] = As[(wm * 16 * TM + i * 16 + lane % 16) * kLD + kk + lane / 16];
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        b[j] = Bs[(wn * 16 * TN + j * 16 + lane % 16) * kLD + kk + lane / 16];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (++step == kFlush) {
+      flush();
+      step = 0;
+    }
+    __syncthreads();
+  }
+  flush();
+  double* out = to_slices ? C + (size_t)blockIdx.z * M * N : C;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + wn * 16 * TN + j * 16 + lane % 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 16 * TM + i * 16 + 4 * (lane / 16) + r;
+        if (row < M && col < N) out[(size_t)row * N + col] = scale * acc64[i][j][r];
+      }
+    }
+}
+
+__global__ void k_cvt_f32(const double* __restrict__ src, float* __restrict__ dst, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
 __global__ __launch_bounds__(256) void k_sum_slices(const double* __restrict__ part, int splits,
                                                     size_t count, double* C) {
   const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -121,8 +233,8 @@ __global__ __launch_bounds__(256) void k_sum_slices(const double* __restrict__ p
   C[e] = s;
 }
 
-template <int TM, int TN>
-void launch_tiles(const double* A, const double* B, double* C, double* part, size_t part_cap,
+template <int TM, int TN, class T>
+void launch_tiles(const T* A, const T* B, double* C, double* part, size_t part_cap,
                   int M, int N, int K, double scale, hipStream_t st) {
   constexpr int BM = 32 * TM, BN = 32 * TN;
   const int tiles_n = (N + BN - 1) / BN, tiles_m = (M + BM - 1) / BM;
@@ -144,25 +256,52 @@ void launch_tiles(const double* A, const double* B, double* C, double* part, siz
   splits = (K + kchunk - 1) / kchunk;
   if (splits <= 1) {
     dim3 grid(tiles_n, tiles_m, 1);
-    k_gemm_f64<TM, TN><<<grid, 256, 0, st>>>(A, B, C, M, N, K, K > 0 ? K : kBK, 0, scale);
+    if constexpr (sizeof(T) == 8)
+      k_gemm_f64<TM, TN><<<grid, 256, 0, st>>>(A, B, C, M, N, K, K > 0 ? K : kBK, 0, scale);
+    else
+      k_gemm_f32<TM, TN><<<grid, 256, 0, st>>>(A, B, C, M, N, K, K > 0 ? K : kBK, 0, scale);
     return;
   }
   dim3 grid(tiles_n, tiles_m, splits);
-  k_gemm_f64<TM, TN><<<grid, 256, 0, st>>>(A, B, part, M, N, K, kchunk, 1, scale);
+  if constexpr (sizeof(T) == 8)
+    k_gemm_f64<TM, TN><<<grid, 256, 0, st>>>(A, B, part, M, N, K, kchunk, 1, scale);
+  else
+    k_gemm_f32<TM, TN><<<grid, 256, 0, st>>>(A, B, part, M, N, K, kchunk, 1, scale);
   k_sum_slices<<<grid_for(mn), kBlock, 0, st>>>(part, splits, mn, C);
+}
+
+template <class T>
+void launch_gemm(const T* A, const T* B, double* C, int M, int N, int K, double scale,
+                 double* part, size_t part_cap, hipStream_t st) {
+  if (M <= 0 || N <= 0) return;
+  // 128 x 96 tiles when they pad N less than 128 x 128 tiles do
+  const long pad4 = (long)((N + 127) / 128) * 128, pad3 = (long)((N + 95) / 96) * 96;
+  // (FP32 operands always take 128 x 96: the wider tile does not fit the
+  // registers with its FP64 accumulators)
+  if constexpr (sizeof(T) == 4) {
+    launch_tiles<4, 3>(A, B, C, part, part_cap, M, N, K, scale, st);
+  } else {
+    if (pad3 < pad4)
+      launch_tiles<4, 3>(A, B, C, part, part_cap, M, N, K, scale, st);
+    else
+      launch_tiles<4, 4>(A, B, C, part, part_cap, M, N, K, scale, st);
+  }
 }
 
 }  // namespace
 
 void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int N, int K,
                         double scale, double* part, size_t part_cap, hipStream_t st) {
-  if (M <= 0 || N <= 0) return;
-  // 128 x 96 tiles when they pad N less than 128 x 128 tiles do
-  const long pad4 = (long)((N + 127) / 128) * 128, pad3 = (long)((N + 95) / 96) * 96;
-  if (pad3 < pad4)
-    launch_tiles<4, 3>(A, B, C, part, part_cap, M, N, K, scale, st);
-  else
-    launch_tiles<4, 4>(A, B, C, part, part_cap, M, N, K, scale, st);
+  launch_gemm(A, B, C, M, N, K, scale, part, part_cap, st);
+}
+
+void launch_gemm_nt_f32(const float* A, const float* B, double* C, int M, int N, int K,
+                        double scale, double* part, size_t part_cap, hipStream_t st) {
+  launch_gemm(A, B, C, M, N, K, scale, part, part_cap, st);
+}
+
+void launch_cvt_f32(const double* src, float* dst, size_t count, hipStream_t st) {
+  k_cvt_f32<<<grid_for(count, kBlock, 65536), kBlock, 0, st>>>(src, dst, count);
 }
 
 }  // namespace qf

@@ -156,11 +156,12 @@ __global__ void k_pack_t2T(const double* __restrict__ t2, int o, int v, double* 
 // One workgroup per (p,q): the row U[p][q][:][:] (contiguous), and, for
 // p <= q, its virtual-virtual part in ladder layout (row tri_row(p,q)) when
 // wv is given.
+template <class WT>
 __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restrict__ g,
                                                          const double* __restrict__ t2,
                                                          const double* __restrict__ P,
                                                          const double* __restrict__ Q, int n,
-                                                         int o, double* U, double* wv) {
+                                                         int o, double* U, WT* wv) {
   __shared__ double tpq[64 * 64];
   const int v = n - o;
   const int p = blockIdx.x / n, q = blockIdx.x % n;
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restric
     }
     U[row + e] = x;
     if (wv && !or_ && !os && p <= q)
-      wv[tri_row(p, q, n) * v * v + (size_t)(r - o) * v + (s_ - o)] = x;
+      wv[tri_row(p, q, n) * v * v + (size_t)(r - o) * v + (s_ - o)] = (WT)x;
   }
 }
 
@@ -349,8 +350,8 @@ __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ energ
 // K index of the ring contractions: k = u * v + (t - o), u occupied, t virtual.
 // Aa[(a,b)][k]      = 2 X[a,u,b,t] - X[a,u,t,b],  Aa[(a,b)][ov + k] = -X[a,u,b,t]
 // A22[(a,b)][k]     = X[a,u,t,b]
-__global__ void k_pack_ring_A(const double* __restrict__ X, int n, int o, double* Aa,
-                              double* A22) {
+template <class T>
+__global__ void k_pack_ring_A(const double* __restrict__ X, int n, int o, T* Aa, T* A22) {
   const int v = n - o;
   const size_t ov = (size_t)o * v, rows = (size_t)n * n;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < rows * ov;
@@ -359,16 +360,16 @@ __global__ void k_pack_ring_A(const double* __restrict__ X, int n, int o, double
     const int a = (int)(row / n), b = (int)(row % n), u = (int)(k / v), t = o + (int)(k % v);
     const double x1 = X[(((size_t)a * n + u) * n + b) * n + t];
     const double x2 = X[(((size_t)a * n + u) * n + t) * n + b];
-    Aa[row * 2 * ov + k] = 2.0 * x1 - x2;
-    Aa[row * 2 * ov + ov + k] = -x1;
-    A22[row * ov + k] = x2;
+    Aa[row * 2 * ov + k] = (T)(2.0 * x1 - x2);
+    Aa[row * 2 * ov + ov + k] = (T)(-x1);
+    A22[row * ov + k] = (T)x2;
   }
 }
 
 // Ta[(g,d)][k] = t2[u,d,t,g], Ta[(g,d)][ov + k] = t2[d,u,t,g], T22[(g,d)][k] = t2[d,u,t,g]
 // with row (g,d) = (g - o) * o + d.
-__global__ void k_pack_ring_T(const double* __restrict__ t2, int o, int v, double* Ta,
-                              double* T22) {
+template <class T>
+__global__ void k_pack_ring_T(const double* __restrict__ t2, int o, int v, T* Ta, T* T22) {
   const size_t ov = (size_t)o * v;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ov * ov;
        idx += (size_t)gridDim.x * blockDim.x) {
@@ -376,15 +377,12 @@ __global__ void k_pack_ring_T(const double* __restrict__ t2, int o, int v, doubl
     const int g = (int)(row / o), d = (int)(row % o), u = (int)(k / v), t = (int)(k % v);
     const double s1 = t2[(((size_t)u * o + d) * v + t) * v + g];
     const double s2 = t2[(((size_t)d * o + u) * v + t) * v + g];
-    Ta[row * 2 * ov + k] = s1;
-    Ta[row * 2 * ov + ov + k] = s2;
-    T22[row * ov + k] = s2;
+    Ta[row * 2 * ov + k] = (T)s1;
+    Ta[row * 2 * ov + ov + k] = (T)s2;
+    T22[row * ov + k] = (T)s2;
   }
 }
 
-// J1[p][q] = - sum_{t,u occ, w virt} X[w,p,t,u] (2 t2[t,u,w,q] - t2[t,u,q,w])
-// J2[q][p] = - sum_{t,u occ, w virt} t2[t,u,w,p] (2 X[t,u,w,q] - X[t,u,q,w])
-// (p virtual in J2, q virtual in J1; the other index runs over all orbitals)
 // Z(p,q,r,s) = sum_t sigma1(p,t) X(t,q,r,s): the one-body part of sigma
 // (t1) applied to the first index of a two-body operator.  With X Hermitian
 // and pair symmetric and sigma1 anti-Hermitian, the four terms of
@@ -533,7 +531,7 @@ void launch_mp2(const double* f, const double* V, int n, int o, double* t1, doub
 
 void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12, double* t2T,
                    bool pack_t2, double* P, double* Q, double* part, size_t part_cap, double* U,
-                   double* wv, hipStream_t st) {
+                   double* wv, float* wv32, hipStream_t st) {
   const int v = n - o;
   const size_t nv = (size_t)n * v, ov2 = (size_t)o * o * v, ovv = (size_t)o * v * v;
   const size_t o2v2 = (size_t)o * ovv;
@@ -553,7 +551,10 @@ void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12,
                        part_cap, st);
   launch_gemm_nt_f64(Ao, Tq, Q, n, (int)ovv, o, -1.0, part, part_cap, st);
   launch_gemm_nt_f64(Ao, Tp, Q + (size_t)n * ovv, n, (int)ovv, o, -1.0, part, part_cap, st);
-  if (U) k_sigma2_assemble<<<n * n, kBlock, 0, st>>>(g, t2, P, Q, n, o, U, wv);
+  if (U && wv32)
+    k_sigma2_assemble<<<n * n, kBlock, 0, st>>>(g, t2, P, Q, n, o, U, wv32);
+  else if (U)
+    k_sigma2_assemble<<<n * n, kBlock, 0, st>>>(g, t2, P, Q, n, o, U, wv);
 }
 
 void launch_yg1(const double* f, const double* t1, const double* t2, int n, int o, double* y1,
@@ -566,7 +567,17 @@ void launch_pack_ring_A(const double* X, int n, int o, double* Aa, double* A22, 
   k_pack_ring_A<<<grid_for(work, kBlock, 65536), kBlock, 0, st>>>(X, n, o, Aa, A22);
 }
 
+void launch_pack_ring_A(const double* X, int n, int o, float* Aa, float* A22, hipStream_t st) {
+  const size_t work = (size_t)n * n * o * (n - o);
+  k_pack_ring_A<<<grid_for(work, kBlock, 65536), kBlock, 0, st>>>(X, n, o, Aa, A22);
+}
+
 void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22, hipStream_t st) {
+  const size_t ov = (size_t)o * v;
+  k_pack_ring_T<<<grid_for(ov * ov, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, Ta, T22);
+}
+
+void launch_pack_ring_T(const double* t2, int o, int v, float* Ta, float* T22, hipStream_t st) {
   const size_t ov = (size_t)o * v;
   k_pack_ring_T<<<grid_for(ov * ov, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, Ta, T22);
 }

@@ -23,13 +23,14 @@ void launch_mp2(const double* f, const double* V, int n, int o, double* t1, doub
 
 // intermediates of one amplitude set
 // U = [G, sigma_2]_2 (dense n^4) for a Hermitian one-body G, and its
-// virtual-virtual rows in ladder layout into wv when wv is not NULL
-// (k_prep.hip).  With U NULL only the compact parts P and Q are formed
-// (read through Sigma2Lazy).  Scratch: A12 2*n*v + n*o, t2T 3*o*o*v*v (packed from t2
-// here when pack_t2), P 4*n*o*o*v and Q 2*n*o*v*v doubles.
+// virtual-virtual rows in ladder layout into wv (FP64) or wv32 (FP32) when
+// one is given (k_prep.hip).  With U NULL only the compact parts P and Q are
+// formed (read through Sigma2Lazy).  Scratch: A12 2*n*v + n*o, t2T
+// 3*o*o*v*v (packed from t2 here when pack_t2), P 4*n*o*o*v and Q 2*n*o*v*v
+// doubles.
 void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12, double* t2T,
                    bool pack_t2, double* P, double* Q, double* part, size_t part_cap, double* U,
-                   double* wv, hipStream_t st);
+                   double* wv, float* wv32, hipStream_t st);
 // y1 = one-body part of [F_N, sigma], scal[2] = its scalar part
 void launch_yg1(const double* f, const double* t1, const double* t2, int n, int o, double* y1,
                 double* scal, hipStream_t st);
@@ -37,6 +38,9 @@ void launch_fill(double* x, size_t count, double value, hipStream_t st);
 // ring intermediates (layouts in qflow_eval.h, DenseOp)
 void launch_pack_ring_A(const double* X, int n, int o, double* Aa, double* A22, hipStream_t st);
 void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22, hipStream_t st);
+// the same operands rounded to FP32 (mixed-precision contractions)
+void launch_pack_ring_A(const double* X, int n, int o, float* Aa, float* A22, hipStream_t st);
+void launch_pack_ring_T(const double* t2, int o, int v, float* Ta, float* T22, hipStream_t st);
 // Z = sigma1 X over the first index (k_prep.hip, k_sigma1_x); n^4 doubles
 void launch_sigma1_x(const double* X, const double* t1, int n, int o, double* Z, hipStream_t st);
 // operands of the occupied-occupied ladder Lo (k_prep.hip)
@@ -53,6 +57,11 @@ void launch_pack_j_B(const double* t2, int o, int v, double* B1, double* B2, hip
 constexpr int kMaxSplits = 128;
 void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int N, int K,
                         double scale, double* part, size_t part_cap, hipStream_t st);
+// The same with FP32 operands on the FP32 matrix cores: products summed in
+// FP32 over 64 consecutive k, those partial sums accumulated in FP64.
+void launch_gemm_nt_f32(const float* A, const float* B, double* C, int M, int N, int K,
+                        double scale, double* part, size_t part_cap, hipStream_t st);
+void launch_cvt_f32(const double* src, float* dst, size_t count, hipStream_t st);
 
 // residual of Hbar(sigma)
 struct RingOps {            // global intermediates of H_N and of Yg

@@ -56,6 +56,9 @@ struct qflow_ctx {
   // and U_Y = [y1, sigma_2]_2
   DevBuf a12, t2T, sp, sq, sp_f;   // sp_f keeps the [F, sigma_2] parts
   DevBuf c1h, c1y;   // one-body parts of [H_N, sigma] and [Yg, sigma], [n][n]
+  // FP32 operands of the mixed-precision ladder and ring products
+  DevBuf w32, wy32, t2_32, ra32_h, r22_32_h, ra32_y, r22_32_y, rta32, rt22_32;
+  bool h32_ready = false;   // w32, ra32_h, r22_32_h hold the loaded H_N
   // occupied-occupied ladders: packed t2 [v*v][o*o], X_oooo of H (constant)
   // and Yg [o*o][o*o], outputs Lo of H and Yg [v*v][o*o]
   DevBuf lo_t, lo_xh, lo_xy, lo_h, lo_y;
@@ -223,45 +226,104 @@ qf::RingOps rings_of(qflow_ctx* ctx) {
 
 // Yg = [F,sigma], the ladder intermediates L = W t2^T, LY = WY t2^T and the
 // ring intermediates (Ga, G22 by matrix cores; J1, J2) of H_N and Yg
+// FP32 copies of the ladder and ring GEMM operands for the mixed-precision
+// contractions; those of H_N are converted once per integral load.
+int ensure_mixed(qflow_ctx* ctx) {
+  const int n = ctx->n, o = ctx->o, v = ctx->v;
+  const size_t n2 = (size_t)n * n, n2p = (size_t)n * (n + 1) / 2, ov = (size_t)o * v;
+  QF_TRY(ensure(ctx, ctx->w32, sizeof(float) * n2p * v * v));
+  QF_TRY(ensure(ctx, ctx->wy32, sizeof(float) * n2p * v * v));
+  QF_TRY(ensure(ctx, ctx->t2_32, sizeof(float) * ov * ov));
+  QF_TRY(ensure(ctx, ctx->ra32_h, sizeof(float) * n2 * 2 * ov));
+  QF_TRY(ensure(ctx, ctx->r22_32_h, sizeof(float) * n2 * ov));
+  QF_TRY(ensure(ctx, ctx->ra32_y, sizeof(float) * n2 * 2 * ov));
+  QF_TRY(ensure(ctx, ctx->r22_32_y, sizeof(float) * n2 * ov));
+  QF_TRY(ensure(ctx, ctx->rta32, sizeof(float) * ov * 2 * ov));
+  QF_TRY(ensure(ctx, ctx->rt22_32, sizeof(float) * ov * ov));
+  if (!ctx->h32_ready) {
+    qf::launch_cvt_f32(P<double>(ctx->W), P<float>(ctx->w32), n2p * v * v, ctx->stream);
+    qf::launch_pack_ring_A(P<double>(ctx->V), n, o, P<float>(ctx->ra32_h), P<float>(ctx->r22_32_h),
+                           ctx->stream);
+    QF_HIP(hipGetLastError());
+    ctx->h32_ready = true;
+  }
+  return QFLOW_OK;
+}
+
+// Yg = [F,sigma], the ladder intermediates L = W t2^T, LY = WY t2^T and the
+// ring intermediates (Ga, G22 by matrix cores; J1, J2) of H_N and Yg.  With
+// QFLOW_FP32 the ladder and ring products (the o^2 v^4 and o^3 v^3
+// contractions) take FP32 operands on the FP32 matrix cores, FP64 sums.
 int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
-  if (precision != QFLOW_FP64)
-    return fail(ctx, QFLOW_E_UNSUPPORTED, "only QFLOW_FP64 contractions are available");
+  if (precision != QFLOW_FP64 && precision != QFLOW_FP32)
+    return fail(ctx, QFLOW_E_UNSUPPORTED, "precision must be QFLOW_FP64 or QFLOW_FP32");
+  const bool mixed = precision == QFLOW_FP32;
+  if (mixed) QF_TRY(ensure_mixed(ctx));
   const int n = ctx->n, o = ctx->o, v = ctx->v;
   const size_t n2 = (size_t)n * n, ov = (size_t)o * v;
   double* part = P<double>(ctx->gpart);
   const size_t pcap = ctx->gpart.bytes / sizeof(double);
+  hipStream_t st = ctx->stream;
   // Yg = [F_N, sigma]: one-body and scalar, two-body (+ its ladder slab), and
   // the compact parts of [y1, sigma_2]_2 (the one-body part of Yg against
   // sigma's two-body), which stay in sp / sq for the lookups
-  qf::launch_yg1(P<double>(ctx->f), t1, t2, n, o, P<double>(ctx->y1), P<double>(ctx->scal),
-                 ctx->stream);
+  qf::launch_yg1(P<double>(ctx->f), t1, t2, n, o, P<double>(ctx->y1), P<double>(ctx->scal), st);
   qf::launch_sigma2(P<double>(ctx->f), t2, n, o, P<double>(ctx->a12), P<double>(ctx->t2T), true,
                     P<double>(ctx->sp_f), P<double>(ctx->sq), part, pcap, P<double>(ctx->y2),
-                    P<double>(ctx->wy), ctx->stream);
+                    mixed ? nullptr : P<double>(ctx->wy), mixed ? P<float>(ctx->wy32) : nullptr,
+                    st);
   qf::launch_sigma2(P<double>(ctx->y1), t2, n, o, P<double>(ctx->a12), P<double>(ctx->t2T),
                     false, P<double>(ctx->sp), P<double>(ctx->sq), part, pcap, nullptr, nullptr,
-                    ctx->stream);
-  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
+                    nullptr, st);
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[1], st));
   const int npair = n * (n + 1) / 2;   // ladder rows p <= q
-  qf::launch_gemm_nt_f64(P<double>(ctx->W), t2, P<double>(ctx->L), npair, o * o, v * v, 1.0, part,
-                         pcap, ctx->stream);
-  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
-  qf::launch_gemm_nt_f64(P<double>(ctx->wy), t2, P<double>(ctx->LY), npair, o * o, v * v, 1.0,
-                         part, pcap, ctx->stream);
-  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[3], ctx->stream));
-  hipStream_t st = ctx->stream;
-  qf::launch_pack_ring_T(t2, o, v, P<double>(ctx->rta), P<double>(ctx->rt22), st);
-  qf::launch_pack_ring_A(P<double>(ctx->y2), n, o, P<double>(ctx->ra_y), P<double>(ctx->r22_y), st);
-  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
-  qf::launch_gemm_nt_f64(P<double>(ctx->ra_h), P<double>(ctx->rta), P<double>(ctx->ga_h),
-                         (int)n2, (int)ov, (int)(2 * ov), 1.0, part, pcap, st);
-  qf::launch_gemm_nt_f64(P<double>(ctx->r22_h), P<double>(ctx->rt22), P<double>(ctx->g22_h),
-                         (int)n2, (int)ov, (int)ov, 1.0, part, pcap, st);
-  qf::launch_gemm_nt_f64(P<double>(ctx->ra_y), P<double>(ctx->rta), P<double>(ctx->ga_y),
-                         (int)n2, (int)ov, (int)(2 * ov), 1.0, part, pcap, st);
-  qf::launch_gemm_nt_f64(P<double>(ctx->r22_y), P<double>(ctx->rt22), P<double>(ctx->g22_y),
-                         (int)n2, (int)ov, (int)ov, 1.0, part, pcap, st);
-  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
+  if (mixed) {
+    qf::launch_cvt_f32(t2, P<float>(ctx->t2_32), ov * ov, st);
+    qf::launch_gemm_nt_f32(P<float>(ctx->w32), P<float>(ctx->t2_32), P<double>(ctx->L), npair,
+                           o * o, v * v, 1.0, part, pcap, st);
+    if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], st));
+    qf::launch_gemm_nt_f32(P<float>(ctx->wy32), P<float>(ctx->t2_32), P<double>(ctx->LY), npair,
+                           o * o, v * v, 1.0, part, pcap, st);
+  } else {
+    qf::launch_gemm_nt_f64(P<double>(ctx->W), t2, P<double>(ctx->L), npair, o * o, v * v, 1.0,
+                           part, pcap, st);
+    if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], st));
+    qf::launch_gemm_nt_f64(P<double>(ctx->wy), t2, P<double>(ctx->LY), npair, o * o, v * v, 1.0,
+                           part, pcap, st);
+  }
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[3], st));
+  if (mixed) {
+    qf::launch_pack_ring_T(t2, o, v, P<float>(ctx->rta32), P<float>(ctx->rt22_32), st);
+    qf::launch_pack_ring_A(P<double>(ctx->y2), n, o, P<float>(ctx->ra32_y),
+                           P<float>(ctx->r22_32_y), st);
+  } else {
+    qf::launch_pack_ring_T(t2, o, v, P<double>(ctx->rta), P<double>(ctx->rt22), st);
+    qf::launch_pack_ring_A(P<double>(ctx->y2), n, o, P<double>(ctx->ra_y), P<double>(ctx->r22_y),
+                           st);
+  }
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[4], st));
+  if (mixed) {
+    const float* ta = P<float>(ctx->rta32);
+    const float* t22 = P<float>(ctx->rt22_32);
+    qf::launch_gemm_nt_f32(P<float>(ctx->ra32_h), ta, P<double>(ctx->ga_h), (int)n2, (int)ov,
+                           (int)(2 * ov), 1.0, part, pcap, st);
+    qf::launch_gemm_nt_f32(P<float>(ctx->r22_32_h), t22, P<double>(ctx->g22_h), (int)n2, (int)ov,
+                           (int)ov, 1.0, part, pcap, st);
+    qf::launch_gemm_nt_f32(P<float>(ctx->ra32_y), ta, P<double>(ctx->ga_y), (int)n2, (int)ov,
+                           (int)(2 * ov), 1.0, part, pcap, st);
+    qf::launch_gemm_nt_f32(P<float>(ctx->r22_32_y), t22, P<double>(ctx->g22_y), (int)n2, (int)ov,
+                           (int)ov, 1.0, part, pcap, st);
+  } else {
+    qf::launch_gemm_nt_f64(P<double>(ctx->ra_h), P<double>(ctx->rta), P<double>(ctx->ga_h),
+                           (int)n2, (int)ov, (int)(2 * ov), 1.0, part, pcap, st);
+    qf::launch_gemm_nt_f64(P<double>(ctx->r22_h), P<double>(ctx->rt22), P<double>(ctx->g22_h),
+                           (int)n2, (int)ov, (int)ov, 1.0, part, pcap, st);
+    qf::launch_gemm_nt_f64(P<double>(ctx->ra_y), P<double>(ctx->rta), P<double>(ctx->ga_y),
+                           (int)n2, (int)ov, (int)(2 * ov), 1.0, part, pcap, st);
+    qf::launch_gemm_nt_f64(P<double>(ctx->r22_y), P<double>(ctx->rt22), P<double>(ctx->g22_y),
+                           (int)n2, (int)ov, (int)ov, 1.0, part, pcap, st);
+  }
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[5], st));
   // one-body ring terms J1, J2 of H_N and Yg
   const size_t kj = (size_t)o * o * v;
   double* b1 = P<double>(ctx->jb);
@@ -354,7 +416,8 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->sq,       &ctx->sp_f,
                     &ctx->c1h,
                     &ctx->c1y,    &ctx->lo_t,     &ctx->lo_xh,  &ctx->lo_xy,    &ctx->lo_h,
-                    &ctx->lo_y,
+                    &ctx->lo_y,   &ctx->w32,      &ctx->wy32,   &ctx->t2_32,    &ctx->ra32_h,
+                    &ctx->r22_32_h, &ctx->ra32_y, &ctx->r22_32_y, &ctx->rta32,  &ctx->rt22_32,
                     &ctx->f,      &ctx->V,        &ctx->W,      &ctx->y1,       &ctx->y2,
                     &ctx->wy,     &ctx->L,        &ctx->LY,     &ctx->scal,     &ctx->r1,
                     &ctx->r2,     &ctx->t1n,      &ctx->t2n,    &ctx->heff,     &ctx->heff_off,
@@ -467,6 +530,7 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   double sc[8] = {0, 0, 0, e, 0, 0, 0, 0};
   QF_HIP(hipMemcpy(ctx->scal.p, sc, sizeof(sc), hipMemcpyHostToDevice));
   ctx->loaded = true;
+  ctx->h32_ready = false;
   ctx->last_spaces.clear();
   return QFLOW_OK;
 }

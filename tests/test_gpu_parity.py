@@ -163,7 +163,7 @@ def test_solve_matches_dense_eigensolver(n, o, seed, K, start):
         assert np.abs(blk[nt1:] - s["t2"].reshape(-1)).max() < 1e-8
 
 
-def _flow_parity(n, o, seed, K, iters, start, flags=0):
+def _flow_parity(n, o, seed, K, iters, start, flags=0, tol_e=1e-9, tol_t=1e-8):
     import paper_2606_04186_amd as qf
     h, eri = problem(n, o, seed)
     pb = qflow.Problem(h, eri, o)
@@ -182,11 +182,12 @@ def _flow_parity(n, o, seed, K, iters, start, flags=0):
     for it in range(iters):
         em, _ = ctx.flow_step(sp, d1, d2, g1, g2, energy, flags)
         t1, t2, E, Em, _s = qflow.flow_step(
-            pb, t1, t2, lists, o1, o2, unowned="frozen" if flags else "residual")
-        assert abs(em - Em) < 1e-9, it
-        assert np.abs(host(energy) - E).max() < 1e-9, it
-        assert np.abs(host(g1) - t1).max() < 1e-8, it
-        assert np.abs(host(g2) - t2).max() < 1e-8, it
+            pb, t1, t2, lists, o1, o2,
+            unowned="frozen" if flags & qf.UNOWNED_FROZEN else "residual")
+        assert abs(em - Em) < tol_e, it
+        assert np.abs(host(energy) - E).max() < tol_e, it
+        assert np.abs(host(g1) - t1).max() < tol_t, it
+        assert np.abs(host(g2) - t2).max() < tol_t, it
 
 
 def test_flow_step_matches_oracle_eight_orbitals():
@@ -198,6 +199,41 @@ def test_flow_step_matches_oracle_partial_coverage():
     """Partial coverage: unowned amplitudes take the residual step."""
     _need_gpu()
     _flow_parity(24, 4, 132, 12, 2, "mp2")
+
+
+@pytest.mark.parametrize("n,o,seed", [(24, 4, 103), (40, 5, 104)])
+def test_residual_fp32_contractions(n, o, seed):
+    """Mixed precision: ladder and ring products with FP32 operands (FP64 sums)
+    against the FP64 oracle."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    v = n - o
+    t1, t2 = synth.random_amplitudes(o, v, seed + 7, scale=0.05)
+    ctx = context(h, eri, o)
+    r1 = torch.zeros(o, v, dtype=torch.float64, device="cuda")
+    r2 = torch.zeros(o, o, v, v, dtype=torch.float64, device="cuda")
+    e0 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.residual(dev(t1), dev(t2), r1, r2, e0, qf.FP32)
+    torch.cuda.synchronize()
+    R1, R2, E0 = qflow.residual(pb, t1, t2)
+    # FP32 operands carry a relative rounding of 6e-8 into each product
+    scale = max(np.abs(R2).max(), np.abs(R1).max())
+    assert np.abs(host(r1) - R1).max() < 1e-6 * scale
+    assert np.abs(host(r2) - R2).max() < 1e-6 * scale
+    assert abs(host(e0)[0] - E0) < 1e-7 * max(1.0, abs(E0))
+    # the FP64 path on the same context is unaffected by the FP32 copies
+    ctx.residual(dev(t1), dev(t2), r1, r2, e0)
+    torch.cuda.synchronize()
+    assert np.abs(host(r2) - R2).max() < 1e-11
+
+
+def test_flow_step_fp32_contractions_partial_coverage():
+    """Mixed precision flow: energies within 1e-6 Eh of the FP64 oracle."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    _flow_parity(24, 4, 132, 12, 2, "mp2", flags=qf.FP32, tol_e=1e-6, tol_t=1e-6)
 
 
 def test_flow_step_frozen_unowned():
