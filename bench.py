@@ -8,13 +8,14 @@ and the pool update, on the 114-orbital workload (13 occupied, 101 virtual,
 integrals).  Inputs are resident in HBM before the timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4]
-                    [--precision both|fp64|fp32] [--no-cpu-baseline]
+                    [--precision all|fp64|fp32|bf16x3] [--no-cpu-baseline]
 
-By default both paths run from the same MP2 start: plain FP64, and the mixed
-one (the ladder and ring contractions with FP32 operands on the FP32 matrix
-cores, FP64 sums; everything else FP64).  `value` is the mixed path's rate when
-its mean and per-space energies stay within 1e-6 Eh of the FP64 path's,
-otherwise the FP64 rate; both are in `modes`.  Prints one JSON line.
+By default three paths run from the same MP2 start: plain FP64, and two mixed
+ones whose ladder and ring contractions take FP32 operands (FP32 matrix
+cores) or BF16x3 hi+lo operands (BF16 matrix cores), with FP64 sums and FP64
+everywhere else.  `value` is the rate of the fastest mixed path whose mean and
+per-space energies stay within 1e-6 Eh of the FP64 path's (the FP64 rate if
+none does); every path is in `modes`.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -32,6 +33,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # dense; BF16x3 spends three products per FP64-equivalent one
 
 
 def parse():
@@ -40,10 +42,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c4")
-    ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both",
-                    help="both: time the FP64 path and the mixed path (FP32 ladder and ring "
-                         "products, FP64 sums) from the same start and report the mixed one "
-                         "when its energies are within 1e-6 Eh of FP64")
+    ap.add_argument("--precision", choices=["all", "fp64", "fp32", "bf16x3"], default="all",
+                    help="all: time the FP64 path and both mixed paths (FP32 or BF16x3 ladder "
+                         "and ring products, FP64 sums) from the same start and report the "
+                         "fastest mixed one whose energies stay within 1e-6 Eh of FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-spaces", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -97,7 +99,7 @@ def main():
     def run_path(precision):
         """W untimed and K timed macro-iterations from the MP2 start."""
         ctx.mp2_guess(t1, t2)
-        tag = {qf.FP64: "fp64", qf.FP32: "fp32"}[precision]
+        tag = {qf.FP64: "fp64", qf.FP32: "fp32", qf.BF16X3: "bf16x3"}[precision]
         print(f"[bench] {tag}: warmup", file=sys.stderr, flush=True)
         for _ in range(args.warmup):
             ctx.flow_step(spaces, d1, d2, t1, t2, energy, precision)
@@ -117,19 +119,23 @@ def main():
                 "energy": energy.detach().cpu().numpy().copy()}
 
     runs = {}
-    if args.precision in ("fp64", "both"):
-        runs["fp64"] = run_path(qf.FP64)
-    if args.precision in ("fp32", "both"):
-        runs["fp32"] = run_path(qf.FP32)
-    d_mean = d_space = None
-    if len(runs) == 2:
-        d_mean = abs(runs["fp32"]["e_mean"] - runs["fp64"]["e_mean"])
-        d_space = float(np.abs(runs["fp32"]["energy"] - runs["fp64"]["energy"]).max())
-    # the reported path: the mixed one when it holds |dE| < 1e-6 Eh against FP64
-    use = "fp32" if "fp32" in runs and (d_mean is None or (d_mean < 1e-6 and d_space < 1e-6)) \
-        else "fp64"
+    for key, flag in (("fp64", qf.FP64), ("fp32", qf.FP32), ("bf16x3", qf.BF16X3)):
+        if args.precision in ("all", key):
+            runs[key] = run_path(flag)
+    dE = {}
+    if "fp64" in runs:
+        for key in ("fp32", "bf16x3"):
+            if key in runs:
+                dE[key] = (abs(runs[key]["e_mean"] - runs["fp64"]["e_mean"]),
+                           float(np.abs(runs[key]["energy"] - runs["fp64"]["energy"]).max()))
+    # the reported path: the fastest mixed one whose mean and per-space
+    # energies stay within 1e-6 Eh of the FP64 path (FP64 itself otherwise)
+    ok = [k for k in ("fp32", "bf16x3") if k in runs and
+          (k not in dE or (dE[k][0] < 1e-6 and dE[k][1] < 1e-6))]
+    use = min(ok, key=lambda k: runs[k]["ms"]) if ok else "fp64"
     ms, st = runs[use]["ms"], runs[use]["stage_ms"]
-    peak = FP32_MFMA_PEAK_TFLOPS if use == "fp32" else FP64_MFMA_PEAK_TFLOPS
+    peak = {"fp64": FP64_MFMA_PEAK_TFLOPS, "fp32": FP32_MFMA_PEAK_TFLOPS,
+            "bf16x3": BF16_MFMA_PEAK_TFLOPS / 3.0}[use]
 
     # Roofline of the matrix-core GEMM kernel k_gemm_f64 over its ladder and
     # ring launches (six per step: two ladders, two Ga rings, two G22 rings):
@@ -141,7 +147,7 @@ def main():
     gemm_flops = 2 * f_ladder + 2 * f_ga + 2 * f_g22
     gemm_ms = st["ladder_h"] + st["ladder_yg"] + st["ring_gemm"]
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
-    roof = {"kernel": "k_gemm_f64" if use == "fp64" else "k_gemm_f32",
+    roof = {"kernel": {"fp64": "k_gemm_f64", "fp32": "k_gemm_f32", "bf16x3": "k_gemm_bf16x3"}[use],
             "scope": "ladder and ring launches, six per step",
             "bound": "mfma", "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": achieved / peak,
@@ -153,9 +159,9 @@ def main():
         modes[key] = {"value": 1e3 / r["ms"], "ms_per_step": r["ms"], "e_mean": r["e_mean"],
                       "residual_gemm_tflops": gemm_flops / (mms * 1e-3) / 1e12,
                       "stage_ms": r["stage_ms"]}
-    if d_mean is not None:
-        modes["abs_dE_mean"] = d_mean
-        modes["abs_dE_max_space"] = d_space
+    for key, (dm, dsp) in dE.items():
+        modes[key]["abs_dE_mean"] = dm
+        modes[key]["abs_dE_max_space"] = dsp
     dominant = max(st, key=st.get)
 
     cpu = None
@@ -173,13 +179,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if use == "fp32" else "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16+f32+f64"}[use],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {n} orbitals ({o} occ, {v} virt), K={K} "
                                f"({no},{nv}) active spaces, MP2 start",
                    "n_orb": n, "n_occ": o, "K": K, "space": [no, nv],
-                   "precision": ("FP32 ladder and ring products with FP64 sums; FP64 "
-                                 "elsewhere") if use == "fp32" else "FP64",
+                   "precision": {"fp64": "FP64",
+                                 "fp32": "FP32 ladder and ring products with FP64 sums; FP64 "
+                                         "elsewhere",
+                                 "bf16x3": "BF16x3 (hi+lo) ladder and ring products, FP32 "
+                                           "partial sums, FP64 sums; FP64 elsewhere"}[use],
                    "e_ref": e_ref, "e_mean_last": runs[use]["e_mean"]},
         "modes": modes,
         "stage_ms": st,

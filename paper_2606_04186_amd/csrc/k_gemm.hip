@@ -224,6 +224,152 @@ __global__ void k_cvt_f32(const double* __restrict__ src, float* __restrict__ ds
     dst[i] = (float)src[i];
 }
 
+// BF16x3 operands: every value is split as x = hi + lo (both bf16; lo =
+// bf16(x - hi)), stored as two arrays of rows padded to a multiple of 32 k
+// with zeros.  v_mfma_f32_16x16x32_bf16 takes eight consecutive k per lane
+// (lane l: row l%16, k = 8*(l/16) .. +7) and returns D[4*(l/16) + i][l%16].
+// Each 32-k step adds lo*hi, hi*lo and hi*hi (the lo*lo term, 2^-16 of the
+// product, is dropped) in FP32; the FP32 sums go into FP64 every 64 k.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef short s8v __attribute__((ext_vector_type(8)));
+constexpr int kBK3 = 32;
+constexpr int kLD3 = kBK3 + 8;   // bf16 per LDS row: 80 bytes keeps a half-wave on distinct banks
+
+template <int TM, int TN>
+__global__ __launch_bounds__(256, 2) void k_gemm_bf16x3(
+    const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al, const __bf16* __restrict__ Bh,
+    const __bf16* __restrict__ Bl, double* __restrict__ C, int M, int N, int Kp, int kchunk,
+    int to_slices, double scale) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  // 16-byte groups (8 k) of a tile row-slice: BM*4 and BN*4 per step, per thread
+  constexpr int NGA = BM * kBK3 / 8, NGB = BN * kBK3 / 8;
+  constexpr int GA = (NGA + 255) / 256, GB = (NGB + 255) / 256;
+  __shared__ __attribute__((aligned(16))) __bf16 Ash[BM * kLD3];
+  __shared__ __attribute__((aligned(16))) __bf16 Asl[BM * kLD3];
+  __shared__ __attribute__((aligned(16))) __bf16 Bsh[BN * kLD3];
+  __shared__ __attribute__((aligned(16))) __bf16 Bsl[BN * kLD3];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
+  const int ks = blockIdx.z * kchunk;
+  const int ke = min(Kp, ks + kchunk);
+  s8v rah[GA], ral[GA], rbh[GB], rbl[GB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < GA; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int gm = m0 + e / 4, gk = k0 + 8 * (e % 4);
+      const bool ok = e < NGA && gm < M && gk < ke;
+      const size_t off = (size_t)gm * Kp + gk;
+      rah[i] = ok ? *reinterpret_cast<const s8v*>(Ah + off) : s8v(0);
+      ral[i] = ok ? *reinterpret_cast<const s8v*>(Al + off) : s8v(0);
+    }
+#pragma unroll
+    for (int i = 0; i < GB; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int gn = n0 + e / 4, gk = k0 + 8 * (e % 4);
+      const bool ok = e < NGB && gn < N && gk < ke;
+      const size_t off = (size_t)gn * Kp + gk;
+      rbh[i] = ok ? *reinterpret_cast<const s8v*>(Bh + off) : s8v(0);
+      rbl[i] = ok ? *reinterpret_cast<const s8v*>(Bl + off) : s8v(0);
+    }
+  };
+  f4 acc[TM][TN];
+  d4 acc64[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      acc64[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  auto flush = [&]() {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+        acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+  if (ks < ke) load(ks);
+  int step = 0;
+  for (int k0 = ks; k0 < ke; k0 += kBK3) {
+#pragma unroll
+    for (int i = 0; i < GA; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e >= NGA) break;
+      const int o = (e / 4) * kLD3 + 8 * (e % 4);
+      *reinterpret_cast<s8v*>(Ash + o) = rah[i];
+      *reinterpret_cast<s8v*>(Asl + o) = ral[i];
+    }
+#pragma unroll
+    for (int i = 0; i < GB; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e >= NGB) break;
+      const int o = (e / 4) * kLD3 + 8 * (e % 4);
+      *reinterpret_cast<s8v*>(Bsh + o) = rbh[i];
+      *reinterpret_cast<s8v*>(Bsl + o) = rbl[i];
+    }
+    __syncthreads();
+    if (k0 + kBK3 < ke) load(k0 + kBK3);
+    bf8 ah[TM], al[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int o = (wm * 16 * TM + i * 16 + lane % 16) * kLD3 + 8 * (lane / 16);
+      ah[i] = *reinterpret_cast<const bf8*>(Ash + o);
+      al[i] = *reinterpret_cast<const bf8*>(Asl + o);
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int o = (wn * 16 * TN + j * 16 + lane % 16) * kLD3 + 8 * (lane / 16);
+      const bf8 bh = *reinterpret_cast<const bf8*>(Bsh + o);
+      const bf8 bl = *reinterpret_cast<const bf8*>(Bsl + o);
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+      }
+    }
+    if (++step == 2) {
+      flush();
+      step = 0;
+    }
+    __syncthreads();
+  }
+  flush();
+  double* out = to_slices ? C + (size_t)blockIdx.z * M * N : C;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + wn * 16 * TN + j * 16 + lane % 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 16 * TM + i * 16 + 4 * (lane / 16) + r;
+        if (row < M && col < N) out[(size_t)row * N + col] = scale * acc64[i][j][r];
+      }
+    }
+}
+
+// hi/lo bf16 split of a row-major [rows][K] FP64 matrix into [rows][Kp]
+// (Kp >= K, zero padded).
+__global__ void k_split_bf16(const double* __restrict__ src, int rows, int K, int Kp,
+                             __bf16* __restrict__ hi, __bf16* __restrict__ lo) {
+  const size_t tot = (size_t)rows * Kp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / Kp;
+    const int k = (int)(e % Kp);
+    const double x = k < K ? src[r * K + k] : 0.0;
+    const __bf16 h = (__bf16)(float)x;
+    hi[e] = h;
+    lo[e] = (__bf16)(float)(x - (double)(float)h);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_sum_slices(const double* __restrict__ part, int splits,
                                                     size_t count, double* C) {
   const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -288,7 +434,51 @@ void launch_gemm(const T* A, const T* B, double* C, int M, int N, int K, double 
   }
 }
 
+template <int TM, int TN>
+void launch_tiles_bf16x3(const __bf16* Ah, const __bf16* Al, const __bf16* Bh, const __bf16* Bl,
+                         double* C, double* part, size_t part_cap, int M, int N, int Kp,
+                         double scale, hipStream_t st) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  const int tiles_n = (N + BN - 1) / BN, tiles_m = (M + BM - 1) / BM;
+  const long tiles = (long)tiles_n * tiles_m;
+  constexpr long kTarget = 4 * 256;
+  const size_t mn = (size_t)M * N;
+  int splits = 1;
+  if (tiles < kTarget && part != nullptr) {
+    splits = (int)((kTarget + tiles - 1) / tiles);
+    splits = std::min(splits, std::max(1, Kp / (8 * kBK3)));
+    splits = (int)std::min<size_t>((size_t)splits, part_cap / mn);
+    splits = std::min(splits, kMaxSplits);
+    splits = std::max(splits, 1);
+  }
+  int kchunk = (Kp + splits - 1) / splits;
+  kchunk = (kchunk + kBK3 - 1) / kBK3 * kBK3;
+  splits = (Kp + kchunk - 1) / kchunk;
+  if (splits <= 1) {
+    dim3 grid(tiles_n, tiles_m, 1);
+    k_gemm_bf16x3<TM, TN><<<grid, 256, 0, st>>>(Ah, Al, Bh, Bl, C, M, N, Kp,
+                                                Kp > 0 ? Kp : kBK3, 0, scale);
+    return;
+  }
+  dim3 grid(tiles_n, tiles_m, splits);
+  k_gemm_bf16x3<TM, TN><<<grid, 256, 0, st>>>(Ah, Al, Bh, Bl, part, M, N, Kp, kchunk, 1, scale);
+  k_sum_slices<<<grid_for(mn), kBlock, 0, st>>>(part, splits, mn, C);
+}
+
 }  // namespace
+
+void launch_gemm_nt_bf16x3(const __bf16* Ah, const __bf16* Al, const __bf16* Bh, const __bf16* Bl,
+                           double* C, int M, int N, int Kp, double scale, double* part,
+                           size_t part_cap, hipStream_t st) {
+  if (M <= 0 || N <= 0) return;
+  launch_tiles_bf16x3<4, 3>(Ah, Al, Bh, Bl, C, part, part_cap, M, N, Kp, scale, st);
+}
+
+void launch_split_bf16(const double* src, int rows, int K, int Kp, __bf16* hi, __bf16* lo,
+                       hipStream_t st) {
+  k_split_bf16<<<grid_for((size_t)rows * Kp, kBlock, 65536), kBlock, 0, st>>>(src, rows, K, Kp,
+                                                                              hi, lo);
+}
 
 void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int N, int K,
                         double scale, double* part, size_t part_cap, hipStream_t st) {

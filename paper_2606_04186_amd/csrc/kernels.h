@@ -62,6 +62,15 @@ void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int 
 void launch_gemm_nt_f32(const float* A, const float* B, double* C, int M, int N, int K,
                         double scale, double* part, size_t part_cap, hipStream_t st);
 void launch_cvt_f32(const double* src, float* dst, size_t count, hipStream_t st);
+// The same with BF16x3 operands (x = hi + lo, both bf16, rows of Kp = a
+// multiple of 32 k, zero padded) on the BF16 matrix cores: lo*hi + hi*lo +
+// hi*hi in FP32 per 32 k, FP64 sums every 64 k.
+inline int bf16_pad(int K) { return (K + 31) / 32 * 32; }
+void launch_gemm_nt_bf16x3(const __bf16* Ah, const __bf16* Al, const __bf16* Bh, const __bf16* Bl,
+                           double* C, int M, int N, int Kp, double scale, double* part,
+                           size_t part_cap, hipStream_t st);
+void launch_split_bf16(const double* src, int rows, int K, int Kp, __bf16* hi, __bf16* lo,
+                       hipStream_t st);
 
 // residual of Hbar(sigma)
 struct RingOps {            // global intermediates of H_N and of Yg

@@ -59,6 +59,9 @@ struct qflow_ctx {
   // FP32 operands of the mixed-precision ladder and ring products
   DevBuf w32, wy32, t2_32, ra32_h, r22_32_h, ra32_y, r22_32_y, rta32, rt22_32;
   bool h32_ready = false;   // w32, ra32_h, r22_32_h hold the loaded H_N
+  // BF16x3 operands (hi and lo halves in one buffer each, rows padded to 32 k)
+  DevBuf wb, wyb, t2b, rab_h, r22b_h, rab_y, r22b_y, rtab, rt22b;
+  bool hb_ready = false;
   // occupied-occupied ladders: packed t2 [v*v][o*o], X_oooo of H (constant)
   // and Yg [o*o][o*o], outputs Lo of H and Yg [v*v][o*o]
   DevBuf lo_t, lo_xh, lo_xy, lo_h, lo_y;
@@ -224,6 +227,46 @@ qf::RingOps rings_of(qflow_ctx* ctx) {
                      P<double>(ctx->sp_f)};
 }
 
+// BF16x3 operands: a [rows][K] FP64 matrix becomes hi and lo bf16 halves of
+// [rows][Kp] each, stored one after the other in one buffer.
+struct Split {
+  __bf16* hi;
+  __bf16* lo;
+};
+Split split_of(DevBuf& b, size_t rows, int K) {
+  __bf16* base = P<__bf16>(b);
+  return Split{base, base + rows * (size_t)qf::bf16_pad(K)};
+}
+int ensure_split(qflow_ctx* ctx, DevBuf& b, size_t rows, int K) {
+  return ensure(ctx, b, sizeof(__bf16) * 2 * rows * (size_t)qf::bf16_pad(K));
+}
+void split(const double* src, size_t rows, int K, Split d, hipStream_t st) {
+  qf::launch_split_bf16(src, (int)rows, K, qf::bf16_pad(K), d.hi, d.lo, st);
+}
+
+int ensure_bf16(qflow_ctx* ctx) {
+  const int n = ctx->n, o = ctx->o, v = ctx->v;
+  const size_t n2 = (size_t)n * n, n2p = (size_t)n * (n + 1) / 2, ov = (size_t)o * v;
+  QF_TRY(ensure_split(ctx, ctx->wb, n2p, v * v));
+  QF_TRY(ensure_split(ctx, ctx->wyb, n2p, v * v));
+  QF_TRY(ensure_split(ctx, ctx->t2b, (size_t)o * o, v * v));
+  QF_TRY(ensure_split(ctx, ctx->rab_h, n2, (int)(2 * ov)));
+  QF_TRY(ensure_split(ctx, ctx->r22b_h, n2, (int)ov));
+  QF_TRY(ensure_split(ctx, ctx->rab_y, n2, (int)(2 * ov)));
+  QF_TRY(ensure_split(ctx, ctx->r22b_y, n2, (int)ov));
+  QF_TRY(ensure_split(ctx, ctx->rtab, ov, (int)(2 * ov)));
+  QF_TRY(ensure_split(ctx, ctx->rt22b, ov, (int)ov));
+  if (!ctx->hb_ready) {
+    hipStream_t st = ctx->stream;
+    split(P<double>(ctx->W), n2p, v * v, split_of(ctx->wb, n2p, v * v), st);
+    split(P<double>(ctx->ra_h), n2, (int)(2 * ov), split_of(ctx->rab_h, n2, (int)(2 * ov)), st);
+    split(P<double>(ctx->r22_h), n2, (int)ov, split_of(ctx->r22b_h, n2, (int)ov), st);
+    QF_HIP(hipGetLastError());
+    ctx->hb_ready = true;
+  }
+  return QFLOW_OK;
+}
+
 // Yg = [F,sigma], the ladder intermediates L = W t2^T, LY = WY t2^T and the
 // ring intermediates (Ga, G22 by matrix cores; J1, J2) of H_N and Yg
 // FP32 copies of the ladder and ring GEMM operands for the mixed-precision
@@ -255,10 +298,12 @@ int ensure_mixed(qflow_ctx* ctx) {
 // QFLOW_FP32 the ladder and ring products (the o^2 v^4 and o^3 v^3
 // contractions) take FP32 operands on the FP32 matrix cores, FP64 sums.
 int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
-  if (precision != QFLOW_FP64 && precision != QFLOW_FP32)
-    return fail(ctx, QFLOW_E_UNSUPPORTED, "precision must be QFLOW_FP64 or QFLOW_FP32");
+  if (precision != QFLOW_FP64 && precision != QFLOW_FP32 && precision != QFLOW_BF16X3)
+    return fail(ctx, QFLOW_E_UNSUPPORTED, "unknown precision");
   const bool mixed = precision == QFLOW_FP32;
+  const bool bf3 = precision == QFLOW_BF16X3;
   if (mixed) QF_TRY(ensure_mixed(ctx));
+  if (bf3) QF_TRY(ensure_bf16(ctx));
   const int n = ctx->n, o = ctx->o, v = ctx->v;
   const size_t n2 = (size_t)n * n, ov = (size_t)o * v;
   double* part = P<double>(ctx->gpart);
@@ -277,7 +322,19 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
                     nullptr, st);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[1], st));
   const int npair = n * (n + 1) / 2;   // ladder rows p <= q
-  if (mixed) {
+  const size_t n2p = (size_t)npair;
+  if (bf3) {
+    const Split tb = split_of(ctx->t2b, (size_t)o * o, v * v);
+    const Split wb = split_of(ctx->wb, n2p, v * v), wyb = split_of(ctx->wyb, n2p, v * v);
+    const int kp = qf::bf16_pad(v * v);
+    split(t2, (size_t)o * o, v * v, tb, st);
+    qf::launch_gemm_nt_bf16x3(wb.hi, wb.lo, tb.hi, tb.lo, P<double>(ctx->L), npair, o * o, kp, 1.0,
+                              part, pcap, st);
+    if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], st));
+    split(P<double>(ctx->wy), n2p, v * v, wyb, st);
+    qf::launch_gemm_nt_bf16x3(wyb.hi, wyb.lo, tb.hi, tb.lo, P<double>(ctx->LY), npair, o * o, kp,
+                              1.0, part, pcap, st);
+  } else if (mixed) {
     qf::launch_cvt_f32(t2, P<float>(ctx->t2_32), ov * ov, st);
     qf::launch_gemm_nt_f32(P<float>(ctx->w32), P<float>(ctx->t2_32), P<double>(ctx->L), npair,
                            o * o, v * v, 1.0, part, pcap, st);
@@ -292,7 +349,15 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
                            part, pcap, st);
   }
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[3], st));
-  if (mixed) {
+  if (bf3) {
+    qf::launch_pack_ring_T(t2, o, v, P<double>(ctx->rta), P<double>(ctx->rt22), st);
+    qf::launch_pack_ring_A(P<double>(ctx->y2), n, o, P<double>(ctx->ra_y), P<double>(ctx->r22_y),
+                           st);
+    split(P<double>(ctx->rta), ov, (int)(2 * ov), split_of(ctx->rtab, ov, (int)(2 * ov)), st);
+    split(P<double>(ctx->rt22), ov, (int)ov, split_of(ctx->rt22b, ov, (int)ov), st);
+    split(P<double>(ctx->ra_y), n2, (int)(2 * ov), split_of(ctx->rab_y, n2, (int)(2 * ov)), st);
+    split(P<double>(ctx->r22_y), n2, (int)ov, split_of(ctx->r22b_y, n2, (int)ov), st);
+  } else if (mixed) {
     qf::launch_pack_ring_T(t2, o, v, P<float>(ctx->rta32), P<float>(ctx->rt22_32), st);
     qf::launch_pack_ring_A(P<double>(ctx->y2), n, o, P<float>(ctx->ra32_y),
                            P<float>(ctx->r22_32_y), st);
@@ -302,7 +367,20 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
                            st);
   }
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[4], st));
-  if (mixed) {
+  if (bf3) {
+    const int ka = qf::bf16_pad((int)(2 * ov)), k22 = qf::bf16_pad((int)ov);
+    const Split ta = split_of(ctx->rtab, ov, (int)(2 * ov)), t22 = split_of(ctx->rt22b, ov, (int)ov);
+    const Split ah = split_of(ctx->rab_h, n2, (int)(2 * ov)), a22h = split_of(ctx->r22b_h, n2, (int)ov);
+    const Split ay = split_of(ctx->rab_y, n2, (int)(2 * ov)), a22y = split_of(ctx->r22b_y, n2, (int)ov);
+    qf::launch_gemm_nt_bf16x3(ah.hi, ah.lo, ta.hi, ta.lo, P<double>(ctx->ga_h), (int)n2, (int)ov,
+                              ka, 1.0, part, pcap, st);
+    qf::launch_gemm_nt_bf16x3(a22h.hi, a22h.lo, t22.hi, t22.lo, P<double>(ctx->g22_h), (int)n2,
+                              (int)ov, k22, 1.0, part, pcap, st);
+    qf::launch_gemm_nt_bf16x3(ay.hi, ay.lo, ta.hi, ta.lo, P<double>(ctx->ga_y), (int)n2, (int)ov,
+                              ka, 1.0, part, pcap, st);
+    qf::launch_gemm_nt_bf16x3(a22y.hi, a22y.lo, t22.hi, t22.lo, P<double>(ctx->g22_y), (int)n2,
+                              (int)ov, k22, 1.0, part, pcap, st);
+  } else if (mixed) {
     const float* ta = P<float>(ctx->rta32);
     const float* t22 = P<float>(ctx->rt22_32);
     qf::launch_gemm_nt_f32(P<float>(ctx->ra32_h), ta, P<double>(ctx->ga_h), (int)n2, (int)ov,
@@ -418,6 +496,8 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->c1y,    &ctx->lo_t,     &ctx->lo_xh,  &ctx->lo_xy,    &ctx->lo_h,
                     &ctx->lo_y,   &ctx->w32,      &ctx->wy32,   &ctx->t2_32,    &ctx->ra32_h,
                     &ctx->r22_32_h, &ctx->ra32_y, &ctx->r22_32_y, &ctx->rta32,  &ctx->rt22_32,
+                    &ctx->wb,     &ctx->wyb,      &ctx->t2b,    &ctx->rab_h,    &ctx->r22b_h,
+                    &ctx->rab_y,  &ctx->r22b_y,   &ctx->rtab,   &ctx->rt22b,
                     &ctx->f,      &ctx->V,        &ctx->W,      &ctx->y1,       &ctx->y2,
                     &ctx->wy,     &ctx->L,        &ctx->LY,     &ctx->scal,     &ctx->r1,
                     &ctx->r2,     &ctx->t1n,      &ctx->t2n,    &ctx->heff,     &ctx->heff_off,
@@ -531,6 +611,7 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_HIP(hipMemcpy(ctx->scal.p, sc, sizeof(sc), hipMemcpyHostToDevice));
   ctx->loaded = true;
   ctx->h32_ready = false;
+  ctx->hb_ready = false;
   ctx->last_spaces.clear();
   return QFLOW_OK;
 }
