@@ -59,7 +59,9 @@ typedef enum {
 /* Arithmetic of the residual contractions (ladder intermediates). */
 typedef enum { QFLOW_FP64 = 0, QFLOW_FP32 = 1, QFLOW_BF16X3 = 2 } qflow_precision;
 
-/* flow_step flags: low 4 bits = qflow_precision. */
+/* flow_step flags: low 4 bits = qflow_precision (the arithmetic of the ladder
+ * and ring contractions: FP64; FP32 operands with FP64 sums; BF16x3 = hi+lo
+ * bf16 operands with FP32 partial and FP64 sums). */
 enum {
   QFLOW_UNOWNED_FROZEN = 1 << 4 /* amplitudes no space owns keep their value */
 };
@@ -123,20 +125,29 @@ int qflow_build_heff(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const
  * n_o*n_v + (n_o*n_v)^2. */
 int64_t qflow_amp_size(const qflow_space* space);
 
+/* Number of doubles of one space's CI vector: C(na, n_o)^2 (determinants
+ * with n_o alpha and n_o beta electrons in the space's na orbitals). */
+int64_t qflow_ci_size(const qflow_space* space);
+
 /* Lowest eigenpair of every space's CAS matrix (determinants with n_o alpha
  * and n_o beta electrons in the space's orbitals: the span of P + Q_int of
- * Eq. (6)), by Davidson iteration in FP64 from the reference determinant.
- * Outputs (device): energy[K] (the E(i) of Eq. (5), eigenvalue reading),
- * c0[K] (reference coefficient of the normalised eigenvector, made >= 0),
- * amp + amp_off[k] (amp_off host, K+1 entries): the intermediate-normalised
- * cluster amplitudes t1[n_o][n_v] then t2[n_o][n_o][n_v][n_v] (local
- * indices; t2[i][j][a][b] pairs i,a alpha with j,b beta), iters[K],
- * status[K] (QFLOW_OK, QFLOW_E_NOT_CONVERGED, QFLOW_E_REF_WEIGHT).
- * Converged when the residual norm of the normalised Ritz vector is < tol. */
+ * Eq. (6)), by Davidson iteration in FP64.  Outputs (device): energy[K] (the
+ * E(i) of Eq. (5), eigenvalue reading), c0[K] (reference coefficient of the
+ * normalised eigenvector, made >= 0), amp + amp_off[k] (amp_off host, K+1
+ * entries): the intermediate-normalised cluster amplitudes t1[n_o][n_v] then
+ * t2[n_o][n_o][n_v][n_v] (local indices; t2[i][j][a][b] pairs i,a alpha with
+ * j,b beta), iters[K], status[K] (QFLOW_OK, QFLOW_E_NOT_CONVERGED,
+ * QFLOW_E_REF_WEIGHT).  Converged when the residual norm of the normalised
+ * Ritz vector is < tol.
+ * ci_warm (device, may be NULL) with ci_off (host, K+1 entries, blocks of
+ * qflow_ci_size): in, a start vector per space (all zeros: start from the
+ * reference determinant); out, the normalised eigenvector with c0 >= 0,
+ * determinants ordered alpha string major, strings lexicographic. */
 int qflow_solve_active_batch(qflow_ctx* ctx, int32_t K, const qflow_space* spaces,
                              const double* heff, const int64_t* heff_off, double* energy,
-                             double* c0, double* amp, const int64_t* amp_off, int32_t* iters,
-                             int32_t* status, double tol, int32_t max_iter);
+                             double* c0, double* amp, const int64_t* amp_off, double* ci_warm,
+                             const int64_t* ci_off, int32_t* iters, int32_t* status, double tol,
+                             int32_t max_iter);
 
 /* One QFlow macro-iteration (a Jacobi sweep: every space reads the pool as
  * it was on entry, then the pool is updated once, as with the end-of-sweep
@@ -149,6 +160,9 @@ int qflow_solve_active_batch(qflow_ctx* ctx, int32_t K, const qflow_space* space
  *      amplitudes unchanged,
  *   4. unowned amplitudes take t <- t - R/Delta (Delta = eps_a - eps_i,
  *      eps_a + eps_b - eps_i - eps_j) unless QFLOW_UNOWNED_FROZEN.
+ * The context keeps each space's eigenvector and starts the next flow step's
+ * solve of that space from it while the space list stays the same; a new
+ * list starts every solve from the reference determinant.
  * t1, t2 (device) are updated in place.  energy[K] (device) receives E(i);
  * *e_mean (host) = mean_i E(i), *max_dt (host) = max |t_new - t_old|.
  * Synchronises the stream. */

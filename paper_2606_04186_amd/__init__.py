@@ -7,5 +7,5 @@ it does not load the library; ``lib()`` does, and raises if it was not built
 """
 from .api import (  # noqa: F401
     FP64, FP32, BF16X3, UNOWNED_FROZEN, SPACE_DTYPE, QFlowError, Context, lib,
-    make_spaces, sample_spaces, build_owners, heff_size, amp_size,
+    make_spaces, sample_spaces, build_owners, heff_size, amp_size, ci_size,
 )

@@ -54,9 +54,10 @@ def lib() -> ctypes.CDLL:
             "qflow_residual": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, ctypes.c_int]),
             "qflow_heff_size": (i64, [vp]),
             "qflow_amp_size": (i64, [vp]),
+            "qflow_ci_size": (i64, [vp]),
             "qflow_build_heff": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, ctypes.c_int]),
             "qflow_solve_active_batch": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp,
-                                                        vp, vp, d, i32]),
+                                                        vp, vp, vp, vp, d, i32]),
             "qflow_flow_step": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32]),
             "qflow_last_timings": (ctypes.c_int, [vp, vp, ctypes.c_int]),
             "qflow_sample_spaces": (ctypes.c_int, [i32, i32, i32, i32, vp, vp, i64, i32, vp, vp,
@@ -104,6 +105,10 @@ def heff_size(space) -> int:
 
 def amp_size(space) -> int:
     return int(lib().qflow_amp_size(_ptr(np.ascontiguousarray(space, dtype=SPACE_DTYPE))))
+
+
+def ci_size(space) -> int:
+    return int(lib().qflow_ci_size(_ptr(np.ascontiguousarray(space, dtype=SPACE_DTYPE))))
 
 
 def offsets(spaces, size_fn) -> np.ndarray:
@@ -170,11 +175,13 @@ class Context:
                                            _ptr(heff), _ptr(heff_off), precision))
 
     def solve_active_batch(self, spaces, heff, heff_off, energy, c0, amp, amp_off, iters,
-                           status, tol=1e-10, max_iter=200):
+                           status, tol=1e-10, max_iter=200, ci=None, ci_off=None):
+        """ci / ci_off (optional): start vectors in, eigenvectors out."""
         sp = _spaces(spaces)
         self._check(lib().qflow_solve_active_batch(
             self.h, len(sp), _ptr(sp), _ptr(heff), _ptr(heff_off), _ptr(energy), _ptr(c0),
-            _ptr(amp), _ptr(amp_off), _ptr(iters), _ptr(status), tol, max_iter))
+            _ptr(amp), _ptr(amp_off), _ptr(ci), _ptr(ci_off), _ptr(iters), _ptr(status), tol,
+            max_iter))
 
     def flow_step(self, spaces, owner1, owner2, t1, t2, energy, flags=FP64):
         sp = _spaces(spaces)

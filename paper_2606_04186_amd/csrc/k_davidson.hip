@@ -111,31 +111,44 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
   }
   __syncthreads();
   // same-spin string Hamiltonian Hs[I][J] = <I| sum k_pq E_pq + 1/2 sum g E_pq E_rs |J>,
-  // k_pq = h_pq - 1/2 sum_r g(pr|rq)
-  for (int e = lane; e < NS * NS; e += 64) {
-    const int I = e / NS, J = e % NS;
-    double x = 0.0;
-    for (int f = 0; f < NR; ++f) {
-      const int r = rep[I * NR + f];
-      if (rep_src(r) == J) {
-        const int p = rep_pq(r) / NA, q = rep_pq(r) % NA;
-        double kk = h[p * NA + q];
-        for (int t = 0; t < NA; ++t) kk -= 0.5 * g[((p * NA + t) * NA + t) * NA + q];
-        x += rep_sgn(r) * kk;
-      }
-      const int Kst = rep_src(r);
-      for (int f2 = 0; f2 < NR; ++f2) {
-        const int r2 = rep[Kst * NR + f2];
-        if (rep_src(r2) == J) x += 0.5 * rep_sgn(r) * rep_sgn(r2) * g[rep_pq(r) * N2 + rep_pq(r2)];
-      }
-    }
-    Hs[e] = x;
+  // k_pq = h_pq - 1/2 sum_r g(pr|rq): lane I scatters the one- and two-step
+  // replacements of string I into row I (one lane per row, in a fixed order)
+  double* kk = rv;   // N2 <= D doubles; rv is free until the iterations start
+  for (int e = lane; e < NS * NS; e += 64) Hs[e] = 0.0;
+  for (int e = lane; e < N2; e += 64) {
+    const int p = e / NA, q = e % NA;
+    double x = h[p * NA + q];
+    for (int t = 0; t < NA; ++t) x -= 0.5 * g[((p * NA + t) * NA + t) * NA + q];
+    kk[e] = x;
   }
   __syncthreads();
-  for (int e = lane; e < D; e += 64) {
-    dg[e] = cas_diag(S, Hs, g, Ec, e / NS, e % NS);
-    bb[e] = (e == 0) ? 1.0 : 0.0;
+  if (lane < NS) {
+    const int I = lane;
+    double* row = Hs + I * NS;
+    for (int f = 0; f < NR; ++f) {
+      const int r = rep[I * NR + f];
+      row[rep_src(r)] += rep_sgn(r) * kk[rep_pq(r)];
+      const int Kst = rep_src(r);
+      const double* gr = g + rep_pq(r) * N2;
+      for (int f2 = 0; f2 < NR; ++f2) {
+        const int r2 = rep[Kst * NR + f2];
+        row[rep_src(r2)] += 0.5 * rep_sgn(r) * rep_sgn(r2) * gr[rep_pq(r2)];
+      }
+    }
   }
+  __syncthreads();
+  for (int e = lane; e < D; e += 64) dg[e] = cas_diag(S, Hs, g, Ec, e / NS, e % NS);
+  // starting vector: the stored eigenvector of this space's previous solve
+  // when there is one (non-zero), else the reference determinant
+  double* civ = a.ci ? a.ci + a.ci_off[k] : nullptr;
+  double cn = 0.0;
+  if (civ) {
+    for (int e = lane; e < D; e += 64) cn += civ[e] * civ[e];
+    cn = wave_sum(cn);
+  }
+  const bool warm = cn > 0.25;
+  const double cinv = warm ? 1.0 / sqrt(cn) : 0.0;
+  for (int e = lane; e < D; e += 64) bb[e] = warm ? civ[e] * cinv : (e == 0 ? 1.0 : 0.0);
   // this lane's beta replacement list
   const bool active = lane < G * NS;
   const int ib = lane % NS, grp = lane / NS;
@@ -257,6 +270,8 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
   // sign convention: reference coefficient >= 0
   const double sgn = (xv[0] < 0.0) ? -1.0 : 1.0;
   const double c0 = sgn * xv[0];
+  if (civ)
+    for (int e = lane; e < D; e += 64) civ[e] = sgn * xv[e];
   if (lane == 0) {
     a.energy[k] = theta;
     a.c0[k] = c0;

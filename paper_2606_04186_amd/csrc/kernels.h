@@ -116,6 +116,8 @@ struct DavidsonArgs {
   double* c0;
   double* amp;
   const int64_t* amp_off;
+  double* ci;                 // per space: ns^2 eigenvector, start and result (NULL: none)
+  const int64_t* ci_off;
   int32_t* iters;
   int32_t* status;
   double tol;

@@ -65,12 +65,13 @@ struct qflow_ctx {
   // occupied-occupied ladders: packed t2 [v*v][o*o], X_oooo of H (constant)
   // and Yg [o*o][o*o], outputs Lo of H and Yg [v*v][o*o]
   DevBuf lo_t, lo_xh, lo_xy, lo_h, lo_y;
+  DevBuf ci, ci_off;   // eigenvectors kept between flow steps (warm starts)
   DevBuf heff, heff_off, amp, amp_off, work, work_off, energy, c0, iters, status, spaces,
       strings, out2, partial, tasks, mtab;
   int task_slots[3] = {0, 0, 0};
   // host mirror of the last uploaded space list
   std::vector<qflow_space> last_spaces;
-  std::vector<int64_t> h_heff_off, h_amp_off, h_work_off;
+  std::vector<int64_t> h_heff_off, h_amp_off, h_work_off, h_ci_off;
   int lds_davidson = 0;
   int na_max = 0;
   int slots_max = 0;
@@ -155,6 +156,7 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   std::vector<SpaceDev> dev(std::max(K, 1));
   ctx->h_heff_off.assign(K + 1, 0);
   ctx->h_amp_off.assign(K + 1, 0);
+  ctx->h_ci_off.assign(K + 1, 0);
   ctx->h_work_off.assign(K + 1, 0);
   int lds = 0, na_max = 0, slots_max = 0;
   for (int k = 0; k < K; ++k) {
@@ -170,6 +172,7 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
     for (int i = 0; i < s.n_o; ++i) ns = ns * (na - i) / (i + 1);
     const int64_t D = ns * ns;
     ctx->h_work_off[k + 1] = ctx->h_work_off[k] + 2 * kMaxSub * D;
+    ctx->h_ci_off[k + 1] = ctx->h_ci_off[k] + D;
     const int nrep = s.n_o * (1 + na - s.n_o);
     const int need = na * na * na * na + (int)(ns * ns) + 4 * (int)D + 3 * kMaxSub * kMaxSub +
                      kMaxSub + 4 + ((int)ns * nrep + 1) / 2;
@@ -189,6 +192,11 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   QF_TRY(ensure(ctx, ctx->work, sizeof(double) * std::max<int64_t>(ctx->h_work_off[K], 1)));
   QF_TRY(ensure(ctx, ctx->heff, sizeof(double) * std::max<int64_t>(ctx->h_heff_off[K], 1)));
   QF_TRY(ensure(ctx, ctx->amp, sizeof(double) * std::max<int64_t>(ctx->h_amp_off[K], 1)));
+  QF_TRY(ensure(ctx, ctx->ci_off, sizeof(int64_t) * (K + 1)));
+  QF_TRY(ensure(ctx, ctx->ci, sizeof(double) * std::max<int64_t>(ctx->h_ci_off[K], 1)));
+  // a new space list starts every solve cold
+  qf::launch_fill(P<double>(ctx->ci), (size_t)std::max<int64_t>(ctx->h_ci_off[K], 1), 0.0,
+                  ctx->stream);
   QF_TRY(ensure(ctx, ctx->energy, sizeof(double) * std::max(K, 1)));
   QF_TRY(ensure(ctx, ctx->c0, sizeof(double) * std::max(K, 1)));
   QF_TRY(ensure(ctx, ctx->iters, sizeof(int32_t) * std::max(K, 1)));
@@ -202,6 +210,8 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   QF_HIP(hipMemcpyAsync(ctx->amp_off.p, ctx->h_amp_off.data(), sizeof(int64_t) * (K + 1),
                         hipMemcpyHostToDevice, ctx->stream));
   QF_HIP(hipMemcpyAsync(ctx->work_off.p, ctx->h_work_off.data(), sizeof(int64_t) * (K + 1),
+                        hipMemcpyHostToDevice, ctx->stream));
+  QF_HIP(hipMemcpyAsync(ctx->ci_off.p, ctx->h_ci_off.data(), sizeof(int64_t) * (K + 1),
                         hipMemcpyHostToDevice, ctx->stream));
   // the host vectors must outlive the asynchronous copies
   QF_HIP(hipStreamSynchronize(ctx->stream));
@@ -502,6 +512,7 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->wy,     &ctx->L,        &ctx->LY,     &ctx->scal,     &ctx->r1,
                     &ctx->r2,     &ctx->t1n,      &ctx->t2n,    &ctx->heff,     &ctx->heff_off,
                     &ctx->amp,    &ctx->amp_off,  &ctx->work,   &ctx->work_off, &ctx->energy,
+                    &ctx->ci,     &ctx->ci_off,
                     &ctx->c0,     &ctx->iters,    &ctx->status, &ctx->spaces,   &ctx->strings,
                     &ctx->out2,   &ctx->partial, &ctx->tasks, &ctx->mtab};
   for (DevBuf* b : bufs)
@@ -660,6 +671,14 @@ int64_t qflow_amp_size(const qflow_space* s) {
   return nt1 + nt1 * nt1;
 }
 
+int64_t qflow_ci_size(const qflow_space* s) {
+  if (!s || s->n_o < 1 || s->n_v < 0) return 0;
+  const int na = s->n_o + s->n_v;
+  int64_t ns = 1;
+  for (int i = 0; i < s->n_o; ++i) ns = ns * (na - i) / (i + 1);
+  return ns * ns;
+}
+
 namespace {
 
 int check_offsets(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const int64_t* off,
@@ -692,8 +711,9 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
 }
 
 int run_solve(qflow_ctx* ctx, int32_t K, const double* heff, const int64_t* heff_off_dev,
-              double* energy, double* c0, double* amp, const int64_t* amp_off_dev,
-              int32_t* iters, int32_t* status, double tol, int32_t max_iter) {
+              double* energy, double* c0, double* amp, const int64_t* amp_off_dev, double* ci,
+              const int64_t* ci_off_dev, int32_t* iters, int32_t* status, double tol,
+              int32_t max_iter) {
   if (K == 0) return QFLOW_OK;
   qf::DavidsonArgs a;
   a.spaces = P<SpaceDev>(ctx->spaces);
@@ -706,6 +726,8 @@ int run_solve(qflow_ctx* ctx, int32_t K, const double* heff, const int64_t* heff
   a.c0 = c0;
   a.amp = amp;
   a.amp_off = amp_off_dev;
+  a.ci = ci;
+  a.ci_off = ci_off_dev;
   a.iters = iters;
   a.status = status;
   a.tol = tol;
@@ -739,8 +761,9 @@ int qflow_build_heff(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const
 
 int qflow_solve_active_batch(qflow_ctx* ctx, int32_t K, const qflow_space* spaces,
                              const double* heff, const int64_t* heff_off, double* energy,
-                             double* c0, double* amp, const int64_t* amp_off, int32_t* iters,
-                             int32_t* status, double tol, int32_t max_iter) {
+                             double* c0, double* amp, const int64_t* amp_off, double* ci_warm,
+                             const int64_t* ci_off, int32_t* iters, int32_t* status, double tol,
+                             int32_t max_iter) {
   QF_TRY(require_loaded(ctx));
   QF_TRY(check_spaces(ctx, K, spaces));
   if (!heff || !energy || !c0 || !amp || !iters || !status)
@@ -748,18 +771,23 @@ int qflow_solve_active_batch(qflow_ctx* ctx, int32_t K, const qflow_space* space
   if (!(tol > 0.0) || max_iter < 1) return fail(ctx, QFLOW_E_INVALID_ARG, "bad tol or max_iter");
   QF_TRY(check_offsets(ctx, K, spaces, heff_off, qflow_heff_size, "heff_off"));
   QF_TRY(check_offsets(ctx, K, spaces, amp_off, qflow_amp_size, "amp_off"));
+  if (ci_warm) QF_TRY(check_offsets(ctx, K, spaces, ci_off, qflow_ci_size, "ci_off"));
   QF_TRY(upload_spaces(ctx, K, spaces));
   DevBuf off;
-  QF_TRY(ensure(ctx, off, sizeof(int64_t) * 2 * (K + 1)));
+  QF_TRY(ensure(ctx, off, sizeof(int64_t) * 3 * (K + 1)));
   int64_t* d_hoff = P<int64_t>(off);
   int64_t* d_aoff = d_hoff + (K + 1);
+  int64_t* d_coff = d_aoff + (K + 1);
   int r = QFLOW_OK;
   if (hipMemcpy(d_hoff, heff_off, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice) !=
           hipSuccess ||
-      hipMemcpy(d_aoff, amp_off, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice) != hipSuccess)
+      hipMemcpy(d_aoff, amp_off, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice) != hipSuccess ||
+      (ci_warm &&
+       hipMemcpy(d_coff, ci_off, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice) != hipSuccess))
     r = fail(ctx, QFLOW_E_DEVICE, "offset upload failed");
   if (r == QFLOW_OK)
-    r = run_solve(ctx, K, heff, d_hoff, energy, c0, amp, d_aoff, iters, status, tol, max_iter);
+    r = run_solve(ctx, K, heff, d_hoff, energy, c0, amp, d_aoff, ci_warm, ci_warm ? d_coff : nullptr,
+                  iters, status, tol, max_iter);
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipFree(off.p);
   return r;
@@ -793,7 +821,8 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
   QF_HIP(hipEventRecord(ctx->ev[9], st));
   r = run_solve(ctx, K, P<double>(ctx->heff), P<int64_t>(ctx->heff_off), P<double>(ctx->energy),
                 P<double>(ctx->c0), P<double>(ctx->amp), P<int64_t>(ctx->amp_off),
-                P<int32_t>(ctx->iters), P<int32_t>(ctx->status), 1e-10, 200);
+                P<double>(ctx->ci), P<int64_t>(ctx->ci_off), P<int32_t>(ctx->iters),
+                P<int32_t>(ctx->status), 1e-10, 200);
   ctx->timed = false;
   if (r != QFLOW_OK) return r;
   QF_HIP(hipEventRecord(ctx->ev[10], st));

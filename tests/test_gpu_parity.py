@@ -163,6 +163,51 @@ def test_solve_matches_dense_eigensolver(n, o, seed, K, start):
         assert np.abs(blk[nt1:] - s["t2"].reshape(-1)).max() < 1e-8
 
 
+def test_solve_warm_start_returns_eigenvectors():
+    """ci_warm: zeros start from the reference determinant and come back as the
+    normalised eigenvectors (c0 >= 0); fed back, each solve converges at once
+    to the same eigenpair."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    n, o, seed, K = 24, 4, 124, 8
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    t1, t2 = qflow.mp2_guess(pb.f, eri, o)
+    lists = _spaces_for(n, o, K, seed, pb.eps)
+    sp = qf.make_spaces(lists)
+    K = len(lists)
+    hoff = qf.api.offsets(sp, qf.heff_size)
+    aoff = qf.api.offsets(sp, qf.amp_size)
+    coff = qf.api.offsets(sp, qf.ci_size)
+    assert qf.ci_size(sp[0]) == 400
+    heff = torch.zeros(int(hoff[-1]), dtype=torch.float64, device="cuda")
+    amp = torch.zeros(int(aoff[-1]), dtype=torch.float64, device="cuda")
+    ci = torch.zeros(int(coff[-1]), dtype=torch.float64, device="cuda")
+    out = {}
+    ctx = context(h, eri, o)
+    ctx.build_heff(sp, dev(t1), dev(t2), heff, hoff)
+    for rnd in ("cold", "warm"):
+        energy = torch.zeros(K, dtype=torch.float64, device="cuda")
+        c0 = torch.zeros(K, dtype=torch.float64, device="cuda")
+        iters = torch.zeros(K, dtype=torch.int32, device="cuda")
+        status = torch.zeros(K, dtype=torch.int32, device="cuda")
+        ctx.solve_active_batch(sp, heff, hoff, energy, c0, amp, aoff, iters, status, ci=ci,
+                               ci_off=coff)
+        torch.cuda.synchronize()
+        out[rnd] = (host(energy), host(c0), host(iters), host(status), host(ci).copy())
+    E, C0, it, st, C = out["cold"]
+    for k, (occ, vir) in enumerate(lists):
+        s = qflow.solve_space(pb, t1, t2, tuple(occ) + tuple(vir), len(occ))
+        assert abs(E[k] - s["E"]) < 1e-9
+        vec = C[coff[k]:coff[k + 1]]
+        assert abs(np.linalg.norm(vec) - 1.0) < 1e-12
+        assert abs(vec[0] - C0[k]) < 1e-14 and vec[0] >= 0.0
+    Ew, C0w, itw, stw, Cw = out["warm"]
+    assert np.abs(Ew - E).max() < 1e-11
+    assert (itw <= 2).all() and (itw < it).all()
+    assert np.abs(Cw - C).max() < 1e-8
+
+
 def _flow_parity(n, o, seed, K, iters, start, flags=0, tol_e=1e-9, tol_t=1e-8):
     import paper_2606_04186_amd as qf
     h, eri = problem(n, o, seed)
