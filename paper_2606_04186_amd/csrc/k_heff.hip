@@ -191,11 +191,11 @@ __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __
     const MarkedE E{T, &A};
     const MarkedSigma D{T, &A};
     const CommE<MarkedE, MarkedSigma, true> ce{E, D, A, n, o};
-    double x;
+    double x;   // (local indices)
     if (kind == 2)
-      x = ce.c2(p, q, r, t);
+      x = ce.c2(la, lb, lc, ld);
     else if (kind == 1)
-      x = ce.c1(p, q);
+      x = ce.c1(la, lb);
     else
       x = ce.c0();
     emit(x, -0.5, false);

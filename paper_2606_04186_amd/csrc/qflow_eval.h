@@ -610,8 +610,16 @@ struct CommE {
   const Active& A;
   int n, o;
 
-  QF_HD bool occ(int p) const { return p < o; }   // markers are negative: "occupied"
-                                                  // tests below never see them
+  // In marked mode every index is local (the position in A.orb, occupied
+  // first) and markers are negative; the class tests below never see markers.
+  QF_HD bool occ(int p) const {
+    if constexpr (kMarked) return p < A.nocc;
+    else return p < o;
+  }
+  QF_HD int act_at(bool occupied, int m) const {
+    if constexpr (kMarked) return occupied ? m : A.nocc + m;
+    else return A.actv(occupied, m);
+  }
 
   template <class F>
   QF_HD void over_ext(bool occupied, F fn) const {
@@ -625,10 +633,10 @@ struct CommE {
   template <class F>
   QF_HD void pair1(bool bt, bool bu, F fn) const {
     over_ext(bt, [&](int x) {
-      for (int m = 0; m < A.nact(bu); ++m) fn(x, A.actv(bu, m));
+      for (int m = 0; m < A.nact(bu); ++m) fn(x, act_at(bu, m));
     });
     for (int k = 0; k < A.nact(bt); ++k) {
-      const int t = A.actv(bt, k);
+      const int t = act_at(bt, k);
       over_ext(bu, [&](int x) { fn(t, x); });
     }
   }
@@ -637,15 +645,15 @@ struct CommE {
   QF_HD void triple1(bool bt, bool bu, bool bw, F fn) const {
     over_ext(bt, [&](int x) {
       for (int j = 0; j < A.nact(bu); ++j)
-        for (int k = 0; k < A.nact(bw); ++k) fn(x, A.actv(bu, j), A.actv(bw, k));
+        for (int k = 0; k < A.nact(bw); ++k) fn(x, act_at(bu, j), act_at(bw, k));
     });
     for (int i = 0; i < A.nact(bt); ++i)
       over_ext(bu, [&](int x) {
-        for (int k = 0; k < A.nact(bw); ++k) fn(A.actv(bt, i), x, A.actv(bw, k));
+        for (int k = 0; k < A.nact(bw); ++k) fn(act_at(bt, i), x, act_at(bw, k));
       });
     for (int i = 0; i < A.nact(bt); ++i)
       for (int j = 0; j < A.nact(bu); ++j)
-        over_ext(bw, [&](int x) { fn(A.actv(bt, i), A.actv(bu, j), x); });
+        over_ext(bw, [&](int x) { fn(act_at(bt, i), act_at(bu, j), x); });
   }
 
   QF_HD double c2(int p, int q, int r, int s) const {
@@ -731,13 +739,13 @@ struct CommE {
          - b.two(t, u, w, x) * (2.0 * a.two(w, x, t, u) - a.two(w, x, u, t));
     };
     triple1(true, true, false, [&](int t, int u, int w) {
-      for (int m = 0; m < A.nact(false); ++m) term(t, u, w, A.actv(false, m));
+      for (int m = 0; m < A.nact(false); ++m) term(t, u, w, act_at(false, m));
     });
     for (int i = 0; i < A.nact(true); ++i)
       for (int j = 0; j < A.nact(true); ++j)
         for (int k = 0; k < A.nact(false); ++k)
           over_ext(false, [&](int x) {
-            term(A.actv(true, i), A.actv(true, j), A.actv(false, k), x);
+            term(act_at(true, i), act_at(true, j), act_at(false, k), x);
           });
     return z;
   }
@@ -772,7 +780,7 @@ QF_HD int mark_sizes(int na, int* tau1, int* tau2, int* d1, int* d2) {
 struct MarkedE {
   MarkTables T;
   const Active* A;
-  QF_HD int loc(int p) const { return A->pos[p]; }
+  QF_HD int loc(int p) const { return p; }   // indices are local in marked mode
   QF_HD double one(int p, int q) const {
     const int na = T.na;
     if (p < 0) return T.tau1[(-1 - p) * na + loc(q)];
@@ -793,7 +801,7 @@ struct MarkedE {
 struct MarkedSigma {
   MarkTables T;
   const Active* A;
-  QF_HD int loc(int p) const { return A->pos[p]; }
+  QF_HD int loc(int p) const { return p; }   // indices are local in marked mode
   QF_HD double one(int p, int q) const {
     const int na = T.na;
     if (p < 0) return T.D1[(0 * na + (-1 - p)) * na + loc(q)];
