@@ -97,11 +97,25 @@ __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
     const double x = (j < 2) ? d01[r + j * n4] : -d01[(j - 2) * n4 + ((t * na + c) * na + a) * na + b];
     out[s1 + s2 + s3 + e] = x;
   }
+  // H_N and Yg restricted to the space (local indices): [f_A | V_A | y1_A | y2_A]
+  double* xo = out + s1 + s2 + s3 + s4;
+  for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+    const int p = A.orb[e / na], q = A.orb[e % na];
+    xo[e] = g.f[p * n + q];
+    xo[n2 + n4 + e] = g.y1[p * n + q];
+  }
+  for (int e = threadIdx.x; e < n4; e += blockDim.x) {
+    const size_t idx = (((size_t)A.orb[e / n3] * n + A.orb[e / n2 % na]) * n +
+                        A.orb[e / na % na]) * n + A.orb[e % na];
+    xo[n2 + e] = g.V[idx];
+    xo[2 * n2 + n4 + e] = g.y2[idx];
+  }
 }
 
 // Slot layout while accumulating: [x0, x1 (na^2), x2 (na^4)].
 // part 0: H + [H,sigma] - [H,tau]         (initialises the slot)
 // part 1: + 1/2 ([Yg,sigma] - [Yg,tau])
+// ([X,tau] from X and tau restricted to the space, staged in LDS, local indices)
 // part 2: + 1/2 ([Ft,tau] - [Ft,sigma]) = - 1/2 [E,sigma], marked evaluation
 template <int PART>
 __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __restrict__ scal,
@@ -116,19 +130,27 @@ __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __
   const SpaceDev sp = spaces[k];
   load_active(sp, g.n, g.o, A);
   MarkTables T{};
-  if constexpr (PART == 2) {
-    int s1, s2, s3, s4;
-    const int tot = mark_sizes(sp.na, &s1, &s2, &s3, &s4);
-    const double* src = tab + (int64_t)k * tab_stride;
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) tl[e] = src[e];
-    __syncthreads();
-    T = MarkTables{tl, tl + s1, tl + s1 + s2, tl + s1 + s2 + s3, sp.na};
-  }
   const int na = sp.na, n = g.n, o = g.o, v = n - o;
-  const int n2 = na * na;
+  const int n2 = na * na, n4 = n2 * n2;
+  int s1, s2, s3, s4;
+  const int tot = mark_sizes(na, &s1, &s2, &s3, &s4);
+  const double* src = tab + (int64_t)k * tab_stride;
+  if constexpr (PART == 2) {
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) tl[e] = src[e];
+    T = MarkTables{tl, tl + s1, tl + s1 + s2, tl + s1 + s2 + s3, na};
+  } else {
+    // [x1_A | x2_A | tau1 | tau2] of the space (local indices)
+    const double* xa = src + tot + (PART == 0 ? 0 : n2 + n4);
+    for (int e = threadIdx.x; e < n2 + n4; e += blockDim.x) {
+      tl[e] = xa[e];
+      tl[n2 + n4 + e] = src[e];
+    }
+  }
+  __syncthreads();
+  const LocalOp XA{tl, tl + n2, na, sp.nocc};
+  const LocalOp tauA{tl + n2 + n4, tl + 2 * n2 + n4, na, sp.nocc};
   double* slot = heff + heff_off[k];
   const Sigma s{g.t1, g.t2, n, o, v};
-  const Tau tau{s, &A};
   const int slot_idx = blockIdx.y * blockDim.x + threadIdx.x;
   if (slot_idx >= task_stride) return;
   const int32_t code = tasks[(sp.nocc - 2) * task_stride + slot_idx];
@@ -165,12 +187,12 @@ __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __
   if constexpr (PART == 0) {
     const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.z_h, g.u_h, g.lo_h};
     const auto cs = make_comm(H, s, n, o);
-    const auto ct = make_comm(H, tau, n, o);
+    const auto ct = make_comm(XA, tauA, na, sp.nocc);
     double x;
     if (kind == 2)
-      x = H.two(p, q, r, t) + cs.c2(p, q, r, t) - ct.c2(p, q, r, t);
+      x = XA.two(la, lb, lc, ld) + cs.c2(p, q, r, t) - ct.c2(la, lb, lc, ld);
     else if (kind == 1)
-      x = H.one(p, q) + g.c1_h[p * n + q] - ct.c1(p, q);
+      x = XA.one(la, lb) + g.c1_h[p * n + q] - ct.c1(la, lb);
     else
       x = scal[3] + scal[0] - ct.c0();
     emit(x, 1.0, true);
@@ -178,12 +200,12 @@ __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __
     const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, nullptr, g.lo_y,
                    Sigma2Lazy{g.y1, g.t2, g.s2p, g.s2q, n, o}};
     const auto cs = make_comm(Y, s, n, o);
-    const auto ct = make_comm(Y, tau, n, o);
+    const auto ct = make_comm(XA, tauA, na, sp.nocc);
     double x;
     if (kind == 2)
-      x = cs.c2(p, q, r, t) - ct.c2(p, q, r, t);
+      x = cs.c2(p, q, r, t) - ct.c2(la, lb, lc, ld);
     else if (kind == 1)
-      x = g.c1_y[p * n + q] - ct.c1(p, q);
+      x = g.c1_y[p * n + q] - ct.c1(la, lb);
     else
       x = scal[1] - ct.c0();
     emit(x, 0.5, false);
@@ -240,9 +262,11 @@ __global__ __launch_bounds__(256) void k_heff_cas(const SpaceDev* __restrict__ s
 
 }  // namespace
 
+// per space: the marked tables, then H_N and Yg restricted to the space
 int heff_table_stride(int na_max) {
   int s1, s2, s3, s4;
-  return mark_sizes(na_max, &s1, &s2, &s3, &s4);
+  const int n2 = na_max * na_max;
+  return mark_sizes(na_max, &s1, &s2, &s3, &s4) + 2 * (n2 + n2 * n2);
 }
 
 void launch_heff(const double* f, const double* V, const double* y1, const double* y2,
@@ -258,13 +282,16 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
   dim3 grid(K, (slots_max + kBlock - 1) / kBlock);
   int s1, s2, s3, s4;
-  const int tab_stride = mark_sizes(na_max, &s1, &s2, &s3, &s4);
+  const int mark = mark_sizes(na_max, &s1, &s2, &s3, &s4);
+  const int tab_stride = heff_table_stride(na_max);
+  const int n2 = na_max * na_max;
+  const size_t lds01 = (size_t)2 * (n2 + n2 * n2) * sizeof(double);
   k_heff_tab<<<K, kBlock, 0, st>>>(g, spaces, tab, tab_stride);
-  k_heff_part<0><<<grid, kBlock, 0, st>>>(g, scal, spaces, heff_off, task_table, task_stride,
-                                          tab, tab_stride, heff);
-  k_heff_part<1><<<grid, kBlock, 0, st>>>(g, scal, spaces, heff_off, task_table, task_stride,
-                                          tab, tab_stride, heff);
-  k_heff_part<2><<<grid, kBlock, (size_t)tab_stride * sizeof(double), st>>>(
+  k_heff_part<0><<<grid, kBlock, lds01, st>>>(g, scal, spaces, heff_off, task_table, task_stride,
+                                              tab, tab_stride, heff);
+  k_heff_part<1><<<grid, kBlock, lds01, st>>>(g, scal, spaces, heff_off, task_table, task_stride,
+                                              tab, tab_stride, heff);
+  k_heff_part<2><<<grid, kBlock, (size_t)mark * sizeof(double), st>>>(
       g, scal, spaces, heff_off, task_table, task_stride, tab, tab_stride, heff);
   const size_t lds = (size_t)tasks * sizeof(double);
   k_heff_cas<<<K, kBlock, lds, st>>>(spaces, heff_off, heff);

@@ -218,6 +218,29 @@ struct DenseOp {
   QF_HD bool act(int) const { return true; }
 };
 
+// An operator restricted to the active space in local indices (positions in
+// A.orb, occupied first): x1[a][b], x2[a][b][c][d].  [X, tau] restricted to
+// the space involves only X restricted to the space, so Comm<LocalOp,
+// LocalOp> with n = na, o = nocc evaluates it entirely from these arrays;
+// as the B operand (tau) its loop ranges are the active orbitals.
+struct LocalOp {
+  static constexpr bool kHasL = false;
+  static constexpr bool kSparse3 = false;
+  static constexpr bool kFull = false;
+  const double* x1;
+  const double* x2;
+  int na, no;
+  QF_HD double one(int p, int q) const { return x1[p * na + q]; }
+  QF_HD double two(int p, int q, int r, int s) const {
+    return x2[((p * na + q) * na + r) * na + s];
+  }
+  QF_HD bool act(int) const { return true; }
+  QF_HD int nocc() const { return no; }
+  QF_HD int occ(int k) const { return k; }
+  QF_HD int nvir() const { return na - no; }
+  QF_HD int vir(int k) const { return no + k; }
+};
+
 // Ft = [F_N, tau]: non-zero only where at least three indices (two-body) or
 // one index (one-body) are active.
 struct FtauOp {
