@@ -13,27 +13,49 @@ namespace qf {
 namespace {
 
 // ---------------------------------------------------------------------------
-// batched Davidson: one wavefront per space
+// batched Davidson: one block per space
 // ---------------------------------------------------------------------------
 
+constexpr int kDavBlock = 256;   // threads per space (four wavefronts)
+
+// Sum over the block, the same value returned to every thread.  red: LDS
+// scratch of one double per wavefront.
+__device__ double block_sum(double x, double* red) {
+  x = wave_sum(x);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = x;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kDavBlock / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
 // Lowest eigenpair of the symmetric m x m matrix A (LDS, row-major,
-// destroyed) by cyclic Jacobi rotations, one wavefront: lane k applies each
-// rotation to row/column k.  V (LDS, m x m) receives the eigenvectors; every
-// lane gets theta, and y[0..m) (LDS) the eigenvector.
-__device__ void jacobi_lowest(double* A, double* V, int m, double* theta, double* y) {
-  const int lane = threadIdx.x;
-  for (int e = lane; e < m * m; e += 64) V[e] = (e / m == e % m) ? 1.0 : 0.0;
+// destroyed) by cyclic Jacobi rotations: thread k < m applies each rotation
+// to row/column k; every thread of the block passes the barriers.  V (LDS,
+// m x m) receives the eigenvectors; every thread gets theta, y[0..m) (LDS)
+// the eigenvector.  flag: one double of LDS scratch.
+__device__ void jacobi_lowest(double* A, double* V, int m, double* theta, double* y,
+                              double* flag) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < m * m; e += kDavBlock) V[e] = (e / m == e % m) ? 1.0 : 0.0;
   __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int e = lane; e < m * m; e += 64) {
-      const int i = e / m, j = e % m;
-      if (i == j) dia += A[e] * A[e];
-      else if (j > i) off += A[e] * A[e];
+    if (tid < 64) {
+      double off = 0.0, dia = 0.0;
+      for (int e = tid; e < m * m; e += 64) {
+        const int i = e / m, j = e % m;
+        if (i == j) dia += A[e] * A[e];
+        else if (j > i) off += A[e] * A[e];
+      }
+      off = wave_sum(off);
+      dia = wave_sum(dia);
+      if (tid == 0) flag[0] = (off <= 1e-32 * (dia + 1e-300)) ? 1.0 : 0.0;
     }
-    off = wave_sum(off);
-    dia = wave_sum(dia);
-    if (off <= 1e-32 * (dia + 1e-300)) break;
+    __syncthreads();
+    const bool done = flag[0] != 0.0;
+    __syncthreads();
+    if (done) break;
     for (int p = 0; p < m; ++p)
       for (int q = p + 1; q < m; ++q) {
         const double apq = A[p * m + q];
@@ -42,19 +64,19 @@ __device__ void jacobi_lowest(double* A, double* V, int m, double* theta, double
         const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
         const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
         __syncthreads();
-        if (lane < m) {
-          const double akp = A[lane * m + p], akq = A[lane * m + q];
-          A[lane * m + p] = c * akp - s * akq;
-          A[lane * m + q] = s * akp + c * akq;
+        if (tid < m) {
+          const double akp = A[tid * m + p], akq = A[tid * m + q];
+          A[tid * m + p] = c * akp - s * akq;
+          A[tid * m + q] = s * akp + c * akq;
         }
         __syncthreads();
-        if (lane < m) {
-          const double apk = A[p * m + lane], aqk = A[q * m + lane];
-          A[p * m + lane] = c * apk - s * aqk;
-          A[q * m + lane] = s * apk + c * aqk;
-          const double vkp = V[lane * m + p], vkq = V[lane * m + q];
-          V[lane * m + p] = c * vkp - s * vkq;
-          V[lane * m + q] = s * vkp + c * vkq;
+        if (tid < m) {
+          const double apk = A[p * m + tid], aqk = A[q * m + tid];
+          A[p * m + tid] = c * apk - s * aqk;
+          A[q * m + tid] = s * apk + c * aqk;
+          const double vkp = V[tid * m + p], vkq = V[tid * m + q];
+          V[tid * m + p] = c * vkp - s * vkq;
+          V[tid * m + q] = s * vkp + c * vkq;
         }
         __syncthreads();
       }
@@ -63,7 +85,7 @@ __device__ void jacobi_lowest(double* A, double* V, int m, double* theta, double
   for (int i = 1; i < m; ++i)
     if (A[i * m + i] < A[best * m + best]) best = i;
   *theta = A[best * m + best];
-  for (int i = lane; i < m; i += 64) y[i] = V[i * m + best];
+  for (int i = tid; i < m; i += kDavBlock) y[i] = V[i * m + best];
   __syncthreads();
 }
 
@@ -74,17 +96,21 @@ __device__ inline int rep_src(int r) { return r & 255; }
 __device__ inline int rep_pq(int r) { return (r >> 8) & 255; }
 __device__ inline double rep_sgn(int r) { return (r >> 16) ? 1.0 : -1.0; }
 
-// One space of NA orbitals and NE electrons per spin, one wavefront.
+// One space of NA orbitals and NE electrons per spin, one block of
+// kDavBlock threads.
 //
-// sigma = H c is evaluated with lane l < G*NS owning beta string Ib = l % NS
-// and the alpha strings Ia = l / NS, l / NS + G, ... (G = 64 / NS); the
-// lane keeps the replacement list of its Ib in registers.
+// sigma = H c is evaluated with thread l < G*NS owning beta string
+// Ib = l % NS and the alpha strings Ia = l / NS, l / NS + G, ... (G =
+// kDavBlock / NS); the thread keeps the replacement list of its Ib in
+// registers.  Gram dot products are reduced for all basis vectors at once;
+// the correction is orthogonalised by two classical Gram-Schmidt passes.
 template <int NA, int NE>
 __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp, double* sm) {
   constexpr int NS = binom(NA, NE), NR = NE * (1 + NA - NE), D = NS * NS;
   constexpr int N2 = NA * NA, N4 = N2 * N2;
-  constexpr int G = 64 / NS, NT = (NS + G - 1) / G;
-  const int lane = threadIdx.x;
+  constexpr int G = kDavBlock / NS, NT = (NS + G - 1) / G;
+  constexpr int NW = kDavBlock / 64;
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const Strings& S = a.strings[sp.nocc - 2];
   const int MS = a.maxsub;
   const double* hin = a.heff + a.heff_off[k];
@@ -101,29 +127,30 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
   double* Vw = Aw + MS * MS;            // MS^2
   double* yv = Vw + MS * MS;            // MS
   double* misc = yv + MS;               // 4
-  int* rep = reinterpret_cast<int*>(misc + 4);   // NS*NR
+  double* red = misc + 4;               // NW * MS
+  int* rep = reinterpret_cast<int*>(red + NW * MS);   // NS*NR
   double* bb = a.work + a.work_off[k];  // MS x D
   double* ss = bb + (size_t)MS * D;     // MS x D
-  for (int e = lane; e < N4; e += 64) g[e] = hin[1 + N2 + e];
-  for (int e = lane; e < NS * NR; e += 64) {
+  for (int e = tid; e < N4; e += kDavBlock) g[e] = hin[1 + N2 + e];
+  for (int e = tid; e < NS * NR; e += kDavBlock) {
     const int I = e / NR, f = e % NR;
     rep[e] = S.src[I][f] | (S.pq[I][f] << 8) | ((S.sgn[I][f] > 0) << 16);
   }
   __syncthreads();
   // same-spin string Hamiltonian Hs[I][J] = <I| sum k_pq E_pq + 1/2 sum g E_pq E_rs |J>,
-  // k_pq = h_pq - 1/2 sum_r g(pr|rq): lane I scatters the one- and two-step
-  // replacements of string I into row I (one lane per row, in a fixed order)
+  // k_pq = h_pq - 1/2 sum_r g(pr|rq): thread I scatters the one- and two-step
+  // replacements of string I into row I (one thread per row, in a fixed order)
   double* kk = rv;   // N2 <= D doubles; rv is free until the iterations start
-  for (int e = lane; e < NS * NS; e += 64) Hs[e] = 0.0;
-  for (int e = lane; e < N2; e += 64) {
+  for (int e = tid; e < NS * NS; e += kDavBlock) Hs[e] = 0.0;
+  for (int e = tid; e < N2; e += kDavBlock) {
     const int p = e / NA, q = e % NA;
     double x = h[p * NA + q];
     for (int t = 0; t < NA; ++t) x -= 0.5 * g[((p * NA + t) * NA + t) * NA + q];
     kk[e] = x;
   }
   __syncthreads();
-  if (lane < NS) {
-    const int I = lane;
+  if (tid < NS) {
+    const int I = tid;
     double* row = Hs + I * NS;
     for (int f = 0; f < NR; ++f) {
       const int r = rep[I * NR + f];
@@ -137,21 +164,20 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
     }
   }
   __syncthreads();
-  for (int e = lane; e < D; e += 64) dg[e] = cas_diag(S, Hs, g, Ec, e / NS, e % NS);
+  for (int e = tid; e < D; e += kDavBlock) dg[e] = cas_diag(S, Hs, g, Ec, e / NS, e % NS);
   // starting vector: the stored eigenvector of this space's previous solve
   // when there is one (non-zero), else the reference determinant
   double* civ = a.ci ? a.ci + a.ci_off[k] : nullptr;
   double cn = 0.0;
-  if (civ) {
-    for (int e = lane; e < D; e += 64) cn += civ[e] * civ[e];
-    cn = wave_sum(cn);
-  }
+  if (civ)
+    for (int e = tid; e < D; e += kDavBlock) cn += civ[e] * civ[e];
+  cn = block_sum(cn, red);
   const bool warm = cn > 0.25;
   const double cinv = warm ? 1.0 / sqrt(cn) : 0.0;
-  for (int e = lane; e < D; e += 64) bb[e] = warm ? civ[e] * cinv : (e == 0 ? 1.0 : 0.0);
-  // this lane's beta replacement list
-  const bool active = lane < G * NS;
-  const int ib = lane % NS, grp = lane / NS;
+  for (int e = tid; e < D; e += kDavBlock) bb[e] = warm ? civ[e] * cinv : (e == 0 ? 1.0 : 0.0);
+  // this thread's beta replacement list
+  const bool active = tid < G * NS;
+  const int ib = tid % NS, grp = tid / NS;
   int jb[NR], rs[NR];
   double sb[NR];
 #pragma unroll
@@ -186,32 +212,44 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
       out[ia * NS + ib] = x;
     }
   };
+  // the dot products of vec with basis vectors 0..m-1, reduced together
+  auto dots = [&](const double* vec, int m, double* outv) {
+    for (int i = 0; i < m; ++i) {
+      double d = 0.0;
+      for (int e = tid; e < D; e += kDavBlock) d += bb[(size_t)i * D + e] * vec[e];
+      d = wave_sum(d);
+      if (lane == 0) red[wv * MS + i] = d;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += kDavBlock) {
+      double d = 0.0;
+      for (int w = 0; w < NW; ++w) d += red[w * MS + i];
+      outv[i] = d;
+    }
+    __syncthreads();
+  };
   int m = 1, it = 0;
   bool conv = false;
   double theta = 0.0;
   for (it = 0; it < a.max_iter; ++it) {
     // sigma of the newest basis vector
     const double* bn = bb + (size_t)(m - 1) * D;
-    for (int e = lane; e < D; e += 64) xv[e] = bn[e];
+    for (int e = tid; e < D; e += kDavBlock) xv[e] = bn[e];
     __syncthreads();
     double* sn = ss + (size_t)(m - 1) * D;
     sigma(xv, sn);
     __syncthreads();
-    for (int i = 0; i < m; ++i) {
-      double d = 0.0;
-      for (int e = lane; e < D; e += 64) d += bb[(size_t)i * D + e] * sn[e];
-      d = wave_sum(d);
-      if (lane == 0) {
-        Gm[i * MS + (m - 1)] = d;
-        Gm[(m - 1) * MS + i] = d;
-      }
+    dots(sn, m, yv);   // yv as scratch: the new column of the projected matrix
+    for (int i = tid; i < m; i += kDavBlock) {
+      Gm[i * MS + (m - 1)] = yv[i];
+      Gm[(m - 1) * MS + i] = yv[i];
     }
     __syncthreads();
-    for (int e = lane; e < m * m; e += 64) Aw[e] = Gm[(e / m) * MS + e % m];
+    for (int e = tid; e < m * m; e += kDavBlock) Aw[e] = Gm[(e / m) * MS + e % m];
     __syncthreads();
-    jacobi_lowest(Aw, Vw, m, &theta, yv);
+    jacobi_lowest(Aw, Vw, m, &theta, yv, misc + 1);
     double rn = 0.0;
-    for (int e = lane; e < D; e += 64) {
+    for (int e = tid; e < D; e += kDavBlock) {
       double x = 0.0, y = 0.0;
       for (int i = 0; i < m; ++i) {
         x += yv[i] * bb[(size_t)i * D + e];
@@ -222,47 +260,47 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
       rv[e] = y - theta * x;
       rn += rv[e] * rv[e];
     }
-    rn = sqrt(wave_sum(rn));
-    __syncthreads();
+    rn = sqrt(block_sum(rn, red));
     if (rn < a.tol) {
       conv = true;
       ++it;
       break;
     }
     if (m == MS) {   // restart from the Ritz vector
-      for (int e = lane; e < D; e += 64) {
+      for (int e = tid; e < D; e += kDavBlock) {
         bb[e] = xv[e];
         ss[e] = hx[e];
       }
-      if (lane == 0) Gm[0] = theta;
+      if (tid == 0) Gm[0] = theta;
       m = 1;
       __syncthreads();
     }
     // diagonal-preconditioned correction, orthogonalised twice
-    for (int e = lane; e < D; e += 64) {
+    for (int e = tid; e < D; e += kDavBlock) {
       double den = dg[e] - theta;
       if (fabs(den) < 1e-8) den = (den < 0.0 ? -1e-8 : 1e-8);
       rv[e] = -rv[e] / den;
     }
     __syncthreads();
-    for (int pass = 0; pass < 2; ++pass)
-      for (int i = 0; i < m; ++i) {
-        double d = 0.0;
-        for (int e = lane; e < D; e += 64) d += bb[(size_t)i * D + e] * rv[e];
-        d = wave_sum(d);
-        for (int e = lane; e < D; e += 64) rv[e] -= d * bb[(size_t)i * D + e];
-        __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      dots(rv, m, Aw);   // Aw as scratch
+      for (int e = tid; e < D; e += kDavBlock) {
+        double x = rv[e];
+        for (int i = 0; i < m; ++i) x -= Aw[i] * bb[(size_t)i * D + e];
+        rv[e] = x;
       }
+      __syncthreads();
+    }
     double nr = 0.0;
-    for (int e = lane; e < D; e += 64) nr += rv[e] * rv[e];
-    nr = sqrt(wave_sum(nr));
+    for (int e = tid; e < D; e += kDavBlock) nr += rv[e] * rv[e];
+    nr = sqrt(block_sum(nr, red));
     if (nr < 1e-14) {
       conv = rn < 1e3 * a.tol;
       ++it;
       break;
     }
     double* bnew = bb + (size_t)m * D;
-    for (int e = lane; e < D; e += 64) bnew[e] = rv[e] / nr;
+    for (int e = tid; e < D; e += kDavBlock) bnew[e] = rv[e] / nr;
     ++m;
     __syncthreads();
   }
@@ -271,8 +309,8 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
   const double sgn = (xv[0] < 0.0) ? -1.0 : 1.0;
   const double c0 = sgn * xv[0];
   if (civ)
-    for (int e = lane; e < D; e += 64) civ[e] = sgn * xv[e];
-  if (lane == 0) {
+    for (int e = tid; e < D; e += kDavBlock) civ[e] = sgn * xv[e];
+  if (tid == 0) {
     a.energy[k] = theta;
     a.c0[k] = c0;
     a.iters[k] = it;
@@ -284,12 +322,12 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
   constexpr int nv = NA - NE, ne = NE;
   double* amp = a.amp + a.amp_off[k];
   const double inv = (c0 > 0.0) ? sgn / c0 : 0.0;
-  for (int e = lane; e < ne * nv; e += 64) {
+  for (int e = tid; e < ne * nv; e += kDavBlock) {
     const int i = e / nv, b = e % nv;
     amp[e] = S.exc_sgn[i][b] * xv[S.exc_str[i][b] * NS] * inv;
   }
   constexpr int nt1 = ne * nv;
-  for (int e = lane; e < nt1 * nt1; e += 64) {
+  for (int e = tid; e < nt1 * nt1; e += kDavBlock) {
     const int b = e % nv, av = e / nv % nv, j = e / (nv * nv) % ne, i = e / (nv * nv * ne);
     const double ta = S.exc_sgn[i][av] * xv[S.exc_str[i][av] * NS] * inv;
     const double tb = S.exc_sgn[j][b] * xv[S.exc_str[j][b] * NS] * inv;
@@ -299,7 +337,7 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
   }
 }
 
-__global__ __launch_bounds__(64) void k_davidson(DavidsonArgs a) {
+__global__ __launch_bounds__(kDavBlock) void k_davidson(DavidsonArgs a) {
   extern __shared__ double sm[];
   const int k = blockIdx.x;
   const SpaceDev sp = a.spaces[k];
@@ -312,7 +350,7 @@ __global__ __launch_bounds__(64) void k_davidson(DavidsonArgs a) {
 }  // namespace
 
 void launch_davidson(const DavidsonArgs& a, int lds_doubles, hipStream_t st) {
-  k_davidson<<<a.K, 64, (size_t)lds_doubles * sizeof(double), st>>>(a);
+  k_davidson<<<a.K, kDavBlock, (size_t)lds_doubles * sizeof(double), st>>>(a);
 }
 
 }  // namespace qf

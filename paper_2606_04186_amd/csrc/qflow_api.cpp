@@ -175,7 +175,7 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
     ctx->h_ci_off[k + 1] = ctx->h_ci_off[k] + D;
     const int nrep = s.n_o * (1 + na - s.n_o);
     const int need = na * na * na * na + (int)(ns * ns) + 4 * (int)D + 3 * kMaxSub * kMaxSub +
-                     kMaxSub + 4 + ((int)ns * nrep + 1) / 2;
+                     kMaxSub + 4 + 4 * kMaxSub + ((int)ns * nrep + 1) / 2;
     lds = std::max(lds, need);
     na_max = std::max(na_max, na);
     slots_max = std::max(slots_max, ctx->task_slots[s.n_o - 2]);
