@@ -39,15 +39,14 @@ __device__ void load_active(const SpaceDev& sp, int n, int o, Active& A) {
 // Per-space tables of the marked [E,sigma] evaluation (see MarkTables and
 // mark_table_entry).  The two-body tables D_j(t;a,b,c) = sum_{x external}
 // f[x][t] sigma(.. x in slot j ..) vanish unless b and c share a class and a
-// is in the other one, and x then runs over the externals of a's class.  D_0
-// and D_1 are summed directly; anti-Hermiticity of sigma gives the others:
+// is in the other one, and x then runs over the externals of a's class.  Only
+// D_0 and D_1 are stored: anti-Hermiticity of sigma gives the others,
 // D_2(t;a,b,c) = -D_0(t;c,a,b), D_3(t;a,b,c) = -D_1(t;c,a,b).
 __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
                                                   const SpaceDev* __restrict__ spaces,
                                                   double* tab, int64_t tab_stride) {
   __shared__ Active A;
   constexpr int kNa = 6;   // largest supported space, (3,3)
-  __shared__ double d01[2 * kNa * kNa * kNa * kNa];
   const int k = blockIdx.x;
   const SpaceDev sp = spaces[k];
   load_active(sp, g.n, g.o, A);
@@ -61,7 +60,7 @@ __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
   // tau1, tau2, D1
   for (int e = threadIdx.x; e < s1 + s2 + s3; e += blockDim.x)
     out[e] = mark_table_entry(s, g.f, A, e);
-  // D_0, D_1
+  // D_0, D_1 (D_2 and D_3 are read from them with permuted indices)
   for (int e = threadIdx.x; e < 2 * n4; e += blockDim.x) {
     const int j = e / n4, t = e / n3 % na, a = e / n2 % na, b = e / na % na, c = e % na;
     const bool ao = a < nocc, bo = b < nocc, co = c < nocc;
@@ -88,14 +87,7 @@ __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
         }
       }
     }
-    d01[e] = acc;
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < 4 * n4; e += blockDim.x) {
-    const int j = e / n4, r = e % n4;
-    const int t = r / n3, a = r / n2 % na, b = r / na % na, c = r % na;
-    const double x = (j < 2) ? d01[r + j * n4] : -d01[(j - 2) * n4 + ((t * na + c) * na + a) * na + b];
-    out[s1 + s2 + s3 + e] = x;
+    out[s1 + s2 + s3 + e] = acc;
   }
   // H_N and Yg restricted to the space (local indices): [f_A | V_A | y1_A | y2_A]
   double* xo = out + s1 + s2 + s3 + s4;

@@ -796,7 +796,7 @@ QF_HD int mark_sizes(int na, int* tau1, int* tau2, int* d1, int* d2) {
   *tau1 = na * na;
   *tau2 = na * na * na * na;
   *d1 = 2 * na * na;
-  *d2 = 4 * na * na * na * na;
+  *d2 = 2 * na * na * na * na;   // D_0 and D_1; D_2, D_3 follow by anti-Hermiticity
   return *tau1 + *tau2 + *d1 + *d2;
 }
 
@@ -833,11 +833,13 @@ struct MarkedSigma {
   QF_HD double two(int p, int q, int r, int s) const {
     const int na = T.na, n3 = na * na * na;
     int j, t, a, b, c;
+    // D_2(t;a,b,c) = -D_0(t;c,a,b) and D_3(t;a,b,c) = -D_1(t;c,a,b)
+    double sg = 1.0;
     if (p < 0) { j = 0; t = -1 - p; a = loc(q); b = loc(r); c = loc(s); }
     else if (q < 0) { j = 1; t = -1 - q; a = loc(p); b = loc(r); c = loc(s); }
-    else if (r < 0) { j = 2; t = -1 - r; a = loc(p); b = loc(q); c = loc(s); }
-    else { j = 3; t = -1 - s; a = loc(p); b = loc(q); c = loc(r); }
-    return T.D2[(j * na + t) * n3 + (a * na + b) * na + c];
+    else if (r < 0) { j = 0; t = -1 - r; a = loc(s); b = loc(p); c = loc(q); sg = -1.0; }
+    else { j = 1; t = -1 - s; a = loc(r); b = loc(p); c = loc(q); sg = -1.0; }
+    return sg * T.D2[(j * na + t) * n3 + (a * na + b) * na + c];
   }
 };
 
@@ -863,9 +865,7 @@ QF_HD double mark_table_entry(const Sigma& s, const double* f, const Active& A, 
   const int j = e / (na * n3), t = A.orb[e / n3 % na];
   const int a = A.orb[e / n2 % na], b = A.orb[e / na % na], c = A.orb[e % na];
   return extern_sum([&](int x) {
-    double sv = (j == 0) ? s.two(x, a, b, c)
-              : (j == 1) ? s.two(a, x, b, c)
-              : (j == 2) ? s.two(a, b, x, c) : s.two(a, b, c, x);
+    const double sv = (j == 0) ? s.two(x, a, b, c) : s.two(a, x, b, c);
     return f[x * n + t] * sv;
   });
 }
