@@ -208,6 +208,11 @@ __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restric
           for (int t = 0; t < o; ++t) x -= g[t * n + s_] * tpq[r * o + t];
       }
     }
+    // entries that vanish for every sigma are never written (the arrays are
+    // zeroed once when allocated)
+    const bool nz = (or_ == os && (or_ ? (!oq || !op) : (oq || op))) ||
+                    (op == oq && (op ? (!os || !or_) : (os || or_)));
+    if (!nz) continue;
     U[row + e] = x;
     if (wv && !or_ && !os && p <= q)
       wv[tri_row(p, q, n) * v * v + (size_t)(r - o) * v + (s_ - o)] = (WT)x;
@@ -396,7 +401,7 @@ constexpr int kZChunk = 16;
 template <int W>
 __global__ __launch_bounds__(256) void k_sigma1_x(const double* __restrict__ X,
                                                   const double* __restrict__ t1, int n, int o,
-                                                  double* Z) {
+                                                  int skip_vvv, double* Z) {
   typedef double vw __attribute__((ext_vector_type(W)));
   extern __shared__ double ts[];   // t1, o*v
   const int v = n - o;
@@ -408,8 +413,16 @@ __global__ __launch_bounds__(256) void k_sigma1_x(const double* __restrict__ X,
   auto ld = [&](int t) { return *reinterpret_cast<const vw*>(X + (size_t)t * n3 + c); };
   auto st = [&](int p, vw x) { *reinterpret_cast<vw*>(Z + (size_t)p * n3 + c) = x; };
   // p occupied: Z[p][c] = -sum_{t virtual} t1[p][t-o] X[t][c]; the column of
-  // X is read eight rows at a time to keep several loads in flight
-  for (int p0 = 0; p0 < o; p0 += kZChunk) {
+  // X is read eight rows at a time to keep several loads in flight.  With
+  // skip_vvv, X vanishes on all-virtual index quadruples (two-body part of
+  // [F, sigma]), so Z[p occ][c] is structurally zero for all-virtual columns
+  // c = (q,r,s) and stays as zeroed at allocation.
+  const size_t n2c = (size_t)n * n;
+  const auto all_vir = [&](size_t cc) {
+    return (int)(cc / n2c) >= o && (int)(cc / n % n) >= o && (int)(cc % n) >= o;
+  };
+  const bool skip = skip_vvv && all_vir(c) && all_vir(c + W - 1);
+  for (int p0 = 0; p0 < (skip ? 0 : o); p0 += kZChunk) {
     vw acc[kZChunk];
 #pragma unroll
     for (int i = 0; i < kZChunk; ++i) acc[i] = vw(0.0);
@@ -582,13 +595,16 @@ void launch_pack_ring_T(const double* t2, int o, int v, float* Ta, float* T22, h
   k_pack_ring_T<<<grid_for(ov * ov, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, Ta, T22);
 }
 
-void launch_sigma1_x(const double* X, const double* t1, int n, int o, double* Z, hipStream_t st) {
+void launch_sigma1_x(const double* X, const double* t1, int n, int o, bool skip_vvv, double* Z,
+                     hipStream_t st) {
   const size_t n3 = (size_t)n * n * n;
   const size_t lds = (size_t)o * (n - o) * sizeof(double);
   if (n3 % 2 == 0)
-    k_sigma1_x<2><<<(unsigned)((n3 / 2 + kBlock - 1) / kBlock), kBlock, lds, st>>>(X, t1, n, o, Z);
+    k_sigma1_x<2><<<(unsigned)((n3 / 2 + kBlock - 1) / kBlock), kBlock, lds, st>>>(
+        X, t1, n, o, skip_vvv ? 1 : 0, Z);
   else
-    k_sigma1_x<1><<<(unsigned)((n3 + kBlock - 1) / kBlock), kBlock, lds, st>>>(X, t1, n, o, Z);
+    k_sigma1_x<1><<<(unsigned)((n3 + kBlock - 1) / kBlock), kBlock, lds, st>>>(
+        X, t1, n, o, skip_vvv ? 1 : 0, Z);
 }
 
 void launch_pack_t2_vvoo(const double* t2, int o, int v, double* T, hipStream_t st) {

@@ -41,8 +41,11 @@ void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22,
 // the same operands rounded to FP32 (mixed-precision contractions)
 void launch_pack_ring_A(const double* X, int n, int o, float* Aa, float* A22, hipStream_t st);
 void launch_pack_ring_T(const double* t2, int o, int v, float* Ta, float* T22, hipStream_t st);
-// Z = sigma1 X over the first index (k_prep.hip, k_sigma1_x); n^4 doubles
-void launch_sigma1_x(const double* X, const double* t1, int n, int o, double* Z, hipStream_t st);
+// Z = sigma1 X over the first index (k_prep.hip, k_sigma1_x); n^4 doubles.
+// skip_vvv: X vanishes on all-virtual quadruples and Z was zeroed once, so the
+// structurally zero part of Z is not rewritten.
+void launch_sigma1_x(const double* X, const double* t1, int n, int o, bool skip_vvv, double* Z,
+                     hipStream_t st);
 // operands of the occupied-occupied ladder Lo (k_prep.hip)
 void launch_pack_t2_vvoo(const double* t2, int o, int v, double* T, hipStream_t st);
 void launch_pack_x_oooo(const double* X, int n, int o, double* Xo, hipStream_t st);

@@ -332,6 +332,9 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
                     nullptr, st);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[1], st));
   const int npair = n * (n + 1) / 2;   // ladder rows p <= q
+  // rows of Yg's ladder operand with p virtual (then q virtual too) vanish:
+  // the Yg ladder runs over the first o*n - o(o-1)/2 rows only
+  const int npo = o * n - o * (o - 1) / 2;
   const size_t n2p = (size_t)npair;
   if (bf3) {
     const Split tb = split_of(ctx->t2b, (size_t)o * o, v * v);
@@ -341,21 +344,21 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
     qf::launch_gemm_nt_bf16x3(wb.hi, wb.lo, tb.hi, tb.lo, P<double>(ctx->L), npair, o * o, kp, 1.0,
                               part, pcap, st);
     if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], st));
-    split(P<double>(ctx->wy), n2p, v * v, wyb, st);
-    qf::launch_gemm_nt_bf16x3(wyb.hi, wyb.lo, tb.hi, tb.lo, P<double>(ctx->LY), npair, o * o, kp,
-                              1.0, part, pcap, st);
+    split(P<double>(ctx->wy), (size_t)npo, v * v, Split{wyb.hi, wyb.hi + (size_t)npo * kp}, st);
+    qf::launch_gemm_nt_bf16x3(wyb.hi, wyb.hi + (size_t)npo * kp, tb.hi, tb.lo, P<double>(ctx->LY),
+                              npo, o * o, kp, 1.0, part, pcap, st);
   } else if (mixed) {
     qf::launch_cvt_f32(t2, P<float>(ctx->t2_32), ov * ov, st);
     qf::launch_gemm_nt_f32(P<float>(ctx->w32), P<float>(ctx->t2_32), P<double>(ctx->L), npair,
                            o * o, v * v, 1.0, part, pcap, st);
     if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], st));
-    qf::launch_gemm_nt_f32(P<float>(ctx->wy32), P<float>(ctx->t2_32), P<double>(ctx->LY), npair,
+    qf::launch_gemm_nt_f32(P<float>(ctx->wy32), P<float>(ctx->t2_32), P<double>(ctx->LY), npo,
                            o * o, v * v, 1.0, part, pcap, st);
   } else {
     qf::launch_gemm_nt_f64(P<double>(ctx->W), t2, P<double>(ctx->L), npair, o * o, v * v, 1.0,
                            part, pcap, st);
     if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], st));
-    qf::launch_gemm_nt_f64(P<double>(ctx->wy), t2, P<double>(ctx->LY), npair, o * o, v * v, 1.0,
+    qf::launch_gemm_nt_f64(P<double>(ctx->wy), t2, P<double>(ctx->LY), npo, o * o, v * v, 1.0,
                            part, pcap, st);
   }
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[3], st));
@@ -437,8 +440,8 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
                          o * o, o * o, 1.0, part, pcap, st);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[6], ctx->stream));
   // Z = sigma1 X of H_N and Yg
-  qf::launch_sigma1_x(P<double>(ctx->V), t1, n, o, P<double>(ctx->z_h), st);
-  qf::launch_sigma1_x(P<double>(ctx->y2), t1, n, o, P<double>(ctx->z_y), st);
+  qf::launch_sigma1_x(P<double>(ctx->V), t1, n, o, false, P<double>(ctx->z_h), st);
+  qf::launch_sigma1_x(P<double>(ctx->y2), t1, n, o, true, P<double>(ctx->z_y), st);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -588,6 +591,13 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
                                            2 * (size_t)((v + 7) / 8) * n2})));
   QF_TRY(ensure(ctx, ctx->z_h, sizeof(double) * n4));
   QF_TRY(ensure(ctx, ctx->z_y, sizeof(double) * n4));
+  // Yg's two-body part, its ladder rows, LY and Z of Yg vanish on fixed
+  // orbital-class patterns for every sigma; the kernels never write those
+  // entries, so they are zeroed here once
+  qf::launch_fill(P<double>(ctx->y2), n4, 0.0, ctx->stream);
+  qf::launch_fill(P<double>(ctx->wy), n2p * v * v, 0.0, ctx->stream);
+  qf::launch_fill(P<double>(ctx->LY), n2p * o * o, 0.0, ctx->stream);
+  qf::launch_fill(P<double>(ctx->z_y), n4, 0.0, ctx->stream);
   QF_TRY(ensure(ctx, ctx->dtpart, sizeof(double) * qf::kFinishParts));
   QF_TRY(ensure(ctx, ctx->a12, sizeof(double) * (2 * n * v + n * o)));
   QF_TRY(ensure(ctx, ctx->t2T, sizeof(double) * 3 * o * o * v * v));
