@@ -15,7 +15,9 @@ ones whose ladder and ring contractions take FP32 operands (FP32 matrix
 cores) or BF16x3 hi+lo operands (BF16 matrix cores), with FP64 sums and FP64
 everywhere else.  `value` is the rate of the fastest mixed path whose mean and
 per-space energies stay within 1e-6 Eh of the FP64 path's (the FP64 rate if
-none does); every path is in `modes`.  Prints one JSON line.
+none does); every path is in `modes`.  Each path runs twice from the MP2
+start: eagerly with HIP events between stages (stage times, roofline), then
+as one captured HIP graph per step (the rate).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -46,6 +48,10 @@ def parse():
                     help="all: time the FP64 path and both mixed paths (FP32 or BF16x3 ladder "
                          "and ring products, FP64 sums) from the same start and report the "
                          "fastest mixed one whose energies stay within 1e-6 Eh of FP64")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager launches only (default: the step as a captured HIP graph "
+                         "gives `value`, an eager pass with per-stage events gives the stage "
+                         "times and the roofline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-spaces", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -96,10 +102,13 @@ def main():
         print(f"[bench] copied {nb} bytes device to device", file=sys.stderr, flush=True)
         del src, dst
 
-    def run_path(precision):
+    def run_path(precision, graph):
         """W untimed and K timed macro-iterations from the MP2 start."""
         ctx.mp2_guess(t1, t2)
         tag = {qf.FP64: "fp64", qf.FP32: "fp32", qf.BF16X3: "bf16x3"}[precision]
+        if graph:
+            precision |= qf.GRAPH
+            tag += " graph"
         print(f"[bench] {tag}: warmup", file=sys.stderr, flush=True)
         for _ in range(args.warmup):
             ctx.flow_step(spaces, d1, d2, t1, t2, energy, precision)
@@ -121,7 +130,15 @@ def main():
     runs = {}
     for key, flag in (("fp64", qf.FP64), ("fp32", qf.FP32), ("bf16x3", qf.BF16X3)):
         if args.precision in ("all", key):
-            runs[key] = run_path(flag)
+            # the eager pass: per-stage HIP events (stage times, roofline)
+            runs[key] = run_path(flag, False)
+            runs[key]["ms_eager"] = runs[key]["ms"]
+            if not args.no_graph:
+                # the graph pass: the rate; same start, same kernels
+                g = run_path(flag, True)
+                runs[key]["ms"] = g["ms"]
+                runs[key]["graph_total_ms"] = g["stage_ms"]["total"]
+                runs[key]["graph_vs_eager_dE"] = abs(g["e_mean"] - runs[key]["e_mean"])
     dE = {}
     if "fp64" in runs:
         for key in ("fp32", "bf16x3"):
@@ -141,10 +158,12 @@ def main():
     # ring launches (six per step: two ladders, two Ga rings, two G22 rings):
     # algorithmic flops per step over their HIP-event time in the timed region.
     ov = o * v
-    f_ladder = 2.0 * (n * (n + 1) // 2) * (o * o) * (v * v)   # rows p <= q
+    f_ladder = 2.0 * (n * (n + 1) // 2) * (o * o) * (v * v)   # H_N: rows p <= q
+    # [F,sigma]'s two-body part vanishes for p, q both virtual: o*n - o(o-1)/2 rows
+    f_ladder_y = 2.0 * (o * n - o * (o - 1) // 2) * (o * o) * (v * v)
     f_ga = 2.0 * (n * n) * ov * (2 * ov)
     f_g22 = 2.0 * (n * n) * ov * ov
-    gemm_flops = 2 * f_ladder + 2 * f_ga + 2 * f_g22
+    gemm_flops = f_ladder + f_ladder_y + 2 * f_ga + 2 * f_g22
     gemm_ms = st["ladder_h"] + st["ladder_yg"] + st["ring_gemm"]
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
     roof = {"kernel": {"fp64": "k_gemm_f64", "fp32": "k_gemm_f32", "bf16x3": "k_gemm_bf16x3"}[use],
@@ -157,12 +176,15 @@ def main():
     for key, r in runs.items():
         mms = r["stage_ms"]["ladder_h"] + r["stage_ms"]["ladder_yg"] + r["stage_ms"]["ring_gemm"]
         modes[key] = {"value": 1e3 / r["ms"], "ms_per_step": r["ms"], "e_mean": r["e_mean"],
+                      "ms_per_step_eager": r["ms_eager"],
+                      "graph_total_ms": r.get("graph_total_ms"),
+                      "graph_vs_eager_abs_dE_mean": r.get("graph_vs_eager_dE"),
                       "residual_gemm_tflops": gemm_flops / (mms * 1e-3) / 1e12,
                       "stage_ms": r["stage_ms"]}
     for key, (dm, dsp) in dE.items():
         modes[key]["abs_dE_mean"] = dm
         modes[key]["abs_dE_max_space"] = dsp
-    dominant = max(st, key=st.get)
+    dominant = max((k_ for k_ in st if k_ != "total"), key=st.get)
 
     cpu = None
     if not args.no_cpu_baseline:

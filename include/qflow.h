@@ -63,7 +63,10 @@ typedef enum { QFLOW_FP64 = 0, QFLOW_FP32 = 1, QFLOW_BF16X3 = 2 } qflow_precisio
  * and ring contractions: FP64; FP32 operands with FP64 sums; BF16x3 = hi+lo
  * bf16 operands with FP32 partial and FP64 sums). */
 enum {
-  QFLOW_UNOWNED_FROZEN = 1 << 4 /* amplitudes no space owns keep their value */
+  QFLOW_UNOWNED_FROZEN = 1 << 4, /* amplitudes no space owns keep their value */
+  QFLOW_GRAPH = 1 << 5           /* run the step's device work as a captured HIP graph,
+                                    re-captured when K, flags, the array pointers or
+                                    the context's buffers change */
 };
 
 /* Create a context on HIP device `device`; hip_stream is a hipStream_t to
@@ -174,8 +177,10 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
  * events on the context's stream), in the order: [F,sigma] intermediate,
  * ladder contraction of H_N, ladder contraction of [F,sigma], ring operand
  * packing, ring contractions (four matrix-core GEMMs), one-body ring terms,
- * sigma1 applied to the two-body parts, residual, build_heff, solve, update.  n is the capacity of ms (host).  Returns the
- * count written. */
+ * sigma1 applied to the two-body parts, residual, build_heff, solve, update,
+ * then the whole step.  A step run with QFLOW_GRAPH reports -1 for the
+ * stages and only the whole.  n is the capacity of ms (host).  Returns the
+ * count written (at most 12). */
 int qflow_last_timings(const qflow_ctx* ctx, float* ms, int n);
 
 /* Algorithm 1 (coverage-driven active-space sampling), host only.

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libqflow.so")
 
 FP64, FP32, BF16X3 = 0, 1, 2
 UNOWNED_FROZEN = 1 << 4
+GRAPH = 1 << 5
 
 SPACE_DTYPE = np.dtype([("n_o", "<i4"), ("n_v", "<i4"), ("orb", "<i4", (8,))])
 
@@ -192,10 +193,11 @@ class Context:
         return em.value, md.value
 
     STAGES = ("yg", "ladder_h", "ladder_yg", "ring_pack", "ring_gemm", "ring_j", "sigma1_x",
-              "residual", "heff", "solve", "update")
+              "residual", "heff", "solve", "update", "total")
 
     def last_timings(self):
-        """Per-stage device milliseconds of the last flow_step (STAGES order)."""
+        """Device milliseconds of the last flow_step per stage and in total
+        (STAGES order; stages are -1 for a graph replay)."""
         ms = np.zeros(len(self.STAGES), dtype=np.float32)
         c = lib().qflow_last_timings(self.h, _ptr(ms), len(self.STAGES))
         return dict(zip(self.STAGES, ms[:c].tolist()))

@@ -625,6 +625,16 @@ void launch_pack_j_B(const double* t2, int o, int v, double* B1, double* B2, hip
   k_pack_j_B<<<grid_for(total, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, B1, B2);
 }
 
+__global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+void launch_copy(const double* src, double* dst, size_t count, hipStream_t st) {
+  k_copy<<<grid_for(count, kBlock, 65536), kBlock, 0, st>>>(src, dst, count);
+}
+
 void launch_fill(double* x, size_t count, double value, hipStream_t st) {
   k_fill<<<grid_for(count, kBlock, 65536), kBlock, 0, st>>>(x, count, value);
 }

@@ -35,6 +35,7 @@ void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12,
 void launch_yg1(const double* f, const double* t1, const double* t2, int n, int o, double* y1,
                 double* scal, hipStream_t st);
 void launch_fill(double* x, size_t count, double value, hipStream_t st);
+void launch_copy(const double* src, double* dst, size_t count, hipStream_t st);
 // ring intermediates (layouts in qflow_eval.h, DenseOp)
 void launch_pack_ring_A(const double* X, int n, int o, double* Aa, double* A22, hipStream_t st);
 void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22, hipStream_t st);

@@ -29,6 +29,16 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+struct GraphKey {
+  int32_t K = -1, flags = 0;
+  const void *t1 = nullptr, *t2 = nullptr, *o1 = nullptr, *o2 = nullptr, *energy = nullptr;
+  uint64_t epoch = 0;
+  bool operator==(const GraphKey& b) const {
+    return K == b.K && flags == b.flags && t1 == b.t1 && t2 == b.t2 && o1 == b.o1 &&
+           o2 == b.o2 && energy == b.energy && epoch == b.epoch;
+  }
+};
+
 }  // namespace
 
 struct qflow_ctx {
@@ -76,7 +86,12 @@ struct qflow_ctx {
   int na_max = 0;
   int slots_max = 0;
   hipEvent_t ev[kStages + 1] = {};
+  // captured flow step (QFLOW_GRAPH) and what it was captured for
+  hipGraphExec_t graph_exec = nullptr;
+  GraphKey graph_key{};
+  uint64_t epoch = 0;   // bumped whenever a device buffer is (re)allocated
   float stage_ms[kStages] = {};
+  float total_ms = 0.f;
   bool timed = false;
 };
 
@@ -108,6 +123,7 @@ int ensure(qflow_ctx* ctx, DevBuf& b, size_t bytes) {
     return fail(ctx, QFLOW_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   }
   b.bytes = bytes;
+  ++ctx->epoch;
   return QFLOW_OK;
 }
 
@@ -216,6 +232,7 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   // the host vectors must outlive the asynchronous copies
   QF_HIP(hipStreamSynchronize(ctx->stream));
   ctx->last_spaces.assign(spaces, spaces + K);
+  ++ctx->epoch;   // launch shapes of the per-space kernels follow the list
   return QFLOW_OK;
 }
 
@@ -520,6 +537,7 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->out2,   &ctx->partial, &ctx->tasks, &ctx->mtab};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
   for (auto& ev : ctx->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -632,6 +650,7 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_HIP(hipMemcpy(ctx->scal.p, sc, sizeof(sc), hipMemcpyHostToDevice));
   ctx->loaded = true;
   ctx->h32_ready = false;
+  ++ctx->epoch;   // sizes may have changed without a reallocation
   ctx->hb_ready = false;
   ctx->last_spaces.clear();
   return QFLOW_OK;
@@ -749,6 +768,48 @@ int run_solve(qflow_ctx* ctx, int32_t K, const double* heff, const int64_t* heff
   return QFLOW_OK;
 }
 
+// The device work of one flow step on ctx->stream: no allocation and no host
+// synchronisation, so that it can be captured into a graph.
+// With `timed` the stage boundaries are marked by events (not under capture).
+int enqueue_step(qflow_ctx* ctx, int32_t K, const int32_t* owner1, const int32_t* owner2,
+                 double* t1, double* t2, double* energy, int precision, bool step, bool timed) {
+  const int n = ctx->n, o = ctx->o, v = ctx->v;
+  hipStream_t st = ctx->stream;
+  ctx->timed = timed;
+  if (timed) QF_HIP(hipEventRecord(ctx->ev[0], st));
+  int r = prepare(ctx, t1, t2, precision);
+  if (r == QFLOW_OK) {
+    if (timed) QF_HIP(hipEventRecord(ctx->ev[7], st));
+    r = run_heff(ctx, K, t1, t2, P<double>(ctx->heff), P<int64_t>(ctx->heff_off));
+  }
+  if (r == QFLOW_OK) {
+    if (timed) QF_HIP(hipEventRecord(ctx->ev[9], st));
+    r = run_solve(ctx, K, P<double>(ctx->heff), P<int64_t>(ctx->heff_off), P<double>(ctx->energy),
+                  P<double>(ctx->c0), P<double>(ctx->amp), P<int64_t>(ctx->amp_off),
+                  P<double>(ctx->ci), P<int64_t>(ctx->ci_off), P<int32_t>(ctx->iters),
+                  P<int32_t>(ctx->status), 1e-10, 200);
+  }
+  ctx->timed = false;
+  if (r != QFLOW_OK) return r;
+  if (timed) QF_HIP(hipEventRecord(ctx->ev[10], st));
+  qf::launch_update(t1, t2, P<double>(ctx->r1), P<double>(ctx->r2), P<double>(ctx->f), owner1,
+                    owner2, n, o, step, P<double>(ctx->t1n), P<double>(ctx->t2n), st);
+  if (K > 0)
+    qf::launch_scatter_owned(P<SpaceDev>(ctx->spaces), P<double>(ctx->amp),
+                             P<int64_t>(ctx->amp_off), P<int32_t>(ctx->status), owner1, owner2,
+                             n, o, K, P<double>(ctx->t1n), P<double>(ctx->t2n), st);
+  qf::launch_finish(P<double>(ctx->energy), K, t1, t2, P<double>(ctx->t1n), P<double>(ctx->t2n),
+                    o, v, P<double>(ctx->dtpart), P<double>(ctx->out2), st);
+  // the new pool and energies into the caller's arrays (copy kernels, no
+  // memory-copy nodes in a captured graph)
+  qf::launch_copy(P<double>(ctx->t1n), t1, (size_t)o * v, st);
+  qf::launch_copy(P<double>(ctx->t2n), t2, (size_t)o * o * v * v, st);
+  if (K > 0) qf::launch_copy(P<double>(ctx->energy), energy, (size_t)K, st);
+  QF_HIP(hipGetLastError());
+  if (timed) QF_HIP(hipEventRecord(ctx->ev[11], st));
+  return QFLOW_OK;
+}
+
 }  // namespace
 
 int qflow_build_heff(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const double* t1,
@@ -810,72 +871,71 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
   QF_TRY(check_spaces(ctx, K, spaces));
   if (!owner1 || !owner2 || !t1 || !t2 || !e_mean || !max_dt || (K > 0 && !energy))
     return fail(ctx, QFLOW_E_INVALID_ARG, "NULL argument");
-  QF_TRY(upload_spaces(ctx, K, spaces));
   const int precision = flags & 15;
+  if (precision != QFLOW_FP64 && precision != QFLOW_FP32 && precision != QFLOW_BF16X3)
+    return fail(ctx, QFLOW_E_UNSUPPORTED, "unknown precision");
+  QF_TRY(upload_spaces(ctx, K, spaces));
+  // allocations and one-time conversions happen here, outside any capture
+  if (precision == QFLOW_FP32) QF_TRY(ensure_mixed(ctx));
+  if (precision == QFLOW_BF16X3) QF_TRY(ensure_bf16(ctx));
   const bool step = !(flags & QFLOW_UNOWNED_FROZEN);
-  const int n = ctx->n, o = ctx->o, v = ctx->v;
   hipStream_t st = ctx->stream;
-  ctx->timed = true;
-  QF_HIP(hipEventRecord(ctx->ev[0], st));
-  int r = prepare(ctx, t1, t2, precision);
-  if (r != QFLOW_OK) {
-    ctx->timed = false;
-    return r;
+  if (flags & QFLOW_GRAPH) {
+    const GraphKey key{K, flags, t1, t2, owner1, owner2, energy, ctx->epoch};
+    if (!ctx->graph_exec || !(key == ctx->graph_key)) {
+      if (ctx->graph_exec) {
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+      }
+      QF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      const int r = enqueue_step(ctx, K, owner1, owner2, t1, t2, energy, precision, step, false);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(st, &graph);
+      if (r != QFLOW_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+      }
+      if (e != hipSuccess)
+        return fail(ctx, QFLOW_E_DEVICE, std::string("stream capture: ") + hipGetErrorString(e));
+      const hipError_t ei = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        ctx->graph_exec = nullptr;
+        return fail(ctx, QFLOW_E_DEVICE, std::string("graph instantiation: ") +
+                                             hipGetErrorString(ei));
+      }
+      ctx->graph_key = key;
+    }
+    QF_HIP(hipEventRecord(ctx->ev[0], st));
+    QF_HIP(hipGraphLaunch(ctx->graph_exec, st));
+    QF_HIP(hipEventRecord(ctx->ev[kStages], st));
+  } else {
+    QF_TRY(enqueue_step(ctx, K, owner1, owner2, t1, t2, energy, precision, step, true));
   }
-  QF_HIP(hipEventRecord(ctx->ev[7], st));
-  r = run_heff(ctx, K, t1, t2, P<double>(ctx->heff), P<int64_t>(ctx->heff_off));
-  if (r != QFLOW_OK) {
-    ctx->timed = false;
-    return r;
-  }
-  QF_HIP(hipEventRecord(ctx->ev[9], st));
-  r = run_solve(ctx, K, P<double>(ctx->heff), P<int64_t>(ctx->heff_off), P<double>(ctx->energy),
-                P<double>(ctx->c0), P<double>(ctx->amp), P<int64_t>(ctx->amp_off),
-                P<double>(ctx->ci), P<int64_t>(ctx->ci_off), P<int32_t>(ctx->iters),
-                P<int32_t>(ctx->status), 1e-10, 200);
-  ctx->timed = false;
-  if (r != QFLOW_OK) return r;
-  QF_HIP(hipEventRecord(ctx->ev[10], st));
-  qf::launch_update(t1, t2, P<double>(ctx->r1), P<double>(ctx->r2), P<double>(ctx->f), owner1,
-                    owner2, n, o, step, P<double>(ctx->t1n), P<double>(ctx->t2n), st);
-  if (K > 0)
-    qf::launch_scatter_owned(P<SpaceDev>(ctx->spaces), P<double>(ctx->amp),
-                             P<int64_t>(ctx->amp_off), P<int32_t>(ctx->status), owner1, owner2,
-                             n, o, K, P<double>(ctx->t1n), P<double>(ctx->t2n), st);
-  qf::launch_finish(P<double>(ctx->energy), K, t1, t2, P<double>(ctx->t1n), P<double>(ctx->t2n),
-                    o, v, P<double>(ctx->dtpart), P<double>(ctx->out2), st);
-  QF_HIP(hipGetLastError());
-  QF_HIP(hipMemcpyAsync(t1, ctx->t1n.p, sizeof(double) * o * v, hipMemcpyDeviceToDevice, st));
-  QF_HIP(hipMemcpyAsync(t2, ctx->t2n.p, sizeof(double) * (size_t)o * o * v * v,
-                        hipMemcpyDeviceToDevice, st));
-  if (K > 0)
-    QF_HIP(hipMemcpyAsync(energy, ctx->energy.p, sizeof(double) * K, hipMemcpyDeviceToDevice, st));
-  QF_HIP(hipEventRecord(ctx->ev[11], st));
   double out[2];
   QF_HIP(hipMemcpyAsync(out, ctx->out2.p, sizeof(out), hipMemcpyDeviceToHost, st));
   QF_HIP(hipStreamSynchronize(st));
   *e_mean = out[0];
   *max_dt = out[1];
   // stage times: Yg | ladder GEMM (H) | ladder GEMM (Yg) | ring packing | ring GEMMs | J |
-  // Z | residual | heff | solve | update
-  int pairs[kStages][2];
+  // Z | residual | heff | solve | update; a graph replay is timed as a whole
   for (int s = 0; s < kStages; ++s) {
-    pairs[s][0] = s;
-    pairs[s][1] = s + 1;
-  }
-  for (int s = 0; s < kStages; ++s) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, ctx->ev[pairs[s][0]], ctx->ev[pairs[s][1]]) != hipSuccess)
+    float ms = -1.f;
+    if (!(flags & QFLOW_GRAPH) &&
+        hipEventElapsedTime(&ms, ctx->ev[s], ctx->ev[s + 1]) != hipSuccess)
       ms = -1.f;
     ctx->stage_ms[s] = ms;
   }
+  float total = -1.f;
+  if (hipEventElapsedTime(&total, ctx->ev[0], ctx->ev[kStages]) != hipSuccess) total = -1.f;
+  ctx->total_ms = total;
   return QFLOW_OK;
 }
 
 int qflow_last_timings(const qflow_ctx* ctx, float* ms, int n) {
   if (!ctx || !ms) return 0;
-  const int c = std::min(n, kStages);
-  for (int s = 0; s < c; ++s) ms[s] = ctx->stage_ms[s];
+  const int c = std::min(n, kStages + 1);
+  for (int s = 0; s < c; ++s) ms[s] = s < kStages ? ctx->stage_ms[s] : ctx->total_ms;
   return c;
 }
 

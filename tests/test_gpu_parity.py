@@ -354,3 +354,51 @@ def test_symmetry_and_argument_errors():
         ctx.build_heff(sp, dev(np.zeros((o, 5))), dev(np.zeros((o, o, 5, 5))), heff,
                        np.array([0, 1333], dtype=np.int64))
     assert e.value.code == -8
+
+
+def test_flow_step_graph_matches_oracle():
+    """The captured step (QFLOW_GRAPH) against the oracle."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    _flow_parity(24, 4, 132, 12, 2, "mp2", flags=qf.GRAPH)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_flow_step_graph_replays_match_eager(prec):
+    """Replays of the captured step against eager steps on a second context:
+    several replays with eager work and synchronisations between them, a
+    re-capture after the amplitude arrays move, and one after the space list
+    changes (same K).  Same kernels in the same order: equal results."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    flag = {"fp64": qf.FP64, "bf16x3": qf.BF16X3}[prec]
+    n, o, seed, K = 40, 5, 141, 8
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    v = n - o
+    t1, t2 = qflow.mp2_guess(pb.f, eri, o)
+    lists_a = _spaces_for(n, o, K, seed, pb.eps)
+    lists_b = _spaces_for(n, o, K, seed + 1, pb.eps)
+    ce, cg = context(h, eri, o), context(h, eri, o)
+    e1, e2, g1, g2 = dev(t1), dev(t2), dev(t1), dev(t2)
+    ee = torch.zeros(K, dtype=torch.float64, device="cuda")
+    eg = torch.zeros(K, dtype=torch.float64, device="cuda")
+    for step in range(7):
+        lists = lists_a if step < 5 else lists_b
+        o1, o2 = sampling.ownership(o, v, lists)
+        sp = qf.make_spaces(lists)
+        d1, d2 = dev(o1, torch.int32), dev(o2, torch.int32)
+        if step == 3:   # the pool moves to new arrays: the graph is captured again
+            g1, g2 = g1.clone(), g2.clone()
+        em_e, dt_e = ce.flow_step(sp, d1, d2, e1, e2, ee, flag)
+        junk = torch.randn(1 << 16, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        em_g, dt_g = cg.flow_step(sp, d1, d2, g1, g2, eg, flag | qf.GRAPH)
+        timings = cg.last_timings()
+        assert timings["total"] > 0 and timings["heff"] == -1
+        print(f"{prec} step {step}: E_mean {em_g:.12f} (junk {float(junk):.3f})")
+        assert abs(em_g - em_e) < 1e-12, step
+        assert abs(dt_g - dt_e) < 1e-12, step
+        assert torch.equal(eg, ee), step
+        assert (g1 - e1).abs().max().item() < 1e-12, step
+        assert (g2 - e2).abs().max().item() < 1e-12, step
