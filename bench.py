@@ -82,10 +82,19 @@ def main():
     ctx = qf.Context(0)
     ctx.load_integrals(torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev), o)
     e_ref, eps, _ = ctx.reference()
-    u = synth.sampling_stream(args.config).uniform(64 * K)
-    no, nv = cfg["sizes"][0]
-    spaces, _, _ = qf.sample_spaces(o, v, no, nv, eps, u, cap=K)
-    assert len(spaces) == K
+    # Algorithm 1 per size class (K / classes spaces each), merged and sorted
+    # by Delta eps
+    parts, deltas = [], []
+    Kc = K // len(cfg["sizes"])
+    for c, (no_c, nv_c) in enumerate(cfg["sizes"]):
+        u = synth.sampling_stream(args.config, c).uniform(64 * Kc)
+        sp_c, de_c, _ = qf.sample_spaces(o, v, no_c, nv_c, eps, u, cap=Kc)
+        assert len(sp_c) == Kc
+        parts.append(sp_c)
+        deltas.append(de_c)
+    order = np.argsort(np.concatenate(deltas), kind="stable")
+    spaces = np.concatenate(parts)[order]
+    sizes_txt = " + ".join(f"{Kc} ({a},{b})" for a, b in cfg["sizes"])
     o1, o2 = qf.build_owners(o, v, spaces)
     d1 = torch.from_numpy(o1).to(dev)
     d2 = torch.from_numpy(o2).to(dev)
@@ -204,8 +213,9 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16+f32+f64"}[use],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {n} orbitals ({o} occ, {v} virt), K={K} "
-                               f"({no},{nv}) active spaces, MP2 start",
-                   "n_orb": n, "n_occ": o, "K": K, "space": [no, nv],
+                               f"active spaces ({sizes_txt}), MP2 start",
+                   "n_orb": n, "n_occ": o, "K": K,
+                   "spaces": [list(sz) for sz in cfg["sizes"]],
                    "precision": {"fp64": "FP64",
                                  "fp32": "FP32 ladder and ring products with FP64 sums; FP64 "
                                          "elsewhere",

@@ -97,7 +97,7 @@ __device__ inline int rep_pq(int r) { return (r >> 8) & 255; }
 __device__ inline double rep_sgn(int r) { return (r >> 16) ? 1.0 : -1.0; }
 
 // One space of NA orbitals and NE electrons per spin, one block of
-// kDavBlock threads.
+// kDavBlock threads (memory layout: dav_layout).
 //
 // sigma = H c is evaluated with thread l < G*NS owning beta string
 // Ib = l % NS and the alpha strings Ia = l / NS, l / NS + G, ... (G =
@@ -116,13 +116,11 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
   const double* hin = a.heff + a.heff_off[k];
   const double Ec = hin[0];
   const double* h = hin + 1;
+  constexpr bool BIG = dav_layout(NA, NE, 1).big;
   double* g = sm;                       // N4
   double* Hs = g + N4;                  // NS^2
-  double* dg = Hs + NS * NS;            // D
-  double* xv = dg + D;                  // D  Ritz vector / sigma staging
-  double* hx = xv + D;                  // D
-  double* rv = hx + D;                  // D
-  double* Gm = rv + D;                  // MS^2
+  double* xv = Hs + NS * NS;            // D  Ritz vector / sigma input
+  double* Gm = xv + D;                  // MS^2
   double* Aw = Gm + MS * MS;            // MS^2
   double* Vw = Aw + MS * MS;            // MS^2
   double* yv = Vw + MS * MS;            // MS
@@ -131,6 +129,11 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
   int* rep = reinterpret_cast<int*>(red + NW * MS);   // NS*NR
   double* bb = a.work + a.work_off[k];  // MS x D
   double* ss = bb + (size_t)MS * D;     // MS x D
+  // diagonal, Ritz sigma and residual: LDS after the replacement lists, or
+  // the global work area after the sigma vectors
+  double* dg = BIG ? ss + (size_t)MS * D : reinterpret_cast<double*>(rep) + (NS * NR + 1) / 2;
+  double* hx = dg + D;
+  double* rv = hx + D;
   for (int e = tid; e < N4; e += kDavBlock) g[e] = hin[1 + N2 + e];
   for (int e = tid; e < NS * NR; e += kDavBlock) {
     const int I = e / NR, f = e % NR;
@@ -337,20 +340,32 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
   }
 }
 
-__global__ __launch_bounds__(kDavBlock) void k_davidson(DavidsonArgs a) {
+template <int NA, int NE>
+__global__ __launch_bounds__(kDavBlock) void k_davidson(DavidsonArgs a,
+                                                        const int32_t* __restrict__ idx) {
   extern __shared__ double sm[];
-  const int k = blockIdx.x;
+  const int k = idx[blockIdx.x];
   const SpaceDev sp = a.spaces[k];
-  if (sp.nocc == 3)
-    davidson_space<6, 3>(a, k, sp, sm);
-  else
-    davidson_space<4, 2>(a, k, sp, sm);
+  davidson_space<NA, NE>(a, k, sp, sm);
+}
+
+template <int NA, int NE>
+void launch_class(const DavidsonArgs& a, const int32_t* idx, int count, hipStream_t st) {
+  if (count <= 0) return;
+  const size_t bytes = (size_t)dav_layout(NA, NE, a.maxsub).lds * sizeof(double);
+  if (bytes > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_davidson<NA, NE>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  k_davidson<NA, NE><<<count, kDavBlock, bytes, st>>>(a, idx);
 }
 
 }  // namespace
 
-void launch_davidson(const DavidsonArgs& a, int lds_doubles, hipStream_t st) {
-  k_davidson<<<a.K, kDavBlock, (size_t)lds_doubles * sizeof(double), st>>>(a);
+void launch_davidson(const DavidsonArgs& a, const int32_t* cls_idx, const int* cls_off,
+                     hipStream_t st) {
+  launch_class<4, 2>(a, cls_idx + cls_off[0], cls_off[1] - cls_off[0], st);
+  launch_class<6, 3>(a, cls_idx + cls_off[1], cls_off[2] - cls_off[1], st);
+  launch_class<8, 4>(a, cls_idx + cls_off[2], cls_off[3] - cls_off[2], st);
 }
 
 }  // namespace qf

@@ -11,6 +11,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 #include "kcommon.h"
 #include "kernels.h"
 #include "qflow_cas.h"
@@ -46,7 +48,7 @@ __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
                                                   const SpaceDev* __restrict__ spaces,
                                                   double* tab, int64_t tab_stride) {
   __shared__ Active A;
-  constexpr int kNa = 6;   // largest supported space, (3,3)
+  constexpr int kNa = 8;   // largest supported space, (4,4)
   const int k = blockIdx.x;
   const SpaceDev sp = spaces[k];
   load_active(sp, g.n, g.o, A);
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
   int s1, s2, s3, s4;
   mark_sizes(sp.na, &s1, &s2, &s3, &s4);
   const int na = sp.na, nocc = sp.nocc, n2 = na * na, n3 = n2 * na, n4 = n3 * na;
-  if (na > kNa) return;   // the host admits (2,2) and (3,3) spaces only
+  if (na > kNa) return;   // the host admits (2,2), (3,3) and (4,4) spaces only
   double* out = tab + (int64_t)k * tab_stride;
   // tau1, tau2, D1
   for (int e = threadIdx.x; e < s1 + s2 + s3; e += blockDim.x)
@@ -112,13 +114,14 @@ __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
 template <int PART>
 __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __restrict__ scal,
                                                    const SpaceDev* __restrict__ spaces,
+                                                   const int32_t* __restrict__ idx,
                                                    const int64_t* __restrict__ heff_off,
                                                    const int32_t* __restrict__ tasks,
                                                    int task_stride, const double* __restrict__ tab,
                                                    int64_t tab_stride, double* heff) {
   __shared__ Active A;
   extern __shared__ double tl[];
-  const int k = blockIdx.x;
+  const int k = idx[blockIdx.x];
   const SpaceDev sp = spaces[k];
   load_active(sp, g.n, g.o, A);
   MarkTables T{};
@@ -261,30 +264,61 @@ int heff_table_stride(int na_max) {
   return mark_sizes(na_max, &s1, &s2, &s3, &s4) + 2 * (n2 + n2 * n2);
 }
 
+int heff_lds_doubles(int na) {
+  int s1, s2, s3, s4;
+  const int n2 = na * na;
+  const int mark = mark_sizes(na, &s1, &s2, &s3, &s4);
+  return std::max(mark, std::max(2 * (n2 + n2 * n2), n2 * n2 + n2 + 1));
+}
+
+namespace {
+template <class Kern>
+void allow_lds(Kern* kern, size_t bytes) {
+  if (bytes > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+}  // namespace
+
 void launch_heff(const double* f, const double* V, const double* y1, const double* y2,
                  const double* L, const double* LY, const RingOps& rings, const double* t1,
                  const double* t2, int n,
                  int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
-                 const int32_t* task_table, int task_stride, int slots_max, int K, int na_max,
+                 const int32_t* task_table, int task_stride, const int* task_slots,
+                 const int32_t* cls_idx, const int* cls_off, int K, int na_max,
                  double* tab, double* heff, hipStream_t st) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
               rings.z_h,  rings.z_y, rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
               rings.lo_h, rings.lo_y, rings.pf};
-  const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
-  dim3 grid(K, (slots_max + kBlock - 1) / kBlock);
-  int s1, s2, s3, s4;
-  const int mark = mark_sizes(na_max, &s1, &s2, &s3, &s4);
   const int tab_stride = heff_table_stride(na_max);
-  const int n2 = na_max * na_max;
-  const size_t lds01 = (size_t)2 * (n2 + n2 * n2) * sizeof(double);
   k_heff_tab<<<K, kBlock, 0, st>>>(g, spaces, tab, tab_stride);
-  k_heff_part<0><<<grid, kBlock, lds01, st>>>(g, scal, spaces, heff_off, task_table, task_stride,
-                                              tab, tab_stride, heff);
-  k_heff_part<1><<<grid, kBlock, lds01, st>>>(g, scal, spaces, heff_off, task_table, task_stride,
-                                              tab, tab_stride, heff);
-  k_heff_part<2><<<grid, kBlock, (size_t)mark * sizeof(double), st>>>(
-      g, scal, spaces, heff_off, task_table, task_stride, tab, tab_stride, heff);
+  // parts 0, 1, 2 per size class: its task count and LDS
+  for (int PART = 0; PART < 3; ++PART)
+    for (int c = 0; c < 3; ++c) {
+      const int count = cls_off[c + 1] - cls_off[c];
+      if (count <= 0) continue;
+      const int na = 2 * (c + 2), n2 = na * na;
+      int s1, s2, s3, s4;
+      const int mark = mark_sizes(na, &s1, &s2, &s3, &s4);
+      const size_t lds = (size_t)(PART == 2 ? mark : 2 * (n2 + n2 * n2)) * sizeof(double);
+      const dim3 grid(count, (task_slots[c] + kBlock - 1) / kBlock);
+      const int32_t* idx = cls_idx + cls_off[c];
+      if (PART == 0) {
+        allow_lds(&k_heff_part<0>, lds);
+        k_heff_part<0><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
+                                                  task_stride, tab, tab_stride, heff);
+      } else if (PART == 1) {
+        allow_lds(&k_heff_part<1>, lds);
+        k_heff_part<1><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
+                                                  task_stride, tab, tab_stride, heff);
+      } else {
+        allow_lds(&k_heff_part<2>, lds);
+        k_heff_part<2><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
+                                                  task_stride, tab, tab_stride, heff);
+      }
+    }
+  const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
   const size_t lds = (size_t)tasks * sizeof(double);
   k_heff_cas<<<K, kBlock, lds, st>>>(spaces, heff_off, heff);
 }

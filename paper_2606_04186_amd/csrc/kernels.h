@@ -96,14 +96,19 @@ void launch_residual(const double* f, const double* V, const double* y1, const d
                      double* part, double* r1, double* r2, double* e0, hipStream_t st);
 
 // per-space downfolded Hamiltonians in CAS form
+// The per-element kernels run one launch per size class (cls_idx / cls_off
+// as for launch_davidson; task_slots[c] = task count of class c).
 void launch_heff(const double* f, const double* V, const double* y1, const double* y2,
                  const double* L, const double* LY, const RingOps& rings, const double* t1,
                  const double* t2, int n,
                  int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
-                 const int32_t* task_table, int task_stride, int slots_max, int K, int na_max,
+                 const int32_t* task_table, int task_stride, const int* task_slots,
+                 const int32_t* cls_idx, const int* cls_off, int K, int na_max,
                  double* tab, double* heff, hipStream_t st);
 // doubles of per-space scratch tables for spaces of up to na_max orbitals
 int heff_table_stride(int na_max);
+// doubles of dynamic LDS the build of a space of na orbitals takes
+int heff_lds_doubles(int na);
 // output-element order of the per-space kernels (host; see strings.cpp)
 int build_tasks(int na, int ne, int32_t* out, int cap);
 constexpr int kTaskStride = 4608;   // >= padded task count of a (4,4) space
@@ -114,7 +119,7 @@ struct DavidsonArgs {
   const Strings* strings;     // one table per size class, indexed by nocc-2
   const double* heff;
   const int64_t* heff_off;
-  double* work;               // per space: 2*maxsub*D doubles
+  double* work;               // per space: dav_layout(...).work doubles
   const int64_t* work_off;
   double* energy;
   double* c0;
@@ -129,7 +134,30 @@ struct DavidsonArgs {
   int maxsub;
   int K;
 };
-void launch_davidson(const DavidsonArgs& a, int lds_doubles, hipStream_t st);
+// Memory of one space's solve (doubles): LDS holds the integrals, the
+// same-spin string Hamiltonian, the vector sigma reads, the subspace problem
+// and the replacement lists; the basis and its sigma vectors sit in the
+// space's global work area, and so do the diagonal, Ritz sigma and residual
+// vectors when they would not fit in LDS as well (the (4,4) class).
+struct DavLayout {
+  int lds;        // doubles of dynamic LDS
+  int64_t work;   // doubles of global work
+  bool big;       // diagonal / Ritz sigma / residual vectors in global memory
+};
+constexpr int kDavBigDets = 1024;
+__host__ __device__ constexpr DavLayout dav_layout(int na, int ne, int maxsub) {
+  int ns = 1;
+  for (int i = 0; i < ne; ++i) ns = ns * (na - i) / (i + 1);
+  const int D = ns * ns, nrep = ne * (1 + na - ne), n4 = na * na * na * na;
+  const bool big = D > kDavBigDets;
+  const int lds = n4 + ns * ns + D + 3 * maxsub * maxsub + maxsub + 4 + 4 * maxsub +
+                  (ns * nrep + 1) / 2 + (big ? 0 : 3 * D);
+  return DavLayout{lds, (int64_t)(2 * maxsub + (big ? 3 : 0)) * D, big};
+}
+// One launch per size class: cls_idx lists the spaces of class c (nocc =
+// c + 2) at [cls_off[c], cls_off[c+1]) (cls_off on the host, 4 entries).
+void launch_davidson(const DavidsonArgs& a, const int32_t* cls_idx, const int* cls_off,
+                     hipStream_t st);
 
 // pool update
 void launch_update(const double* t1, const double* t2, const double* r1, const double* r2,

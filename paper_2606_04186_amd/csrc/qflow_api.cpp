@@ -78,11 +78,14 @@ struct qflow_ctx {
   DevBuf ci, ci_off;   // eigenvectors kept between flow steps (warm starts)
   DevBuf heff, heff_off, amp, amp_off, work, work_off, energy, c0, iters, status, spaces,
       strings, out2, partial, tasks, mtab;
+  // spaces grouped by size class (nocc 2, 3, 4): indices at [cls_off[c], cls_off[c+1])
+  DevBuf cls_idx;
+  int cls_off[4] = {0, 0, 0, 0};
   int task_slots[3] = {0, 0, 0};
+  int lds_limit = 64 * 1024;   // dynamic LDS bytes a block may use
   // host mirror of the last uploaded space list
   std::vector<qflow_space> last_spaces;
   std::vector<int64_t> h_heff_off, h_amp_off, h_work_off, h_ci_off;
-  int lds_davidson = 0;
   int na_max = 0;
   int slots_max = 0;
   hipEvent_t ev[kStages + 1] = {};
@@ -145,9 +148,9 @@ int check_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   if (K > 0 && !spaces) return fail(ctx, QFLOW_E_INVALID_ARG, "spaces is NULL");
   for (int k = 0; k < K; ++k) {
     const qflow_space& s = spaces[k];
-    if (s.n_o < 2 || s.n_o > 3 || s.n_v != s.n_o)
+    if (s.n_o < 2 || s.n_o > 4 || s.n_v != s.n_o)
       return fail(ctx, QFLOW_E_UNSUPPORTED,
-                  "space " + std::to_string(k) + ": only (2,2) and (3,3) spaces");
+                  "space " + std::to_string(k) + ": only (2,2), (3,3) and (4,4) spaces");
     for (int a = 0; a < na_of(s); ++a) {
       const int p = s.orb[a];
       const bool occ = a < s.n_o;
@@ -175,6 +178,7 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   ctx->h_ci_off.assign(K + 1, 0);
   ctx->h_work_off.assign(K + 1, 0);
   int lds = 0, na_max = 0, slots_max = 0;
+  std::vector<int32_t> cls[3];
   for (int k = 0; k < K; ++k) {
     const qflow_space& s = spaces[k];
     dev[k].na = na_of(s);
@@ -184,23 +188,27 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
     const int64_t nt1 = (int64_t)s.n_o * s.n_v;
     ctx->h_heff_off[k + 1] = ctx->h_heff_off[k] + qflow_heff_size(&s);
     ctx->h_amp_off[k + 1] = ctx->h_amp_off[k] + nt1 + nt1 * nt1;
-    int64_t ns = 1;
-    for (int i = 0; i < s.n_o; ++i) ns = ns * (na - i) / (i + 1);
-    const int64_t D = ns * ns;
-    ctx->h_work_off[k + 1] = ctx->h_work_off[k] + 2 * kMaxSub * D;
-    ctx->h_ci_off[k + 1] = ctx->h_ci_off[k] + D;
-    const int nrep = s.n_o * (1 + na - s.n_o);
-    const int need = na * na * na * na + (int)(ns * ns) + 4 * (int)D + 3 * kMaxSub * kMaxSub +
-                     kMaxSub + 4 + 4 * kMaxSub + ((int)ns * nrep + 1) / 2;
-    lds = std::max(lds, need);
+    const qf::DavLayout lay = qf::dav_layout(na, s.n_o, kMaxSub);
+    ctx->h_work_off[k + 1] = ctx->h_work_off[k] + lay.work;
+    ctx->h_ci_off[k + 1] = ctx->h_ci_off[k] + qflow_ci_size(&s);
+    lds = std::max(lds, lay.lds);
+    lds = std::max(lds, qf::heff_lds_doubles(na));
     na_max = std::max(na_max, na);
     slots_max = std::max(slots_max, ctx->task_slots[s.n_o - 2]);
+    cls[s.n_o - 2].push_back(k);
   }
-  if ((size_t)lds * sizeof(double) > 160 * 1024)
-    return fail(ctx, QFLOW_E_UNSUPPORTED, "active space too large for the LDS-resident solver");
-  ctx->lds_davidson = lds;
+  if ((size_t)lds * sizeof(double) > (size_t)ctx->lds_limit)
+    return fail(ctx, QFLOW_E_UNSUPPORTED, "active space too large for the device's LDS");
   ctx->na_max = na_max;
   ctx->slots_max = slots_max;
+  std::vector<int32_t> idx;
+  for (int c = 0; c < 3; ++c) {
+    ctx->cls_off[c] = (int)idx.size();
+    idx.insert(idx.end(), cls[c].begin(), cls[c].end());
+  }
+  ctx->cls_off[3] = (int)idx.size();
+  idx.resize(std::max(K, 1), 0);
+  QF_TRY(ensure(ctx, ctx->cls_idx, sizeof(int32_t) * std::max(K, 1)));
   QF_TRY(ensure(ctx, ctx->spaces, sizeof(SpaceDev) * std::max(K, 1)));
   QF_TRY(ensure(ctx, ctx->heff_off, sizeof(int64_t) * (K + 1)));
   QF_TRY(ensure(ctx, ctx->amp_off, sizeof(int64_t) * (K + 1)));
@@ -228,6 +236,8 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   QF_HIP(hipMemcpyAsync(ctx->work_off.p, ctx->h_work_off.data(), sizeof(int64_t) * (K + 1),
                         hipMemcpyHostToDevice, ctx->stream));
   QF_HIP(hipMemcpyAsync(ctx->ci_off.p, ctx->h_ci_off.data(), sizeof(int64_t) * (K + 1),
+                        hipMemcpyHostToDevice, ctx->stream));
+  QF_HIP(hipMemcpyAsync(ctx->cls_idx.p, idx.data(), sizeof(int32_t) * std::max(K, 1),
                         hipMemcpyHostToDevice, ctx->stream));
   // the host vectors must outlive the asynchronous copies
   QF_HIP(hipStreamSynchronize(ctx->stream));
@@ -492,6 +502,11 @@ int qflow_create(qflow_ctx** out, int device, void* hip_stream) {
       qflow_destroy(ctx);
       return QFLOW_E_DEVICE;
     }
+  int lds_limit = 0;
+  if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+          hipSuccess &&
+      lds_limit > 0)
+    ctx->lds_limit = lds_limit;
   std::vector<qf::Strings> tabs(3);
   for (int s = 0; s < 3; ++s) qf::build_strings(2 * (s + 2), s + 2, &tabs[s]);
   std::vector<int32_t> task_tab(3 * qf::kTaskStride, -1);
@@ -534,7 +549,7 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->amp,    &ctx->amp_off,  &ctx->work,   &ctx->work_off, &ctx->energy,
                     &ctx->ci,     &ctx->ci_off,
                     &ctx->c0,     &ctx->iters,    &ctx->status, &ctx->spaces,   &ctx->strings,
-                    &ctx->out2,   &ctx->partial, &ctx->tasks, &ctx->mtab};
+                    &ctx->out2,   &ctx->partial, &ctx->tasks, &ctx->mtab,   &ctx->cls_idx};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -733,7 +748,8 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
     qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1), P<double>(ctx->y2),
                     P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx), t1, t2, ctx->n, ctx->o,
                     P<double>(ctx->scal), P<SpaceDev>(ctx->spaces), heff_off_dev,
-                    P<int32_t>(ctx->tasks), qf::kTaskStride, ctx->slots_max, K, ctx->na_max,
+                    P<int32_t>(ctx->tasks), qf::kTaskStride, ctx->task_slots,
+                    P<int32_t>(ctx->cls_idx), ctx->cls_off, K, ctx->na_max,
                     P<double>(ctx->mtab), heff, ctx->stream);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
@@ -763,7 +779,7 @@ int run_solve(qflow_ctx* ctx, int32_t K, const double* heff, const int64_t* heff
   a.max_iter = max_iter;
   a.maxsub = kMaxSub;
   a.K = K;
-  qf::launch_davidson(a, ctx->lds_davidson, ctx->stream);
+  qf::launch_davidson(a, P<int32_t>(ctx->cls_idx), ctx->cls_off, ctx->stream);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }

@@ -113,9 +113,11 @@ def config_integrals(name: str):
     return gen_integrals(c["n"], c["o"], c["L"], 1000 + c["idx"])
 
 
-def sampling_stream(name: str) -> Stream:
-    """Uniform stream for active-space sampling of config `name`."""
-    return Stream(2000 + CONFIGS[name]["idx"])
+def sampling_stream(name: str, size_class: int = 0) -> Stream:
+    """Uniform stream for active-space sampling of config `name`; a config
+    with several space sizes draws each size class (its position in
+    `sizes`) from a stream of its own, seeded 2000 + N + 100 * class."""
+    return Stream(2000 + CONFIGS[name]["idx"] + 100 * size_class)
 
 
 def random_amplitudes(o: int, v: int, seed: int, scale: float = 0.05):

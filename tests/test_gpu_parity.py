@@ -402,3 +402,70 @@ def test_flow_step_graph_replays_match_eager(prec):
         assert torch.equal(eg, ee), step
         assert (g1 - e1).abs().max().item() < 1e-12, step
         assert (g2 - e2).abs().max().item() < 1e-12, step
+
+
+def _mixed_spaces(n, o, seed, eps, caps=(3, 3, 2)):
+    """(2,2), (3,3) and (4,4) spaces, one Algorithm 1 stream per size class,
+    merged and sorted by Delta eps."""
+    out = []
+    for size, cap in zip((2, 3, 4), caps):
+        S = sampling.algorithm1(o, n - o, size, size, eps, synth.Stream(seed + size), cap=cap)
+        out += [(tuple(s[0]), tuple(s[1]), s[2]) for s in S]
+    out.sort(key=lambda s: s[2])
+    return [(s[0], s[1]) for s in out]
+
+
+def test_heff_size_classes_match_oracle():
+    """Spaces of all three size classes in one list (one launch per class)."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    n, o, seed = 16, 5, 161
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    t1, t2 = synth.random_amplitudes(o, n - o, seed + 1, scale=0.05)
+    lists = _mixed_spaces(n, o, seed, pb.eps)
+    assert sorted({len(s[0]) for s in lists}) == [2, 3, 4]
+    sp = qf.make_spaces(lists)
+    off = qf.api.offsets(sp, qf.heff_size)
+    heff = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
+    ctx = context(h, eri, o)
+    ctx.build_heff(sp, dev(t1), dev(t2), heff, off)
+    torch.cuda.synchronize()
+    out = host(heff)
+    for k, (occ, vir) in enumerate(lists):
+        x = qflow.heff(pb, t1, t2, tuple(occ) + tuple(vir))
+        ec, hs, g = qflow.cas_integrals(*x, len(occ))
+        na = len(occ) + len(vir)
+        blk = out[off[k]:off[k + 1]]
+        assert len(blk) == 1 + na * na + na ** 4
+        assert abs(blk[0] - ec) < 1e-10, k
+        assert np.abs(blk[1:1 + na * na].reshape(na, na) - hs).max() < 1e-11, k
+        assert np.abs(blk[1 + na * na:].reshape(na, na, na, na) - g).max() < 1e-11, k
+
+
+@pytest.mark.parametrize("flags", ["fp64", "graph"])
+def test_flow_step_size_classes_matches_oracle(flags):
+    """One macro-iteration over (2,2), (3,3) and (4,4) spaces (36, 400 and
+    4900 determinants) against the oracle: energies, eigenvector-derived
+    amplitudes through the pool update."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    n, o, seed = 16, 5, 162
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    v = n - o
+    lists = _mixed_spaces(n, o, seed, pb.eps, caps=(3, 2, 2))
+    o1, o2 = sampling.ownership(o, v, lists)
+    t1, t2 = qflow.mp2_guess(pb.f, eri, o)
+    sp = qf.make_spaces(lists)
+    ctx = context(h, eri, o)
+    g1, g2 = dev(t1), dev(t2)
+    energy = torch.zeros(len(lists), dtype=torch.float64, device="cuda")
+    flag = qf.GRAPH if flags == "graph" else qf.FP64
+    em, _ = ctx.flow_step(sp, dev(o1, torch.int32), dev(o2, torch.int32), g1, g2, energy, flag)
+    t1n, t2n, E, Em, _s = qflow.flow_step(pb, t1, t2, lists, o1, o2)
+    print("per-space |dE|", np.abs(host(energy) - E))
+    assert abs(em - Em) < 1e-9
+    assert np.abs(host(energy) - E).max() < 1e-9
+    assert np.abs(host(g1) - t1n).max() < 1e-8
+    assert np.abs(host(g2) - t2n).max() < 1e-8
