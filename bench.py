@@ -163,9 +163,12 @@ def main():
     peak = {"fp64": FP64_MFMA_PEAK_TFLOPS, "fp32": FP32_MFMA_PEAK_TFLOPS,
             "bf16x3": BF16_MFMA_PEAK_TFLOPS / 3.0}[use]
 
-    # Roofline of the matrix-core GEMM kernel k_gemm_f64 over its ladder and
-    # ring launches (six per step: two ladders, two Ga rings, two G22 rings):
-    # algorithmic flops per step over their HIP-event time in the timed region.
+    # Roofline of the reported path's matrix-core GEMM kernel (k_gemm_f64,
+    # k_gemm_f32 or k_gemm_bf16x3) over its ladder and ring launches (six per
+    # step: two ladders, two Ga rings, two G22 rings): algorithmic flops per
+    # step (FP64-equivalent products) over their HIP-event time in the timed
+    # steps; the event brackets hold those launches and the split-K slice sums
+    # of the two ladders.
     ov = o * v
     f_ladder = 2.0 * (n * (n + 1) // 2) * (o * o) * (v * v)   # H_N: rows p <= q
     # [F,sigma]'s two-body part vanishes for p, q both virtual: o*n - o(o-1)/2 rows
@@ -175,11 +178,15 @@ def main():
     gemm_flops = f_ladder + f_ladder_y + 2 * f_ga + 2 * f_g22
     gemm_ms = st["ladder_h"] + st["ladder_yg"] + st["ring_gemm"]
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
-    roof = {"kernel": {"fp64": "k_gemm_f64", "fp32": "k_gemm_f32", "bf16x3": "k_gemm_bf16x3"}[use],
+    kname = {"fp64": "k_gemm_f64", "fp32": "k_gemm_f32", "bf16x3": "k_gemm_bf16x3"}[use]
+    roof = {"kernel": kname,
             "scope": "ladder and ring launches, six per step",
             "bound": "mfma", "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": gemm_traffic() if use == "fp64" else None,
+            "traffic": gemm_traffic(kname) if args.config == "c4" else None,
+            "traffic_unit": "HBM bytes per step of the six launches (rocprofv3 FETCH_SIZE + "
+                            "WRITE_SIZE, copy-calibrated)",
+            "launches_per_step": 6, "avg_launch_ms": gemm_ms / 6,
             "flop_per_step": gemm_flops, "ms_per_step": gemm_ms}
     modes = {}
     for key, r in runs.items():
@@ -231,14 +238,15 @@ def main():
     print(json.dumps(out))
 
 
-def gemm_traffic():
-    """HBM bytes per step of the six ladder and ring GEMM launches, from the
-    rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in
-    profiles/k_gemm_f64_c4_traffic.md (scaled by a device copy of known size);
-    None when the GEMM source has changed since those counters were taken."""
+def gemm_traffic(kernel):
+    """HBM bytes per step of the six ladder and ring GEMM launches of
+    `kernel`, from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in
+    profiles/<kernel>_c4_traffic.md (scaled by a device copy of known size);
+    None when there is no such summary or the GEMM source has changed since
+    those counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "k_gemm_f64_c4_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_c4_traffic.md")
     src = os.path.join(ROOT, "paper_2606_04186_amd", "csrc", "k_gemm.hip")
     try:
         text = open(path).read()

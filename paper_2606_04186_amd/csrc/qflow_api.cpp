@@ -357,25 +357,31 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   qf::launch_sigma2(P<double>(ctx->y1), t2, n, o, P<double>(ctx->a12), P<double>(ctx->t2T),
                     false, P<double>(ctx->sp), P<double>(ctx->sq), part, pcap, nullptr, nullptr,
                     nullptr, st);
-  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[1], st));
   const int npair = n * (n + 1) / 2;   // ladder rows p <= q
   // rows of Yg's ladder operand with p virtual (then q virtual too) vanish:
   // the Yg ladder runs over the first o*n - o(o-1)/2 rows only
   const int npo = o * n - o * (o - 1) / 2;
   const size_t n2p = (size_t)npair;
-  if (bf3) {
-    const Split tb = split_of(ctx->t2b, (size_t)o * o, v * v);
-    const Split wb = split_of(ctx->wb, n2p, v * v), wyb = split_of(ctx->wyb, n2p, v * v);
-    const int kp = qf::bf16_pad(v * v);
+  const int kp = qf::bf16_pad(v * v);
+  Split tb{}, wyb_rows{};
+  if (bf3) {   // ladder operands of this step (the GEMM stages hold GEMMs only)
+    tb = split_of(ctx->t2b, (size_t)o * o, v * v);
+    const Split wyb = split_of(ctx->wyb, n2p, v * v);
+    wyb_rows = Split{wyb.hi, wyb.hi + (size_t)npo * kp};   // hi | lo of the npo rows
     split(t2, (size_t)o * o, v * v, tb, st);
+    split(P<double>(ctx->wy), (size_t)npo, v * v, wyb_rows, st);
+  } else if (mixed) {
+    qf::launch_cvt_f32(t2, P<float>(ctx->t2_32), ov * ov, st);
+  }
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[1], st));
+  if (bf3) {
+    const Split wb = split_of(ctx->wb, n2p, v * v);
     qf::launch_gemm_nt_bf16x3(wb.hi, wb.lo, tb.hi, tb.lo, P<double>(ctx->L), npair, o * o, kp, 1.0,
                               part, pcap, st);
     if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], st));
-    split(P<double>(ctx->wy), (size_t)npo, v * v, Split{wyb.hi, wyb.hi + (size_t)npo * kp}, st);
-    qf::launch_gemm_nt_bf16x3(wyb.hi, wyb.hi + (size_t)npo * kp, tb.hi, tb.lo, P<double>(ctx->LY),
-                              npo, o * o, kp, 1.0, part, pcap, st);
+    qf::launch_gemm_nt_bf16x3(wyb_rows.hi, wyb_rows.lo, tb.hi, tb.lo, P<double>(ctx->LY), npo,
+                              o * o, kp, 1.0, part, pcap, st);
   } else if (mixed) {
-    qf::launch_cvt_f32(t2, P<float>(ctx->t2_32), ov * ov, st);
     qf::launch_gemm_nt_f32(P<float>(ctx->w32), P<float>(ctx->t2_32), P<double>(ctx->L), npair,
                            o * o, v * v, 1.0, part, pcap, st);
     if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], st));
