@@ -16,16 +16,15 @@ namespace {
 // batched Davidson: one block per space
 // ---------------------------------------------------------------------------
 
-constexpr int kDavBlock = 256;   // threads per space (four wavefronts)
-
-// Sum over the block, the same value returned to every thread.  red: LDS
-// scratch of one double per wavefront.
+// Sum over the block of BLK threads, the same value returned to every
+// thread.  red: LDS scratch of one double per wavefront.
+template <int BLK>
 __device__ double block_sum(double x, double* red) {
   x = wave_sum(x);
   if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = x;
   __syncthreads();
   double s = 0.0;
-  for (int w = 0; w < kDavBlock / 64; ++w) s += red[w];
+  for (int w = 0; w < BLK / 64; ++w) s += red[w];
   __syncthreads();
   return s;
 }
@@ -35,10 +34,11 @@ __device__ double block_sum(double x, double* red) {
 // to row/column k; every thread of the block passes the barriers.  V (LDS,
 // m x m) receives the eigenvectors; every thread gets theta, y[0..m) (LDS)
 // the eigenvector.  flag: one double of LDS scratch.
+template <int BLK>
 __device__ void jacobi_lowest(double* A, double* V, int m, double* theta, double* y,
                               double* flag) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < m * m; e += kDavBlock) V[e] = (e / m == e % m) ? 1.0 : 0.0;
+  for (int e = tid; e < m * m; e += BLK) V[e] = (e / m == e % m) ? 1.0 : 0.0;
   __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid < 64) {
@@ -85,7 +85,7 @@ __device__ void jacobi_lowest(double* A, double* V, int m, double* theta, double
   for (int i = 1; i < m; ++i)
     if (A[i * m + i] < A[best * m + best]) best = i;
   *theta = A[best * m + best];
-  for (int i = tid; i < m; i += kDavBlock) y[i] = V[i * m + best];
+  for (int i = tid; i < m; i += BLK) y[i] = V[i * m + best];
   __syncthreads();
 }
 
@@ -97,7 +97,7 @@ __device__ inline int rep_pq(int r) { return (r >> 8) & 255; }
 __device__ inline double rep_sgn(int r) { return (r >> 16) ? 1.0 : -1.0; }
 
 // One space of NA orbitals and NE electrons per spin, one block of
-// kDavBlock threads (memory layout: dav_layout).
+// kDavBlock = dav_block(NA) threads (memory layout: dav_layout).
 //
 // sigma = H c is evaluated with thread l < G*NS owning beta string
 // Ib = l % NS and the alpha strings Ia = l / NS, l / NS + G, ... (G =
@@ -106,6 +106,7 @@ __device__ inline double rep_sgn(int r) { return (r >> 16) ? 1.0 : -1.0; }
 // the correction is orthogonalised by two classical Gram-Schmidt passes.
 template <int NA, int NE>
 __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp, double* sm) {
+  constexpr int kDavBlock = dav_block(NA);
   constexpr int NS = binom(NA, NE), NR = NE * (1 + NA - NE), D = NS * NS;
   constexpr int N2 = NA * NA, N4 = N2 * N2;
   constexpr int G = kDavBlock / NS, NT = (NS + G - 1) / G;
@@ -174,7 +175,7 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
   double cn = 0.0;
   if (civ)
     for (int e = tid; e < D; e += kDavBlock) cn += civ[e] * civ[e];
-  cn = block_sum(cn, red);
+  cn = block_sum<kDavBlock>(cn, red);
   const bool warm = cn > 0.25;
   const double cinv = warm ? 1.0 / sqrt(cn) : 0.0;
   for (int e = tid; e < D; e += kDavBlock) bb[e] = warm ? civ[e] * cinv : (e == 0 ? 1.0 : 0.0);
@@ -250,7 +251,7 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
     __syncthreads();
     for (int e = tid; e < m * m; e += kDavBlock) Aw[e] = Gm[(e / m) * MS + e % m];
     __syncthreads();
-    jacobi_lowest(Aw, Vw, m, &theta, yv, misc + 1);
+    jacobi_lowest<kDavBlock>(Aw, Vw, m, &theta, yv, misc + 1);
     double rn = 0.0;
     for (int e = tid; e < D; e += kDavBlock) {
       double x = 0.0, y = 0.0;
@@ -263,7 +264,7 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
       rv[e] = y - theta * x;
       rn += rv[e] * rv[e];
     }
-    rn = sqrt(block_sum(rn, red));
+    rn = sqrt(block_sum<kDavBlock>(rn, red));
     if (rn < a.tol) {
       conv = true;
       ++it;
@@ -296,7 +297,7 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
     }
     double nr = 0.0;
     for (int e = tid; e < D; e += kDavBlock) nr += rv[e] * rv[e];
-    nr = sqrt(block_sum(nr, red));
+    nr = sqrt(block_sum<kDavBlock>(nr, red));
     if (nr < 1e-14) {
       conv = rn < 1e3 * a.tol;
       ++it;
@@ -341,7 +342,7 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
 }
 
 template <int NA, int NE>
-__global__ __launch_bounds__(kDavBlock) void k_davidson(DavidsonArgs a,
+__global__ __launch_bounds__(dav_block(NA)) void k_davidson(DavidsonArgs a,
                                                         const int32_t* __restrict__ idx) {
   extern __shared__ double sm[];
   const int k = idx[blockIdx.x];
@@ -356,7 +357,7 @@ void launch_class(const DavidsonArgs& a, const int32_t* idx, int count, hipStrea
   if (bytes > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_davidson<NA, NE>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  k_davidson<NA, NE><<<count, kDavBlock, bytes, st>>>(a, idx);
+  k_davidson<NA, NE><<<count, dav_block(NA), bytes, st>>>(a, idx);
 }
 
 }  // namespace

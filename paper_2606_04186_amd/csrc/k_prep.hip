@@ -155,14 +155,20 @@ __global__ void k_pack_t2T(const double* __restrict__ t2, int o, int v, double* 
 
 // One workgroup per (p,q): the row U[p][q][:][:] (contiguous), and, for
 // p <= q, its virtual-virtual part in ladder layout (row tri_row(p,q)) when
-// wv is given.
+// wv is given.  Only the entries that can be non-zero for the (p,q) class are
+// visited; the others were zeroed once when the arrays were allocated:
+//   p, q occupied: all (r,s) but occupied-occupied (Q1 + Q2, P3, P4 terms)
+//   one of p, q occupied: (r,s) both occupied (P1 or P2) or both virtual (Q2 or Q1)
+//   p, q virtual: r or s occupied (P1 + P2 and the sums over occupied t of
+//   g[t][r] t2[t][s][p][q] and g[t][s] t2[r][t][p][q], with g's occupied rows
+//   and those t2 elements staged in LDS)
 template <class WT>
 __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restrict__ g,
                                                          const double* __restrict__ t2,
                                                          const double* __restrict__ P,
                                                          const double* __restrict__ Q, int n,
                                                          int o, double* U, WT* wv) {
-  __shared__ double tpq[64 * 64];
+  extern __shared__ double sg[];   // p, q virtual: tpq[o*o] | g occupied rows [o][n]
   const int v = n - o;
   const int p = blockIdx.x / n, q = blockIdx.x % n;
   const bool op = p < o, oq = q < o;
@@ -171,51 +177,73 @@ __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restric
   const double* P2 = P + nv;
   const double* P3 = P + 2 * nv;
   const double* P4 = P + 3 * nv;
-  const size_t ovv = (size_t)o * v * v;
+  const size_t ovv = (size_t)o * v * v, vv = (size_t)v * v;
   const double* Q1 = Q;
   const double* Q2 = Q + (size_t)n * ovv;
-  if (!op && !oq) {
-    // sigma_pq.. needs t2[t][u][p][q] for occupied t, u
+  const size_t row = ((size_t)p * n + q) * n * n;
+  const bool lad = wv != nullptr && p <= q;
+  WT* wrow = lad ? wv + tri_row(p, q, n) * vv : nullptr;
+  if (op && oq) {
+    const size_t pq = ((size_t)p * o + q) * v;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int r = e / n, s_ = e % n;
+      if (r < o && s_ < o) continue;
+      double x = 0.0;
+      if (r >= o && s_ >= o) {
+        const size_t rs = (size_t)(r - o) * v + (s_ - o);
+        x += Q1[(size_t)p * ovv + (size_t)q * vv + rs];
+        x += Q2[(size_t)q * ovv + (size_t)p * vv + rs];
+      }
+      if (s_ >= o) x += P3[(size_t)r * ov2 + pq + (s_ - o)];
+      if (r >= o) x += P4[(size_t)s_ * ov2 + pq + (r - o)];
+      U[row + e] = x;
+      if (lad && r >= o && s_ >= o) wrow[(size_t)(r - o) * v + (s_ - o)] = (WT)x;
+    }
+  } else if (op != oq) {
+    const int o2 = o * o;
+    for (int e = threadIdx.x; e < o2 + v * v; e += blockDim.x) {
+      double x = 0.0;
+      if (e < o2) {   // r, s occupied
+        const int r = e / o, s_ = e % o;
+        const size_t rs = ((size_t)r * o + s_) * v;
+        x += op ? P1[(size_t)p * ov2 + rs + (q - o)] : P2[(size_t)q * ov2 + rs + (p - o)];
+        U[row + (size_t)r * n + s_] = x;
+      } else {        // r, s virtual
+        const int f = e - o2, r = o + f / v, s_ = o + f % v;
+        x += op ? Q2[(size_t)q * ovv + (size_t)p * vv + f] : Q1[(size_t)p * ovv + (size_t)q * vv + f];
+        U[row + (size_t)r * n + s_] = x;
+        if (lad) wrow[f] = (WT)x;
+      }
+    }
+  } else {
+    double* tpq = sg;
+    double* go = sg + o * o;
     for (int e = threadIdx.x; e < o * o; e += blockDim.x)
       tpq[e] = t2[((size_t)e * v + (p - o)) * v + (q - o)];
+    for (int e = threadIdx.x; e < o * n; e += blockDim.x) go[e] = g[e];
     __syncthreads();
-  }
-  const size_t row = ((size_t)p * n + q) * n * n;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int r = e / n, s_ = e % n;
-    const bool or_ = r < o, os = s_ < o;
-    double x = 0.0;
-    if (or_ == os) {
-      if (or_) {   // r, s occupied
+    const int on = o * n;
+    for (int e = threadIdx.x; e < on + v * o; e += blockDim.x) {
+      int r, s_;
+      if (e < on) {
+        r = e / n;
+        s_ = e % n;
+      } else {
+        r = o + (e - on) / o;
+        s_ = (e - on) % o;
+      }
+      double x = 0.0;
+      if (r < o && s_ < o) {
         const size_t rs = ((size_t)r * o + s_) * v;
-        if (!oq) x += P1[(size_t)p * ov2 + rs + (q - o)];
-        if (!op) x += P2[(size_t)q * ov2 + rs + (p - o)];
-      } else {     // r, s virtual
-        const size_t rs = (size_t)(r - o) * v + (s_ - o);
-        if (oq) x += Q1[(size_t)p * ovv + (size_t)q * v * v + rs];
-        if (op) x += Q2[(size_t)q * ovv + (size_t)p * v * v + rs];
+        x += P1[(size_t)p * ov2 + rs + (q - o)];
+        x += P2[(size_t)q * ov2 + rs + (p - o)];
       }
+      if (s_ < o)
+        for (int t = 0; t < o; ++t) x -= go[t * n + r] * tpq[t * o + s_];
+      if (r < o)
+        for (int t = 0; t < o; ++t) x -= go[t * n + s_] * tpq[r * o + t];
+      U[row + (size_t)r * n + s_] = x;
     }
-    if (op == oq) {
-      if (op) {    // p, q occupied
-        const size_t pq = ((size_t)p * o + q) * v;
-        if (!os) x += P3[(size_t)r * ov2 + pq + (s_ - o)];
-        if (!or_) x += P4[(size_t)s_ * ov2 + pq + (r - o)];
-      } else {     // p, q virtual
-        if (os)
-          for (int t = 0; t < o; ++t) x -= g[t * n + r] * tpq[t * o + s_];
-        if (or_)
-          for (int t = 0; t < o; ++t) x -= g[t * n + s_] * tpq[r * o + t];
-      }
-    }
-    // entries that vanish for every sigma are never written (the arrays are
-    // zeroed once when allocated)
-    const bool nz = (or_ == os && (or_ ? (!oq || !op) : (oq || op))) ||
-                    (op == oq && (op ? (!os || !or_) : (os || or_)));
-    if (!nz) continue;
-    U[row + e] = x;
-    if (wv && !or_ && !os && p <= q)
-      wv[tri_row(p, q, n) * v * v + (size_t)(r - o) * v + (s_ - o)] = (WT)x;
   }
 }
 
@@ -411,6 +439,8 @@ __global__ __launch_bounds__(256) void k_sigma1_x(const double* __restrict__ X,
   const size_t c = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * W;
   if (c >= n3) return;
   auto ld = [&](int t) { return *reinterpret_cast<const vw*>(X + (size_t)t * n3 + c); };
+  // (plain stores: Z's lines that stay in the last-level cache serve the
+  // lookups of the per-space kernels that follow)
   auto st = [&](int p, vw x) { *reinterpret_cast<vw*>(Z + (size_t)p * n3 + c) = x; };
   // p occupied: Z[p][c] = -sum_{t virtual} t1[p][t-o] X[t][c]; the column of
   // X is read eight rows at a time to keep several loads in flight.  With
@@ -564,10 +594,18 @@ void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12,
                        part_cap, st);
   launch_gemm_nt_f64(Ao, Tq, Q, n, (int)ovv, o, -1.0, part, part_cap, st);
   launch_gemm_nt_f64(Ao, Tp, Q + (size_t)n * ovv, n, (int)ovv, o, -1.0, part, part_cap, st);
-  if (U && wv32)
-    k_sigma2_assemble<<<n * n, kBlock, 0, st>>>(g, t2, P, Q, n, o, U, wv32);
-  else if (U)
-    k_sigma2_assemble<<<n * n, kBlock, 0, st>>>(g, t2, P, Q, n, o, U, wv);
+  const size_t lds = (size_t)(o * o + o * n) * sizeof(double);
+  if (U && wv32) {
+    if (lds > 64 * 1024)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma2_assemble<float>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_sigma2_assemble<<<n * n, kBlock, lds, st>>>(g, t2, P, Q, n, o, U, wv32);
+  } else if (U) {
+    if (lds > 64 * 1024)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma2_assemble<double>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_sigma2_assemble<<<n * n, kBlock, lds, st>>>(g, t2, P, Q, n, o, U, wv);
+  }
 }
 
 void launch_yg1(const double* f, const double* t1, const double* t2, int n, int o, double* y1,

@@ -145,13 +145,16 @@ struct DavLayout {
   bool big;       // diagonal / Ritz sigma / residual vectors in global memory
 };
 constexpr int kDavBigDets = 1024;
+// threads per space: 256, and 512 for the (4,4) class, whose LDS admits one
+// block per compute unit (two wavefronts per SIMD hide the LDS gathers)
+__host__ __device__ constexpr int dav_block(int na) { return na >= 8 ? 512 : 256; }
 __host__ __device__ constexpr DavLayout dav_layout(int na, int ne, int maxsub) {
   int ns = 1;
   for (int i = 0; i < ne; ++i) ns = ns * (na - i) / (i + 1);
   const int D = ns * ns, nrep = ne * (1 + na - ne), n4 = na * na * na * na;
   const bool big = D > kDavBigDets;
-  const int lds = n4 + ns * ns + D + 3 * maxsub * maxsub + maxsub + 4 + 4 * maxsub +
-                  (ns * nrep + 1) / 2 + (big ? 0 : 3 * D);
+  const int lds = n4 + ns * ns + D + 3 * maxsub * maxsub + maxsub + 4 +
+                  dav_block(na) / 64 * maxsub + (ns * nrep + 1) / 2 + (big ? 0 : 3 * D);
   return DavLayout{lds, (int64_t)(2 * maxsub + (big ? 3 : 0)) * D, big};
 }
 // One launch per size class: cls_idx lists the spaces of class c (nocc =
