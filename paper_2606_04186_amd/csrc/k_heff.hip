@@ -111,8 +111,11 @@ __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
 // part 1: + 1/2 ([Yg,sigma] - [Yg,tau])
 // ([X,tau] from X and tau restricted to the space, staged in LDS, local indices)
 // part 2: + 1/2 ([Ft,tau] - [Ft,sigma]) = - 1/2 [E,sigma], marked evaluation
-template <int PART>
-__global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __restrict__ scal,
+//
+// Workgroups of BLK threads; workgroup (x, y) takes space idx[x] and the
+// task slots [y * BLK, (y + 1) * BLK).
+template <int PART, int BLK>
+__global__ __launch_bounds__(BLK) void k_heff_part(GlobalOps g, const double* __restrict__ scal,
                                                    const SpaceDev* __restrict__ spaces,
                                                    const int32_t* __restrict__ idx,
                                                    const int64_t* __restrict__ heff_off,
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(256) void k_heff_part(GlobalOps g, const double* __
   const LocalOp tauA{tl + n2 + n4, tl + 2 * n2 + n4, na, sp.nocc};
   double* slot = heff + heff_off[k];
   const Sigma s{g.t1, g.t2, n, o, v};
-  const int slot_idx = blockIdx.y * blockDim.x + threadIdx.x;
+  const int slot_idx = (int)blockIdx.y * BLK + (int)threadIdx.x;
   if (slot_idx >= task_stride) return;
   const int32_t code = tasks[(sp.nocc - 2) * task_stride + slot_idx];
   if (code < 0) return;
@@ -293,7 +296,12 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
               rings.lo_h, rings.lo_y, rings.pf};
   const int tab_stride = heff_table_stride(na_max);
   k_heff_tab<<<K, kBlock, 0, st>>>(g, spaces, tab, tab_stride);
-  // parts 0, 1, 2 per size class: its task count and LDS
+  // parts 0, 1, 2 per size class: its task count and LDS.  The (4,4) class
+  // (about 100 KB of staged tables) runs 1024-thread workgroups, so that its
+  // tables are staged twice per space instead of five times and four times
+  // as many wavefronts share them; the others run 256-thread workgroups.
+  // Workgroup x takes a space, y a chunk of tasks, x fastest: the chunks of
+  // one space never run together (they update the same output lines).
   for (int PART = 0; PART < 3; ++PART)
     for (int c = 0; c < 3; ++c) {
       const int count = cls_off[c + 1] - cls_off[c];
@@ -302,21 +310,34 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
       int s1, s2, s3, s4;
       const int mark = mark_sizes(na, &s1, &s2, &s3, &s4);
       const size_t lds = (size_t)(PART == 2 ? mark : 2 * (n2 + n2 * n2)) * sizeof(double);
-      const dim3 grid(count, (task_slots[c] + kBlock - 1) / kBlock);
       const int32_t* idx = cls_idx + cls_off[c];
-      if (PART == 0) {
-        allow_lds(&k_heff_part<0>, lds);
-        k_heff_part<0><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
-                                                  task_stride, tab, tab_stride, heff);
-      } else if (PART == 1) {
-        allow_lds(&k_heff_part<1>, lds);
-        k_heff_part<1><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
-                                                  task_stride, tab, tab_stride, heff);
-      } else {
-        allow_lds(&k_heff_part<2>, lds);
-        k_heff_part<2><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
-                                                  task_stride, tab, tab_stride, heff);
+      if (c == 2) {
+        const dim3 grid(count, (task_slots[c] + 1023) / 1024);
+        if (PART == 0) {
+          allow_lds(&k_heff_part<0, 1024>, lds);
+          k_heff_part<0, 1024><<<grid, 1024, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
+                                                        task_stride, tab, tab_stride, heff);
+        } else if (PART == 1) {
+          allow_lds(&k_heff_part<1, 1024>, lds);
+          k_heff_part<1, 1024><<<grid, 1024, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
+                                                        task_stride, tab, tab_stride, heff);
+        } else {
+          allow_lds(&k_heff_part<2, 1024>, lds);
+          k_heff_part<2, 1024><<<grid, 1024, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
+                                                        task_stride, tab, tab_stride, heff);
+        }
+        continue;
       }
+      const dim3 grid(count, (task_slots[c] + kBlock - 1) / kBlock);
+      if (PART == 0)
+        k_heff_part<0, 256><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
+                                                       task_stride, tab, tab_stride, heff);
+      else if (PART == 1)
+        k_heff_part<1, 256><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
+                                                       task_stride, tab, tab_stride, heff);
+      else
+        k_heff_part<2, 256><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
+                                                       task_stride, tab, tab_stride, heff);
     }
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
   const size_t lds = (size_t)tasks * sizeof(double);
