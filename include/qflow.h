@@ -64,9 +64,18 @@ typedef enum { QFLOW_FP64 = 0, QFLOW_FP32 = 1, QFLOW_BF16X3 = 2 } qflow_precisio
  * bf16 operands with FP32 partial and FP64 sums). */
 enum {
   QFLOW_UNOWNED_FROZEN = 1 << 4, /* amplitudes no space owns keep their value */
-  QFLOW_GRAPH = 1 << 5           /* run the step's device work as a captured HIP graph,
+  QFLOW_GRAPH = 1 << 5,          /* run the step's device work as a captured HIP graph,
                                     re-captured when K, flags, the array pointers or
                                     the context's buffers change */
+  QFLOW_DIIS = 1 << 6            /* Pulay DIIS on the pool vector [t1 | t2] after the
+                                    update: the last 8 (updated pool, change) pairs;
+                                    from the third consecutive DIIS step on, the pool
+                                    becomes the combination of updated pools whose
+                                    changes have the least norm (coefficients summing
+                                    to one; Gaussian elimination with partial pivoting,
+                                    a pivot below 1e-14 max|B| drops the oldest pair).
+                                    A step without the flag, a new space list or new
+                                    integrals end the history. */
 };
 
 /* Create a context on HIP device `device`; hip_stream is a hipStream_t to

@@ -255,3 +255,89 @@ def flow_step(pb: Problem, t1, t2, spaces, owner1, owner2, unowned="residual"):
                         if owner2[i, j, a - o, b - o] == k:
                             nt2[i, j, a - o, b - o] = s["t2"][I, J, A, B]
     return nt1, nt2, E, float(np.mean(E)), sols
+
+
+# ----------------------------------------------------------------------------
+# DIIS over the amplitude vector (reading R9; the paper itself has none)
+# ----------------------------------------------------------------------------
+
+DIIS_MAX_VECTORS = 8
+DIIS_START = 3
+DIIS_PIVOT_TOL = 1e-14
+
+
+def _solve_bordered(B, pivot_tol):
+    """Solve [B 1; 1^T 0] [c; lam] = [0; 1] by Gaussian elimination with
+    partial pivoting.  Returns c, or None when a pivot falls below
+    pivot_tol * max|B| (the system is treated as singular)."""
+    m = B.shape[0]
+    A = np.zeros((m + 1, m + 2))
+    A[:m, :m] = B
+    A[:m, m] = 1.0
+    A[m, :m] = 1.0
+    A[m, m + 1] = 1.0
+    scale = np.abs(B).max()
+    for col in range(m + 1):
+        piv = col + int(np.argmax(np.abs(A[col:, col])))
+        if abs(A[piv, col]) < pivot_tol * scale:
+            return None
+        A[[col, piv]] = A[[piv, col]]
+        for r in range(col + 1, m + 1):
+            A[r, col:] -= A[r, col] / A[col, col] * A[col, col:]
+    x = np.zeros(m + 1)
+    for r in range(m, -1, -1):
+        x[r] = (A[r, m + 1] - A[r, r + 1:m + 1] @ x[r + 1:]) / A[r, r]
+    return x[:m]
+
+
+class DIIS:
+    """Pulay's direct inversion in the iterative subspace on the whole
+    amplitude vector.  Each call takes the plainly updated vector t_new and
+    its error e = t_new - t_old, keeps the last max_vectors pairs, and from
+    the start-th call on returns sum_i c_i t_new_i with the c minimising
+    |sum_i c_i e_i| under sum_i c_i = 1 (B_ij = e_i . e_j); when the bordered
+    system is singular the oldest pair is dropped and it is solved again."""
+
+    def __init__(self, max_vectors=DIIS_MAX_VECTORS, start=DIIS_START,
+                 pivot_tol=DIIS_PIVOT_TOL):
+        self.max_vectors, self.start, self.pivot_tol = max_vectors, start, pivot_tol
+        self.T, self.E = [], []
+        self.calls = 0
+
+    def step(self, t_new, err):
+        self.T.append(np.array(t_new, dtype=np.float64))
+        self.E.append(np.array(err, dtype=np.float64))
+        if len(self.T) > self.max_vectors:
+            self.T.pop(0)
+            self.E.pop(0)
+        self.calls += 1
+        if self.calls < self.start:
+            return self.T[-1].copy()
+        first = 0
+        while True:
+            Es = self.E[first:]
+            m = len(Es)
+            if m == 1:
+                return self.T[-1].copy()
+            B = np.array([[ei @ ej for ej in Es] for ei in Es])
+            c = _solve_bordered(B, self.pivot_tol)
+            if c is not None:
+                return sum(ci * Ti for ci, Ti in zip(c, self.T[first:]))
+            first += 1
+
+
+def pack(t1, t2):
+    return np.concatenate([t1.reshape(-1), t2.reshape(-1)])
+
+
+def unpack(x, o, v):
+    return x[:o * v].reshape(o, v).copy(), x[o * v:].reshape(o, o, v, v).copy()
+
+
+def flow_step_diis(pb: Problem, t1, t2, spaces, owner1, owner2, diis: DIIS,
+                   unowned="residual"):
+    """One macro-iteration followed by the DIIS extrapolation of the pool."""
+    nt1, nt2, E, Em, sols = flow_step(pb, t1, t2, spaces, owner1, owner2, unowned)
+    x = diis.step(pack(nt1, nt2), pack(nt1, nt2) - pack(t1, t2))
+    xt1, xt2 = unpack(x, pb.o, pb.v)
+    return xt1, xt2, E, Em, sols

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libqflow.so")
 FP64, FP32, BF16X3 = 0, 1, 2
 UNOWNED_FROZEN = 1 << 4
 GRAPH = 1 << 5
+DIIS = 1 << 6
 
 SPACE_DTYPE = np.dtype([("n_o", "<i4"), ("n_v", "<i4"), ("orb", "<i4", (8,))])
 

@@ -377,6 +377,148 @@ __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ energ
 }
 
 // ---------------------------------------------------------------------------
+// DIIS over the amplitude vector x = [t1 | t2] (N = o v + o^2 v^2 doubles)
+// ---------------------------------------------------------------------------
+
+// Store the plainly updated vector xn and its error e = xn - x in the slot of
+// the new pair (count % kDiisMax), and the partial sums of e . E_j over this
+// block for every held pair j (part[j * gridDim.x + block]).
+__global__ __launch_bounds__(256) void k_diis_store(const double* __restrict__ t1n,
+                                                    const double* __restrict__ t2n,
+                                                    const double* __restrict__ t1,
+                                                    const double* __restrict__ t2, int o, int v,
+                                                    double* T, double* E,
+                                                    const DiisState* __restrict__ state,
+                                                    double* part) {
+  __shared__ double red[4][kDiisMax];
+  const size_t nt1 = (size_t)o * v, N = nt1 + (size_t)o * o * v * v;
+  const int count = state->count;
+  const int slot = count % kDiisMax;
+  const int held = min(count + 1, kDiisMax);   // pairs held once this one is stored
+  double acc[kDiisMax];
+#pragma unroll
+  for (int j = 0; j < kDiisMax; ++j) acc[j] = 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < N;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const double xn = i < nt1 ? t1n[i] : t2n[i - nt1];
+    const double x = i < nt1 ? t1[i] : t2[i - nt1];
+    const double e = xn - x;
+    T[(size_t)slot * N + i] = xn;
+    E[(size_t)slot * N + i] = e;
+#pragma unroll
+    for (int j = 0; j < kDiisMax; ++j)
+      if (j < held) acc[j] += e * (j == slot ? e : E[(size_t)j * N + i]);
+  }
+#pragma unroll
+  for (int j = 0; j < kDiisMax; ++j) {
+    const double w = wave_sum(acc[j]);
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64][j] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < kDiisMax)
+    part[threadIdx.x * gridDim.x + blockIdx.x] =
+        red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+// One thread: sums the partials into the new row and column of B, counts the
+// pair, and sets the extrapolation coefficients c (by slot): from the
+// start-th pair on, the solution of [B 1; 1^T 0][c; lam] = [0; 1] over the
+// held pairs (Gaussian elimination with partial pivoting; a pivot below
+// kDiisPivotTol * max|B| drops the oldest pair and the system is solved
+// again), else the newest vector alone.
+__global__ void k_diis_solve(const double* __restrict__ part, int nparts, DiisState* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int count = st->count;
+  const int slot = count % kDiisMax;
+  const int held = min(count + 1, kDiisMax);
+  for (int j = 0; j < held; ++j) {
+    double b = 0.0;
+    for (int q = 0; q < nparts; ++q) b += part[j * nparts + q];
+    st->B[slot * kDiisMax + j] = b;
+    st->B[j * kDiisMax + slot] = b;
+  }
+  st->count = count + 1;
+  for (int j = 0; j < kDiisMax; ++j) st->c[j] = 0.0;
+  // held pairs in chronological order, oldest first
+  int order[kDiisMax];
+  for (int i = 0; i < held; ++i) order[i] = (count + 1 - held + i) % kDiisMax;
+  if (count + 1 < kDiisStart) {
+    st->c[slot] = 1.0;
+    return;
+  }
+  for (int first = 0; first < held; ++first) {
+    const int m = held - first;
+    if (m == 1) break;
+    double A[kDiisMax + 1][kDiisMax + 2];
+    double scale = 0.0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        A[i][j] = st->B[order[first + i] * kDiisMax + order[first + j]];
+        scale = fmax(scale, fabs(A[i][j]));
+      }
+    for (int i = 0; i < m; ++i) {
+      A[i][m] = 1.0;
+      A[m][i] = 1.0;
+      A[i][m + 1] = 0.0;
+    }
+    A[m][m] = 0.0;
+    A[m][m + 1] = 1.0;
+    bool singular = false;
+    for (int col = 0; col <= m && !singular; ++col) {
+      int piv = col;
+      for (int r = col + 1; r <= m; ++r)
+        if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+      if (fabs(A[piv][col]) < kDiisPivotTol * scale) {
+        singular = true;
+        break;
+      }
+      if (piv != col)
+        for (int c = 0; c <= m + 1; ++c) {
+          const double tmp = A[col][c];
+          A[col][c] = A[piv][c];
+          A[piv][c] = tmp;
+        }
+      for (int r = col + 1; r <= m; ++r) {
+        const double f = A[r][col] / A[col][col];
+        for (int c = col; c <= m + 1; ++c) A[r][c] -= f * A[col][c];
+      }
+    }
+    if (singular) continue;
+    double x[kDiisMax + 1];
+    for (int r = m; r >= 0; --r) {
+      double y = A[r][m + 1];
+      for (int c = r + 1; c <= m; ++c) y -= A[r][c] * x[c];
+      x[r] = y / A[r][r];
+    }
+    for (int i = 0; i < m; ++i) st->c[order[first + i]] = x[i];
+    return;
+  }
+  st->c[slot] = 1.0;
+}
+
+// x_out = sum_j c_j T_j over the held pairs, oldest first, into t1n / t2n.
+__global__ __launch_bounds__(256) void k_diis_extrap(const double* __restrict__ T,
+                                                     const DiisState* __restrict__ st, int o,
+                                                     int v, double* t1n, double* t2n) {
+  const size_t nt1 = (size_t)o * v, N = nt1 + (size_t)o * o * v * v;
+  const int count = st->count;   // already includes the new pair
+  const int held = min(count, kDiisMax);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < N;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double x = 0.0;
+    for (int q = 0; q < held; ++q) {
+      const int j = (count - held + q) % kDiisMax;
+      const double c = st->c[j];
+      if (c != 0.0) x += c * T[(size_t)j * N + i];
+    }
+    if (i < nt1)
+      t1n[i] = x;
+    else
+      t2n[i - nt1] = x;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // ring intermediates: operand packing and the o^2 v one-body contraction
 // ---------------------------------------------------------------------------
 
@@ -690,6 +832,14 @@ void launch_scatter_owned(const SpaceDev* spaces, const double* amp, const int64
                           int n, int o, int K, double* t1n, double* t2n, hipStream_t st) {
   k_scatter_owned<<<K, kBlock, 0, st>>>(spaces, amp, amp_off, status, owner1, owner2, n, o, t1n,
                                          t2n);
+}
+
+void launch_diis(const double* t1, const double* t2, int o, int v, double* T, double* E,
+                 DiisState* state, double* part, double* t1n, double* t2n, hipStream_t st) {
+  k_diis_store<<<kDiisParts, kBlock, 0, st>>>(t1n, t2n, t1, t2, o, v, T, E, state, part);
+  k_diis_solve<<<1, 64, 0, st>>>(part, kDiisParts, state);
+  const size_t N = (size_t)o * v + (size_t)o * o * v * v;
+  k_diis_extrap<<<grid_for(N, kBlock, 65536), kBlock, 0, st>>>(T, state, o, v, t1n, t2n);
 }
 
 void launch_finish(const double* energy, int K, const double* t1, const double* t2,

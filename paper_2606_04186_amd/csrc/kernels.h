@@ -169,6 +169,23 @@ void launch_update(const double* t1, const double* t2, const double* r1, const d
 void launch_scatter_owned(const SpaceDev* spaces, const double* amp, const int64_t* amp_off,
                           const int32_t* status, const int32_t* owner1, const int32_t* owner2,
                           int n, int o, int K, double* t1n, double* t2n, hipStream_t st);
+// DIIS over the amplitude vector [t1 | t2]: up to kDiisMax (t_new, error)
+// pairs in T and E (kDiisMax * N doubles each), the Gram matrix of the
+// errors, the pair count and the extrapolation coefficients in one device
+// struct (zeroed to start a history).  From the kDiisStart-th pair on,
+// t1n / t2n are replaced by the extrapolated vector.  part: kDiisMax *
+// kDiisParts doubles of scratch.
+constexpr int kDiisMax = 8;
+constexpr int kDiisStart = 3;
+constexpr double kDiisPivotTol = 1e-14;
+constexpr int kDiisParts = 1024;
+struct DiisState {
+  int count, pad;
+  double B[kDiisMax * kDiisMax];
+  double c[kDiisMax];
+};
+void launch_diis(const double* t1, const double* t2, int o, int v, double* T, double* E,
+                 DiisState* state, double* part, double* t1n, double* t2n, hipStream_t st);
 // mean energy and max |t_new - t_old| into out2[0..1]; part holds
 // kFinishParts doubles of scratch
 constexpr int kFinishParts = 512;

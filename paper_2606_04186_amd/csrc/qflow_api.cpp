@@ -76,6 +76,9 @@ struct qflow_ctx {
   // and Yg [o*o][o*o], outputs Lo of H and Yg [v*v][o*o]
   DevBuf lo_t, lo_xh, lo_xy, lo_h, lo_y;
   DevBuf ci, ci_off;   // eigenvectors kept between flow steps (warm starts)
+  // DIIS history (QFLOW_DIIS): pairs (t_new, error), scratch, device state
+  DevBuf diis_t, diis_e, diis_part, diis_state;
+  bool diis_active = false;   // the device state holds a running history
   DevBuf heff, heff_off, amp, amp_off, work, work_off, energy, c0, iters, status, spaces,
       strings, out2, partial, tasks, mtab;
   // spaces grouped by size class (nocc 2, 3, 4): indices at [cls_off[c], cls_off[c+1])
@@ -243,6 +246,7 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   QF_HIP(hipStreamSynchronize(ctx->stream));
   ctx->last_spaces.assign(spaces, spaces + K);
   ++ctx->epoch;   // launch shapes of the per-space kernels follow the list
+  ctx->diis_active = false;   // a new list starts a new DIIS history
   return QFLOW_OK;
 }
 
@@ -555,7 +559,8 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->amp,    &ctx->amp_off,  &ctx->work,   &ctx->work_off, &ctx->energy,
                     &ctx->ci,     &ctx->ci_off,
                     &ctx->c0,     &ctx->iters,    &ctx->status, &ctx->spaces,   &ctx->strings,
-                    &ctx->out2,   &ctx->partial, &ctx->tasks, &ctx->mtab,   &ctx->cls_idx};
+                    &ctx->out2,   &ctx->partial, &ctx->tasks, &ctx->mtab,   &ctx->cls_idx,
+                    &ctx->diis_t, &ctx->diis_e, &ctx->diis_part, &ctx->diis_state};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -671,6 +676,7 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_HIP(hipMemcpy(ctx->scal.p, sc, sizeof(sc), hipMemcpyHostToDevice));
   ctx->loaded = true;
   ctx->h32_ready = false;
+  ctx->diis_active = false;
   ++ctx->epoch;   // sizes may have changed without a reallocation
   ctx->hb_ready = false;
   ctx->last_spaces.clear();
@@ -794,7 +800,8 @@ int run_solve(qflow_ctx* ctx, int32_t K, const double* heff, const int64_t* heff
 // synchronisation, so that it can be captured into a graph.
 // With `timed` the stage boundaries are marked by events (not under capture).
 int enqueue_step(qflow_ctx* ctx, int32_t K, const int32_t* owner1, const int32_t* owner2,
-                 double* t1, double* t2, double* energy, int precision, bool step, bool timed) {
+                 double* t1, double* t2, double* energy, int precision, bool step, bool diis,
+                 bool timed) {
   const int n = ctx->n, o = ctx->o, v = ctx->v;
   hipStream_t st = ctx->stream;
   ctx->timed = timed;
@@ -820,6 +827,10 @@ int enqueue_step(qflow_ctx* ctx, int32_t K, const int32_t* owner1, const int32_t
     qf::launch_scatter_owned(P<SpaceDev>(ctx->spaces), P<double>(ctx->amp),
                              P<int64_t>(ctx->amp_off), P<int32_t>(ctx->status), owner1, owner2,
                              n, o, K, P<double>(ctx->t1n), P<double>(ctx->t2n), st);
+  if (diis)
+    qf::launch_diis(t1, t2, o, v, P<double>(ctx->diis_t), P<double>(ctx->diis_e),
+                    P<qf::DiisState>(ctx->diis_state), P<double>(ctx->diis_part),
+                    P<double>(ctx->t1n), P<double>(ctx->t2n), st);
   qf::launch_finish(P<double>(ctx->energy), K, t1, t2, P<double>(ctx->t1n), P<double>(ctx->t2n),
                     o, v, P<double>(ctx->dtpart), P<double>(ctx->out2), st);
   // the new pool and energies into the caller's arrays (copy kernels, no
@@ -901,7 +912,22 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
   if (precision == QFLOW_FP32) QF_TRY(ensure_mixed(ctx));
   if (precision == QFLOW_BF16X3) QF_TRY(ensure_bf16(ctx));
   const bool step = !(flags & QFLOW_UNOWNED_FROZEN);
+  const bool diis = (flags & QFLOW_DIIS) != 0;
   hipStream_t st = ctx->stream;
+  if (diis) {
+    const size_t N = (size_t)ctx->o * ctx->v + (size_t)ctx->o * ctx->o * ctx->v * ctx->v;
+    QF_TRY(ensure(ctx, ctx->diis_t, sizeof(double) * qf::kDiisMax * N));
+    QF_TRY(ensure(ctx, ctx->diis_e, sizeof(double) * qf::kDiisMax * N));
+    QF_TRY(ensure(ctx, ctx->diis_part, sizeof(double) * qf::kDiisMax * qf::kDiisParts));
+    QF_TRY(ensure(ctx, ctx->diis_state, sizeof(qf::DiisState)));
+    if (!ctx->diis_active) {   // start a history: zero the device state
+      qf::launch_fill(P<double>(ctx->diis_state), sizeof(qf::DiisState) / sizeof(double), 0.0,
+                      st);
+      ctx->diis_active = true;
+    }
+  } else {
+    ctx->diis_active = false;
+  }
   if (flags & QFLOW_GRAPH) {
     const GraphKey key{K, flags, t1, t2, owner1, owner2, energy, ctx->epoch};
     if (!ctx->graph_exec || !(key == ctx->graph_key)) {
@@ -910,7 +936,8 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
         ctx->graph_exec = nullptr;
       }
       QF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      const int r = enqueue_step(ctx, K, owner1, owner2, t1, t2, energy, precision, step, false);
+      const int r =
+          enqueue_step(ctx, K, owner1, owner2, t1, t2, energy, precision, step, diis, false);
       hipGraph_t graph = nullptr;
       const hipError_t e = hipStreamEndCapture(st, &graph);
       if (r != QFLOW_OK) {
@@ -932,7 +959,7 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
     QF_HIP(hipGraphLaunch(ctx->graph_exec, st));
     QF_HIP(hipEventRecord(ctx->ev[kStages], st));
   } else {
-    QF_TRY(enqueue_step(ctx, K, owner1, owner2, t1, t2, energy, precision, step, true));
+    QF_TRY(enqueue_step(ctx, K, owner1, owner2, t1, t2, energy, precision, step, diis, true));
   }
   double out[2];
   QF_HIP(hipMemcpyAsync(out, ctx->out2.p, sizeof(out), hipMemcpyDeviceToHost, st));

@@ -469,3 +469,35 @@ def test_flow_step_size_classes_matches_oracle(flags):
     assert np.abs(host(energy) - E).max() < 1e-9
     assert np.abs(host(g1) - t1n).max() < 1e-8
     assert np.abs(host(g2) - t2n).max() < 1e-8
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_flow_step_diis_matches_oracle(graph):
+    """Five macro-iterations with DIIS (extrapolation from the third on)
+    against the oracle's DIIS, partial coverage on 24 orbitals."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    n, o, seed, K = 24, 4, 171, 12
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    v = n - o
+    lists = _spaces_for(n, o, K, seed, pb.eps)
+    o1, o2 = sampling.ownership(o, v, lists)
+    t1, t2 = qflow.mp2_guess(pb.f, eri, o)
+    sp = qf.make_spaces(lists)
+    ctx = context(h, eri, o)
+    g1, g2 = dev(t1), dev(t2)
+    energy = torch.zeros(len(lists), dtype=torch.float64, device="cuda")
+    d1, d2 = dev(o1, torch.int32), dev(o2, torch.int32)
+    flags = qf.DIIS | (qf.GRAPH if graph else 0)
+    dz = qflow.DIIS()
+    for it in range(5):
+        em, dt = ctx.flow_step(sp, d1, d2, g1, g2, energy, flags)
+        nt1, nt2, E, Em, _s = qflow.flow_step_diis(pb, t1, t2, lists, o1, o2, dz)
+        ddt = max(np.abs(nt1 - t1).max(), np.abs(nt2 - t2).max())
+        t1, t2 = nt1, nt2
+        print(f"it {it}: E_mean {em:.12f} max|dt| {dt:.3e} (oracle {ddt:.3e})")
+        assert abs(em - Em) < 1e-9, it
+        assert np.abs(host(g1) - t1).max() < 1e-8, it
+        assert np.abs(host(g2) - t2).max() < 1e-8, it
+        assert abs(dt - ddt) < 1e-8, it

@@ -338,3 +338,54 @@ def test_cas_integrals_reproduce_space_spectrum():
     w1 = np.linalg.eigvalsh(Hb)
     w2 = np.linalg.eigvalsh(qflow.cas_matrix(*x, 2))
     assert np.abs(w1 - w2).max() < 1e-12
+
+
+def test_diis_reaches_fixed_point_of_linear_iteration():
+    """DIIS on x <- M x + c in dimension d: once more than d error vectors
+    are held (and no pair was dropped) the errors are linearly dependent and
+    the extrapolated vector is the exact fixed point (I - M)^-1 c; before
+    the start call the plain iterate is returned unchanged."""
+    rng = np.random.default_rng(7)
+    d = 4
+    Q = np.linalg.qr(rng.standard_normal((d, d)))[0]
+    M = Q @ np.diag([0.9, -0.7, 0.5, 0.2]) @ Q.T
+    c = rng.standard_normal(d)
+    xstar = np.linalg.solve(np.eye(d) - M, c)
+    dz = qflow.DIIS(max_vectors=8, start=3)
+    x = np.zeros(d)
+    for it in range(1, 7):
+        xn = M @ x + c
+        y = dz.step(xn, xn - x)
+        if it < 3:
+            assert np.array_equal(y, xn)
+        x = y
+    assert np.abs(x - xstar).max() < 1e-10
+    # without DIIS the same six plain steps are still far from it
+    z = np.zeros(d)
+    for _ in range(6):
+        z = M @ z + c
+    assert np.abs(z - xstar).max() > 1e-2
+
+
+def test_diis_coefficients_minimise_the_error_norm():
+    """The returned combination's coefficients sum to one and minimise
+    |sum c_i e_i| (checked against a direct constrained least-squares solve),
+    and a history of identical errors (singular B) falls back to the newest
+    vector."""
+    rng = np.random.default_rng(8)
+    d, m = 12, 5
+    T = rng.standard_normal((m, d))
+    E = rng.standard_normal((m, d))
+    dz = qflow.DIIS(max_vectors=8, start=1)
+    for i in range(m):
+        y = dz.step(T[i], E[i])
+    # constrained minimum: c = argmin |E^T c| with sum c = 1
+    G = E @ E.T
+    w = np.linalg.solve(G, np.ones(m))
+    c = w / w.sum()
+    assert np.abs(y - c @ T).max() < 1e-10
+    dz2 = qflow.DIIS(max_vectors=8, start=1)
+    e = rng.standard_normal(d)
+    for i in range(3):
+        y2 = dz2.step(T[i], e)
+    assert np.array_equal(y2, T[2])
