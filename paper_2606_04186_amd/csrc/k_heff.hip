@@ -113,8 +113,9 @@ __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
 // part 2: + 1/2 ([Ft,tau] - [Ft,sigma]) = - 1/2 [E,sigma], marked evaluation
 //
 // Workgroups of BLK threads; workgroup (x, y) takes space idx[x] and the
-// task slots [y * BLK, (y + 1) * BLK).
-template <int PART, int BLK>
+// task slots [y * BLK, (y + 1) * BLK).  NA: the size class's orbital count
+// (compile-time shape of the marked evaluation of part 2; 0 for parts 0, 1).
+template <int PART, int BLK, int NA>
 __global__ __launch_bounds__(BLK) void k_heff_part(GlobalOps g, const double* __restrict__ scal,
                                                    const SpaceDev* __restrict__ spaces,
                                                    const int32_t* __restrict__ idx,
@@ -208,9 +209,11 @@ __global__ __launch_bounds__(BLK) void k_heff_part(GlobalOps g, const double* __
       x = scal[1] - ct.c0();
     emit(x, 0.5, false);
   } else {
-    const MarkedE E{T, &A};
-    const MarkedSigma D{T, &A};
-    const CommE<MarkedE, MarkedSigma, true> ce{E, D, A, n, o};
+    static_assert(PART != 2 || NA > 0, "the marked evaluation needs the space size");
+    const MarkedE<NA> E{T};
+    const MarkedSigma<NA> D{T};
+    const MarkedShape<NA> shape;
+    const CommE<MarkedE<NA>, MarkedSigma<NA>, true, MarkedShape<NA>> ce{E, D, shape, n, o};
     double x;   // (local indices)
     if (kind == 2)
       x = ce.c2(la, lb, lc, ld);
@@ -314,30 +317,37 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
       if (c == 2) {
         const dim3 grid(count, (task_slots[c] + 1023) / 1024);
         if (PART == 0) {
-          allow_lds(&k_heff_part<0, 1024>, lds);
-          k_heff_part<0, 1024><<<grid, 1024, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
+          allow_lds(&k_heff_part<0, 1024, 0>, lds);
+          k_heff_part<0, 1024, 0><<<grid, 1024, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
                                                         task_stride, tab, tab_stride, heff);
         } else if (PART == 1) {
-          allow_lds(&k_heff_part<1, 1024>, lds);
-          k_heff_part<1, 1024><<<grid, 1024, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
+          allow_lds(&k_heff_part<1, 1024, 0>, lds);
+          k_heff_part<1, 1024, 0><<<grid, 1024, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
                                                         task_stride, tab, tab_stride, heff);
         } else {
-          allow_lds(&k_heff_part<2, 1024>, lds);
-          k_heff_part<2, 1024><<<grid, 1024, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
+          allow_lds(&k_heff_part<2, 1024, 8>, lds);
+          k_heff_part<2, 1024, 8><<<grid, 1024, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
                                                         task_stride, tab, tab_stride, heff);
         }
         continue;
       }
       const dim3 grid(count, (task_slots[c] + kBlock - 1) / kBlock);
       if (PART == 0)
-        k_heff_part<0, 256><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
-                                                       task_stride, tab, tab_stride, heff);
+        k_heff_part<0, 256, 0><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off,
+                                                          task_table, task_stride, tab, tab_stride,
+                                                          heff);
       else if (PART == 1)
-        k_heff_part<1, 256><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
-                                                       task_stride, tab, tab_stride, heff);
+        k_heff_part<1, 256, 0><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off,
+                                                          task_table, task_stride, tab, tab_stride,
+                                                          heff);
+      else if (c == 0)
+        k_heff_part<2, 256, 4><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off,
+                                                          task_table, task_stride, tab, tab_stride,
+                                                          heff);
       else
-        k_heff_part<2, 256><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
-                                                       task_stride, tab, tab_stride, heff);
+        k_heff_part<2, 256, 6><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off,
+                                                          task_table, task_stride, tab, tab_stride,
+                                                          heff);
     }
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
   const size_t lds = (size_t)tasks * sizeof(double);

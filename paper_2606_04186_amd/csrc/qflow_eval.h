@@ -626,11 +626,11 @@ QF_HD Comm<AOp, BOp> make_comm_split(const AOp& a, const BOp& b, int n, int o, i
 // themselves (kMarked = false), or, with the sum over the external orbital x
 // moved inside per-space tables, the active orbital t that E's Fock leg
 // attaches to (kMarked = true; the index is passed as the marker -1-t).
-template <class EOp, class BOp, bool kMarked = false>
+template <class EOp, class BOp, bool kMarked = false, class ActT = Active>
 struct CommE {
   const EOp& a;        // E accessor (one index external, or marked)
   const BOp& b;        // sigma accessor (one index external, or marked)
-  const Active& A;
+  const ActT& A;
   int n, o;
 
   // In marked mode every index is local (the position in A.orb, occupied
@@ -647,8 +647,10 @@ struct CommE {
   template <class F>
   QF_HD void over_ext(bool occupied, F fn) const {
     if constexpr (kMarked) {
+#pragma unroll 1
       for (int t = 0; t < A.na; ++t) fn(-1 - t);
     } else {
+#pragma unroll 1
       for (int k = 0; k < A.next(occupied); ++k) fn(A.extv(occupied, k));
     }
   }
@@ -656,8 +658,10 @@ struct CommE {
   template <class F>
   QF_HD void pair1(bool bt, bool bu, F fn) const {
     over_ext(bt, [&](int x) {
+#pragma unroll 1
       for (int m = 0; m < A.nact(bu); ++m) fn(x, act_at(bu, m));
     });
+#pragma unroll 1
     for (int k = 0; k < A.nact(bt); ++k) {
       const int t = act_at(bt, k);
       over_ext(bu, [&](int x) { fn(t, x); });
@@ -667,14 +671,20 @@ struct CommE {
   template <class F>
   QF_HD void triple1(bool bt, bool bu, bool bw, F fn) const {
     over_ext(bt, [&](int x) {
+#pragma unroll 1
       for (int j = 0; j < A.nact(bu); ++j)
+#pragma unroll 1
         for (int k = 0; k < A.nact(bw); ++k) fn(x, act_at(bu, j), act_at(bw, k));
     });
+#pragma unroll 1
     for (int i = 0; i < A.nact(bt); ++i)
       over_ext(bu, [&](int x) {
+#pragma unroll 1
         for (int k = 0; k < A.nact(bw); ++k) fn(act_at(bt, i), x, act_at(bw, k));
       });
+#pragma unroll 1
     for (int i = 0; i < A.nact(bt); ++i)
+#pragma unroll 1
       for (int j = 0; j < A.nact(bu); ++j)
         over_ext(bw, [&](int x) { fn(act_at(bt, i), act_at(bu, j), x); });
   }
@@ -762,10 +772,14 @@ struct CommE {
          - b.two(t, u, w, x) * (2.0 * a.two(w, x, t, u) - a.two(w, x, u, t));
     };
     triple1(true, true, false, [&](int t, int u, int w) {
+#pragma unroll 1
       for (int m = 0; m < A.nact(false); ++m) term(t, u, w, act_at(false, m));
     });
+#pragma unroll 1
     for (int i = 0; i < A.nact(true); ++i)
+#pragma unroll 1
       for (int j = 0; j < A.nact(true); ++j)
+#pragma unroll 1
         for (int k = 0; k < A.nact(false); ++k)
           over_ext(false, [&](int x) {
             term(act_at(true, i), act_at(true, j), act_at(false, k), x);
@@ -800,17 +814,25 @@ QF_HD int mark_sizes(int na, int* tau1, int* tau2, int* d1, int* d2) {
   return *tau1 + *tau2 + *d1 + *d2;
 }
 
+// Shape of a space of NA orbitals (NA/2 occupied) for the marked evaluation,
+// known at compile time so that its loops and strides fold to constants.
+template <int NA>
+struct MarkedShape {
+  static constexpr int na = NA, nocc = NA / 2;
+  QF_HD static constexpr int nact(bool occ) { return occ ? nocc : na - nocc; }
+};
+
+template <int NA>
 struct MarkedE {
   MarkTables T;
-  const Active* A;
   QF_HD int loc(int p) const { return p; }   // indices are local in marked mode
   QF_HD double one(int p, int q) const {
-    const int na = T.na;
+    constexpr int na = NA;
     if (p < 0) return T.tau1[(-1 - p) * na + loc(q)];
     return -T.tau1[loc(p) * na + (-1 - q)];
   }
   QF_HD double two(int p, int q, int r, int s) const {
-    const int na = T.na;
+    constexpr int na = NA;
     int i0, i1, i2, i3;
     double sg = 1.0;
     if (p < 0) { i0 = -1 - p; i1 = loc(q); i2 = loc(r); i3 = loc(s); }
@@ -821,17 +843,17 @@ struct MarkedE {
   }
 };
 
+template <int NA>
 struct MarkedSigma {
   MarkTables T;
-  const Active* A;
   QF_HD int loc(int p) const { return p; }   // indices are local in marked mode
   QF_HD double one(int p, int q) const {
-    const int na = T.na;
+    constexpr int na = NA;
     if (p < 0) return T.D1[(0 * na + (-1 - p)) * na + loc(q)];
     return T.D1[(1 * na + (-1 - q)) * na + loc(p)];
   }
   QF_HD double two(int p, int q, int r, int s) const {
-    const int na = T.na, n3 = na * na * na;
+    constexpr int na = NA, n3 = na * na * na;
     int j, t, a, b, c;
     // D_2(t;a,b,c) = -D_0(t;c,a,b) and D_3(t;a,b,c) = -D_1(t;c,a,b)
     double sg = 1.0;
