@@ -119,8 +119,11 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
   const double* h = hin + 1;
   constexpr bool BIG = dav_layout(NA, NE, 1).big;
   double* g = sm;                       // N4
-  double* Hs = g + N4;                  // NS^2
-  double* xv = Hs + NS * NS;            // D  Ritz vector / sigma input
+  // Hs rows padded to an odd stride: lanes reading Hs[ib][J] for different
+  // ib then fall on different LDS banks
+  constexpr int HS = NS | 1;
+  double* Hs = g + N4;                  // NS x HS
+  double* xv = Hs + NS * HS;            // D  Ritz vector / sigma input
   double* Gm = xv + D;                  // MS^2
   double* Aw = Gm + MS * MS;            // MS^2
   double* Vw = Aw + MS * MS;            // MS^2
@@ -145,7 +148,7 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
   // k_pq = h_pq - 1/2 sum_r g(pr|rq): thread I scatters the one- and two-step
   // replacements of string I into row I (one thread per row, in a fixed order)
   double* kk = rv;   // N2 <= D doubles; rv is free until the iterations start
-  for (int e = tid; e < NS * NS; e += kDavBlock) Hs[e] = 0.0;
+  for (int e = tid; e < NS * HS; e += kDavBlock) Hs[e] = 0.0;
   for (int e = tid; e < N2; e += kDavBlock) {
     const int p = e / NA, q = e % NA;
     double x = h[p * NA + q];
@@ -155,7 +158,7 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
   __syncthreads();
   if (tid < NS) {
     const int I = tid;
-    double* row = Hs + I * NS;
+    double* row = Hs + I * HS;
     for (int f = 0; f < NR; ++f) {
       const int r = rep[I * NR + f];
       row[rep_src(r)] += rep_sgn(r) * kk[rep_pq(r)];
@@ -168,7 +171,7 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
     }
   }
   __syncthreads();
-  for (int e = tid; e < D; e += kDavBlock) dg[e] = cas_diag(S, Hs, g, Ec, e / NS, e % NS);
+  for (int e = tid; e < D; e += kDavBlock) dg[e] = cas_diag(S, Hs, HS, g, Ec, e / NS, e % NS);
   // starting vector: the stored eigenvector of this space's previous solve
   // when there is one (non-zero), else the reference determinant
   double* civ = a.ci ? a.ci + a.ci_off[k] : nullptr;
@@ -202,7 +205,7 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
       double x = Ec * c[ia * NS + ib];
 #pragma unroll
       for (int J = 0; J < NS; ++J)
-        x += Hs[ia * NS + J] * c[J * NS + ib] + Hs[ib * NS + J] * c[ia * NS + J];
+        x += Hs[ia * HS + J] * c[J * NS + ib] + Hs[ib * HS + J] * c[ia * NS + J];
 #pragma unroll
       for (int e = 0; e < NR; ++e) {
         const int r = rep[ia * NR + e];

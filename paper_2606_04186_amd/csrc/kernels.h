@@ -153,7 +153,7 @@ __host__ __device__ constexpr DavLayout dav_layout(int na, int ne, int maxsub) {
   for (int i = 0; i < ne; ++i) ns = ns * (na - i) / (i + 1);
   const int D = ns * ns, nrep = ne * (1 + na - ne), n4 = na * na * na * na;
   const bool big = D > kDavBigDets;
-  const int lds = n4 + ns * ns + D + 3 * maxsub * maxsub + maxsub + 4 +
+  const int lds = n4 + ns * (ns | 1) + D + 3 * maxsub * maxsub + maxsub + 4 +
                   dav_block(na) / 64 * maxsub + (ns * nrep + 1) / 2 + (big ? 0 : 3 * D);
   return DavLayout{lds, (int64_t)(2 * maxsub + (big ? 3 : 0)) * D, big};
 }
