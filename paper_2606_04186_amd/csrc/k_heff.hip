@@ -115,8 +115,10 @@ __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
 // Workgroups of BLK threads; workgroup (x, y) takes space idx[x] and the
 // task slots [y * BLK, (y + 1) * BLK).  NA: the size class's orbital count
 // (compile-time shape of the marked evaluation of part 2; 0 for parts 0, 1).
+// (Parts 0 and 1 wait on scattered global lookups: their 256-thread form is
+// held to seven workgroups' worth of registers per compute unit.)
 template <int PART, int BLK, int NA>
-__global__ __launch_bounds__(BLK) void k_heff_part(GlobalOps g, const double* __restrict__ scal,
+__global__ __launch_bounds__(BLK, (PART < 2 && BLK == 256) ? 7 : 1) void k_heff_part(GlobalOps g, const double* __restrict__ scal,
                                                    const SpaceDev* __restrict__ spaces,
                                                    const int32_t* __restrict__ idx,
                                                    const int64_t* __restrict__ heff_off,
