@@ -364,9 +364,7 @@ __global__ void k_split_bf16(const double* __restrict__ src, int rows, int K, in
     const size_t r = e / Kp;
     const int k = (int)(e % Kp);
     const double x = k < K ? src[r * K + k] : 0.0;
-    const __bf16 h = (__bf16)(float)x;
-    hi[e] = h;
-    lo[e] = (__bf16)(float)(x - (double)(float)h);
+    store_bf16_split(x, hi, lo, e);
   }
 }
 

@@ -162,12 +162,28 @@ __global__ void k_pack_t2T(const double* __restrict__ t2, int o, int v, double* 
 //   p, q virtual: r or s occupied (P1 + P2 and the sums over occupied t of
 //   g[t][r] t2[t][s][p][q] and g[t][s] t2[r][t][p][q], with g's occupied rows
 //   and those t2 elements staged in LDS)
+// Writers of the ladder rows: FP64, FP32, or BF16 hi/lo planes with rows
+// padded to kp (padding zeroed once by the caller).
+struct LadderRows {
+  double* f64;
+  float* f32;
+  __bf16 *hi, *lo;
+  size_t stride;   // elements per row
+  __device__ bool on() const { return f64 || f32 || hi; }
+  __device__ void put(size_t row, size_t k, double x) const {
+    const size_t i = row * stride + k;
+    if (f64) f64[i] = x;
+    else if (f32) f32[i] = (float)x;
+    else store_bf16_split(x, hi, lo, i);
+  }
+};
+
 template <class WT>
 __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restrict__ g,
                                                          const double* __restrict__ t2,
                                                          const double* __restrict__ P,
                                                          const double* __restrict__ Q, int n,
-                                                         int o, double* U, WT* wv) {
+                                                         int o, double* U, WT wv) {
   extern __shared__ double sg[];   // p, q virtual: tpq[o*o] | g occupied rows [o][n]
   const int v = n - o;
   const int p = blockIdx.x / n, q = blockIdx.x % n;
@@ -181,8 +197,8 @@ __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restric
   const double* Q1 = Q;
   const double* Q2 = Q + (size_t)n * ovv;
   const size_t row = ((size_t)p * n + q) * n * n;
-  const bool lad = wv != nullptr && p <= q;
-  WT* wrow = lad ? wv + tri_row(p, q, n) * vv : nullptr;
+  const bool lad = wv.on() && p <= q;
+  const size_t wrow = tri_row(p, q, n);
   if (op && oq) {
     const size_t pq = ((size_t)p * o + q) * v;
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
@@ -197,7 +213,7 @@ __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restric
       if (s_ >= o) x += P3[(size_t)r * ov2 + pq + (s_ - o)];
       if (r >= o) x += P4[(size_t)s_ * ov2 + pq + (r - o)];
       U[row + e] = x;
-      if (lad && r >= o && s_ >= o) wrow[(size_t)(r - o) * v + (s_ - o)] = (WT)x;
+      if (lad && r >= o && s_ >= o) wv.put(wrow, (size_t)(r - o) * v + (s_ - o), x);
     }
   } else if (op != oq) {
     const int o2 = o * o;
@@ -212,7 +228,7 @@ __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restric
         const int f = e - o2, r = o + f / v, s_ = o + f % v;
         x += op ? Q2[(size_t)q * ovv + (size_t)p * vv + f] : Q1[(size_t)p * ovv + (size_t)q * vv + f];
         U[row + (size_t)r * n + s_] = x;
-        if (lad) wrow[f] = (WT)x;
+        if (lad) wv.put(wrow, f, x);
       }
     }
   } else {
@@ -558,6 +574,39 @@ __global__ void k_pack_ring_T(const double* __restrict__ t2, int o, int v, T* Ta
   }
 }
 
+// The same operands as BF16 hi/lo planes (rows padded to a multiple of 32 k;
+// the padding is zeroed once when the planes are allocated and never written).
+__global__ void k_pack_ring_A_bf16(const double* __restrict__ X, int n, int o, __bf16* Ah,
+                                   __bf16* Al, int kpa, __bf16* A22h, __bf16* A22l, int kp22) {
+  const int v = n - o;
+  const size_t ov = (size_t)o * v, rows = (size_t)n * n;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < rows * ov;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t row = idx / ov, k = idx % ov;
+    const int a = (int)(row / n), b = (int)(row % n), u = (int)(k / v), t = o + (int)(k % v);
+    const double x1 = X[(((size_t)a * n + u) * n + b) * n + t];
+    const double x2 = X[(((size_t)a * n + u) * n + t) * n + b];
+    store_bf16_split(2.0 * x1 - x2, Ah, Al, row * kpa + k);
+    store_bf16_split(-x1, Ah, Al, row * kpa + ov + k);
+    store_bf16_split(x2, A22h, A22l, row * kp22 + k);
+  }
+}
+
+__global__ void k_pack_ring_T_bf16(const double* __restrict__ t2, int o, int v, __bf16* Th,
+                                   __bf16* Tl, int kpa, __bf16* T22h, __bf16* T22l, int kp22) {
+  const size_t ov = (size_t)o * v;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < ov * ov;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t row = idx / ov, k = idx % ov;
+    const int g = (int)(row / o), d = (int)(row % o), u = (int)(k / v), t = (int)(k % v);
+    const double s1 = t2[(((size_t)u * o + d) * v + t) * v + g];
+    const double s2 = t2[(((size_t)d * o + u) * v + t) * v + g];
+    store_bf16_split(s1, Th, Tl, row * kpa + k);
+    store_bf16_split(s2, Th, Tl, row * kpa + ov + k);
+    store_bf16_split(s2, T22h, T22l, row * kp22 + k);
+  }
+}
+
 // Z(p,q,r,s) = sum_t sigma1(p,t) X(t,q,r,s): the one-body part of sigma
 // (t1) applied to the first index of a two-body operator.  With X Hermitian
 // and pair symmetric and sigma1 anti-Hermitian, the four terms of
@@ -716,7 +765,7 @@ void launch_mp2(const double* f, const double* V, int n, int o, double* t1, doub
 
 void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12, double* t2T,
                    bool pack_t2, double* P, double* Q, double* part, size_t part_cap, double* U,
-                   double* wv, float* wv32, hipStream_t st) {
+                   double* wv, float* wv32, __bf16* wvb_hi, __bf16* wvb_lo, hipStream_t st) {
   const int v = n - o;
   const size_t nv = (size_t)n * v, ov2 = (size_t)o * o * v, ovv = (size_t)o * v * v;
   const size_t o2v2 = (size_t)o * ovv;
@@ -737,16 +786,12 @@ void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12,
   launch_gemm_nt_f64(Ao, Tq, Q, n, (int)ovv, o, -1.0, part, part_cap, st);
   launch_gemm_nt_f64(Ao, Tp, Q + (size_t)n * ovv, n, (int)ovv, o, -1.0, part, part_cap, st);
   const size_t lds = (size_t)(o * o + o * n) * sizeof(double);
-  if (U && wv32) {
+  if (U) {
     if (lds > 64 * 1024)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma2_assemble<float>),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma2_assemble<LadderRows>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_sigma2_assemble<<<n * n, kBlock, lds, st>>>(g, t2, P, Q, n, o, U, wv32);
-  } else if (U) {
-    if (lds > 64 * 1024)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma2_assemble<double>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_sigma2_assemble<<<n * n, kBlock, lds, st>>>(g, t2, P, Q, n, o, U, wv);
+    const LadderRows rows{wv, wv32, wvb_hi, wvb_lo, wvb_hi ? (size_t)bf16_pad(v * v) : (size_t)v * v};
+    k_sigma2_assemble<<<n * n, kBlock, lds, st>>>(g, t2, P, Q, n, o, U, rows);
   }
 }
 
@@ -768,6 +813,20 @@ void launch_pack_ring_A(const double* X, int n, int o, float* Aa, float* A22, hi
 void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22, hipStream_t st) {
   const size_t ov = (size_t)o * v;
   k_pack_ring_T<<<grid_for(ov * ov, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, Ta, T22);
+}
+
+void launch_pack_ring_A_bf16(const double* X, int n, int o, __bf16* Ah, __bf16* Al, __bf16* A22h,
+                             __bf16* A22l, hipStream_t st) {
+  const size_t ov = (size_t)o * (n - o);
+  k_pack_ring_A_bf16<<<grid_for((size_t)n * n * ov, kBlock, 65536), kBlock, 0, st>>>(
+      X, n, o, Ah, Al, bf16_pad((int)(2 * ov)), A22h, A22l, bf16_pad((int)ov));
+}
+
+void launch_pack_ring_T_bf16(const double* t2, int o, int v, __bf16* Th, __bf16* Tl, __bf16* T22h,
+                             __bf16* T22l, hipStream_t st) {
+  const size_t ov = (size_t)o * v;
+  k_pack_ring_T_bf16<<<grid_for(ov * ov, kBlock, 65536), kBlock, 0, st>>>(
+      t2, o, v, Th, Tl, bf16_pad((int)(2 * ov)), T22h, T22l, bf16_pad((int)ov));
 }
 
 void launch_pack_ring_T(const double* t2, int o, int v, float* Ta, float* T22, hipStream_t st) {

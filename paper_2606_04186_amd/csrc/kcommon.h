@@ -21,6 +21,14 @@ __device__ inline double wave_sum(double x) {
   return x;
 }
 
+// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi) (round to nearest
+// through FP32), stored at element i of the two planes
+__device__ inline void store_bf16_split(double x, __bf16* hi, __bf16* lo, size_t i) {
+  const __bf16 h = (__bf16)(float)x;
+  hi[i] = h;
+  lo[i] = (__bf16)(float)(x - (double)(float)h);
+}
+
 __device__ inline double wave_max(double x) {
   for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
   return x;

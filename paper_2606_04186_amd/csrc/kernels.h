@@ -23,14 +23,15 @@ void launch_mp2(const double* f, const double* V, int n, int o, double* t1, doub
 
 // intermediates of one amplitude set
 // U = [G, sigma_2]_2 (dense n^4) for a Hermitian one-body G, and its
-// virtual-virtual rows in ladder layout into wv (FP64) or wv32 (FP32) when
-// one is given (k_prep.hip).  With U NULL only the compact parts P and Q are
-// formed (read through Sigma2Lazy).  Scratch: A12 2*n*v + n*o, t2T
-// 3*o*o*v*v (packed from t2 here when pack_t2), P 4*n*o*o*v and Q 2*n*o*v*v
-// doubles.
+// virtual-virtual rows in ladder layout into wv (FP64), wv32 (FP32) or the
+// BF16 hi/lo planes wvb_hi / wvb_lo (rows padded to bf16_pad(v*v), padding
+// zeroed by the caller) when one is given (k_prep.hip).  With U NULL only
+// the compact parts P and Q are formed (read through Sigma2Lazy).  Scratch:
+// A12 2*n*v + n*o, t2T 3*o*o*v*v (packed from t2 here when pack_t2),
+// P 4*n*o*o*v and Q 2*n*o*v*v doubles.
 void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12, double* t2T,
                    bool pack_t2, double* P, double* Q, double* part, size_t part_cap, double* U,
-                   double* wv, float* wv32, hipStream_t st);
+                   double* wv, float* wv32, __bf16* wvb_hi, __bf16* wvb_lo, hipStream_t st);
 // y1 = one-body part of [F_N, sigma], scal[2] = its scalar part
 void launch_yg1(const double* f, const double* t1, const double* t2, int n, int o, double* y1,
                 double* scal, hipStream_t st);
@@ -42,6 +43,12 @@ void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22,
 // the same operands rounded to FP32 (mixed-precision contractions)
 void launch_pack_ring_A(const double* X, int n, int o, float* Aa, float* A22, hipStream_t st);
 void launch_pack_ring_T(const double* t2, int o, int v, float* Ta, float* T22, hipStream_t st);
+// ... and as BF16 hi/lo planes, rows padded to bf16_pad(2ov) and bf16_pad(ov)
+// (padding zeroed by the caller once)
+void launch_pack_ring_A_bf16(const double* X, int n, int o, __bf16* Ah, __bf16* Al, __bf16* A22h,
+                             __bf16* A22l, hipStream_t st);
+void launch_pack_ring_T_bf16(const double* t2, int o, int v, __bf16* Th, __bf16* Tl, __bf16* T22h,
+                             __bf16* T22l, hipStream_t st);
 // Z = sigma1 X over the first index (k_prep.hip, k_sigma1_x); n^4 doubles.
 // skip_vvv: X vanishes on all-virtual quadruples and Z was zeroed once, so the
 // structurally zero part of Z is not rewritten.

@@ -299,6 +299,10 @@ int ensure_bf16(qflow_ctx* ctx) {
   QF_TRY(ensure_split(ctx, ctx->rt22b, ov, (int)ov));
   if (!ctx->hb_ready) {
     hipStream_t st = ctx->stream;
+    // the per-step ring operands are packed straight into their planes and
+    // never write the K padding: zero it (whole buffers) once here
+    for (DevBuf* b : {&ctx->rab_y, &ctx->r22b_y, &ctx->rtab, &ctx->rt22b, &ctx->wyb})
+      qf::launch_fill(P<double>(*b), b->bytes / sizeof(double), 0.0, st);
     split(P<double>(ctx->W), n2p, v * v, split_of(ctx->wb, n2p, v * v), st);
     split(P<double>(ctx->ra_h), n2, (int)(2 * ov), split_of(ctx->rab_h, n2, (int)(2 * ov)), st);
     split(P<double>(ctx->r22_h), n2, (int)ov, split_of(ctx->r22b_h, n2, (int)ov), st);
@@ -354,26 +358,28 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   // the compact parts of [y1, sigma_2]_2 (the one-body part of Yg against
   // sigma's two-body), which stay in sp / sq for the lookups
   qf::launch_yg1(P<double>(ctx->f), t1, t2, n, o, P<double>(ctx->y1), P<double>(ctx->scal), st);
+  const int npo = o * n - o * (o - 1) / 2;   // non-zero ladder rows of Yg (see below)
+  const int kp = qf::bf16_pad(v * v);
+  Split wyb_rows{};
+  if (bf3) {   // Yg's ladder rows go straight into BF16 planes (npo rows each)
+    const Split wyb = split_of(ctx->wyb, (size_t)n * (n + 1) / 2, v * v);
+    wyb_rows = Split{wyb.hi, wyb.hi + (size_t)npo * kp};
+  }
   qf::launch_sigma2(P<double>(ctx->f), t2, n, o, P<double>(ctx->a12), P<double>(ctx->t2T), true,
                     P<double>(ctx->sp_f), P<double>(ctx->sq), part, pcap, P<double>(ctx->y2),
-                    mixed ? nullptr : P<double>(ctx->wy), mixed ? P<float>(ctx->wy32) : nullptr,
-                    st);
+                    (mixed || bf3) ? nullptr : P<double>(ctx->wy),
+                    mixed ? P<float>(ctx->wy32) : nullptr, wyb_rows.hi, wyb_rows.lo, st);
   qf::launch_sigma2(P<double>(ctx->y1), t2, n, o, P<double>(ctx->a12), P<double>(ctx->t2T),
                     false, P<double>(ctx->sp), P<double>(ctx->sq), part, pcap, nullptr, nullptr,
-                    nullptr, st);
+                    nullptr, nullptr, nullptr, st);
   const int npair = n * (n + 1) / 2;   // ladder rows p <= q
   // rows of Yg's ladder operand with p virtual (then q virtual too) vanish:
-  // the Yg ladder runs over the first o*n - o(o-1)/2 rows only
-  const int npo = o * n - o * (o - 1) / 2;
+  // the Yg ladder runs over the first npo = o*n - o(o-1)/2 rows only
   const size_t n2p = (size_t)npair;
-  const int kp = qf::bf16_pad(v * v);
-  Split tb{}, wyb_rows{};
-  if (bf3) {   // ladder operands of this step (the GEMM stages hold GEMMs only)
+  Split tb{};
+  if (bf3) {   // t2 as the ladder operand (the GEMM stages hold GEMMs only)
     tb = split_of(ctx->t2b, (size_t)o * o, v * v);
-    const Split wyb = split_of(ctx->wyb, n2p, v * v);
-    wyb_rows = Split{wyb.hi, wyb.hi + (size_t)npo * kp};   // hi | lo of the npo rows
     split(t2, (size_t)o * o, v * v, tb, st);
-    split(P<double>(ctx->wy), (size_t)npo, v * v, wyb_rows, st);
   } else if (mixed) {
     qf::launch_cvt_f32(t2, P<float>(ctx->t2_32), ov * ov, st);
   }
@@ -400,13 +406,11 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   }
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[3], st));
   if (bf3) {
-    qf::launch_pack_ring_T(t2, o, v, P<double>(ctx->rta), P<double>(ctx->rt22), st);
-    qf::launch_pack_ring_A(P<double>(ctx->y2), n, o, P<double>(ctx->ra_y), P<double>(ctx->r22_y),
-                           st);
-    split(P<double>(ctx->rta), ov, (int)(2 * ov), split_of(ctx->rtab, ov, (int)(2 * ov)), st);
-    split(P<double>(ctx->rt22), ov, (int)ov, split_of(ctx->rt22b, ov, (int)ov), st);
-    split(P<double>(ctx->ra_y), n2, (int)(2 * ov), split_of(ctx->rab_y, n2, (int)(2 * ov)), st);
-    split(P<double>(ctx->r22_y), n2, (int)ov, split_of(ctx->r22b_y, n2, (int)ov), st);
+    const Split ta = split_of(ctx->rtab, ov, (int)(2 * ov)), t22 = split_of(ctx->rt22b, ov, (int)ov);
+    const Split ay = split_of(ctx->rab_y, n2, (int)(2 * ov));
+    const Split a22y = split_of(ctx->r22b_y, n2, (int)ov);
+    qf::launch_pack_ring_T_bf16(t2, o, v, ta.hi, ta.lo, t22.hi, t22.lo, st);
+    qf::launch_pack_ring_A_bf16(P<double>(ctx->y2), n, o, ay.hi, ay.lo, a22y.hi, a22y.lo, st);
   } else if (mixed) {
     qf::launch_pack_ring_T(t2, o, v, P<float>(ctx->rta32), P<float>(ctx->rt22_32), st);
     qf::launch_pack_ring_A(P<double>(ctx->y2), n, o, P<float>(ctx->ra32_y),
