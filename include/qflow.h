@@ -182,6 +182,25 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
                     const int32_t* owner2, double* t1, double* t2, double* energy, double* e_mean,
                     double* max_dt, int32_t flags);
 
+/* One windowed Gauss-Seidel sweep (the process groups of the paper's
+ * parallel implementation take spaces in Delta-eps order and update the pool
+ * as they finish): the spaces, in the given order, are taken in consecutive
+ * windows of `window` spaces; for each window the downfolded Hamiltonians
+ * are built from the pool as it stands, the window's spaces are solved, and
+ * the amplitudes they own are written into t1, t2 before the next window.
+ * Amplitudes no space owns take t <- t - R/Delta with R from the pool at the
+ * start of the sweep (unless QFLOW_UNOWNED_FROZEN), so window >= K gives the
+ * same result as qflow_flow_step.  Arguments as for qflow_flow_step; flags:
+ * precision and QFLOW_UNOWNED_FROZEN (QFLOW_GRAPH and QFLOW_DIIS are
+ * rejected with QFLOW_E_UNSUPPORTED); window < 1 is QFLOW_E_INVALID_ARG.
+ * Each window recomputes every global intermediate, so a sweep costs about
+ * ceil(K / window) times the global part of a flow step.  *max_dt = max
+ * |t_end - t_start|.  Synchronises the stream. */
+int qflow_flow_sweep_windowed(qflow_ctx* ctx, int32_t K, const qflow_space* spaces,
+                              const int32_t* owner1, const int32_t* owner2, double* t1,
+                              double* t2, double* energy, int32_t window, double* e_mean,
+                              double* max_dt, int32_t flags);
+
 /* Per-stage device times of the last qflow_flow_step in milliseconds (HIP
  * events on the context's stream), in the order: [F,sigma] intermediate,
  * ladder contraction of H_N, ladder contraction of [F,sigma], ring operand

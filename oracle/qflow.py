@@ -341,3 +341,53 @@ def flow_step_diis(pb: Problem, t1, t2, spaces, owner1, owner2, diis: DIIS,
     x = diis.step(pack(nt1, nt2), pack(nt1, nt2) - pack(t1, t2))
     xt1, xt2 = unpack(x, pb.o, pb.v)
     return xt1, xt2, E, Em, sols
+
+
+# ----------------------------------------------------------------------------
+# windowed Gauss-Seidel sweep (the paper's process groups taking spaces in
+# Delta-epsilon order and updating the pool as they finish)
+# ----------------------------------------------------------------------------
+
+def flow_sweep_windowed(pb: Problem, t1, t2, spaces, owner1, owner2, window,
+                        unowned="residual"):
+    """One sweep over the spaces (Delta-epsilon order) in consecutive windows
+    of `window` spaces: each window's spaces are solved with the pool as it
+    stands, then their owned amplitudes are written into the pool before the
+    next window starts.  The amplitudes no space owns take t <- t - R/Delta
+    with R from the pool at the start of the sweep (as in the Jacobi step, so
+    a single window reproduces it).  Returns new (t1, t2), per-space energies
+    and their mean."""
+    o = pb.o
+    step_unowned = unowned == "residual" and (np.any(owner1 < 0) or np.any(owner2 < 0))
+    if step_unowned:
+        R1, R2, _ = residual(pb, t1, t2)
+    t1, t2 = t1.copy(), t2.copy()
+    E = np.zeros(len(spaces))
+    for w0 in range(0, len(spaces), window):
+        chunk = list(range(w0, min(w0 + window, len(spaces))))
+        sols = {k: solve_space(pb, t1, t2, tuple(spaces[k][0]) + tuple(spaces[k][1]),
+                               len(spaces[k][0])) for k in chunk}
+        for k in chunk:
+            s = sols[k]
+            E[k] = s["E"]
+            if abs(s["c0"]) < REF_WEIGHT_MIN:
+                continue
+            occ, vir = spaces[k]
+            for I, i in enumerate(occ):
+                for A, a in enumerate(vir):
+                    if owner1[i, a - o] == k:
+                        t1[i, a - o] = s["t1"][I, A]
+            for I, i in enumerate(occ):
+                for J, j in enumerate(occ):
+                    for A, a in enumerate(vir):
+                        for B, b in enumerate(vir):
+                            if owner2[i, j, a - o, b - o] == k:
+                                t2[i, j, a - o, b - o] = s["t2"][I, J, A, B]
+    if step_unowned:
+        e = pb.eps
+        d1 = e[o:][None, :] - e[:o][:, None]
+        d2 = (e[o:][None, None, :, None] + e[o:][None, None, None, :]
+              - e[:o][:, None, None, None] - e[:o][None, :, None, None])
+        t1 = np.where(owner1 < 0, t1 - R1 / d1, t1)
+        t2 = np.where(owner2 < 0, t2 - R2 / d2, t2)
+    return t1, t2, E, float(np.mean(E))

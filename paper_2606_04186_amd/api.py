@@ -61,6 +61,8 @@ def lib() -> ctypes.CDLL:
             "qflow_solve_active_batch": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp,
                                                         vp, vp, vp, vp, d, i32]),
             "qflow_flow_step": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32]),
+            "qflow_flow_sweep_windowed": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, i32, vp,
+                                                         vp, i32]),
             "qflow_last_timings": (ctypes.c_int, [vp, vp, ctypes.c_int]),
             "qflow_sample_spaces": (ctypes.c_int, [i32, i32, i32, i32, vp, vp, i64, i32, vp, vp,
                                                    i32, vp, vp]),
@@ -191,6 +193,15 @@ class Context:
         self._check(lib().qflow_flow_step(self.h, len(sp), _ptr(sp), _ptr(owner1), _ptr(owner2),
                                           _ptr(t1), _ptr(t2), _ptr(energy), ctypes.byref(em),
                                           ctypes.byref(md), flags))
+        return em.value, md.value
+
+    def flow_sweep_windowed(self, spaces, owner1, owner2, t1, t2, energy, window, flags=FP64):
+        """One windowed Gauss-Seidel sweep; returns (e_mean, max_dt)."""
+        sp = _spaces(spaces)
+        em, md = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().qflow_flow_sweep_windowed(
+            self.h, len(sp), _ptr(sp), _ptr(owner1), _ptr(owner2), _ptr(t1), _ptr(t2),
+            _ptr(energy), int(window), ctypes.byref(em), ctypes.byref(md), flags))
         return em.value, md.value
 
     STAGES = ("yg", "ladder_h", "ladder_yg", "ring_pack", "ring_gemm", "ring_j", "sigma1_x",

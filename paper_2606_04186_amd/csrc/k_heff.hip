@@ -46,10 +46,11 @@ __device__ void load_active(const SpaceDev& sp, int n, int o, Active& A) {
 // D_2(t;a,b,c) = -D_0(t;c,a,b), D_3(t;a,b,c) = -D_1(t;c,a,b).
 __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
                                                   const SpaceDev* __restrict__ spaces,
-                                                  double* tab, int64_t tab_stride) {
+                                                  const int32_t* __restrict__ idx, double* tab,
+                                                  int64_t tab_stride) {
   __shared__ Active A;
   constexpr int kNa = 8;   // largest supported space, (4,4)
-  const int k = blockIdx.x;
+  const int k = idx[blockIdx.x];
   const SpaceDev sp = spaces[k];
   load_active(sp, g.n, g.o, A);
   const int n = g.n;
@@ -231,10 +232,11 @@ __global__ __launch_bounds__(BLK, (PART < 2 && BLK == 256) ? 7 : 1) void k_heff_
 //   Ec = x0 - 2 sum_k x1_kk + sum_kl (2 x2_klkl - x2_kllk)
 //   h_pq = x1_pq - sum_k (2 x2_pkqk - x2_pkkq),  g(pq|rs) = x2_prqs
 __global__ __launch_bounds__(256) void k_heff_cas(const SpaceDev* __restrict__ spaces,
+                                                  const int32_t* __restrict__ idx,
                                                   const int64_t* __restrict__ heff_off,
                                                   double* heff) {
   extern __shared__ double sm[];
-  const int k = blockIdx.x;
+  const int k = idx[blockIdx.x];
   const SpaceDev sp = spaces[k];
   const int na = sp.na, ne = sp.nocc, n2 = na * na, n4 = n2 * n2;
   double* slot = heff + heff_off[k];
@@ -300,7 +302,7 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
               rings.z_h,  rings.z_y, rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
               rings.lo_h, rings.lo_y, rings.pf};
   const int tab_stride = heff_table_stride(na_max);
-  k_heff_tab<<<K, kBlock, 0, st>>>(g, spaces, tab, tab_stride);
+  k_heff_tab<<<K, kBlock, 0, st>>>(g, spaces, cls_idx, tab, tab_stride);
   // parts 0, 1, 2 per size class: its task count and LDS.  The (4,4) class
   // (about 100 KB of staged tables) runs 1024-thread workgroups, so that its
   // tables are staged twice per space instead of five times and four times
@@ -353,7 +355,7 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
     }
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
   const size_t lds = (size_t)tasks * sizeof(double);
-  k_heff_cas<<<K, kBlock, lds, st>>>(spaces, heff_off, heff);
+  k_heff_cas<<<K, kBlock, lds, st>>>(spaces, cls_idx, heff_off, heff);
 }
 
 }  // namespace qf

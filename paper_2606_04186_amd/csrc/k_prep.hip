@@ -326,9 +326,9 @@ __global__ void k_scatter_owned(const SpaceDev* __restrict__ spaces, const doubl
                                 const int64_t* __restrict__ amp_off,
                                 const int32_t* __restrict__ status,
                                 const int32_t* __restrict__ owner1,
-                                const int32_t* __restrict__ owner2, int n, int o, double* t1n,
-                                double* t2n) {
-  const int k = blockIdx.x;
+                                const int32_t* __restrict__ owner2, int n, int o, int k0,
+                                double* t1n, double* t2n) {
+  const int k = k0 + blockIdx.x;
   if (status[k] != 0) return;
   const SpaceDev sp = spaces[k];
   const int ne = sp.nocc, nv = sp.na - sp.nocc, v = n - o;
@@ -888,9 +888,31 @@ void launch_update(const double* t1, const double* t2, const double* r1, const d
 
 void launch_scatter_owned(const SpaceDev* spaces, const double* amp, const int64_t* amp_off,
                           const int32_t* status, const int32_t* owner1, const int32_t* owner2,
-                          int n, int o, int K, double* t1n, double* t2n, hipStream_t st) {
-  k_scatter_owned<<<K, kBlock, 0, st>>>(spaces, amp, amp_off, status, owner1, owner2, n, o, t1n,
-                                         t2n);
+                          int n, int o, int k0, int K, double* t1n, double* t2n, hipStream_t st) {
+  k_scatter_owned<<<K, kBlock, 0, st>>>(spaces, amp, amp_off, status, owner1, owner2, n, o, k0,
+                                         t1n, t2n);
+}
+
+__global__ void k_merge_unowned(const double* __restrict__ t1n, const double* __restrict__ t2n,
+                                const int32_t* __restrict__ owner1,
+                                const int32_t* __restrict__ owner2, size_t nt1, size_t nt2,
+                                double* t1, double* t2) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nt1 + nt2;
+       i += (size_t)gridDim.x * blockDim.x) {
+    if (i < nt2) {
+      if (owner2[i] < 0) t2[i] = t2n[i];
+    } else if (owner1[i - nt2] < 0) {
+      t1[i - nt2] = t1n[i - nt2];
+    }
+  }
+}
+
+void launch_merge_unowned(const double* t1n, const double* t2n, const int32_t* owner1,
+                          const int32_t* owner2, int o, int v, double* t1, double* t2,
+                          hipStream_t st) {
+  const size_t nt1 = (size_t)o * v, nt2 = nt1 * nt1;
+  k_merge_unowned<<<grid_for(nt1 + nt2, kBlock, 65536), kBlock, 0, st>>>(t1n, t2n, owner1,
+                                                                          owner2, nt1, nt2, t1, t2);
 }
 
 void launch_diis(const double* t1, const double* t2, int o, int v, double* T, double* E,

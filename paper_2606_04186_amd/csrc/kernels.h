@@ -104,7 +104,8 @@ void launch_residual(const double* f, const double* V, const double* y1, const d
 
 // per-space downfolded Hamiltonians in CAS form
 // The per-element kernels run one launch per size class (cls_idx / cls_off
-// as for launch_davidson; task_slots[c] = task count of class c).
+// as for launch_davidson; task_slots[c] = task count of class c); K = the
+// number of spaces in the lists (cls_off[3]).
 void launch_heff(const double* f, const double* V, const double* y1, const double* y2,
                  const double* L, const double* LY, const RingOps& rings, const double* t1,
                  const double* t2, int n,
@@ -173,9 +174,15 @@ void launch_davidson(const DavidsonArgs& a, const int32_t* cls_idx, const int* c
 void launch_update(const double* t1, const double* t2, const double* r1, const double* r2,
                    const double* f, const int32_t* owner1, const int32_t* owner2, int n, int o,
                    bool unowned_step, double* t1n, double* t2n, hipStream_t st);
+// spaces k0 .. k0+K-1 write the amplitudes they own
 void launch_scatter_owned(const SpaceDev* spaces, const double* amp, const int64_t* amp_off,
                           const int32_t* status, const int32_t* owner1, const int32_t* owner2,
-                          int n, int o, int K, double* t1n, double* t2n, hipStream_t st);
+                          int n, int o, int k0, int K, double* t1n, double* t2n, hipStream_t st);
+// t[i] = owner[i] < 0 ? tn[i] : t[i] over t1 and t2 (the unowned step of a
+// windowed sweep, taken from the pool at its start)
+void launch_merge_unowned(const double* t1n, const double* t2n, const int32_t* owner1,
+                          const int32_t* owner2, int o, int v, double* t1, double* t2,
+                          hipStream_t st);
 // DIIS over the amplitude vector [t1 | t2]: up to kDiisMax (t_new, error)
 // pairs in T and E (kDiisMax * N doubles each), the Gram matrix of the
 // errors, the pair count and the extrapolation coefficients in one device

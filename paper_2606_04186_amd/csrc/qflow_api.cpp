@@ -84,6 +84,11 @@ struct qflow_ctx {
   // spaces grouped by size class (nocc 2, 3, 4): indices at [cls_off[c], cls_off[c+1])
   DevBuf cls_idx;
   int cls_off[4] = {0, 0, 0, 0};
+  // windowed sweeps: per window of win_size consecutive spaces, the class
+  // lists at win_idx + win_base[w] with offsets win_off[4w .. 4w+3]
+  DevBuf win_idx, t1s, t2s;
+  std::vector<int> win_base, win_off;
+  int win_size = 0;
   int task_slots[3] = {0, 0, 0};
   int lds_limit = 64 * 1024;   // dynamic LDS bytes a block may use
   // host mirror of the last uploaded space list
@@ -247,6 +252,7 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   ctx->last_spaces.assign(spaces, spaces + K);
   ++ctx->epoch;   // launch shapes of the per-space kernels follow the list
   ctx->diis_active = false;   // a new list starts a new DIIS history
+  ctx->win_size = 0;
   return QFLOW_OK;
 }
 
@@ -564,7 +570,8 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->ci,     &ctx->ci_off,
                     &ctx->c0,     &ctx->iters,    &ctx->status, &ctx->spaces,   &ctx->strings,
                     &ctx->out2,   &ctx->partial, &ctx->tasks, &ctx->mtab,   &ctx->cls_idx,
-                    &ctx->diis_t, &ctx->diis_e, &ctx->diis_part, &ctx->diis_state};
+                    &ctx->diis_t, &ctx->diis_e, &ctx->diis_part, &ctx->diis_state,
+                    &ctx->win_idx, &ctx->t1s,    &ctx->t2s};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -751,8 +758,18 @@ int check_offsets(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const in
   return QFLOW_OK;
 }
 
+// The downfolded Hamiltonians of the spaces in the class lists idx / cls_off
+// (count = cls_off[3]; the whole list when idx is NULL), after the residual
+// and zero-body parts of the pool (t1, t2).
 int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, double* heff,
-             const int64_t* heff_off_dev) {
+             const int64_t* heff_off_dev, const int32_t* idx = nullptr,
+             const int* cls_off = nullptr) {
+  if (!idx) {
+    idx = P<int32_t>(ctx->cls_idx);
+    cls_off = ctx->cls_off;
+  } else {
+    K = cls_off[3];
+  }
   // zero-body parts of [H_N, sigma] and [Yg, sigma] (scal[0], scal[1])
   qf::launch_residual(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
                       P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx),
@@ -765,8 +782,7 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
                     P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx), t1, t2, ctx->n, ctx->o,
                     P<double>(ctx->scal), P<SpaceDev>(ctx->spaces), heff_off_dev,
                     P<int32_t>(ctx->tasks), qf::kTaskStride, ctx->task_slots,
-                    P<int32_t>(ctx->cls_idx), ctx->cls_off, K, ctx->na_max,
-                    P<double>(ctx->mtab), heff, ctx->stream);
+                    idx, cls_off, K, ctx->na_max, P<double>(ctx->mtab), heff, ctx->stream);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -774,7 +790,13 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
 int run_solve(qflow_ctx* ctx, int32_t K, const double* heff, const int64_t* heff_off_dev,
               double* energy, double* c0, double* amp, const int64_t* amp_off_dev, double* ci,
               const int64_t* ci_off_dev, int32_t* iters, int32_t* status, double tol,
-              int32_t max_iter) {
+              int32_t max_iter, const int32_t* idx = nullptr, const int* cls_off = nullptr) {
+  if (!idx) {
+    idx = P<int32_t>(ctx->cls_idx);
+    cls_off = ctx->cls_off;
+  } else {
+    K = cls_off[3];
+  }
   if (K == 0) return QFLOW_OK;
   qf::DavidsonArgs a;
   a.spaces = P<SpaceDev>(ctx->spaces);
@@ -795,7 +817,7 @@ int run_solve(qflow_ctx* ctx, int32_t K, const double* heff, const int64_t* heff
   a.max_iter = max_iter;
   a.maxsub = kMaxSub;
   a.K = K;
-  qf::launch_davidson(a, P<int32_t>(ctx->cls_idx), ctx->cls_off, ctx->stream);
+  qf::launch_davidson(a, idx, cls_off, ctx->stream);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -830,7 +852,7 @@ int enqueue_step(qflow_ctx* ctx, int32_t K, const int32_t* owner1, const int32_t
   if (K > 0)
     qf::launch_scatter_owned(P<SpaceDev>(ctx->spaces), P<double>(ctx->amp),
                              P<int64_t>(ctx->amp_off), P<int32_t>(ctx->status), owner1, owner2,
-                             n, o, K, P<double>(ctx->t1n), P<double>(ctx->t2n), st);
+                             n, o, 0, K, P<double>(ctx->t1n), P<double>(ctx->t2n), st);
   if (diis)
     qf::launch_diis(t1, t2, o, v, P<double>(ctx->diis_t), P<double>(ctx->diis_e),
                     P<qf::DiisState>(ctx->diis_state), P<double>(ctx->diis_part),
@@ -844,6 +866,31 @@ int enqueue_step(qflow_ctx* ctx, int32_t K, const int32_t* owner1, const int32_t
   if (K > 0) qf::launch_copy(P<double>(ctx->energy), energy, (size_t)K, st);
   QF_HIP(hipGetLastError());
   if (timed) QF_HIP(hipEventRecord(ctx->ev[11], st));
+  return QFLOW_OK;
+}
+
+// Class lists of each window of W consecutive spaces of the uploaded list.
+int build_windows(qflow_ctx* ctx, int32_t K, int32_t W) {
+  if (ctx->win_size == W) return QFLOW_OK;
+  const int nwin = std::max(1, (K + W - 1) / W);
+  std::vector<int32_t> idx;
+  ctx->win_base.assign(nwin, 0);
+  ctx->win_off.assign(4 * nwin, 0);
+  for (int w = 0; w < nwin; ++w) {
+    const int k0 = w * W, k1 = std::min(K, k0 + W);
+    ctx->win_base[w] = (int)idx.size();
+    for (int c = 0; c < 3; ++c) {
+      ctx->win_off[4 * w + c] = (int)idx.size() - ctx->win_base[w];
+      for (int k = k0; k < k1; ++k)
+        if (ctx->last_spaces[k].n_o - 2 == c) idx.push_back(k);
+    }
+    ctx->win_off[4 * w + 3] = (int)idx.size() - ctx->win_base[w];
+  }
+  idx.resize(std::max<size_t>(idx.size(), 1), 0);
+  QF_TRY(ensure(ctx, ctx->win_idx, sizeof(int32_t) * idx.size()));
+  QF_HIP(hipMemcpy(ctx->win_idx.p, idx.data(), sizeof(int32_t) * idx.size(),
+                   hipMemcpyHostToDevice));
+  ctx->win_size = W;
   return QFLOW_OK;
 }
 
@@ -982,6 +1029,70 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
   float total = -1.f;
   if (hipEventElapsedTime(&total, ctx->ev[0], ctx->ev[kStages]) != hipSuccess) total = -1.f;
   ctx->total_ms = total;
+  return QFLOW_OK;
+}
+
+int qflow_flow_sweep_windowed(qflow_ctx* ctx, int32_t K, const qflow_space* spaces,
+                              const int32_t* owner1, const int32_t* owner2, double* t1,
+                              double* t2, double* energy, int32_t window, double* e_mean,
+                              double* max_dt, int32_t flags) {
+  QF_TRY(require_loaded(ctx));
+  QF_TRY(check_spaces(ctx, K, spaces));
+  if (!owner1 || !owner2 || !t1 || !t2 || !e_mean || !max_dt || (K > 0 && !energy))
+    return fail(ctx, QFLOW_E_INVALID_ARG, "NULL argument");
+  if (window < 1) return fail(ctx, QFLOW_E_INVALID_ARG, "window < 1");
+  if (flags & (QFLOW_GRAPH | QFLOW_DIIS))
+    return fail(ctx, QFLOW_E_UNSUPPORTED, "windowed sweeps take neither QFLOW_GRAPH nor QFLOW_DIIS");
+  const int precision = flags & 15;
+  if (precision != QFLOW_FP64 && precision != QFLOW_FP32 && precision != QFLOW_BF16X3)
+    return fail(ctx, QFLOW_E_UNSUPPORTED, "unknown precision");
+  QF_TRY(upload_spaces(ctx, K, spaces));
+  if (precision == QFLOW_FP32) QF_TRY(ensure_mixed(ctx));
+  if (precision == QFLOW_BF16X3) QF_TRY(ensure_bf16(ctx));
+  QF_TRY(build_windows(ctx, K, window));
+  const int n = ctx->n, o = ctx->o, v = ctx->v;
+  const size_t nt1 = (size_t)o * v, nt2 = nt1 * nt1;
+  QF_TRY(ensure(ctx, ctx->t1s, sizeof(double) * nt1));
+  QF_TRY(ensure(ctx, ctx->t2s, sizeof(double) * nt2));
+  const bool step = !(flags & QFLOW_UNOWNED_FROZEN);
+  hipStream_t st = ctx->stream;
+  ctx->timed = false;
+  qf::launch_copy(t1, P<double>(ctx->t1s), nt1, st);
+  qf::launch_copy(t2, P<double>(ctx->t2s), nt2, st);
+  const int nwin = (int)ctx->win_base.size();
+  for (int w = 0; w < nwin; ++w) {
+    const int32_t* idx = P<int32_t>(ctx->win_idx) + ctx->win_base[w];
+    const int* off = &ctx->win_off[4 * w];
+    const int k0 = w * window, count = off[3];
+    // global intermediates and residual of the pool as it stands
+    QF_TRY(prepare(ctx, t1, t2, precision));
+    QF_TRY(run_heff(ctx, 0, t1, t2, P<double>(ctx->heff), P<int64_t>(ctx->heff_off), idx, off));
+    // the unowned step takes the residual of the pool at the start of the
+    // sweep (the first window's); its result is merged after the last window
+    if (w == 0)
+      qf::launch_update(t1, t2, P<double>(ctx->r1), P<double>(ctx->r2), P<double>(ctx->f),
+                        owner1, owner2, n, o, step, P<double>(ctx->t1n), P<double>(ctx->t2n),
+                        st);
+    QF_TRY(run_solve(ctx, 0, P<double>(ctx->heff), P<int64_t>(ctx->heff_off),
+                     P<double>(ctx->energy), P<double>(ctx->c0), P<double>(ctx->amp),
+                     P<int64_t>(ctx->amp_off), P<double>(ctx->ci), P<int64_t>(ctx->ci_off),
+                     P<int32_t>(ctx->iters), P<int32_t>(ctx->status), 1e-10, 200, idx, off));
+    if (count > 0)
+      qf::launch_scatter_owned(P<SpaceDev>(ctx->spaces), P<double>(ctx->amp),
+                               P<int64_t>(ctx->amp_off), P<int32_t>(ctx->status), owner1, owner2,
+                               n, o, k0, std::min(window, K - k0), t1, t2, st);
+  }
+  qf::launch_merge_unowned(P<double>(ctx->t1n), P<double>(ctx->t2n), owner1, owner2, o, v, t1, t2,
+                           st);
+  qf::launch_finish(P<double>(ctx->energy), K, P<double>(ctx->t1s), P<double>(ctx->t2s), t1, t2,
+                    o, v, P<double>(ctx->dtpart), P<double>(ctx->out2), st);
+  if (K > 0) qf::launch_copy(P<double>(ctx->energy), energy, (size_t)K, st);
+  QF_HIP(hipGetLastError());
+  double out[2];
+  QF_HIP(hipMemcpyAsync(out, ctx->out2.p, sizeof(out), hipMemcpyDeviceToHost, st));
+  QF_HIP(hipStreamSynchronize(st));
+  *e_mean = out[0];
+  *max_dt = out[1];
   return QFLOW_OK;
 }
 

@@ -501,3 +501,87 @@ def test_flow_step_diis_matches_oracle(graph):
         assert np.abs(host(g1) - t1).max() < 1e-8, it
         assert np.abs(host(g2) - t2).max() < 1e-8, it
         assert abs(dt - ddt) < 1e-8, it
+
+
+def test_windowed_sweep_matches_oracle():
+    """Two windowed Gauss-Seidel sweeps (windows of 5, 5 and 2 spaces) against
+    the oracle, partial coverage on 24 orbitals."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    n, o, seed, K = 24, 4, 191, 12
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    v = n - o
+    lists = _spaces_for(n, o, K, seed, pb.eps)
+    o1, o2 = sampling.ownership(o, v, lists)
+    t1, t2 = qflow.mp2_guess(pb.f, eri, o)
+    sp = qf.make_spaces(lists)
+    ctx = context(h, eri, o)
+    g1, g2 = dev(t1), dev(t2)
+    energy = torch.zeros(len(lists), dtype=torch.float64, device="cuda")
+    d1, d2 = dev(o1, torch.int32), dev(o2, torch.int32)
+    for it in range(2):
+        em, dt = ctx.flow_sweep_windowed(sp, d1, d2, g1, g2, energy, 5)
+        nt1, nt2, E, Em = qflow.flow_sweep_windowed(pb, t1, t2, lists, o1, o2, 5)
+        ddt = max(np.abs(nt1 - t1).max(), np.abs(nt2 - t2).max())
+        t1, t2 = nt1, nt2
+        print(f"sweep {it}: E_mean {em:.12f} max|dt| {dt:.3e}")
+        assert abs(em - Em) < 1e-9, it
+        assert np.abs(host(energy) - E).max() < 1e-9, it
+        assert np.abs(host(g1) - t1).max() < 1e-8, it
+        assert np.abs(host(g2) - t2).max() < 1e-8, it
+        assert abs(dt - ddt) < 1e-8, it
+
+
+def test_windowed_sweep_single_window_equals_flow_step():
+    """A window holding every space reproduces the Jacobi flow step."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    n, o, seed, K = 24, 4, 192, 12
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    v = n - o
+    lists = _spaces_for(n, o, K, seed, pb.eps)
+    o1, o2 = sampling.ownership(o, v, lists)
+    t1, t2 = qflow.mp2_guess(pb.f, eri, o)
+    sp = qf.make_spaces(lists)
+    d1, d2 = dev(o1, torch.int32), dev(o2, torch.int32)
+    ca, cb = context(h, eri, o), context(h, eri, o)
+    a1, a2, b1, b2 = dev(t1), dev(t2), dev(t1), dev(t2)
+    ea = torch.zeros(K, dtype=torch.float64, device="cuda")
+    eb = torch.zeros(K, dtype=torch.float64, device="cuda")
+    ema, dta = ca.flow_step(sp, d1, d2, a1, a2, ea)
+    emb, dtb = cb.flow_sweep_windowed(sp, d1, d2, b1, b2, eb, K + 3)
+    assert abs(ema - emb) < 1e-12 and abs(dta - dtb) < 1e-12
+    assert (ea - eb).abs().max().item() < 1e-12
+    assert (a1 - b1).abs().max().item() < 1e-12 and (a2 - b2).abs().max().item() < 1e-12
+    with pytest.raises(qf.QFlowError) as e:
+        cb.flow_sweep_windowed(sp, d1, d2, b1, b2, eb, 0)
+    assert e.value.code == -1
+    with pytest.raises(qf.QFlowError) as e:
+        cb.flow_sweep_windowed(sp, d1, d2, b1, b2, eb, 4, qf.GRAPH)
+    assert e.value.code == -8
+
+
+def test_windowed_sweep_size_classes_matches_oracle():
+    """One windowed sweep (windows of 3) over (2,2), (3,3) and (4,4) spaces."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    n, o, seed = 16, 5, 193
+    h, eri = problem(n, o, seed)
+    pb = qflow.Problem(h, eri, o)
+    v = n - o
+    lists = _mixed_spaces(n, o, seed, pb.eps, caps=(3, 2, 2))
+    o1, o2 = sampling.ownership(o, v, lists)
+    t1, t2 = qflow.mp2_guess(pb.f, eri, o)
+    sp = qf.make_spaces(lists)
+    ctx = context(h, eri, o)
+    g1, g2 = dev(t1), dev(t2)
+    energy = torch.zeros(len(lists), dtype=torch.float64, device="cuda")
+    em, _ = ctx.flow_sweep_windowed(sp, dev(o1, torch.int32), dev(o2, torch.int32), g1, g2,
+                                    energy, 3)
+    nt1, nt2, E, Em = qflow.flow_sweep_windowed(pb, t1, t2, lists, o1, o2, 3)
+    assert abs(em - Em) < 1e-9
+    assert np.abs(host(energy) - E).max() < 1e-9
+    assert np.abs(host(g1) - nt1).max() < 1e-8
+    assert np.abs(host(g2) - nt2).max() < 1e-8

@@ -389,3 +389,26 @@ def test_diis_coefficients_minimise_the_error_norm():
     for i in range(3):
         y2 = dz2.step(T[i], e)
     assert np.array_equal(y2, T[2])
+
+
+def test_windowed_sweep_with_one_window_is_the_jacobi_step():
+    """A window holding every space reads one pool for all of them: the
+    windowed sweep then equals the Jacobi macro-iteration (same solves, same
+    owned writes, same residual step); with smaller windows the owned
+    amplitudes of the first window still equal the Jacobi ones, while later
+    windows see the updated pool."""
+    h, eri = synth.gen_integrals(12, 3, 24, 181, b_std=0.04, off_std=0.03)
+    pb = qflow.Problem(h, eri, 3)
+    lists = [(s[0], s[1]) for s in sampling.algorithm1(3, 9, 2, 2, pb.eps, synth.Stream(181),
+                                                       cap=6)]
+    o1, o2 = sampling.ownership(3, 9, lists)
+    t1, t2 = qflow.mp2_guess(pb.f, eri, 3)
+    j1, j2, Ej, Emj, _ = qflow.flow_step(pb, t1, t2, lists, o1, o2)
+    w1, w2, Ew, Emw = qflow.flow_sweep_windowed(pb, t1, t2, lists, o1, o2, window=len(lists))
+    assert np.array_equal(Ew, Ej) and Emw == Emj
+    assert np.array_equal(w1, j1) and np.array_equal(w2, j2)
+    g1, g2, Eg, _ = qflow.flow_sweep_windowed(pb, t1, t2, lists, o1, o2, window=2)
+    assert np.array_equal(Eg[:2], Ej[:2])
+    first = (o2 == 0) | (o2 == 1)
+    assert np.array_equal(g2[first], j2[first])
+    assert not np.allclose(Eg[2:], Ej[2:], rtol=0, atol=1e-12)
