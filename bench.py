@@ -52,6 +52,9 @@ def parse():
                     help="time eager launches only (default: the step as a captured HIP graph "
                          "gives `value`, an eager pass with per-stage events gives the stage "
                          "times and the roofline)")
+    ap.add_argument("--windowed", type=int, default=0, metavar="W",
+                    help="also time one windowed Gauss-Seidel sweep in windows of W spaces "
+                         "(the reported path's precision; reported in modes, not in value)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-spaces", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -201,6 +204,20 @@ def main():
         modes[key]["abs_dE_mean"] = dm
         modes[key]["abs_dE_max_space"] = dsp
     dominant = max((k_ for k_ in st if k_ != "total"), key=st.get)
+    if args.windowed > 0:
+        flag = {"fp64": qf.FP64, "fp32": qf.FP32, "bf16x3": qf.BF16X3}[use]
+        ctx.mp2_guess(t1, t2)
+        ctx.flow_sweep_windowed(spaces, d1, d2, t1, t2, energy, args.windowed, flag)   # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        em_w, dt_w = ctx.flow_sweep_windowed(spaces, d1, d2, t1, t2, energy, args.windowed, flag)
+        torch.cuda.synchronize()
+        ms_w = (time.perf_counter() - t0) * 1e3
+        modes["windowed"] = {"window": args.windowed, "precision": use, "ms_per_sweep": ms_w,
+                             "sweeps_per_s": 1e3 / ms_w, "e_mean": em_w, "max_dt": dt_w,
+                             "windows": (K + args.windowed - 1) // args.windowed}
+        print(f"[bench] windowed sweep (W={args.windowed}): {ms_w:.1f} ms, E_mean {em_w:.10f}",
+              file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
