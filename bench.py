@@ -90,13 +90,26 @@ def main():
     parts, deltas = [], []
     Kc = K // len(cfg["sizes"])
     for c, (no_c, nv_c) in enumerate(cfg["sizes"]):
-        u = synth.sampling_stream(args.config, c).uniform(64 * Kc)
-        sp_c, de_c, _ = qf.sample_spaces(o, v, no_c, nv_c, eps, u, cap=Kc)
-        assert len(sp_c) == Kc
+        if Kc > 0:
+            u = synth.sampling_stream(args.config, c).uniform(64 * Kc)
+            sp_c, de_c, _ = qf.sample_spaces(o, v, no_c, nv_c, eps, u, cap=Kc)
+            assert len(sp_c) == Kc
+        else:   # a full cycle: uniforms until every tuple is covered
+            nu = 1 << 20
+            while True:
+                u = synth.sampling_stream(args.config, c).uniform(nu)
+                try:
+                    sp_c, de_c, _ = qf.sample_spaces(o, v, no_c, nv_c, eps, u, cap=0,
+                                                     max_out=nu)
+                    break
+                except qf.QFlowError:
+                    nu *= 4
         parts.append(sp_c)
         deltas.append(de_c)
     order = np.argsort(np.concatenate(deltas), kind="stable")
     spaces = np.concatenate(parts)[order]
+    K = len(spaces)
+    Kc = K // len(cfg["sizes"])
     sizes_txt = " + ".join(f"{Kc} ({a},{b})" for a, b in cfg["sizes"])
     o1, o2 = qf.build_owners(o, v, spaces)
     d1 = torch.from_numpy(o1).to(dev)

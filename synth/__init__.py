@@ -29,13 +29,20 @@ _M1 = np.uint64(0xBF58476D1CE4E5B9)
 _M2 = np.uint64(0x94D049BB133111EB)
 _MASK64 = (1 << 64) - 1
 
-# Workload configurations: name -> (n_orb, n_occ, L, K, space sizes, seed index)
+# Workload configurations: name -> (n_orb, n_occ, L, K, space sizes, seed index);
+# K = 0 runs Algorithm 1 to full coverage
 CONFIGS = {
     "c1": dict(n=8, o=3, L=16, K=10, sizes=((3, 3),), idx=1),
     "c2": dict(n=40, o=5, L=80, K=256, sizes=((3, 3),), idx=2),
     "c3": dict(n=82, o=10, L=164, K=2048, sizes=((3, 3),), idx=3),
     "c4": dict(n=114, o=13, L=228, K=4096, sizes=((3, 3),), idx=4),
     "c5": dict(n=114, o=13, L=228, K=6144, sizes=((2, 2), (3, 3), (4, 4)), idx=5),
+    # full Algorithm 1 cycles (K = 0: every (o1<o2, v1<v2) tuple covered) at
+    # the shapes of the paper's largest workloads: 4 correlated occupied and
+    # 110 virtual orbitals (water, cc-pVQZ; about 10.3k spaces) and 13 and 69
+    # (propane, cc-pVDZ; about 56.9k spaces)
+    "c6": dict(n=114, o=4, L=228, K=0, sizes=((3, 3),), idx=6),
+    "c7": dict(n=82, o=13, L=164, K=0, sizes=((3, 3),), idx=7),
 }
 
 

@@ -175,3 +175,78 @@ def test_full_size_mixed_classes_sampled_against_oracle():
                             assert abs(F2[i, j, a - o, b - o] - ref) < 1e-8
                             assert abs(B2[i, j, a - o, b - o] - ref) < 1e-6
         print(f"({size},{size}) space {k}: {owned} owned amplitudes checked")
+
+
+def _full_cycle(qf, o, v, eps, name):
+    nu = 1 << 22
+    while True:
+        u = synth.sampling_stream(name, 0).uniform(nu)
+        try:
+            return qf.sample_spaces(o, v, 3, 3, eps, u, cap=0, max_out=nu)[0]
+        except qf.QFlowError:
+            nu *= 4
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,size", [("c6", 10319), ("c7", 56860)])
+def test_full_cycle_at_paper_shapes_sampled_against_oracle(name, size):
+    """A full Algorithm 1 cycle at the shapes of the paper's largest
+    workloads (4 + 110 orbitals, about 10.3k spaces; 13 + 69, about 56.9k):
+    every amplitude is owned, so the pool update is the paper's pure
+    owned-amplitude rule.  The first and last spaces' energies and owned
+    amplitudes (FP64, and BF16x3 as a captured graph) against the oracle."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_04186_amd as qf
+    cfg = synth.CONFIGS[name]
+    n, o = cfg["n"], cfg["o"]
+    v = n - o
+    h, eri = synth.config_integrals(name)
+    dev = torch.device("cuda:0")
+    dh, deri = torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev)
+    ctx_b, ctx_f = qf.Context(0), qf.Context(0)
+    ctx_b.load_integrals(dh, deri, o)
+    ctx_f.load_integrals(dh, deri, o)
+    del dh, deri
+    _, eps, _ = ctx_b.reference()
+    spaces = _full_cycle(qf, o, v, eps, name)
+    K = len(spaces)
+    assert abs(K - size) / size < 0.05
+    o1, o2 = qf.build_owners(o, v, spaces)
+    assert (o1 >= 0).all() and (o2 >= 0).all()
+    d1, d2 = torch.from_numpy(o1).to(dev), torch.from_numpy(o2).to(dev)
+    t1 = torch.zeros(o, v, dtype=torch.float64, device=dev)
+    t2 = torch.zeros(o, o, v, v, dtype=torch.float64, device=dev)
+    ctx_b.mp2_guess(t1, t2)
+    t1h, t2h = t1.cpu().numpy().copy(), t2.cpu().numpy().copy()
+    b1, b2, f1, f2 = t1.clone(), t2.clone(), t1.clone(), t2.clone()
+    eb = torch.zeros(K, dtype=torch.float64, device=dev)
+    ef = torch.zeros(K, dtype=torch.float64, device=dev)
+    ctx_b.flow_step(spaces, d1, d2, b1, b2, eb, qf.BF16X3 | qf.GRAPH)
+    ctx_f.flow_step(spaces, d1, d2, f1, f2, ef, qf.FP64)
+    Eb, Ef = eb.cpu().numpy(), ef.cpu().numpy()
+    B1, B2, F1, F2 = (x.cpu().numpy() for x in (b1, b2, f1, f2))
+    assert np.abs(Eb - Ef).max() < 1e-6
+    pb = qflow.Problem(h, eri, o)
+    for k in (0, K - 1):
+        s = spaces[k]
+        occ = [int(x) for x in s["orb"][:3]]
+        vir = [int(x) for x in s["orb"][3:6]]
+        sol = qflow.solve_space(pb, t1h, t2h, tuple(occ) + tuple(vir), 3)
+        print(f"{name} space {k} of {K}: E oracle {sol['E']:.12f} FP64 {Ef[k]:.12f} "
+              f"BF16x3 {Eb[k]:.12f}")
+        assert abs(Ef[k] - sol["E"]) < 1e-9
+        assert abs(Eb[k] - sol["E"]) < 1e-6
+        for I, i in enumerate(occ):
+            for A, a in enumerate(vir):
+                if o1[i, a - o] == k:
+                    assert abs(F1[i, a - o] - sol["t1"][I, A]) < 1e-8
+                    assert abs(B1[i, a - o] - sol["t1"][I, A]) < 1e-6
+        for I, i in enumerate(occ):
+            for J, j in enumerate(occ):
+                for A, a in enumerate(vir):
+                    for Bv, b in enumerate(vir):
+                        if o2[i, j, a - o, b - o] == k:
+                            ref = sol["t2"][I, J, A, Bv]
+                            assert abs(F2[i, j, a - o, b - o] - ref) < 1e-8
+                            assert abs(B2[i, j, a - o, b - o] - ref) < 1e-6
