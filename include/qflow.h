@@ -37,8 +37,9 @@ typedef struct qflow_ctx qflow_ctx;
 
 /* One active space (Eq. (3) partition): n_o occupied then n_v virtual
  * absolute orbital indices in orb[], each group ascending.  Supported sizes:
- * (n_o, n_v) = (2,2) and (3,3) (36 and 400 determinants); other sizes give
- * QFLOW_E_UNSUPPORTED. */
+ * (n_o, n_v) = (2,2), (3,3) and (4,4) (36, 400 and 4900 determinants), mixed
+ * freely in one list; other sizes give QFLOW_E_UNSUPPORTED, and so does a
+ * list whose largest space needs more LDS than the device offers. */
 typedef struct {
   int32_t n_o, n_v;
   int32_t orb[8];
