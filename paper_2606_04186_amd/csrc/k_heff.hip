@@ -212,19 +212,64 @@ __global__ __launch_bounds__(BLK, (PART < 2 && BLK == 256) ? 7 : 1) void k_heff_
       x = scal[1] - ct.c0();
     emit(x, 0.5, false);
   } else {
+    // two-body elements only; the one- and zero-body ones (k_heff_low) take
+    // a wavefront each
     static_assert(PART != 2 || NA > 0, "the marked evaluation needs the space size");
+    if (kind != 2) return;
     const MarkedE<NA> E{T};
     const MarkedSigma<NA> D{T};
     const MarkedShape<NA> shape;
     const CommE<MarkedE<NA>, MarkedSigma<NA>, true, MarkedShape<NA>> ce{E, D, shape, n, o};
-    double x;   // (local indices)
-    if (kind == 2)
-      x = ce.c2(la, lb, lc, ld);
-    else if (kind == 1)
-      x = ce.c1(la, lb);
-    else
-      x = ce.c0();
-    emit(x, -0.5, false);
+    emit(ce.c2(la, lb, lc, ld), -0.5, false);   // (local indices)
+  }
+}
+
+// The one- and zero-body elements of part 2 (- 1/2 [E,sigma]): one
+// wavefront per element (the pairs la <= lb, then the scalar), its terms
+// split over the 64 lanes and summed; 512 threads per space.
+template <int NA>
+__global__ __launch_bounds__(512) void k_heff_low(const SpaceDev* __restrict__ spaces,
+                                                  const int32_t* __restrict__ idx,
+                                                  const int64_t* __restrict__ heff_off,
+                                                  const double* __restrict__ tab,
+                                                  int64_t tab_stride, int n, int o,
+                                                  double* heff) {
+  extern __shared__ double tl[];
+  const int k = idx[blockIdx.x];
+  int s1, s2, s3, s4;
+  const int tot = mark_sizes(NA, &s1, &s2, &s3, &s4);
+  const double* src = tab + (int64_t)k * tab_stride;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) tl[e] = src[e];
+  __syncthreads();
+  const MarkTables T{tl, tl + s1, tl + s1 + s2, tl + s1 + s2 + s3, NA};
+  const MarkedE<NA> E{T};
+  const MarkedSigma<NA> D{T};
+  const MarkedShape<NA> shape;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  CommE<MarkedE<NA>, MarkedSigma<NA>, true, MarkedShape<NA>> ce{E, D, shape, n, o};
+  ce.ln = lane;
+  ce.nl = 64;
+  double* slot = heff + heff_off[k];
+  constexpr int npairs = NA * (NA + 1) / 2;
+  for (int e = wave; e <= npairs; e += blockDim.x / 64) {
+    int la = 0, lb = 0;
+    if (e < npairs) {   // the e-th pair la <= lb
+      int r = e;
+      while (r >= NA - la) {
+        r -= NA - la;
+        ++la;
+      }
+      lb = la + r;
+    }
+    const double x = wave_sum(e < npairs ? ce.c1(la, lb) : ce.c0());
+    if (lane == 0) {
+      if (e < npairs) {
+        slot[1 + la * NA + lb] += -0.5 * x;
+        if (la != lb) slot[1 + lb * NA + la] += -0.5 * x;
+      } else {
+        slot[0] += -0.5 * x;
+      }
+    }
   }
 }
 
@@ -353,6 +398,22 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
                                                           task_table, task_stride, tab, tab_stride,
                                                           heff);
     }
+  for (int c = 0; c < 3; ++c) {
+    const int count = cls_off[c + 1] - cls_off[c];
+    if (count <= 0) continue;
+    const int na = 2 * (c + 2);
+    int s1, s2, s3, s4;
+    const size_t lds = (size_t)mark_sizes(na, &s1, &s2, &s3, &s4) * sizeof(double);
+    const int32_t* idx = cls_idx + cls_off[c];
+    if (c == 0) {
+      k_heff_low<4><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
+    } else if (c == 1) {
+      k_heff_low<6><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
+    } else {
+      allow_lds(&k_heff_low<8>, lds);
+      k_heff_low<8><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
+    }
+  }
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
   const size_t lds = (size_t)tasks * sizeof(double);
   k_heff_cas<<<K, kBlock, lds, st>>>(spaces, cls_idx, heff_off, heff);

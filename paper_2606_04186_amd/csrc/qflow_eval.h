@@ -626,12 +626,22 @@ QF_HD Comm<AOp, BOp> make_comm_split(const AOp& a, const BOp& b, int n, int o, i
 // themselves (kMarked = false), or, with the sum over the external orbital x
 // moved inside per-space tables, the active orbital t that E's Fock leg
 // attaches to (kMarked = true; the index is passed as the marker -1-t).
+// The marker of the marked evaluation: the active orbital t that E's Fock leg
+// attaches to, carried as its own type so that each accessor call resolves
+// the marked slot at compile time.
+struct Mk {
+  int t;
+};
+
 template <class EOp, class BOp, bool kMarked = false, class ActT = Active>
 struct CommE {
   const EOp& a;        // E accessor (one index external, or marked)
   const BOp& b;        // sigma accessor (one index external, or marked)
   const ActT& A;
   int n, o;
+  // Lane split of the one- and zero-body elements: the terms are taken in
+  // turn by lanes ln, ln + nl, ...; the caller sums the nl partial results.
+  int ln = 0, nl = 1;
 
   // In marked mode every index is local (the position in A.orb, occupied
   // first) and markers are negative; the class tests below never see markers.
@@ -648,7 +658,7 @@ struct CommE {
   QF_HD void over_ext(bool occupied, F fn) const {
     if constexpr (kMarked) {
 #pragma unroll 1
-      for (int t = 0; t < A.na; ++t) fn(-1 - t);
+      for (int t = 0; t < A.na; ++t) fn(Mk{t});
     } else {
 #pragma unroll 1
       for (int k = 0; k < A.next(occupied); ++k) fn(A.extv(occupied, k));
@@ -657,20 +667,20 @@ struct CommE {
   // (t in block bt, u in block bu) with exactly one of t, u external
   template <class F>
   QF_HD void pair1(bool bt, bool bu, F fn) const {
-    over_ext(bt, [&](int x) {
+    over_ext(bt, [&](auto x) {
 #pragma unroll 1
       for (int m = 0; m < A.nact(bu); ++m) fn(x, act_at(bu, m));
     });
 #pragma unroll 1
     for (int k = 0; k < A.nact(bt); ++k) {
       const int t = act_at(bt, k);
-      over_ext(bu, [&](int x) { fn(t, x); });
+      over_ext(bu, [&](auto x) { fn(t, x); });
     }
   }
   // (t, u, w) with exactly one external
   template <class F>
   QF_HD void triple1(bool bt, bool bu, bool bw, F fn) const {
-    over_ext(bt, [&](int x) {
+    over_ext(bt, [&](auto x) {
 #pragma unroll 1
       for (int j = 0; j < A.nact(bu); ++j)
 #pragma unroll 1
@@ -678,7 +688,7 @@ struct CommE {
     });
 #pragma unroll 1
     for (int i = 0; i < A.nact(bt); ++i)
-      over_ext(bu, [&](int x) {
+      over_ext(bu, [&](auto x) {
 #pragma unroll 1
         for (int k = 0; k < A.nact(bw); ++k) fn(act_at(bt, i), x, act_at(bw, k));
       });
@@ -686,36 +696,36 @@ struct CommE {
     for (int i = 0; i < A.nact(bt); ++i)
 #pragma unroll 1
       for (int j = 0; j < A.nact(bu); ++j)
-        over_ext(bw, [&](int x) { fn(act_at(bt, i), act_at(bu, j), x); });
+        over_ext(bw, [&](auto x) { fn(act_at(bt, i), act_at(bu, j), x); });
   }
 
   QF_HD double c2(int p, int q, int r, int s) const {
     double res = 0.0;
     const bool op = occ(p), oq = occ(q), or_ = occ(r), os = occ(s);
-    if (or_ == os && oq != or_) over_ext(oq, [&](int t) { res += a.one(p, t) * b.two(t, q, r, s); });
-    if (or_ == os && op != or_) over_ext(op, [&](int t) { res += a.one(q, t) * b.two(p, t, r, s); });
-    if (op == oq && os != op) over_ext(os, [&](int t) { res -= a.one(t, r) * b.two(p, q, t, s); });
-    if (op == oq && or_ != op) over_ext(or_, [&](int t) { res -= a.one(t, s) * b.two(p, q, r, t); });
-    over_ext(!op, [&](int t) { res -= b.one(p, t) * a.two(t, q, r, s); });
-    over_ext(!oq, [&](int t) { res -= b.one(q, t) * a.two(p, t, r, s); });
-    over_ext(!or_, [&](int t) { res += b.one(t, r) * a.two(p, q, t, s); });
-    over_ext(!os, [&](int t) { res += b.one(t, s) * a.two(p, q, r, t); });
-    if (or_ && os) pair1(false, false, [&](int t, int u) { res += a.two(p, q, t, u) * b.two(t, u, r, s); });
-    if (!or_ && !os) pair1(true, true, [&](int t, int u) { res -= a.two(p, q, t, u) * b.two(t, u, r, s); });
-    if (!op && !oq) pair1(true, true, [&](int t, int u) { res += b.two(p, q, t, u) * a.two(t, u, r, s); });
-    if (op && oq) pair1(false, false, [&](int t, int u) { res -= b.two(p, q, t, u) * a.two(t, u, r, s); });
+    if (or_ == os && oq != or_) over_ext(oq, [&](auto t) { res += a.one(p, t) * b.two(t, q, r, s); });
+    if (or_ == os && op != or_) over_ext(op, [&](auto t) { res += a.one(q, t) * b.two(p, t, r, s); });
+    if (op == oq && os != op) over_ext(os, [&](auto t) { res -= a.one(t, r) * b.two(p, q, t, s); });
+    if (op == oq && or_ != op) over_ext(or_, [&](auto t) { res -= a.one(t, s) * b.two(p, q, r, t); });
+    over_ext(!op, [&](auto t) { res -= b.one(p, t) * a.two(t, q, r, s); });
+    over_ext(!oq, [&](auto t) { res -= b.one(q, t) * a.two(p, t, r, s); });
+    over_ext(!or_, [&](auto t) { res += b.one(t, r) * a.two(p, q, t, s); });
+    over_ext(!os, [&](auto t) { res += b.one(t, s) * a.two(p, q, r, t); });
+    if (or_ && os) pair1(false, false, [&](auto t, auto u) { res += a.two(p, q, t, u) * b.two(t, u, r, s); });
+    if (!or_ && !os) pair1(true, true, [&](auto t, auto u) { res -= a.two(p, q, t, u) * b.two(t, u, r, s); });
+    if (!op && !oq) pair1(true, true, [&](auto t, auto u) { res += b.two(p, q, t, u) * a.two(t, u, r, s); });
+    if (op && oq) pair1(false, false, [&](auto t, auto u) { res -= b.two(p, q, t, u) * a.two(t, u, r, s); });
     res += xa(p, q, r, s) - xb(p, q, r, s) - xc(p, q, r, s) + xa(q, p, s, r);
     return res;
   }
   QF_HD double xa(int p, int q, int r, int s) const {
     double x = 0.0;
     if (!occ(q) && occ(s))
-      pair1(false, true, [&](int t, int u) {
+      pair1(false, true, [&](auto t, auto u) {
         x += (2.0 * a.two(p, u, r, t) - a.two(p, u, t, r)) * b.two(t, q, u, s)
            - a.two(p, u, r, t) * b.two(t, q, s, u);
       });
     if (occ(p) && !occ(r))
-      pair1(false, true, [&](int t, int u) {
+      pair1(false, true, [&](auto t, auto u) {
         x += (b.two(p, u, t, r) - 2.0 * b.two(p, u, r, t)) * a.two(t, q, u, s)
            + b.two(p, u, r, t) * a.two(t, q, s, u);
       });
@@ -723,38 +733,111 @@ struct CommE {
   }
   QF_HD double xb(int p, int q, int r, int s) const {
     double x = 0.0;
-    if (!occ(p) && occ(s)) pair1(false, true, [&](int t, int u) { x += a.two(q, u, t, r) * b.two(t, p, s, u); });
-    if (occ(q) && !occ(r)) pair1(false, true, [&](int t, int u) { x -= b.two(q, u, t, r) * a.two(t, p, s, u); });
+    if (!occ(p) && occ(s)) pair1(false, true, [&](auto t, auto u) { x += a.two(q, u, t, r) * b.two(t, p, s, u); });
+    if (occ(q) && !occ(r)) pair1(false, true, [&](auto t, auto u) { x -= b.two(q, u, t, r) * a.two(t, p, s, u); });
     return x;
   }
   QF_HD double xc(int p, int q, int r, int s) const {
     double x = 0.0;
-    if (!occ(q) && occ(r)) pair1(false, true, [&](int t, int u) { x += a.two(p, u, t, s) * b.two(t, q, r, u); });
-    if (occ(p) && !occ(s)) pair1(false, true, [&](int t, int u) { x -= b.two(p, u, t, s) * a.two(t, q, r, u); });
+    if (!occ(q) && occ(r)) pair1(false, true, [&](auto t, auto u) { x += a.two(p, u, t, s) * b.two(t, q, r, u); });
+    if (occ(p) && !occ(s)) pair1(false, true, [&](auto t, auto u) { x -= b.two(p, u, t, s) * a.two(t, q, r, u); });
     return x;
+  }
+
+  // ----- lane-split enumerations (the one- and zero-body elements) -----
+  QF_HD int ext_count(bool occupied) const {
+    if constexpr (kMarked) return A.na;
+    else return A.next(occupied);
+  }
+  template <class F>
+  QF_HD void ext_call(bool occupied, int k, F fn) const {
+    if constexpr (kMarked) fn(Mk{k});
+    else fn(A.extv(occupied, k));
+  }
+  // The index tuples over the blocks b[0..N) with exactly one external
+  // index, as one flat range: segment s holds the tuples whose external is
+  // in position s.  Lane ln takes the flat indices ln, ln + nl, ...; g gets
+  // the segment and the tuple (the external's number in position s, active
+  // positions elsewhere).
+  template <int N, class G>
+  QF_HD void s_flat(const bool (&b)[N], G g) const {
+    int base = 0;
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+      int dim[N], size = 1;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        dim[i] = i == s ? ext_count(b[i]) : A.nact(b[i]);
+        size *= dim[i];
+      }
+      const int j0 = (((ln - base) % nl) + nl) % nl;
+#pragma unroll 1
+      for (int j = j0; j < size; j += nl) {
+        int id[N], r = j;
+#pragma unroll
+        for (int i = N - 1; i >= 0; --i) {
+          id[i] = r % dim[i];
+          r /= dim[i];
+        }
+        g(s, id);
+      }
+      base += size;
+    }
+  }
+  // fn(t, u): exactly one of t (block bt), u (block bu) external
+  template <class F>
+  QF_HD void s_pair1(bool bt, bool bu, F fn) const {
+    const bool b[2] = {bt, bu};
+    s_flat<2>(b, [&](int s, const int* id) {
+      if (s == 0) ext_call(bt, id[0], [&](auto x) { fn(x, act_at(bu, id[1])); });
+      else ext_call(bu, id[1], [&](auto x) { fn(act_at(bt, id[0]), x); });
+    });
+  }
+  // fn(t, u, w): exactly one external
+  template <class F>
+  QF_HD void s_triple1(bool bt, bool bu, bool bw, F fn) const {
+    const bool b[3] = {bt, bu, bw};
+    s_flat<3>(b, [&](int s, const int* id) {
+      if (s == 0) {
+        ext_call(bt, id[0], [&](auto x) { fn(x, act_at(bu, id[1]), act_at(bw, id[2])); });
+      } else if (s == 1) {
+        ext_call(bu, id[1], [&](auto x) { fn(act_at(bt, id[0]), x, act_at(bw, id[2])); });
+      } else {
+        ext_call(bw, id[2], [&](auto x) { fn(act_at(bt, id[0]), act_at(bu, id[1]), x); });
+      }
+    });
+  }
+  template <class F>
+  QF_HD void s_ext(bool occupied, F fn) const {
+#pragma unroll 1
+    for (int k = ln; k < ext_count(occupied); k += nl) ext_call(occupied, k, fn);
   }
 
   QF_HD double c1(int p, int q) const {
     double res = 0.0;
     const bool op = occ(p), oq = occ(q);
-    over_ext(!oq, [&](int t) { res += a.one(p, t) * b.one(t, q); });
-    over_ext(!op, [&](int t) { res -= b.one(p, t) * a.one(t, q); });
+    s_ext(!oq, [&](auto t) { res += a.one(p, t) * b.one(t, q); });
+    s_ext(!op, [&](auto t) { res -= b.one(p, t) * a.one(t, q); });
     if (!op && oq)
-      pair1(true, false, [&](int t, int u) { res += a.one(t, u) * (2.0 * b.two(u, p, t, q) - b.two(u, p, q, t)); });
+      s_pair1(true, false, [&](auto t, auto u) {
+        res += a.one(t, u) * (2.0 * b.two(u, p, t, q) - b.two(u, p, q, t));
+      });
     if (op && !oq)
-      pair1(false, true, [&](int t, int u) { res -= a.one(t, u) * (2.0 * b.two(u, p, t, q) - b.two(u, p, q, t)); });
-    pair1(true, false, [&](int t, int u) {
+      s_pair1(false, true, [&](auto t, auto u) {
+        res -= a.one(t, u) * (2.0 * b.two(u, p, t, q) - b.two(u, p, q, t));
+      });
+    s_pair1(true, false, [&](auto t, auto u) {
       res -= b.one(t, u) * (2.0 * a.two(u, p, t, q) - a.two(u, p, q, t));
       res += b.one(u, t) * (2.0 * a.two(t, p, u, q) - a.two(t, p, q, u));
     });
     // (t,u occupied, w virtual) and (t,u virtual, w occupied), one external
     if (!oq || !op)
-      triple1(true, true, false, [&](int t, int u, int w) {
+      s_triple1(true, true, false, [&](auto t, auto u, auto w) {
         if (!oq) res += a.two(w, p, t, u) * (2.0 * b.two(t, u, w, q) - b.two(t, u, q, w));
         if (!op) res -= b.two(w, p, t, u) * (2.0 * a.two(t, u, w, q) - a.two(t, u, q, w));
       });
     if (oq || op)
-      triple1(false, false, true, [&](int t, int u, int w) {
+      s_triple1(false, false, true, [&](auto t, auto u, auto w) {
         if (oq) res += a.two(w, p, t, u) * (2.0 * b.two(t, u, w, q) - b.two(t, u, q, w));
         if (op) res -= b.two(w, p, t, u) * (2.0 * a.two(t, u, w, q) - a.two(t, u, q, w));
       });
@@ -763,27 +846,23 @@ struct CommE {
 
   QF_HD double c0() const {
     double z = 0.0;
-    pair1(true, false, [&](int t, int u) {
+    s_pair1(true, false, [&](auto t, auto u) {
       z += 2.0 * (a.one(t, u) * b.one(u, t) - a.one(u, t) * b.one(t, u));
     });
     // (t,u occupied; w,x virtual) with exactly one external among the four
-    auto term = [&](int t, int u, int w, int x) {
+    auto term = [&](auto t, auto u, auto w, auto x) {
       z += a.two(t, u, w, x) * (2.0 * b.two(w, x, t, u) - b.two(w, x, u, t))
          - b.two(t, u, w, x) * (2.0 * a.two(w, x, t, u) - a.two(w, x, u, t));
     };
-    triple1(true, true, false, [&](int t, int u, int w) {
-#pragma unroll 1
-      for (int m = 0; m < A.nact(false); ++m) term(t, u, w, act_at(false, m));
+    const bool blk[4] = {true, true, false, false};
+    s_flat<4>(blk, [&](int s, const int* id) {
+      // position s holds the external's number, not an active position
+      auto at = [&](int i) { return act_at(i < 2, id[i]); };
+      if (s == 0) ext_call(true, id[0], [&](auto e) { term(e, at(1), at(2), at(3)); });
+      else if (s == 1) ext_call(true, id[1], [&](auto e) { term(at(0), e, at(2), at(3)); });
+      else if (s == 2) ext_call(false, id[2], [&](auto e) { term(at(0), at(1), e, at(3)); });
+      else ext_call(false, id[3], [&](auto e) { term(at(0), at(1), at(2), e); });
     });
-#pragma unroll 1
-    for (int i = 0; i < A.nact(true); ++i)
-#pragma unroll 1
-      for (int j = 0; j < A.nact(true); ++j)
-#pragma unroll 1
-        for (int k = 0; k < A.nact(false); ++k)
-          over_ext(false, [&](int x) {
-            term(act_at(true, i), act_at(true, j), act_at(false, k), x);
-          });
     return z;
   }
 };
@@ -825,44 +904,32 @@ struct MarkedShape {
 template <int NA>
 struct MarkedE {
   MarkTables T;
-  QF_HD int loc(int p) const { return p; }   // indices are local in marked mode
-  QF_HD double one(int p, int q) const {
-    constexpr int na = NA;
-    if (p < 0) return T.tau1[(-1 - p) * na + loc(q)];
-    return -T.tau1[loc(p) * na + (-1 - q)];
+  static constexpr int na = NA;
+  QF_HD double one(Mk p, int q) const { return T.tau1[p.t * na + q]; }
+  QF_HD double one(int p, Mk q) const { return -T.tau1[p * na + q.t]; }
+  QF_HD double t2(int a, int b, int c, int d) const {
+    return T.tau2[((a * na + b) * na + c) * na + d];
   }
-  QF_HD double two(int p, int q, int r, int s) const {
-    constexpr int na = NA;
-    int i0, i1, i2, i3;
-    double sg = 1.0;
-    if (p < 0) { i0 = -1 - p; i1 = loc(q); i2 = loc(r); i3 = loc(s); }
-    else if (q < 0) { i0 = loc(p); i1 = -1 - q; i2 = loc(r); i3 = loc(s); }
-    else if (r < 0) { i0 = loc(p); i1 = loc(q); i2 = -1 - r; i3 = loc(s); sg = -1.0; }
-    else { i0 = loc(p); i1 = loc(q); i2 = loc(r); i3 = -1 - s; sg = -1.0; }
-    return sg * T.tau2[((i0 * na + i1) * na + i2) * na + i3];
-  }
+  QF_HD double two(Mk p, int q, int r, int s) const { return t2(p.t, q, r, s); }
+  QF_HD double two(int p, Mk q, int r, int s) const { return t2(p, q.t, r, s); }
+  QF_HD double two(int p, int q, Mk r, int s) const { return -t2(p, q, r.t, s); }
+  QF_HD double two(int p, int q, int r, Mk s) const { return -t2(p, q, r, s.t); }
 };
 
 template <int NA>
 struct MarkedSigma {
   MarkTables T;
-  QF_HD int loc(int p) const { return p; }   // indices are local in marked mode
-  QF_HD double one(int p, int q) const {
-    constexpr int na = NA;
-    if (p < 0) return T.D1[(0 * na + (-1 - p)) * na + loc(q)];
-    return T.D1[(1 * na + (-1 - q)) * na + loc(p)];
+  static constexpr int na = NA, n3 = NA * NA * NA;
+  QF_HD double one(Mk p, int q) const { return T.D1[(0 * na + p.t) * na + q]; }
+  QF_HD double one(int p, Mk q) const { return T.D1[(1 * na + q.t) * na + p]; }
+  QF_HD double d(int j, int t, int a, int b, int c) const {
+    return T.D2[(j * na + t) * n3 + (a * na + b) * na + c];
   }
-  QF_HD double two(int p, int q, int r, int s) const {
-    constexpr int na = NA, n3 = na * na * na;
-    int j, t, a, b, c;
-    // D_2(t;a,b,c) = -D_0(t;c,a,b) and D_3(t;a,b,c) = -D_1(t;c,a,b)
-    double sg = 1.0;
-    if (p < 0) { j = 0; t = -1 - p; a = loc(q); b = loc(r); c = loc(s); }
-    else if (q < 0) { j = 1; t = -1 - q; a = loc(p); b = loc(r); c = loc(s); }
-    else if (r < 0) { j = 0; t = -1 - r; a = loc(s); b = loc(p); c = loc(q); sg = -1.0; }
-    else { j = 1; t = -1 - s; a = loc(r); b = loc(p); c = loc(q); sg = -1.0; }
-    return sg * T.D2[(j * na + t) * n3 + (a * na + b) * na + c];
-  }
+  // D_2(t;a,b,c) = -D_0(t;c,a,b) and D_3(t;a,b,c) = -D_1(t;c,a,b)
+  QF_HD double two(Mk p, int q, int r, int s) const { return d(0, p.t, q, r, s); }
+  QF_HD double two(int p, Mk q, int r, int s) const { return d(1, q.t, p, r, s); }
+  QF_HD double two(int p, int q, Mk r, int s) const { return -d(0, r.t, s, p, q); }
+  QF_HD double two(int p, int q, int r, Mk s) const { return -d(1, s.t, r, p, q); }
 };
 
 // Fill the tables of one space; element e of the concatenated
