@@ -206,11 +206,24 @@ int qflow_flow_sweep_windowed(qflow_ctx* ctx, int32_t K, const qflow_space* spac
  * events on the context's stream), in the order: [F,sigma] intermediate,
  * ladder contraction of H_N, ladder contraction of [F,sigma], ring operand
  * packing, ring contractions (four matrix-core GEMMs), one-body ring terms,
- * sigma1 applied to the two-body parts, residual, build_heff, solve, update,
+ * sigma1 applied to the two-body parts (the residual's pieces), residual,
+ * build_heff (with the dense Z when that form is taken), solve, update,
  * then the whole step.  A step run with QFLOW_GRAPH reports -1 for the
  * stages and only the whole.  n is the capacity of ms (host).  Returns the
  * count written (at most 12). */
 int qflow_last_timings(const qflow_ctx* ctx, float* ms, int n);
+
+/* How the downfolded Hamiltonians get the terms where sigma's one-body part
+ * meets a two-body operator, Z = sigma1 X over the first index with
+ * X = H_N + Yg/2 (the [X_2, sigma_1] part of the commutators of Eq. (6)):
+ *   QFLOW_Z_AUTO   per call, the form that moves fewer bytes (default);
+ *   QFLOW_Z_SPACE  per space, from the rows of H_N and Yg the space touches;
+ *   QFLOW_Z_DENSE  one dense Z per build (n^4 doubles of device memory,
+ *                  allocated by this call or the next one given spaces).
+ * The forms agree to rounding.  Another mode is QFLOW_E_INVALID_ARG; a flow
+ * step captured as a graph is captured again after a change. */
+typedef enum { QFLOW_Z_AUTO = 0, QFLOW_Z_SPACE = 1, QFLOW_Z_DENSE = 2 } qflow_z_mode;
+int qflow_set_z_mode(qflow_ctx* ctx, int mode);
 
 /* Algorithm 1 (coverage-driven active-space sampling), host only.
  * Draws (Otilde, Vtilde) of sizes (no, nv) from {0..No-1} and

@@ -19,6 +19,7 @@ FP64, FP32, BF16X3 = 0, 1, 2
 UNOWNED_FROZEN = 1 << 4
 GRAPH = 1 << 5
 DIIS = 1 << 6
+Z_AUTO, Z_SPACE, Z_DENSE = 0, 1, 2   # qflow_z_mode
 
 SPACE_DTYPE = np.dtype([("n_o", "<i4"), ("n_v", "<i4"), ("orb", "<i4", (8,))])
 
@@ -64,6 +65,7 @@ def lib() -> ctypes.CDLL:
             "qflow_flow_sweep_windowed": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, i32, vp,
                                                          vp, i32]),
             "qflow_last_timings": (ctypes.c_int, [vp, vp, ctypes.c_int]),
+            "qflow_set_z_mode": (ctypes.c_int, [vp, ctypes.c_int]),
             "qflow_sample_spaces": (ctypes.c_int, [i32, i32, i32, i32, vp, vp, i64, i32, vp, vp,
                                                    i32, vp, vp]),
             "qflow_build_owners": (ctypes.c_int, [i32, i32, i32, vp, vp, vp]),
@@ -203,6 +205,11 @@ class Context:
             self.h, len(sp), _ptr(sp), _ptr(owner1), _ptr(owner2), _ptr(t1), _ptr(t2),
             _ptr(energy), int(window), ctypes.byref(em), ctypes.byref(md), flags))
         return em.value, md.value
+
+    def set_z_mode(self, mode):
+        """How build_heff forms the sigma1 x two-body terms: Z_AUTO, Z_SPACE
+        or Z_DENSE (module constants)."""
+        self._check(lib().qflow_set_z_mode(self.h, int(mode)))
 
     STAGES = ("yg", "ladder_h", "ladder_yg", "ring_pack", "ring_gemm", "ring_j", "sigma1_x",
               "residual", "heff", "solve", "update", "total")

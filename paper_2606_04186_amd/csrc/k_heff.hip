@@ -187,7 +187,8 @@ __global__ __launch_bounds__(BLK, (PART < 2 && BLK == 256) ? 7 : 1) void k_heff_
       if (ds[i] >= 0) slot[ds[i]] = init ? x : slot[ds[i]] + scale * x;
   };
   if constexpr (PART == 0) {
-    const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.z_h, g.u_h, g.lo_h};
+    DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.u_h, g.lo_h};
+    H.Z = g.zc;   // Z of H_N + Yg/2 (dense mode; else k_heff_z adds this part)
     const auto cs = make_comm(H, s, n, o);
     const auto ct = make_comm(XA, tauA, na, sp.nocc);
     double x;
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(BLK, (PART < 2 && BLK == 256) ? 7 : 1) void k_heff_
       x = scal[3] + scal[0] - ct.c0();
     emit(x, 1.0, true);
   } else if constexpr (PART == 1) {
-    const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, nullptr, g.lo_y,
+    const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, nullptr, g.lo_y,
                    Sigma2Lazy{g.y1, g.t2, g.s2p, g.s2q, n, o}};
     const auto cs = make_comm(Y, s, n, o);
     const auto ct = make_comm(XA, tauA, na, sp.nocc);
@@ -221,6 +222,80 @@ __global__ __launch_bounds__(BLK, (PART < 2 && BLK == 256) ? 7 : 1) void k_heff_
     const MarkedShape<NA> shape;
     const CommE<MarkedE<NA>, MarkedSigma<NA>, true, MarkedShape<NA>> ce{E, D, shape, n, o};
     emit(ce.c2(la, lb, lc, ld), -0.5, false);   // (local indices)
+  }
+}
+
+// The sigma1 x two-body part of [H_N, sigma] + [Yg, sigma]/2 on the space's
+// two-body block: with X = H_N + Yg/2 (two-body parts, Hermitian and pair
+// symmetric, so X(t,q,r,s) = X[s][r][q][t]),
+//   Z[a][(b,c,d)] = sum_t sigma1(p_a, t) X[p_d][p_c][p_b][t]      (all t)
+//   heff2[a][b][c][d] -= Z[a][bcd] + Z[b][adc] + Z[c][dab] + Z[d][cba].
+// The contraction runs on the matrix cores (v_mfma_f64_16x16x4f64): rows
+// (b,c,d) of X gathered 16 at a time, the space's sigma1 rows as the other
+// operand (columns a, padded to 16); each wavefront takes row tiles in turn.
+// Dynamic LDS: sigma1 rows [NA][np] (np = n rounded up to 4) and Z [NA][NA^3].
+template <int NA>
+__global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
+                                                const double* __restrict__ Xy,
+                                                const double* __restrict__ t1,
+                                                const SpaceDev* __restrict__ spaces,
+                                                const int32_t* __restrict__ idx,
+                                                const int64_t* __restrict__ heff_off, int n,
+                                                int o, double* heff) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int N2 = NA * NA, N3 = N2 * NA, NT = (N3 + 15) / 16;
+  extern __shared__ double zl[];
+  const int np = (n + 3) & ~3, v = n - o;
+  double* S = zl;             // [NA][np]
+  double* Z = zl + NA * np;   // [NA][N3]
+  __shared__ int orb[NA];
+  const int k = idx[blockIdx.x];
+  if (threadIdx.x < NA) orb[threadIdx.x] = spaces[k].orb[threadIdx.x];
+  __syncthreads();
+  for (int e = threadIdx.x; e < NA * np; e += blockDim.x) {
+    const int a = e / np, t = e % np, p = orb[a];
+    double s = 0.0;   // sigma1(p,t)
+    if (t < n) {
+      if (p < o && t >= o) s = -t1[p * v + (t - o)];
+      if (p >= o && t < o) s = t1[t * v + (p - o)];
+    }
+    S[e] = s;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int col = lane % 16, kq = lane / 16;   // operand column (a) and k slot
+  for (int tile = wave; tile < NT; tile += (int)blockDim.x / 64) {
+    const int row = tile * 16 + col;   // this lane's A row (b,c,d)
+    const bool live = row < N3;
+    size_t off = 0;
+    if (live) {
+      const int b = row / N2, c = row / NA % NA, d = row % NA;
+      off = (((size_t)orb[d] * n + orb[c]) * n + orb[b]) * n;
+    }
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int t0 = 0; t0 < np; t0 += 4) {
+      const int t = t0 + kq;
+      const double sb = col < NA ? S[col * np + t] : 0.0;
+      const bool in = live && t < n;
+      const double ah = in ? Xh[off + t] : 0.0;
+      const double ay = in ? Xy[off + t] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ah, sb, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, 0.5 * sb, acc, 0, 0, 0);
+    }
+    // lane holds D[row kq + 4r][column col]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int orow = tile * 16 + kq + 4 * r;
+      if (orow < N3 && col < NA) Z[col * N3 + orow] = acc[r];
+    }
+  }
+  __syncthreads();
+  double* slot = heff + heff_off[k] + 1 + N2;
+  for (int e = threadIdx.x; e < N2 * N2; e += blockDim.x) {
+    const int a = e / N3, b = e / N2 % NA, c = e / NA % NA, d = e % NA;
+    slot[e] -= Z[a * N3 + (b * NA + c) * NA + d] + Z[b * N3 + (a * NA + d) * NA + c] +
+               Z[c * N3 + (d * NA + a) * NA + b] + Z[d * N3 + (c * NA + b) * NA + a];
   }
 }
 
@@ -341,11 +416,12 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
                  int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
                  const int32_t* task_table, int task_stride, const int* task_slots,
                  const int32_t* cls_idx, const int* cls_off, int K, int na_max,
-                 double* tab, double* heff, hipStream_t st) {
+                 double* tab, const double* zc, double* heff, hipStream_t st) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
-              rings.z_h,  rings.z_y, rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
+              rings.zv,   rings.zo,  rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
               rings.lo_h, rings.lo_y, rings.pf};
+  g.zc = zc;
   const int tab_stride = heff_table_stride(na_max);
   k_heff_tab<<<K, kBlock, 0, st>>>(g, spaces, cls_idx, tab, tab_stride);
   // parts 0, 1, 2 per size class: its task count and LDS.  The (4,4) class
@@ -405,13 +481,17 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
     int s1, s2, s3, s4;
     const size_t lds = (size_t)mark_sizes(na, &s1, &s2, &s3, &s4) * sizeof(double);
     const int32_t* idx = cls_idx + cls_off[c];
+    const size_t zlds = (size_t)(na * ((n + 3) & ~3) + na * na * na * na) * sizeof(double);
     if (c == 0) {
       k_heff_low<4><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
+      if (!zc) k_heff_z<4><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
     } else if (c == 1) {
       k_heff_low<6><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
+      if (!zc) k_heff_z<6><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
     } else {
       allow_lds(&k_heff_low<8>, lds);
       k_heff_low<8><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
+      if (!zc) k_heff_z<8><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
     }
   }
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;

@@ -607,10 +607,11 @@ __global__ void k_pack_ring_T_bf16(const double* __restrict__ t2, int o, int v, 
   }
 }
 
-// Z(p,q,r,s) = sum_t sigma1(p,t) X(t,q,r,s): the one-body part of sigma
-// (t1) applied to the first index of a two-body operator.  With X Hermitian
-// and pair symmetric and sigma1 anti-Hermitian, the four terms of
-// [X, sigma1]_2 are -(Z_pqrs + Z_qpsr + Z_rspq + Z_srqp).
+// Z(p,q,r,s) = sum_t sigma1(p,t) X(t,q,r,s) with X = Xh + Xy/2 (the two-body
+// parts of H_N and Yg): the one-body part of sigma (t1) applied to the first
+// index.  With X Hermitian and pair symmetric and sigma1 anti-Hermitian, the
+// four terms of [X, sigma1]_2 are -(Z_pqrs + Z_qpsr + Z_rspq + Z_srqp).  The
+// dense form, for calls whose spaces would gather more of X than n^4.
 // sigma1(a,i) = t1[i][a], sigma1(i,a) = -t1[i][a].  One thread per column
 // c = (q,r,s); t1 is staged in LDS (o*v doubles) and read by broadcast.
 constexpr int kZChunk = 16;
@@ -618,9 +619,10 @@ constexpr int kZChunk = 16;
 // W adjacent columns per thread (W = 2: 16-byte loads and stores; the host
 // picks W = 2 when n^3 is even).
 template <int W>
-__global__ __launch_bounds__(256) void k_sigma1_x(const double* __restrict__ X,
+__global__ __launch_bounds__(256) void k_sigma1_x(const double* __restrict__ Xh,
+                                                  const double* __restrict__ Xy,
                                                   const double* __restrict__ t1, int n, int o,
-                                                  int skip_vvv, double* Z) {
+                                                  double* Z) {
   typedef double vw __attribute__((ext_vector_type(W)));
   extern __shared__ double ts[];   // t1, o*v
   const int v = n - o;
@@ -629,21 +631,16 @@ __global__ __launch_bounds__(256) void k_sigma1_x(const double* __restrict__ X,
   const size_t n3 = (size_t)n * n * n;
   const size_t c = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * W;
   if (c >= n3) return;
-  auto ld = [&](int t) { return *reinterpret_cast<const vw*>(X + (size_t)t * n3 + c); };
+  auto ld = [&](int t) {
+    return *reinterpret_cast<const vw*>(Xh + (size_t)t * n3 + c) +
+           0.5 * *reinterpret_cast<const vw*>(Xy + (size_t)t * n3 + c);
+  };
   // (plain stores: Z's lines that stay in the last-level cache serve the
   // lookups of the per-space kernels that follow)
   auto st = [&](int p, vw x) { *reinterpret_cast<vw*>(Z + (size_t)p * n3 + c) = x; };
   // p occupied: Z[p][c] = -sum_{t virtual} t1[p][t-o] X[t][c]; the column of
-  // X is read eight rows at a time to keep several loads in flight.  With
-  // skip_vvv, X vanishes on all-virtual index quadruples (two-body part of
-  // [F, sigma]), so Z[p occ][c] is structurally zero for all-virtual columns
-  // c = (q,r,s) and stays as zeroed at allocation.
-  const size_t n2c = (size_t)n * n;
-  const auto all_vir = [&](size_t cc) {
-    return (int)(cc / n2c) >= o && (int)(cc / n % n) >= o && (int)(cc % n) >= o;
-  };
-  const bool skip = skip_vvv && all_vir(c) && all_vir(c + W - 1);
-  for (int p0 = 0; p0 < (skip ? 0 : o); p0 += kZChunk) {
+  // X is read eight rows at a time to keep several loads in flight.
+  for (int p0 = 0; p0 < o; p0 += kZChunk) {
     vw acc[kZChunk];
 #pragma unroll
     for (int i = 0; i < kZChunk; ++i) acc[i] = vw(0.0);
@@ -834,16 +831,16 @@ void launch_pack_ring_T(const double* t2, int o, int v, float* Ta, float* T22, h
   k_pack_ring_T<<<grid_for(ov * ov, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, Ta, T22);
 }
 
-void launch_sigma1_x(const double* X, const double* t1, int n, int o, bool skip_vvv, double* Z,
-                     hipStream_t st) {
+void launch_sigma1_x(const double* Xh, const double* Xy, const double* t1, int n, int o,
+                     double* Z, hipStream_t st) {
   const size_t n3 = (size_t)n * n * n;
   const size_t lds = (size_t)o * (n - o) * sizeof(double);
   if (n3 % 2 == 0)
-    k_sigma1_x<2><<<(unsigned)((n3 / 2 + kBlock - 1) / kBlock), kBlock, lds, st>>>(
-        X, t1, n, o, skip_vvv ? 1 : 0, Z);
+    k_sigma1_x<2><<<(unsigned)((n3 / 2 + kBlock - 1) / kBlock), kBlock, lds, st>>>(Xh, Xy, t1,
+                                                                                   n, o, Z);
   else
-    k_sigma1_x<1><<<(unsigned)((n3 + kBlock - 1) / kBlock), kBlock, lds, st>>>(
-        X, t1, n, o, skip_vvv ? 1 : 0, Z);
+    k_sigma1_x<1><<<(unsigned)((n3 + kBlock - 1) / kBlock), kBlock, lds, st>>>(Xh, Xy, t1, n, o,
+                                                                               Z);
 }
 
 void launch_pack_t2_vvoo(const double* t2, int o, int v, double* T, hipStream_t st) {

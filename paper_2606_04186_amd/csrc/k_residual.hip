@@ -19,8 +19,8 @@ namespace {
 __global__ void k_residual2(GlobalOps g, double* r2) {
   const int n = g.n, o = g.o, v = n - o;
   const Sigma s{g.t1, g.t2, n, o, v};
-  const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.z_h, g.u_h, g.lo_h};
-  const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, nullptr, g.lo_y,
+  const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.u_h, g.lo_h};
+  const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, nullptr, g.lo_y,
                    Sigma2Lazy{g.y1, g.t2, g.s2p, g.s2q, n, o}};
   const auto cH = make_comm(H, s, n, o);
   const auto cY = make_comm(Y, s, n, o);
@@ -30,8 +30,69 @@ __global__ void k_residual2(GlobalOps g, double* r2) {
     const int b = (int)(idx % v), a = (int)(idx / v % v), j = (int)(idx / v / v % o),
               i = (int)(idx / v / v / o);
     const int pa = o + a, pb = o + b;
-    r2[idx] = H.two(pa, pb, i, j) + cH.c2(pa, pb, i, j) + 0.5 * cY.c2(pa, pb, i, j);
+    // the sigma1 x two-body part of both commutators, -(Z_abij + Z_baji +
+    // Z_ijab + Z_jiba) of H_N + Yg/2, from the pieces of k_zv and k_zo
+    const double w = g.zv[(((size_t)a * v + b) * o + i) * o + j] +
+                     g.zv[(((size_t)b * v + a) * o + j) * o + i] +
+                     g.zo[(((size_t)i * o + j) * v + a) * v + b] +
+                     g.zo[(((size_t)j * o + i) * v + b) * v + a];
+    r2[idx] = H.two(pa, pb, i, j) + cH.c2(pa, pb, i, j) + 0.5 * cY.c2(pa, pb, i, j) - w;
   }
+}
+
+// Z = sigma1 X over the first index, X = H_N + Yg/2 (two-body parts; both
+// Hermitian and pair symmetric), on the two orbital classes the residual
+// needs (a, b virtual; i, j occupied; sigma1(a,k) = t1[k][a],
+// sigma1(i,c) = -t1[i][c]):
+//   zv[a][b][i][j] = Z_abij =  sum_{k occ} t1[k][a] X[k][b][i][j]
+//   zo[i][j][a][b] = Z_ijab = -sum_{c vir} t1[i][c] X[c][j][a][b]
+// One thread per element of zv (j fastest; the o v o o block of X is small
+// and stays in cache).
+__global__ void k_zv(const double* __restrict__ Xh, const double* __restrict__ Xy,
+                     const double* __restrict__ t1, int n, int o, double* zv) {
+  const int v = n - o;
+  const size_t tot = (size_t)v * v * o * o;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e % o), i = (int)(e / o % o), b = (int)(e / o / o % v),
+              a = (int)(e / o / o / v);
+    double z = 0.0;
+    for (int k = 0; k < o; ++k) {
+      const size_t x = (((size_t)k * n + o + b) * n + i) * n + j;
+      z += t1[k * v + a] * (Xh[x] + 0.5 * Xy[x]);
+    }
+    zv[e] = z;
+  }
+}
+
+// zo: workgroup (j, a), one thread per b; the rows X[c][j][a][*] are read
+// coalesced and t1 is staged in LDS (o*v doubles).
+__global__ __launch_bounds__(128) void k_zo(const double* __restrict__ Xh,
+                                            const double* __restrict__ Xy,
+                                            const double* __restrict__ t1, int n, int o,
+                                            double* zo) {
+  extern __shared__ double ts[];
+  const int v = n - o;
+  for (int e = threadIdx.x; e < o * v; e += blockDim.x) ts[e] = t1[e];
+  __syncthreads();
+  const int j = blockIdx.x / v, a = blockIdx.x % v;
+  constexpr int kChunk = 16;   // occupied i per pass over the rows
+  for (int b = threadIdx.x; b < v; b += blockDim.x)
+    for (int i0 = 0; i0 < o; i0 += kChunk) {
+      double acc[kChunk];
+#pragma unroll
+      for (int i = 0; i < kChunk; ++i) acc[i] = 0.0;
+      for (int c = 0; c < v; ++c) {
+        const size_t x = (((size_t)(o + c) * n + j) * n + o + a) * n + o + b;
+        const double xv = Xh[x] + 0.5 * Xy[x];
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i)
+          if (i0 + i < o) acc[i] -= ts[(i0 + i) * v + c] * xv;
+      }
+#pragma unroll
+      for (int i = 0; i < kChunk; ++i)
+        if (i0 + i < o) zo[(((size_t)(i0 + i) * o + j) * v + a) * v + b] = acc[i];
+    }
 }
 
 // one-body parts of [H_N, sigma] and [Yg, sigma] for all (p,q): one wavefront
@@ -45,12 +106,12 @@ __global__ __launch_bounds__(256) void k_comm1(GlobalOps g, double* c1h, double*
   const Sigma s{g.t1, g.t2, n, o, v};
   double x;
   if (which == 0) {
-    const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.z_h, g.u_h, g.lo_h};
+    const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.u_h, g.lo_h};
     auto c = make_comm_split(H, s, n, o, lane, 64);
     c.ring1 = false;
     x = c.c1(e / n, e % n);
   } else {
-    const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, nullptr, g.lo_y,
+    const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, nullptr, g.lo_y,
                    Sigma2Lazy{g.y1, g.t2, g.s2p, g.s2q, n, o}};
     auto c = make_comm_split(Y, s, n, o, lane, 64);
     c.ring1 = false;
@@ -118,8 +179,8 @@ __global__ __launch_bounds__(64) void k_residual0(GlobalOps g, double* scal, dou
   const int n = g.n, o = g.o, v = n - o;
   const int lane = threadIdx.x;
   const Sigma s{g.t1, g.t2, n, o, v};
-  const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.z_h, g.u_h, g.lo_h};
-  const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, g.z_y, nullptr, g.lo_y,
+  const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.u_h, g.lo_h};
+  const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, nullptr, g.lo_y,
                    Sigma2Lazy{g.y1, g.t2, g.s2p, g.s2q, n, o}};
   const double zh = wave_sum(make_comm_split(H, s, n, o, lane, 64).c0());
   const double zy = wave_sum(make_comm_split(Y, s, n, o, lane, 64).c0());
@@ -132,13 +193,20 @@ __global__ __launch_bounds__(64) void k_residual0(GlobalOps g, double* scal, dou
 
 }  // namespace
 
+void launch_z_vvoo(const double* Xh, const double* Xy, const double* t1, int n, int o, double* zv,
+                   double* zo, hipStream_t st) {
+  const size_t v = n - o;
+  k_zv<<<grid_for(v * v * o * o, kBlock, 65536), kBlock, 0, st>>>(Xh, Xy, t1, n, o, zv);
+  k_zo<<<(unsigned)(o * v), 128, (size_t)o * v * sizeof(double), st>>>(Xh, Xy, t1, n, o, zo);
+}
+
 void launch_residual(const double* f, const double* V, const double* y1, const double* y2,
                      const double* L, const double* LY, const RingOps& rings, const double* t1,
                      const double* t2, int n, int o, double* scal, double* c1h, double* c1y,
                      double* part, double* r1, double* r2, double* e0, hipStream_t st) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
-              rings.z_h,  rings.z_y, rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
+              rings.zv,   rings.zo,  rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
               rings.lo_h, rings.lo_y, rings.pf};
   const size_t v = n - o;
   k_comm1<<<grid_for((size_t)2 * n * n * 64), kBlock, 0, st>>>(g, c1h, c1y);

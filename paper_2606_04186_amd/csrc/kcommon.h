@@ -39,12 +39,13 @@ struct GlobalOps {
   const double *f, *V, *y1, *y2, *L, *LY, *t1, *t2;
   int n, o;
   const double *ga_h, *g22_h, *j1_h, *j2_h, *ga_y, *g22_y, *j1_y, *j2_y;
-  const double *z_h, *z_y;
+  const double *zv, *zo;     // [v][v][o][o], [o][o][v][v]: sigma1 x two-body pieces (residual)
   const double *u_h;         // [x1, sigma_2]_2 of H_N (= two-body of Yg), dense
   const double *s2p, *s2q;   // compact parts of [y1, sigma_2]_2 (Sigma2Lazy)
   const double *c1_h, *c1_y; // [n][n] one-body parts of [H_N, sigma] and [Yg, sigma]
   const double *lo_h, *lo_y; // [v*v][o*o] occupied-occupied ladders
   const double *pf;          // compact parts P1..P4 of [F, sigma_2] (launch_sigma2)
+  const double* zc = nullptr;   // dense sigma1 (H_N + Yg/2) (heff), or NULL
 };
 
 }  // namespace qf

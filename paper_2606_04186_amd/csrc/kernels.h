@@ -49,11 +49,14 @@ void launch_pack_ring_A_bf16(const double* X, int n, int o, __bf16* Ah, __bf16* 
                              __bf16* A22l, hipStream_t st);
 void launch_pack_ring_T_bf16(const double* t2, int o, int v, __bf16* Th, __bf16* Tl, __bf16* T22h,
                              __bf16* T22l, hipStream_t st);
-// Z = sigma1 X over the first index (k_prep.hip, k_sigma1_x); n^4 doubles.
-// skip_vvv: X vanishes on all-virtual quadruples and Z was zeroed once, so the
-// structurally zero part of Z is not rewritten.
-void launch_sigma1_x(const double* X, const double* t1, int n, int o, bool skip_vvv, double* Z,
-                     hipStream_t st);
+// The sigma1 x two-body pieces of H_N + Yg/2 that the residual needs
+// (k_residual.hip, k_zv / k_zo): zv [v][v][o][o], zo [o][o][v][v].
+// Dense Z = sigma1 (Xh + Xy/2) over the first index, n^4 doubles (k_prep.hip,
+// k_sigma1_x).
+void launch_sigma1_x(const double* Xh, const double* Xy, const double* t1, int n, int o,
+                     double* Z, hipStream_t st);
+void launch_z_vvoo(const double* Xh, const double* Xy, const double* t1, int n, int o, double* zv,
+                   double* zo, hipStream_t st);
 // operands of the occupied-occupied ladder Lo (k_prep.hip)
 void launch_pack_t2_vvoo(const double* t2, int o, int v, double* T, hipStream_t st);
 void launch_pack_x_oooo(const double* X, int n, int o, double* Xo, hipStream_t st);
@@ -86,7 +89,7 @@ void launch_split_bf16(const double* src, int rows, int K, int Kp, __bf16* hi, _
 // residual of Hbar(sigma)
 struct RingOps {            // global intermediates of H_N and of Yg
   const double *ga_h, *g22_h, *j1_h, *j2_h, *ga_y, *g22_y, *j1_y, *j2_y;
-  const double *z_h, *z_y;
+  const double *zv, *zo;     // [v][v][o][o], [o][o][v][v]: sigma1 x two-body pieces (residual)
   const double *u_h;         // [x1, sigma_2]_2 of H_N (= two-body of Yg), dense
   const double *s2p, *s2q;   // compact parts of [y1, sigma_2]_2 (Sigma2Lazy)
   const double *c1_h, *c1_y; // [n][n] one-body parts of [H_N, sigma] and [Yg, sigma]
@@ -105,14 +108,16 @@ void launch_residual(const double* f, const double* V, const double* y1, const d
 // per-space downfolded Hamiltonians in CAS form
 // The per-element kernels run one launch per size class (cls_idx / cls_off
 // as for launch_davidson; task_slots[c] = task count of class c); K = the
-// number of spaces in the lists (cls_off[3]).
+// number of spaces in the lists (cls_off[3]).  zc: the dense
+// Z = sigma1 (H_N + Yg/2) (launch_sigma1_x), read by the element kernels; when
+// NULL, k_heff_z adds that part per space from the rows of H_N and Yg.
 void launch_heff(const double* f, const double* V, const double* y1, const double* y2,
                  const double* L, const double* LY, const RingOps& rings, const double* t1,
                  const double* t2, int n,
                  int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
                  const int32_t* task_table, int task_stride, const int* task_slots,
                  const int32_t* cls_idx, const int* cls_off, int K, int na_max,
-                 double* tab, double* heff, hipStream_t st);
+                 double* tab, const double* zc, double* heff, hipStream_t st);
 // doubles of per-space scratch tables for spaces of up to na_max orbitals
 int heff_table_stride(int na_max);
 // doubles of dynamic LDS the build of a space of na orbitals takes

@@ -60,7 +60,9 @@ struct qflow_ctx {
   DevBuf ja_h, ja_y, jb;
   DevBuf gpart;   // split-K slices of the matrix-core contractions
   // Z = sigma1 X (first index) of H_N and Yg, n^4 each
-  DevBuf z_h, z_y;
+  DevBuf zv, zo;   // sigma1 x two-body pieces of the residual
+  DevBuf zc;       // dense sigma1 (H_N + Yg/2), n^4, when some call takes that form
+  int z_mode = QFLOW_Z_AUTO;
   DevBuf dtpart;   // per-block maxima of |t_new - t_old|
   // [G, sigma_2]_2 scratch (packed one-body, transposed t2, GEMM outputs)
   // and U_Y = [y1, sigma_2]_2
@@ -178,7 +180,36 @@ bool same_spaces(const qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
 }
 
 // Upload the space list (and its derived offsets) when it changed.
+// The sigma1 x two-body part of the space Hamiltonians, for the spaces of
+// the class lists cls_off: dense (form Z = sigma1 (H_N + Yg/2) once: read
+// both operators, write Z, 3 n^4 doubles) when that moves fewer doubles than
+// the per-space gathers (both operators, na^3 rows of n per space), unless
+// the mode says otherwise.
+bool z_dense_for(const qflow_ctx* ctx, const int* cls_off) {
+  if (ctx->z_mode != QFLOW_Z_AUTO) return ctx->z_mode == QFLOW_Z_DENSE;
+  double rows = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double na = 2 * (c + 2);
+    rows += (double)(cls_off[c + 1] - cls_off[c]) * na * na * na;
+  }
+  const double n = ctx->n;
+  return 2.0 * rows * n > 3.0 * n * n * n * n;
+}
+
+int ensure_zc(qflow_ctx* ctx) {
+  if (!ctx->loaded || !z_dense_for(ctx, ctx->cls_off)) return QFLOW_OK;
+  const size_t n = ctx->n;
+  return ensure(ctx, ctx->zc, sizeof(double) * n * n * n * n);
+}
+
+int upload_space_list(qflow_ctx* ctx, int32_t K, const qflow_space* spaces);
+
 int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
+  QF_TRY(upload_space_list(ctx, K, spaces));
+  return ensure_zc(ctx);   // outside any graph capture
+}
+
+int upload_space_list(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   if (same_spaces(ctx, K, spaces) && ctx->spaces.p) return QFLOW_OK;
   std::vector<SpaceDev> dev(std::max(K, 1));
   ctx->h_heff_off.assign(K + 1, 0);
@@ -267,7 +298,7 @@ qf::RingOps rings_of(qflow_ctx* ctx) {
   return qf::RingOps{P<double>(ctx->ga_h), P<double>(ctx->g22_h), P<double>(ctx->jh),
                      P<double>(ctx->jh) + nv,  P<double>(ctx->ga_y), P<double>(ctx->g22_y),
                      P<double>(ctx->jy),       P<double>(ctx->jy) + nv,
-                     P<double>(ctx->z_h),      P<double>(ctx->z_y),
+                     P<double>(ctx->zv),       P<double>(ctx->zo),
                      P<double>(ctx->y2),       P<double>(ctx->sp),       P<double>(ctx->sq),
                      P<double>(ctx->c1h),      P<double>(ctx->c1y),
                      P<double>(ctx->lo_h),     P<double>(ctx->lo_y),
@@ -486,9 +517,10 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   qf::launch_gemm_nt_f64(P<double>(ctx->lo_t), P<double>(ctx->lo_xy), P<double>(ctx->lo_y), v * v,
                          o * o, o * o, 1.0, part, pcap, st);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[6], ctx->stream));
-  // Z = sigma1 X of H_N and Yg
-  qf::launch_sigma1_x(P<double>(ctx->V), t1, n, o, false, P<double>(ctx->z_h), st);
-  qf::launch_sigma1_x(P<double>(ctx->y2), t1, n, o, true, P<double>(ctx->z_y), st);
+  // sigma1 x two-body pieces of H_N + Yg/2 for the residual (the per-space
+  // Hamiltonians evaluate theirs in k_heff_z)
+  qf::launch_z_vvoo(P<double>(ctx->V), P<double>(ctx->y2), t1, n, o, P<double>(ctx->zv),
+                    P<double>(ctx->zo), st);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -555,7 +587,7 @@ int qflow_destroy(qflow_ctx* ctx) {
   DevBuf* bufs[] = {&ctx->ra_h,   &ctx->r22_h,    &ctx->ra_y,   &ctx->r22_y,    &ctx->rta,
                     &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
                     &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
-                    &ctx->gpart,  &ctx->z_h,      &ctx->z_y,      &ctx->dtpart,
+                    &ctx->gpart,  &ctx->zv,       &ctx->zo,      &ctx->zc,     &ctx->dtpart,
                     &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->sq,       &ctx->sp_f,
                     &ctx->c1h,
                     &ctx->c1y,    &ctx->lo_t,     &ctx->lo_xh,  &ctx->lo_xy,    &ctx->lo_h,
@@ -644,15 +676,14 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->gpart,
                 sizeof(double) * std::max({8 * n2 * o * o, (size_t)qf::kMaxSplits * n * v,
                                            2 * (size_t)((v + 7) / 8) * n2})));
-  QF_TRY(ensure(ctx, ctx->z_h, sizeof(double) * n4));
-  QF_TRY(ensure(ctx, ctx->z_y, sizeof(double) * n4));
-  // Yg's two-body part, its ladder rows, LY and Z of Yg vanish on fixed
+  QF_TRY(ensure(ctx, ctx->zv, sizeof(double) * o * o * v * v));
+  QF_TRY(ensure(ctx, ctx->zo, sizeof(double) * o * o * v * v));
+  // Yg's two-body part, its ladder rows and LY vanish on fixed
   // orbital-class patterns for every sigma; the kernels never write those
   // entries, so they are zeroed here once
   qf::launch_fill(P<double>(ctx->y2), n4, 0.0, ctx->stream);
   qf::launch_fill(P<double>(ctx->wy), n2p * v * v, 0.0, ctx->stream);
   qf::launch_fill(P<double>(ctx->LY), n2p * o * o, 0.0, ctx->stream);
-  qf::launch_fill(P<double>(ctx->z_y), n4, 0.0, ctx->stream);
   QF_TRY(ensure(ctx, ctx->dtpart, sizeof(double) * qf::kFinishParts));
   QF_TRY(ensure(ctx, ctx->a12, sizeof(double) * (2 * n * v + n * o)));
   QF_TRY(ensure(ctx, ctx->t2T, sizeof(double) * 3 * o * o * v * v));
@@ -777,12 +808,19 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
                       P<double>(ctx->c1y), P<double>(ctx->gpart), P<double>(ctx->r1),
                       P<double>(ctx->r2), nullptr, ctx->stream);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[8], ctx->stream));
+  const size_t n = ctx->n;
+  const bool dense = K > 0 && z_dense_for(ctx, cls_off) &&
+                     ctx->zc.bytes >= sizeof(double) * n * n * n * n;
+  if (dense)
+    qf::launch_sigma1_x(P<double>(ctx->V), P<double>(ctx->y2), t1, ctx->n, ctx->o,
+                        P<double>(ctx->zc), ctx->stream);
   if (K > 0)
     qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1), P<double>(ctx->y2),
                     P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx), t1, t2, ctx->n, ctx->o,
                     P<double>(ctx->scal), P<SpaceDev>(ctx->spaces), heff_off_dev,
                     P<int32_t>(ctx->tasks), qf::kTaskStride, ctx->task_slots,
-                    idx, cls_off, K, ctx->na_max, P<double>(ctx->mtab), heff, ctx->stream);
+                    idx, cls_off, K, ctx->na_max, P<double>(ctx->mtab),
+                    dense ? P<double>(ctx->zc) : nullptr, heff, ctx->stream);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -1094,6 +1132,16 @@ int qflow_flow_sweep_windowed(qflow_ctx* ctx, int32_t K, const qflow_space* spac
   *e_mean = out[0];
   *max_dt = out[1];
   return QFLOW_OK;
+}
+
+int qflow_set_z_mode(qflow_ctx* ctx, int mode) {
+  if (!ctx) return QFLOW_E_INVALID_ARG;
+  if (mode != QFLOW_Z_AUTO && mode != QFLOW_Z_SPACE && mode != QFLOW_Z_DENSE)
+    return fail(ctx, QFLOW_E_INVALID_ARG, "unknown Z mode");
+  QF_HIP(hipSetDevice(ctx->device));
+  ctx->z_mode = mode;
+  ++ctx->epoch;   // a captured step follows the mode
+  return ensure_zc(ctx);
 }
 
 int qflow_last_timings(const qflow_ctx* ctx, float* ms, int n) {

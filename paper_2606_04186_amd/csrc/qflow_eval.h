@@ -183,10 +183,12 @@ struct DenseOp {
   const double* G22 = nullptr;   // [n*n][v*o]
   const double* J1 = nullptr;    // [n][v]
   const double* J2 = nullptr;    // [n][v]
-  const double* Z = nullptr;     // [n][n][n][n], sum_t sigma1(p,t) x2(t,q,r,s)
   const double* U = nullptr;     // [n][n][n][n], [x1, sigma_2]_2; when NULL, Ul is used
   const double* Lo = nullptr;    // [v*v][o*o], sum_{tu occ} t2[t,u,a,b] x2(t,u,i,j)
   Sigma2Lazy Ul{};
+  // [n][n][n][n], sum_t sigma1(p,t) x2(t,q,r,s); NULL when the caller adds
+  // this part itself
+  const double* Z = nullptr;
   QF_HD double one(int p, int q) const { return x1[p * n + q]; }
   QF_HD double two(int p, int q, int r, int s) const {
     return x2[(((size_t)p * n + q) * n + r) * n + s];
@@ -393,9 +395,11 @@ struct Comm {
     // one-body B x two-body A:
     //   - sum_t [B_pt A_tqrs + B_qt A_ptrs - B_tr A_pqts - B_ts A_pqrt]
     // = -(Z_pqrs + Z_qpsr + Z_rspq + Z_srqp) with Z = B A over the first index
-    // (A Hermitian and pair symmetric, B anti-Hermitian)
+    // (A Hermitian and pair symmetric, B anti-Hermitian).  A dense operator
+    // either carries Z or leaves this part to the caller (per-space tables,
+    // the residual's vvoo pieces).
     if constexpr (kUseL) {
-      if (lead()) res -= a.z(p, q, r, s) + a.z(q, p, s, r) + a.z(r, s, p, q) + a.z(s, r, q, p);
+      if (lead() && a.Z) res -= a.z(p, q, r, s) + a.z(q, p, s, r) + a.z(r, s, p, q) + a.z(s, r, q, p);
     } else {
       over_block(!op, [&](int t) { res -= b.one(p, t) * a.two(t, q, r, s); });
       over_block(!oq, [&](int t) { res -= b.one(q, t) * a.two(p, t, r, s); });

@@ -92,8 +92,18 @@ def _spaces_for(n, o, K, seed, eps):
     return [(s[0], s[1]) for s in S]
 
 
+ZMODES = ["auto", "space", "dense"]
+
+
+def _z_mode(ctx, zmode):
+    import paper_2606_04186_amd as qf
+    ctx.set_z_mode({"auto": qf.Z_AUTO, "space": qf.Z_SPACE, "dense": qf.Z_DENSE}[zmode])
+
+
+@pytest.mark.parametrize("zmode", ZMODES)
 @pytest.mark.parametrize("n,o,seed,K", [(8, 3, 111, 10), (24, 4, 112, 12), (40, 5, 113, 6)])
-def test_heff_matches_oracle(n, o, seed, K):
+def test_heff_matches_oracle(n, o, seed, K, zmode):
+    """Both forms of the sigma1 x two-body terms (per space, dense Z)."""
     _need_gpu()
     import paper_2606_04186_amd as qf
     h, eri = problem(n, o, seed)
@@ -105,6 +115,7 @@ def test_heff_matches_oracle(n, o, seed, K):
     off = qf.api.offsets(sp, qf.heff_size)
     heff = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
     ctx = context(h, eri, o)
+    _z_mode(ctx, zmode)
     ctx.build_heff(sp, dev(t1), dev(t2), heff, off)
     torch.cuda.synchronize()
     out = host(heff)
@@ -354,6 +365,9 @@ def test_symmetry_and_argument_errors():
         ctx.build_heff(sp, dev(np.zeros((o, 5))), dev(np.zeros((o, o, 5, 5))), heff,
                        np.array([0, 1333], dtype=np.int64))
     assert e.value.code == -8
+    with pytest.raises(qf.QFlowError) as e:
+        ctx.set_z_mode(3)
+    assert e.value.code == -1
 
 
 def test_flow_step_graph_matches_oracle():
@@ -363,8 +377,8 @@ def test_flow_step_graph_matches_oracle():
     _flow_parity(24, 4, 132, 12, 2, "mp2", flags=qf.GRAPH)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
-def test_flow_step_graph_replays_match_eager(prec):
+@pytest.mark.parametrize("prec,zmode", [("fp64", "auto"), ("bf16x3", "auto"), ("fp64", "dense")])
+def test_flow_step_graph_replays_match_eager(prec, zmode):
     """Replays of the captured step against eager steps on a second context:
     several replays with eager work and synchronisations between them, a
     re-capture after the amplitude arrays move, and one after the space list
@@ -380,6 +394,8 @@ def test_flow_step_graph_replays_match_eager(prec):
     lists_a = _spaces_for(n, o, K, seed, pb.eps)
     lists_b = _spaces_for(n, o, K, seed + 1, pb.eps)
     ce, cg = context(h, eri, o), context(h, eri, o)
+    _z_mode(ce, zmode)
+    _z_mode(cg, zmode)
     e1, e2, g1, g2 = dev(t1), dev(t2), dev(t1), dev(t2)
     ee = torch.zeros(K, dtype=torch.float64, device="cuda")
     eg = torch.zeros(K, dtype=torch.float64, device="cuda")
@@ -415,7 +431,8 @@ def _mixed_spaces(n, o, seed, eps, caps=(3, 3, 2)):
     return [(s[0], s[1]) for s in out]
 
 
-def test_heff_size_classes_match_oracle():
+@pytest.mark.parametrize("zmode", ZMODES)
+def test_heff_size_classes_match_oracle(zmode):
     """Spaces of all three size classes in one list (one launch per class)."""
     _need_gpu()
     import paper_2606_04186_amd as qf
@@ -429,6 +446,7 @@ def test_heff_size_classes_match_oracle():
     off = qf.api.offsets(sp, qf.heff_size)
     heff = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
     ctx = context(h, eri, o)
+    _z_mode(ctx, zmode)
     ctx.build_heff(sp, dev(t1), dev(t2), heff, off)
     torch.cuda.synchronize()
     out = host(heff)
@@ -443,7 +461,7 @@ def test_heff_size_classes_match_oracle():
         assert np.abs(blk[1 + na * na:].reshape(na, na, na, na) - g).max() < 1e-11, k
 
 
-@pytest.mark.parametrize("flags", ["fp64", "graph"])
+@pytest.mark.parametrize("flags", ["fp64", "graph", "dense", "graph-dense"])
 def test_flow_step_size_classes_matches_oracle(flags):
     """One macro-iteration over (2,2), (3,3) and (4,4) spaces (36, 400 and
     4900 determinants) against the oracle: energies, eigenvector-derived
@@ -459,9 +477,10 @@ def test_flow_step_size_classes_matches_oracle(flags):
     t1, t2 = qflow.mp2_guess(pb.f, eri, o)
     sp = qf.make_spaces(lists)
     ctx = context(h, eri, o)
+    _z_mode(ctx, "dense" if "dense" in flags else "space")
     g1, g2 = dev(t1), dev(t2)
     energy = torch.zeros(len(lists), dtype=torch.float64, device="cuda")
-    flag = qf.GRAPH if flags == "graph" else qf.FP64
+    flag = qf.GRAPH if flags.startswith("graph") else qf.FP64
     em, _ = ctx.flow_step(sp, dev(o1, torch.int32), dev(o2, torch.int32), g1, g2, energy, flag)
     t1n, t2n, E, Em, _s = qflow.flow_step(pb, t1, t2, lists, o1, o2)
     print("per-space |dE|", np.abs(host(energy) - E))
