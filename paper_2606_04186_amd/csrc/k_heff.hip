@@ -129,7 +129,7 @@ __global__ __launch_bounds__(BLK, (PART < 2 && BLK == 256) ? 7 : 1) void k_heff_
   __shared__ Active A;
   extern __shared__ double tl[];
   const int k = idx[blockIdx.x];
-  const SpaceDev sp = spaces[k];
+  const SpaceDev& sp = spaces[k];
   load_active(sp, g.n, g.o, A);
   MarkTables T{};
   const int na = sp.na, n = g.n, o = g.o, v = n - o;

@@ -330,7 +330,7 @@ __global__ void k_scatter_owned(const SpaceDev* __restrict__ spaces, const doubl
                                 double* t1n, double* t2n) {
   const int k = k0 + blockIdx.x;
   if (status[k] != 0) return;
-  const SpaceDev sp = spaces[k];
+  const SpaceDev& sp = spaces[k];   // (a reference: no private copy to index)
   const int ne = sp.nocc, nv = sp.na - sp.nocc, v = n - o;
   const double* x = amp + amp_off[k];
   const int nt1 = ne * nv;
