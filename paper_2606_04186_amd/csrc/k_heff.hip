@@ -189,7 +189,8 @@ __global__ __launch_bounds__(BLK, (PART < 2 && BLK == 256) ? 7 : 1) void k_heff_
   if constexpr (PART == 0) {
     DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.u_h, g.lo_h};
     H.Z = g.zc;   // Z of H_N + Yg/2 (dense mode; else k_heff_z adds this part)
-    const auto cs = make_comm(H, s, n, o);
+    auto cs = make_comm(H, s, n, o);
+    cs.pp_loops = false;   // k_heff_pp
     const auto ct = make_comm(XA, tauA, na, sp.nocc);
     double x;
     if (kind == 2)
@@ -202,7 +203,8 @@ __global__ __launch_bounds__(BLK, (PART < 2 && BLK == 256) ? 7 : 1) void k_heff_
   } else if constexpr (PART == 1) {
     const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, nullptr, g.lo_y,
                    Sigma2Lazy{g.y1, g.t2, g.s2p, g.s2q, n, o}};
-    const auto cs = make_comm(Y, s, n, o);
+    auto cs = make_comm(Y, s, n, o);
+    cs.pp_loops = false;   // k_heff_pp
     const auto ct = make_comm(XA, tauA, na, sp.nocc);
     double x;
     if (kind == 2)
@@ -296,6 +298,78 @@ __global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
     const int a = e / N3, b = e / N2 % NA, c = e / NA % NA, d = e % NA;
     slot[e] -= Z[a * N3 + (b * NA + c) * NA + d] + Z[b * N3 + (a * NA + d) * NA + c] +
                Z[c * N3 + (d * NA + a) * NA + b] + Z[d * N3 + (c * NA + b) * NA + a];
+  }
+}
+
+// The occupied-pair ladders of [H_N, sigma] + [Yg, sigma]/2 that have no
+// global precomputed form, on the space's two-body block: with X = H_N + Yg/2,
+//   M[(p,q)][(r,s)] = sum_{t,u occupied} X(p,q,t,u) t2[t,u,r,s]   (r,s virtual)
+// (orbital indices of the space, all t,u), the element (p,q,r,s) gains
+//   M[(p,q)][(r,s)]  when r,s are virtual and p,q not both occupied, and
+//   M[(r,s)][(p,q)]  when p,q are virtual and r,s not both occupied
+// (the second by X(t,u,r,s) = X(r,s,t,u)); the assignment is the same on every
+// member of an element's symmetry orbit.  The (t,u) pairs are staged in
+// chunks: X rows [NA^2][chunk] and t2 [chunk][NV^2] in LDS, one thread per M
+// entry.
+template <int NA>
+__global__ __launch_bounds__(256) void k_heff_pp(const double* __restrict__ Xh,
+                                                 const double* __restrict__ Xy,
+                                                 const double* __restrict__ t2,
+                                                 const SpaceDev* __restrict__ spaces,
+                                                 const int32_t* __restrict__ idx,
+                                                 const int64_t* __restrict__ heff_off, int n,
+                                                 int o, double* heff) {
+  constexpr int NO = NA / 2, NV = NA - NO, N2 = NA * NA, NR = NV * NV, NM = N2 * NR;
+  constexpr int kChunk = 64, kPer = (NM + 255) / 256;
+  __shared__ double xs[N2 * kChunk];   // X(p,q,t,u), [pq][tu - c0]
+  __shared__ double ts[kChunk * NR];   // t2[t,u,r,s], [tu - c0][rs]
+  __shared__ double M[NM];
+  __shared__ int orb[NA];
+  const int k = idx[blockIdx.x];
+  if (threadIdx.x < NA) orb[threadIdx.x] = spaces[k].orb[threadIdx.x];
+  __syncthreads();
+  const int v = n - o, oo = o * o;
+  double acc[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) acc[j] = 0.0;
+  for (int c0 = 0; c0 < oo; c0 += kChunk) {
+    const int cn = min(kChunk, oo - c0);
+    for (int e = threadIdx.x; e < N2 * cn; e += blockDim.x) {
+      const int pq = e / cn, tu = c0 + e % cn;
+      const size_t x = (((size_t)orb[pq / NA] * n + orb[pq % NA]) * n + tu / o) * n + tu % o;
+      xs[pq * kChunk + e % cn] = Xh[x] + 0.5 * Xy[x];
+    }
+    for (int e = threadIdx.x; e < cn * NR; e += blockDim.x) {
+      const int tu = c0 + e / NR, rs = e % NR;
+      const int r = orb[NO + rs / NV] - o, s = orb[NO + rs % NV] - o;
+      ts[e] = t2[((size_t)tu * v + r) * v + s];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int m = threadIdx.x + 256 * j;
+      if (m < NM) {
+        const int pq = m / NR, rs = m % NR;
+        double a = acc[j];
+        for (int i = 0; i < cn; ++i) a += xs[pq * kChunk + i] * ts[i * NR + rs];
+        acc[j] = a;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < kPer; ++j)
+    if (threadIdx.x + 256 * j < NM) M[threadIdx.x + 256 * j] = acc[j];
+  __syncthreads();
+  double* slot = heff + heff_off[k] + 1 + N2;
+  for (int e = threadIdx.x; e < N2 * N2; e += blockDim.x) {
+    const int a = e / (N2 * NA), b = e / N2 % NA, c = e / NA % NA, d = e % NA;
+    double x = 0.0;
+    if (c >= NO && d >= NO && !(a < NO && b < NO))
+      x += M[(a * NA + b) * NR + (c - NO) * NV + (d - NO)];
+    if (a >= NO && b >= NO && !(c < NO && d < NO))
+      x += M[(c * NA + d) * NR + (a - NO) * NV + (b - NO)];
+    slot[e] += x;
   }
 }
 
@@ -485,13 +559,16 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
     if (c == 0) {
       k_heff_low<4><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
       if (!zc) k_heff_z<4><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
+      k_heff_pp<4><<<count, 256, 0, st>>>(V, y2, t2, spaces, idx, heff_off, n, o, heff);
     } else if (c == 1) {
       k_heff_low<6><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
       if (!zc) k_heff_z<6><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
+      k_heff_pp<6><<<count, 256, 0, st>>>(V, y2, t2, spaces, idx, heff_off, n, o, heff);
     } else {
       allow_lds(&k_heff_low<8>, lds);
       k_heff_low<8><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
       if (!zc) k_heff_z<8><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
+      k_heff_pp<8><<<count, 256, 0, st>>>(V, y2, t2, spaces, idx, heff_off, n, o, heff);
     }
   }
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;

@@ -317,6 +317,11 @@ struct Comm {
   // false: leave out the sigma1 x A_2 part of the one-body element (the
   // caller evaluates it for all (p,q) at once)
   bool ring1 = true;
+  // false (dense A): leave out the occupied-pair ladders of the two-body
+  // element that have no precomputed form, sum_{t,u occ} A_pqtu t2[t,u,r,s]
+  // (r,s virtual, p,q not both occupied) and its mirror (p,q virtual, r,s
+  // not both occupied); the caller adds them (per-space tables)
+  bool pp_loops = true;
 
   QF_HD bool occ(int p) const { return p < o; }
   QF_HD bool lead() const { return ln == 0; }
@@ -418,7 +423,7 @@ struct Comm {
           done = true;
         }
       }
-      if (!done)
+      if (!done && (!kUseL || pp_loops))
         over_pair(true, true, [&](int t, int u) { res -= a.two(p, q, t, u) * b.two(t, u, r, s); });
     }
     if (!op && !oq) {
@@ -429,7 +434,7 @@ struct Comm {
           done = true;
         }
       }
-      if (!done)
+      if (!done && (!kUseL || pp_loops))
         over_pair(true, true, [&](int t, int u) { res += b.two(p, q, t, u) * a.two(t, u, r, s); });
     }
     if (op && oq) res -= ladder_vv_rev(p, q, r, s);
