@@ -29,64 +29,69 @@ __device__ double block_sum(double x, double* red) {
   return s;
 }
 
+// Orders the LDS accesses of one wavefront (the lanes exchange values through
+// LDS between the steps of a rotation).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Lowest eigenpair of the symmetric m x m matrix A (LDS, row-major,
-// destroyed) by cyclic Jacobi rotations: thread k < m applies each rotation
-// to row/column k; every thread of the block passes the barriers.  V (LDS,
-// m x m) receives the eigenvectors; every thread gets theta, y[0..m) (LDS)
-// the eigenvector.  flag: one double of LDS scratch.
-template <int BLK>
+// destroyed; m <= 64) by cyclic Jacobi rotations, run by wavefront 0 alone:
+// lane k applies each rotation to row/column k, and the lanes exchange values
+// through LDS within the one wavefront, so no rotation waits at a workgroup
+// barrier.  V (LDS, m x m) receives the eigenvectors; every thread gets theta
+// and y[0..m) (LDS) the eigenvector.  flag: one double of LDS.
 __device__ void jacobi_lowest(double* A, double* V, int m, double* theta, double* y,
                               double* flag) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < m * m; e += BLK) V[e] = (e / m == e % m) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    if (tid < 64) {
+  const int k = threadIdx.x;
+  if (k < 64) {
+    for (int e = k; e < m * m; e += 64) V[e] = (e / m == e % m) ? 1.0 : 0.0;
+    wave_lds_sync();
+    for (int sweep = 0; sweep < 60; ++sweep) {
       double off = 0.0, dia = 0.0;
-      for (int e = tid; e < m * m; e += 64) {
+      for (int e = k; e < m * m; e += 64) {
         const int i = e / m, j = e % m;
         if (i == j) dia += A[e] * A[e];
         else if (j > i) off += A[e] * A[e];
       }
       off = wave_sum(off);
       dia = wave_sum(dia);
-      if (tid == 0) flag[0] = (off <= 1e-32 * (dia + 1e-300)) ? 1.0 : 0.0;
+      if (off <= 1e-32 * (dia + 1e-300)) break;   // the same on every lane
+      for (int p = 0; p < m; ++p)
+        for (int q = p + 1; q < m; ++q) {
+          const double apq = A[p * m + q];
+          if (apq == 0.0) continue;
+          const double th = (A[q * m + q] - A[p * m + p]) / (2.0 * apq);
+          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+          wave_lds_sync();
+          if (k < m) {
+            const double akp = A[k * m + p], akq = A[k * m + q];
+            A[k * m + p] = c * akp - s * akq;
+            A[k * m + q] = s * akp + c * akq;
+          }
+          wave_lds_sync();
+          if (k < m) {
+            const double apk = A[p * m + k], aqk = A[q * m + k];
+            A[p * m + k] = c * apk - s * aqk;
+            A[q * m + k] = s * apk + c * aqk;
+            const double vkp = V[k * m + p], vkq = V[k * m + q];
+            V[k * m + p] = c * vkp - s * vkq;
+            V[k * m + q] = s * vkp + c * vkq;
+          }
+          wave_lds_sync();
+        }
     }
-    __syncthreads();
-    const bool done = flag[0] != 0.0;
-    __syncthreads();
-    if (done) break;
-    for (int p = 0; p < m; ++p)
-      for (int q = p + 1; q < m; ++q) {
-        const double apq = A[p * m + q];
-        if (apq == 0.0) continue;
-        const double th = (A[q * m + q] - A[p * m + p]) / (2.0 * apq);
-        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        __syncthreads();
-        if (tid < m) {
-          const double akp = A[tid * m + p], akq = A[tid * m + q];
-          A[tid * m + p] = c * akp - s * akq;
-          A[tid * m + q] = s * akp + c * akq;
-        }
-        __syncthreads();
-        if (tid < m) {
-          const double apk = A[p * m + tid], aqk = A[q * m + tid];
-          A[p * m + tid] = c * apk - s * aqk;
-          A[q * m + tid] = s * apk + c * aqk;
-          const double vkp = V[tid * m + p], vkq = V[tid * m + q];
-          V[tid * m + p] = c * vkp - s * vkq;
-          V[tid * m + q] = s * vkp + c * vkq;
-        }
-        __syncthreads();
-      }
+    int best = 0;
+    for (int i = 1; i < m; ++i)
+      if (A[i * m + i] < A[best * m + best]) best = i;
+    if (k < m) y[k] = V[k * m + best];
+    if (k == 0) flag[0] = A[best * m + best];
   }
-  int best = 0;
-  for (int i = 1; i < m; ++i)
-    if (A[i * m + i] < A[best * m + best]) best = i;
-  *theta = A[best * m + best];
-  for (int i = tid; i < m; i += BLK) y[i] = V[i * m + best];
   __syncthreads();
+  *theta = flag[0];
 }
 
 constexpr int binom(int n, int k) { return k == 0 ? 1 : binom(n - 1, k - 1) * n / k; }
@@ -254,7 +259,7 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
     __syncthreads();
     for (int e = tid; e < m * m; e += kDavBlock) Aw[e] = Gm[(e / m) * MS + e % m];
     __syncthreads();
-    jacobi_lowest<kDavBlock>(Aw, Vw, m, &theta, yv, misc + 1);
+    jacobi_lowest(Aw, Vw, m, &theta, yv, misc + 1);
     double rn = 0.0;
     for (int e = tid; e < D; e += kDavBlock) {
       double x = 0.0, y = 0.0;
