@@ -71,11 +71,16 @@ __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
     if (bo == co && ao != bo) {
       const int ft = A.orb[t], pa = A.orb[a], pb = A.orb[b], pc = A.orb[c];
       if (ao) {
-        // x over the occupied externals
-        const int m = A.next(true);
-        for (int i = 0; i < m; ++i) {
-          const int x = A.extv(true, i);
-          acc += g.f[x * n + ft] * (j == 0 ? s.two(x, pa, pb, pc) : s.two(pa, x, pb, pc));
+        // x over all occupied orbitals is Q1 (slot 0) / Q2 (slot 1) of
+        // [F, sigma_2] (-sum_x f[t][x] t2[x][a][b][c] and -sum_x f[t][x]
+        // t2[a][x][b][c]; f symmetric), less the active occupied orbitals
+        const int v = n - g.o;
+        const size_t ovv = (size_t)g.o * v * v;
+        acc = g.qf[(size_t)j * n * ovv + (size_t)ft * ovv + ((size_t)pa * v + (pb - g.o)) * v +
+                   (pc - g.o)];
+        for (int i = 0; i < nocc; ++i) {
+          const int x = A.orb[i];
+          acc -= g.f[x * n + ft] * (j == 0 ? s.two(x, pa, pb, pc) : s.two(pa, x, pb, pc));
         }
       } else {
         // x over all virtuals is P3 (slot 0) / P4 (slot 1) of [F, sigma_2]
@@ -496,6 +501,7 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
               rings.zv,   rings.zo,  rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
               rings.lo_h, rings.lo_y, rings.pf};
   g.zc = zc;
+  g.qf = rings.qf;
   const int tab_stride = heff_table_stride(na_max);
   k_heff_tab<<<K, kBlock, 0, st>>>(g, spaces, cls_idx, tab, tab_stride);
   // parts 0, 1, 2 per size class: its task count and LDS.  The (4,4) class

@@ -46,6 +46,7 @@ struct GlobalOps {
   const double *lo_h, *lo_y; // [v*v][o*o] occupied-occupied ladders
   const double *pf;          // compact parts P1..P4 of [F, sigma_2] (launch_sigma2)
   const double* zc = nullptr;   // dense sigma1 (H_N + Yg/2) (heff), or NULL
+  const double* qf = nullptr;   // compact parts Q1, Q2 of [F, sigma_2] (launch_sigma2)
 };
 
 }  // namespace qf

@@ -95,6 +95,7 @@ struct RingOps {            // global intermediates of H_N and of Yg
   const double *c1_h, *c1_y; // [n][n] one-body parts of [H_N, sigma] and [Yg, sigma]
   const double *lo_h, *lo_y; // [v*v][o*o] occupied-occupied ladders
   const double *pf;          // compact parts P1..P4 of [F, sigma_2] (launch_sigma2)
+  const double *qf;          // compact parts Q1, Q2 of [F, sigma_2] (launch_sigma2)
 };
 // One-body parts of [H_N, sigma] and [Yg, sigma] for every (p,q) into
 // c1h, c1y ([n][n] each; the buffers RingOps.c1_h / c1_y point to), then the

@@ -66,7 +66,7 @@ struct qflow_ctx {
   DevBuf dtpart;   // per-block maxima of |t_new - t_old|
   // [G, sigma_2]_2 scratch (packed one-body, transposed t2, GEMM outputs)
   // and U_Y = [y1, sigma_2]_2
-  DevBuf a12, t2T, sp, sq, sp_f;   // sp_f keeps the [F, sigma_2] parts
+  DevBuf a12, t2T, sp, sq, sp_f, sq_f;   // sp_f, sq_f keep the [F, sigma_2] parts
   DevBuf c1h, c1y;   // one-body parts of [H_N, sigma] and [Yg, sigma], [n][n]
   // FP32 operands of the mixed-precision ladder and ring products
   DevBuf w32, wy32, t2_32, ra32_h, r22_32_h, ra32_y, r22_32_y, rta32, rt22_32;
@@ -302,7 +302,7 @@ qf::RingOps rings_of(qflow_ctx* ctx) {
                      P<double>(ctx->y2),       P<double>(ctx->sp),       P<double>(ctx->sq),
                      P<double>(ctx->c1h),      P<double>(ctx->c1y),
                      P<double>(ctx->lo_h),     P<double>(ctx->lo_y),
-                     P<double>(ctx->sp_f)};
+                     P<double>(ctx->sp_f),     P<double>(ctx->sq_f)};
 }
 
 // BF16x3 operands: a [rows][K] FP64 matrix becomes hi and lo bf16 halves of
@@ -403,7 +403,7 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
     wyb_rows = Split{wyb.hi, wyb.hi + (size_t)npo * kp};
   }
   qf::launch_sigma2(P<double>(ctx->f), t2, n, o, P<double>(ctx->a12), P<double>(ctx->t2T), true,
-                    P<double>(ctx->sp_f), P<double>(ctx->sq), part, pcap, P<double>(ctx->y2),
+                    P<double>(ctx->sp_f), P<double>(ctx->sq_f), part, pcap, P<double>(ctx->y2),
                     (mixed || bf3) ? nullptr : P<double>(ctx->wy),
                     mixed ? P<float>(ctx->wy32) : nullptr, wyb_rows.hi, wyb_rows.lo, st);
   qf::launch_sigma2(P<double>(ctx->y1), t2, n, o, P<double>(ctx->a12), P<double>(ctx->t2T),
@@ -588,7 +588,7 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
                     &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
                     &ctx->gpart,  &ctx->zv,       &ctx->zo,      &ctx->zc,     &ctx->dtpart,
-                    &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->sq,       &ctx->sp_f,
+                    &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->sq,       &ctx->sp_f,     &ctx->sq_f,
                     &ctx->c1h,
                     &ctx->c1y,    &ctx->lo_t,     &ctx->lo_xh,  &ctx->lo_xy,    &ctx->lo_h,
                     &ctx->lo_y,   &ctx->w32,      &ctx->wy32,   &ctx->t2_32,    &ctx->ra32_h,
@@ -690,6 +690,7 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->sp, sizeof(double) * 4 * n * o * o * v));
   QF_TRY(ensure(ctx, ctx->sq, sizeof(double) * 2 * n * o * v * v));
   QF_TRY(ensure(ctx, ctx->sp_f, sizeof(double) * 4 * n * o * o * v));
+  QF_TRY(ensure(ctx, ctx->sq_f, sizeof(double) * 2 * n * o * v * v));
   QF_TRY(ensure(ctx, ctx->c1h, sizeof(double) * n2));
   QF_TRY(ensure(ctx, ctx->c1y, sizeof(double) * n2));
   QF_TRY(ensure(ctx, ctx->lo_t, sizeof(double) * o * o * v * v));
