@@ -240,8 +240,11 @@ __global__ __launch_bounds__(BLK, (PART < 2 && BLK == 256) ? 7 : 1) void k_heff_
 // The contraction runs on the matrix cores (v_mfma_f64_16x16x4f64): rows
 // (b,c,d) of X gathered 16 at a time, the space's sigma1 rows as the other
 // operand (columns a, padded to 16); each wavefront takes row tiles in turn.
-// Dynamic LDS: sigma1 rows [NA][np] (np = n rounded up to 4) and Z [NA][NA^3].
-template <int NA>
+// A lane loads W consecutive t of its row at once (W = 2 when n is even:
+// 16-byte loads) and feeds them to W MFMAs, whose k slots then hold
+// t = t0 + W*kq + w; the sigma1 operand follows the same order.
+// Dynamic LDS: sigma1 rows [NA][np] (np = n rounded up to 4W) and Z [NA][NA^3].
+template <int NA, int W>
 __global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
                                                 const double* __restrict__ Xy,
                                                 const double* __restrict__ t1,
@@ -250,9 +253,10 @@ __global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
                                                 const int64_t* __restrict__ heff_off, int n,
                                                 int o, double* heff) {
   typedef double d4 __attribute__((ext_vector_type(4)));
+  typedef double dw __attribute__((ext_vector_type(W)));
   constexpr int N2 = NA * NA, N3 = N2 * NA, NT = (N3 + 15) / 16;
   extern __shared__ double zl[];
-  const int np = (n + 3) & ~3, v = n - o;
+  const int np = (n + 4 * W - 1) / (4 * W) * (4 * W), v = n - o;
   double* S = zl;             // [NA][np]
   double* Z = zl + NA * np;   // [NA][N3]
   __shared__ int orb[NA];
@@ -281,14 +285,22 @@ __global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
     }
     d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
-    for (int t0 = 0; t0 < np; t0 += 4) {
-      const int t = t0 + kq;
-      const double sb = col < NA ? S[col * np + t] : 0.0;
+    for (int t0 = 0; t0 < np; t0 += 4 * W) {
+      const int t = t0 + W * kq;   // this lane's W consecutive t (all < n or all >= n)
       const bool in = live && t < n;
-      const double ah = in ? Xh[off + t] : 0.0;
-      const double ay = in ? Xy[off + t] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ah, sb, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, 0.5 * sb, acc, 0, 0, 0);
+      dw ah, ay;
+#pragma unroll
+      for (int w = 0; w < W; ++w) ah[w] = ay[w] = 0.0;
+      if (in) {
+        ah = *reinterpret_cast<const dw*>(Xh + off + t);
+        ay = *reinterpret_cast<const dw*>(Xy + off + t);
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const double sb = col < NA ? S[col * np + t + w] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ah[w], sb, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ay[w], 0.5 * sb, acc, 0, 0, 0);
+      }
     }
     // lane holds D[row kq + 4r][column col]
 #pragma unroll
@@ -561,19 +573,25 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
     int s1, s2, s3, s4;
     const size_t lds = (size_t)mark_sizes(na, &s1, &s2, &s3, &s4) * sizeof(double);
     const int32_t* idx = cls_idx + cls_off[c];
-    const size_t zlds = (size_t)(na * ((n + 3) & ~3) + na * na * na * na) * sizeof(double);
+    // W = 2 (16-byte row loads) needs even n: rows then start 16-byte aligned
+    // and a lane's pair of t never straddles n
+    const bool w2 = n % 2 == 0;
+    const size_t zlds = (size_t)(na * ((n + 7) & ~7) + na * na * na * na) * sizeof(double);
     if (c == 0) {
       k_heff_low<4><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
-      if (!zc) k_heff_z<4><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
+      if (!zc && w2) k_heff_z<4, 2><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
+      if (!zc && !w2) k_heff_z<4, 1><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
       k_heff_pp<4><<<count, 256, 0, st>>>(V, y2, t2, spaces, idx, heff_off, n, o, heff);
     } else if (c == 1) {
       k_heff_low<6><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
-      if (!zc) k_heff_z<6><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
+      if (!zc && w2) k_heff_z<6, 2><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
+      if (!zc && !w2) k_heff_z<6, 1><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
       k_heff_pp<6><<<count, 256, 0, st>>>(V, y2, t2, spaces, idx, heff_off, n, o, heff);
     } else {
       allow_lds(&k_heff_low<8>, lds);
       k_heff_low<8><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
-      if (!zc) k_heff_z<8><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
+      if (!zc && w2) k_heff_z<8, 2><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
+      if (!zc && !w2) k_heff_z<8, 1><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
       k_heff_pp<8><<<count, 256, 0, st>>>(V, y2, t2, spaces, idx, heff_off, n, o, heff);
     }
   }

@@ -101,9 +101,11 @@ def _z_mode(ctx, zmode):
 
 
 @pytest.mark.parametrize("zmode", ZMODES)
-@pytest.mark.parametrize("n,o,seed,K", [(8, 3, 111, 10), (24, 4, 112, 12), (40, 5, 113, 6)])
+@pytest.mark.parametrize("n,o,seed,K", [(8, 3, 111, 10), (24, 4, 112, 12), (40, 5, 113, 6),
+                                         (15, 4, 114, 8)])
 def test_heff_matches_oracle(n, o, seed, K, zmode):
-    """Both forms of the sigma1 x two-body terms (per space, dense Z)."""
+    """Both forms of the sigma1 x two-body terms (per space, dense Z); an odd
+    orbital count takes the per-space kernel's one-double row loads."""
     _need_gpu()
     import paper_2606_04186_amd as qf
     h, eri = problem(n, o, seed)
