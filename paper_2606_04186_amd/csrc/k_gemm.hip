@@ -33,11 +33,22 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kBK = 16;
 constexpr int kLD = kBK + 2;
 
+// Up to kMaxBatch products of one shape in one launch: blockIdx.z = batch
+// entry * splits + K split.
+constexpr int kMaxBatch = 4;
+struct GemmBatch {
+  const double* A[kMaxBatch];
+  const double* B[kMaxBatch];
+  double* C[kMaxBatch];
+};
+
 template <int TM, int TN>
-__global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ A,
-                                                  const double* __restrict__ B,
-                                                  double* __restrict__ C, int M, int N, int K,
-                                                  int kchunk, int to_slices, double scale) {
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(GemmBatch gb, double* __restrict__ part,
+                                                  int M, int N, int K, int kchunk, int splits,
+                                                  int to_slices, double scale) {
+  const int bz = blockIdx.z / splits;
+  const double* __restrict__ A = gb.A[bz];
+  const double* __restrict__ B = gb.B[bz];
   constexpr int BM = 32 * TM, BN = 32 * TN;
   constexpr int LA = BM * kBK / 256, LB = BN * kBK / 256;
   __shared__ double As[BM * kLD];
@@ -45,7 +56,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int wm = wave / 2, wn = wave % 2;
   const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
-  const int ks = blockIdx.z * kchunk;
+  const int ks = (blockIdx.z % splits) * kchunk;
   const int ke = min(K, ks + kchunk);
   double ra[LA], rb[LB];
   auto load = [&](int k0) {
@@ -98,7 +109,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
     }
     __syncthreads();
   }
-  double* out = to_slices ? C + (size_t)blockIdx.z * M * N : C;
+  double* out = to_slices ? part + (size_t)blockIdx.z * M * N : gb.C[bz];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -377,6 +388,20 @@ __global__ __launch_bounds__(256) void k_sum_slices(const double* __restrict__ p
   C[e] = s;
 }
 
+// the same for the entries of a batch: entry b's slices at part + b*splits*count
+__global__ __launch_bounds__(256) void k_sum_slices_batch(const double* __restrict__ part,
+                                                          int splits, size_t count, GemmBatch gb,
+                                                          int nb) {
+  const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (e >= count * nb) return;
+  const int b = (int)(e / count);
+  const size_t i0 = e % count;
+  const double* src = part + (size_t)b * splits * count;
+  double s = 0.0;
+  for (int i = 0; i < splits; ++i) s += src[(size_t)i * count + i0];
+  gb.C[b][i0] = s;
+}
+
 template <int TM, int TN, class T>
 void launch_tiles(const T* A, const T* B, double* C, double* part, size_t part_cap,
                   int M, int N, int K, double scale, hipStream_t st) {
@@ -398,20 +423,58 @@ void launch_tiles(const T* A, const T* B, double* C, double* part, size_t part_c
   int kchunk = (K + splits - 1) / splits;
   kchunk = (kchunk + kBK - 1) / kBK * kBK;
   splits = (K + kchunk - 1) / kchunk;
+  GemmBatch one{};
+  if constexpr (sizeof(T) == 8) {
+    one.A[0] = A;
+    one.B[0] = B;
+    one.C[0] = C;
+  }
   if (splits <= 1) {
     dim3 grid(tiles_n, tiles_m, 1);
     if constexpr (sizeof(T) == 8)
-      k_gemm_f64<TM, TN><<<grid, 256, 0, st>>>(A, B, C, M, N, K, K > 0 ? K : kBK, 0, scale);
+      k_gemm_f64<TM, TN><<<grid, 256, 0, st>>>(one, nullptr, M, N, K, K > 0 ? K : kBK, 1, 0,
+                                               scale);
     else
       k_gemm_f32<TM, TN><<<grid, 256, 0, st>>>(A, B, C, M, N, K, K > 0 ? K : kBK, 0, scale);
     return;
   }
   dim3 grid(tiles_n, tiles_m, splits);
   if constexpr (sizeof(T) == 8)
-    k_gemm_f64<TM, TN><<<grid, 256, 0, st>>>(A, B, part, M, N, K, kchunk, 1, scale);
+    k_gemm_f64<TM, TN><<<grid, 256, 0, st>>>(one, part, M, N, K, kchunk, splits, 1, scale);
   else
     k_gemm_f32<TM, TN><<<grid, 256, 0, st>>>(A, B, part, M, N, K, kchunk, 1, scale);
   k_sum_slices<<<grid_for(mn), kBlock, 0, st>>>(part, splits, mn, C);
+}
+
+// nb <= kMaxBatch FP64 products of one shape in one launch (K split as in
+// launch_tiles, counting the workgroups of all entries)
+template <int TM, int TN>
+void launch_tiles_batch(const GemmBatch& gb, int nb, double* part, size_t part_cap, int M,
+                        int N, int K, double scale, hipStream_t st) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  const int tiles_n = (N + BN - 1) / BN, tiles_m = (M + BM - 1) / BM;
+  const long tiles = (long)tiles_n * tiles_m * nb;
+  constexpr long kTarget = 4 * 256;
+  const size_t mn = (size_t)M * N;
+  int splits = 1;
+  if (tiles < kTarget && part != nullptr) {
+    splits = (int)((kTarget + tiles - 1) / tiles);
+    splits = std::min(splits, std::max(1, K / (8 * kBK)));
+    splits = (int)std::min<size_t>((size_t)splits, part_cap / (mn * nb));
+    splits = std::min(splits, kMaxSplits);
+    splits = std::max(splits, 1);
+  }
+  int kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + kBK - 1) / kBK * kBK;
+  splits = (K + kchunk - 1) / kchunk;
+  if (splits <= 1) {
+    dim3 grid(tiles_n, tiles_m, nb);
+    k_gemm_f64<TM, TN><<<grid, 256, 0, st>>>(gb, nullptr, M, N, K, K > 0 ? K : kBK, 1, 0, scale);
+    return;
+  }
+  dim3 grid(tiles_n, tiles_m, nb * splits);
+  k_gemm_f64<TM, TN><<<grid, 256, 0, st>>>(gb, part, M, N, K, kchunk, splits, 1, scale);
+  k_sum_slices_batch<<<grid_for(mn * nb), kBlock, 0, st>>>(part, splits, mn, gb, nb);
 }
 
 template <class T>
@@ -481,6 +544,25 @@ void launch_split_bf16(const double* src, int rows, int K, int Kp, __bf16* hi, _
 void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int N, int K,
                         double scale, double* part, size_t part_cap, hipStream_t st) {
   launch_gemm(A, B, C, M, N, K, scale, part, part_cap, st);
+}
+
+int launch_gemm_nt_f64_batch(const double* const* A, const double* const* B, double* const* C,
+                             int nb, int M, int N, int K, double scale, double* part,
+                             size_t part_cap, hipStream_t st) {
+  if (nb < 1 || nb > kMaxBatch) return -1;
+  if (M <= 0 || N <= 0) return 0;
+  GemmBatch gb{};
+  for (int b = 0; b < nb; ++b) {
+    gb.A[b] = A[b];
+    gb.B[b] = B[b];
+    gb.C[b] = C[b];
+  }
+  const long pad4 = (long)((N + 127) / 128) * 128, pad3 = (long)((N + 95) / 96) * 96;
+  if (pad3 < pad4)
+    launch_tiles_batch<4, 3>(gb, nb, part, part_cap, M, N, K, scale, st);
+  else
+    launch_tiles_batch<4, 4>(gb, nb, part, part_cap, M, N, K, scale, st);
+  return 0;
 }
 
 void launch_gemm_nt_f32(const float* A, const float* B, double* C, int M, int N, int K,

@@ -776,12 +776,14 @@ void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12,
     k_pack_t2T<<<grid_for(o2v2, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, t2T);
     k_pack_t2_occ<<<grid_for(o2v2, kBlock, 65536), kBlock, 0, st>>>(t2, o, v, Tq, Tp);
   }
-  const double* Bs[4] = {t2T, t2, t2T, t2};
-  for (int i = 0; i < 4; ++i)
-    launch_gemm_nt_f64(A12 + (i < 2 ? 0 : nv), Bs[i], P + i * n * ov2, n, (int)ov2, v, 1.0, part,
-                       part_cap, st);
-  launch_gemm_nt_f64(Ao, Tq, Q, n, (int)ovv, o, -1.0, part, part_cap, st);
-  launch_gemm_nt_f64(Ao, Tp, Q + (size_t)n * ovv, n, (int)ovv, o, -1.0, part, part_cap, st);
+  const double* pa[4] = {A12, A12, A12 + nv, A12 + nv};
+  const double* pb[4] = {t2T, t2, t2T, t2};
+  double* pc[4] = {P, P + n * ov2, P + 2 * n * ov2, P + 3 * n * ov2};
+  (void)launch_gemm_nt_f64_batch(pa, pb, pc, 4, n, (int)ov2, v, 1.0, part, part_cap, st);
+  const double* qa[2] = {Ao, Ao};
+  const double* qb[2] = {Tq, Tp};
+  double* qc[2] = {Q, Q + (size_t)n * ovv};
+  (void)launch_gemm_nt_f64_batch(qa, qb, qc, 2, n, (int)ovv, o, -1.0, part, part_cap, st);
   const size_t lds = (size_t)(o * o + o * n) * sizeof(double);
   if (U) {
     if (lds > 64 * 1024)

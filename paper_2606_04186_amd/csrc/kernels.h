@@ -69,6 +69,11 @@ void launch_pack_j_B(const double* t2, int o, int v, double* B1, double* B2, hip
 // for no split) and the slices are summed in a fixed order, so the result is
 // deterministic.
 constexpr int kMaxSplits = 128;
+// nb (1..4) products C[b] = scale A[b] B[b]^T of one shape in one launch
+// (host arrays of device pointers); -1 for another nb.
+int launch_gemm_nt_f64_batch(const double* const* A, const double* const* B, double* const* C,
+                             int nb, int M, int N, int K, double scale, double* part,
+                             size_t part_cap, hipStream_t st);
 void launch_gemm_nt_f64(const double* A, const double* B, double* C, int M, int N, int K,
                         double scale, double* part, size_t part_cap, hipStream_t st);
 // The same with FP32 operands on the FP32 matrix cores: products summed in

@@ -500,22 +500,23 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   qf::launch_pack_j_B(t2, o, v, b1, b2, st);
   qf::launch_pack_j_A(P<double>(ctx->y2), n, o, P<double>(ctx->ja_y),
                       P<double>(ctx->ja_y) + (size_t)n * kj, st);
-  const struct {
-    DevBuf* a;
-    DevBuf* j;
-  } jops[2] = {{&ctx->ja_h, &ctx->jh}, {&ctx->ja_y, &ctx->jy}};
-  for (const auto& op : jops)
-    for (int which = 0; which < 2; ++which)
-      qf::launch_gemm_nt_f64(P<double>(*op.a) + which * (size_t)n * kj, which == 0 ? b1 : b2,
-                             P<double>(*op.j) + which * (size_t)n * v, n, v, (int)kj, -1.0, part,
-                             pcap, st);
+  {   // J1, J2 of H_N and of Yg: four products of one shape in one launch
+    const double* ja[4] = {P<double>(ctx->ja_h), P<double>(ctx->ja_h) + (size_t)n * kj,
+                           P<double>(ctx->ja_y), P<double>(ctx->ja_y) + (size_t)n * kj};
+    const double* jbs[4] = {b1, b2, b1, b2};
+    double* jc[4] = {P<double>(ctx->jh), P<double>(ctx->jh) + (size_t)n * v, P<double>(ctx->jy),
+                     P<double>(ctx->jy) + (size_t)n * v};
+    (void)qf::launch_gemm_nt_f64_batch(ja, jbs, jc, 4, n, v, (int)kj, -1.0, part, pcap, st);
+  }
   // occupied-occupied ladders Lo of H_N and Yg
   qf::launch_pack_t2_vvoo(t2, o, v, P<double>(ctx->lo_t), st);
   qf::launch_pack_x_oooo(P<double>(ctx->y2), n, o, P<double>(ctx->lo_xy), st);
-  qf::launch_gemm_nt_f64(P<double>(ctx->lo_t), P<double>(ctx->lo_xh), P<double>(ctx->lo_h), v * v,
-                         o * o, o * o, 1.0, part, pcap, st);
-  qf::launch_gemm_nt_f64(P<double>(ctx->lo_t), P<double>(ctx->lo_xy), P<double>(ctx->lo_y), v * v,
-                         o * o, o * o, 1.0, part, pcap, st);
+  {
+    const double* la[2] = {P<double>(ctx->lo_t), P<double>(ctx->lo_t)};
+    const double* lb[2] = {P<double>(ctx->lo_xh), P<double>(ctx->lo_xy)};
+    double* lc[2] = {P<double>(ctx->lo_h), P<double>(ctx->lo_y)};
+    (void)qf::launch_gemm_nt_f64_batch(la, lb, lc, 2, v * v, o * o, o * o, 1.0, part, pcap, st);
+  }
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[6], ctx->stream));
   // sigma1 x two-body pieces of H_N + Yg/2 for the residual (the per-space
   // Hamiltonians evaluate theirs in k_heff_z)
