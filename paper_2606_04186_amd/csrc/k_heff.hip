@@ -38,78 +38,105 @@ __device__ void load_active(const SpaceDev& sp, int n, int o, Active& A) {
   __syncthreads();
 }
 
-// Per-space tables of the marked [E,sigma] evaluation (see MarkTables and
-// mark_table_entry).  The two-body tables D_j(t;a,b,c) = sum_{x external}
-// f[x][t] sigma(.. x in slot j ..) vanish unless b and c share a class and a
-// is in the other one, and x then runs over the externals of a's class.  Only
-// D_0 and D_1 are stored: anti-Hermiticity of sigma gives the others,
-// D_2(t;a,b,c) = -D_0(t;c,a,b), D_3(t;a,b,c) = -D_1(t;c,a,b).
+// Per-space tables of the marked [E,sigma] evaluation (see MarkTables), for
+// a size class of NA orbitals (NA/2 occupied):
+//   tau1[a][b], tau2[a][b][c][d]           sigma restricted to the space;
+//   D1[j][t][a] = sum_{x external} f[x][t] sigma1(x in slot j, a in the other)
+//     = fs1[j][t][a] (the sum over every orbital, k_fs1) less the active x;
+//   D_j(t;a,b,c) = sum_{x external} f[x][t] sigma(.. x in slot j ..), j = 0, 1,
+//     which vanish unless b and c share a class and a is in the other one; x
+//     then runs over the externals of a's class: the sums over all orbitals of
+//     that class are [F, sigma_2]'s P3/P4 (a virtual) or Q1/Q2 (a occupied),
+//     less the active ones.  D_2(t;a,b,c) = -D_0(t;c,a,b) and
+//     D_3(t;a,b,c) = -D_1(t;c,a,b) by anti-Hermiticity, so they are not stored;
+// then H_N and Yg restricted to the space: [f_A | V_A | y1_A | y2_A].
+template <int NA>
 __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
                                                   const SpaceDev* __restrict__ spaces,
                                                   const int32_t* __restrict__ idx, double* tab,
                                                   int64_t tab_stride) {
-  __shared__ Active A;
-  constexpr int kNa = 8;   // largest supported space, (4,4)
+  constexpr int NO = NA / 2, N2 = NA * NA, N3 = N2 * NA, N4 = N3 * NA;
+  constexpr int S1 = N2, S2 = N4, S3 = 2 * N2, S4 = 2 * N4;
+  __shared__ int orb[NA];
   const int k = idx[blockIdx.x];
-  const SpaceDev sp = spaces[k];
-  load_active(sp, g.n, g.o, A);
-  const int n = g.n;
-  const Sigma s{g.t1, g.t2, n, g.o, n - g.o};
-  int s1, s2, s3, s4;
-  mark_sizes(sp.na, &s1, &s2, &s3, &s4);
-  const int na = sp.na, nocc = sp.nocc, n2 = na * na, n3 = n2 * na, n4 = n3 * na;
-  if (na > kNa) return;   // the host admits (2,2), (3,3) and (4,4) spaces only
+  if (threadIdx.x < NA) orb[threadIdx.x] = spaces[k].orb[threadIdx.x];
+  __syncthreads();
+  const int n = g.n, o = g.o, v = n - o;
+  const Sigma s{g.t1, g.t2, n, o, v};
   double* out = tab + (int64_t)k * tab_stride;
-  // tau1, tau2, D1
-  for (int e = threadIdx.x; e < s1 + s2 + s3; e += blockDim.x)
-    out[e] = mark_table_entry(s, g.f, A, e);
+  for (int e = threadIdx.x; e < N2; e += blockDim.x) out[e] = s.one(orb[e / NA], orb[e % NA]);
+  for (int e = threadIdx.x; e < N4; e += blockDim.x)
+    out[S1 + e] = s.two(orb[e / N3], orb[e / N2 % NA], orb[e / NA % NA], orb[e % NA]);
+  for (int e = threadIdx.x; e < 2 * N2; e += blockDim.x) {
+    const int j = e / N2, ft = orb[e / NA % NA], pa = orb[e % NA];
+    double acc = g.fs1[((size_t)j * n + ft) * n + pa];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int x = orb[i];
+      acc -= g.f[x * n + ft] * (j == 0 ? s.one(x, pa) : s.one(pa, x));
+    }
+    out[S1 + S2 + e] = acc;
+  }
   // D_0, D_1 (D_2 and D_3 are read from them with permuted indices)
-  for (int e = threadIdx.x; e < 2 * n4; e += blockDim.x) {
-    const int j = e / n4, t = e / n3 % na, a = e / n2 % na, b = e / na % na, c = e % na;
-    const bool ao = a < nocc, bo = b < nocc, co = c < nocc;
+  for (int e = threadIdx.x; e < 2 * N4; e += blockDim.x) {
+    const int j = e / N4, t = e / N3 % NA, a = e / N2 % NA, b = e / NA % NA, c = e % NA;
+    const bool ao = a < NO, bo = b < NO, co = c < NO;
     double acc = 0.0;
     if (bo == co && ao != bo) {
-      const int ft = A.orb[t], pa = A.orb[a], pb = A.orb[b], pc = A.orb[c];
+      const int ft = orb[t], pa = orb[a], pb = orb[b], pc = orb[c];
       if (ao) {
         // x over all occupied orbitals is Q1 (slot 0) / Q2 (slot 1) of
         // [F, sigma_2] (-sum_x f[t][x] t2[x][a][b][c] and -sum_x f[t][x]
         // t2[a][x][b][c]; f symmetric), less the active occupied orbitals
-        const int v = n - g.o;
-        const size_t ovv = (size_t)g.o * v * v;
-        acc = g.qf[(size_t)j * n * ovv + (size_t)ft * ovv + ((size_t)pa * v + (pb - g.o)) * v +
-                   (pc - g.o)];
-        for (int i = 0; i < nocc; ++i) {
-          const int x = A.orb[i];
+        const size_t ovv = (size_t)o * v * v;
+        acc = g.qf[(size_t)j * n * ovv + (size_t)ft * ovv + ((size_t)pa * v + (pb - o)) * v +
+                   (pc - o)];
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+          const int x = orb[i];
           acc -= g.f[x * n + ft] * (j == 0 ? s.two(x, pa, pb, pc) : s.two(pa, x, pb, pc));
         }
       } else {
         // x over all virtuals is P3 (slot 0) / P4 (slot 1) of [F, sigma_2]
         // (sum_x f[x][t] t2[b][c][x][a] and sum_x f[x][t] t2[b][c][a][x]),
         // less the active virtuals
-        const int v = n - g.o;
-        const size_t ov2 = (size_t)g.o * g.o * v, nv = (size_t)n * ov2;
-        acc = g.pf[(2 + j) * nv + (size_t)ft * ov2 + ((size_t)pb * g.o + pc) * v + (pa - g.o)];
-        for (int i = nocc; i < na; ++i) {
-          const int x = A.orb[i];
+        const size_t ov2 = (size_t)o * o * v, nv = (size_t)n * ov2;
+        acc = g.pf[(2 + j) * nv + (size_t)ft * ov2 + ((size_t)pb * o + pc) * v + (pa - o)];
+#pragma unroll
+        for (int i = NO; i < NA; ++i) {
+          const int x = orb[i];
           acc -= g.f[x * n + ft] * (j == 0 ? s.two(x, pa, pb, pc) : s.two(pa, x, pb, pc));
         }
       }
     }
-    out[s1 + s2 + s3 + e] = acc;
+    out[S1 + S2 + S3 + e] = acc;
   }
-  // H_N and Yg restricted to the space (local indices): [f_A | V_A | y1_A | y2_A]
-  double* xo = out + s1 + s2 + s3 + s4;
-  for (int e = threadIdx.x; e < n2; e += blockDim.x) {
-    const int p = A.orb[e / na], q = A.orb[e % na];
+  double* xo = out + S1 + S2 + S3 + S4;
+  for (int e = threadIdx.x; e < N2; e += blockDim.x) {
+    const int p = orb[e / NA], q = orb[e % NA];
     xo[e] = g.f[p * n + q];
-    xo[n2 + n4 + e] = g.y1[p * n + q];
+    xo[N2 + N4 + e] = g.y1[p * n + q];
   }
-  for (int e = threadIdx.x; e < n4; e += blockDim.x) {
-    const size_t idx = (((size_t)A.orb[e / n3] * n + A.orb[e / n2 % na]) * n +
-                        A.orb[e / na % na]) * n + A.orb[e % na];
-    xo[n2 + e] = g.V[idx];
-    xo[2 * n2 + n4 + e] = g.y2[idx];
+  for (int e = threadIdx.x; e < N4; e += blockDim.x) {
+    const size_t i4 =
+        (((size_t)orb[e / N3] * n + orb[e / N2 % NA]) * n + orb[e / NA % NA]) * n + orb[e % NA];
+    xo[N2 + e] = g.V[i4];
+    xo[2 * N2 + N4 + e] = g.y2[i4];
   }
+}
+
+// fs1[j][t][a] = sum_x f[x][t] sigma1(x, a) (j = 0) or sigma1(a, x) (j = 1),
+// over every orbital x: the external sums of the D1 tables before the
+// active orbitals are taken out.  One thread per entry.
+__global__ void k_fs1(const double* __restrict__ f, const double* __restrict__ t1, int n, int o,
+                      double* fs1) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 2 * n * n) return;
+  const int j = e / (n * n), t = e / n % n, a = e % n;
+  const Sigma s{t1, nullptr, n, o, n - o};
+  double acc = 0.0;
+  for (int x = 0; x < n; ++x) acc += f[x * n + t] * (j == 0 ? s.one(x, a) : s.one(a, x));
+  fs1[e] = acc;
 }
 
 // Slot layout while accumulating: [x0, x1 (na^2), x2 (na^4)].
@@ -326,8 +353,9 @@ __global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
 //   M[(r,s)][(p,q)]  when p,q are virtual and r,s not both occupied
 // (the second by X(t,u,r,s) = X(r,s,t,u)); the assignment is the same on every
 // member of an element's symmetry orbit.  The (t,u) pairs are staged in
-// chunks: X rows [NA^2][chunk] and t2 [chunk][NV^2] in LDS, one thread per M
-// entry.
+// chunks: X rows [NA^2][chunk] and t2 [chunk][NV^2] in LDS; the product runs
+// on the matrix cores (v_mfma_f64_16x16x4f64), wavefront w taking rows
+// [16w, 16w + 16) of M (NA^2 <= 64 rows, NV^2 <= 16 columns).
 template <int NA>
 __global__ __launch_bounds__(256) void k_heff_pp(const double* __restrict__ Xh,
                                                  const double* __restrict__ Xy,
@@ -336,8 +364,10 @@ __global__ __launch_bounds__(256) void k_heff_pp(const double* __restrict__ Xh,
                                                  const int32_t* __restrict__ idx,
                                                  const int64_t* __restrict__ heff_off, int n,
                                                  int o, double* heff) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
   constexpr int NO = NA / 2, NV = NA - NO, N2 = NA * NA, NR = NV * NV, NM = N2 * NR;
-  constexpr int kChunk = 64, kPer = (NM + 255) / 256;
+  constexpr int kChunk = 64, NT = (N2 + 15) / 16;
+  static_assert(NT <= 4 && NR <= 16, "one row tile per wavefront, one column tile");
   __shared__ double xs[N2 * kChunk];   // X(p,q,t,u), [pq][tu - c0]
   __shared__ double ts[kChunk * NR];   // t2[t,u,r,s], [tu - c0][rs]
   __shared__ double M[NM];
@@ -346,15 +376,20 @@ __global__ __launch_bounds__(256) void k_heff_pp(const double* __restrict__ Xh,
   if (threadIdx.x < NA) orb[threadIdx.x] = spaces[k].orb[threadIdx.x];
   __syncthreads();
   const int v = n - o, oo = o * o;
-  double acc[kPer];
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) acc[j] = 0.0;
+  const float inv_o = 1.0f / (float)o;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int row = wave * 16 + lane % 16, col = lane % 16, kq = lane / 16;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
   for (int c0 = 0; c0 < oo; c0 += kChunk) {
     const int cn = min(kChunk, oo - c0);
-    for (int e = threadIdx.x; e < N2 * cn; e += blockDim.x) {
-      const int pq = e / cn, tu = c0 + e % cn;
-      const size_t x = (((size_t)orb[pq / NA] * n + orb[pq % NA]) * n + tu / o) * n + tu % o;
-      xs[pq * kChunk + e % cn] = Xh[x] + 0.5 * Xy[x];
+    for (int e = threadIdx.x; e < N2 * kChunk; e += blockDim.x) {
+      const int pq = e / kChunk, i = e % kChunk, tu = c0 + i;
+      if (i >= cn) continue;
+      // t = tu / o in single precision: (tu + 1/2) / o is at least 1/(2o)
+      // from an integer, far beyond the rounding error for tu < 2^12
+      const int t = (int)(((float)tu + 0.5f) * inv_o), u = tu - t * o;
+      const size_t x = (((size_t)orb[pq / NA] * n + orb[pq % NA]) * n + t) * n + u;
+      xs[pq * kChunk + i] = Xh[x] + 0.5 * Xy[x];
     }
     for (int e = threadIdx.x; e < cn * NR; e += blockDim.x) {
       const int tu = c0 + e / NR, rs = e % NR;
@@ -362,21 +397,22 @@ __global__ __launch_bounds__(256) void k_heff_pp(const double* __restrict__ Xh,
       ts[e] = t2[((size_t)tu * v + r) * v + s];
     }
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      const int m = threadIdx.x + 256 * j;
-      if (m < NM) {
-        const int pq = m / NR, rs = m % NR;
-        double a = acc[j];
-        for (int i = 0; i < cn; ++i) a += xs[pq * kChunk + i] * ts[i * NR + rs];
-        acc[j] = a;
+    if (wave < NT)
+      for (int k0 = 0; k0 < cn; k0 += 4) {
+        const int k = k0 + kq;
+        const double a = (row < N2 && k < cn) ? xs[row * kChunk + k] : 0.0;
+        const double b = (col < NR && k < cn) ? ts[k * NR + col] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
       }
-    }
     __syncthreads();
   }
+  // lane holds M[row 16w + kq + 4r][column col]
+  if (wave < NT)
 #pragma unroll
-  for (int j = 0; j < kPer; ++j)
-    if (threadIdx.x + 256 * j < NM) M[threadIdx.x + 256 * j] = acc[j];
+    for (int r = 0; r < 4; ++r) {
+      const int orow = wave * 16 + kq + 4 * r;
+      if (orow < N2 && col < NR) M[orow * NR + col] = acc[r];
+    }
   __syncthreads();
   double* slot = heff + heff_off[k] + 1 + N2;
   for (int e = threadIdx.x; e < N2 * N2; e += blockDim.x) {
@@ -507,15 +543,24 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
                  int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
                  const int32_t* task_table, int task_stride, const int* task_slots,
                  const int32_t* cls_idx, const int* cls_off, int K, int na_max,
-                 double* tab, const double* zc, double* heff, hipStream_t st) {
+                 double* tab, double* fs1, const double* zc, double* heff, hipStream_t st) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
               rings.zv,   rings.zo,  rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
               rings.lo_h, rings.lo_y, rings.pf};
   g.zc = zc;
   g.qf = rings.qf;
+  g.fs1 = fs1;
   const int tab_stride = heff_table_stride(na_max);
-  k_heff_tab<<<K, kBlock, 0, st>>>(g, spaces, cls_idx, tab, tab_stride);
+  k_fs1<<<(2 * n * n + kBlock - 1) / kBlock, kBlock, 0, st>>>(f, t1, n, o, fs1);
+  for (int c = 0; c < 3; ++c) {
+    const int count = cls_off[c + 1] - cls_off[c];
+    if (count <= 0) continue;
+    const int32_t* idx = cls_idx + cls_off[c];
+    if (c == 0) k_heff_tab<4><<<count, kBlock, 0, st>>>(g, spaces, idx, tab, tab_stride);
+    if (c == 1) k_heff_tab<6><<<count, kBlock, 0, st>>>(g, spaces, idx, tab, tab_stride);
+    if (c == 2) k_heff_tab<8><<<count, kBlock, 0, st>>>(g, spaces, idx, tab, tab_stride);
+  }
   // parts 0, 1, 2 per size class: its task count and LDS.  The (4,4) class
   // (about 100 KB of staged tables) runs 1024-thread workgroups, so that its
   // tables are staged twice per space instead of five times and four times

@@ -178,6 +178,8 @@ struct LadderRows {
   }
 };
 
+constexpr int kAssembleParts = 8;
+
 template <class WT>
 __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restrict__ g,
                                                          const double* __restrict__ t2,
@@ -186,7 +188,18 @@ __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restric
                                                          int o, double* U, WT wv) {
   extern __shared__ double sg[];   // p, q virtual: tpq[o*o] | g occupied rows [o][n]
   const int v = n - o;
-  const int p = blockIdx.x / n, q = blockIdx.x % n;
+  // workgroups [0, n^2): pair (p, q), part 0; after them, parts 1 ..
+  // kAssembleParts-1 of the occupied pairs, whose rows are the longest
+  int p, q, part = 0;
+  if (blockIdx.x < (unsigned)(n * n)) {
+    p = blockIdx.x / n;
+    q = blockIdx.x % n;
+  } else {
+    const int j = blockIdx.x - n * n, pair = j / (kAssembleParts - 1);
+    p = pair / o;
+    q = pair % o;
+    part = 1 + j % (kAssembleParts - 1);
+  }
   const bool op = p < o, oq = q < o;
   const size_t ov2 = (size_t)o * o * v, nv = (size_t)n * ov2;
   const double* P1 = P;
@@ -201,7 +214,7 @@ __global__ __launch_bounds__(256) void k_sigma2_assemble(const double* __restric
   const size_t wrow = tri_row(p, q, n);
   if (op && oq) {
     const size_t pq = ((size_t)p * o + q) * v;
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    for (int e = threadIdx.x + part * blockDim.x; e < n * n; e += kAssembleParts * blockDim.x) {
       const int r = e / n, s_ = e % n;
       if (r < o && s_ < o) continue;
       double x = 0.0;
@@ -790,7 +803,8 @@ void launch_sigma2(const double* g, const double* t2, int n, int o, double* A12,
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma2_assemble<LadderRows>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const LadderRows rows{wv, wv32, wvb_hi, wvb_lo, wvb_hi ? (size_t)bf16_pad(v * v) : (size_t)v * v};
-    k_sigma2_assemble<<<n * n, kBlock, lds, st>>>(g, t2, P, Q, n, o, U, rows);
+    k_sigma2_assemble<<<n * n + o * o * (kAssembleParts - 1), kBlock, lds, st>>>(g, t2, P, Q, n,
+                                                                                  o, U, rows);
   }
 }
 

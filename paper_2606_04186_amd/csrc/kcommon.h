@@ -47,6 +47,7 @@ struct GlobalOps {
   const double *pf;          // compact parts P1..P4 of [F, sigma_2] (launch_sigma2)
   const double* zc = nullptr;   // dense sigma1 (H_N + Yg/2) (heff), or NULL
   const double* qf = nullptr;   // compact parts Q1, Q2 of [F, sigma_2] (launch_sigma2)
+  const double* fs1 = nullptr;  // [2][n][n] one-body external sums of the D1 tables
 };
 
 }  // namespace qf

@@ -67,6 +67,7 @@ struct qflow_ctx {
   // [G, sigma_2]_2 scratch (packed one-body, transposed t2, GEMM outputs)
   // and U_Y = [y1, sigma_2]_2
   DevBuf a12, t2T, sp, sq, sp_f, sq_f;   // sp_f, sq_f keep the [F, sigma_2] parts
+  DevBuf fs1;                            // one-body external sums of the marked tables
   DevBuf c1h, c1y;   // one-body parts of [H_N, sigma] and [Yg, sigma], [n][n]
   // FP32 operands of the mixed-precision ladder and ring products
   DevBuf w32, wy32, t2_32, ra32_h, r22_32_h, ra32_y, r22_32_y, rta32, rt22_32;
@@ -589,7 +590,7 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
                     &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
                     &ctx->gpart,  &ctx->zv,       &ctx->zo,      &ctx->zc,     &ctx->dtpart,
-                    &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->sq,       &ctx->sp_f,     &ctx->sq_f,
+                    &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->sq,       &ctx->sp_f,     &ctx->sq_f,     &ctx->fs1,
                     &ctx->c1h,
                     &ctx->c1y,    &ctx->lo_t,     &ctx->lo_xh,  &ctx->lo_xy,    &ctx->lo_h,
                     &ctx->lo_y,   &ctx->w32,      &ctx->wy32,   &ctx->t2_32,    &ctx->ra32_h,
@@ -692,6 +693,7 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->sq, sizeof(double) * 2 * n * o * v * v));
   QF_TRY(ensure(ctx, ctx->sp_f, sizeof(double) * 4 * n * o * o * v));
   QF_TRY(ensure(ctx, ctx->sq_f, sizeof(double) * 2 * n * o * v * v));
+  QF_TRY(ensure(ctx, ctx->fs1, sizeof(double) * 2 * n * n));
   QF_TRY(ensure(ctx, ctx->c1h, sizeof(double) * n2));
   QF_TRY(ensure(ctx, ctx->c1y, sizeof(double) * n2));
   QF_TRY(ensure(ctx, ctx->lo_t, sizeof(double) * o * o * v * v));
@@ -821,7 +823,7 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
                     P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx), t1, t2, ctx->n, ctx->o,
                     P<double>(ctx->scal), P<SpaceDev>(ctx->spaces), heff_off_dev,
                     P<int32_t>(ctx->tasks), qf::kTaskStride, ctx->task_slots,
-                    idx, cls_off, K, ctx->na_max, P<double>(ctx->mtab),
+                    idx, cls_off, K, ctx->na_max, P<double>(ctx->mtab), P<double>(ctx->fs1),
                     dense ? P<double>(ctx->zc) : nullptr, heff, ctx->stream);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;

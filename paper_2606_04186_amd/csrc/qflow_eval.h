@@ -941,33 +941,6 @@ struct MarkedSigma {
   QF_HD double two(int p, int q, int r, Mk s) const { return -d(1, s.t, r, p, q); }
 };
 
-// Fill the tables of one space; element e of the concatenated
-// [tau1 | tau2 | D1 | D2] block (lets a block of threads share the work).
-QF_HD double mark_table_entry(const Sigma& s, const double* f, const Active& A, int e) {
-  const int na = A.na, n = s.n, n2 = na * na, n3 = n2 * na, n4 = n3 * na;
-  if (e < n2) return s.one(A.orb[e / na], A.orb[e % na]);
-  e -= n2;
-  if (e < n4)
-    return s.two(A.orb[e / n3], A.orb[e / n2 % na], A.orb[e / na % na], A.orb[e % na]);
-  e -= n4;
-  auto extern_sum = [&](auto val) {
-    double acc = 0.0;
-    for (int k = 0; k < A.next_o + A.next_v; ++k) acc += val((int)A.ext[k]);
-    return acc;
-  };
-  if (e < 2 * n2) {
-    const int j = e / n2, t = A.orb[e / na % na], a = A.orb[e % na];
-    return extern_sum([&](int x) { return f[x * n + t] * (j == 0 ? s.one(x, a) : s.one(a, x)); });
-  }
-  e -= 2 * n2;
-  const int j = e / (na * n3), t = A.orb[e / n3 % na];
-  const int a = A.orb[e / n2 % na], b = A.orb[e / na % na], c = A.orb[e % na];
-  return extern_sum([&](int x) {
-    const double sv = (j == 0) ? s.two(x, a, b, c) : s.two(a, x, b, c);
-    return f[x * n + t] * sv;
-  });
-}
-
 template <class AOp, class BOp>
 QF_HD Comm<AOp, BOp> make_comm(const AOp& a, const BOp& b, int n, int o) {
   return Comm<AOp, BOp>{a, b, n, o};
