@@ -219,7 +219,10 @@ int qflow_last_timings(const qflow_ctx* ctx, float* ms, int n);
  *   QFLOW_Z_AUTO   per call, the form that moves fewer bytes (default);
  *   QFLOW_Z_SPACE  per space, from the rows of H_N and Yg the space touches;
  *   QFLOW_Z_DENSE  one dense Z per build (n^4 doubles of device memory,
- *                  allocated by this call or the next one given spaces).
+ *                  allocated by this call or the next one given spaces); this
+ *                  form also takes the occupied-pair ladders of the same
+ *                  commutators, sum_{t,u occ} X_pqtu t2[t,u,r,s], as one
+ *                  table over all pairs p <= q (n(n+1)/2 (o^2 + v^2) doubles).
  * The forms agree to rounding.  Another mode is QFLOW_E_INVALID_ARG; a flow
  * step captured as a graph is captured again after a change. */
 typedef enum { QFLOW_Z_AUTO = 0, QFLOW_Z_SPACE = 1, QFLOW_Z_DENSE = 2 } qflow_z_mode;

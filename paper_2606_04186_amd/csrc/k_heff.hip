@@ -125,6 +125,23 @@ __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
   }
 }
 
+// Rows of the dense occupied-pair ladder's operand: xp[tri(p,q)][(t,u)] =
+// (H_N + Yg/2)(p,q,t,u) for p <= q, t, u occupied.
+__global__ void k_pack_x_pairs(const double* __restrict__ Xh, const double* __restrict__ Xy,
+                               int n, int o, double* xp) {
+  const size_t oo = (size_t)o * o, tot = (size_t)n * (n + 1) / 2 * oo;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t pr = e / oo;
+    const int tu = (int)(e % oo), t = tu / o, u = tu % o;
+    int p = 0;   // row pr = tri_row(p, q, n)
+    while (tri_row(p + 1, p + 1, n) <= pr) ++p;
+    const int q = p + (int)(pr - tri_row(p, p, n));
+    const size_t x = (((size_t)p * n + q) * n + t) * n + u;
+    xp[e] = Xh[x] + 0.5 * Xy[x];
+  }
+}
+
 // fs1[j][t][a] = sum_x f[x][t] sigma1(x, a) (j = 0) or sigma1(a, x) (j = 1),
 // over every orbital x: the external sums of the D1 tables before the
 // active orbitals are taken out.  One thread per entry.
@@ -356,10 +373,14 @@ __global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
 // chunks: X rows [NA^2][chunk] and t2 [chunk][NV^2] in LDS; the product runs
 // on the matrix cores (v_mfma_f64_16x16x4f64), wavefront w taking rows
 // [16w, 16w + 16) of M (NA^2 <= 64 rows, NV^2 <= 16 columns).
+// With mpd (the dense form, for large space counts) M is read from
+// mpd[tri(p,q)][(r,s)] = sum_{t,u occ} X(p,q,t,u) t2[t,u,r,s] (rows p <= q;
+// M(q,p,s,r) = M(p,q,r,s) by the pair symmetry of X and t2) instead.
 template <int NA>
 __global__ __launch_bounds__(256) void k_heff_pp(const double* __restrict__ Xh,
                                                  const double* __restrict__ Xy,
                                                  const double* __restrict__ t2,
+                                                 const double* __restrict__ mpd,
                                                  const SpaceDev* __restrict__ spaces,
                                                  const int32_t* __restrict__ idx,
                                                  const int64_t* __restrict__ heff_off, int n,
@@ -376,6 +397,14 @@ __global__ __launch_bounds__(256) void k_heff_pp(const double* __restrict__ Xh,
   if (threadIdx.x < NA) orb[threadIdx.x] = spaces[k].orb[threadIdx.x];
   __syncthreads();
   const int v = n - o, oo = o * o;
+  if (mpd) {
+    for (int m = threadIdx.x; m < NM; m += blockDim.x) {
+      const int p = orb[m / NR / NA], q = orb[m / NR % NA];
+      const int r = orb[NO + m % NR / NV] - o, s = orb[NO + m % NV] - o;
+      M[m] = p <= q ? mpd[tri_row(p, q, n) * v * v + (size_t)r * v + s]
+                    : mpd[tri_row(q, p, n) * v * v + (size_t)s * v + r];
+    }
+  } else {
   const float inv_o = 1.0f / (float)o;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int row = wave * 16 + lane % 16, col = lane % 16, kq = lane / 16;
@@ -413,6 +442,7 @@ __global__ __launch_bounds__(256) void k_heff_pp(const double* __restrict__ Xh,
       const int orow = wave * 16 + kq + 4 * r;
       if (orow < N2 && col < NR) M[orow * NR + col] = acc[r];
     }
+  }
   __syncthreads();
   double* slot = heff + heff_off[k] + 1 + N2;
   for (int e = threadIdx.x; e < N2 * N2; e += blockDim.x) {
@@ -514,6 +544,12 @@ __global__ __launch_bounds__(256) void k_heff_cas(const SpaceDev* __restrict__ s
 
 }  // namespace
 
+void launch_pack_x_pairs(const double* Xh, const double* Xy, int n, int o, double* xp,
+                         hipStream_t st) {
+  k_pack_x_pairs<<<grid_for((size_t)n * (n + 1) / 2 * o * o, kBlock, 65536), kBlock, 0, st>>>(
+      Xh, Xy, n, o, xp);
+}
+
 // per space: the marked tables, then H_N and Yg restricted to the space
 int heff_table_stride(int na_max) {
   int s1, s2, s3, s4;
@@ -543,7 +579,8 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
                  int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
                  const int32_t* task_table, int task_stride, const int* task_slots,
                  const int32_t* cls_idx, const int* cls_off, int K, int na_max,
-                 double* tab, double* fs1, const double* zc, double* heff, hipStream_t st) {
+                 double* tab, double* fs1, const double* zc, const double* mpd, double* heff,
+                 hipStream_t st) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
               rings.zv,   rings.zo,  rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
@@ -626,18 +663,18 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
       k_heff_low<4><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
       if (!zc && w2) k_heff_z<4, 2><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
       if (!zc && !w2) k_heff_z<4, 1><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
-      k_heff_pp<4><<<count, 256, 0, st>>>(V, y2, t2, spaces, idx, heff_off, n, o, heff);
+      k_heff_pp<4><<<count, 256, 0, st>>>(V, y2, t2, mpd, spaces, idx, heff_off, n, o, heff);
     } else if (c == 1) {
       k_heff_low<6><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
       if (!zc && w2) k_heff_z<6, 2><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
       if (!zc && !w2) k_heff_z<6, 1><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
-      k_heff_pp<6><<<count, 256, 0, st>>>(V, y2, t2, spaces, idx, heff_off, n, o, heff);
+      k_heff_pp<6><<<count, 256, 0, st>>>(V, y2, t2, mpd, spaces, idx, heff_off, n, o, heff);
     } else {
       allow_lds(&k_heff_low<8>, lds);
       k_heff_low<8><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
       if (!zc && w2) k_heff_z<8, 2><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
       if (!zc && !w2) k_heff_z<8, 1><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
-      k_heff_pp<8><<<count, 256, 0, st>>>(V, y2, t2, spaces, idx, heff_off, n, o, heff);
+      k_heff_pp<8><<<count, 256, 0, st>>>(V, y2, t2, mpd, spaces, idx, heff_off, n, o, heff);
     }
   }
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;

@@ -62,6 +62,7 @@ struct qflow_ctx {
   // Z = sigma1 X (first index) of H_N and Yg, n^4 each
   DevBuf zv, zo;   // sigma1 x two-body pieces of the residual
   DevBuf zc;       // dense sigma1 (H_N + Yg/2), n^4, when some call takes that form
+  DevBuf xp, mp;   // dense occupied-pair ladder: its operand and the table (same form)
   int z_mode = QFLOW_Z_AUTO;
   DevBuf dtpart;   // per-block maxima of |t_new - t_old|
   // [G, sigma_2]_2 scratch (packed one-body, transposed t2, GEMM outputs)
@@ -197,9 +198,13 @@ bool z_dense_for(const qflow_ctx* ctx, const int* cls_off) {
   return 2.0 * rows * n > 3.0 * n * n * n * n;
 }
 
+// The dense form also takes the occupied-pair ladders as one table over all
+// pairs p <= q (k_heff_pp otherwise gathers the rows per space).
 int ensure_zc(qflow_ctx* ctx) {
   if (!ctx->loaded || !z_dense_for(ctx, ctx->cls_off)) return QFLOW_OK;
-  const size_t n = ctx->n;
+  const size_t n = ctx->n, o = ctx->o, v = ctx->v, npair = n * (n + 1) / 2;
+  QF_TRY(ensure(ctx, ctx->xp, sizeof(double) * npair * o * o));
+  QF_TRY(ensure(ctx, ctx->mp, sizeof(double) * npair * v * v));
   return ensure(ctx, ctx->zc, sizeof(double) * n * n * n * n);
 }
 
@@ -589,7 +594,7 @@ int qflow_destroy(qflow_ctx* ctx) {
   DevBuf* bufs[] = {&ctx->ra_h,   &ctx->r22_h,    &ctx->ra_y,   &ctx->r22_y,    &ctx->rta,
                     &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
                     &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
-                    &ctx->gpart,  &ctx->zv,       &ctx->zo,      &ctx->zc,     &ctx->dtpart,
+                    &ctx->gpart,  &ctx->zv,       &ctx->zo,      &ctx->zc,     &ctx->xp,     &ctx->mp,     &ctx->dtpart,
                     &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->sq,       &ctx->sp_f,     &ctx->sq_f,     &ctx->fs1,
                     &ctx->c1h,
                     &ctx->c1y,    &ctx->lo_t,     &ctx->lo_xh,  &ctx->lo_xy,    &ctx->lo_h,
@@ -813,18 +818,29 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
                       P<double>(ctx->r2), nullptr, ctx->stream);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[8], ctx->stream));
   const size_t n = ctx->n;
+  const size_t npair = n * (n + 1) / 2, oo = (size_t)ctx->o * ctx->o,
+               vv = (size_t)ctx->v * ctx->v;
   const bool dense = K > 0 && z_dense_for(ctx, cls_off) &&
-                     ctx->zc.bytes >= sizeof(double) * n * n * n * n;
-  if (dense)
+                     ctx->zc.bytes >= sizeof(double) * n * n * n * n &&
+                     ctx->xp.bytes >= sizeof(double) * npair * oo &&
+                     ctx->mp.bytes >= sizeof(double) * npair * vv;
+  if (dense) {
     qf::launch_sigma1_x(P<double>(ctx->V), P<double>(ctx->y2), t1, ctx->n, ctx->o,
                         P<double>(ctx->zc), ctx->stream);
+    qf::launch_pack_x_pairs(P<double>(ctx->V), P<double>(ctx->y2), ctx->n, ctx->o,
+                            P<double>(ctx->xp), ctx->stream);
+    qf::launch_gemm_nt_f64(P<double>(ctx->xp), P<double>(ctx->lo_t), P<double>(ctx->mp),
+                           (int)npair, (int)vv, (int)oo, 1.0, P<double>(ctx->gpart),
+                           ctx->gpart.bytes / sizeof(double), ctx->stream);
+  }
   if (K > 0)
     qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1), P<double>(ctx->y2),
                     P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx), t1, t2, ctx->n, ctx->o,
                     P<double>(ctx->scal), P<SpaceDev>(ctx->spaces), heff_off_dev,
                     P<int32_t>(ctx->tasks), qf::kTaskStride, ctx->task_slots,
                     idx, cls_off, K, ctx->na_max, P<double>(ctx->mtab), P<double>(ctx->fs1),
-                    dense ? P<double>(ctx->zc) : nullptr, heff, ctx->stream);
+                    dense ? P<double>(ctx->zc) : nullptr, dense ? P<double>(ctx->mp) : nullptr,
+                    heff, ctx->stream);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
