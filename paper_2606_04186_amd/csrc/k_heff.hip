@@ -22,22 +22,6 @@ namespace qf {
 
 namespace {
 
-// Active-set description shared by the block.
-__device__ void load_active(const SpaceDev& sp, int n, int o, Active& A) {
-  for (int p = threadIdx.x; p < kMaxOrb; p += blockDim.x) A.pos[p] = -1;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    A.na = sp.na;
-    A.nocc = sp.nocc;
-    for (int a = 0; a < sp.na; ++a) {
-      A.orb[a] = sp.orb[a];
-      A.pos[sp.orb[a]] = (int8_t)a;
-    }
-    active_fill_ext(A, n, o);
-  }
-  __syncthreads();
-}
-
 // Per-space tables of the marked [E,sigma] evaluation (see MarkTables), for
 // a size class of NA orbitals (NA/2 occupied):
 //   tau1[a][b], tau2[a][b][c][d]           sigma restricted to the space;
@@ -175,11 +159,11 @@ __global__ __launch_bounds__(BLK, (PART < 2 && BLK == 256) ? 7 : 1) void k_heff_
                                                    const int32_t* __restrict__ tasks,
                                                    int task_stride, const double* __restrict__ tab,
                                                    int64_t tab_stride, double* heff) {
-  __shared__ Active A;
+  __shared__ int orb[kMaxAct];   // the space's orbitals (synchronised below)
   extern __shared__ double tl[];
   const int k = idx[blockIdx.x];
   const SpaceDev& sp = spaces[k];
-  load_active(sp, g.n, g.o, A);
+  if (threadIdx.x < sp.na) orb[threadIdx.x] = sp.orb[threadIdx.x];
   MarkTables T{};
   const int na = sp.na, n = g.n, o = g.o, v = n - o;
   const int n2 = na * na, n4 = n2 * n2;
@@ -208,7 +192,7 @@ __global__ __launch_bounds__(BLK, (PART < 2 && BLK == 256) ? 7 : 1) void k_heff_
   if (code < 0) return;
   const int kind = code >> 24;
   const int la = (code >> 18) & 63, lb = (code >> 12) & 63, lc = (code >> 6) & 63, ld = code & 63;
-  const int p = A.orb[la], q = A.orb[lb], r = A.orb[lc], t = A.orb[ld];
+  const int p = orb[la], q = orb[lb], r = orb[lc], t = orb[ld];
   // distinct slot positions of the task's symmetry orbit (see build_tasks)
   int d0, d1 = -1, d2 = -1, d3 = -1;
   if (kind == 2) {
