@@ -589,16 +589,32 @@ __global__ void k_pack_ring_T(const double* __restrict__ t2, int o, int v, T* Ta
 
 // The same operands as BF16 hi/lo planes (rows padded to a multiple of 32 k;
 // the padding is zeroed once when the planes are allocated and never written).
-__global__ void k_pack_ring_A_bf16(const double* __restrict__ X, int n, int o, __bf16* Ah,
-                                   __bf16* Al, int kpa, __bf16* A22h, __bf16* A22l, int kp22) {
-  const int v = n - o;
-  const size_t ov = (size_t)o * v, rows = (size_t)n * n;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < rows * ov;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const size_t row = idx / ov, k = idx % ov;
-    const int a = (int)(row / n), b = (int)(row % n), u = (int)(k / v), t = o + (int)(k % v);
-    const double x1 = X[(((size_t)a * n + u) * n + b) * n + t];
-    const double x2 = X[(((size_t)a * n + u) * n + t) * n + b];
+// Workgroup (a, u, 32 consecutive b): the transposed operand X[a][u][t][b] is
+// read row by row (b fastest) into LDS, then every output row segment (a, b;
+// u, all virtual t) is written with t fastest, both reads of X coalesced.
+constexpr int kRingTileB = 32;
+
+__global__ __launch_bounds__(256) void k_pack_ring_A_bf16(const double* __restrict__ X, int n,
+                                                          int o, __bf16* Ah, __bf16* Al, int kpa,
+                                                          __bf16* A22h, __bf16* A22l, int kp22) {
+  extern __shared__ double xt[];   // [v][kRingTileB + 1]: X[a][u][o+t][b0+bb]
+  constexpr int LD = kRingTileB + 1;
+  const int v = n - o, nbt = (n + kRingTileB - 1) / kRingTileB;
+  const int a = blockIdx.x / (o * nbt), u = blockIdx.x / nbt % o,
+            b0 = blockIdx.x % nbt * kRingTileB;
+  const size_t ov = (size_t)o * v;
+  const double* slab = X + ((size_t)a * n + u) * n * n;   // X[a][u][*][*]
+  for (int e = threadIdx.x; e < v * kRingTileB; e += blockDim.x) {
+    const int t = e / kRingTileB, bb = e % kRingTileB;
+    xt[t * LD + bb] = b0 + bb < n ? slab[(size_t)(o + t) * n + b0 + bb] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < v * kRingTileB; e += blockDim.x) {
+    const int bb = e / v, t = e % v, b = b0 + bb;
+    if (b >= n) break;   // e grows with bb
+    const double x1 = slab[(size_t)b * n + o + t];
+    const double x2 = xt[t * LD + bb];
+    const size_t row = (size_t)a * n + b, k = (size_t)u * v + t;
     store_bf16_split(2.0 * x1 - x2, Ah, Al, row * kpa + k);
     store_bf16_split(-x1, Ah, Al, row * kpa + ov + k);
     store_bf16_split(x2, A22h, A22l, row * kp22 + k);
@@ -831,7 +847,9 @@ void launch_pack_ring_T(const double* t2, int o, int v, double* Ta, double* T22,
 void launch_pack_ring_A_bf16(const double* X, int n, int o, __bf16* Ah, __bf16* Al, __bf16* A22h,
                              __bf16* A22l, hipStream_t st) {
   const size_t ov = (size_t)o * (n - o);
-  k_pack_ring_A_bf16<<<grid_for((size_t)n * n * ov, kBlock, 65536), kBlock, 0, st>>>(
+  const int nbt = (n + kRingTileB - 1) / kRingTileB;
+  const size_t lds = (size_t)(n - o) * (kRingTileB + 1) * sizeof(double);
+  k_pack_ring_A_bf16<<<(unsigned)(n * o * nbt), kBlock, lds, st>>>(
       X, n, o, Ah, Al, bf16_pad((int)(2 * ov)), A22h, A22l, bf16_pad((int)ov));
 }
 

@@ -82,6 +82,7 @@ __global__ __launch_bounds__(128) void k_zo(const double* __restrict__ Xh,
       double acc[kChunk];
 #pragma unroll
       for (int i = 0; i < kChunk; ++i) acc[i] = 0.0;
+#pragma unroll 4
       for (int c = 0; c < v; ++c) {
         const size_t x = (((size_t)(o + c) * n + j) * n + o + a) * n + o + b;
         const double xv = Xh[x] + 0.5 * Xy[x];
