@@ -122,8 +122,9 @@ struct Tau {
 
 // U = [G, sigma_2]_2 of a Hermitian one-body G evaluated from the compact
 // contractions of the K = v and K = o GEMMs (P1..P4, Q1, Q2; layouts as in
-// launch_sigma2) instead of a dense n^4 array.  Zero unless r,s or p,q share
-// a class; the p,q-virtual cases with r or s occupied are o-term sums.
+// launch_sigma2) instead of a dense n^4 array: a few lookups per element.
+// Zero unless r,s or p,q share a class.  (g and t2 are kept for callers that
+// name them; every case reads P and Q.)
 struct Sigma2Lazy {
   const double* g;    // G [n][n]
   const double* t2;
@@ -153,11 +154,12 @@ struct Sigma2Lazy {
         if (!os) x += P[2 * nv + (size_t)r * ov2 + pq + (s - o)];
         if (!or_) x += P[3 * nv + (size_t)s * ov2 + pq + (r - o)];
       } else {
+        // p, q virtual: -sum_{t occ} G_tr t2[t,s,p,q] (s occupied) and
+        // -sum_{t occ} G_ts t2[r,t,p,q] (r occupied) are Q1[r][(s,p,q)] and
+        // Q2[s][(r,p,q)] (G symmetric)
         const size_t ab = (size_t)(p - o) * v + (q - o);
-        if (os)
-          for (int t = 0; t < o; ++t) x -= g[t * n + r] * t2[((size_t)t * o + s) * vv + ab];
-        if (or_)
-          for (int t = 0; t < o; ++t) x -= g[t * n + s] * t2[((size_t)r * o + t) * vv + ab];
+        if (os) x += Q[(size_t)r * ovv + (size_t)s * vv + ab];
+        if (or_) x += Q[(size_t)n * ovv + (size_t)s * ovv + (size_t)r * vv + ab];
       }
     }
     return x;
