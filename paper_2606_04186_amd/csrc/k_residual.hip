@@ -16,27 +16,42 @@ namespace {
 // residual of Hbar(sigma)
 // ---------------------------------------------------------------------------
 
-__global__ void k_residual2(GlobalOps g, double* r2) {
-  const int n = g.n, o = g.o, v = n - o;
+// Workgroup (a, bc virtual b starting at b0): the elements (a, b; i, j) are
+// evaluated with (i, j) fastest, so that the lookups (X, L, Lo, Ga, G22, ...
+// all [..][i][j]) run along memory, into LDS, then written to r2[i][j][a][b]
+// with b fastest.  bc is a power of two with bc o^2 <= 8192 (at most 16).
+__global__ __launch_bounds__(256) void k_residual2(GlobalOps g, int bc, double* r2) {
+  extern __shared__ double rt[];   // [bc][o*o]
+  const int n = g.n, o = g.o, v = n - o, oo = o * o;
+  const int nbc = (v + bc - 1) / bc;
+  const int a = blockIdx.x / nbc, b0 = blockIdx.x % nbc * bc;
+  const float inv_o = 1.0f / (float)o;
   const Sigma s{g.t1, g.t2, n, o, v};
   const DenseOp H{g.f, g.V, g.L, n, o, g.ga_h, g.g22_h, g.j1_h, g.j2_h, g.u_h, g.lo_h};
   const DenseOp Y{g.y1, g.y2, g.LY, n, o, g.ga_y, g.g22_y, g.j1_y, g.j2_y, nullptr, g.lo_y,
                    Sigma2Lazy{g.y1, g.t2, g.s2p, g.s2q, n, o}};
   const auto cH = make_comm(H, s, n, o);
   const auto cY = make_comm(Y, s, n, o);
-  const size_t tot = (size_t)o * o * v * v;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const int b = (int)(idx % v), a = (int)(idx / v % v), j = (int)(idx / v / v % o),
-              i = (int)(idx / v / v / o);
-    const int pa = o + a, pb = o + b;
-    // the sigma1 x two-body part of both commutators, -(Z_abij + Z_baji +
-    // Z_ijab + Z_jiba) of H_N + Yg/2, from the pieces of k_zv and k_zo
-    const double w = g.zv[(((size_t)a * v + b) * o + i) * o + j] +
-                     g.zv[(((size_t)b * v + a) * o + j) * o + i] +
-                     g.zo[(((size_t)i * o + j) * v + a) * v + b] +
-                     g.zo[(((size_t)j * o + i) * v + b) * v + a];
-    r2[idx] = H.two(pa, pb, i, j) + cH.c2(pa, pb, i, j) + 0.5 * cY.c2(pa, pb, i, j) - w;
+  for (int bb = 0; bb < bc && b0 + bb < v; ++bb)
+    for (int ij = threadIdx.x; ij < oo; ij += blockDim.x) {
+      const int b = b0 + bb;
+      // i = ij / o in single precision ((ij + 1/2)/o is at least 1/(2o) from
+      // an integer; ij < 2^12)
+      const int i = (int)(((float)ij + 0.5f) * inv_o), j = ij - i * o;
+      const int pa = o + a, pb = o + b;
+      // the sigma1 x two-body part of both commutators, -(Z_abij + Z_baji +
+      // Z_ijab + Z_jiba) of H_N + Yg/2, from the pieces of k_zv and k_zo
+      const double w = g.zv[(((size_t)a * v + b) * o + i) * o + j] +
+                       g.zv[(((size_t)b * v + a) * o + j) * o + i] +
+                       g.zo[(((size_t)i * o + j) * v + a) * v + b] +
+                       g.zo[(((size_t)j * o + i) * v + b) * v + a];
+      rt[bb * oo + ij] = H.two(pa, pb, i, j) + cH.c2(pa, pb, i, j) + 0.5 * cY.c2(pa, pb, i, j) - w;
+    }
+  __syncthreads();
+  const int lbc = __ffs(bc) - 1;   // bc = 2^lbc
+  for (int e = threadIdx.x; e < oo * bc; e += blockDim.x) {
+    const int ij = e >> lbc, bb = e & (bc - 1);
+    if (b0 + bb < v) r2[((size_t)ij * v + a) * v + b0 + bb] = rt[bb * oo + ij];
   }
 }
 
@@ -214,7 +229,10 @@ void launch_residual(const double* f, const double* V, const double* y1, const d
   const int nch = (int)((v + kRingChunk - 1) / kRingChunk);
   k_comm1_ring<<<dim3(n, nch, 2), 128, 0, st>>>(V, y2, t1, n, o, part);
   k_comm1_sum<<<grid_for((size_t)2 * n * n), kBlock, 0, st>>>(part, n, nch, c1h, c1y);
-  k_residual2<<<grid_for(o * o * v * v, kBlock, 65536), kBlock, 0, st>>>(g, r2);
+  int bc = 16;
+  while (bc > 1 && bc * o * o > 8192) bc /= 2;
+  const unsigned nbc = (unsigned)((v + bc - 1) / bc);
+  k_residual2<<<(unsigned)v * nbc, kBlock, (size_t)bc * o * o * sizeof(double), st>>>(g, bc, r2);
   k_residual1<<<grid_for(o * v), kBlock, 0, st>>>(g, r1);
   k_residual0<<<1, 64, 0, st>>>(g, scal, e0);
 }
