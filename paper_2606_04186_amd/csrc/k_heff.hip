@@ -597,8 +597,10 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
       const int mark = mark_sizes(na, &s1, &s2, &s3, &s4);
       const size_t lds = (size_t)(PART == 2 ? mark : 2 * (n2 + n2 * n2)) * sizeof(double);
       const int32_t* idx = cls_idx + cls_off[c];
+      // part 2 (two-body elements only) covers the two-body slots
+      const int slots = PART == 2 ? task_slots[3 + c] : task_slots[c];
       if (c == 2) {
-        const dim3 grid(count, (task_slots[c] + 1023) / 1024);
+        const dim3 grid(count, (slots + 1023) / 1024);
         if (PART == 0) {
           allow_lds(&k_heff_part<0, 1024, 0>, lds);
           k_heff_part<0, 1024, 0><<<grid, 1024, lds, st>>>(g, scal, spaces, idx, heff_off, task_table,
@@ -614,7 +616,7 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
         }
         continue;
       }
-      const dim3 grid(count, (task_slots[c] + kBlock - 1) / kBlock);
+      const dim3 grid(count, (slots + kBlock - 1) / kBlock);
       if (PART == 0)
         k_heff_part<0, 256, 0><<<grid, kBlock, lds, st>>>(g, scal, spaces, idx, heff_off,
                                                           task_table, task_stride, tab, tab_stride,

@@ -113,7 +113,8 @@ void launch_residual(const double* f, const double* V, const double* y1, const d
 
 // per-space downfolded Hamiltonians in CAS form
 // The per-element kernels run one launch per size class (cls_idx / cls_off
-// as for launch_davidson; task_slots[c] = task count of class c); K = the
+// as for launch_davidson; task_slots[c] = task count of class c,
+// task_slots[3 + c] = the slots of its two-body elements, which come first); K = the
 // number of spaces in the lists (cls_off[3]).  zc: the dense
 // Z = sigma1 (H_N + Yg/2) (launch_sigma1_x), read by the element kernels; when
 // NULL, k_heff_z adds that part per space from the rows of H_N and Yg.

@@ -93,7 +93,8 @@ struct qflow_ctx {
   DevBuf win_idx, t1s, t2s;
   std::vector<int> win_base, win_off;
   int win_size = 0;
-  int task_slots[3] = {0, 0, 0};
+  // task slots per class, then the slots of its two-body elements (first)
+  int task_slots[6] = {0, 0, 0, 0, 0, 0};
   int lds_limit = 64 * 1024;   // dynamic LDS bytes a block may use
   // host mirror of the last uploaded space list
   std::vector<qflow_space> last_spaces;
@@ -569,9 +570,14 @@ int qflow_create(qflow_ctx** out, int device, void* hip_stream) {
   std::vector<qf::Strings> tabs(3);
   for (int s = 0; s < 3; ++s) qf::build_strings(2 * (s + 2), s + 2, &tabs[s]);
   std::vector<int32_t> task_tab(3 * qf::kTaskStride, -1);
-  for (int s = 0; s < 3; ++s)
+  for (int s = 0; s < 3; ++s) {
+    const int32_t* tt = &task_tab[s * qf::kTaskStride];
     ctx->task_slots[s] = qf::build_tasks(2 * (s + 2), s + 2, &task_tab[s * qf::kTaskStride],
                                          qf::kTaskStride);
+    int two = 0;   // the two-body groups come first (kind 2 in bits 24..)
+    while (two < ctx->task_slots[s] && (tt[two] < 0 || (tt[two] >> 24) == 2)) ++two;
+    ctx->task_slots[3 + s] = two;
+  }
   if (ensure(ctx, ctx->strings, sizeof(qf::Strings) * 3) != QFLOW_OK ||
       hipMemcpy(ctx->strings.p, tabs.data(), sizeof(qf::Strings) * 3, hipMemcpyHostToDevice) !=
           hipSuccess ||
