@@ -282,7 +282,7 @@ __global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
                                                 int o, double* heff) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   typedef double dw __attribute__((ext_vector_type(W)));
-  constexpr int N2 = NA * NA, N3 = N2 * NA, NT = (N3 + 15) / 16;
+  constexpr int N2 = NA * NA, N3 = N2 * NA, NT = (N3 + 15) / 16, NO = NA / 2;
   extern __shared__ double zl[];
   const int np = (n + 4 * W - 1) / (4 * W) * (4 * W), v = n - o;
   double* S = zl;             // [NA][np]
@@ -307,9 +307,18 @@ __global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
     const int row = tile * 16 + col;   // this lane's A row (b,c,d)
     const bool live = row < N3;
     size_t off = 0;
+    // Yg's two-body part vanishes unless its class pattern is within one
+    // index of (v,v,o,o) or (o,o,v,v): which classes of t its row admits
+    bool y_occ = false, y_vir = false;
     if (live) {
       const int b = row / N2, c = row / NA % NA, d = row % NA;
       off = (((size_t)orb[d] * n + orb[c]) * n + orb[b]) * n;
+      const int qrs = (b < NO) << 2 | (c < NO) << 1 | (d < NO);   // occupied bits
+      auto near = [&](int pat) {   // pat: occupied bits of (t, q, r, s)
+        return __builtin_popcount(pat ^ 0x3) <= 1 || __builtin_popcount(pat ^ 0xC) <= 1;
+      };
+      y_occ = near(8 | qrs);
+      y_vir = near(qrs);
     }
     d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
@@ -321,7 +330,15 @@ __global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
       for (int w = 0; w < W; ++w) ah[w] = ay[w] = 0.0;
       if (in) {
         ah = *reinterpret_cast<const dw*>(Xh + off + t);
-        ay = *reinterpret_cast<const dw*>(Xy + off + t);
+        bool any = false;
+#pragma unroll
+        for (int w = 0; w < W; ++w) any = any || (t + w < o ? y_occ : y_vir);
+        if (any) {   // structural zeros of Yg are not read
+          ay = *reinterpret_cast<const dw*>(Xy + off + t);
+#pragma unroll
+          for (int w = 0; w < W; ++w)
+            if (!(t + w < o ? y_occ : y_vir)) ay[w] = 0.0;
+        }
       }
 #pragma unroll
       for (int w = 0; w < W; ++w) {
