@@ -102,10 +102,14 @@ __global__ __launch_bounds__(256) void k_heff_tab(GlobalOps g,
     xo[N2 + N4 + e] = g.y1[p * n + q];
   }
   for (int e = threadIdx.x; e < N4; e += blockDim.x) {
-    const size_t i4 =
-        (((size_t)orb[e / N3] * n + orb[e / N2 % NA]) * n + orb[e / NA % NA]) * n + orb[e % NA];
+    const int a = e / N3, b = e / N2 % NA, c = e / NA % NA, d = e % NA;
+    const size_t i4 = (((size_t)orb[a] * n + orb[b]) * n + orb[c]) * n + orb[d];
     xo[N2 + e] = g.V[i4];
-    xo[2 * N2 + N4 + e] = g.y2[i4];
+    // Yg's two-body part is an exact zero unless the class pattern lies
+    // within one index of (v,v,o,o) or (o,o,v,v): not read there
+    const int pat = (a < NO) << 3 | (b < NO) << 2 | (c < NO) << 1 | (d < NO);
+    const bool y_on = __builtin_popcount(pat ^ 0x3) <= 1 || __builtin_popcount(pat ^ 0xC) <= 1;
+    xo[2 * N2 + N4 + e] = y_on ? g.y2[i4] : 0.0;
   }
 }
 
@@ -419,7 +423,9 @@ __global__ __launch_bounds__(256) void k_heff_pp(const double* __restrict__ Xh,
       // from an integer, far beyond the rounding error for tu < 2^12
       const int t = (int)(((float)tu + 0.5f) * inv_o), u = tu - t * o;
       const size_t x = (((size_t)orb[pq / NA] * n + orb[pq % NA]) * n + t) * n + u;
-      xs[pq * kChunk + i] = Xh[x] + 0.5 * Xy[x];
+      // Yg vanishes on (o,o,o,o): not read for p, q both occupied
+      const bool y_on = pq / NA >= NO || pq % NA >= NO;
+      xs[pq * kChunk + i] = Xh[x] + (y_on ? 0.5 * Xy[x] : 0.0);
     }
     for (int e = threadIdx.x; e < cn * NR; e += blockDim.x) {
       const int tu = c0 + e / NR, rs = e % NR;
