@@ -287,25 +287,31 @@ __device__ void davidson_space(const DavidsonArgs& a, int k, const SpaceDev& sp,
       m = 1;
       __syncthreads();
     }
-    // diagonal-preconditioned correction, orthogonalised twice
+    // diagonal-preconditioned correction, orthogonalised by classical
+    // Gram-Schmidt; a second pass only when the first left less than
+    // 1/sqrt(2) of its norm (the Daniel-Gragg-Kaufman-Stewart criterion)
+    double n0 = 0.0;
     for (int e = tid; e < D; e += kDavBlock) {
       double den = dg[e] - theta;
       if (fabs(den) < 1e-8) den = (den < 0.0 ? -1e-8 : 1e-8);
       rv[e] = -rv[e] / den;
+      n0 += rv[e] * rv[e];
     }
-    __syncthreads();
+    n0 = sqrt(block_sum<kDavBlock>(n0, red));
+    double nr = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
       dots(rv, m, Aw);   // Aw as scratch
+      nr = 0.0;
       for (int e = tid; e < D; e += kDavBlock) {
         double x = rv[e];
         for (int i = 0; i < m; ++i) x -= Aw[i] * bb[(size_t)i * D + e];
         rv[e] = x;
+        nr += x * x;
       }
-      __syncthreads();
+      nr = sqrt(block_sum<kDavBlock>(nr, red));   // (also orders the rv writes)
+      if (nr > 0.70710678118654752 * n0) break;   // the same on every thread
+      n0 = nr;
     }
-    double nr = 0.0;
-    for (int e = tid; e < D; e += kDavBlock) nr += rv[e] * rv[e];
-    nr = sqrt(block_sum<kDavBlock>(nr, red));
     if (nr < 1e-14) {
       conv = rn < 1e3 * a.tol;
       ++it;
