@@ -80,7 +80,12 @@ enum {
 };
 
 /* Create a context on HIP device `device`; hip_stream is a hipStream_t to
- * enqueue on, or NULL for a stream the context creates.  *out is NULL on
+ * enqueue on, or NULL for a stream the context creates.  The context also
+ * creates a second stream of its own (default priority): outside the
+ * stage-timed eager flow step, H_N's ladder and ring contractions run there
+ * beside [F, sigma]'s and are joined back into the main stream by events
+ * before anything reads them, so every call still completes in the main
+ * stream's order (and a captured step captures both).  *out is NULL on
  * failure. */
 int qflow_create(qflow_ctx** out, int device, void* hip_stream);
 

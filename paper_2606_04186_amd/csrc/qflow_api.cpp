@@ -45,6 +45,10 @@ struct qflow_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // H_N's contractions (they need only t2) run here beside Yg's, joined back
+  // into `stream` by events; its split-K slices go to gpart2
+  hipStream_t stream2 = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::string err;
   // problem
   int n = 0, o = 0, v = 0;
@@ -59,6 +63,7 @@ struct qflow_ctx {
   // step) and the split-K slices
   DevBuf ja_h, ja_y, jb;
   DevBuf gpart;   // split-K slices of the matrix-core contractions
+  DevBuf gpart2;  // the same for the contractions on stream2
   // Z = sigma1 X (first index) of H_N and Yg, n^4 each
   DevBuf zv, zo;   // sigma1 x two-body pieces of the residual
   DevBuf zc;       // dense sigma1 (H_N + Yg/2), n^4, when some call takes that form
@@ -398,12 +403,77 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   double* part = P<double>(ctx->gpart);
   const size_t pcap = ctx->gpart.bytes / sizeof(double);
   hipStream_t st = ctx->stream;
+  const int npair = n * (n + 1) / 2;   // ladder rows p <= q
+  const size_t n2p = (size_t)npair;
+  const int kp = qf::bf16_pad(v * v);
+  // t2 as the ladder operand, and the ring operands of t2 (read by the
+  // contractions of H_N and of Yg)
+  Split tb{};
+  if (bf3) {
+    tb = split_of(ctx->t2b, (size_t)o * o, v * v);
+    split(t2, (size_t)o * o, v * v, tb, st);
+    const Split ta = split_of(ctx->rtab, ov, (int)(2 * ov)), t22 = split_of(ctx->rt22b, ov, (int)ov);
+    qf::launch_pack_ring_T_bf16(t2, o, v, ta.hi, ta.lo, t22.hi, t22.lo, st);
+  } else if (mixed) {
+    qf::launch_cvt_f32(t2, P<float>(ctx->t2_32), ov * ov, st);
+    qf::launch_pack_ring_T(t2, o, v, P<float>(ctx->rta32), P<float>(ctx->rt22_32), st);
+  } else {
+    qf::launch_pack_ring_T(t2, o, v, P<double>(ctx->rta), P<double>(ctx->rt22), st);
+  }
+  // H_N's particle-particle ladder and ring contractions need nothing else:
+  // outside the stage-timed mode they run on stream2 beside the Yg chain
+  // (their own split-K slices) and are joined back at the end of this
+  // function; in it they keep their place in the stage order.
+  auto ladder_h = [&](hipStream_t s, double* pp, size_t pc) {
+    if (bf3) {
+      const Split wb = split_of(ctx->wb, n2p, v * v);
+      qf::launch_gemm_nt_bf16x3(wb.hi, wb.lo, tb.hi, tb.lo, P<double>(ctx->L), npair, o * o, kp,
+                                1.0, pp, pc, s);
+    } else if (mixed) {
+      qf::launch_gemm_nt_f32(P<float>(ctx->w32), P<float>(ctx->t2_32), P<double>(ctx->L), npair,
+                             o * o, v * v, 1.0, pp, pc, s);
+    } else {
+      qf::launch_gemm_nt_f64(P<double>(ctx->W), t2, P<double>(ctx->L), npair, o * o, v * v, 1.0,
+                             pp, pc, s);
+    }
+  };
+  auto rings_h = [&](hipStream_t s, double* pp, size_t pc) {
+    if (bf3) {
+      const int ka = qf::bf16_pad((int)(2 * ov)), k22 = qf::bf16_pad((int)ov);
+      const Split ta = split_of(ctx->rtab, ov, (int)(2 * ov)), t22 = split_of(ctx->rt22b, ov, (int)ov);
+      const Split ah = split_of(ctx->rab_h, n2, (int)(2 * ov)), a22h = split_of(ctx->r22b_h, n2, (int)ov);
+      qf::launch_gemm_nt_bf16x3(ah.hi, ah.lo, ta.hi, ta.lo, P<double>(ctx->ga_h), (int)n2, (int)ov,
+                                ka, 1.0, pp, pc, s);
+      qf::launch_gemm_nt_bf16x3(a22h.hi, a22h.lo, t22.hi, t22.lo, P<double>(ctx->g22_h), (int)n2,
+                                (int)ov, k22, 1.0, pp, pc, s);
+    } else if (mixed) {
+      qf::launch_gemm_nt_f32(P<float>(ctx->ra32_h), P<float>(ctx->rta32), P<double>(ctx->ga_h),
+                             (int)n2, (int)ov, (int)(2 * ov), 1.0, pp, pc, s);
+      qf::launch_gemm_nt_f32(P<float>(ctx->r22_32_h), P<float>(ctx->rt22_32), P<double>(ctx->g22_h),
+                             (int)n2, (int)ov, (int)ov, 1.0, pp, pc, s);
+    } else {
+      qf::launch_gemm_nt_f64(P<double>(ctx->ra_h), P<double>(ctx->rta), P<double>(ctx->ga_h),
+                             (int)n2, (int)ov, (int)(2 * ov), 1.0, pp, pc, s);
+      qf::launch_gemm_nt_f64(P<double>(ctx->r22_h), P<double>(ctx->rt22), P<double>(ctx->g22_h),
+                             (int)n2, (int)ov, (int)ov, 1.0, pp, pc, s);
+    }
+  };
+  const bool fork = !ctx->timed;
+  if (fork) {
+    hipStream_t sh = ctx->stream2;
+    double* ph = P<double>(ctx->gpart2);
+    const size_t pch = ctx->gpart2.bytes / sizeof(double);
+    QF_HIP(hipEventRecord(ctx->fork_ev, st));
+    QF_HIP(hipStreamWaitEvent(sh, ctx->fork_ev, 0));
+    ladder_h(sh, ph, pch);
+    rings_h(sh, ph, pch);
+    QF_HIP(hipEventRecord(ctx->join_ev, sh));
+  }
   // Yg = [F_N, sigma]: one-body and scalar, two-body (+ its ladder slab), and
   // the compact parts of [y1, sigma_2]_2 (the one-body part of Yg against
   // sigma's two-body), which stay in sp / sq for the lookups
   qf::launch_yg1(P<double>(ctx->f), t1, t2, n, o, P<double>(ctx->y1), P<double>(ctx->scal), st);
   const int npo = o * n - o * (o - 1) / 2;   // non-zero ladder rows of Yg (see below)
-  const int kp = qf::bf16_pad(v * v);
   Split wyb_rows{};
   if (bf3) {   // Yg's ladder rows go straight into BF16 planes (npo rows each)
     const Split wyb = split_of(ctx->wyb, (size_t)n * (n + 1) / 2, v * v);
@@ -416,64 +486,39 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   qf::launch_sigma2(P<double>(ctx->y1), t2, n, o, P<double>(ctx->a12), P<double>(ctx->t2T),
                     false, P<double>(ctx->sp), P<double>(ctx->sq), part, pcap, nullptr, nullptr,
                     nullptr, nullptr, nullptr, st);
-  const int npair = n * (n + 1) / 2;   // ladder rows p <= q
   // rows of Yg's ladder operand with p virtual (then q virtual too) vanish:
   // the Yg ladder runs over the first npo = o*n - o(o-1)/2 rows only
-  const size_t n2p = (size_t)npair;
-  Split tb{};
-  if (bf3) {   // t2 as the ladder operand (the GEMM stages hold GEMMs only)
-    tb = split_of(ctx->t2b, (size_t)o * o, v * v);
-    split(t2, (size_t)o * o, v * v, tb, st);
-  } else if (mixed) {
-    qf::launch_cvt_f32(t2, P<float>(ctx->t2_32), ov * ov, st);
-  }
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[1], st));
+  if (!fork) ladder_h(st, part, pcap);
+  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], st));
   if (bf3) {
-    const Split wb = split_of(ctx->wb, n2p, v * v);
-    qf::launch_gemm_nt_bf16x3(wb.hi, wb.lo, tb.hi, tb.lo, P<double>(ctx->L), npair, o * o, kp, 1.0,
-                              part, pcap, st);
-    if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], st));
     qf::launch_gemm_nt_bf16x3(wyb_rows.hi, wyb_rows.lo, tb.hi, tb.lo, P<double>(ctx->LY), npo,
                               o * o, kp, 1.0, part, pcap, st);
   } else if (mixed) {
-    qf::launch_gemm_nt_f32(P<float>(ctx->w32), P<float>(ctx->t2_32), P<double>(ctx->L), npair,
-                           o * o, v * v, 1.0, part, pcap, st);
-    if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], st));
     qf::launch_gemm_nt_f32(P<float>(ctx->wy32), P<float>(ctx->t2_32), P<double>(ctx->LY), npo,
                            o * o, v * v, 1.0, part, pcap, st);
   } else {
-    qf::launch_gemm_nt_f64(P<double>(ctx->W), t2, P<double>(ctx->L), npair, o * o, v * v, 1.0,
-                           part, pcap, st);
-    if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[2], st));
     qf::launch_gemm_nt_f64(P<double>(ctx->wy), t2, P<double>(ctx->LY), npo, o * o, v * v, 1.0,
                            part, pcap, st);
   }
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[3], st));
   if (bf3) {
-    const Split ta = split_of(ctx->rtab, ov, (int)(2 * ov)), t22 = split_of(ctx->rt22b, ov, (int)ov);
     const Split ay = split_of(ctx->rab_y, n2, (int)(2 * ov));
     const Split a22y = split_of(ctx->r22b_y, n2, (int)ov);
-    qf::launch_pack_ring_T_bf16(t2, o, v, ta.hi, ta.lo, t22.hi, t22.lo, st);
     qf::launch_pack_ring_A_bf16(P<double>(ctx->y2), n, o, ay.hi, ay.lo, a22y.hi, a22y.lo, st);
   } else if (mixed) {
-    qf::launch_pack_ring_T(t2, o, v, P<float>(ctx->rta32), P<float>(ctx->rt22_32), st);
     qf::launch_pack_ring_A(P<double>(ctx->y2), n, o, P<float>(ctx->ra32_y),
                            P<float>(ctx->r22_32_y), st);
   } else {
-    qf::launch_pack_ring_T(t2, o, v, P<double>(ctx->rta), P<double>(ctx->rt22), st);
     qf::launch_pack_ring_A(P<double>(ctx->y2), n, o, P<double>(ctx->ra_y), P<double>(ctx->r22_y),
                            st);
   }
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[4], st));
+  if (!fork) rings_h(st, part, pcap);
   if (bf3) {
     const int ka = qf::bf16_pad((int)(2 * ov)), k22 = qf::bf16_pad((int)ov);
     const Split ta = split_of(ctx->rtab, ov, (int)(2 * ov)), t22 = split_of(ctx->rt22b, ov, (int)ov);
-    const Split ah = split_of(ctx->rab_h, n2, (int)(2 * ov)), a22h = split_of(ctx->r22b_h, n2, (int)ov);
     const Split ay = split_of(ctx->rab_y, n2, (int)(2 * ov)), a22y = split_of(ctx->r22b_y, n2, (int)ov);
-    qf::launch_gemm_nt_bf16x3(ah.hi, ah.lo, ta.hi, ta.lo, P<double>(ctx->ga_h), (int)n2, (int)ov,
-                              ka, 1.0, part, pcap, st);
-    qf::launch_gemm_nt_bf16x3(a22h.hi, a22h.lo, t22.hi, t22.lo, P<double>(ctx->g22_h), (int)n2,
-                              (int)ov, k22, 1.0, part, pcap, st);
     qf::launch_gemm_nt_bf16x3(ay.hi, ay.lo, ta.hi, ta.lo, P<double>(ctx->ga_y), (int)n2, (int)ov,
                               ka, 1.0, part, pcap, st);
     qf::launch_gemm_nt_bf16x3(a22y.hi, a22y.lo, t22.hi, t22.lo, P<double>(ctx->g22_y), (int)n2,
@@ -481,19 +526,11 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   } else if (mixed) {
     const float* ta = P<float>(ctx->rta32);
     const float* t22 = P<float>(ctx->rt22_32);
-    qf::launch_gemm_nt_f32(P<float>(ctx->ra32_h), ta, P<double>(ctx->ga_h), (int)n2, (int)ov,
-                           (int)(2 * ov), 1.0, part, pcap, st);
-    qf::launch_gemm_nt_f32(P<float>(ctx->r22_32_h), t22, P<double>(ctx->g22_h), (int)n2, (int)ov,
-                           (int)ov, 1.0, part, pcap, st);
     qf::launch_gemm_nt_f32(P<float>(ctx->ra32_y), ta, P<double>(ctx->ga_y), (int)n2, (int)ov,
                            (int)(2 * ov), 1.0, part, pcap, st);
     qf::launch_gemm_nt_f32(P<float>(ctx->r22_32_y), t22, P<double>(ctx->g22_y), (int)n2, (int)ov,
                            (int)ov, 1.0, part, pcap, st);
   } else {
-    qf::launch_gemm_nt_f64(P<double>(ctx->ra_h), P<double>(ctx->rta), P<double>(ctx->ga_h),
-                           (int)n2, (int)ov, (int)(2 * ov), 1.0, part, pcap, st);
-    qf::launch_gemm_nt_f64(P<double>(ctx->r22_h), P<double>(ctx->rt22), P<double>(ctx->g22_h),
-                           (int)n2, (int)ov, (int)ov, 1.0, part, pcap, st);
     qf::launch_gemm_nt_f64(P<double>(ctx->ra_y), P<double>(ctx->rta), P<double>(ctx->ga_y),
                            (int)n2, (int)ov, (int)(2 * ov), 1.0, part, pcap, st);
     qf::launch_gemm_nt_f64(P<double>(ctx->r22_y), P<double>(ctx->rt22), P<double>(ctx->g22_y),
@@ -529,6 +566,7 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
   // Hamiltonians evaluate theirs in k_heff_z)
   qf::launch_z_vvoo(P<double>(ctx->V), P<double>(ctx->y2), t1, n, o, P<double>(ctx->zv),
                     P<double>(ctx->zo), st);
+  if (fork) QF_HIP(hipStreamWaitEvent(st, ctx->join_ev, 0));   // H_N's contractions
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -562,6 +600,12 @@ int qflow_create(qflow_ctx** out, int device, void* hip_stream) {
       qflow_destroy(ctx);
       return QFLOW_E_DEVICE;
     }
+  if (hipStreamCreateWithFlags(&ctx->stream2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess) {
+    qflow_destroy(ctx);
+    return QFLOW_E_DEVICE;
+  }
   int lds_limit = 0;
   if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
           hipSuccess &&
@@ -597,10 +641,11 @@ int qflow_destroy(qflow_ctx* ctx) {
   if (!ctx) return QFLOW_OK;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->stream2) (void)hipStreamSynchronize(ctx->stream2);
   DevBuf* bufs[] = {&ctx->ra_h,   &ctx->r22_h,    &ctx->ra_y,   &ctx->r22_y,    &ctx->rta,
                     &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
                     &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
-                    &ctx->gpart,  &ctx->zv,       &ctx->zo,      &ctx->zc,     &ctx->xp,     &ctx->mp,     &ctx->dtpart,
+                    &ctx->gpart,  &ctx->gpart2, &ctx->zv,       &ctx->zo,      &ctx->zc,     &ctx->xp,     &ctx->mp,     &ctx->dtpart,
                     &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->sq,       &ctx->sp_f,     &ctx->sq_f,     &ctx->fs1,
                     &ctx->c1h,
                     &ctx->c1y,    &ctx->lo_t,     &ctx->lo_xh,  &ctx->lo_xy,    &ctx->lo_h,
@@ -623,6 +668,9 @@ int qflow_destroy(qflow_ctx* ctx) {
   for (auto& ev : ctx->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  if (ctx->stream2) (void)hipStreamDestroy(ctx->stream2);
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
   delete ctx;
   return QFLOW_OK;
 }
@@ -689,6 +737,7 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->gpart,
                 sizeof(double) * std::max({8 * n2 * o * o, (size_t)qf::kMaxSplits * n * v,
                                            2 * (size_t)((v + 7) / 8) * n2})));
+  QF_TRY(ensure(ctx, ctx->gpart2, sizeof(double) * 8 * n2 * o * o));   // H_N's ladder slices
   QF_TRY(ensure(ctx, ctx->zv, sizeof(double) * o * o * v * v));
   QF_TRY(ensure(ctx, ctx->zo, sizeof(double) * o * o * v * v));
   // Yg's two-body part, its ladder rows and LY vanish on fixed
