@@ -276,6 +276,8 @@ __global__ __launch_bounds__(BLK, (PART < 2 && BLK == 256) ? 7 : 1) void k_heff_
 // 16-byte loads) and feeds them to W MFMAs, whose k slots then hold
 // t = t0 + W*kq + w; the sigma1 operand follows the same order.
 // Dynamic LDS: sigma1 rows [NA][np] (np = n rounded up to 4W) and Z [NA][NA^3].
+// With zs the block writes the negated sum to zs[blockIdx.x][NA^4] instead
+// (k_heff_cas adds it), so that it may run beside the element kernels.
 template <int NA, int W>
 __global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
                                                 const double* __restrict__ Xy,
@@ -283,7 +285,7 @@ __global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
                                                 const SpaceDev* __restrict__ spaces,
                                                 const int32_t* __restrict__ idx,
                                                 const int64_t* __restrict__ heff_off, int n,
-                                                int o, double* heff) {
+                                                int o, double* heff, double* zs) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   typedef double dw __attribute__((ext_vector_type(W)));
   constexpr int N2 = NA * NA, N3 = N2 * NA, NT = (N3 + 15) / 16, NO = NA / 2;
@@ -360,10 +362,15 @@ __global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
   }
   __syncthreads();
   double* slot = heff + heff_off[k] + 1 + N2;
+  double* zk = zs ? zs + (size_t)blockIdx.x * (N2 * N2) : nullptr;
   for (int e = threadIdx.x; e < N2 * N2; e += blockDim.x) {
     const int a = e / N3, b = e / N2 % NA, c = e / NA % NA, d = e % NA;
-    slot[e] -= Z[a * N3 + (b * NA + c) * NA + d] + Z[b * N3 + (a * NA + d) * NA + c] +
-               Z[c * N3 + (d * NA + a) * NA + b] + Z[d * N3 + (c * NA + b) * NA + a];
+    const double z = Z[a * N3 + (b * NA + c) * NA + d] + Z[b * N3 + (a * NA + d) * NA + c] +
+                     Z[c * N3 + (d * NA + a) * NA + b] + Z[d * N3 + (c * NA + b) * NA + a];
+    if (zk)
+      zk[e] = -z;
+    else
+      slot[e] -= z;
   }
 }
 
@@ -381,6 +388,8 @@ __global__ __launch_bounds__(256) void k_heff_z(const double* __restrict__ Xh,
 // With mpd (the dense form, for large space counts) M is read from
 // mpd[tri(p,q)][(r,s)] = sum_{t,u occ} X(p,q,t,u) t2[t,u,r,s] (rows p <= q;
 // M(q,p,s,r) = M(p,q,r,s) by the pair symmetry of X and t2) instead.
+// With zs the block adds its part to zs[blockIdx.x][NA^4] (writes it when
+// zs_init, i.e. when no k_heff_z wrote there first) instead of the slot.
 template <int NA>
 __global__ __launch_bounds__(256) void k_heff_pp(const double* __restrict__ Xh,
                                                  const double* __restrict__ Xy,
@@ -389,7 +398,7 @@ __global__ __launch_bounds__(256) void k_heff_pp(const double* __restrict__ Xh,
                                                  const SpaceDev* __restrict__ spaces,
                                                  const int32_t* __restrict__ idx,
                                                  const int64_t* __restrict__ heff_off, int n,
-                                                 int o, double* heff) {
+                                                 int o, double* heff, double* zs, int zs_init) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   constexpr int NO = NA / 2, NV = NA - NO, N2 = NA * NA, NR = NV * NV, NM = N2 * NR;
   constexpr int kChunk = 64, NT = (N2 + 15) / 16;
@@ -452,6 +461,7 @@ __global__ __launch_bounds__(256) void k_heff_pp(const double* __restrict__ Xh,
   }
   __syncthreads();
   double* slot = heff + heff_off[k] + 1 + N2;
+  double* zk = zs ? zs + (size_t)blockIdx.x * (N2 * N2) : nullptr;
   for (int e = threadIdx.x; e < N2 * N2; e += blockDim.x) {
     const int a = e / (N2 * NA), b = e / N2 % NA, c = e / NA % NA, d = e % NA;
     double x = 0.0;
@@ -459,7 +469,12 @@ __global__ __launch_bounds__(256) void k_heff_pp(const double* __restrict__ Xh,
       x += M[(a * NA + b) * NR + (c - NO) * NV + (d - NO)];
     if (a >= NO && b >= NO && !(c < NO && d < NO))
       x += M[(c * NA + d) * NR + (a - NO) * NV + (b - NO)];
-    slot[e] += x;
+    if (!zk)
+      slot[e] += x;
+    else if (zs_init)
+      zk[e] = x;
+    else
+      zk[e] += x;
   }
 }
 
@@ -512,19 +527,35 @@ __global__ __launch_bounds__(512) void k_heff_low(const SpaceDev* __restrict__ s
   }
 }
 
-// Rewrite each slot from normal order to CAS form:
+// The two-body parts that k_heff_z and k_heff_pp leave in a buffer of their
+// own: class c's block i at p + off[c] + i * na^4, its spaces the ones at
+// [first[c], first[c + 1]) of the list (p NULL: none).
+struct ZSum {
+  const double* p;
+  long long off[3];
+  int first[3];
+};
+
+// Rewrite each slot from normal order to CAS form (after adding the ZSum
+// part to the two-body block):
 //   Ec = x0 - 2 sum_k x1_kk + sum_kl (2 x2_klkl - x2_kllk)
 //   h_pq = x1_pq - sum_k (2 x2_pkqk - x2_pkkq),  g(pq|rs) = x2_prqs
 __global__ __launch_bounds__(256) void k_heff_cas(const SpaceDev* __restrict__ spaces,
                                                   const int32_t* __restrict__ idx,
                                                   const int64_t* __restrict__ heff_off,
-                                                  double* heff) {
+                                                  ZSum zsum, double* heff) {
   extern __shared__ double sm[];
   const int k = idx[blockIdx.x];
   const SpaceDev sp = spaces[k];
   const int na = sp.na, ne = sp.nocc, n2 = na * na, n4 = n2 * n2;
   double* slot = heff + heff_off[k];
-  for (int e = threadIdx.x; e < 1 + n2 + n4; e += blockDim.x) sm[e] = slot[e];
+  const double* zk = nullptr;
+  if (zsum.p) {
+    const int c = ne - 2;   // size class: na = 2 nocc
+    zk = zsum.p + zsum.off[c] + (size_t)(blockIdx.x - zsum.first[c]) * n4;
+  }
+  for (int e = threadIdx.x; e < 1 + n2 + n4; e += blockDim.x)
+    sm[e] = zk && e > n2 ? slot[e] + zk[e - 1 - n2] : slot[e];
   __syncthreads();
   const double* x1 = sm + 1;
   const double* x2 = sm + 1 + n2;
@@ -580,14 +611,15 @@ void allow_lds(Kern* kern, size_t bytes) {
 }
 }  // namespace
 
-void launch_heff(const double* f, const double* V, const double* y1, const double* y2,
+hipError_t launch_heff(const double* f, const double* V, const double* y1, const double* y2,
                  const double* L, const double* LY, const RingOps& rings, const double* t1,
                  const double* t2, int n,
                  int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
                  const int32_t* task_table, int task_stride, const int* task_slots,
                  const int32_t* cls_idx, const int* cls_off, int K, int na_max,
                  double* tab, double* fs1, const double* zc, const double* mpd, double* heff,
-                 hipStream_t st) {
+                 hipStream_t st, double* zs, hipStream_t st2, hipEvent_t fork_ev,
+                 hipEvent_t join_ev) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
               rings.zv,   rings.zo,  rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
@@ -596,6 +628,57 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
   g.qf = rings.qf;
   g.fs1 = fs1;
   const int tab_stride = heff_table_stride(na_max);
+  // k_heff_z and k_heff_pp read only the operators, t1, t2 and mpd: with zs
+  // they run on st2 beside the table and element kernels, into zs
+  ZSum zsum{nullptr, {0, 0, 0}, {0, 0, 0}};
+  const bool fork = zs != nullptr;
+  if (fork) {
+    long long acc = 0;
+    for (int c = 0; c < 3; ++c) {
+      const long long na = 2 * (c + 2);
+      zsum.off[c] = acc;
+      zsum.first[c] = cls_off[c];
+      acc += (long long)(cls_off[c + 1] - cls_off[c]) * na * na * na * na;
+    }
+    zsum.p = zs;
+    hipError_t e = hipEventRecord(fork_ev, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st2, fork_ev, 0);
+    if (e != hipSuccess) return e;
+  }
+  // per class: the sigma1 x two-body part (per-space form) and the
+  // occupied-pair ladders, into the slots or (fork) into zs
+  auto z_pp = [&](hipStream_t s) {
+    for (int c = 0; c < 3; ++c) {
+      const int count = cls_off[c + 1] - cls_off[c];
+      if (count <= 0) continue;
+      const int na = 2 * (c + 2);
+      const int32_t* idx = cls_idx + cls_off[c];
+      double* zsc = fork ? zs + zsum.off[c] : nullptr;
+      const int init = zc != nullptr;   // no k_heff_z wrote zs first
+      // W = 2 (16-byte row loads) needs even n: rows then start 16-byte
+      // aligned and a lane's pair of t never straddles n
+      const bool w2 = n % 2 == 0;
+      const size_t zlds = (size_t)(na * ((n + 7) & ~7) + na * na * na * na) * sizeof(double);
+      if (c == 0) {
+        if (!zc && w2) k_heff_z<4, 2><<<count, 256, zlds, s>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff, zsc);
+        if (!zc && !w2) k_heff_z<4, 1><<<count, 256, zlds, s>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff, zsc);
+        k_heff_pp<4><<<count, 256, 0, s>>>(V, y2, t2, mpd, spaces, idx, heff_off, n, o, heff, zsc, init);
+      } else if (c == 1) {
+        if (!zc && w2) k_heff_z<6, 2><<<count, 256, zlds, s>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff, zsc);
+        if (!zc && !w2) k_heff_z<6, 1><<<count, 256, zlds, s>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff, zsc);
+        k_heff_pp<6><<<count, 256, 0, s>>>(V, y2, t2, mpd, spaces, idx, heff_off, n, o, heff, zsc, init);
+      } else {
+        if (!zc && w2) k_heff_z<8, 2><<<count, 256, zlds, s>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff, zsc);
+        if (!zc && !w2) k_heff_z<8, 1><<<count, 256, zlds, s>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff, zsc);
+        k_heff_pp<8><<<count, 256, 0, s>>>(V, y2, t2, mpd, spaces, idx, heff_off, n, o, heff, zsc, init);
+      }
+    }
+  };
+  if (fork) {
+    z_pp(st2);
+    const hipError_t e = hipEventRecord(join_ev, st2);
+    if (e != hipSuccess) return e;
+  }
   k_fs1<<<(2 * n * n + kBlock - 1) / kBlock, kBlock, 0, st>>>(f, t1, n, o, fs1);
   for (int c = 0; c < 3; ++c) {
     const int count = cls_off[c + 1] - cls_off[c];
@@ -664,31 +747,25 @@ void launch_heff(const double* f, const double* V, const double* y1, const doubl
     int s1, s2, s3, s4;
     const size_t lds = (size_t)mark_sizes(na, &s1, &s2, &s3, &s4) * sizeof(double);
     const int32_t* idx = cls_idx + cls_off[c];
-    // W = 2 (16-byte row loads) needs even n: rows then start 16-byte aligned
-    // and a lane's pair of t never straddles n
-    const bool w2 = n % 2 == 0;
-    const size_t zlds = (size_t)(na * ((n + 7) & ~7) + na * na * na * na) * sizeof(double);
     if (c == 0) {
       k_heff_low<4><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
-      if (!zc && w2) k_heff_z<4, 2><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
-      if (!zc && !w2) k_heff_z<4, 1><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
-      k_heff_pp<4><<<count, 256, 0, st>>>(V, y2, t2, mpd, spaces, idx, heff_off, n, o, heff);
     } else if (c == 1) {
       k_heff_low<6><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
-      if (!zc && w2) k_heff_z<6, 2><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
-      if (!zc && !w2) k_heff_z<6, 1><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
-      k_heff_pp<6><<<count, 256, 0, st>>>(V, y2, t2, mpd, spaces, idx, heff_off, n, o, heff);
     } else {
       allow_lds(&k_heff_low<8>, lds);
       k_heff_low<8><<<count, 512, lds, st>>>(spaces, idx, heff_off, tab, tab_stride, n, o, heff);
-      if (!zc && w2) k_heff_z<8, 2><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
-      if (!zc && !w2) k_heff_z<8, 1><<<count, 256, zlds, st>>>(V, y2, t1, spaces, idx, heff_off, n, o, heff);
-      k_heff_pp<8><<<count, 256, 0, st>>>(V, y2, t2, mpd, spaces, idx, heff_off, n, o, heff);
     }
+  }
+  if (fork) {
+    const hipError_t e = hipStreamWaitEvent(st, join_ev, 0);
+    if (e != hipSuccess) return e;
+  } else {
+    z_pp(st);
   }
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
   const size_t lds = (size_t)tasks * sizeof(double);
-  k_heff_cas<<<K, kBlock, lds, st>>>(spaces, cls_idx, heff_off, heff);
+  k_heff_cas<<<K, kBlock, lds, st>>>(spaces, cls_idx, heff_off, zsum, heff);
+  return hipSuccess;
 }
 
 }  // namespace qf

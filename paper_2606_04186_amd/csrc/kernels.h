@@ -119,15 +119,20 @@ void launch_residual(const double* f, const double* V, const double* y1, const d
 // Z = sigma1 (H_N + Yg/2) (launch_sigma1_x), read by the element kernels; when
 // NULL, k_heff_z adds that part per space from the rows of H_N and Yg.
 // mpd: the dense occupied-pair ladder table (launch_pack_x_pairs), or NULL
-// for the per-space form.  fs1: scratch of 2 n^2 doubles.
-void launch_heff(const double* f, const double* V, const double* y1, const double* y2,
-                 const double* L, const double* LY, const RingOps& rings, const double* t1,
-                 const double* t2, int n,
-                 int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
-                 const int32_t* task_table, int task_stride, const int* task_slots,
-                 const int32_t* cls_idx, const int* cls_off, int K, int na_max,
-                 double* tab, double* fs1, const double* zc, const double* mpd, double* heff,
-                 hipStream_t st);
+// for the per-space form.  fs1: scratch of 2 n^2 doubles.  zs (or NULL):
+// sum over the classes of count_c * na_c^4 doubles; with it the per-space
+// sigma1 x two-body and occupied-pair ladder kernels run on st2 (forked from
+// st by fork_ev, joined back by join_ev before the CAS rewrite) into zs.
+// Returns the first error of the event calls.
+hipError_t launch_heff(const double* f, const double* V, const double* y1, const double* y2,
+                       const double* L, const double* LY, const RingOps& rings, const double* t1,
+                       const double* t2, int n,
+                       int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
+                       const int32_t* task_table, int task_stride, const int* task_slots,
+                       const int32_t* cls_idx, const int* cls_off, int K, int na_max,
+                       double* tab, double* fs1, const double* zc, const double* mpd, double* heff,
+                       hipStream_t st, double* zs, hipStream_t st2, hipEvent_t fork_ev,
+                       hipEvent_t join_ev);
 // Operand of the dense occupied-pair ladder (k_heff.hip): xp[tri(p,q)][(t,u)]
 // = (H_N + Yg/2)(p,q,t,u), p <= q, t, u occupied; n(n+1)/2 x o^2 doubles.  The
 // ladder mpd = xp T^T with T[(a,b)][(t,u)] = t2[t,u,a,b] (launch_pack_t2_vvoo).

@@ -49,6 +49,9 @@ struct qflow_ctx {
   // into `stream` by events; its split-K slices go to gpart2
   hipStream_t stream2 = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // the same for the per-space Hamiltonians: their sigma1 x two-body and
+  // occupied-pair ladder parts run on stream2 into zsum
+  hipEvent_t fork2_ev = nullptr, join2_ev = nullptr;
   std::string err;
   // problem
   int n = 0, o = 0, v = 0;
@@ -68,6 +71,7 @@ struct qflow_ctx {
   DevBuf zv, zo;   // sigma1 x two-body pieces of the residual
   DevBuf zc;       // dense sigma1 (H_N + Yg/2), n^4, when some call takes that form
   DevBuf xp, mp;   // dense occupied-pair ladder: its operand and the table (same form)
+  DevBuf zsum;     // per space na^4: those parts of H_eff made on stream2
   int z_mode = QFLOW_Z_AUTO;
   DevBuf dtpart;   // per-block maxima of |t_new - t_old|
   // [G, sigma_2]_2 scratch (packed one-body, transposed t2, GEMM outputs)
@@ -216,6 +220,16 @@ int ensure_zc(qflow_ctx* ctx) {
 
 int upload_space_list(qflow_ctx* ctx, int32_t K, const qflow_space* spaces);
 
+// doubles of the stream2 part buffer for the class lists cls_off
+size_t zsum_doubles(const int* cls_off) {
+  size_t d = 0;
+  for (int c = 0; c < 3; ++c) {
+    const size_t na = 2 * (c + 2);
+    d += (size_t)(cls_off[c + 1] - cls_off[c]) * na * na * na * na;
+  }
+  return d;
+}
+
 int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   QF_TRY(upload_space_list(ctx, K, spaces));
   return ensure_zc(ctx);   // outside any graph capture
@@ -266,6 +280,7 @@ int upload_space_list(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   QF_TRY(ensure(ctx, ctx->work_off, sizeof(int64_t) * (K + 1)));
   QF_TRY(ensure(ctx, ctx->work, sizeof(double) * std::max<int64_t>(ctx->h_work_off[K], 1)));
   QF_TRY(ensure(ctx, ctx->heff, sizeof(double) * std::max<int64_t>(ctx->h_heff_off[K], 1)));
+  QF_TRY(ensure(ctx, ctx->zsum, sizeof(double) * std::max<size_t>(zsum_doubles(ctx->cls_off), 1)));
   QF_TRY(ensure(ctx, ctx->amp, sizeof(double) * std::max<int64_t>(ctx->h_amp_off[K], 1)));
   QF_TRY(ensure(ctx, ctx->ci_off, sizeof(int64_t) * (K + 1)));
   QF_TRY(ensure(ctx, ctx->ci, sizeof(double) * std::max<int64_t>(ctx->h_ci_off[K], 1)));
@@ -602,7 +617,9 @@ int qflow_create(qflow_ctx** out, int device, void* hip_stream) {
     }
   if (hipStreamCreateWithFlags(&ctx->stream2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->fork2_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->join2_ev, hipEventDisableTiming) != hipSuccess) {
     qflow_destroy(ctx);
     return QFLOW_E_DEVICE;
   }
@@ -645,7 +662,7 @@ int qflow_destroy(qflow_ctx* ctx) {
   DevBuf* bufs[] = {&ctx->ra_h,   &ctx->r22_h,    &ctx->ra_y,   &ctx->r22_y,    &ctx->rta,
                     &ctx->rt22,   &ctx->ga_h,     &ctx->g22_h,  &ctx->ga_y,     &ctx->g22_y,
                     &ctx->jh,     &ctx->jy,       &ctx->ja_h,   &ctx->ja_y,     &ctx->jb,
-                    &ctx->gpart,  &ctx->gpart2, &ctx->zv,       &ctx->zo,      &ctx->zc,     &ctx->xp,     &ctx->mp,     &ctx->dtpart,
+                    &ctx->gpart,  &ctx->gpart2, &ctx->zv,       &ctx->zo,      &ctx->zc,     &ctx->xp,     &ctx->mp,     &ctx->zsum,     &ctx->dtpart,
                     &ctx->a12,    &ctx->t2T,      &ctx->sp,     &ctx->sq,       &ctx->sp_f,     &ctx->sq_f,     &ctx->fs1,
                     &ctx->c1h,
                     &ctx->c1y,    &ctx->lo_t,     &ctx->lo_xh,  &ctx->lo_xy,    &ctx->lo_h,
@@ -671,6 +688,8 @@ int qflow_destroy(qflow_ctx* ctx) {
   if (ctx->stream2) (void)hipStreamDestroy(ctx->stream2);
   if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+  if (ctx->fork2_ev) (void)hipEventDestroy(ctx->fork2_ev);
+  if (ctx->join2_ev) (void)hipEventDestroy(ctx->join2_ev);
   delete ctx;
   return QFLOW_OK;
 }
@@ -888,14 +907,19 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
                            (int)npair, (int)vv, (int)oo, 1.0, P<double>(ctx->gpart),
                            ctx->gpart.bytes / sizeof(double), ctx->stream);
   }
+  // the stream2 parts need a zsum block per space of the lists
+  const bool fork = ctx->zsum.bytes >= sizeof(double) * zsum_doubles(cls_off);
   if (K > 0)
-    qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1), P<double>(ctx->y2),
-                    P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx), t1, t2, ctx->n, ctx->o,
-                    P<double>(ctx->scal), P<SpaceDev>(ctx->spaces), heff_off_dev,
-                    P<int32_t>(ctx->tasks), qf::kTaskStride, ctx->task_slots,
-                    idx, cls_off, K, ctx->na_max, P<double>(ctx->mtab), P<double>(ctx->fs1),
-                    dense ? P<double>(ctx->zc) : nullptr, dense ? P<double>(ctx->mp) : nullptr,
-                    heff, ctx->stream);
+    QF_HIP(qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
+                           P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY),
+                           rings_of(ctx), t1, t2, ctx->n, ctx->o, P<double>(ctx->scal),
+                           P<SpaceDev>(ctx->spaces), heff_off_dev, P<int32_t>(ctx->tasks),
+                           qf::kTaskStride, ctx->task_slots, idx, cls_off, K, ctx->na_max,
+                           P<double>(ctx->mtab), P<double>(ctx->fs1),
+                           dense ? P<double>(ctx->zc) : nullptr,
+                           dense ? P<double>(ctx->mp) : nullptr, heff, ctx->stream,
+                           fork ? P<double>(ctx->zsum) : nullptr, ctx->stream2, ctx->fork2_ev,
+                           ctx->join2_ev));
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
