@@ -325,23 +325,34 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16x3(
     }
     __syncthreads();
     if (k0 + kBK3 < ke) load(k0 + kBK3);
-    bf8 ah[TM], al[TM];
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      const int o = (wm * 16 * TM + i * 16 + lane % 16) * kLD3 + 8 * (lane / 16);
-      ah[i] = *reinterpret_cast<const bf8*>(Ash + o);
-      al[i] = *reinterpret_cast<const bf8*>(Asl + o);
-    }
+    // all B fragments of the step held, A's streamed one row tile ahead, so
+    // that each A read has the previous tile's 3 TN MFMAs to land behind
+    bf8 bh[TN], bl[TN];
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int o = (wn * 16 * TN + j * 16 + lane % 16) * kLD3 + 8 * (lane / 16);
-      const bf8 bh = *reinterpret_cast<const bf8*>(Bsh + o);
-      const bf8 bl = *reinterpret_cast<const bf8*>(Bsl + o);
+      bh[j] = *reinterpret_cast<const bf8*>(Bsh + o);
+      bl[j] = *reinterpret_cast<const bf8*>(Bsl + o);
+    }
+    const int oa = (wm * 16 * TM + lane % 16) * kLD3 + 8 * (lane / 16);
+    bf8 ah = *reinterpret_cast<const bf8*>(Ash + oa);
+    bf8 al = *reinterpret_cast<const bf8*>(Asl + oa);
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+    for (int i = 0; i < TM; ++i) {
+      bf8 nh, nl;
+      if (i + 1 < TM) {
+        nh = *reinterpret_cast<const bf8*>(Ash + oa + (i + 1) * 16 * kLD3);
+        nl = *reinterpret_cast<const bf8*>(Asl + oa + (i + 1) * 16 * kLD3);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+      }
+      if (i + 1 < TM) {
+        ah = nh;
+        al = nl;
       }
     }
     if (++step == 2) {
