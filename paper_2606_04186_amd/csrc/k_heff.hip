@@ -629,10 +629,11 @@ hipError_t launch_heff(const double* f, const double* V, const double* y1, const
   g.fs1 = fs1;
   const int tab_stride = heff_table_stride(na_max);
   // k_heff_z and k_heff_pp read only the operators, t1, t2 and mpd: with zs
-  // they run on st2 beside the table and element kernels, into zs
+  // they write there (k_heff_cas adds it), on st2 when given, beside the
+  // table and element kernels
   ZSum zsum{nullptr, {0, 0, 0}, {0, 0, 0}};
-  const bool fork = zs != nullptr;
-  if (fork) {
+  const bool use_zs = zs != nullptr, fork = use_zs && st2 != nullptr;
+  if (use_zs) {
     long long acc = 0;
     for (int c = 0; c < 3; ++c) {
       const long long na = 2 * (c + 2);
@@ -641,19 +642,21 @@ hipError_t launch_heff(const double* f, const double* V, const double* y1, const
       acc += (long long)(cls_off[c + 1] - cls_off[c]) * na * na * na * na;
     }
     zsum.p = zs;
+  }
+  if (fork) {
     hipError_t e = hipEventRecord(fork_ev, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(st2, fork_ev, 0);
     if (e != hipSuccess) return e;
   }
   // per class: the sigma1 x two-body part (per-space form) and the
-  // occupied-pair ladders, into the slots or (fork) into zs
+  // occupied-pair ladders, into zs when given, else into the slots
   auto z_pp = [&](hipStream_t s) {
     for (int c = 0; c < 3; ++c) {
       const int count = cls_off[c + 1] - cls_off[c];
       if (count <= 0) continue;
       const int na = 2 * (c + 2);
       const int32_t* idx = cls_idx + cls_off[c];
-      double* zsc = fork ? zs + zsum.off[c] : nullptr;
+      double* zsc = use_zs ? zs + zsum.off[c] : nullptr;
       const int init = zc != nullptr;   // no k_heff_z wrote zs first
       // W = 2 (16-byte row loads) needs even n: rows then start 16-byte
       // aligned and a lane's pair of t never straddles n
@@ -678,6 +681,8 @@ hipError_t launch_heff(const double* f, const double* V, const double* y1, const
     z_pp(st2);
     const hipError_t e = hipEventRecord(join_ev, st2);
     if (e != hipSuccess) return e;
+  } else if (use_zs) {
+    z_pp(st);
   }
   k_fs1<<<(2 * n * n + kBlock - 1) / kBlock, kBlock, 0, st>>>(f, t1, n, o, fs1);
   for (int c = 0; c < 3; ++c) {
@@ -759,7 +764,7 @@ hipError_t launch_heff(const double* f, const double* V, const double* y1, const
   if (fork) {
     const hipError_t e = hipStreamWaitEvent(st, join_ev, 0);
     if (e != hipSuccess) return e;
-  } else {
+  } else if (!use_zs) {
     z_pp(st);
   }
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;

@@ -121,8 +121,9 @@ void launch_residual(const double* f, const double* V, const double* y1, const d
 // mpd: the dense occupied-pair ladder table (launch_pack_x_pairs), or NULL
 // for the per-space form.  fs1: scratch of 2 n^2 doubles.  zs (or NULL):
 // sum over the classes of count_c * na_c^4 doubles; with it the per-space
-// sigma1 x two-body and occupied-pair ladder kernels run on st2 (forked from
-// st by fork_ev, joined back by join_ev before the CAS rewrite) into zs.
+// sigma1 x two-body and occupied-pair ladder kernels write into zs, which
+// the CAS rewrite adds, and with st2 (or NULL) they run there (forked from
+// st by fork_ev, joined back by join_ev before the CAS rewrite).
 // Returns the first error of the event calls.
 hipError_t launch_heff(const double* f, const double* V, const double* y1, const double* y2,
                        const double* L, const double* LY, const RingOps& rings, const double* t1,

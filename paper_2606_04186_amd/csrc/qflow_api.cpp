@@ -907,8 +907,10 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
                            (int)npair, (int)vv, (int)oo, 1.0, P<double>(ctx->gpart),
                            ctx->gpart.bytes / sizeof(double), ctx->stream);
   }
-  // the stream2 parts need a zsum block per space of the lists
-  const bool fork = ctx->zsum.bytes >= sizeof(double) * zsum_doubles(cls_off);
+  // the zsum parts need a block per space of the lists; they run on stream2
+  // except in the stage-timed eager step, which keeps one stream (as in
+  // prepare) and the same arithmetic
+  const bool use_zs = ctx->zsum.bytes >= sizeof(double) * zsum_doubles(cls_off);
   if (K > 0)
     QF_HIP(qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
                            P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY),
@@ -918,8 +920,8 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
                            P<double>(ctx->mtab), P<double>(ctx->fs1),
                            dense ? P<double>(ctx->zc) : nullptr,
                            dense ? P<double>(ctx->mp) : nullptr, heff, ctx->stream,
-                           fork ? P<double>(ctx->zsum) : nullptr, ctx->stream2, ctx->fork2_ev,
-                           ctx->join2_ev));
+                           use_zs ? P<double>(ctx->zsum) : nullptr,
+                           ctx->timed ? nullptr : ctx->stream2, ctx->fork2_ev, ctx->join2_ev));
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
