@@ -49,6 +49,7 @@ struct qflow_ctx {
   // into `stream` by events; its split-K slices go to gpart2
   hipStream_t stream2 = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  hipEvent_t y_ev = nullptr;   // Yg's two-body part written (J, Lo, Z may start)
   // the same for the per-space Hamiltonians: their sigma1 x two-body and
   // occupied-pair ladder parts run on stream2 into zsum
   hipEvent_t fork2_ev = nullptr, join2_ev = nullptr;
@@ -473,6 +474,40 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
                              (int)n2, (int)ov, (int)ov, 1.0, pp, pc, s);
     }
   };
+  // J, Lo and the residual's vvoo Z pieces read Yg's two-body part (and t2,
+  // t1) but nothing that Yg's ladder and rings write
+  auto tail_y = [&](hipStream_t s, double* pp, size_t pc) -> int {
+    // one-body ring terms J1, J2 of H_N and Yg
+    const size_t kj = (size_t)o * o * v;
+    double* b1 = P<double>(ctx->jb);
+    double* b2 = b1 + (size_t)v * kj;
+    qf::launch_pack_j_B(t2, o, v, b1, b2, s);
+    qf::launch_pack_j_A(P<double>(ctx->y2), n, o, P<double>(ctx->ja_y),
+                        P<double>(ctx->ja_y) + (size_t)n * kj, s);
+    {   // J1, J2 of H_N and of Yg: four products of one shape in one launch
+      const double* ja[4] = {P<double>(ctx->ja_h), P<double>(ctx->ja_h) + (size_t)n * kj,
+                             P<double>(ctx->ja_y), P<double>(ctx->ja_y) + (size_t)n * kj};
+      const double* jbs[4] = {b1, b2, b1, b2};
+      double* jc[4] = {P<double>(ctx->jh), P<double>(ctx->jh) + (size_t)n * v, P<double>(ctx->jy),
+                       P<double>(ctx->jy) + (size_t)n * v};
+      (void)qf::launch_gemm_nt_f64_batch(ja, jbs, jc, 4, n, v, (int)kj, -1.0, pp, pc, s);
+    }
+    // occupied-occupied ladders Lo of H_N and Yg
+    qf::launch_pack_t2_vvoo(t2, o, v, P<double>(ctx->lo_t), s);
+    qf::launch_pack_x_oooo(P<double>(ctx->y2), n, o, P<double>(ctx->lo_xy), s);
+    {
+      const double* la[2] = {P<double>(ctx->lo_t), P<double>(ctx->lo_t)};
+      const double* lb[2] = {P<double>(ctx->lo_xh), P<double>(ctx->lo_xy)};
+      double* lc[2] = {P<double>(ctx->lo_h), P<double>(ctx->lo_y)};
+      (void)qf::launch_gemm_nt_f64_batch(la, lb, lc, 2, v * v, o * o, o * o, 1.0, pp, pc, s);
+    }
+    if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[6], s));
+    // sigma1 x two-body pieces of H_N + Yg/2 for the residual (the per-space
+    // Hamiltonians evaluate theirs in k_heff_z)
+    qf::launch_z_vvoo(P<double>(ctx->V), P<double>(ctx->y2), t1, n, o, P<double>(ctx->zv),
+                      P<double>(ctx->zo), s);
+    return QFLOW_OK;
+  };
   const bool fork = !ctx->timed;
   if (fork) {
     hipStream_t sh = ctx->stream2;
@@ -482,7 +517,6 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
     QF_HIP(hipStreamWaitEvent(sh, ctx->fork_ev, 0));
     ladder_h(sh, ph, pch);
     rings_h(sh, ph, pch);
-    QF_HIP(hipEventRecord(ctx->join_ev, sh));
   }
   // Yg = [F_N, sigma]: one-body and scalar, two-body (+ its ladder slab), and
   // the compact parts of [y1, sigma_2]_2 (the one-body part of Yg against
@@ -498,6 +532,13 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
                     P<double>(ctx->sp_f), P<double>(ctx->sq_f), part, pcap, P<double>(ctx->y2),
                     (mixed || bf3) ? nullptr : P<double>(ctx->wy),
                     mixed ? P<float>(ctx->wy32) : nullptr, wyb_rows.hi, wyb_rows.lo, st);
+  if (fork) {   // Yg's two-body part is complete: J, Lo, Z follow H_N's products on stream2
+    hipStream_t sh = ctx->stream2;
+    QF_HIP(hipEventRecord(ctx->y_ev, st));
+    QF_HIP(hipStreamWaitEvent(sh, ctx->y_ev, 0));
+    QF_TRY(tail_y(sh, P<double>(ctx->gpart2), ctx->gpart2.bytes / sizeof(double)));
+    QF_HIP(hipEventRecord(ctx->join_ev, sh));
+  }
   qf::launch_sigma2(P<double>(ctx->y1), t2, n, o, P<double>(ctx->a12), P<double>(ctx->t2T),
                     false, P<double>(ctx->sp), P<double>(ctx->sq), part, pcap, nullptr, nullptr,
                     nullptr, nullptr, nullptr, st);
@@ -552,36 +593,8 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
                            (int)n2, (int)ov, (int)ov, 1.0, part, pcap, st);
   }
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[5], st));
-  // one-body ring terms J1, J2 of H_N and Yg
-  const size_t kj = (size_t)o * o * v;
-  double* b1 = P<double>(ctx->jb);
-  double* b2 = b1 + (size_t)v * kj;
-  qf::launch_pack_j_B(t2, o, v, b1, b2, st);
-  qf::launch_pack_j_A(P<double>(ctx->y2), n, o, P<double>(ctx->ja_y),
-                      P<double>(ctx->ja_y) + (size_t)n * kj, st);
-  {   // J1, J2 of H_N and of Yg: four products of one shape in one launch
-    const double* ja[4] = {P<double>(ctx->ja_h), P<double>(ctx->ja_h) + (size_t)n * kj,
-                           P<double>(ctx->ja_y), P<double>(ctx->ja_y) + (size_t)n * kj};
-    const double* jbs[4] = {b1, b2, b1, b2};
-    double* jc[4] = {P<double>(ctx->jh), P<double>(ctx->jh) + (size_t)n * v, P<double>(ctx->jy),
-                     P<double>(ctx->jy) + (size_t)n * v};
-    (void)qf::launch_gemm_nt_f64_batch(ja, jbs, jc, 4, n, v, (int)kj, -1.0, part, pcap, st);
-  }
-  // occupied-occupied ladders Lo of H_N and Yg
-  qf::launch_pack_t2_vvoo(t2, o, v, P<double>(ctx->lo_t), st);
-  qf::launch_pack_x_oooo(P<double>(ctx->y2), n, o, P<double>(ctx->lo_xy), st);
-  {
-    const double* la[2] = {P<double>(ctx->lo_t), P<double>(ctx->lo_t)};
-    const double* lb[2] = {P<double>(ctx->lo_xh), P<double>(ctx->lo_xy)};
-    double* lc[2] = {P<double>(ctx->lo_h), P<double>(ctx->lo_y)};
-    (void)qf::launch_gemm_nt_f64_batch(la, lb, lc, 2, v * v, o * o, o * o, 1.0, part, pcap, st);
-  }
-  if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[6], ctx->stream));
-  // sigma1 x two-body pieces of H_N + Yg/2 for the residual (the per-space
-  // Hamiltonians evaluate theirs in k_heff_z)
-  qf::launch_z_vvoo(P<double>(ctx->V), P<double>(ctx->y2), t1, n, o, P<double>(ctx->zv),
-                    P<double>(ctx->zo), st);
-  if (fork) QF_HIP(hipStreamWaitEvent(st, ctx->join_ev, 0));   // H_N's contractions
+  if (!fork) QF_TRY(tail_y(st, part, pcap));
+  if (fork) QF_HIP(hipStreamWaitEvent(st, ctx->join_ev, 0));   // stream2's part
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -618,6 +631,7 @@ int qflow_create(qflow_ctx** out, int device, void* hip_stream) {
   if (hipStreamCreateWithFlags(&ctx->stream2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->y_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->fork2_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->join2_ev, hipEventDisableTiming) != hipSuccess) {
     qflow_destroy(ctx);
@@ -688,6 +702,7 @@ int qflow_destroy(qflow_ctx* ctx) {
   if (ctx->stream2) (void)hipStreamDestroy(ctx->stream2);
   if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+  if (ctx->y_ev) (void)hipEventDestroy(ctx->y_ev);
   if (ctx->fork2_ev) (void)hipEventDestroy(ctx->fork2_ev);
   if (ctx->join2_ev) (void)hipEventDestroy(ctx->join2_ev);
   delete ctx;
@@ -756,7 +771,8 @@ int qflow_load_integrals(qflow_ctx* ctx, int32_t n_orb, int32_t n_occ, const dou
   QF_TRY(ensure(ctx, ctx->gpart,
                 sizeof(double) * std::max({8 * n2 * o * o, (size_t)qf::kMaxSplits * n * v,
                                            2 * (size_t)((v + 7) / 8) * n2})));
-  QF_TRY(ensure(ctx, ctx->gpart2, sizeof(double) * 8 * n2 * o * o));   // H_N's ladder slices
+  // stream2's products take the same split counts as on the main stream
+  QF_TRY(ensure(ctx, ctx->gpart2, ctx->gpart.bytes));
   QF_TRY(ensure(ctx, ctx->zv, sizeof(double) * o * o * v * v));
   QF_TRY(ensure(ctx, ctx->zo, sizeof(double) * o * o * v * v));
   // Yg's two-body part, its ladder rows and LY vanish on fixed
