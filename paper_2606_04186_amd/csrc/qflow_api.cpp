@@ -45,8 +45,9 @@ struct qflow_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  // H_N's contractions (they need only t2) run here beside Yg's, joined back
-  // into `stream` by events; its split-K slices go to gpart2
+  // H_N's contractions (they need only t2), then J, Lo and Z (once Yg's
+  // two-body part is written) run here beside Yg's chain, joined back into
+  // `stream` by events; their split-K slices go to gpart2
   hipStream_t stream2 = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   hipEvent_t y_ev = nullptr;   // Yg's two-body part written (J, Lo, Z may start)
