@@ -612,14 +612,14 @@ void allow_lds(Kern* kern, size_t bytes) {
 }  // namespace
 
 hipError_t launch_heff(const double* f, const double* V, const double* y1, const double* y2,
-                 const double* L, const double* LY, const RingOps& rings, const double* t1,
-                 const double* t2, int n,
-                 int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
-                 const int32_t* task_table, int task_stride, const int* task_slots,
-                 const int32_t* cls_idx, const int* cls_off, int K, int na_max,
-                 double* tab, double* fs1, const double* zc, const double* mpd, double* heff,
-                 hipStream_t st, double* zs, hipStream_t st2, hipEvent_t fork_ev,
-                 hipEvent_t join_ev) {
+                       const double* L, const double* LY, const RingOps& rings, const double* t1,
+                       const double* t2, int n,
+                       int o, const double* scal, const SpaceDev* spaces, const int64_t* heff_off,
+                       const int32_t* task_table, int task_stride, const int* task_slots,
+                       const int32_t* cls_idx, const int* cls_off, int K, int na_max,
+                       double* tab, double* fs1, const double* zc, const double* mpd, double* heff,
+                       hipStream_t st, double* zs, hipStream_t st2, hipEvent_t fork_ev,
+                       hipEvent_t join_ev) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
               rings.zv,   rings.zo,  rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
