@@ -619,7 +619,7 @@ hipError_t launch_heff(const double* f, const double* V, const double* y1, const
                        const int32_t* cls_idx, const int* cls_off, int K, int na_max,
                        double* tab, double* fs1, const double* zc, const double* mpd, double* heff,
                        hipStream_t st, double* zs, hipStream_t st2, hipEvent_t fork_ev,
-                       hipEvent_t join_ev) {
+                       hipEvent_t join_ev, int phase) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
               rings.zv,   rings.zo,  rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
@@ -628,6 +628,19 @@ hipError_t launch_heff(const double* f, const double* V, const double* y1, const
   g.qf = rings.qf;
   g.fs1 = fs1;
   const int tab_stride = heff_table_stride(na_max);
+  // the tables (phase 0) read only prepare's outputs, f and t1
+  if (phase != 1) {
+    k_fs1<<<(2 * n * n + kBlock - 1) / kBlock, kBlock, 0, st>>>(f, t1, n, o, fs1);
+    for (int c = 0; c < 3; ++c) {
+      const int count = cls_off[c + 1] - cls_off[c];
+      if (count <= 0) continue;
+      const int32_t* idx = cls_idx + cls_off[c];
+      if (c == 0) k_heff_tab<4><<<count, kBlock, 0, st>>>(g, spaces, idx, tab, tab_stride);
+      if (c == 1) k_heff_tab<6><<<count, kBlock, 0, st>>>(g, spaces, idx, tab, tab_stride);
+      if (c == 2) k_heff_tab<8><<<count, kBlock, 0, st>>>(g, spaces, idx, tab, tab_stride);
+    }
+  }
+  if (phase == 0) return hipSuccess;
   // k_heff_z and k_heff_pp read only the operators, t1, t2 and mpd: with zs
   // they write there (k_heff_cas adds it), on st2 when given, beside the
   // table and element kernels
@@ -683,15 +696,6 @@ hipError_t launch_heff(const double* f, const double* V, const double* y1, const
     if (e != hipSuccess) return e;
   } else if (use_zs) {
     z_pp(st);
-  }
-  k_fs1<<<(2 * n * n + kBlock - 1) / kBlock, kBlock, 0, st>>>(f, t1, n, o, fs1);
-  for (int c = 0; c < 3; ++c) {
-    const int count = cls_off[c + 1] - cls_off[c];
-    if (count <= 0) continue;
-    const int32_t* idx = cls_idx + cls_off[c];
-    if (c == 0) k_heff_tab<4><<<count, kBlock, 0, st>>>(g, spaces, idx, tab, tab_stride);
-    if (c == 1) k_heff_tab<6><<<count, kBlock, 0, st>>>(g, spaces, idx, tab, tab_stride);
-    if (c == 2) k_heff_tab<8><<<count, kBlock, 0, st>>>(g, spaces, idx, tab, tab_stride);
   }
   // parts 0, 1, 2 per size class: its task count and LDS.  The (4,4) class
   // (about 100 KB of staged tables) runs 1024-thread workgroups, so that its

@@ -123,7 +123,9 @@ void launch_residual(const double* f, const double* V, const double* y1, const d
 // sum over the classes of count_c * na_c^4 doubles; with it the per-space
 // sigma1 x two-body and occupied-pair ladder kernels write into zs, which
 // the CAS rewrite adds, and with st2 (or NULL) they run there (forked from
-// st by fork_ev, joined back by join_ev before the CAS rewrite).
+// st by fork_ev, joined back by join_ev before the CAS rewrite).  phase:
+// 0 launches only fs1 and the per-space tables (which read prepare's
+// outputs, not the residual's), 1 everything after them, -1 both.
 // Returns the first error of the event calls.
 hipError_t launch_heff(const double* f, const double* V, const double* y1, const double* y2,
                        const double* L, const double* LY, const RingOps& rings, const double* t1,
@@ -133,7 +135,7 @@ hipError_t launch_heff(const double* f, const double* V, const double* y1, const
                        const int32_t* cls_idx, const int* cls_off, int K, int na_max,
                        double* tab, double* fs1, const double* zc, const double* mpd, double* heff,
                        hipStream_t st, double* zs, hipStream_t st2, hipEvent_t fork_ev,
-                       hipEvent_t join_ev);
+                       hipEvent_t join_ev, int phase = -1);
 // Operand of the dense occupied-pair ladder (k_heff.hip): xp[tri(p,q)][(t,u)]
 // = (H_N + Yg/2)(p,q,t,u), p <= q, t, u occupied; n(n+1)/2 x o^2 doubles.  The
 // ladder mpd = xp T^T with T[(a,b)][(t,u)] = t2[t,u,a,b] (launch_pack_t2_vvoo).

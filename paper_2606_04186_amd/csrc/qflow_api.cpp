@@ -54,6 +54,7 @@ struct qflow_ctx {
   // the same for the per-space Hamiltonians: their sigma1 x two-body and
   // occupied-pair ladder parts run on stream2 into zsum
   hipEvent_t fork2_ev = nullptr, join2_ev = nullptr;
+  hipEvent_t tabf_ev = nullptr, tab_ev = nullptr;   // the tables on stream2
   std::string err;
   // problem
   int n = 0, o = 0, v = 0;
@@ -634,7 +635,9 @@ int qflow_create(qflow_ctx** out, int device, void* hip_stream) {
       hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->y_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->fork2_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->join2_ev, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&ctx->join2_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->tabf_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->tab_ev, hipEventDisableTiming) != hipSuccess) {
     qflow_destroy(ctx);
     return QFLOW_E_DEVICE;
   }
@@ -706,6 +709,8 @@ int qflow_destroy(qflow_ctx* ctx) {
   if (ctx->y_ev) (void)hipEventDestroy(ctx->y_ev);
   if (ctx->fork2_ev) (void)hipEventDestroy(ctx->fork2_ev);
   if (ctx->join2_ev) (void)hipEventDestroy(ctx->join2_ev);
+  if (ctx->tabf_ev) (void)hipEventDestroy(ctx->tabf_ev);
+  if (ctx->tab_ev) (void)hipEventDestroy(ctx->tab_ev);
   delete ctx;
   return QFLOW_OK;
 }
@@ -901,6 +906,32 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
   } else {
     K = cls_off[3];
   }
+  // the zsum parts need a block per space of the lists; they run on stream2
+  // except in the stage-timed eager step, which keeps one stream (as in
+  // prepare) and the same arithmetic.  With stream2 the per-space tables
+  // (phase 0) run there too, beside the residual, whose outputs they do
+  // not read.
+  const bool use_zs = ctx->zsum.bytes >= sizeof(double) * zsum_doubles(cls_off);
+  const bool split = K > 0 && use_zs && !ctx->timed;
+  auto heff_phase = [&](hipStream_t s, bool dense, int phase) {
+    return qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
+                           P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY),
+                           rings_of(ctx), t1, t2, ctx->n, ctx->o, P<double>(ctx->scal),
+                           P<SpaceDev>(ctx->spaces), heff_off_dev, P<int32_t>(ctx->tasks),
+                           qf::kTaskStride, ctx->task_slots, idx, cls_off, K, ctx->na_max,
+                           P<double>(ctx->mtab), P<double>(ctx->fs1),
+                           dense ? P<double>(ctx->zc) : nullptr,
+                           dense ? P<double>(ctx->mp) : nullptr, heff, s,
+                           use_zs ? P<double>(ctx->zsum) : nullptr,
+                           ctx->timed ? nullptr : ctx->stream2, ctx->fork2_ev, ctx->join2_ev,
+                           phase);
+  };
+  if (split) {
+    QF_HIP(hipEventRecord(ctx->tabf_ev, ctx->stream));
+    QF_HIP(hipStreamWaitEvent(ctx->stream2, ctx->tabf_ev, 0));
+    QF_HIP(heff_phase(ctx->stream2, false, 0));
+    QF_HIP(hipEventRecord(ctx->tab_ev, ctx->stream2));
+  }
   // zero-body parts of [H_N, sigma] and [Yg, sigma] (scal[0], scal[1])
   qf::launch_residual(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
                       P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx),
@@ -924,21 +955,10 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
                            (int)npair, (int)vv, (int)oo, 1.0, P<double>(ctx->gpart),
                            ctx->gpart.bytes / sizeof(double), ctx->stream);
   }
-  // the zsum parts need a block per space of the lists; they run on stream2
-  // except in the stage-timed eager step, which keeps one stream (as in
-  // prepare) and the same arithmetic
-  const bool use_zs = ctx->zsum.bytes >= sizeof(double) * zsum_doubles(cls_off);
-  if (K > 0)
-    QF_HIP(qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
-                           P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY),
-                           rings_of(ctx), t1, t2, ctx->n, ctx->o, P<double>(ctx->scal),
-                           P<SpaceDev>(ctx->spaces), heff_off_dev, P<int32_t>(ctx->tasks),
-                           qf::kTaskStride, ctx->task_slots, idx, cls_off, K, ctx->na_max,
-                           P<double>(ctx->mtab), P<double>(ctx->fs1),
-                           dense ? P<double>(ctx->zc) : nullptr,
-                           dense ? P<double>(ctx->mp) : nullptr, heff, ctx->stream,
-                           use_zs ? P<double>(ctx->zsum) : nullptr,
-                           ctx->timed ? nullptr : ctx->stream2, ctx->fork2_ev, ctx->join2_ev));
+  if (K > 0) {
+    if (split) QF_HIP(hipStreamWaitEvent(ctx->stream, ctx->tab_ev, 0));
+    QF_HIP(heff_phase(ctx->stream, dense, split ? 1 : -1));
+  }
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
