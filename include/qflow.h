@@ -83,9 +83,10 @@ enum {
  * enqueue on, or NULL for a stream the context creates.  The context also
  * creates a second stream of its own (default priority): outside the
  * stage-timed eager flow step, H_N's ladder and ring contractions and then
- * the J, Lo and Z pieces run there beside Yg's chain, and the per-space
- * Hamiltonians' sigma1 x two-body and occupied-pair ladder parts beside
- * their element terms; both are joined back into the main stream by events
+ * the J, Lo and Z pieces run there beside Yg's chain, the per-space
+ * Hamiltonians' tables beside the residual, and their sigma1 x two-body and
+ * occupied-pair ladder parts beside their element terms; all are joined
+ * back into the main stream by events
  * before anything reads them, so every call still completes in the main
  * stream's order (and a captured step captures both).  *out is NULL on
  * failure. */
