@@ -220,11 +220,43 @@ def residual(pb: Problem, t1, t2, occ=None, vir=None):
 REF_WEIGHT_MIN = 0.1
 
 
+def denominators(eps, o):
+    """Delta_ia = eps_a - eps_i and Delta_ijab = eps_a + eps_b - eps_i - eps_j
+    of the residual step taken by amplitudes no space owns."""
+    eo, ev = eps[:o], eps[o:]
+    d1 = ev[None, :] - eo[:, None]
+    d2 = (ev[None, None, :, None] + ev[None, None, None, :]
+          - eo[:, None, None, None] - eo[None, :, None, None])
+    return d1, d2
+
+
+def write_owned(t1, t2, sol, k, occ, vir, owner1, owner2, o):
+    """Write the amplitudes space k owns (assignment of each excitation to the
+    first space, in Delta-epsilon order, that reaches it) from its local
+    cluster amplitudes sol['t1'][I,A], sol['t2'][I,J,A,B] into the pool."""
+    for I, i in enumerate(occ):
+        for A, a in enumerate(vir):
+            if owner1[i, a - o] == k:
+                t1[i, a - o] = sol["t1"][I, A]
+    for I, i in enumerate(occ):
+        for J, j in enumerate(occ):
+            for A, a in enumerate(vir):
+                for B, b in enumerate(vir):
+                    if owner2[i, j, a - o, b - o] == k:
+                        t2[i, j, a - o, b - o] = sol["t2"][I, J, A, B]
+
+
+def mean_energy(E):
+    """Unweighted mean of the space energies; NaN when there is no space."""
+    return float(np.mean(E)) if len(E) else float("nan")
+
+
 def flow_step(pb: Problem, t1, t2, spaces, owner1, owner2, unowned="residual"):
     """One Jacobi macro-iteration.  spaces: list of (occ tuple, vir tuple) of
     absolute spatial orbitals, in Delta-epsilon order.  owner1[i,a] and
     owner2[i,j,a,b] hold the owning space index or -1.  Returns new (t1, t2),
-    per-space energies, the mean energy and per-space solutions."""
+    per-space energies, the mean energy (NaN with no space) and per-space
+    solutions."""
     o = pb.o
     sols = []
     for (occ, vir) in spaces:
@@ -234,27 +266,14 @@ def flow_step(pb: Problem, t1, t2, spaces, owner1, owner2, unowned="residual"):
     nt1, nt2 = t1.copy(), t2.copy()
     if unowned == "residual" and (np.any(owner1 < 0) or np.any(owner2 < 0)):
         R1, R2, _ = residual(pb, t1, t2)
-        e = pb.eps
-        d1 = e[o:][None, :] - e[:o][:, None]
-        d2 = (e[o:][None, None, :, None] + e[o:][None, None, None, :]
-              - e[:o][:, None, None, None] - e[:o][None, :, None, None])
+        d1, d2 = denominators(pb.eps, o)
         nt1 = np.where(owner1 < 0, t1 - R1 / d1, nt1)
         nt2 = np.where(owner2 < 0, t2 - R2 / d2, nt2)
     for k, (occ, vir) in enumerate(spaces):
-        s = sols[k]
-        if abs(s["c0"]) < REF_WEIGHT_MIN:
+        if abs(sols[k]["c0"]) < REF_WEIGHT_MIN:
             continue
-        for I, i in enumerate(occ):
-            for A, a in enumerate(vir):
-                if owner1[i, a - o] == k:
-                    nt1[i, a - o] = s["t1"][I, A]
-        for I, i in enumerate(occ):
-            for J, j in enumerate(occ):
-                for A, a in enumerate(vir):
-                    for B, b in enumerate(vir):
-                        if owner2[i, j, a - o, b - o] == k:
-                            nt2[i, j, a - o, b - o] = s["t2"][I, J, A, B]
-    return nt1, nt2, E, float(np.mean(E)), sols
+        write_owned(nt1, nt2, sols[k], k, occ, vir, owner1, owner2, o)
+    return nt1, nt2, E, mean_energy(E), sols
 
 
 # ----------------------------------------------------------------------------
@@ -368,26 +387,12 @@ def flow_sweep_windowed(pb: Problem, t1, t2, spaces, owner1, owner2, window,
         sols = {k: solve_space(pb, t1, t2, tuple(spaces[k][0]) + tuple(spaces[k][1]),
                                len(spaces[k][0])) for k in chunk}
         for k in chunk:
-            s = sols[k]
-            E[k] = s["E"]
-            if abs(s["c0"]) < REF_WEIGHT_MIN:
+            E[k] = sols[k]["E"]
+            if abs(sols[k]["c0"]) < REF_WEIGHT_MIN:
                 continue
-            occ, vir = spaces[k]
-            for I, i in enumerate(occ):
-                for A, a in enumerate(vir):
-                    if owner1[i, a - o] == k:
-                        t1[i, a - o] = s["t1"][I, A]
-            for I, i in enumerate(occ):
-                for J, j in enumerate(occ):
-                    for A, a in enumerate(vir):
-                        for B, b in enumerate(vir):
-                            if owner2[i, j, a - o, b - o] == k:
-                                t2[i, j, a - o, b - o] = s["t2"][I, J, A, B]
+            write_owned(t1, t2, sols[k], k, spaces[k][0], spaces[k][1], owner1, owner2, o)
     if step_unowned:
-        e = pb.eps
-        d1 = e[o:][None, :] - e[:o][:, None]
-        d2 = (e[o:][None, None, :, None] + e[o:][None, None, None, :]
-              - e[:o][:, None, None, None] - e[:o][None, :, None, None])
+        d1, d2 = denominators(pb.eps, o)
         t1 = np.where(owner1 < 0, t1 - R1 / d1, t1)
         t2 = np.where(owner2 < 0, t2 - R2 / d2, t2)
-    return t1, t2, E, float(np.mean(E))
+    return t1, t2, E, mean_energy(E)
