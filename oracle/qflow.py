@@ -219,6 +219,42 @@ def residual(pb: Problem, t1, t2, occ=None, vir=None):
 
 REF_WEIGHT_MIN = 0.1
 
+_SHARED = None
+
+
+def _one_blas_thread():
+    """Worker start-up: one BLAS thread per worker process (the workers
+    already spread the spaces over the cores)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(limits=1)
+    except ImportError:
+        pass
+
+
+def _solve_shared(k):
+    pb, t1, t2, spaces = _SHARED
+    occ, vir = spaces[k]
+    return solve_space(pb, t1, t2, tuple(occ) + tuple(vir), len(occ))
+
+
+def solve_spaces(pb: Problem, t1, t2, spaces, workers=1):
+    """solve_space for every space of the list, all from the same pool (the
+    Jacobi sweep).  The spaces are independent, so with workers > 1 they are
+    spread over forked processes; each solve is the same computation either
+    way."""
+    if workers <= 1 or len(spaces) < 2:
+        return [solve_space(pb, t1, t2, tuple(occ) + tuple(vir), len(occ))
+                for (occ, vir) in spaces]
+    import multiprocessing
+    global _SHARED
+    _SHARED = (pb, t1, t2, [(tuple(s[0]), tuple(s[1])) for s in spaces])
+    try:
+        with multiprocessing.get_context("fork").Pool(workers, initializer=_one_blas_thread) as pool:
+            return pool.map(_solve_shared, range(len(spaces)), chunksize=1)
+    finally:
+        _SHARED = None
+
 
 def denominators(eps, o):
     """Delta_ia = eps_a - eps_i and Delta_ijab = eps_a + eps_b - eps_i - eps_j
@@ -251,17 +287,15 @@ def mean_energy(E):
     return float(np.mean(E)) if len(E) else float("nan")
 
 
-def flow_step(pb: Problem, t1, t2, spaces, owner1, owner2, unowned="residual"):
+def flow_step(pb: Problem, t1, t2, spaces, owner1, owner2, unowned="residual", workers=1):
     """One Jacobi macro-iteration.  spaces: list of (occ tuple, vir tuple) of
     absolute spatial orbitals, in Delta-epsilon order.  owner1[i,a] and
     owner2[i,j,a,b] hold the owning space index or -1.  Returns new (t1, t2),
     per-space energies, the mean energy (NaN with no space) and per-space
-    solutions."""
+    solutions.  workers > 1 solves the (independent) spaces in that many
+    forked processes."""
     o = pb.o
-    sols = []
-    for (occ, vir) in spaces:
-        orbs = tuple(occ) + tuple(vir)
-        sols.append(solve_space(pb, t1, t2, orbs, len(occ)))
+    sols = solve_spaces(pb, t1, t2, spaces, workers)
     E = np.array([s["E"] for s in sols])
     nt1, nt2 = t1.copy(), t2.copy()
     if unowned == "residual" and (np.any(owner1 < 0) or np.any(owner2 < 0)):

@@ -180,16 +180,35 @@ class Cluster(Op):
             x[np.ix_(mi, ma)] = 0.0
         return x
 
+    def _t2_masked(self):
+        """The dense antisymmetric spin-orbital t2 with the mask applied
+        (every amplitude whose four spatial indices lie in the space set to
+        zero), built once and kept read-only so that no caller can alter it."""
+        if getattr(self, "_t2m", None) is None:
+            x = self._full()[1].copy()
+            if self.mask is not None:
+                o2 = 2 * self.o
+                occ = np.nonzero(self.mask[np.arange(o2) // 2])[0]
+                vir = np.nonzero(self.mask[(np.arange(x.shape[2]) + o2) // 2])[0]
+                x[np.ix_(occ, occ, vir, vir)] = 0.0
+            x.flags.writeable = False
+            self._t2m = x
+        return self._t2m
+
     def _t2(self, i, j, a, b):
         """spin-orbital t_{ij}^{ab} (antisymmetric), shape [i,j,a,b]:
-        t2[i,j,a,b] for opposite spins, t2[i,j,a,b] - t2[i,j,b,a] for equal."""
+        t2[i,j,a,b] for opposite spins, t2[i,j,a,b] - t2[i,j,b,a] for equal;
+        amplitudes with every index in the mask are zero.  A request for the
+        whole occupied and virtual ranges returns the stored (read-only)
+        array itself."""
         o2 = 2 * self.o
-        x = self._full()[1][np.ix_(i, j, a - o2, b - o2)]
-        if self.mask is not None:
-            m = self.mask
-            sub = [np.nonzero(m[k // 2])[0] for k in (i, j, a, b)]
-            x[np.ix_(*sub)] = 0.0      # amplitudes with every index in the space
-        return x
+        x = self._t2_masked()
+        if (len(i) == len(j) == o2 and len(a) == len(b) == x.shape[2]
+                and np.array_equal(i, np.arange(o2)) and np.array_equal(j, np.arange(o2))
+                and np.array_equal(a, np.arange(o2, o2 + x.shape[2]))
+                and np.array_equal(b, np.arange(o2, o2 + x.shape[2]))):
+            return x
+        return x[np.ix_(i, j, a - o2, b - o2)]
 
     def one(self, I, J):
         if I[0] == "v" and J[0] == "o":

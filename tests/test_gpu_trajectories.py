@@ -1,0 +1,192 @@
+"""Multi-step flows on the larger workloads against the oracle's stored
+trajectories (tests/golden/make_golden.py, which calls only the oracle and
+the seeded generator).
+
+* 40 orbitals (5 occupied, 35 virtual), K = 256 (3,3) spaces, MP2 start:
+  30 plain FP64 macro-iterations (eager, and as a captured graph), every
+  space's energy and the mean at every iteration within 1e-8 Eh, the pool
+  after the first and the last iteration within 1e-8; the mixed-precision
+  paths (FP32, BF16x3) within the mixed target of 1e-6 Eh per space at every
+  iteration.
+* 82 orbitals (10 occupied, 72 virtual), K = 2048: two macro-iterations.
+  FP64: all 2048 energies of the first, and 16 sampled spaces of the second
+  (energies and owned amplitudes), plus a sampled block of the pool (owned and
+  unowned doubles and singles) after each; FP32 and BF16x3: every space's
+  energy within 1e-6 Eh of the FP64 path and of the oracle.
+
+The library samples the spaces itself (Algorithm 1 on the same uniform
+stream); the list must equal the stored one.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _gold(name):
+    path = os.path.join(GOLD, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated")
+    return np.load(path, allow_pickle=False)
+
+
+def _setup(cfg_name, gold):
+    import paper_2606_04186_amd as qf
+    cfg = synth.CONFIGS[cfg_name]
+    n, o, K = cfg["n"], cfg["o"], cfg["K"]
+    v = n - o
+    h, eri = synth.config_integrals(cfg_name)
+    dev = torch.device("cuda:0")
+    ctx = qf.Context(0)
+    dh, deri = torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev)
+    ctx.load_integrals(dh, deri, o)
+    _, eps, _ = ctx.reference()
+    u = synth.sampling_stream(cfg_name, 0).uniform(64 * K)
+    spaces, _, _ = qf.sample_spaces(o, v, 3, 3, eps, u, cap=K)
+    orbs = np.array([s["orb"][:6] for s in spaces], dtype=np.int32)
+    assert np.array_equal(orbs, gold["orbs"]), "library sampler differs from the oracle's"
+    o1, o2 = qf.build_owners(o, v, spaces)
+    return ctx, (dh, deri), spaces, o1, o2, (n, o, v, K)
+
+
+def _pool(ctx, o, v):
+    t1 = torch.zeros(o, v, dtype=torch.float64, device="cuda")
+    t2 = torch.zeros(o, o, v, v, dtype=torch.float64, device="cuda")
+    ctx.mp2_guess(t1, t2)
+    return t1, t2
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("mode", ["eager", "graph"])
+def test_forty_orbitals_thirty_steps_match_oracle_trajectory(mode):
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    gold = _gold("qflow_c2_trajectory.npz")
+    ctx, keep, spaces, o1, o2, (n, o, v, K) = _setup("c2", gold)
+    d1, d2 = torch.from_numpy(o1).cuda(), torch.from_numpy(o2).cuda()
+    t1, t2 = _pool(ctx, o, v)
+    energy = torch.zeros(K, dtype=torch.float64, device="cuda")
+    flags = qf.FP64 | (qf.GRAPH if mode == "graph" else 0)
+    worst = 0.0
+    for it in range(gold["e_mean"].shape[0]):
+        em, _ = ctx.flow_step(spaces, d1, d2, t1, t2, energy, flags)
+        E = energy.cpu().numpy()
+        de = max(np.abs(E - gold["e_space"][it]).max(), abs(em - gold["e_mean"][it]))
+        worst = max(worst, de)
+        assert de < 1e-8, (it, de)
+        if it == 0:
+            assert np.abs(t1.cpu().numpy() - gold["t1_first"]).max() < 1e-8
+            assert np.abs(t2.cpu().numpy() - gold["t2_first"]).max() < 1e-8
+    d_t = max(np.abs(t1.cpu().numpy() - gold["t1_last"]).max(),
+              np.abs(t2.cpu().numpy() - gold["t2_last"]).max())
+    print(f"40 orbitals, {mode}: worst |dE| {worst:.2e} Eh over 30 steps, final |dt| {d_t:.2e}")
+    assert d_t < 1e-8
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_forty_orbitals_mixed_precision_trajectory(prec):
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    gold = _gold("qflow_c2_trajectory.npz")
+    ctx, keep, spaces, o1, o2, (n, o, v, K) = _setup("c2", gold)
+    d1, d2 = torch.from_numpy(o1).cuda(), torch.from_numpy(o2).cuda()
+    t1, t2 = _pool(ctx, o, v)
+    energy = torch.zeros(K, dtype=torch.float64, device="cuda")
+    flags = {"fp32": qf.FP32, "bf16x3": qf.BF16X3}[prec] | qf.GRAPH
+    worst = 0.0
+    for it in range(gold["e_mean"].shape[0]):
+        em, _ = ctx.flow_step(spaces, d1, d2, t1, t2, energy, flags)
+        de = np.abs(energy.cpu().numpy() - gold["e_space"][it]).max()
+        worst = max(worst, de, abs(em - gold["e_mean"][it]))
+    print(f"40 orbitals, {prec}: worst per-space |dE| {worst:.2e} Eh over 30 steps")
+    assert worst < 1e-6
+
+
+def _owned_check(sp_orb, k, lt1, lt2, o1, o2, T1, T2, o, tol):
+    occ, vir = [int(x) for x in sp_orb[:3]], [int(x) for x in sp_orb[3:6]]
+    count = 0
+    for I, i in enumerate(occ):
+        for A, a in enumerate(vir):
+            if o1[i, a - o] == k:
+                assert abs(T1[i, a - o] - lt1[I, A]) < tol
+                count += 1
+    for I, i in enumerate(occ):
+        for J, j in enumerate(occ):
+            for A, a in enumerate(vir):
+                for B, b in enumerate(vir):
+                    if o2[i, j, a - o, b - o] == k:
+                        assert abs(T2[i, j, a - o, b - o] - lt2[I, J, A, B]) < tol
+                        count += 1
+    return count
+
+
+@pytest.mark.timeout(600)
+def test_eighty_two_orbitals_two_steps_match_oracle():
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    gold = _gold("qflow_c3_two_steps.npz")
+    ctx, keep, spaces, o1, o2, (n, o, v, K) = _setup("c3", gold)
+    d1, d2 = torch.from_numpy(o1).cuda(), torch.from_numpy(o2).cuda()
+    samp = gold["samp"]
+    bo, bv = gold["block_occ"], gold["block_vir"] - o
+    blk = np.ix_(bo, bo, bv, bv)
+    blk1 = np.ix_(bo, bv)
+    energies = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        flag = {"fp64": qf.FP64, "fp32": qf.FP32, "bf16x3": qf.BF16X3}[prec] | qf.GRAPH
+        t1, t2 = _pool(ctx, o, v)
+        energy = torch.zeros(K, dtype=torch.float64, device="cuda")
+        out = []
+        for it in range(2):
+            pre1, pre2 = t1.cpu().numpy(), t2.cpu().numpy()
+            em, _ = ctx.flow_step(spaces, d1, d2, t1, t2, energy, flag)
+            out.append((energy.cpu().numpy().copy(), em, pre1, pre2, t1.cpu().numpy(),
+                        t2.cpu().numpy()))
+        energies[prec] = out
+        if prec != "fp64":
+            continue
+        (E1, em1, _, _, T1a, T2a), (E2, em2, P1, P2, T1b, T2b) = out
+        # first iteration: every space, the sampled spaces' owned amplitudes,
+        # and the sampled block of the pool
+        assert np.abs(E1 - gold["e_space_1"]).max() < 1e-9
+        assert abs(em1 - gold["e_mean_1"]) < 1e-9
+        owned = 0
+        for m, k in enumerate(samp):
+            owned += _owned_check(gold["orbs"][k], k, gold["t1_samp_1"][m], gold["t2_samp_1"][m],
+                                  o1, o2, T1a, T2a, o, 1e-8)
+        assert owned > 0
+        assert np.abs(T2a[blk] - gold["block_t2_1"]).max() < 1e-8
+        assert np.abs(T1a[blk1] - gold["block_t1_1"]).max() < 1e-8
+        # second iteration (from the oracle's full first-iteration pool):
+        # sampled spaces and the unowned residual steps of the block
+        assert np.abs(E2[samp] - gold["e_samp_2"]).max() < 1e-9
+        for m, k in enumerate(samp):
+            _owned_check(gold["orbs"][k], k, gold["t1_samp_2"][m], gold["t2_samp_2"][m],
+                         o1, o2, T1b, T2b, o, 1e-8)
+        un2 = gold["block_unowned2_1"]
+        assert un2.any()
+        assert np.abs(T2b[blk][un2] - gold["block_t2_step_2"][un2]).max() < 1e-10
+        un1 = gold["block_unowned1_1"]
+        if un1.any():
+            assert np.abs(T1b[blk1][un1] - gold["block_t1_step_2"][un1]).max() < 1e-10
+    for prec in ("fp32", "bf16x3"):
+        for it in range(2):
+            dE = np.abs(energies[prec][it][0] - energies["fp64"][it][0]).max()
+            print(f"82 orbitals, {prec} step {it}: max per-space |dE| vs FP64 {dE:.2e} Eh")
+            assert dE < 1e-6
+        assert np.abs(energies[prec][0][0] - gold["e_space_1"]).max() < 1e-6
+        assert np.abs(energies[prec][1][0][samp] - gold["e_samp_2"]).max() < 1e-6
