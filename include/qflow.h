@@ -170,9 +170,12 @@ int qflow_solve_active_batch(qflow_ctx* ctx, int32_t K, const qflow_space* space
                              const int64_t* ci_off, int32_t* iters, int32_t* status, double tol,
                              int32_t max_iter);
 
-/* One QFlow macro-iteration (a Jacobi sweep: every space reads the pool as
- * it was on entry, then the pool is updated once, as with the end-of-sweep
- * barrier of the parallel implementation):
+/* One QFlow macro-iteration ("Numerical Implementation": the process groups
+ * downfold and solve their spaces, write the optimised amplitudes back into
+ * the global pool, each excitation being written by the first space in
+ * energy order that reaches it, and meet at a barrier at the end of each
+ * sweep).  Here the sweep is a Jacobi sweep: every space reads the pool as it
+ * was on entry, then the pool is updated once, as at that barrier:
  *   1. build every space's downfolded Hamiltonian from (t1, t2),
  *   2. solve every space,
  *   3. write each amplitude from the space that owns it (owner1[o][v],
@@ -209,6 +212,21 @@ int qflow_flow_sweep_windowed(qflow_ctx* ctx, int32_t K, const qflow_space* spac
                               const int32_t* owner1, const int32_t* owner2, double* t1,
                               double* t2, double* energy, int32_t window, double* e_mean,
                               double* max_dt, int32_t flags);
+
+/* Per-space results of the eigensolves of the last qflow_flow_step (or
+ * windowed sweep) on ctx: iters[K] (Davidson iterations) and status[K]
+ * (QFLOW_OK, QFLOW_E_NOT_CONVERGED, QFLOW_E_REF_WEIGHT), host arrays, either
+ * may be NULL.  K must be the length of that step's space list.
+ * Synchronises the stream. */
+int qflow_last_solve(qflow_ctx* ctx, int32_t K, int32_t* iters, int32_t* status);
+
+/* Stopping rule of the eigensolves inside qflow_flow_step and
+ * qflow_flow_sweep_windowed: a space's Davidson iteration stops when the
+ * residual norm of its normalised Ritz vector falls below tol, or after
+ * max_iter iterations with per-space status QFLOW_E_NOT_CONVERGED (that space
+ * then writes none of its amplitudes in that step).  Defaults: 1e-10, 200.
+ * tol <= 0 or max_iter < 1 is QFLOW_E_INVALID_ARG. */
+int qflow_set_solver(qflow_ctx* ctx, double tol, int32_t max_iter);
 
 /* Per-stage device times of the last qflow_flow_step in milliseconds (HIP
  * events on the context's stream), in the order: [F,sigma] intermediate,
@@ -250,8 +268,15 @@ int qflow_sample_spaces(int32_t No, int32_t Nv, int32_t no, int32_t nv, const do
                         const double* u, int64_t n_u, int32_t cap, qflow_space* out,
                         double* delta_eps, int32_t max_out, int32_t* K_out, int64_t* used);
 
-/* Ownership (host): owner1[i][a], owner2[i][j][a][b] = index of the first
- * space in list order that reaches the amplitude, or -1. */
+/* Ownership (host; "Numerical Implementation", the assignment of each
+ * excitation to the first active space, in the Delta-eps order of
+ * Algorithm 1, that can reach it, so that every amplitude is written once per
+ * sweep): owner1[i][a], owner2[i][j][a][b] = index of the first space in list
+ * order that reaches the amplitude, or -1.  owner2 is keyed on the spatial
+ * pair, owner2[i][j][a][b] = owner2[j][i][b][a].  owner1 holds No*Nv and
+ * owner2 No*No*Nv*Nv int32 (host, caller-owned).  A space with n_o or n_v
+ * below 1, more than 8 orbitals, or an orbital outside its block gives
+ * QFLOW_E_INVALID_ARG (the arrays are then partly written). */
 int qflow_build_owners(int32_t No, int32_t Nv, int32_t K, const qflow_space* spaces,
                        int32_t* owner1, int32_t* owner2);
 

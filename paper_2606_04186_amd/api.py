@@ -66,6 +66,8 @@ def lib() -> ctypes.CDLL:
                                                          vp, i32]),
             "qflow_last_timings": (ctypes.c_int, [vp, vp, ctypes.c_int]),
             "qflow_set_z_mode": (ctypes.c_int, [vp, ctypes.c_int]),
+            "qflow_set_solver": (ctypes.c_int, [vp, d, i32]),
+            "qflow_last_solve": (ctypes.c_int, [vp, i32, vp, vp]),
             "qflow_sample_spaces": (ctypes.c_int, [i32, i32, i32, i32, vp, vp, i64, i32, vp, vp,
                                                    i32, vp, vp]),
             "qflow_build_owners": (ctypes.c_int, [i32, i32, i32, vp, vp, vp]),
@@ -210,6 +212,17 @@ class Context:
         """How build_heff forms the sigma1 x two-body terms: Z_AUTO, Z_SPACE
         or Z_DENSE (module constants)."""
         self._check(lib().qflow_set_z_mode(self.h, int(mode)))
+
+    def last_solve(self, K):
+        """(iters, status) of the last flow step's eigensolves, numpy int32."""
+        it = np.zeros(K, dtype=np.int32)
+        st = np.zeros(K, dtype=np.int32)
+        self._check(lib().qflow_last_solve(self.h, int(K), _ptr(it), _ptr(st)))
+        return it, st
+
+    def set_solver(self, tol=1e-10, max_iter=200):
+        """Stopping rule of the flow steps' eigensolves."""
+        self._check(lib().qflow_set_solver(self.h, float(tol), int(max_iter)))
 
     STAGES = ("yg", "ladder_h", "ladder_yg", "ring_pack", "ring_gemm", "ring_j", "sigma1_x",
               "residual", "heff", "solve", "update", "total")

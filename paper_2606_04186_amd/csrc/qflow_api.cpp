@@ -121,6 +121,9 @@ struct qflow_ctx {
   float stage_ms[kStages] = {};
   float total_ms = 0.f;
   bool timed = false;
+  // stopping rule of the flow steps' eigensolves (qflow_set_solver)
+  double dav_tol = 1e-10;
+  int dav_max_iter = 200;
 };
 
 namespace {
@@ -1018,7 +1021,7 @@ int enqueue_step(qflow_ctx* ctx, int32_t K, const int32_t* owner1, const int32_t
     r = run_solve(ctx, K, P<double>(ctx->heff), P<int64_t>(ctx->heff_off), P<double>(ctx->energy),
                   P<double>(ctx->c0), P<double>(ctx->amp), P<int64_t>(ctx->amp_off),
                   P<double>(ctx->ci), P<int64_t>(ctx->ci_off), P<int32_t>(ctx->iters),
-                  P<int32_t>(ctx->status), 1e-10, 200);
+                  P<int32_t>(ctx->status), ctx->dav_tol, ctx->dav_max_iter);
   }
   ctx->timed = false;
   if (r != QFLOW_OK) return r;
@@ -1252,7 +1255,8 @@ int qflow_flow_sweep_windowed(qflow_ctx* ctx, int32_t K, const qflow_space* spac
     QF_TRY(run_solve(ctx, 0, P<double>(ctx->heff), P<int64_t>(ctx->heff_off),
                      P<double>(ctx->energy), P<double>(ctx->c0), P<double>(ctx->amp),
                      P<int64_t>(ctx->amp_off), P<double>(ctx->ci), P<int64_t>(ctx->ci_off),
-                     P<int32_t>(ctx->iters), P<int32_t>(ctx->status), 1e-10, 200, idx, off));
+                     P<int32_t>(ctx->iters), P<int32_t>(ctx->status), ctx->dav_tol,
+                     ctx->dav_max_iter, idx, off));
     if (count > 0)
       qf::launch_scatter_owned(P<SpaceDev>(ctx->spaces), P<double>(ctx->amp),
                                P<int64_t>(ctx->amp_off), P<int32_t>(ctx->status), owner1, owner2,
@@ -1280,6 +1284,29 @@ int qflow_set_z_mode(qflow_ctx* ctx, int mode) {
   ctx->z_mode = mode;
   ++ctx->epoch;   // a captured step follows the mode
   return ensure_zc(ctx);
+}
+
+int qflow_last_solve(qflow_ctx* ctx, int32_t K, int32_t* iters, int32_t* status) {
+  if (!ctx || K < 0) return QFLOW_E_INVALID_ARG;
+  if (K != (int32_t)ctx->last_spaces.size())
+    return fail(ctx, QFLOW_E_INVALID_ARG, "K differs from the last flow step's list");
+  if (K == 0) return QFLOW_OK;
+  QF_HIP(hipSetDevice(ctx->device));
+  QF_HIP(hipStreamSynchronize(ctx->stream));
+  if (iters)
+    QF_HIP(hipMemcpy(iters, ctx->iters.p, sizeof(int32_t) * K, hipMemcpyDeviceToHost));
+  if (status)
+    QF_HIP(hipMemcpy(status, ctx->status.p, sizeof(int32_t) * K, hipMemcpyDeviceToHost));
+  return QFLOW_OK;
+}
+
+int qflow_set_solver(qflow_ctx* ctx, double tol, int32_t max_iter) {
+  if (!ctx) return QFLOW_E_INVALID_ARG;
+  if (!(tol > 0.0) || max_iter < 1) return fail(ctx, QFLOW_E_INVALID_ARG, "bad tol or max_iter");
+  ctx->dav_tol = tol;
+  ctx->dav_max_iter = max_iter;
+  ++ctx->epoch;   // a captured step holds the old values in its kernel arguments
+  return QFLOW_OK;
 }
 
 int qflow_last_timings(const qflow_ctx* ctx, float* ms, int n) {
