@@ -170,6 +170,33 @@ int qflow_solve_active_batch(qflow_ctx* ctx, int32_t K, const qflow_space* space
                              const int64_t* ci_off, int32_t* iters, int32_t* status, double tol,
                              int32_t max_iter);
 
+/* Bytes of device memory qflow_solve_active_batch_static may use: 128 MiB,
+ * held by every device the library runs on from its first context until the
+ * process ends. */
+#define QFLOW_STATIC_SCRATCH_BYTES (128u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as qflow_solve_active_batch, with the same arguments, results and
+ * errors, that allocates nothing.  Its space records, class lists, offsets
+ * and Davidson work areas live in one file-scope device array of
+ * QFLOW_STATIC_SCRATCH_BYTES; the library resolves that array's address on
+ * each device once, at qflow_create.  A batch needs 256-byte-aligned
+ * sections of 40 K (records), 4 K (class lists) and 4 x 8 (K + 1) (offsets)
+ * bytes plus 8 x 24 D bytes of work per space of D determinants (27 D for
+ * the (4,4) class), about 77 KB per (3,3) space (at most about 1,700 (3,3),
+ * 19,000 (2,2) or 126 (4,4) spaces per call); a larger batch returns
+ * QFLOW_E_UNSUPPORTED before any work is enqueued.  The work areas need no
+ * initial contents.  Every call on one device shares that device's array and
+ * overwrites it: calls that overlap on one device (several contexts or
+ * streams, or threads) race and must be serialised by the caller.  The call
+ * copies the records from host memory and synchronises the stream. */
+int qflow_solve_active_batch_static(qflow_ctx* ctx, int32_t K, const qflow_space* spaces,
+                                    const double* heff, const int64_t* heff_off, double* energy,
+                                    double* c0, double* amp, const int64_t* amp_off,
+                                    double* ci_warm, const int64_t* ci_off, int32_t* iters,
+                                    int32_t* status, double tol, int32_t max_iter);
+
 /* One QFlow macro-iteration ("Numerical Implementation": the process groups
  * downfold and solve their spaces, write the optimised amplitudes back into
  * the global pool, each excitation being written by the first space in

@@ -20,6 +20,7 @@ UNOWNED_FROZEN = 1 << 4
 GRAPH = 1 << 5
 DIIS = 1 << 6
 Z_AUTO, Z_SPACE, Z_DENSE = 0, 1, 2   # qflow_z_mode
+STATIC_SCRATCH_BYTES = 128 * 1024 * 1024   # QFLOW_STATIC_SCRATCH_BYTES
 
 SPACE_DTYPE = np.dtype([("n_o", "<i4"), ("n_v", "<i4"), ("orb", "<i4", (8,))])
 
@@ -61,6 +62,9 @@ def lib() -> ctypes.CDLL:
             "qflow_build_heff": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, ctypes.c_int]),
             "qflow_solve_active_batch": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp,
                                                         vp, vp, vp, vp, d, i32]),
+            "qflow_solve_active_batch_static": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp,
+                                                               vp, vp, vp, vp, vp, vp, d,
+                                                               i32]),
             "qflow_flow_step": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32]),
             "qflow_flow_sweep_windowed": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, i32, vp,
                                                          vp, i32]),
@@ -187,6 +191,17 @@ class Context:
         """ci / ci_off (optional): start vectors in, eigenvectors out."""
         sp = _spaces(spaces)
         self._check(lib().qflow_solve_active_batch(
+            self.h, len(sp), _ptr(sp), _ptr(heff), _ptr(heff_off), _ptr(energy), _ptr(c0),
+            _ptr(amp), _ptr(amp_off), _ptr(ci), _ptr(ci_off), _ptr(iters), _ptr(status), tol,
+            max_iter))
+
+    def solve_active_batch_static(self, spaces, heff, heff_off, energy, c0, amp, amp_off,
+                                  iters, status, tol=1e-10, max_iter=200, ci=None,
+                                  ci_off=None):
+        """solve_active_batch without device allocation (work memory in the
+        library's static scratch of STATIC_SCRATCH_BYTES per device)."""
+        sp = _spaces(spaces)
+        self._check(lib().qflow_solve_active_batch_static(
             self.h, len(sp), _ptr(sp), _ptr(heff), _ptr(heff_off), _ptr(energy), _ptr(c0),
             _ptr(amp), _ptr(amp_off), _ptr(ci), _ptr(ci_off), _ptr(iters), _ptr(status), tol,
             max_iter))

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -38,6 +39,35 @@ struct GraphKey {
            o2 == b.o2 && energy == b.energy && epoch == b.epoch;
   }
 };
+
+}  // namespace
+
+// Work memory of qflow_solve_active_batch_static: one file-scope array, of
+// which every device the library runs on holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in, never the
+// device memory: host code uses only the address resolved below.
+static __device__ __align__(256) unsigned char scratch[QFLOW_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (which must be current),
+// resolved once per device and kept.
+hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 }  // namespace
 
@@ -121,6 +151,7 @@ struct qflow_ctx {
   float stage_ms[kStages] = {};
   float total_ms = 0.f;
   bool timed = false;
+  void* scratch = nullptr;   // this device's copy of `scratch` (device address)
   // stopping rule of the flow steps' eigensolves (qflow_set_solver)
   double dav_tol = 1e-10;
   int dav_max_iter = 200;
@@ -644,6 +675,10 @@ int qflow_create(qflow_ctx** out, int device, void* hip_stream) {
     qflow_destroy(ctx);
     return QFLOW_E_DEVICE;
   }
+  if (scratch_address(device, &ctx->scratch) != hipSuccess) {
+    qflow_destroy(ctx);
+    return QFLOW_E_DEVICE;
+  }
   int lds_limit = 0;
   if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
           hipSuccess &&
@@ -1125,6 +1160,96 @@ int qflow_solve_active_batch(qflow_ctx* ctx, int32_t K, const qflow_space* space
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipFree(off.p);
   return r;
+}
+
+int qflow_solve_active_batch_static(qflow_ctx* ctx, int32_t K, const qflow_space* spaces,
+                                    const double* heff, const int64_t* heff_off, double* energy,
+                                    double* c0, double* amp, const int64_t* amp_off,
+                                    double* ci_warm, const int64_t* ci_off, int32_t* iters,
+                                    int32_t* status, double tol, int32_t max_iter) {
+  QF_TRY(require_loaded(ctx));
+  QF_TRY(check_spaces(ctx, K, spaces));
+  if (!heff || !energy || !c0 || !amp || !iters || !status)
+    return fail(ctx, QFLOW_E_INVALID_ARG, "NULL array argument");
+  if (!(tol > 0.0) || max_iter < 1) return fail(ctx, QFLOW_E_INVALID_ARG, "bad tol or max_iter");
+  QF_TRY(check_offsets(ctx, K, spaces, heff_off, qflow_heff_size, "heff_off"));
+  QF_TRY(check_offsets(ctx, K, spaces, amp_off, qflow_amp_size, "amp_off"));
+  if (ci_warm) QF_TRY(check_offsets(ctx, K, spaces, ci_off, qflow_ci_size, "ci_off"));
+  if (!ctx->scratch) return fail(ctx, QFLOW_E_STATE, "no scratch address on this device");
+  if (K == 0) return QFLOW_OK;
+  QF_HIP(hipSetDevice(ctx->device));
+  // host records of the list: space descriptors, class lists, work offsets
+  std::vector<SpaceDev> dev(K);
+  std::vector<int64_t> work_off(K + 1, 0);
+  std::vector<int32_t> cls[3];
+  int lds = 0;
+  for (int k = 0; k < K; ++k) {
+    const qflow_space& s = spaces[k];
+    dev[k].na = na_of(s);
+    dev[k].nocc = s.n_o;
+    for (int a = 0; a < 8; ++a) dev[k].orb[a] = a < dev[k].na ? s.orb[a] : 0;
+    const qf::DavLayout lay = qf::dav_layout(dev[k].na, s.n_o, kMaxSub);
+    work_off[k + 1] = work_off[k] + lay.work;
+    lds = std::max(lds, lay.lds);
+    cls[s.n_o - 2].push_back(k);
+  }
+  if ((size_t)lds * sizeof(double) > (size_t)ctx->lds_limit)
+    return fail(ctx, QFLOW_E_UNSUPPORTED, "active space too large for the device's LDS");
+  int cls_off[4];
+  std::vector<int32_t> idx;
+  for (int c = 0; c < 3; ++c) {
+    cls_off[c] = (int)idx.size();
+    idx.insert(idx.end(), cls[c].begin(), cls[c].end());
+  }
+  cls_off[3] = (int)idx.size();
+  // scratch layout, each section 256-byte aligned: descriptors | class
+  // lists | heff, amp, ci and work offsets | Davidson work areas
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t b_sp = up(sizeof(SpaceDev) * K), b_idx = up(sizeof(int32_t) * K),
+               b_off = up(sizeof(int64_t) * (K + 1));
+  const size_t head = b_sp + b_idx + 4 * b_off;
+  const size_t need = head + sizeof(double) * (size_t)work_off[K];
+  if (need > (size_t)QFLOW_STATIC_SCRATCH_BYTES)
+    return fail(ctx, QFLOW_E_UNSUPPORTED,
+                "batch needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                    std::to_string((size_t)QFLOW_STATIC_SCRATCH_BYTES));
+  std::vector<unsigned char> host(head, 0);
+  std::memcpy(host.data(), dev.data(), sizeof(SpaceDev) * K);
+  std::memcpy(host.data() + b_sp, idx.data(), sizeof(int32_t) * K);
+  unsigned char* offs = host.data() + b_sp + b_idx;
+  std::memcpy(offs, heff_off, sizeof(int64_t) * (K + 1));
+  std::memcpy(offs + b_off, amp_off, sizeof(int64_t) * (K + 1));
+  if (ci_warm) std::memcpy(offs + 2 * b_off, ci_off, sizeof(int64_t) * (K + 1));
+  std::memcpy(offs + 3 * b_off, work_off.data(), sizeof(int64_t) * (K + 1));
+  unsigned char* base = static_cast<unsigned char*>(ctx->scratch);
+  unsigned char* d_offs = base + b_sp + b_idx;
+  QF_HIP(hipMemcpyAsync(base, host.data(), head, hipMemcpyHostToDevice, ctx->stream));
+  qf::DavidsonArgs a;
+  a.spaces = reinterpret_cast<const SpaceDev*>(base);
+  a.strings = P<qf::Strings>(ctx->strings);
+  a.heff = heff;
+  a.heff_off = reinterpret_cast<const int64_t*>(d_offs);
+  a.work = reinterpret_cast<double*>(base + head);
+  a.work_off = reinterpret_cast<const int64_t*>(d_offs + 3 * b_off);
+  a.energy = energy;
+  a.c0 = c0;
+  a.amp = amp;
+  a.amp_off = reinterpret_cast<const int64_t*>(d_offs + b_off);
+  a.ci = ci_warm;
+  a.ci_off = ci_warm ? reinterpret_cast<const int64_t*>(d_offs + 2 * b_off) : nullptr;
+  a.iters = iters;
+  a.status = status;
+  a.tol = tol;
+  a.max_iter = max_iter;
+  a.maxsub = kMaxSub;
+  a.K = K;
+  qf::launch_davidson(a, reinterpret_cast<const int32_t*>(base + b_sp), cls_off, ctx->stream);
+  const hipError_t el = hipGetLastError();
+  // the host records must outlive the copy
+  QF_HIP(hipStreamSynchronize(ctx->stream));
+  if (el != hipSuccess)
+    return fail(ctx, QFLOW_E_DEVICE, std::string("davidson launch: ") + hipGetErrorString(el));
+  return QFLOW_OK;
 }
 
 int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const int32_t* owner1,
