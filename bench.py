@@ -135,8 +135,12 @@ def main():
             precision |= qf.GRAPH
             tag += " graph"
         print(f"[bench] {tag}: warmup", file=sys.stderr, flush=True)
-        for _ in range(args.warmup):
+        warm_ms, hist = [], {}
+        for w in range(args.warmup):
             ctx.flow_step(spaces, d1, d2, t1, t2, energy, precision)
+            warm_ms.append(ctx.last_timings()["total"])
+            if w == 0:
+                hist["step0"] = iteration_histogram(ctx.last_solve(K)[0])
         stages, e_means = [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -149,8 +153,12 @@ def main():
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         st = {key: float(np.mean([s_[key] for s_ in stages])) for key in stages[0]}
-        return {"ms": ms, "stage_ms": st, "e_mean": e_means[-1],
-                "energy": energy.detach().cpu().numpy().copy()}
+        its, _ = ctx.last_solve(K)
+        hist["last"] = iteration_histogram(its)
+        cold = (warm_ms + [s_["total"] for s_ in stages])[:5]
+        return {"ms": ms, "stage_ms": st, "e_mean": e_means[-1], "e_means": e_means,
+                "energy": energy.detach().cpu().numpy().copy(),
+                "cold_ms_steps": cold, "iters_hist": hist, "iters_mean_last": float(its.mean())}
 
     runs = {}
     for key, flag in (("fp64", qf.FP64), ("fp32", qf.FP32), ("bf16x3", qf.BF16X3)):
@@ -161,9 +169,14 @@ def main():
             if not args.no_graph:
                 # the graph pass: the rate; same start, same kernels
                 g = run_path(flag, True)
+                for k_ in ("cold_ms_steps", "iters_hist", "iters_mean_last", "e_means"):
+                    runs[key][k_] = g[k_]
                 runs[key]["ms"] = g["ms"]
                 runs[key]["graph_total_ms"] = g["stage_ms"]["total"]
                 runs[key]["graph_vs_eager_dE"] = abs(g["e_mean"] - runs[key]["e_mean"])
+    for r in runs.values():
+        c = [x for x in r["cold_ms_steps"] if x > 0]
+        r["cold_ms_mean"] = float(np.mean(c)) if c else None
     dE = {}
     if "fp64" in runs:
         for key in ("fp32", "bf16x3"):
@@ -177,23 +190,28 @@ def main():
     use = min(ok, key=lambda k: runs[k]["ms"]) if ok else "fp64"
     ms, st = runs[use]["ms"], runs[use]["stage_ms"]
     peak = {"fp64": FP64_MFMA_PEAK_TFLOPS, "fp32": FP32_MFMA_PEAK_TFLOPS,
-            "bf16x3": BF16_MFMA_PEAK_TFLOPS / 3.0}[use]
+            "bf16x3": BF16_MFMA_PEAK_TFLOPS}[use]
 
     # Roofline of the reported path's matrix-core GEMM kernel (k_gemm_f64,
     # k_gemm_f32 or k_gemm_bf16x3) over its ladder and ring launches (six per
-    # step: two ladders, two Ga rings, two G22 rings): algorithmic flops per
-    # step (FP64-equivalent products) over their HIP-event time in the timed
-    # steps; the event brackets hold those launches and the split-K slice sums
-    # of the two ladders.
+    # step: two ladders, two Ga rings, two G22 rings).  achieved = the
+    # algorithmic flops of the method's ladder and ring contractions per
+    # macro-iteration, 2 o^2 v^4 + 3 x 2 o^3 v^3, over the HIP-event time of
+    # those launches in the timed steps (the brackets also hold the split-K
+    # slice sums of the two ladders); peak = the published dense matrix-core
+    # peak of the products' data type.  The flops this formulation executes
+    # (ladder rows over every orbital pair, ring rows over all n^2 pairs, for
+    # H_N and [F, sigma]) are reported beside it.
     ov = o * v
+    alg_flops = 2.0 * o * o * v ** 4 + 3 * 2.0 * (o * v) ** 3
     f_ladder = 2.0 * (n * (n + 1) // 2) * (o * o) * (v * v)   # H_N: rows p <= q
     # [F,sigma]'s two-body part vanishes for p, q both virtual: o*n - o(o-1)/2 rows
     f_ladder_y = 2.0 * (o * n - o * (o - 1) // 2) * (o * o) * (v * v)
     f_ga = 2.0 * (n * n) * ov * (2 * ov)
     f_g22 = 2.0 * (n * n) * ov * ov
-    gemm_flops = f_ladder + f_ladder_y + 2 * f_ga + 2 * f_g22
+    exec_flops = f_ladder + f_ladder_y + 2 * f_ga + 2 * f_g22
     gemm_ms = st["ladder_h"] + st["ladder_yg"] + st["ring_gemm"]
-    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
+    achieved = alg_flops / (gemm_ms * 1e-3) / 1e12
     kname = {"fp64": "k_gemm_f64", "fp32": "k_gemm_f32", "bf16x3": "k_gemm_bf16x3"}[use]
     roof = {"kernel": kname,
             "scope": "ladder and ring launches, six per step",
@@ -203,15 +221,29 @@ def main():
             "traffic_unit": "HBM bytes per step of the six launches (rocprofv3 FETCH_SIZE + "
                             "WRITE_SIZE, copy-calibrated)",
             "launches_per_step": 6, "avg_launch_ms": gemm_ms / 6,
-            "flop_per_step": gemm_flops, "ms_per_step": gemm_ms}
+            "algorithmic_flop_per_step": alg_flops, "ms_per_step": gemm_ms,
+            "executed_flop_per_step": exec_flops,
+            "executed_tflops": exec_flops / (gemm_ms * 1e-3) / 1e12,
+            "products_per_executed_flop": 3 if use == "bf16x3" else 1}
+    class_counts = [int(np.sum(spaces["n_o"] == c)) for c in (2, 3, 4)]
+    t_roof = step_roofline(n, o, class_counts, use, runs[use]["iters_mean_last"])
+    roof["step"] = {"t_roof_ms": t_roof["total"], "t_measured_ms": ms,
+                    "frac": t_roof["total"] / ms, "stages_ms": t_roof}
     modes = {}
     for key, r in runs.items():
         mms = r["stage_ms"]["ladder_h"] + r["stage_ms"]["ladder_yg"] + r["stage_ms"]["ring_gemm"]
+        tr = step_roofline(n, o, class_counts, key, r["iters_mean_last"])
         modes[key] = {"value": 1e3 / r["ms"], "ms_per_step": r["ms"], "e_mean": r["e_mean"],
                       "ms_per_step_eager": r["ms_eager"],
                       "graph_total_ms": r.get("graph_total_ms"),
                       "graph_vs_eager_abs_dE_mean": r.get("graph_vs_eager_dE"),
-                      "residual_gemm_tflops": gemm_flops / (mms * 1e-3) / 1e12,
+                      "residual_tflops_algorithmic": alg_flops / (mms * 1e-3) / 1e12,
+                      "residual_tflops_executed": exec_flops / (mms * 1e-3) / 1e12,
+                      "step_roofline_frac": tr["total"] / r["ms"],
+                      "cold_ms_steps_0_4_from_mp2": r.get("cold_ms_steps"),
+                      "cold_ms_mean_steps_0_4": r.get("cold_ms_mean"),
+                      "davidson_iterations": r.get("iters_hist"),
+                      "e_mean_timed_steps": r.get("e_means"),
                       "stage_ms": r["stage_ms"]}
     for key, (dm, dsp) in dE.items():
         modes[key]["abs_dE_mean"] = dm
@@ -234,7 +266,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(h, eri, o, spaces, args.cpu_sample_spaces, K)
+        cpu = cpu_baseline(h, eri, o, spaces, args.cpu_sample_spaces, K, args.config)
 
     out = {
         "metric": "QFlow macro-iterations/s at 114 orbitals, mixed vs FP64, |dE| < 1e-6 Eh",
@@ -290,13 +322,63 @@ def gemm_traffic(kernel):
     return int(m_b.group(1))
 
 
-def cpu_baseline(h, eri, o, spaces, m, K):
-    """The oracle on a bounded sample: the full per-space work (downfolded
-    Hamiltonian, CAS eigenproblem, cluster analysis) of the first m spaces,
-    scaled to one macro-iteration of K spaces.  The oracle's global residual
-    and update are not in the sample, so the figure is an upper bound on its
-    rate."""
-    from oracle import qflow
+def iteration_histogram(iters):
+    """{iterations: number of spaces} of one step's eigensolves."""
+    vals, counts = np.unique(np.asarray(iters), return_counts=True)
+    return {int(a): int(b) for a, b in zip(vals, counts)}
+
+
+def step_roofline(n, o, class_counts, precision, iters):
+    """Lower bound on one macro-iteration's device time: for each stage the
+    larger of (algorithmic flops / peak of its arithmetic) and (compulsory
+    HBM bytes / 8 TB/s), summed over the stages.  Per-unit figures:
+    ladder 2 o^2 v^4 flop with the (ac|bd) block streamed once (8 B per
+    element in FP64, 4 B in FP32 or BF16 hi+lo); rings 3 x 2 o^3 v^3; hole-hole
+    ladder and Fock terms 2 (o^4 v^2 + o^2 v^3 + o^3 v^2); per-space
+    Hamiltonians 2e6 flop per space (the low end of the 2-10e6 estimate) and
+    their CAS-form output written once; Davidson: per sigma product
+    1.28 x D r^2 multiply-adds (D determinants, r = n_o n_v + n_o), `iters`
+    sigma products per space; update: t, R and the new t of o^2 v^2 doubles.
+    Ladder and rings at the products' peak (BF16x3: three BF16 products per
+    FP64-equivalent one), everything else at the FP64 peak."""
+    v = n - o
+    p_mix = {"fp64": FP64_MFMA_PEAK_TFLOPS, "fp32": FP32_MFMA_PEAK_TFLOPS,
+             "bf16x3": BF16_MFMA_PEAK_TFLOPS / 3.0}[precision] * 1e12
+    p64, bw = FP64_MFMA_PEAK_TFLOPS * 1e12, HBM_PEAK_GBS * 1e9
+    w_bytes = (8.0 if precision == "fp64" else 4.0) * v ** 4
+    stages = {"ladder": max(2.0 * o * o * v ** 4 / p_mix, w_bytes / bw),
+              "rings": 6.0 * (o * v) ** 3 / p_mix,
+              "other_residual": 2.0 * (o ** 4 * v * v + o * o * v ** 3 + o ** 3 * v * v) / p64}
+    heff_f, heff_b, dav = 0.0, 0.0, 0.0
+    for c, kc in zip((2, 3, 4), class_counts):
+        na = 2 * c
+        ns = int(round(np.prod([(na - i) / (i + 1) for i in range(c)])))
+        r = c * c + c
+        heff_f += kc * 2e6
+        heff_b += kc * 8.0 * (1 + na ** 2 + na ** 4)
+        dav += kc * iters * 2.0 * 1.28 * ns * ns * r * r
+    stages["heff"] = max(heff_f / p64, heff_b / bw)
+    stages["davidson"] = dav / p64
+    stages["update"] = 3 * 8.0 * (o * v) ** 2 / bw
+    out = {k: 1e3 * t for k, t in stages.items()}
+    out["total"] = sum(out.values())
+    return out
+
+
+def cpu_baseline(h, eri, o, spaces, m, K, config):
+    """The oracle on the GPU machine's host cores, on bounded samples.
+
+    * The reported workload: the full per-space work (downfolded Hamiltonian,
+      CAS eigenproblem, cluster analysis) of the first m spaces, scaled by K,
+      plus the oracle's residual on a sampled block (2 occupied x 3 virtual
+      orbitals) of its output, which is a lower bound on the full residual's
+      cost; the value is therefore an upper bound on the oracle's rate.
+    * Whole macro-iterations (every space, the full residual and the update)
+      of the 8-orbital (10 spaces) and 40-orbital (K = 256) workloads, the
+      spaces spread over the host cores."""
+    import synth
+    from oracle import qflow, sampling
+    workers = max(1, min(16, os.cpu_count() or 1))
     pb = qflow.Problem(h, eri, o)
     t1, t2 = qflow.mp2_guess(pb.f, eri, o)
     t0 = time.perf_counter()
@@ -304,11 +386,38 @@ def cpu_baseline(h, eri, o, spaces, m, K):
         orbs = tuple(int(x) for x in s["orb"][: s["n_o"] + s["n_v"]])
         qflow.solve_space(pb, t1, t2, orbs, int(s["n_o"]))
     dt = (time.perf_counter() - t0) / m
+    print(f"[bench] cpu baseline: {m} spaces, {dt:.1f} s each", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    qflow.residual(pb, t1, t2, occ=[0, o - 1], vir=[o, (o + pb.n) // 2, pb.n - 1])
+    dt_r = time.perf_counter() - t0
+    print(f"[bench] cpu baseline: residual block {dt_r:.1f} s", file=sys.stderr, flush=True)
+    full = {}
+    for name in ("c1", "c2"):
+        c = synth.CONFIGS[name]
+        hh, ee = synth.config_integrals(name)
+        pq = qflow.Problem(hh, ee, c["o"])
+        if name == "c1":
+            S = sampling.enumerate_spaces(c["o"], c["n"] - c["o"], 3, 3, pq.eps)
+        else:
+            S = sampling.algorithm1(c["o"], c["n"] - c["o"], 3, 3, pq.eps,
+                                    synth.sampling_stream(name), cap=c["K"])
+        lists = [(x[0], x[1]) for x in S]
+        o1, o2 = sampling.ownership(c["o"], c["n"] - c["o"], lists)
+        a1, a2 = qflow.mp2_guess(pq.f, ee, c["o"])
+        t0 = time.perf_counter()
+        qflow.flow_step(pq, a1, a2, lists, o1, o2, workers=workers)
+        sec = time.perf_counter() - t0
+        full[name] = {"s_per_macro_iteration": sec, "macro_iterations_per_s": 1.0 / sec,
+                      "K": len(lists), "n_orb": c["n"], "workers": workers}
+        print(f"[bench] cpu baseline: {name} macro-iteration {sec:.1f} s ({workers} workers)",
+              file=sys.stderr, flush=True)
     threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-    return {"value": 1.0 / (dt * K), "unit": "macro-iterations/s", "cores": int(threads),
+    return {"value": 1.0 / (dt * K + dt_r), "unit": "macro-iterations/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": f"{m} of {K} active spaces (H_eff + CAS eigenproblem + cluster analysis), "
-                      f"{dt:.1f} s each, scaled by K; residual and update excluded"}
+            "sample": f"{config}: {m} of {K} active spaces (H_eff + CAS eigenproblem + cluster "
+                      f"analysis, {dt:.1f} s each, scaled by K) plus the residual on a 2x3 "
+                      f"orbital block ({dt_r:.1f} s, a lower bound on the full residual)",
+            "full_macro_iterations": full}
 
 
 if __name__ == "__main__":
