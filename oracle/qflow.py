@@ -16,9 +16,10 @@ Steps, in the order the paper states them:
   (commutators truncated to 0-, 1- and 2-body parts; F_N the normal-ordered
   Fock operator), then restricted to the orbitals of the space: the projector
   P + Q_int(i) keeps Phi and every determinant excited inside the space.
-* E(i) is the lowest eigenvalue of that active-space matrix (Eq. (5) with the
-  exact active-space ground state standing in for the UCCSD-VQE solver), with
-  the eigenvector's reference coefficient made positive.
+* E(i) is the lowest eigenvalue of that active-space matrix in the spin-flip
+  sector of Phi (Eq. (5) with the exact active-space ground state standing in
+  for the UCCSD-VQE solver), with the eigenvector's reference coefficient
+  made positive.
 * The eigenvector is mapped back to amplitudes by intermediate-normalised
   cluster analysis: T1 = C1, T2 = C2 - T1^2/2 (in spin orbitals).
 * Each amplitude is written by the first space in Delta-epsilon order that
@@ -140,15 +141,48 @@ def cas_matrix(x0, x1, x2, n_occ):
     return basis(n_occ, na).matrix(x0, x1, x2)
 
 
+def spin_flip(n_occ, na):
+    """Matrix of the spin flip in the space's CAS basis: every creator
+    a+_{P alpha} exchanged with a+_{P beta} (local spin orbitals 2P <-> 2P+1),
+    the product reordered ascending with its permutation sign."""
+    B = basis(n_occ, na)
+    F = np.zeros((B.dim, B.dim))
+    for k, d in enumerate(B.dets):
+        occ = [p for p in range(B.M) if (int(d) >> p) & 1]
+        new = [p ^ 1 for p in occ]
+        order = sorted(range(len(new)), key=lambda i: new[i])
+        sign, seen = 1, [False] * len(order)
+        for i in range(len(order)):          # parity of the sorting permutation
+            if not seen[i]:
+                j, cyc = i, 0
+                while not seen[j]:
+                    seen[j] = True
+                    j = order[j]
+                    cyc += 1
+                if cyc % 2 == 0:
+                    sign = -sign
+        F[B.index[sum(1 << p for p in new)], k] = sign
+    return F
+
+
 def solve_cas(x0, x1, x2, n_occ):
-    """Lowest eigenpair of the active-space matrix; reference weight > 0."""
-    B = basis(n_occ, x1.shape[0] // 2)
+    """Lowest eigenpair of the active-space matrix within the spin-flip sector
+    of Phi (reading R15: Sz = 0 determinants, the solve started from Phi and
+    kept in its even-S sector); reference weight > 0.  The downfolded
+    operator is spin-free, so the matrix commutes with the spin flip F and
+    the sector is the range of the projector (1 + f F)/2, F Phi = f Phi."""
+    na = x1.shape[0] // 2
+    B = basis(n_occ, na)
     Hc = B.matrix(x0, x1, x2)
-    w, U = np.linalg.eigh(Hc)
-    c = U[:, 0].copy()
+    F = spin_flip(n_occ, na)
+    f = F[B.iref, B.iref]
+    w, U = np.linalg.eigh(0.5 * (np.eye(B.dim) + f * F))
+    Q = U[:, w > 0.5]
+    e, V = np.linalg.eigh(Q.T @ Hc @ Q)
+    c = Q @ V[:, 0]
     if c[B.iref] < 0:
         c = -c
-    return float(w[0]), c, Hc
+    return float(e[0]), c, Hc
 
 
 def cluster_analysis(c, n_occ, n_vir):
