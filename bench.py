@@ -55,6 +55,14 @@ def parse():
     ap.add_argument("--windowed", type=int, default=0, metavar="W",
                     help="also time one windowed Gauss-Seidel sweep in windows of W spaces "
                          "(the reported path's precision; reported in modes, not in value)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch choices (default: qflow_autotune "
+                         "picks them per precision path from timed flow steps)")
+    ap.add_argument("--tuning", default=None, metavar="D,S,T,Z[,B]",
+                    help="fixed launch choices davidson,split_target,f64_tile,z_mode[,block_44] "
+                         "(implies --no-autotune)")
+    ap.add_argument("--tune-cache", default=None, metavar="PATH",
+                    help="JSON cache of the autotuner's choices (default: none, tune afresh)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-spaces", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -127,6 +135,31 @@ def main():
         print(f"[bench] copied {nb} bytes device to device", file=sys.stderr, flush=True)
         del src, dst
 
+    tunings = {}
+
+    def tune(precision):
+        """Launch choices for this precision path (tuned with the graph flag
+        the rate is taken with), from the MP2 pool."""
+        tag = {qf.FP64: "fp64", qf.FP32: "fp32", qf.BF16X3: "bf16x3"}[precision]
+        if args.tuning:
+            v_ = [int(x) for x in args.tuning.split(",")]
+            ctx.set_tuning(davidson=v_[0], split_target=v_[1], f64_tile=v_[2], z_mode=v_[3],
+                           block_44=v_[4] if len(v_) > 4 else None)
+            tunings[tag] = {"choice": ctx.get_tuning().as_dict(), "source": "--tuning"}
+            return
+        if args.no_autotune:
+            tunings[tag] = {"choice": ctx.get_tuning().as_dict(), "source": "library default"}
+            return
+        ctx.mp2_guess(t1, t2)
+        flags = precision | (0 if args.no_graph else qf.GRAPH)
+        t0 = time.perf_counter()
+        choice, rep = ctx.autotune(spaces, d1, d2, t1, t2, flags, args.tune_cache)
+        tunings[tag] = {"choice": choice.as_dict(), "source": "qflow_autotune",
+                        "seconds": time.perf_counter() - t0,
+                        "candidates": [ln for ln in rep.splitlines() if ln.startswith("davidson=")
+                                       or ln.startswith("cached")]}
+        print(f"[bench] {tag}: autotune {tunings[tag]}", file=sys.stderr, flush=True)
+
     def run_path(precision, graph):
         """W untimed and K timed macro-iterations from the MP2 start."""
         ctx.mp2_guess(t1, t2)
@@ -163,6 +196,7 @@ def main():
     runs = {}
     for key, flag in (("fp64", qf.FP64), ("fp32", qf.FP32), ("bf16x3", qf.BF16X3)):
         if args.precision in ("all", key):
+            tune(flag)
             # the eager pass: per-stage HIP events (stage times, roofline)
             runs[key] = run_path(flag, False)
             runs[key]["ms_eager"] = runs[key]["ms"]
@@ -243,6 +277,7 @@ def main():
                       "cold_ms_steps_0_4_from_mp2": r.get("cold_ms_steps"),
                       "cold_ms_mean_steps_0_4": r.get("cold_ms_mean"),
                       "davidson_iterations": r.get("iters_hist"),
+                      "tuning": tunings.get(key),
                       "e_mean_timed_steps": r.get("e_means"),
                       "stage_ms": r["stage_ms"]}
     for key, (dm, dsp) in dE.items():

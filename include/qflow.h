@@ -178,19 +178,24 @@ int qflow_solve_active_batch(qflow_ctx* ctx, int32_t K, const qflow_space* space
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * solve as qflow_solve_active_batch, with the same arguments, results and
- * errors, that allocates nothing.  Its space records, class lists, offsets
- * and Davidson work areas live in one file-scope device array of
+ * errors, that allocates nothing.  Its space records, class lists, offsets,
+ * work counter and Davidson work areas live in one file-scope device array of
  * QFLOW_STATIC_SCRATCH_BYTES; the library resolves that array's address on
- * each device once, at qflow_create.  A batch needs 256-byte-aligned
- * sections of 40 K (records), 4 K (class lists) and 4 x 8 (K + 1) (offsets)
- * bytes plus 8 x 24 D bytes of work per space of D determinants (27 D for
- * the (4,4) class), about 77 KB per (3,3) space (at most about 1,700 (3,3),
- * 19,000 (2,2) or 126 (4,4) spaces per call); a larger batch returns
+ * each device once, at qflow_create.  It follows the context's Davidson
+ * schedule (qflow_set_tuning), so its results equal those of
+ * qflow_solve_active_batch bit for bit.  A batch needs 256-byte-aligned
+ * sections of 256 bytes (the persistent launch's work counter), 40 K
+ * (records), 4 K (class lists) and 4 x 8 (K + 1) (offsets) bytes, plus
+ * 8 x 24 H bytes of work per space whose CI vectors have H = ns (ns + 1) / 2
+ * spin-flip symmetric entries (ns strings per spin; 8 x 27 H for the (4,4)
+ * class): about 40 KB per (3,3) space, so at most about 3,300 (3,3), 33,000
+ * (2,2) or 249 (4,4) spaces per call; a larger batch returns
  * QFLOW_E_UNSUPPORTED before any work is enqueued.  The work areas need no
- * initial contents.  Every call on one device shares that device's array and
- * overwrites it: calls that overlap on one device (several contexts or
- * streams, or threads) race and must be serialised by the caller.  The call
- * copies the records from host memory and synchronises the stream. */
+ * initial contents; the counter is reset by a kernel on the stream.  Every
+ * call on one device shares that device's array and overwrites it: calls
+ * that overlap on one device (several contexts or streams, or threads) race
+ * and must be serialised by the caller.  The call copies the records from
+ * host memory and synchronises the stream. */
 int qflow_solve_active_batch_static(qflow_ctx* ctx, int32_t K, const qflow_space* spaces,
                                     const double* heff, const int64_t* heff_off, double* energy,
                                     double* c0, double* amp, const int64_t* amp_off,
@@ -254,6 +259,52 @@ int qflow_last_solve(qflow_ctx* ctx, int32_t K, int32_t* iters, int32_t* status)
  * then writes none of its amplitudes in that step).  Defaults: 1e-10, 200.
  * tol <= 0 or max_iter < 1 is QFLOW_E_INVALID_ARG. */
 int qflow_set_solver(qflow_ctx* ctx, double tol, int32_t max_iter);
+
+/* Launch choices of a context (each changes only the schedule, never the
+ * arithmetic beyond the summation order of split products):
+ *   davidson      QFLOW_DAV_PER_CLASS: one launch per size class, a workgroup
+ *                 per space; QFLOW_DAV_PERSISTENT: one persistent launch over
+ *                 every size class, as many workgroups as fit taking spaces from
+ *                 a shared counter, the costliest class first;
+ *   split_target  matrix-core products split K until about split_target
+ *                 workgroups per compute unit are available (1..16);
+ *   f64_tile      FP64 products: 0 = the tile that pads the columns less,
+ *                 1 = 128 x 96, 2 = 128 x 128;
+ *   z_mode        as qflow_set_z_mode;
+ *   block_44      threads per (4,4) space in per-class launches: 512 or 1024.
+ * Defaults: QFLOW_DAV_PER_CLASS, 4, 0, QFLOW_Z_AUTO, 512. */
+enum { QFLOW_DAV_PER_CLASS = 0, QFLOW_DAV_PERSISTENT = 1 };
+typedef struct {
+  int32_t davidson, split_target, f64_tile, z_mode, block_44;
+} qflow_tuning;
+
+/* Set (QFLOW_E_INVALID_ARG for a value out of range) or read the context's
+ * launch choices.  A flow step captured as a graph is captured again after a
+ * change. */
+int qflow_set_tuning(qflow_ctx* ctx, const qflow_tuning* tuning);
+int qflow_get_tuning(const qflow_ctx* ctx, qflow_tuning* tuning);
+
+/* Autotuner: choose the launch choices for this problem (loaded integrals,
+ * the space list, the flags' precision and QFLOW_GRAPH) by timing flow steps.
+ * Starting from the current choices it varies one choice at a time
+ * (davidson, split_target in {2, 4, 8}, f64_tile in {0, 1, 2} on the FP64
+ * path, z_mode in {QFLOW_Z_SPACE, QFLOW_Z_DENSE}, block_44 in {512, 1024}
+ * when the list holds (4,4) spaces) and keeps a change when it
+ * lowers the device time of three flow steps (HIP events, after one untimed
+ * step), each candidate starting from the same pool (copies of t1, t2, device;
+ * the caller's arrays are not changed) with cold eigensolver starts.
+ * QFLOW_DIIS is ignored while timing.  The result is applied to ctx and
+ * written to *out (may be NULL).  cache_path (may be NULL): a JSON object
+ * file, one entry per line, keyed by the orbital counts, the size-class
+ * counts, the precision and graph flag and the device's architecture name;
+ * an existing entry is applied without timing, a new one is added.  report
+ * (host, may be NULL): the timed candidates as text, NUL-terminated within
+ * report_len bytes.  Afterwards the next flow step starts its eigensolves
+ * from the reference determinant and a new DIIS history.  Synchronises the
+ * stream. */
+int qflow_autotune(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const int32_t* owner1,
+                   const int32_t* owner2, const double* t1, const double* t2, int32_t flags,
+                   const char* cache_path, qflow_tuning* out, char* report, int32_t report_len);
 
 /* Per-stage device times of the last qflow_flow_step in milliseconds (HIP
  * events on the context's stream), in the order: [F,sigma] intermediate,

@@ -23,6 +23,17 @@ Z_AUTO, Z_SPACE, Z_DENSE = 0, 1, 2   # qflow_z_mode
 STATIC_SCRATCH_BYTES = 128 * 1024 * 1024   # QFLOW_STATIC_SCRATCH_BYTES
 
 SPACE_DTYPE = np.dtype([("n_o", "<i4"), ("n_v", "<i4"), ("orb", "<i4", (8,))])
+DAV_PER_CLASS, DAV_PERSISTENT = 0, 1   # qflow_tuning.davidson
+
+
+class Tuning(ctypes.Structure):
+    """qflow_tuning: the context's launch choices."""
+    _fields_ = [("davidson", ctypes.c_int32), ("split_target", ctypes.c_int32),
+                ("f64_tile", ctypes.c_int32), ("z_mode", ctypes.c_int32),
+                ("block_44", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 _STATUS = {
     0: "QFLOW_OK", -1: "QFLOW_E_INVALID_ARG", -2: "QFLOW_E_SYMMETRY", -3: "QFLOW_E_OOM",
@@ -72,6 +83,10 @@ def lib() -> ctypes.CDLL:
             "qflow_set_z_mode": (ctypes.c_int, [vp, ctypes.c_int]),
             "qflow_set_solver": (ctypes.c_int, [vp, d, i32]),
             "qflow_last_solve": (ctypes.c_int, [vp, i32, vp, vp]),
+            "qflow_set_tuning": (ctypes.c_int, [vp, vp]),
+            "qflow_get_tuning": (ctypes.c_int, [vp, vp]),
+            "qflow_autotune": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, i32, ctypes.c_char_p,
+                                              vp, vp, i32]),
             "qflow_sample_spaces": (ctypes.c_int, [i32, i32, i32, i32, vp, vp, i64, i32, vp, vp,
                                                    i32, vp, vp]),
             "qflow_build_owners": (ctypes.c_int, [i32, i32, i32, vp, vp, vp]),
@@ -227,6 +242,33 @@ class Context:
         """How build_heff forms the sigma1 x two-body terms: Z_AUTO, Z_SPACE
         or Z_DENSE (module constants)."""
         self._check(lib().qflow_set_z_mode(self.h, int(mode)))
+
+    def set_tuning(self, davidson=None, split_target=None, f64_tile=None, z_mode=None,
+                   block_44=None):
+        """Change some of the launch choices (None keeps the current value)."""
+        t = self.get_tuning()
+        for name, val in (("davidson", davidson), ("split_target", split_target),
+                          ("f64_tile", f64_tile), ("z_mode", z_mode), ("block_44", block_44)):
+            if val is not None:
+                setattr(t, name, int(val))
+        self._check(lib().qflow_set_tuning(self.h, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        self._check(lib().qflow_get_tuning(self.h, ctypes.byref(t)))
+        return t
+
+    def autotune(self, spaces, owner1, owner2, t1, t2, flags=FP64, cache_path=None):
+        """Choose and apply the launch choices by timing flow steps; returns
+        (Tuning, report text).  t1, t2 are read, not changed."""
+        sp = _spaces(spaces)
+        t = Tuning()
+        rep = ctypes.create_string_buffer(8192)
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(lib().qflow_autotune(self.h, len(sp), _ptr(sp), _ptr(owner1), _ptr(owner2),
+                                         _ptr(t1), _ptr(t2), int(flags), path, ctypes.byref(t),
+                                         rep, len(rep)))
+        return t, rep.value.decode()
 
     def last_solve(self, K):
         """(iters, status) of the last flow step's eigensolves, numpy int32."""

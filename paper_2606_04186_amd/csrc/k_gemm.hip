@@ -28,6 +28,16 @@ namespace {
 // (C + z*M*N) and k_sum_slices adds the slices in order.
 // ---------------------------------------------------------------------------
 
+GemmTuning g_tune{};
+constexpr int kComputeUnits = 256;
+long split_target_workgroups() { return (long)g_tune.split_target * kComputeUnits; }
+// FP64 tile: 128 x 96 when it pads N less than 128 x 128 (f64_tile 0)
+bool f64_tile_4x3(int N) {
+  if (g_tune.f64_tile == 1) return true;
+  if (g_tune.f64_tile == 2) return false;
+  return (long)((N + 95) / 96) * 96 < (long)((N + 127) / 128) * 128;
+}
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBK = 16;
@@ -421,7 +431,7 @@ void launch_tiles(const T* A, const T* B, double* C, double* part, size_t part_c
   const long tiles = (long)tiles_n * tiles_m;
   // split K until about four workgroups per compute unit are available,
   // keeping at least eight K steps per split and the slices within `part`
-  constexpr long kTarget = 4 * 256;
+  const long kTarget = split_target_workgroups();
   const size_t mn = (size_t)M * N;
   int splits = 1;
   if (tiles < kTarget && part != nullptr) {
@@ -465,7 +475,7 @@ void launch_tiles_batch(const GemmBatch& gb, int nb, double* part, size_t part_c
   constexpr int BM = 32 * TM, BN = 32 * TN;
   const int tiles_n = (N + BN - 1) / BN, tiles_m = (M + BM - 1) / BM;
   const long tiles = (long)tiles_n * tiles_m * nb;
-  constexpr long kTarget = 4 * 256;
+  const long kTarget = split_target_workgroups();
   const size_t mn = (size_t)M * N;
   int splits = 1;
   if (tiles < kTarget && part != nullptr) {
@@ -492,14 +502,13 @@ template <class T>
 void launch_gemm(const T* A, const T* B, double* C, int M, int N, int K, double scale,
                  double* part, size_t part_cap, hipStream_t st) {
   if (M <= 0 || N <= 0) return;
-  // 128 x 96 tiles when they pad N less than 128 x 128 tiles do
-  const long pad4 = (long)((N + 127) / 128) * 128, pad3 = (long)((N + 95) / 96) * 96;
+  // 128 x 96 or 128 x 128 tiles (f64_tile_4x3)
   // (FP32 operands always take 128 x 96: the wider tile does not fit the
   // registers with its FP64 accumulators)
   if constexpr (sizeof(T) == 4) {
     launch_tiles<4, 3>(A, B, C, part, part_cap, M, N, K, scale, st);
   } else {
-    if (pad3 < pad4)
+    if (f64_tile_4x3(N))
       launch_tiles<4, 3>(A, B, C, part, part_cap, M, N, K, scale, st);
     else
       launch_tiles<4, 4>(A, B, C, part, part_cap, M, N, K, scale, st);
@@ -513,7 +522,7 @@ void launch_tiles_bf16x3(const __bf16* Ah, const __bf16* Al, const __bf16* Bh, c
   constexpr int BM = 32 * TM, BN = 32 * TN;
   const int tiles_n = (N + BN - 1) / BN, tiles_m = (M + BM - 1) / BM;
   const long tiles = (long)tiles_n * tiles_m;
-  constexpr long kTarget = 4 * 256;
+  const long kTarget = split_target_workgroups();
   const size_t mn = (size_t)M * N;
   int splits = 1;
   if (tiles < kTarget && part != nullptr) {
@@ -546,6 +555,8 @@ void launch_gemm_nt_bf16x3(const __bf16* Ah, const __bf16* Al, const __bf16* Bh,
   launch_tiles_bf16x3<4, 3>(Ah, Al, Bh, Bl, C, part, part_cap, M, N, Kp, scale, st);
 }
 
+void set_gemm_tuning(const GemmTuning& t) { g_tune = t; }
+
 void launch_split_bf16(const double* src, int rows, int K, int Kp, __bf16* hi, __bf16* lo,
                        hipStream_t st) {
   k_split_bf16<<<grid_for((size_t)rows * Kp, kBlock, 65536), kBlock, 0, st>>>(src, rows, K, Kp,
@@ -568,8 +579,7 @@ int launch_gemm_nt_f64_batch(const double* const* A, const double* const* B, dou
     gb.B[b] = B[b];
     gb.C[b] = C[b];
   }
-  const long pad4 = (long)((N + 127) / 128) * 128, pad3 = (long)((N + 95) / 96) * 96;
-  if (pad3 < pad4)
+  if (f64_tile_4x3(N))
     launch_tiles_batch<4, 3>(gb, nb, part, part_cap, M, N, K, scale, st);
   else
     launch_tiles_batch<4, 4>(gb, nb, part, part_cap, M, N, K, scale, st);

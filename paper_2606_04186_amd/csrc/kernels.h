@@ -69,6 +69,15 @@ void launch_pack_j_B(const double* t2, int o, int v, double* B1, double* B2, hip
 // for no split) and the slices are summed in a fixed order, so the result is
 // deterministic.
 constexpr int kMaxSplits = 128;
+// Launch choices of the matrix-core products (set by the context before it
+// enqueues them): K is split until about split_target workgroups per compute
+// unit are available; f64_tile picks the FP64 tile (0: the one that pads N
+// less, 1: 128 x 96, 2: 128 x 128).
+struct GemmTuning {
+  int split_target = 4;
+  int f64_tile = 0;
+};
+void set_gemm_tuning(const GemmTuning& t);
 // nb (1..4) products C[b] = scale A[b] B[b]^T of one shape in one launch
 // (host arrays of device pointers); -1 for another nb.
 int launch_gemm_nt_f64_batch(const double* const* A, const double* const* B, double* const* C,
@@ -169,12 +178,15 @@ struct DavidsonArgs {
   int max_iter;
   int maxsub;
   int K;
+  int* counter = nullptr;     // work counter of the persistent launch (one int)
+  int big_block = 512;        // threads per (4,4) space in per-class launches: 512 or 1024
 };
 // Memory of one space's solve (doubles): LDS holds the integrals, the
-// same-spin string Hamiltonian, the vector sigma reads, the subspace problem
-// and the replacement lists; the basis and its sigma vectors sit in the
+// same-spin string Hamiltonian, the full vector sigma reads, the subspace
+// problem and the replacement lists; the basis and its sigma vectors (spin-
+// flip symmetric, kept as their halves of ns (ns + 1) / 2 entries) sit in the
 // space's global work area, and so do the diagonal, Ritz sigma and residual
-// vectors when they would not fit in LDS as well (the (4,4) class).
+// halves when they would not fit in LDS as well (the (4,4) class).
 struct DavLayout {
   int lds;        // doubles of dynamic LDS
   int64_t work;   // doubles of global work
@@ -184,19 +196,27 @@ constexpr int kDavBigDets = 1024;
 // threads per space: 256, and 512 for the (4,4) class, whose LDS admits one
 // block per compute unit (two wavefronts per SIMD hide the LDS gathers)
 __host__ __device__ constexpr int dav_block(int na) { return na >= 8 ? 512 : 256; }
-__host__ __device__ constexpr DavLayout dav_layout(int na, int ne, int maxsub) {
+// (blk: threads of the workgroup solving the space; 0 = dav_block(na))
+__host__ __device__ constexpr DavLayout dav_layout(int na, int ne, int maxsub, int blk = 0) {
   int ns = 1;
   for (int i = 0; i < ne; ++i) ns = ns * (na - i) / (i + 1);
-  const int D = ns * ns, nrep = ne * (1 + na - ne), n4 = na * na * na * na;
+  const int D = ns * ns, DU = ns * (ns + 1) / 2, nrep = ne * (1 + na - ne),
+            n4 = na * na * na * na;
   const bool big = D > kDavBigDets;
   const int lds = n4 + ns * (ns | 1) + D + 3 * maxsub * maxsub + maxsub + 4 +
-                  dav_block(na) / 64 * maxsub + (ns * nrep + 1) / 2 + (big ? 0 : 3 * D);
-  return DavLayout{lds, (int64_t)(2 * maxsub + (big ? 3 : 0)) * D, big};
+                  (blk > 0 ? blk : dav_block(na)) / 64 * maxsub + (ns * nrep + 1) / 2 +
+                  (big ? 0 : 3 * DU);
+  return DavLayout{lds, (int64_t)(2 * maxsub + (big ? 3 : 0)) * DU, big};
 }
-// One launch per size class: cls_idx lists the spaces of class c (nocc =
-// c + 2) at [cls_off[c], cls_off[c+1]) (cls_off on the host, 4 entries).
+// cls_idx lists the spaces of class c (nocc = c + 2) at [cls_off[c],
+// cls_off[c+1]) (cls_off on the host, 4 entries).  persistent = false: one
+// launch per size class, a workgroup per space.  persistent = true: one
+// launch over every class; as many workgroups as fit on the device (threads
+// and LDS sized for the largest class present) take spaces from the counter
+// a.counter (reset by the launch, on the stream), the largest class first,
+// until the list is exhausted.
 void launch_davidson(const DavidsonArgs& a, const int32_t* cls_idx, const int* cls_off,
-                     hipStream_t st);
+                     hipStream_t st, bool persistent = false);
 
 // pool update
 void launch_update(const double* t1, const double* t2, const double* r1, const double* r2,

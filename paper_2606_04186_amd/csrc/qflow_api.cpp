@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -155,6 +157,10 @@ struct qflow_ctx {
   // stopping rule of the flow steps' eigensolves (qflow_set_solver)
   double dav_tol = 1e-10;
   int dav_max_iter = 200;
+  // launch choices (qflow_set_tuning / qflow_autotune); z_mode lives above
+  int dav_persistent = 0, split_target = 4, f64_tile = 0, block_44 = 512;
+  DevBuf dav_counter;          // work counter of the persistent Davidson launch
+  DevBuf tune_t1, tune_t2, tune_e;   // the autotuner's copies of the pool, energies
 };
 
 namespace {
@@ -448,6 +454,10 @@ int prepare(qflow_ctx* ctx, const double* t1, const double* t2, int precision) {
     return fail(ctx, QFLOW_E_UNSUPPORTED, "unknown precision");
   const bool mixed = precision == QFLOW_FP32;
   const bool bf3 = precision == QFLOW_BF16X3;
+  qf::GemmTuning gt;
+  gt.split_target = ctx->split_target;
+  gt.f64_tile = ctx->f64_tile;
+  qf::set_gemm_tuning(gt);
   if (mixed) QF_TRY(ensure_mixed(ctx));
   if (bf3) QF_TRY(ensure_bf16(ctx));
   const int n = ctx->n, o = ctx->o, v = ctx->v;
@@ -702,7 +712,8 @@ int qflow_create(qflow_ctx** out, int device, void* hip_stream) {
       hipMemcpy(ctx->tasks.p, task_tab.data(), sizeof(int32_t) * task_tab.size(),
                 hipMemcpyHostToDevice) != hipSuccess ||
       ensure(ctx, ctx->scal, sizeof(double) * 8) != QFLOW_OK ||
-      ensure(ctx, ctx->out2, sizeof(double) * 2) != QFLOW_OK) {
+      ensure(ctx, ctx->out2, sizeof(double) * 2) != QFLOW_OK ||
+      ensure(ctx, ctx->dav_counter, sizeof(int) * 2) != QFLOW_OK) {
     qflow_destroy(ctx);
     return QFLOW_E_DEVICE;
   }
@@ -734,7 +745,8 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->c0,     &ctx->iters,    &ctx->status, &ctx->spaces,   &ctx->strings,
                     &ctx->out2,   &ctx->partial, &ctx->tasks, &ctx->mtab,   &ctx->cls_idx,
                     &ctx->diis_t, &ctx->diis_e, &ctx->diis_part, &ctx->diis_state,
-                    &ctx->win_idx, &ctx->t1s,    &ctx->t2s};
+                    &ctx->win_idx, &ctx->t1s,    &ctx->t2s,
+                    &ctx->dav_counter, &ctx->tune_t1, &ctx->tune_t2, &ctx->tune_e};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -1031,7 +1043,9 @@ int run_solve(qflow_ctx* ctx, int32_t K, const double* heff, const int64_t* heff
   a.max_iter = max_iter;
   a.maxsub = kMaxSub;
   a.K = K;
-  qf::launch_davidson(a, idx, cls_off, ctx->stream);
+  a.counter = P<int>(ctx->dav_counter);
+  a.big_block = ctx->block_44;
+  qf::launch_davidson(a, idx, cls_off, ctx->stream, ctx->dav_persistent != 0);
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -1202,30 +1216,31 @@ int qflow_solve_active_batch_static(qflow_ctx* ctx, int32_t K, const qflow_space
     idx.insert(idx.end(), cls[c].begin(), cls[c].end());
   }
   cls_off[3] = (int)idx.size();
-  // scratch layout, each section 256-byte aligned: descriptors | class
-  // lists | heff, amp, ci and work offsets | Davidson work areas
+  // scratch layout, each section 256-byte aligned: work counter of the
+  // persistent launch | descriptors | class lists | heff, amp, ci and work
+  // offsets | Davidson work areas
   auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-  const size_t b_sp = up(sizeof(SpaceDev) * K), b_idx = up(sizeof(int32_t) * K),
+  const size_t b_ctr = 256, b_sp = up(sizeof(SpaceDev) * K), b_idx = up(sizeof(int32_t) * K),
                b_off = up(sizeof(int64_t) * (K + 1));
-  const size_t head = b_sp + b_idx + 4 * b_off;
+  const size_t head = b_ctr + b_sp + b_idx + 4 * b_off;
   const size_t need = head + sizeof(double) * (size_t)work_off[K];
   if (need > (size_t)QFLOW_STATIC_SCRATCH_BYTES)
     return fail(ctx, QFLOW_E_UNSUPPORTED,
                 "batch needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
                     std::to_string((size_t)QFLOW_STATIC_SCRATCH_BYTES));
   std::vector<unsigned char> host(head, 0);
-  std::memcpy(host.data(), dev.data(), sizeof(SpaceDev) * K);
-  std::memcpy(host.data() + b_sp, idx.data(), sizeof(int32_t) * K);
-  unsigned char* offs = host.data() + b_sp + b_idx;
+  std::memcpy(host.data() + b_ctr, dev.data(), sizeof(SpaceDev) * K);
+  std::memcpy(host.data() + b_ctr + b_sp, idx.data(), sizeof(int32_t) * K);
+  unsigned char* offs = host.data() + b_ctr + b_sp + b_idx;
   std::memcpy(offs, heff_off, sizeof(int64_t) * (K + 1));
   std::memcpy(offs + b_off, amp_off, sizeof(int64_t) * (K + 1));
   if (ci_warm) std::memcpy(offs + 2 * b_off, ci_off, sizeof(int64_t) * (K + 1));
   std::memcpy(offs + 3 * b_off, work_off.data(), sizeof(int64_t) * (K + 1));
   unsigned char* base = static_cast<unsigned char*>(ctx->scratch);
-  unsigned char* d_offs = base + b_sp + b_idx;
+  unsigned char* d_offs = base + b_ctr + b_sp + b_idx;
   QF_HIP(hipMemcpyAsync(base, host.data(), head, hipMemcpyHostToDevice, ctx->stream));
   qf::DavidsonArgs a;
-  a.spaces = reinterpret_cast<const SpaceDev*>(base);
+  a.spaces = reinterpret_cast<const SpaceDev*>(base + b_ctr);
   a.strings = P<qf::Strings>(ctx->strings);
   a.heff = heff;
   a.heff_off = reinterpret_cast<const int64_t*>(d_offs);
@@ -1243,7 +1258,10 @@ int qflow_solve_active_batch_static(qflow_ctx* ctx, int32_t K, const qflow_space
   a.max_iter = max_iter;
   a.maxsub = kMaxSub;
   a.K = K;
-  qf::launch_davidson(a, reinterpret_cast<const int32_t*>(base + b_sp), cls_off, ctx->stream);
+  a.counter = reinterpret_cast<int*>(base);
+  a.big_block = ctx->block_44;
+  qf::launch_davidson(a, reinterpret_cast<const int32_t*>(base + b_ctr + b_sp), cls_off,
+                      ctx->stream, ctx->dav_persistent != 0);
   const hipError_t el = hipGetLastError();
   // the host records must outlive the copy
   QF_HIP(hipStreamSynchronize(ctx->stream));
@@ -1431,6 +1449,203 @@ int qflow_set_solver(qflow_ctx* ctx, double tol, int32_t max_iter) {
   ctx->dav_tol = tol;
   ctx->dav_max_iter = max_iter;
   ++ctx->epoch;   // a captured step holds the old values in its kernel arguments
+  return QFLOW_OK;
+}
+
+int qflow_set_tuning(qflow_ctx* ctx, const qflow_tuning* t) {
+  if (!ctx) return QFLOW_E_INVALID_ARG;
+  if (!t) return fail(ctx, QFLOW_E_INVALID_ARG, "NULL tuning");
+  if ((t->davidson != QFLOW_DAV_PER_CLASS && t->davidson != QFLOW_DAV_PERSISTENT) ||
+      t->split_target < 1 || t->split_target > 16 || t->f64_tile < 0 || t->f64_tile > 2 ||
+      (t->z_mode != QFLOW_Z_AUTO && t->z_mode != QFLOW_Z_SPACE && t->z_mode != QFLOW_Z_DENSE) ||
+      (t->block_44 != 512 && t->block_44 != 1024))
+    return fail(ctx, QFLOW_E_INVALID_ARG, "tuning value out of range");
+  ctx->dav_persistent = t->davidson;
+  ctx->block_44 = t->block_44;
+  ctx->split_target = t->split_target;
+  ctx->f64_tile = t->f64_tile;
+  return qflow_set_z_mode(ctx, t->z_mode);   // bumps the epoch (graph re-capture)
+}
+
+int qflow_get_tuning(const qflow_ctx* ctx, qflow_tuning* t) {
+  if (!ctx || !t) return QFLOW_E_INVALID_ARG;
+  t->davidson = ctx->dav_persistent;
+  t->split_target = ctx->split_target;
+  t->f64_tile = ctx->f64_tile;
+  t->z_mode = ctx->z_mode;
+  t->block_44 = ctx->block_44;
+  return QFLOW_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+std::string tune_key(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, int flags) {
+  int cls[3] = {0, 0, 0};
+  for (int k = 0; k < K; ++k) ++cls[spaces[k].n_o - 2];
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
+  std::ostringstream k;
+  k << "n=" << ctx->n << " o=" << ctx->o << " classes=" << cls[0] << "/" << cls[1] << "/"
+    << cls[2] << " precision=" << (flags & 15) << " graph=" << ((flags & QFLOW_GRAPH) ? 1 : 0)
+    << " arch=" << arch;
+  return k.str();
+}
+
+bool read_int_field(const std::string& line, const char* name, int* v) {
+  const std::string pat = std::string("\"") + name + "\":";
+  const size_t p = line.find(pat);
+  if (p == std::string::npos) return false;
+  return std::sscanf(line.c_str() + p + pat.size(), " %d", v) == 1;
+}
+
+// Entries of the cache file: one `"key": {...}` per line.
+std::vector<std::pair<std::string, std::string>> read_cache(const char* path) {
+  std::vector<std::pair<std::string, std::string>> out;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t a = line.find('"');
+    const size_t b = a == std::string::npos ? a : line.find("\": {", a + 1);
+    const size_t c = line.rfind('}');
+    if (a == std::string::npos || b == std::string::npos || c == std::string::npos || c < b)
+      continue;
+    out.emplace_back(line.substr(a + 1, b - a - 1), line.substr(b + 3, c - b - 2));
+  }
+  return out;
+}
+
+bool write_cache(const char* path, const std::vector<std::pair<std::string, std::string>>& e) {
+  std::ofstream f(path, std::ios::trunc);
+  if (!f) return false;
+  f << "{\n";
+  for (size_t i = 0; i < e.size(); ++i)
+    f << "\"" << e[i].first << "\": " << e[i].second << (i + 1 < e.size() ? ",\n" : "\n");
+  f << "}\n";
+  return (bool)f;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qflow_autotune(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const int32_t* owner1,
+                   const int32_t* owner2, const double* t1, const double* t2, int32_t flags,
+                   const char* cache_path, qflow_tuning* out, char* report, int32_t report_len) {
+  QF_TRY(require_loaded(ctx));
+  QF_TRY(check_spaces(ctx, K, spaces));
+  if (!owner1 || !owner2 || !t1 || !t2) return fail(ctx, QFLOW_E_INVALID_ARG, "NULL argument");
+  const int precision = flags & 15;
+  if (precision != QFLOW_FP64 && precision != QFLOW_FP32 && precision != QFLOW_BF16X3)
+    return fail(ctx, QFLOW_E_UNSUPPORTED, "unknown precision");
+  flags &= ~QFLOW_DIIS;
+  QF_HIP(hipSetDevice(ctx->device));
+  const std::string key = tune_key(ctx, K, spaces, flags);
+  std::ostringstream rep;
+  auto finish = [&](const qflow_tuning& t) {
+    if (out) *out = t;
+    if (report && report_len > 0) {
+      const std::string r = rep.str();
+      const size_t n = std::min((size_t)report_len - 1, r.size());
+      std::memcpy(report, r.data(), n);
+      report[n] = '\0';
+    }
+  };
+  std::vector<std::pair<std::string, std::string>> cache;
+  if (cache_path) {
+    cache = read_cache(cache_path);
+    for (auto& e : cache)
+      if (e.first == key) {
+        qflow_tuning t{};
+        if (read_int_field(e.second, "davidson", &t.davidson) &&
+            read_int_field(e.second, "split_target", &t.split_target) &&
+            read_int_field(e.second, "f64_tile", &t.f64_tile) &&
+            read_int_field(e.second, "z_mode", &t.z_mode) &&
+            read_int_field(e.second, "block_44", &t.block_44) &&
+            qflow_set_tuning(ctx, &t) == QFLOW_OK) {
+          rep << "cached: " << key << " -> " << e.second << "\n";
+          finish(t);
+          return QFLOW_OK;
+        }
+      }
+  }
+  const size_t n1 = (size_t)ctx->o * ctx->v, n2 = n1 * n1;
+  QF_TRY(ensure(ctx, ctx->tune_t1, sizeof(double) * n1));
+  QF_TRY(ensure(ctx, ctx->tune_t2, sizeof(double) * n2));
+  QF_TRY(ensure(ctx, ctx->tune_e, sizeof(double) * std::max(K, 1)));
+  // one candidate: the same start pool, cold eigensolver starts, one untimed
+  // and three timed flow steps
+  auto measure = [&](const qflow_tuning& t, float* ms) -> int {
+    QF_TRY(qflow_set_tuning(ctx, &t));
+    QF_TRY(upload_spaces(ctx, K, spaces));
+    qf::launch_copy(t1, P<double>(ctx->tune_t1), n1, ctx->stream);
+    qf::launch_copy(t2, P<double>(ctx->tune_t2), n2, ctx->stream);
+    qf::launch_fill(P<double>(ctx->ci), ctx->ci.bytes / sizeof(double), 0.0, ctx->stream);
+    double em = 0.0, dt = 0.0;
+    float total = 0.f;
+    for (int s = 0; s < 4; ++s) {
+      QF_TRY(qflow_flow_step(ctx, K, spaces, owner1, owner2, P<double>(ctx->tune_t1),
+                             P<double>(ctx->tune_t2), P<double>(ctx->tune_e), &em, &dt, flags));
+      if (s > 0) total += ctx->total_ms;
+    }
+    *ms = total / 3.f;
+    rep << "davidson=" << t.davidson << " split_target=" << t.split_target
+        << " f64_tile=" << t.f64_tile << " z_mode=" << t.z_mode << " block_44=" << t.block_44
+        << ": " << *ms << " ms\n";
+    return QFLOW_OK;
+  };
+  qflow_tuning best{};
+  QF_TRY(qflow_get_tuning(ctx, &best));
+  float best_ms = 0.f;
+  QF_TRY(measure(best, &best_ms));
+  bool has44 = false;
+  for (int k = 0; k < K; ++k) has44 = has44 || spaces[k].n_o == 4;
+  std::vector<std::vector<int>> values = {{QFLOW_DAV_PER_CLASS, QFLOW_DAV_PERSISTENT},
+                                          {2, 4, 8},
+                                          precision == QFLOW_FP64 ? std::vector<int>{0, 1, 2}
+                                                                  : std::vector<int>{best.f64_tile},
+                                          {QFLOW_Z_SPACE, QFLOW_Z_DENSE},
+                                          has44 ? std::vector<int>{512, 1024}
+                                                : std::vector<int>{best.block_44}};
+  for (int d = 0; d < 5; ++d)
+    for (int val : values[d]) {
+      qflow_tuning c = best;
+      int* field[5] = {&c.davidson, &c.split_target, &c.f64_tile, &c.z_mode, &c.block_44};
+      if (*field[d] == val) continue;
+      *field[d] = val;
+      float ms = 0.f;
+      QF_TRY(measure(c, &ms));
+      if (ms < best_ms) {
+        best = c;
+        best_ms = ms;
+      }
+    }
+  QF_TRY(qflow_set_tuning(ctx, &best));
+  // the caller's next step: cold eigensolver starts, no DIIS history
+  qf::launch_fill(P<double>(ctx->ci), ctx->ci.bytes / sizeof(double), 0.0, ctx->stream);
+  ctx->diis_active = false;
+  QF_HIP(hipStreamSynchronize(ctx->stream));
+  rep << "chosen: davidson=" << best.davidson << " split_target=" << best.split_target
+      << " f64_tile=" << best.f64_tile << " z_mode=" << best.z_mode
+      << " block_44=" << best.block_44 << " (" << best_ms << " ms)\n";
+  if (cache_path) {
+    std::ostringstream v;
+    v << "{\"davidson\": " << best.davidson << ", \"split_target\": " << best.split_target
+      << ", \"f64_tile\": " << best.f64_tile << ", \"z_mode\": " << best.z_mode
+      << ", \"block_44\": " << best.block_44 << ", \"ms\": " << best_ms << "}";
+    bool found = false;
+    for (auto& e : cache)
+      if (e.first == key) {
+        e.second = v.str();
+        found = true;
+      }
+    if (!found) cache.emplace_back(key, v.str());
+    if (!write_cache(cache_path, cache))
+      return fail(ctx, QFLOW_E_INVALID_ARG, std::string("cannot write ") + cache_path);
+  }
+  finish(best);
   return QFLOW_OK;
 }
 

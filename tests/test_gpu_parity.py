@@ -518,11 +518,14 @@ def test_heff_size_classes_match_oracle(zmode):
         assert np.abs(blk[1 + na * na:].reshape(na, na, na, na) - g).max() < 1e-11, k
 
 
-@pytest.mark.parametrize("flags", ["fp64", "graph", "dense", "graph-dense"])
+@pytest.mark.parametrize("flags", ["fp64", "graph", "dense", "graph-dense", "per-class",
+                                   "graph-per-class"])
 def test_flow_step_size_classes_matches_oracle(flags):
     """One macro-iteration over (2,2), (3,3) and (4,4) spaces (36, 400 and
     4900 determinants) against the oracle: energies, eigenvector-derived
-    amplitudes through the pool update."""
+    amplitudes through the pool update; the eigensolves as one persistent
+    launch over all classes or one launch per class (the (4,4) class with 512
+    or 1024 threads)."""
     _need_gpu()
     import paper_2606_04186_amd as qf
     n, o, seed = 16, 5, 162
@@ -535,6 +538,10 @@ def test_flow_step_size_classes_matches_oracle(flags):
     sp = qf.make_spaces(lists)
     ctx = context(h, eri, o)
     _z_mode(ctx, "dense" if "dense" in flags else "space")
+    if "per-class" in flags:
+        ctx.set_tuning(davidson=qf.api.DAV_PER_CLASS, block_44=1024 if "graph" in flags else 512)
+    else:
+        ctx.set_tuning(davidson=qf.api.DAV_PERSISTENT)
     g1, g2 = dev(t1), dev(t2)
     energy = torch.zeros(len(lists), dtype=torch.float64, device="cuda")
     flag = qf.GRAPH if flags.startswith("graph") else qf.FP64

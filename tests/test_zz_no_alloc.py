@@ -98,7 +98,7 @@ def test_static_scratch_refuses_an_oversized_batch():
     h, eri = synth.gen_integrals(n, o, 2 * n, 172, b_std=0.04, off_std=0.03)
     ctx = qf.Context(0)
     ctx.load_integrals(torch.from_numpy(h).cuda(), torch.from_numpy(eri).cuda(), o)
-    per_space = 8 * 24 * 400          # Davidson work of one (3,3) space, bytes
+    per_space = 8 * 24 * 210          # Davidson work of one (3,3) space, bytes (half vectors)
     K = qf.api.STATIC_SCRATCH_BYTES // per_space + 1
     sp = qf.make_spaces([((0, 1, 2), (5, 6, 7))] * K)
     hoff = qf.api.offsets(sp[:1], qf.heff_size)
