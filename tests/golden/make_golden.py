@@ -1,6 +1,6 @@
 """Write the oracle's expected values for the larger workloads.
 
-    python tests/golden/make_golden.py c2|c3|c4 [--workers W]
+    python tests/golden/make_golden.py c2|c3|c4|vqe [--workers W]
 
 Calls only ``oracle`` (the plain FP64 CPU implementation) and ``synth`` (the
 seeded inputs); nothing here comes from the HIP path.  The active spaces are
@@ -21,6 +21,13 @@ amplitudes no space owns.
   sampled spaces (energies, local cluster amplitudes) and the pool on a
   sampled block after it.  With --full, the whole first iteration is taken
   and the second one is stored for the sampled spaces as for c3.
+
+* vqe (16 and 24 orbitals, 4 occupied; (2,2) and (3,3) spaces of Algorithm
+  1): the UCCSD-VQE solver of oracle.vqe.  Two VQE macro-iterations from MP2
+  on 16 orbitals (every space's energy, the mean and the whole pool after
+  each), and batch solves of the spaces from the pool's own amplitudes
+  (16 orbitals) and from zero (24 orbitals) with their energies and
+  parameters.
 
 Sampled spaces: 16 positions evenly spread over the Delta-eps order, the
 first replaced where needed so that the sample holds a space with the first
@@ -43,7 +50,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 import synth  # noqa: E402
-from oracle import qflow, sampling  # noqa: E402
+from oracle import qflow, sampling, vqe  # noqa: E402
 
 
 def workload(name):
@@ -153,15 +160,75 @@ def make_two_steps(name, workers, full):
     np.savez_compressed(os.path.join(HERE, f"qflow_{name}_{tag}.npz"), **out)
 
 
+# (n, o, seed, caps of the (2,2) and (3,3) classes)
+VQE_FLOW = (16, 4, 731, (5, 2))
+VQE_SOLVE_POOL = (16, 4, 711, (5, 2))
+VQE_SOLVE_ZERO = (24, 4, 712, (4, 2))
+
+
+def vqe_inputs(n, o, seed, caps):
+    """Integrals (the stress recipe), the problem, the MP2 pool and the
+    spaces: Algorithm 1 per size class on its own stream, merged in Delta-eps
+    order."""
+    h, eri = synth.gen_integrals(n, o, 2 * n, seed, b_std=0.04, off_std=0.03)
+    pb = qflow.Problem(h, eri, o)
+    out = []
+    for size, cap in zip((2, 3), caps):
+        S = sampling.algorithm1(o, n - o, size, size, pb.eps, synth.Stream(seed + size), cap=cap)
+        out += [(tuple(s[0]), tuple(s[1]), s[2]) for s in S]
+    out.sort(key=lambda s: s[2])
+    spaces = [(s[0], s[1]) for s in out]
+    t1, t2 = qflow.mp2_guess(pb.f, eri, o)
+    return pb, spaces, t1, t2
+
+
+def local_amplitudes(t1, t2, occ, vir, o):
+    vv = [a - o for a in vir]
+    return np.concatenate([t1[np.ix_(occ, vv)].ravel(), t2[np.ix_(occ, occ, vv, vv)].ravel()])
+
+
+def make_vqe():
+    out = {}
+    pb, spaces, t1, t2 = vqe_inputs(*VQE_FLOW)
+    o, v = pb.o, pb.n - pb.o
+    o1, o2 = sampling.ownership(o, v, spaces)
+    for it in range(2):
+        t0 = time.time()
+        t1, t2, E, Em, _ = vqe.flow_step(pb, t1, t2, spaces, o1, o2)
+        out.update({f"flow_e_{it}": E, f"flow_mean_{it}": Em, f"flow_t1_{it}": t1,
+                    f"flow_t2_{it}": t2})
+        print(f"vqe flow step {it}: E_mean {Em:.12f} ({time.time() - t0:.1f} s)", flush=True)
+    for tag, case in (("pool", VQE_SOLVE_POOL), ("zero", VQE_SOLVE_ZERO)):
+        t0 = time.time()
+        pb, spaces, t1, t2 = vqe_inputs(*case)
+        E, amp = [], []
+        for occ, vir in spaces:
+            no, nv = len(occ), len(vir)
+            H = qflow.cas_matrix(*qflow.heff(pb, t1, t2, tuple(occ) + tuple(vir)), no)
+            th0 = None
+            if tag == "pool":
+                lt = local_amplitudes(t1, t2, occ, vir, pb.o)
+                th0 = vqe.pack(lt[:no * nv].reshape(no, nv), lt[no * nv:].reshape(no, no, nv, nv),
+                               no, nv)
+            s = vqe.solve(H, no, nv, theta0=th0)
+            E.append(s["E"])
+            amp.append(np.concatenate([s["t1"].ravel(), s["t2"].ravel()]))
+        out.update({f"solve_{tag}_e": np.array(E), f"solve_{tag}_amp": np.concatenate(amp)})
+        print(f"vqe solves ({tag}) done ({time.time() - t0:.1f} s)", flush=True)
+    np.savez_compressed(os.path.join(HERE, "qflow_vqe.npz"), **out)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["c2", "c3", "c4"])
+    ap.add_argument("config", choices=["c2", "c3", "c4", "vqe"])
     ap.add_argument("--workers", type=int, default=os.cpu_count())
     ap.add_argument("--full", action="store_true",
                     help="c4: take the whole first iteration and the sampled second")
     a = ap.parse_args()
     if a.config == "c2":
         make_c2(a.workers)
+    elif a.config == "vqe":
+        make_vqe()
     elif a.config == "c3":
         make_two_steps("c3", a.workers, True)
     else:
