@@ -68,7 +68,7 @@ enum {
   QFLOW_GRAPH = 1 << 5,          /* run the step's device work as a captured HIP graph,
                                     re-captured when K, flags, the array pointers or
                                     the context's buffers change */
-  QFLOW_DIIS = 1 << 6            /* Pulay DIIS on the pool vector [t1 | t2] after the
+  QFLOW_DIIS = 1 << 6,           /* Pulay DIIS on the pool vector [t1 | t2] after the
                                     update: the last 8 (updated pool, change) pairs;
                                     from the third consecutive DIIS step on, the pool
                                     becomes the combination of updated pools whose
@@ -77,6 +77,12 @@ enum {
                                     a pivot below 1e-14 max|B| drops the oldest pair).
                                     A step without the flag, a new space list or new
                                     integrals end the history. */
+  QFLOW_SOLVER_VQE = 1 << 7      /* solve the spaces with the UCCSD-VQE solver of
+                                    qflow_solve_vqe_batch, each started from the pool's
+                                    amplitudes of its orbitals, instead of the CI
+                                    eigensolver and its cluster analysis; every space
+                                    then writes its optimised parameters (stopping rule:
+                                    qflow_set_vqe).  (2,2) and (3,3) spaces only. */
 };
 
 /* Create a context on HIP device `device`; hip_stream is a hipStream_t to
@@ -169,6 +175,42 @@ int qflow_solve_active_batch(qflow_ctx* ctx, int32_t K, const qflow_space* space
                              double* c0, double* amp, const int64_t* amp_off, double* ci_warm,
                              const int64_t* ci_off, int32_t* iters, int32_t* status, double tol,
                              int32_t max_iter);
+
+/* The paper's own active-space solver ("Numerical Implementation"): per
+ * space, the UCCSD parameters theta of sigma_int = T - T^dagger (the space's
+ * spin-adapted singles t1[I][A] and doubles t2[I][J][A][B] = t2[J][I][B][A],
+ * T = sum t1 E_AI + 1/2 sum t2 E_AI E_BJ with spin-summed excitation
+ * operators, local indices) minimising the energy of Eq. (5) for the trial
+ * state e^{sigma_int} |Phi> of Eq. (8) at N = 1:
+ *   E(theta) = <Phi| e^{-sigma_int} H_eff e^{sigma_int} |Phi>,
+ * evaluated exactly in the space's determinant basis (the CAS matrix of
+ * qflow_solve_active_batch) in FP64: e^{sigma_int} applied by its Taylor
+ * series to 1e-17 relative, the exact gradient by 8-point Gauss-Legendre
+ * quadrature of the exponential's Frechet derivative, minimised by BFGS
+ * with an Armijo line search from the diagonal inverse Hessian
+ * 1 / (4 max(d, 0.05)) (d: excitation energy of the parameter's determinant)
+ * until the largest gradient entry is below gtol.
+ * heff, heff_off as for qflow_solve_active_batch.  theta0 (device): the start
+ * parameters in the amp layout (t1[n_o][n_v] then t2[n_o][n_o][n_v][n_v] per
+ * space at amp_off[k], host offsets, K+1 entries; t2 must be pair
+ * symmetric: the (I,A) <= (J,B) entry of each pair is read).  Outputs
+ * (device): amp (the optimised parameters, same layout, both entries of every
+ * pair; may be theta0 itself), energy[K] (E(theta)), iters[K] (BFGS
+ * iterations), status[K] (QFLOW_OK, or QFLOW_E_NOT_CONVERGED after max_iter
+ * iterations; max_iter = 0 only evaluates E(theta0)).  (2,2) and (3,3) spaces
+ * only (a (4,4) space's workgroup would need 1.6 MB of LDS):
+ * QFLOW_E_UNSUPPORTED otherwise.  Synchronises the stream. */
+int qflow_solve_vqe_batch(qflow_ctx* ctx, int32_t K, const qflow_space* spaces,
+                          const double* heff, const int64_t* heff_off, const double* theta0,
+                          double* amp, const int64_t* amp_off, double* energy, int32_t* iters,
+                          int32_t* status, double gtol, int32_t max_iter);
+
+/* Stopping rule of the VQE solves inside qflow_flow_step (QFLOW_SOLVER_VQE):
+ * largest gradient entry below gtol, at most max_iter BFGS iterations (the
+ * space then has status QFLOW_E_NOT_CONVERGED and writes none of its
+ * amplitudes).  Defaults: 1e-10, 500.  gtol <= 0 or max_iter < 0 is
+ * QFLOW_E_INVALID_ARG. */
+int qflow_set_vqe(qflow_ctx* ctx, double gtol, int32_t max_iter);
 
 /* Bytes of device memory qflow_solve_active_batch_static may use: 128 MiB,
  * held by every device the library runs on from its first context until the

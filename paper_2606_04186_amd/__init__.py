@@ -6,7 +6,8 @@ it does not load the library; ``lib()`` does, and raises if it was not built
 (``python -m paper_2606_04186_amd.build``).  There is no CPU fallback.
 """
 from .api import (  # noqa: F401
-    FP64, FP32, BF16X3, UNOWNED_FROZEN, GRAPH, DIIS, Z_AUTO, Z_SPACE, Z_DENSE, SPACE_DTYPE,
+    FP64, FP32, BF16X3, UNOWNED_FROZEN, GRAPH, DIIS, SOLVER_VQE, Z_AUTO, Z_SPACE, Z_DENSE,
+    SPACE_DTYPE,
     QFlowError, Context, lib,
     make_spaces, sample_spaces, build_owners, heff_size, amp_size, ci_size,
 )

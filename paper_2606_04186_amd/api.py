@@ -19,6 +19,7 @@ FP64, FP32, BF16X3 = 0, 1, 2
 UNOWNED_FROZEN = 1 << 4
 GRAPH = 1 << 5
 DIIS = 1 << 6
+SOLVER_VQE = 1 << 7
 Z_AUTO, Z_SPACE, Z_DENSE = 0, 1, 2   # qflow_z_mode
 STATIC_SCRATCH_BYTES = 128 * 1024 * 1024   # QFLOW_STATIC_SCRATCH_BYTES
 
@@ -76,6 +77,9 @@ def lib() -> ctypes.CDLL:
             "qflow_solve_active_batch_static": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp,
                                                                vp, vp, vp, vp, vp, vp, d,
                                                                i32]),
+            "qflow_solve_vqe_batch": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp,
+                                                     vp, d, i32]),
+            "qflow_set_vqe": (ctypes.c_int, [vp, d, i32]),
             "qflow_flow_step": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32]),
             "qflow_flow_sweep_windowed": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, i32, vp,
                                                          vp, i32]),
@@ -220,6 +224,19 @@ class Context:
             self.h, len(sp), _ptr(sp), _ptr(heff), _ptr(heff_off), _ptr(energy), _ptr(c0),
             _ptr(amp), _ptr(amp_off), _ptr(ci), _ptr(ci_off), _ptr(iters), _ptr(status), tol,
             max_iter))
+
+    def solve_vqe_batch(self, spaces, heff, heff_off, theta0, amp, amp_off, energy, iters,
+                        status, gtol=1e-10, max_iter=500):
+        """UCCSD-VQE solve of every space from the parameters theta0 (amp
+        layout); optimised parameters into amp (may be theta0)."""
+        sp = _spaces(spaces)
+        self._check(lib().qflow_solve_vqe_batch(
+            self.h, len(sp), _ptr(sp), _ptr(heff), _ptr(heff_off), _ptr(theta0), _ptr(amp),
+            _ptr(amp_off), _ptr(energy), _ptr(iters), _ptr(status), float(gtol), int(max_iter)))
+
+    def set_vqe(self, gtol=1e-10, max_iter=500):
+        """Stopping rule of the flow steps' VQE solves (SOLVER_VQE)."""
+        self._check(lib().qflow_set_vqe(self.h, float(gtol), int(max_iter)))
 
     def flow_step(self, spaces, owner1, owner2, t1, t2, energy, flags=FP64):
         sp = _spaces(spaces)

@@ -924,6 +924,34 @@ void launch_scatter_owned(const SpaceDev* spaces, const double* amp, const int64
                                          t1n, t2n);
 }
 
+// The inverse of the write-back without ownership: space k's slice of the
+// pool in the local amplitude layout (t1[I][A], then t2[I][J][A][B]).
+__global__ void k_gather_local(const SpaceDev* __restrict__ spaces,
+                               const int64_t* __restrict__ amp_off, const double* __restrict__ t1,
+                               const double* __restrict__ t2, int n, int o, double* out) {
+  const int k = blockIdx.x;
+  const SpaceDev& sp = spaces[k];
+  const int ne = sp.nocc, nv = sp.na - sp.nocc, v = n - o;
+  double* x = out + amp_off[k];
+  const int nt1 = ne * nv;
+  for (int e = threadIdx.x; e < nt1 + nt1 * nt1; e += blockDim.x) {
+    if (e < nt1) {
+      x[e] = t1[sp.orb[e / nv] * v + sp.orb[ne + e % nv] - o];
+    } else {
+      const int q = e - nt1;
+      const int b = q % nv, a = q / nv % nv, j = q / (nv * nv) % ne, i = q / (nv * nv * ne);
+      const int I = sp.orb[i], J = sp.orb[j], Av = sp.orb[ne + a] - o, Bv = sp.orb[ne + b] - o;
+      x[e] = t2[(((size_t)I * o + J) * v + Av) * v + Bv];
+    }
+  }
+}
+
+void launch_gather_local(const SpaceDev* spaces, const int64_t* amp_off, const double* t1,
+                         const double* t2, int n, int o, int K, double* out, hipStream_t st) {
+  if (K <= 0) return;
+  k_gather_local<<<K, kBlock, 0, st>>>(spaces, amp_off, t1, t2, n, o, out);
+}
+
 __global__ void k_merge_unowned(const double* __restrict__ t1n, const double* __restrict__ t2n,
                                 const int32_t* __restrict__ owner1,
                                 const int32_t* __restrict__ owner2, size_t nt1, size_t nt2,

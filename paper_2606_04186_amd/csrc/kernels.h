@@ -218,6 +218,34 @@ __host__ __device__ constexpr DavLayout dav_layout(int na, int ne, int maxsub, i
 void launch_davidson(const DavidsonArgs& a, const int32_t* cls_idx, const int* cls_off,
                      hipStream_t st, bool persistent = false);
 
+// UCCSD-VQE solve of every (2,2) and (3,3) space of the class lists: the
+// parameters of sigma_int minimising <Phi|e^-sigma H_eff e^sigma|Phi>, started
+// from theta0 (per space in the amp layout: t1[n_o][n_v] then
+// t2[n_o][n_o][n_v][n_v]); writes energy, the parameters (amp layout), iters
+// and status (0, or -5 when max_iter BFGS iterations did not bring the largest
+// gradient entry below gtol); c0 = 1.
+struct VqeArgs {
+  const SpaceDev* spaces;
+  const Strings* strings;
+  const double* heff;
+  const int64_t* heff_off;
+  const double* theta0;
+  const int64_t* amp_off;
+  double* energy;
+  double* c0;
+  double* amp;
+  int32_t* iters;
+  int32_t* status;
+  double gtol;
+  int max_iter;
+  int K;
+};
+int vqe_lds_bytes(int nocc);   // dynamic LDS of one space's workgroup (-1: unsupported)
+void launch_vqe(const VqeArgs& a, const int32_t* cls_idx, const int* cls_off, hipStream_t st);
+// the pool's amplitudes of every space into the amp layout (local indices)
+void launch_gather_local(const SpaceDev* spaces, const int64_t* amp_off, const double* t1,
+                         const double* t2, int n, int o, int K, double* out, hipStream_t st);
+
 // pool update
 void launch_update(const double* t1, const double* t2, const double* r1, const double* r2,
                    const double* f, const int32_t* owner1, const int32_t* owner2, int n, int o,

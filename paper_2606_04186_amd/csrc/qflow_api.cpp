@@ -161,6 +161,10 @@ struct qflow_ctx {
   int dav_persistent = 0, split_target = 4, f64_tile = 0, block_44 = 512;
   DevBuf dav_counter;          // work counter of the persistent Davidson launch
   DevBuf tune_t1, tune_t2, tune_e;   // the autotuner's copies of the pool, energies
+  // the UCCSD-VQE solver (QFLOW_SOLVER_VQE): stopping rule, start parameters
+  double vqe_gtol = 1e-10;
+  int vqe_max_iter = 500;
+  DevBuf vqe_theta;
 };
 
 namespace {
@@ -746,7 +750,8 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->out2,   &ctx->partial, &ctx->tasks, &ctx->mtab,   &ctx->cls_idx,
                     &ctx->diis_t, &ctx->diis_e, &ctx->diis_part, &ctx->diis_state,
                     &ctx->win_idx, &ctx->t1s,    &ctx->t2s,
-                    &ctx->dav_counter, &ctx->tune_t1, &ctx->tune_t2, &ctx->tune_e};
+                    &ctx->dav_counter, &ctx->tune_t1, &ctx->tune_t2, &ctx->tune_e,
+                    &ctx->vqe_theta};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -1050,12 +1055,53 @@ int run_solve(qflow_ctx* ctx, int32_t K, const double* heff, const int64_t* heff
   return QFLOW_OK;
 }
 
+// QFLOW_E_UNSUPPORTED unless every size class present in cls_off has a VQE
+// kernel whose workgroup fits the device's LDS.
+int check_vqe(qflow_ctx* ctx, const int* cls_off) {
+  for (int c = 0; c < 3; ++c) {
+    if (cls_off[c + 1] == cls_off[c]) continue;
+    const int bytes = qf::vqe_lds_bytes(c + 2);
+    if (bytes < 0 || bytes > ctx->lds_limit)
+      return fail(ctx, QFLOW_E_UNSUPPORTED,
+                  "the VQE solver takes (2,2) and (3,3) spaces only");
+  }
+  return QFLOW_OK;
+}
+
+// UCCSD-VQE solve of every space of the uploaded list from the parameters
+// theta0 (amp layout); results as run_solve's, with c0 = 1.
+int run_vqe(qflow_ctx* ctx, const double* heff, const int64_t* heff_off_dev,
+            const double* theta0, const int64_t* amp_off_dev, double* energy, double* amp,
+            int32_t* iters, int32_t* status, double gtol, int max_iter) {
+  const int K = ctx->cls_off[3];
+  if (K == 0) return QFLOW_OK;
+  QF_TRY(check_vqe(ctx, ctx->cls_off));
+  qf::VqeArgs a;
+  a.spaces = P<SpaceDev>(ctx->spaces);
+  a.strings = P<qf::Strings>(ctx->strings);
+  a.heff = heff;
+  a.heff_off = heff_off_dev;
+  a.theta0 = theta0;
+  a.amp_off = amp_off_dev;
+  a.energy = energy;
+  a.c0 = P<double>(ctx->c0);
+  a.amp = amp;
+  a.iters = iters;
+  a.status = status;
+  a.gtol = gtol;
+  a.max_iter = max_iter;
+  a.K = K;
+  qf::launch_vqe(a, P<int32_t>(ctx->cls_idx), ctx->cls_off, ctx->stream);
+  QF_HIP(hipGetLastError());
+  return QFLOW_OK;
+}
+
 // The device work of one flow step on ctx->stream: no allocation and no host
 // synchronisation, so that it can be captured into a graph.
 // With `timed` the stage boundaries are marked by events (not under capture).
 int enqueue_step(qflow_ctx* ctx, int32_t K, const int32_t* owner1, const int32_t* owner2,
                  double* t1, double* t2, double* energy, int precision, bool step, bool diis,
-                 bool timed) {
+                 bool timed, bool vqe = false) {
   const int n = ctx->n, o = ctx->o, v = ctx->v;
   hipStream_t st = ctx->stream;
   ctx->timed = timed;
@@ -1067,10 +1113,21 @@ int enqueue_step(qflow_ctx* ctx, int32_t K, const int32_t* owner1, const int32_t
   }
   if (r == QFLOW_OK) {
     if (timed) QF_HIP(hipEventRecord(ctx->ev[9], st));
-    r = run_solve(ctx, K, P<double>(ctx->heff), P<int64_t>(ctx->heff_off), P<double>(ctx->energy),
-                  P<double>(ctx->c0), P<double>(ctx->amp), P<int64_t>(ctx->amp_off),
-                  P<double>(ctx->ci), P<int64_t>(ctx->ci_off), P<int32_t>(ctx->iters),
-                  P<int32_t>(ctx->status), ctx->dav_tol, ctx->dav_max_iter);
+    if (vqe) {
+      // every space starts from the pool's amplitudes of its orbitals
+      qf::launch_gather_local(P<SpaceDev>(ctx->spaces), P<int64_t>(ctx->amp_off), t1, t2, n, o, K,
+                              P<double>(ctx->vqe_theta), st);
+      r = run_vqe(ctx, P<double>(ctx->heff), P<int64_t>(ctx->heff_off),
+                  P<double>(ctx->vqe_theta), P<int64_t>(ctx->amp_off), P<double>(ctx->energy),
+                  P<double>(ctx->amp), P<int32_t>(ctx->iters), P<int32_t>(ctx->status),
+                  ctx->vqe_gtol, ctx->vqe_max_iter);
+    } else {
+      r = run_solve(ctx, K, P<double>(ctx->heff), P<int64_t>(ctx->heff_off),
+                    P<double>(ctx->energy), P<double>(ctx->c0), P<double>(ctx->amp),
+                    P<int64_t>(ctx->amp_off), P<double>(ctx->ci), P<int64_t>(ctx->ci_off),
+                    P<int32_t>(ctx->iters), P<int32_t>(ctx->status), ctx->dav_tol,
+                    ctx->dav_max_iter);
+    }
   }
   ctx->timed = false;
   if (r != QFLOW_OK) return r;
@@ -1171,6 +1228,35 @@ int qflow_solve_active_batch(qflow_ctx* ctx, int32_t K, const qflow_space* space
   if (r == QFLOW_OK)
     r = run_solve(ctx, K, heff, d_hoff, energy, c0, amp, d_aoff, ci_warm, ci_warm ? d_coff : nullptr,
                   iters, status, tol, max_iter);
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(off.p);
+  return r;
+}
+
+int qflow_solve_vqe_batch(qflow_ctx* ctx, int32_t K, const qflow_space* spaces,
+                          const double* heff, const int64_t* heff_off, const double* theta0,
+                          double* amp, const int64_t* amp_off, double* energy, int32_t* iters,
+                          int32_t* status, double gtol, int32_t max_iter) {
+  QF_TRY(require_loaded(ctx));
+  QF_TRY(check_spaces(ctx, K, spaces));
+  if (!heff || !theta0 || !amp || !energy || !iters || !status)
+    return fail(ctx, QFLOW_E_INVALID_ARG, "NULL array argument");
+  if (!(gtol > 0.0) || max_iter < 0) return fail(ctx, QFLOW_E_INVALID_ARG, "bad gtol or max_iter");
+  QF_TRY(check_offsets(ctx, K, spaces, heff_off, qflow_heff_size, "heff_off"));
+  QF_TRY(check_offsets(ctx, K, spaces, amp_off, qflow_amp_size, "amp_off"));
+  QF_TRY(upload_spaces(ctx, K, spaces));
+  QF_TRY(check_vqe(ctx, ctx->cls_off));
+  DevBuf off;
+  QF_TRY(ensure(ctx, off, sizeof(int64_t) * 2 * (K + 1)));
+  int64_t* d_hoff = P<int64_t>(off);
+  int64_t* d_aoff = d_hoff + (K + 1);
+  int r = QFLOW_OK;
+  if (hipMemcpy(d_hoff, heff_off, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(d_aoff, amp_off, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice) != hipSuccess)
+    r = fail(ctx, QFLOW_E_DEVICE, "offset upload failed");
+  if (r == QFLOW_OK)
+    r = run_vqe(ctx, heff, d_hoff, theta0, d_aoff, energy, amp, iters, status, gtol, max_iter);
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipFree(off.p);
   return r;
@@ -1286,7 +1372,12 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
   if (precision == QFLOW_BF16X3) QF_TRY(ensure_bf16(ctx));
   const bool step = !(flags & QFLOW_UNOWNED_FROZEN);
   const bool diis = (flags & QFLOW_DIIS) != 0;
+  const bool vqe = (flags & QFLOW_SOLVER_VQE) != 0;
   hipStream_t st = ctx->stream;
+  if (vqe) {
+    QF_TRY(check_vqe(ctx, ctx->cls_off));
+    QF_TRY(ensure(ctx, ctx->vqe_theta, sizeof(double) * std::max<int64_t>(ctx->h_amp_off[K], 1)));
+  }
   if (diis) {
     const size_t N = (size_t)ctx->o * ctx->v + (size_t)ctx->o * ctx->o * ctx->v * ctx->v;
     QF_TRY(ensure(ctx, ctx->diis_t, sizeof(double) * qf::kDiisMax * N));
@@ -1310,7 +1401,7 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
       }
       QF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       const int r =
-          enqueue_step(ctx, K, owner1, owner2, t1, t2, energy, precision, step, diis, false);
+          enqueue_step(ctx, K, owner1, owner2, t1, t2, energy, precision, step, diis, false, vqe);
       hipGraph_t graph = nullptr;
       const hipError_t e = hipStreamEndCapture(st, &graph);
       if (r != QFLOW_OK) {
@@ -1332,7 +1423,7 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
     QF_HIP(hipGraphLaunch(ctx->graph_exec, st));
     QF_HIP(hipEventRecord(ctx->ev[kStages], st));
   } else {
-    QF_TRY(enqueue_step(ctx, K, owner1, owner2, t1, t2, energy, precision, step, diis, true));
+    QF_TRY(enqueue_step(ctx, K, owner1, owner2, t1, t2, energy, precision, step, diis, true, vqe));
   }
   double out[2];
   QF_HIP(hipMemcpyAsync(out, ctx->out2.p, sizeof(out), hipMemcpyDeviceToHost, st));
@@ -1363,8 +1454,9 @@ int qflow_flow_sweep_windowed(qflow_ctx* ctx, int32_t K, const qflow_space* spac
   if (!owner1 || !owner2 || !t1 || !t2 || !e_mean || !max_dt || (K > 0 && !energy))
     return fail(ctx, QFLOW_E_INVALID_ARG, "NULL argument");
   if (window < 1) return fail(ctx, QFLOW_E_INVALID_ARG, "window < 1");
-  if (flags & (QFLOW_GRAPH | QFLOW_DIIS))
-    return fail(ctx, QFLOW_E_UNSUPPORTED, "windowed sweeps take neither QFLOW_GRAPH nor QFLOW_DIIS");
+  if (flags & (QFLOW_GRAPH | QFLOW_DIIS | QFLOW_SOLVER_VQE))
+    return fail(ctx, QFLOW_E_UNSUPPORTED,
+                "windowed sweeps take none of QFLOW_GRAPH, QFLOW_DIIS, QFLOW_SOLVER_VQE");
   const int precision = flags & 15;
   if (precision != QFLOW_FP64 && precision != QFLOW_FP32 && precision != QFLOW_BF16X3)
     return fail(ctx, QFLOW_E_UNSUPPORTED, "unknown precision");
@@ -1448,6 +1540,15 @@ int qflow_set_solver(qflow_ctx* ctx, double tol, int32_t max_iter) {
   if (!(tol > 0.0) || max_iter < 1) return fail(ctx, QFLOW_E_INVALID_ARG, "bad tol or max_iter");
   ctx->dav_tol = tol;
   ctx->dav_max_iter = max_iter;
+  ++ctx->epoch;   // a captured step holds the old values in its kernel arguments
+  return QFLOW_OK;
+}
+
+int qflow_set_vqe(qflow_ctx* ctx, double gtol, int32_t max_iter) {
+  if (!ctx) return QFLOW_E_INVALID_ARG;
+  if (!(gtol > 0.0) || max_iter < 0) return fail(ctx, QFLOW_E_INVALID_ARG, "bad gtol or max_iter");
+  ctx->vqe_gtol = gtol;
+  ctx->vqe_max_iter = max_iter;
   ++ctx->epoch;   // a captured step holds the old values in its kernel arguments
   return QFLOW_OK;
 }
