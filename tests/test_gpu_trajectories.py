@@ -13,6 +13,8 @@ the seeded generator).
   (energies and owned amplitudes), plus a sampled block of the pool (owned and
   unowned doubles and singles) after each; FP32 and BF16x3: every space's
   energy within 1e-6 Eh of the FP64 path and of the oracle.
+* 114 orbitals (13 occupied, 101 virtual), K = 4096: the first
+  macro-iteration, FP64 and BF16x3, on 16 sampled spaces and a sampled block.
 
 The library samples the spaces itself (Algorithm 1 on the same uniform
 stream); the list must equal the stored one.
@@ -190,3 +192,43 @@ def test_eighty_two_orbitals_two_steps_match_oracle():
             assert dE < 1e-6
         assert np.abs(energies[prec][0][0] - gold["e_space_1"]).max() < 1e-6
         assert np.abs(energies[prec][1][0][samp] - gold["e_samp_2"]).max() < 1e-6
+
+
+@pytest.mark.timeout(600)
+def test_hundred_fourteen_orbitals_sampled_spaces_match_oracle():
+    """114 orbitals (13 occupied), K = 4096, first macro-iteration from MP2
+    in plain FP64 and in the BF16x3 graph configuration that bench.py times:
+    16 spaces spread over the Delta-eps order (orbitals 0 and 113 among
+    them; energies and owned amplitudes) and the residual steps of the
+    unowned doubles of a sampled 3 x 3 x 4 x 4 block, against the oracle's
+    values computed space by space."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    gold = _gold("qflow_c4_first_step.npz")
+    ctx, keep, spaces, o1, o2, (n, o, v, K) = _setup("c4", gold)
+    d1, d2 = torch.from_numpy(o1).cuda(), torch.from_numpy(o2).cuda()
+    samp = gold["samp"]
+    assert gold["orbs"][samp].min() == 0 and gold["orbs"][samp].max() == n - 1
+    bo, bv = gold["block_occ"], gold["block_vir"] - o
+    blk = np.ix_(bo, bo, bv, bv)
+    un2 = gold["block_unowned2_1"]
+    assert un2.sum() > 0
+    ref_step = gold["block_t2_step_1"][un2]
+    scale = np.abs(ref_step).max()
+    for prec, flag, tol_e, tol_t, tol_u in (("fp64", qf.FP64, 1e-9, 1e-8, 1e-10),
+                                             ("bf16x3", qf.BF16X3 | qf.GRAPH, 1e-6, 1e-6,
+                                              1e-4 * scale)):
+        t1, t2 = _pool(ctx, o, v)
+        energy = torch.zeros(K, dtype=torch.float64, device="cuda")
+        ctx.flow_step(spaces, d1, d2, t1, t2, energy, flag)
+        E, T1, T2 = energy.cpu().numpy(), t1.cpu().numpy(), t2.cpu().numpy()
+        dE = np.abs(E[samp] - gold["e_samp_1"]).max()
+        print(f"114 orbitals, {prec}: 16 sampled spaces, max |dE| {dE:.2e} Eh")
+        assert dE < tol_e
+        owned = 0
+        for m, k in enumerate(samp):
+            owned += _owned_check(gold["orbs"][k], k, gold["t1_samp_1"][m],
+                                  gold["t2_samp_1"][m], o1, o2, T1, T2, o, tol_t)
+        assert owned > 0
+        assert np.abs(T2[blk][un2] - ref_step).max() < tol_u
+        print(f"114 orbitals, {prec}: {owned} owned amplitudes, {un2.sum()} unowned doubles")
