@@ -16,6 +16,9 @@ Steps, in the order the paper states them:
   (commutators truncated to 0-, 1- and 2-body parts; F_N the normal-ordered
   Fock operator), then restricted to the orbitals of the space: the projector
   P + Q_int(i) keeps Phi and every determinant excited inside the space.
+  The next truncation of the expansion (the paper's route to the remaining
+  correlation, closing paragraph of "Results") adds
+  1/2 [[V_N, sigma_ext]_2, sigma_ext]_2 (Problem(..., truncation="H")).
 * E(i) is the lowest eigenvalue of that active-space matrix in the spin-flip
   sector of Phi (Eq. (5) with the exact active-space ground state standing in
   for the UCCSD-VQE solver), with the eigenvector's reference coefficient
@@ -61,9 +64,20 @@ def mp2_guess(f, eri, o):
     return t1, t2
 
 
+TRUNCATIONS = ("F", "H")
+
+
 class Problem:
-    def __init__(self, h, eri, o):
+    """Integrals and reference quantities; `truncation` selects the double
+    commutator of the downfolded Hamiltonian: "F" keeps 1/2 [[F_N, s]_2, s]_2
+    only, "H" also 1/2 [[V_N, s]_2, s]_2 (V_N = H_N - F_N, the two-body part),
+    i.e. 1/2 [[H_N, s]_2, s]_2 in all."""
+
+    def __init__(self, h, eri, o, truncation="F"):
+        if truncation not in TRUNCATIONS:
+            raise ValueError(f"truncation must be one of {TRUNCATIONS}")
         self.h, self.eri, self.o = h, eri, o
+        self.truncation = truncation
         self.n = h.shape[0]
         self.v = self.n - o
         self.f, self.e_ref, self.eps = reference(h, eri, o)
@@ -71,6 +85,7 @@ class Problem:
         self.H = so.Hamiltonian(self.f, eri, self.e_ref)
         self.HN = so.Hamiltonian(self.f, eri, 0.0)
         self.F = so.Fock(self.f)
+        self.VN = so.Hamiltonian(np.zeros_like(self.f), eri, 0.0)
 
 
 class Sum(so.Op):
@@ -89,11 +104,18 @@ class Sum(so.Op):
 
 def hbar(pb: Problem, t1, t2, mask=None) -> so.Op:
     """H + [H_N, s]_2 + 1/2 [[F_N, s]_2, s]_2 with s = sigma (mask None) or
-    s = sigma_ext of the space whose spatial orbitals are `mask`."""
+    s = sigma_ext of the space whose spatial orbitals are `mask`; with the
+    problem's truncation "H" also + 1/2 [[V_N, s]_2, s]_2, the inner
+    commutator truncated to its 0-, 1- and 2-body parts before the outer one
+    is taken."""
     S = so.Cluster(pb.bl, t1, t2, mask)
     Y = so.Commutator(pb.F, S, pb.bl)
-    return Sum([(1.0, pb.H), (1.0, so.Commutator(pb.HN, S, pb.bl)),
-                (0.5, so.Commutator(Y, S, pb.bl))])
+    terms = [(1.0, pb.H), (1.0, so.Commutator(pb.HN, S, pb.bl)),
+             (0.5, so.Commutator(Y, S, pb.bl))]
+    if pb.truncation == "H":
+        W = so.Dense(*so.to_dense(so.Commutator(pb.VN, S, pb.bl), pb.bl))
+        terms.append((0.5, so.Commutator(W, S, pb.bl)))
+    return Sum(terms)
 
 
 def spin_orbitals(orbs):
