@@ -205,6 +205,24 @@ int qflow_solve_vqe_batch(qflow_ctx* ctx, int32_t K, const qflow_space* spaces,
                           double* amp, const int64_t* amp_off, double* energy, int32_t* iters,
                           int32_t* status, double gtol, int32_t max_iter);
 
+/* Truncation of the downfolded Hamiltonian of Eq. (6) at N = 1 used by
+ * qflow_residual, qflow_build_heff, qflow_flow_step and qflow_autotune:
+ *   QFLOW_TRUNC_F (default)  H + [H_N, s]_2 + 1/2 [[F_N, s]_2, s]_2,
+ *   QFLOW_TRUNC_H            the same + 1/2 [[V_N, s]_2, s]_2 (V_N the
+ *                            two-body part of H_N), the next term of the
+ *                            expansion (closing paragraph of "Results"),
+ * s = sigma_ext of the space (sigma for the residual); every commutator is
+ * truncated to its 0-, 1- and 2-body parts, the inner one before the outer
+ * one is taken.  QFLOW_TRUNC_H evaluates its term directly, with no global
+ * intermediates: [V_N, sigma]_2 over all n^4 elements once per call, then per
+ * space its own W = [V_N, s]_2 (n^4 doubles, up to 4 GiB of spaces at a time)
+ * and [W, s]_2 on the space's orbitals, a cost of order n^4 (o^2 + v^2 + o v)
+ * + K n^4 + K na^4 n^2 operations: a path for problems of tens of orbitals.
+ * Windowed sweeps take QFLOW_TRUNC_F only.  Unknown values are
+ * QFLOW_E_INVALID_ARG. */
+enum { QFLOW_TRUNC_F = 0, QFLOW_TRUNC_H = 1 };
+int qflow_set_truncation(qflow_ctx* ctx, int truncation);
+
 /* Stopping rule of the VQE solves inside qflow_flow_step (QFLOW_SOLVER_VQE):
  * largest gradient entry below gtol, at most max_iter BFGS iterations (the
  * space then has status QFLOW_E_NOT_CONVERGED and writes none of its

@@ -7,7 +7,7 @@ it does not load the library; ``lib()`` does, and raises if it was not built
 """
 from .api import (  # noqa: F401
     FP64, FP32, BF16X3, UNOWNED_FROZEN, GRAPH, DIIS, SOLVER_VQE, Z_AUTO, Z_SPACE, Z_DENSE,
-    SPACE_DTYPE,
+    SPACE_DTYPE, TRUNC_F, TRUNC_H,
     QFlowError, Context, lib,
     make_spaces, sample_spaces, build_owners, heff_size, amp_size, ci_size,
 )

@@ -20,6 +20,7 @@ UNOWNED_FROZEN = 1 << 4
 GRAPH = 1 << 5
 DIIS = 1 << 6
 SOLVER_VQE = 1 << 7
+TRUNC_F, TRUNC_H = 0, 1   # qflow_set_truncation
 Z_AUTO, Z_SPACE, Z_DENSE = 0, 1, 2   # qflow_z_mode
 STATIC_SCRATCH_BYTES = 128 * 1024 * 1024   # QFLOW_STATIC_SCRATCH_BYTES
 
@@ -80,6 +81,7 @@ def lib() -> ctypes.CDLL:
             "qflow_solve_vqe_batch": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp,
                                                      vp, d, i32]),
             "qflow_set_vqe": (ctypes.c_int, [vp, d, i32]),
+            "qflow_set_truncation": (ctypes.c_int, [vp, ctypes.c_int]),
             "qflow_flow_step": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32]),
             "qflow_flow_sweep_windowed": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, i32, vp,
                                                          vp, i32]),
@@ -233,6 +235,10 @@ class Context:
         self._check(lib().qflow_solve_vqe_batch(
             self.h, len(sp), _ptr(sp), _ptr(heff), _ptr(heff_off), _ptr(theta0), _ptr(amp),
             _ptr(amp_off), _ptr(energy), _ptr(iters), _ptr(status), float(gtol), int(max_iter)))
+
+    def set_truncation(self, truncation):
+        """TRUNC_F (DUCC(2F), the default) or TRUNC_H (adds 1/2 [[V_N, s]_2, s]_2)."""
+        self._check(lib().qflow_set_truncation(self.h, int(truncation)))
 
     def set_vqe(self, gtol=1e-10, max_iter=500):
         """Stopping rule of the flow steps' VQE solves (SOLVER_VQE)."""

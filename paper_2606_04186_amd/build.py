@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqflow.so")
 SOURCES = ["k_prep.hip", "k_gemm.hip", "k_residual.hip", "k_heff.hip", "k_davidson.hip", "k_vqe.hip",
+           "k_vdouble.hip",
            "qflow_api.cpp", "strings.cpp", "sampling.cpp"]
 ARCH = os.environ.get("QFLOW_OFFLOAD_ARCH", "gfx950")
 

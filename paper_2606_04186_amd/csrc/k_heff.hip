@@ -537,13 +537,15 @@ struct ZSum {
 };
 
 // Rewrite each slot from normal order to CAS form (after adding the ZSum
-// part to the two-body block):
+// part to the two-body block and, when given, the extra terms xtra at the
+// slot's offset to every part):
 //   Ec = x0 - 2 sum_k x1_kk + sum_kl (2 x2_klkl - x2_kllk)
 //   h_pq = x1_pq - sum_k (2 x2_pkqk - x2_pkkq),  g(pq|rs) = x2_prqs
 __global__ __launch_bounds__(256) void k_heff_cas(const SpaceDev* __restrict__ spaces,
                                                   const int32_t* __restrict__ idx,
                                                   const int64_t* __restrict__ heff_off,
-                                                  ZSum zsum, double* heff) {
+                                                  ZSum zsum, const double* __restrict__ xtra,
+                                                  double* heff) {
   extern __shared__ double sm[];
   const int k = idx[blockIdx.x];
   const SpaceDev sp = spaces[k];
@@ -554,8 +556,9 @@ __global__ __launch_bounds__(256) void k_heff_cas(const SpaceDev* __restrict__ s
     const int c = ne - 2;   // size class: na = 2 nocc
     zk = zsum.p + zsum.off[c] + (size_t)(blockIdx.x - zsum.first[c]) * n4;
   }
+  const double* xk = xtra ? xtra + heff_off[k] : nullptr;
   for (int e = threadIdx.x; e < 1 + n2 + n4; e += blockDim.x)
-    sm[e] = zk && e > n2 ? slot[e] + zk[e - 1 - n2] : slot[e];
+    sm[e] = (zk && e > n2 ? slot[e] + zk[e - 1 - n2] : slot[e]) + (xk ? xk[e] : 0.0);
   __syncthreads();
   const double* x1 = sm + 1;
   const double* x2 = sm + 1 + n2;
@@ -619,7 +622,7 @@ hipError_t launch_heff(const double* f, const double* V, const double* y1, const
                        const int32_t* cls_idx, const int* cls_off, int K, int na_max,
                        double* tab, double* fs1, const double* zc, const double* mpd, double* heff,
                        hipStream_t st, double* zs, hipStream_t st2, hipEvent_t fork_ev,
-                       hipEvent_t join_ev, int phase) {
+                       hipEvent_t join_ev, int phase, const double* xtra) {
   GlobalOps g{f, V, y1, y2, L, LY, t1, t2, n, o, rings.ga_h, rings.g22_h, rings.j1_h,
               rings.j2_h, rings.ga_y, rings.g22_y, rings.j1_y, rings.j2_y,
               rings.zv,   rings.zo,  rings.u_h, rings.s2p, rings.s2q, rings.c1_h, rings.c1_y,
@@ -773,7 +776,7 @@ hipError_t launch_heff(const double* f, const double* V, const double* y1, const
   }
   const int tasks = na_max * na_max * na_max * na_max + na_max * na_max + 1;
   const size_t lds = (size_t)tasks * sizeof(double);
-  k_heff_cas<<<K, kBlock, lds, st>>>(spaces, cls_idx, heff_off, zsum, heff);
+  k_heff_cas<<<K, kBlock, lds, st>>>(spaces, cls_idx, heff_off, zsum, xtra, heff);
   return hipSuccess;
 }
 

@@ -144,7 +144,24 @@ hipError_t launch_heff(const double* f, const double* V, const double* y1, const
                        const int32_t* cls_idx, const int* cls_off, int K, int na_max,
                        double* tab, double* fs1, const double* zc, const double* mpd, double* heff,
                        hipStream_t st, double* zs, hipStream_t st2, hipEvent_t fork_ev,
-                       hipEvent_t join_ev, int phase = -1);
+                       hipEvent_t join_ev, int phase = -1, const double* xtra = nullptr);
+// The next DUCC truncation, 1/2 [[V_N, s]_2, s]_2 (k_vdouble.hip).  A W buffer
+// holds a dense operator over all orbitals: two-body [n^4], one-body [n^2],
+// zero-body; vd_space_doubles(n) doubles.
+size_t vd_space_doubles(int n);
+// wg = [V_N, sigma]_2
+void launch_vd_global(const double* V, const double* t1, const double* t2, int n, int o,
+                      double* wg, hipStream_t st);
+// spaces k0 .. k0+kb-1 of the list: their W (into wsp, kb buffers), then
+// 1/2 [W, s]_2 on the space's orbitals into xtra at heff_off[k], in the
+// layout of the H_eff block before its CAS form ([x0, x1, x2], local indices)
+void launch_vd_spaces(const double* V, const double* t1, const double* t2,
+                      const SpaceDev* spaces, int k0, int kb, int n, int o, const double* wg,
+                      double* wsp, const int64_t* heff_off, double* xtra, hipStream_t st);
+// r2 += 1/2 [wg, sigma]_2 (a,b,i,j), r1 += 1/2 [wg, sigma]_1 (a,i), *e0 +=
+// its zero-body part (e0 may be NULL)
+void launch_vd_resid(const double* wg, const double* t1, const double* t2, int n, int o,
+                     double* r1, double* r2, double* e0, hipStream_t st);
 // Operand of the dense occupied-pair ladder (k_heff.hip): xp[tri(p,q)][(t,u)]
 // = (H_N + Yg/2)(p,q,t,u), p <= q, t, u occupied; n(n+1)/2 x o^2 doubles.  The
 // ladder mpd = xp T^T with T[(a,b)][(t,u)] = t2[t,u,a,b] (launch_pack_t2_vvoo).

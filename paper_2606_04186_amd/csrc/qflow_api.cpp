@@ -165,6 +165,12 @@ struct qflow_ctx {
   double vqe_gtol = 1e-10;
   int vqe_max_iter = 500;
   DevBuf vqe_theta;
+  // truncation of the downfolded Hamiltonian (qflow_set_truncation); for
+  // QFLOW_TRUNC_H: Wg, a batch of per-space W buffers, the per-space extra
+  // terms (laid out like heff)
+  int trunc = QFLOW_TRUNC_F;
+  DevBuf vd_wg, vd_wsp, vd_xtra;
+  int vd_batch = 0;
 };
 
 namespace {
@@ -280,6 +286,19 @@ size_t zsum_doubles(const int* cls_off) {
 int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   QF_TRY(upload_space_list(ctx, K, spaces));
   return ensure_zc(ctx);   // outside any graph capture
+}
+
+// Buffers of the next truncation for the uploaded list (outside any capture):
+// Wg, W of up to vd_batch spaces at once (at most 4 GiB), the extra terms.
+int ensure_vdouble(qflow_ctx* ctx, int32_t K, int64_t xtra_doubles) {
+  if (ctx->trunc != QFLOW_TRUNC_H) return QFLOW_OK;
+  const size_t wn = qf::vd_space_doubles(ctx->n);
+  const size_t cap = (size_t)4 << 30;
+  ctx->vd_batch = (int)std::max<size_t>(1, std::min<size_t>(std::max(K, 1), cap / (wn * 8)));
+  QF_TRY(ensure(ctx, ctx->vd_wg, sizeof(double) * wn));
+  QF_TRY(ensure(ctx, ctx->vd_wsp, sizeof(double) * wn * ctx->vd_batch));
+  QF_TRY(ensure(ctx, ctx->vd_xtra, sizeof(double) * std::max<int64_t>(xtra_doubles, 1)));
+  return QFLOW_OK;
 }
 
 int upload_space_list(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
@@ -751,7 +770,7 @@ int qflow_destroy(qflow_ctx* ctx) {
                     &ctx->diis_t, &ctx->diis_e, &ctx->diis_part, &ctx->diis_state,
                     &ctx->win_idx, &ctx->t1s,    &ctx->t2s,
                     &ctx->dav_counter, &ctx->tune_t1, &ctx->tune_t2, &ctx->tune_e,
-                    &ctx->vqe_theta};
+                    &ctx->vqe_theta, &ctx->vd_wg, &ctx->vd_wsp, &ctx->vd_xtra};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -908,11 +927,17 @@ int qflow_residual(qflow_ctx* ctx, const double* t1, const double* t2, double* r
   QF_TRY(require_loaded(ctx));
   if (!t1 || !t2 || !r1 || !r2 || !e0)
     return fail(ctx, QFLOW_E_INVALID_ARG, "NULL array argument");
+  QF_TRY(ensure_vdouble(ctx, 0, 1));
   QF_TRY(prepare(ctx, t1, t2, precision));
   qf::launch_residual(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
                       P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY), rings_of(ctx),
                       t1, t2, ctx->n, ctx->o, P<double>(ctx->scal), P<double>(ctx->c1h),
                       P<double>(ctx->c1y), P<double>(ctx->gpart), r1, r2, e0, ctx->stream);
+  if (ctx->trunc == QFLOW_TRUNC_H) {
+    qf::launch_vd_global(P<double>(ctx->V), t1, t2, ctx->n, ctx->o, P<double>(ctx->vd_wg),
+                         ctx->stream);
+    qf::launch_vd_resid(P<double>(ctx->vd_wg), t1, t2, ctx->n, ctx->o, r1, r2, e0, ctx->stream);
+  }
   QF_HIP(hipGetLastError());
   return QFLOW_OK;
 }
@@ -952,6 +977,21 @@ int check_offsets(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const in
 // The downfolded Hamiltonians of the spaces in the class lists idx / cls_off
 // (count = cls_off[3]; the whole list when idx is NULL), after the residual
 // and zero-body parts of the pool (t1, t2).
+// Wg = [V_N, sigma]_2, then 1/2 [[V_N, s]_2, s]_2 on every space's orbitals
+// into vd_xtra (the list's order, offsets heff_off_dev)
+int run_vdouble(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2,
+                const int64_t* heff_off_dev) {
+  const int n = ctx->n, o = ctx->o;
+  qf::launch_vd_global(P<double>(ctx->V), t1, t2, n, o, P<double>(ctx->vd_wg), ctx->stream);
+  for (int k0 = 0; k0 < K; k0 += ctx->vd_batch)
+    qf::launch_vd_spaces(P<double>(ctx->V), t1, t2, P<SpaceDev>(ctx->spaces), k0,
+                         std::min(ctx->vd_batch, K - k0), n, o, P<double>(ctx->vd_wg),
+                         P<double>(ctx->vd_wsp), heff_off_dev, P<double>(ctx->vd_xtra),
+                         ctx->stream);
+  QF_HIP(hipGetLastError());
+  return QFLOW_OK;
+}
+
 int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, double* heff,
              const int64_t* heff_off_dev, const int32_t* idx = nullptr,
              const int* cls_off = nullptr) {
@@ -968,6 +1008,7 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
   // not read.
   const bool use_zs = ctx->zsum.bytes >= sizeof(double) * zsum_doubles(cls_off);
   const bool split = K > 0 && use_zs && !ctx->timed;
+  const bool vd = ctx->trunc == QFLOW_TRUNC_H;
   auto heff_phase = [&](hipStream_t s, bool dense, int phase) {
     return qf::launch_heff(P<double>(ctx->f), P<double>(ctx->V), P<double>(ctx->y1),
                            P<double>(ctx->y2), P<double>(ctx->L), P<double>(ctx->LY),
@@ -979,8 +1020,11 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
                            dense ? P<double>(ctx->mp) : nullptr, heff, s,
                            use_zs ? P<double>(ctx->zsum) : nullptr,
                            ctx->timed ? nullptr : ctx->stream2, ctx->fork2_ev, ctx->join2_ev,
-                           phase);
+                           phase, vd && K > 0 ? P<double>(ctx->vd_xtra) : nullptr);
   };
+  // the next truncation (whole lists only): Wg, then every space's extra
+  // terms, on the main stream ahead of the residual that reads Wg
+  if (vd) QF_TRY(run_vdouble(ctx, K, t1, t2, heff_off_dev));
   if (split) {
     QF_HIP(hipEventRecord(ctx->tabf_ev, ctx->stream));
     QF_HIP(hipStreamWaitEvent(ctx->stream2, ctx->tabf_ev, 0));
@@ -993,6 +1037,9 @@ int run_heff(qflow_ctx* ctx, int32_t K, const double* t1, const double* t2, doub
                       t1, t2, ctx->n, ctx->o, P<double>(ctx->scal), P<double>(ctx->c1h),
                       P<double>(ctx->c1y), P<double>(ctx->gpart), P<double>(ctx->r1),
                       P<double>(ctx->r2), nullptr, ctx->stream);
+  if (vd)
+    qf::launch_vd_resid(P<double>(ctx->vd_wg), t1, t2, ctx->n, ctx->o, P<double>(ctx->r1),
+                        P<double>(ctx->r2), nullptr, ctx->stream);
   if (ctx->timed) QF_HIP(hipEventRecord(ctx->ev[8], ctx->stream));
   const size_t n = ctx->n;
   const size_t npair = n * (n + 1) / 2, oo = (size_t)ctx->o * ctx->o,
@@ -1188,6 +1235,7 @@ int qflow_build_heff(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const
   if (!t1 || !t2 || !heff) return fail(ctx, QFLOW_E_INVALID_ARG, "NULL array argument");
   QF_TRY(check_offsets(ctx, K, spaces, heff_off, qflow_heff_size, "heff_off"));
   QF_TRY(upload_spaces(ctx, K, spaces));
+  QF_TRY(ensure_vdouble(ctx, K, heff_off[K]));
   DevBuf off;
   QF_TRY(ensure(ctx, off, sizeof(int64_t) * (K + 1)));
   hipError_t e = hipMemcpy(off.p, heff_off, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice);
@@ -1374,6 +1422,7 @@ int qflow_flow_step(qflow_ctx* ctx, int32_t K, const qflow_space* spaces, const 
   const bool diis = (flags & QFLOW_DIIS) != 0;
   const bool vqe = (flags & QFLOW_SOLVER_VQE) != 0;
   hipStream_t st = ctx->stream;
+  QF_TRY(ensure_vdouble(ctx, K, ctx->h_heff_off[K]));
   if (vqe) {
     QF_TRY(check_vqe(ctx, ctx->cls_off));
     QF_TRY(ensure(ctx, ctx->vqe_theta, sizeof(double) * std::max<int64_t>(ctx->h_amp_off[K], 1)));
@@ -1457,6 +1506,8 @@ int qflow_flow_sweep_windowed(qflow_ctx* ctx, int32_t K, const qflow_space* spac
   if (flags & (QFLOW_GRAPH | QFLOW_DIIS | QFLOW_SOLVER_VQE))
     return fail(ctx, QFLOW_E_UNSUPPORTED,
                 "windowed sweeps take none of QFLOW_GRAPH, QFLOW_DIIS, QFLOW_SOLVER_VQE");
+  if (ctx->trunc != QFLOW_TRUNC_F)
+    return fail(ctx, QFLOW_E_UNSUPPORTED, "windowed sweeps take the DUCC(2F) truncation only");
   const int precision = flags & 15;
   if (precision != QFLOW_FP64 && precision != QFLOW_FP32 && precision != QFLOW_BF16X3)
     return fail(ctx, QFLOW_E_UNSUPPORTED, "unknown precision");
@@ -1541,6 +1592,15 @@ int qflow_set_solver(qflow_ctx* ctx, double tol, int32_t max_iter) {
   ctx->dav_tol = tol;
   ctx->dav_max_iter = max_iter;
   ++ctx->epoch;   // a captured step holds the old values in its kernel arguments
+  return QFLOW_OK;
+}
+
+int qflow_set_truncation(qflow_ctx* ctx, int truncation) {
+  if (!ctx) return QFLOW_E_INVALID_ARG;
+  if (truncation != QFLOW_TRUNC_F && truncation != QFLOW_TRUNC_H)
+    return fail(ctx, QFLOW_E_INVALID_ARG, "unknown truncation");
+  ctx->trunc = truncation;
+  ++ctx->epoch;   // a captured step follows the truncation
   return QFLOW_OK;
 }
 
