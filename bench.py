@@ -63,6 +63,12 @@ def parse():
                          "(implies --no-autotune)")
     ap.add_argument("--tune-cache", default=None, metavar="PATH",
                     help="JSON cache of the autotuner's choices (default: none, tune afresh)")
+    ap.add_argument("--solver", choices=["ci", "vqe"], default="ci",
+                    help="active-space solver: CI eigenvector + cluster analysis, or the "
+                         "UCCSD-VQE solver ((2,2) and (3,3) spaces)")
+    ap.add_argument("--truncation", choices=["F", "H"], default="F",
+                    help="downfolded Hamiltonian: DUCC(2F), or with 1/2 [[V_N,s],s] added "
+                         "(tens of orbitals)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-spaces", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -92,6 +98,9 @@ def main():
     dev = torch.device("cuda:0")
     ctx = qf.Context(0)
     ctx.load_integrals(torch.from_numpy(h).to(dev), torch.from_numpy(eri).to(dev), o)
+    if args.truncation == "H":
+        ctx.set_truncation(qf.TRUNC_H)
+    solver_flag = qf.SOLVER_VQE if args.solver == "vqe" else 0
     e_ref, eps, _ = ctx.reference()
     # Algorithm 1 per size class (K / classes spaces each), merged and sorted
     # by Delta eps
@@ -151,7 +160,7 @@ def main():
             tunings[tag] = {"choice": ctx.get_tuning().as_dict(), "source": "library default"}
             return
         ctx.mp2_guess(t1, t2)
-        flags = precision | (0 if args.no_graph else qf.GRAPH)
+        flags = precision | solver_flag | (0 if args.no_graph else qf.GRAPH)
         t0 = time.perf_counter()
         choice, rep = ctx.autotune(spaces, d1, d2, t1, t2, flags, args.tune_cache)
         tunings[tag] = {"choice": choice.as_dict(), "source": "qflow_autotune",
@@ -164,6 +173,7 @@ def main():
         """W untimed and K timed macro-iterations from the MP2 start."""
         ctx.mp2_guess(t1, t2)
         tag = {qf.FP64: "fp64", qf.FP32: "fp32", qf.BF16X3: "bf16x3"}[precision]
+        precision |= solver_flag
         if graph:
             precision |= qf.GRAPH
             tag += " graph"
@@ -285,7 +295,7 @@ def main():
         modes[key]["abs_dE_max_space"] = dsp
     dominant = max((k_ for k_ in st if k_ != "total"), key=st.get)
     if args.windowed > 0:
-        flag = {"fp64": qf.FP64, "fp32": qf.FP32, "bf16x3": qf.BF16X3}[use]
+        flag = {"fp64": qf.FP64, "fp32": qf.FP32, "bf16x3": qf.BF16X3}[use] | solver_flag
         ctx.mp2_guess(t1, t2)
         ctx.flow_sweep_windowed(spaces, d1, d2, t1, t2, energy, args.windowed, flag)   # warm
         torch.cuda.synchronize()
@@ -325,6 +335,10 @@ def main():
                                          "elsewhere",
                                  "bf16x3": "BF16x3 (hi+lo) ladder and ring products, FP32 "
                                            "partial sums, FP64 sums; FP64 elsewhere"}[use],
+                   "solver": {"ci": "CI eigenvector + cluster analysis",
+                              "vqe": "UCCSD-VQE"}[args.solver],
+                   "truncation": {"F": "DUCC(2F)",
+                                  "H": "DUCC(2F) + 1/2 [[V_N,s]_2,s]_2"}[args.truncation],
                    "e_ref": e_ref, "e_mean_last": runs[use]["e_mean"]},
         "modes": modes,
         "stage_ms": st,
