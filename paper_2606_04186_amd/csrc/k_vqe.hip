@@ -53,8 +53,10 @@ struct VqeShape {
   static constexpr int N2 = NA * NA, N4 = N2 * N2, HS = NS | 1;
   // LDS doubles: g, Hs, string tables (ints), vectors, BFGS state, scratch
   static constexpr int NVEC = 4 + 2 * NT1 + 4;   // psi, w, phi, lam, 2 NT1 sets, 4 scratch
+  // ... BFGS (NP^2 + 8 NP), dot products (NT1 + NT1^2), 1/2 theta2 table
+  // (NT1^2), misc (8), reduction slots (2 per wavefront)
   static constexpr int LDS = N4 + NS * HS + (NS * N2 + NS * NR + 1) / 2 + NVEC * D +
-                             NP * NP + 8 * NP + NT1 * NT1 + 8 + kVqeBlock / 64;
+                             NP * NP + 8 * NP + NT1 + 2 * NT1 * NT1 + 8 + 2 * (kVqeBlock / 64);
 };
 
 __device__ double vqe_block_sum(double x, double* red) {
@@ -77,6 +79,23 @@ __device__ double vqe_block_max(double x, double* red) {
   return s;
 }
 
+// (max a, max b) over the workgroup, one pair of barriers
+__device__ void vqe_block_max2(double& a, double& b, double* red) {
+  a = wave_max(a);
+  b = wave_max(b);
+  if (threadIdx.x % 64 == 0) {
+    red[2 * (threadIdx.x / 64)] = a;
+    red[2 * (threadIdx.x / 64) + 1] = b;
+  }
+  __syncthreads();
+  a = b = 0.0;
+  for (int w = 0; w < kVqeBlock / 64; ++w) {
+    a = fmax(a, red[2 * w]);
+    b = fmax(b, red[2 * w + 1]);
+  }
+  __syncthreads();
+}
+
 template <int NA, int NE>
 struct VqeSpace {
   using S_ = VqeShape<NA, NE>;
@@ -87,7 +106,7 @@ struct VqeSpace {
   double *g, *Hs, *red;
   int *emap, *rep;
   double *psi, *w, *phi, *lam, *setA, *setB, *s0, *s1, *s2, *s3;
-  double *Hinv, *th, *gr, *p, *sv, *yv, *th2, *g2, *dk, *misc;
+  double *Hinv, *th, *gr, *p, *sv, *yv, *th2, *g2, *dk, *misc, *t2h;
 
   // (E_PQ v)(Ia, Ib) for spin-summed E_PQ, P,Q local orbitals; out = or += (acc)
   __device__ void apply_E(int P, int Q, const double* v, double* out, bool acc) const {
@@ -102,41 +121,60 @@ struct VqeSpace {
     }
   }
 
-  // out = A v with A = T - T^dag of the parameters th (x scales A); uses
-  // setA (NT1 vectors) and s3 as scratch.  v and out distinct from them.
+  // (E_PQ v) at (ia, ib) for the table entry pq = P * NA + Q
+  __device__ double e_at(int pq, const double* v, int ia, int ib) const {
+    double x = 0.0;
+    const int sa = emap[ia * N2 + pq], sb = emap[ib * N2 + pq];
+    if (sa != 0) x += (sa > 0 ? 1.0 : -1.0) * v[(abs(sa) - 1) * NS + ib];
+    if (sb != 0) x += (sb > 0 ? 1.0 : -1.0) * v[ia * NS + (abs(sb) - 1)];
+    return x;
+  }
+
+  // theta1[ia] v[f] + 1/2 sum_jb theta2[ia][jb] set_jb[f]
+  __device__ double s_val(int ia, const double* v, const double* set, int f) const {
+    double x = th[ia] * v[f];
+    const double* tr = t2h + ia * NT1;
+#pragma unroll
+    for (int jb = 0; jb < NT1; ++jb) x += tr[jb] * set[jb * D + f];
+    return x;
+  }
+
+  // 1/2 theta2 as a full NT1 x NT1 table; after every change of th
+  __device__ void prep_theta() {
+    for (int q = threadIdx.x; q < NT1 * NT1; q += kVqeBlock) t2h[q] = 0.5 * t2(q / NT1, q % NT1);
+    __syncthreads();
+  }
+
+  // out = x A v with A = T - T^dag of the parameters th:
+  //   T v     = sum_IA E_AI (theta1 v + 1/2 sum_JB theta2 E_BJ v),
+  //   T^dag v = sum_IA E_IA (theta1 v + 1/2 sum_JB theta2 E_JB v)
+  // (E_AI and E_BJ commute, as do E_IA and E_JB).  The NT1 vectors E_BJ v
+  // go to setA, E_JB v to setB; each output then gathers its sources
+  // directly: two barriers in all.  out distinct from v, setA, setB.
   __device__ void apply_A(double x, const double* v, double* out) {
-    for (int e = threadIdx.x; e < D; e += kVqeBlock) out[e] = 0.0;
-    for (int pass = 0; pass < 2; ++pass) {
-      const bool dag = pass == 1;   // T^dag: de-excitations, subtracted
-      // u_Jb = E_BJ v (or E_JB v)
-      for (int jb = 0; jb < NT1; ++jb) {
-        const int J = jb / NV, B = NE + jb % NV;
-        apply_E(dag ? J : B, dag ? B : J, v, setA + jb * D, false);
-      }
-      __syncthreads();
+    for (int q = threadIdx.x; q < NT1 * D; q += kVqeBlock) {
+      const int jb = q / D, e = q % D;
+      const int J = jb / NV, B = NE + jb % NV;
+      setA[q] = e_at(B * NA + J, v, e / NS, e % NS);
+      setB[q] = e_at(J * NA + B, v, e / NS, e % NS);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < D; e += kVqeBlock) {
+      const int ja = e / NS, jb2 = e % NS;
+      double acc = 0.0;
       for (int ia = 0; ia < NT1; ++ia) {
         const int I = ia / NV, A = NE + ia % NV;
-        // w = theta1[ia] v + 1/2 sum_jb theta2[ia][jb] u_jb  (theta2 symmetric)
-        for (int e = threadIdx.x; e < D; e += kVqeBlock) {
-          double t = th[ia] * v[e];
-          for (int jb = 0; jb < NT1; ++jb) t += 0.5 * t2(ia, jb) * setA[jb * D + e];
-          s3[e] = t;
-        }
-        __syncthreads();
-        // out +-= x E_AI w (or E_IA w)
-        const int pq = dag ? (I * NA + A) : (A * NA + I);
-        const double sc = dag ? -x : x;
-        for (int e = threadIdx.x; e < D; e += kVqeBlock) {
-          const int ja = e / NS, jb2 = e % NS;
-          double y = 0.0;
-          const int sa = emap[ja * N2 + pq], sb = emap[jb2 * N2 + pq];
-          if (sa != 0) y += (sa > 0 ? 1.0 : -1.0) * s3[(abs(sa) - 1) * NS + jb2];
-          if (sb != 0) y += (sb > 0 ? 1.0 : -1.0) * s3[ja * NS + (abs(sb) - 1)];
-          out[e] += sc * y;
-        }
-        __syncthreads();
+        int sa = emap[ja * N2 + A * NA + I], sb = emap[jb2 * N2 + A * NA + I];
+        if (sa != 0) acc += (sa > 0 ? 1.0 : -1.0) * s_val(ia, v, setA, (abs(sa) - 1) * NS + jb2);
+        if (sb != 0) acc += (sb > 0 ? 1.0 : -1.0) * s_val(ia, v, setA, ja * NS + (abs(sb) - 1));
+        sa = emap[ja * N2 + I * NA + A];
+        sb = emap[jb2 * N2 + I * NA + A];
+        if (sa != 0) acc -= (sa > 0 ? 1.0 : -1.0) * s_val(ia, v, setB, (abs(sa) - 1) * NS + jb2);
+        if (sb != 0) acc -= (sb > 0 ? 1.0 : -1.0) * s_val(ia, v, setB, ja * NS + (abs(sb) - 1));
       }
+      out[e] = x * acc;
     }
+    __syncthreads();
   }
 
   // theta2 of the pair of singles (p1, p2), symmetric
@@ -162,11 +200,9 @@ struct VqeSpace {
         tm = fmax(tm, fabs(t));
         ym = fmax(ym, fabs(y[e]));
       }
-      tm = vqe_block_max(tm, red);
-      ym = vqe_block_max(ym, red);
+      vqe_block_max2(tm, ym, red);
       if (tm <= 1e-17 * ym) break;
     }
-    __syncthreads();
   }
 
   // out = H v on full vectors (the CAS matrix of the space)
@@ -194,6 +230,7 @@ struct VqeSpace {
 
   // E(theta) into the return value; psi = e^{A} Phi, w = H psi
   __device__ double energy() {
+    prep_theta();
     for (int e = threadIdx.x; e < D; e += kVqeBlock) s2[e] = e == 0 ? 1.0 : 0.0;
     __syncthreads();
     expm_apply(1.0, s2, psi);
@@ -203,79 +240,94 @@ struct VqeSpace {
     return vqe_block_sum(d, red);
   }
 
-  // dot products of two sets of NT1 vectors: out[p1 * NT1 + p2] = X_p1 . Y_p2
-  __device__ void set_dots(const double* X, const double* Y, double* out) const {
-    for (int q = threadIdx.x; q < NT1 * NT1; q += kVqeBlock) {
-      const double* a = X + (q / NT1) * D;
-      const double* b = Y + (q % NT1) * D;
+  // out[p] = a . S_p (p < NT1), out[NT1 + p1 NT1 + p2] = P_p1 . Q_p2: one
+  // thread per dot product, one barrier
+  __device__ void phase_dots(const double* a, const double* S, const double* P, const double* Q,
+                             double* out) const {
+    for (int q = threadIdx.x; q < NT1 + NT1 * NT1; q += kVqeBlock) {
+      const double *x, *y;
+      if (q < NT1) {
+        x = a;
+        y = S + q * D;
+      } else {
+        x = P + ((q - NT1) / NT1) * D;
+        y = Q + ((q - NT1) % NT1) * D;
+      }
       double d = 0.0;
-      for (int e = 0; e < D; ++e) d += a[e] * b[e];
+      for (int e = 0; e < D; ++e) d += x[e] * y[e];
       out[q] = d;
     }
     __syncthreads();
   }
 
-  // gradient into gr (energy() must have set psi and w for th)
+  // gr += c (singles: out[p]; pairs (a <= b): f out[NT1 + a NT1 + b], f = 1/2
+  // for a = b), then a barrier
+  __device__ void phase_add(double c, const double* out) {
+    for (int k = threadIdx.x; k < NP; k += kVqeBlock) {
+      if (k < NT1) {
+        gr[k] += c * out[k];
+      } else {
+        int a = 0, r = k - NT1;
+        while (r >= NT1 - a) {
+          r -= NT1 - a;
+          ++a;
+        }
+        const int b = a + r;
+        gr[k] += c * (a == b ? 0.5 : 1.0) * out[NT1 + a * NT1 + b];
+      }
+    }
+    __syncthreads();
+  }
+
+  // gradient into gr (energy() must have set psi, w and the theta table for th):
+  // dE/dtheta_k = 2 int_0^1 lam(s)^T G_k phi(s) ds, phi(s) = e^{(1-s)A} Phi,
+  // lam(s) = e^{-sA} w, by Gauss-Legendre quadrature; phi and lam move from
+  // node to node by the exponential of the node spacing.  Singles
+  // G = E_AI - E_IA: lam.E_AI phi - phi.E_AI lam; pairs G = E_AI E_BJ -
+  // E_JB E_IA: (E_IA lam).(E_BJ phi) - (E_BJ lam).(E_IA phi).
   __device__ void gradient() {
     for (int k = threadIdx.x; k < NP; k += kVqeBlock) gr[k] = 0.0;
-    double* dots = dk + NP;   // NT1*NT1 doubles after the diagonal (misc region)
+    double* dots = dk + NP;   // NT1 + NT1^2 doubles after the diagonal
+    for (int e = threadIdx.x; e < D; e += kVqeBlock) s2[e] = e == 0 ? 1.0 : 0.0;
+    __syncthreads();
+    double* fp = phi;   // phi and lam at the current node
+    double* lp = lam;
+    double* tmp = s2;   // the free vector (Phi is no longer needed once phi(s_0) is formed)
+    expm_apply(1.0 - kGLx[0], s2, fp);
+    expm_apply(-kGLx[0], w, lp);
     for (int q = 0; q < kVqeNodes; ++q) {
-      const double s = kGLx[q], wt = kGLw[q];
-      for (int e = threadIdx.x; e < D; e += kVqeBlock) s2[e] = e == 0 ? 1.0 : 0.0;
-      __syncthreads();
-      expm_apply(1.0 - s, s2, phi);
-      expm_apply(-s, w, lam);
-      // phase 1: X_p = E_AI phi, Y_p = E_IA lam
-      for (int p1 = 0; p1 < NT1; ++p1) {
+      if (q > 0) {
+        const double ds = kGLx[q] - kGLx[q - 1];
+        expm_apply(-ds, fp, tmp);   // phi(s_q) = e^{-(s_q - s_{q-1}) A} phi(s_{q-1})
+        double* t = fp;
+        fp = tmp;
+        tmp = t;
+        expm_apply(-ds, lp, tmp);
+        t = lp;
+        lp = tmp;
+        tmp = t;
+      }
+      const double wt = 2.0 * kGLw[q];
+      // phase 1: X_p = E_AI phi (setA), Y_p = E_IA lam (setB)
+      for (int r = threadIdx.x; r < NT1 * D; r += kVqeBlock) {
+        const int p1 = r / D, e = r % D;
         const int I = p1 / NV, A = NE + p1 % NV;
-        apply_E(A, I, phi, setA + p1 * D, false);
-        apply_E(I, A, lam, setB + p1 * D, false);
+        setA[r] = e_at(A * NA + I, fp, e / NS, e % NS);
+        setB[r] = e_at(I * NA + A, lp, e / NS, e % NS);
       }
       __syncthreads();
-      // singles, first half: lam . X_p
-      for (int p1 = 0; p1 < NT1; ++p1) {
-        double d = 0.0;
-        for (int e = threadIdx.x; e < D; e += kVqeBlock) d += lam[e] * setA[p1 * D + e];
-        d = vqe_block_sum(d, red);
-        if (threadIdx.x == 0) gr[p1] += 2.0 * wt * d;
-      }
-      set_dots(setB, setA, dots);   // Y_p1 . X_p2
-      for (int k = threadIdx.x; k < NT1 * (NT1 + 1) / 2; k += kVqeBlock) {
-        int a = 0, r = k;
-        while (r >= NT1 - a) {
-          r -= NT1 - a;
-          ++a;
-        }
-        const int b = a + r;
-        const double f = a == b ? 0.5 : 1.0;
-        gr[NT1 + k] += 2.0 * wt * f * dots[a * NT1 + b];
-      }
-      __syncthreads();
-      // phase 2: X'_p = E_IA phi, Y'_p = E_AI lam
-      for (int p1 = 0; p1 < NT1; ++p1) {
+      phase_dots(lp, setA, setB, setA, dots);   // lam.X_p, Y_p1.X_p2
+      phase_add(wt, dots);
+      // phase 2: X'_p = E_IA phi (setA), Y'_p = E_AI lam (setB)
+      for (int r = threadIdx.x; r < NT1 * D; r += kVqeBlock) {
+        const int p1 = r / D, e = r % D;
         const int I = p1 / NV, A = NE + p1 % NV;
-        apply_E(I, A, phi, setA + p1 * D, false);
-        apply_E(A, I, lam, setB + p1 * D, false);
+        setA[r] = e_at(I * NA + A, fp, e / NS, e % NS);
+        setB[r] = e_at(A * NA + I, lp, e / NS, e % NS);
       }
       __syncthreads();
-      for (int p1 = 0; p1 < NT1; ++p1) {
-        double d = 0.0;
-        for (int e = threadIdx.x; e < D; e += kVqeBlock) d += phi[e] * setB[p1 * D + e];
-        d = vqe_block_sum(d, red);
-        if (threadIdx.x == 0) gr[p1] -= 2.0 * wt * d;
-      }
-      set_dots(setA, setB, dots);   // X'_p1 . Y'_p2
-      for (int k = threadIdx.x; k < NT1 * (NT1 + 1) / 2; k += kVqeBlock) {
-        int a = 0, r = k;
-        while (r >= NT1 - a) {
-          r -= NT1 - a;
-          ++a;
-        }
-        const int b = a + r;
-        const double f = a == b ? 0.5 : 1.0;
-        gr[NT1 + k] -= 2.0 * wt * f * dots[a * NT1 + b];
-      }
-      __syncthreads();
+      phase_dots(fp, setB, setA, setB, dots);   // phi.Y'_p, X'_p1.Y'_p2
+      phase_add(-wt, dots);
     }
   }
 };
@@ -319,10 +371,12 @@ __device__ void vqe_space(const VqeArgs& a, int k, const SpaceDev& sp, double* s
   q.yv = q.sv + NP;
   q.th2 = q.yv + NP;
   q.g2 = q.th2 + NP;
-  q.dk = q.g2 + NP;   // NP diagonal, then NT1*NT1 dots
-  cur = q.dk + NP + NT1 * NT1;
+  q.dk = q.g2 + NP;   // NP diagonal, then NT1 + NT1*NT1 dots
+  cur = q.dk + NP + NT1 + NT1 * NT1;
+  q.t2h = cur;        // NT1*NT1
+  cur += NT1 * NT1;
   q.misc = cur;       // 8
-  q.red = cur + 8;
+  q.red = cur + 8;    // 2 per wavefront
   // integrals, string tables
   for (int e = tid; e < N4; e += kVqeBlock) q.g[e] = hin[1 + N2 + e];
   for (int e = tid; e < NS * N2; e += kVqeBlock) q.emap[e] = 0;
