@@ -218,6 +218,8 @@ int qflow_solve_vqe_batch(qflow_ctx* ctx, int32_t K, const qflow_space* spaces,
  * space its own W = [V_N, s]_2 (n^4 doubles, up to 4 GiB of spaces at a time)
  * and [W, s]_2 on the space's orbitals, a cost of order n^4 (o^2 + v^2 + o v)
  * + K n^4 + K na^4 n^2 operations: a path for problems of tens of orbitals.
+ * It takes at most 64 orbitals: QFLOW_E_UNSUPPORTED here (integrals
+ * loaded) or at the first call that would use it (integrals loaded later).
  * Windowed sweeps take QFLOW_TRUNC_F only.  Unknown values are
  * QFLOW_E_INVALID_ARG. */
 enum { QFLOW_TRUNC_F = 0, QFLOW_TRUNC_H = 1 };

@@ -288,16 +288,23 @@ int upload_spaces(qflow_ctx* ctx, int32_t K, const qflow_space* spaces) {
   return ensure_zc(ctx);   // outside any graph capture
 }
 
+// The next truncation's direct evaluation costs O(K n^4) per step.
+constexpr int kTruncHMaxOrb = 64;
+
 // Buffers of the next truncation for the uploaded list (outside any capture):
 // Wg, W of up to vd_batch spaces at once (at most 4 GiB), the extra terms.
 int ensure_vdouble(qflow_ctx* ctx, int32_t K, int64_t xtra_doubles) {
   if (ctx->trunc != QFLOW_TRUNC_H) return QFLOW_OK;
+  if (ctx->n > kTruncHMaxOrb)
+    return fail(ctx, QFLOW_E_UNSUPPORTED, "QFLOW_TRUNC_H takes at most 64 orbitals");
   const size_t wn = qf::vd_space_doubles(ctx->n);
   const size_t cap = (size_t)4 << 30;
   ctx->vd_batch = (int)std::max<size_t>(1, std::min<size_t>(std::max(K, 1), cap / (wn * 8)));
   QF_TRY(ensure(ctx, ctx->vd_wg, sizeof(double) * wn));
-  QF_TRY(ensure(ctx, ctx->vd_wsp, sizeof(double) * wn * ctx->vd_batch));
-  QF_TRY(ensure(ctx, ctx->vd_xtra, sizeof(double) * std::max<int64_t>(xtra_doubles, 1)));
+  if (K > 0) {
+    QF_TRY(ensure(ctx, ctx->vd_wsp, sizeof(double) * wn * ctx->vd_batch));
+    QF_TRY(ensure(ctx, ctx->vd_xtra, sizeof(double) * std::max<int64_t>(xtra_doubles, 1)));
+  }
   return QFLOW_OK;
 }
 
@@ -1599,6 +1606,8 @@ int qflow_set_truncation(qflow_ctx* ctx, int truncation) {
   if (!ctx) return QFLOW_E_INVALID_ARG;
   if (truncation != QFLOW_TRUNC_F && truncation != QFLOW_TRUNC_H)
     return fail(ctx, QFLOW_E_INVALID_ARG, "unknown truncation");
+  if (truncation == QFLOW_TRUNC_H && ctx->loaded && ctx->n > kTruncHMaxOrb)
+    return fail(ctx, QFLOW_E_UNSUPPORTED, "QFLOW_TRUNC_H takes at most 64 orbitals");
   ctx->trunc = truncation;
   ++ctx->epoch;   // a captured step follows the truncation
   return QFLOW_OK;

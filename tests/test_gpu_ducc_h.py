@@ -161,3 +161,28 @@ def test_truncation_setting_errors_and_default():
     ctx.residual(dev(tt1), dev(tt2), r1, r2, one)
     R1, R2, _ = qflow.residual(qflow.Problem(h, eri, o), tt1, tt2)
     assert np.abs(host(r2) - R2).max() < 1e-11
+
+
+def test_truncation_h_refuses_more_than_64_orbitals():
+    """The direct evaluation costs O(K n^4): beyond 64 orbitals it is refused,
+    at the setting (integrals loaded) or at the first call that would use it."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    n, o = 65, 2
+    h, eri = synth.gen_integrals(n, o, 2 * n, 841)
+    ctx = qf.Context(0)
+    ctx.set_truncation(qf.TRUNC_H)          # nothing loaded yet: accepted
+    ctx.load_integrals(dev(h), dev(eri), o)
+    v = n - o
+    r1 = torch.zeros(o, v, dtype=torch.float64, device="cuda")
+    r2 = torch.zeros(o, o, v, v, dtype=torch.float64, device="cuda")
+    e0 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t1, t2 = dev(np.zeros((o, v))), dev(np.zeros((o, o, v, v)))
+    with pytest.raises(qf.QFlowError) as e:
+        ctx.residual(t1, t2, r1, r2, e0)
+    assert e.value.code == -8
+    ctx.set_truncation(qf.TRUNC_F)
+    with pytest.raises(qf.QFlowError) as e:
+        ctx.set_truncation(qf.TRUNC_H)
+    assert e.value.code == -8
+    ctx.residual(t1, t2, r1, r2, e0)        # DUCC(2F) still works
