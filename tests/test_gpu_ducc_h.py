@@ -186,3 +186,32 @@ def test_truncation_h_refuses_more_than_64_orbitals():
         ctx.set_truncation(qf.TRUNC_H)
     assert e.value.code == -8
     ctx.residual(t1, t2, r1, r2, e0)        # DUCC(2F) still works
+
+
+def test_vqe_flow_with_v_double_commutator_matches_oracle():
+    """Both next rows at once: UCCSD-VQE solves of H_eff with the new term,
+    two macro-iterations over (2,2) spaces of 8 orbitals from MP2, against the
+    oracle's VQE flow with truncation H (energies 1e-10 Eh, pool 1e-7: the
+    solvers meet at a gradient below 1e-10)."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    from oracle import vqe
+    n, o = 8, 3
+    h, eri, pb, ctx = _setup(n, o, 851)
+    v = n - o
+    S = sampling.algorithm1(o, v, 2, 2, pb.eps, synth.Stream(853), cap=6)
+    lists = [(tuple(s[0]), tuple(s[1])) for s in S]
+    o1, o2 = sampling.ownership(o, v, lists)
+    t1, t2 = qflow.mp2_guess(pb.f, eri, o)
+    sp = qf.make_spaces(lists)
+    g1, g2 = dev(t1), dev(t2)
+    energy = torch.zeros(len(lists), dtype=torch.float64, device="cuda")
+    d1, d2 = dev(o1, torch.int32), dev(o2, torch.int32)
+    for it in range(2):
+        em, _ = ctx.flow_step(sp, d1, d2, g1, g2, energy, qf.FP64 | qf.SOLVER_VQE)
+        t1, t2, E, Em, _ = vqe.flow_step(pb, t1, t2, lists, o1, o2)
+        assert np.all(ctx.last_solve(len(lists))[1] == 0), it
+        assert abs(em - Em) < 1e-10, it
+        assert np.abs(host(energy) - E).max() < 1e-10, it
+        assert np.abs(host(g1) - t1).max() < 1e-7, it
+        assert np.abs(host(g2) - t2).max() < 1e-7, it
