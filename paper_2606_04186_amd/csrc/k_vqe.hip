@@ -79,23 +79,6 @@ __device__ double vqe_block_max(double x, double* red) {
   return s;
 }
 
-// (max a, max b) over the workgroup, one pair of barriers
-__device__ void vqe_block_max2(double& a, double& b, double* red) {
-  a = wave_max(a);
-  b = wave_max(b);
-  if (threadIdx.x % 64 == 0) {
-    red[2 * (threadIdx.x / 64)] = a;
-    red[2 * (threadIdx.x / 64) + 1] = b;
-  }
-  __syncthreads();
-  a = b = 0.0;
-  for (int w = 0; w < kVqeBlock / 64; ++w) {
-    a = fmax(a, red[2 * w]);
-    b = fmax(b, red[2 * w + 1]);
-  }
-  __syncthreads();
-}
-
 template <int NA, int NE>
 struct VqeSpace {
   using S_ = VqeShape<NA, NE>;
@@ -130,15 +113,6 @@ struct VqeSpace {
     return x;
   }
 
-  // theta1[ia] v[f] + 1/2 sum_jb theta2[ia][jb] set_jb[f]
-  __device__ double s_val(int ia, const double* v, const double* set, int f) const {
-    double x = th[ia] * v[f];
-    const double* tr = t2h + ia * NT1;
-#pragma unroll
-    for (int jb = 0; jb < NT1; ++jb) x += tr[jb] * set[jb * D + f];
-    return x;
-  }
-
   // 1/2 theta2 as a full NT1 x NT1 table; after every change of th
   __device__ void prep_theta() {
     for (int q = threadIdx.x; q < NT1 * NT1; q += kVqeBlock) t2h[q] = 0.5 * t2(q / NT1, q % NT1);
@@ -146,33 +120,65 @@ struct VqeSpace {
   }
 
   // out = x A v with A = T - T^dag of the parameters th:
-  //   T v     = sum_IA E_AI (theta1 v + 1/2 sum_JB theta2 E_BJ v),
-  //   T^dag v = sum_IA E_IA (theta1 v + 1/2 sum_JB theta2 E_JB v)
-  // (E_AI and E_BJ commute, as do E_IA and E_JB).  The NT1 vectors E_BJ v
-  // go to setA, E_JB v to setB; each output then gathers its sources
-  // directly: two barriers in all.  out distinct from v, setA, setB.
-  __device__ void apply_A(double x, const double* v, double* out) {
-    for (int q = threadIdx.x; q < NT1 * D; q += kVqeBlock) {
-      const int jb = q / D, e = q % D;
-      const int J = jb / NV, B = NE + jb % NV;
-      setA[q] = e_at(B * NA + J, v, e / NS, e % NS);
-      setB[q] = e_at(J * NA + B, v, e / NS, e % NS);
+  //   T v     = sum_IA E_AI S_IA,  S_IA = theta1 v + 1/2 sum_JB theta2 E_BJ v,
+  //   T^dag v = sum_IA E_IA R_IA,  R_IA = theta1 v + 1/2 sum_JB theta2 E_JB v
+  // (E_AI and E_BJ commute, as do E_IA and E_JB).  Each thread forms, for
+  // its entry f, every E_BJ v and E_JB v at f and accumulates S_IA[f] and
+  // R_IA[f] in registers (written to setA, setB); after one barrier each
+  // output gathers its sources from those: two barriers in all, and few LDS
+  // reads per product.  With y given, also y += out and, per wavefront,
+  // (max |out|, max |y|) into slot[2 w], slot[2 w + 1] (visible after the
+  // closing barrier).  out distinct from v, setA, setB.
+  __device__ void apply_A(double x, const double* v, double* out, double* y = nullptr,
+                          double* slot = nullptr) {
+    for (int f = threadIdx.x; f < D; f += kVqeBlock) {
+      const int fa = f / NS, fb = f % NS;
+      const double vf = v[f];
+      double sx[NT1], rx[NT1];
+#pragma unroll
+      for (int ia = 0; ia < NT1; ++ia) sx[ia] = rx[ia] = th[ia] * vf;
+#pragma unroll 1
+      for (int jb = 0; jb < NT1; ++jb) {
+        const int J = jb / NV, B = NE + jb % NV;
+        const double u = e_at(B * NA + J, v, fa, fb);
+        const double l = e_at(J * NA + B, v, fa, fb);
+#pragma unroll
+        for (int ia = 0; ia < NT1; ++ia) {
+          const double c = t2h[ia * NT1 + jb];
+          sx[ia] += c * u;
+          rx[ia] += c * l;
+        }
+      }
+#pragma unroll
+      for (int ia = 0; ia < NT1; ++ia) {
+        setA[ia * D + f] = sx[ia];
+        setB[ia * D + f] = rx[ia];
+      }
     }
     __syncthreads();
+    double tm = 0.0, ym = 0.0;
     for (int e = threadIdx.x; e < D; e += kVqeBlock) {
       const int ja = e / NS, jb2 = e % NS;
       double acc = 0.0;
+#pragma unroll 1
       for (int ia = 0; ia < NT1; ++ia) {
         const int I = ia / NV, A = NE + ia % NV;
-        int sa = emap[ja * N2 + A * NA + I], sb = emap[jb2 * N2 + A * NA + I];
-        if (sa != 0) acc += (sa > 0 ? 1.0 : -1.0) * s_val(ia, v, setA, (abs(sa) - 1) * NS + jb2);
-        if (sb != 0) acc += (sb > 0 ? 1.0 : -1.0) * s_val(ia, v, setA, ja * NS + (abs(sb) - 1));
-        sa = emap[ja * N2 + I * NA + A];
-        sb = emap[jb2 * N2 + I * NA + A];
-        if (sa != 0) acc -= (sa > 0 ? 1.0 : -1.0) * s_val(ia, v, setB, (abs(sa) - 1) * NS + jb2);
-        if (sb != 0) acc -= (sb > 0 ? 1.0 : -1.0) * s_val(ia, v, setB, ja * NS + (abs(sb) - 1));
+        acc += e_at(A * NA + I, setA + ia * D, ja, jb2) - e_at(I * NA + A, setB + ia * D, ja, jb2);
       }
       out[e] = x * acc;
+      if (y) {
+        y[e] += x * acc;
+        tm = fmax(tm, fabs(x * acc));
+        ym = fmax(ym, fabs(y[e]));
+      }
+    }
+    if (y) {
+      tm = wave_max(tm);
+      ym = wave_max(ym);
+      if (threadIdx.x % 64 == 0) {
+        slot[2 * (threadIdx.x / 64)] = tm;
+        slot[2 * (threadIdx.x / 64) + 1] = ym;
+      }
     }
     __syncthreads();
   }
@@ -183,25 +189,31 @@ struct VqeSpace {
     return th[NT1 + a * NT1 - a * (a - 1) / 2 + (b - a)];
   }
 
-  // y = e^{xA} v (Taylor series); term in s0, product in s1
+  // y = e^{xA} v (Taylor series, terms up to the first one below 1e-17 of
+  // the sum).  Term n = (x/n) A term(n-1) is formed by one product whose
+  // output loop also adds it to y and takes the stopping test's maxima, so
+  // each term costs the product's two barriers; terms alternate between s0
+  // and s1.
   __device__ void expm_apply(double x, const double* v, double* y) {
+    constexpr int NW = kVqeBlock / 64;
     for (int e = threadIdx.x; e < D; e += kVqeBlock) {
       y[e] = v[e];
       s0[e] = v[e];
     }
     __syncthreads();
+    double* a = s0;
+    double* b = s1;
     for (int n = 1; n <= 60; ++n) {
-      apply_A(x, s0, s1);
+      apply_A(x / n, a, b, y, red);
       double tm = 0.0, ym = 0.0;
-      for (int e = threadIdx.x; e < D; e += kVqeBlock) {
-        const double t = s1[e] / n;
-        s0[e] = t;
-        y[e] += t;
-        tm = fmax(tm, fabs(t));
-        ym = fmax(ym, fabs(y[e]));
+      for (int w_ = 0; w_ < NW; ++w_) {
+        tm = fmax(tm, red[2 * w_]);
+        ym = fmax(ym, red[2 * w_ + 1]);
       }
-      vqe_block_max2(tm, ym, red);
       if (tm <= 1e-17 * ym) break;
+      double* t = a;   // (the next product writes red only after its first barrier)
+      a = b;
+      b = t;
     }
   }
 
