@@ -54,9 +54,9 @@ struct VqeShape {
   // LDS doubles: g, Hs, string tables (ints), vectors, BFGS state, scratch
   static constexpr int NVEC = 4 + 2 * NT1 + 4;   // psi, w, phi, lam, 2 NT1 sets, 4 scratch
   // ... BFGS (NP^2 + 8 NP), dot products (NT1 + NT1^2), 1/2 theta2 table
-  // (NT1^2), misc (8), reduction slots (2 per wavefront)
+  // (NT1^2), reduction slots (2 per wavefront)
   static constexpr int LDS = N4 + NS * HS + (NS * N2 + NS * NR + 1) / 2 + NVEC * D +
-                             NP * NP + 8 * NP + NT1 + 2 * NT1 * NT1 + 8 + 2 * (kVqeBlock / 64);
+                             NP * NP + 8 * NP + NT1 + 2 * NT1 * NT1 + 2 * (kVqeBlock / 64);
 };
 
 __device__ double vqe_block_sum(double x, double* red) {
@@ -89,7 +89,7 @@ struct VqeSpace {
   double *g, *Hs, *red;
   int *emap, *rep;
   double *psi, *w, *phi, *lam, *setA, *setB, *s0, *s1, *s2, *s3;
-  double *Hinv, *th, *gr, *p, *sv, *yv, *th2, *g2, *dk, *misc, *t2h;
+  double *Hinv, *th, *gr, *p, *sv, *yv, *th2, *g2, *dk, *t2h;
 
   // (E_PQ v)(Ia, Ib) for spin-summed E_PQ, P,Q local orbitals; out = or += (acc)
   __device__ void apply_E(int P, int Q, const double* v, double* out, bool acc) const {
@@ -387,8 +387,7 @@ __device__ void vqe_space(const VqeArgs& a, int k, const SpaceDev& sp, double* s
   cur = q.dk + NP + NT1 + NT1 * NT1;
   q.t2h = cur;        // NT1*NT1
   cur += NT1 * NT1;
-  q.misc = cur;       // 8
-  q.red = cur + 8;    // 2 per wavefront
+  q.red = cur;        // 2 per wavefront
   // integrals, string tables
   for (int e = tid; e < N4; e += kVqeBlock) q.g[e] = hin[1 + N2 + e];
   for (int e = tid; e < NS * N2; e += kVqeBlock) q.emap[e] = 0;
