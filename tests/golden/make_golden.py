@@ -1,6 +1,6 @@
 """Write the oracle's expected values for the larger workloads.
 
-    python tests/golden/make_golden.py c2|c3|c4|vqe [--workers W]
+    python tests/golden/make_golden.py c2|c3|c4|vqe|vqe_c4 [--workers W]
 
 Calls only ``oracle`` (the plain FP64 CPU implementation) and ``synth`` (the
 seeded inputs); nothing here comes from the HIP path.  The active spaces are
@@ -28,6 +28,8 @@ amplitudes no space owns.
   each), and batch solves of the spaces from the pool's own amplitudes
   (16 orbitals) and from zero (24 orbitals) with their energies and
   parameters.
+* vqe_c4 (114 orbitals, K = 4096): the first VQE macro-iteration from MP2 on
+  four sampled spaces (their energies and optimised parameters).
 
 Sampled spaces: 16 positions evenly spread over the Delta-eps order, the
 first replaced where needed so that the sample holds a space with the first
@@ -218,9 +220,32 @@ def make_vqe():
     np.savez_compressed(os.path.join(HERE, "qflow_vqe.npz"), **out)
 
 
+def make_vqe_c4(workers):
+    """The 114-orbital workload's first VQE macro-iteration from MP2 on four
+    sampled spaces (first, last, and two spread over the Delta-eps order, one
+    holding orbital 113): their VQE energies and optimised parameters."""
+    pb, spaces, o1, o2, t1, t2, orbs = workload("c4")
+    n, o, K = pb.n, pb.o, len(spaces)
+    pos = [0, K // 3, 2 * K // 3, K - 1]
+    if not any((n - 1) in spaces[k][1] for k in pos):
+        pos[2] = next(k for k in range(K) if (n - 1) in spaces[k][1] and k not in pos)
+    pos = sorted(set(pos))
+    t0 = time.time()
+    E, amp = [], []
+    for k in pos:
+        occ, vir = spaces[k]
+        sol = vqe.solve_space(pb, t1, t2, tuple(occ) + tuple(vir), len(occ))
+        E.append(sol["E"])
+        amp.append(np.concatenate([sol["t1"].ravel(), sol["t2"].ravel()]))
+        print(f"c4 vqe space {k}: E {sol['E']:.12f} ({time.time() - t0:.1f} s)", flush=True)
+    np.savez_compressed(os.path.join(HERE, "qflow_c4_vqe_first_step.npz"), orbs=orbs,
+                        samp=np.array(pos, dtype=np.int32), e_samp=np.array(E),
+                        amp_samp=np.array(amp))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["c2", "c3", "c4", "vqe"])
+    ap.add_argument("config", choices=["c2", "c3", "c4", "vqe", "vqe_c4"])
     ap.add_argument("--workers", type=int, default=os.cpu_count())
     ap.add_argument("--full", action="store_true",
                     help="c4: take the whole first iteration and the sampled second")
@@ -229,6 +254,8 @@ def main():
         make_c2(a.workers)
     elif a.config == "vqe":
         make_vqe()
+    elif a.config == "vqe_c4":
+        make_vqe_c4(a.workers)
     elif a.config == "c3":
         make_two_steps("c3", a.workers, True)
     else:

@@ -232,3 +232,37 @@ def test_hundred_fourteen_orbitals_sampled_spaces_match_oracle():
         assert owned > 0
         assert np.abs(T2[blk][un2] - ref_step).max() < tol_u
         print(f"114 orbitals, {prec}: {owned} owned amplitudes, {un2.sum()} unowned doubles")
+
+
+@pytest.mark.timeout(600)
+def test_hundred_fourteen_orbitals_vqe_sampled_spaces_match_oracle():
+    """The UCCSD-VQE solver at full size: the first VQE macro-iteration of the
+    114-orbital workload (K = 4096) from MP2, FP64 and the BF16x3 graph
+    configuration, against the oracle's VQE solutions of four sampled spaces
+    (orbital 113 among them): energies (FP64 1e-9 Eh, BF16x3 1e-6) and owned
+    amplitudes (1e-7: the solvers meet at a gradient below 1e-10; BF16x3
+    1e-6)."""
+    _need_gpu()
+    import paper_2606_04186_amd as qf
+    gold = _gold("qflow_c4_vqe_first_step.npz")
+    ctx, keep, spaces, o1, o2, (n, o, v, K) = _setup("c4", gold)
+    d1, d2 = torch.from_numpy(o1).cuda(), torch.from_numpy(o2).cuda()
+    samp = gold["samp"]
+    assert gold["orbs"][samp].max() == n - 1
+    for prec, flag, tol_e, tol_t in (("fp64", qf.FP64, 1e-9, 1e-7),
+                                     ("bf16x3", qf.BF16X3 | qf.GRAPH, 1e-6, 1e-6)):
+        t1, t2 = _pool(ctx, o, v)
+        energy = torch.zeros(K, dtype=torch.float64, device="cuda")
+        ctx.flow_step(spaces, d1, d2, t1, t2, energy, flag | qf.SOLVER_VQE)
+        _, st = ctx.last_solve(K)
+        assert np.all(st == 0), prec
+        E, T1, T2 = energy.cpu().numpy(), t1.cpu().numpy(), t2.cpu().numpy()
+        dE = np.abs(E[samp] - gold["e_samp"]).max()
+        print(f"114 orbitals, VQE, {prec}: sampled spaces max |dE| {dE:.2e} Eh")
+        assert dE < tol_e
+        owned = 0
+        for m, k in enumerate(samp):
+            a = gold["amp_samp"][m]
+            owned += _owned_check(gold["orbs"][k], k, a[:9].reshape(3, 3),
+                                  a[9:].reshape(3, 3, 3, 3), o1, o2, T1, T2, o, tol_t)
+        assert owned > 0
