@@ -415,7 +415,7 @@ def step_roofline(n, o, class_counts, precision, iters):
 
 
 def cpu_baseline(h, eri, o, spaces, m, K, config):
-    """The oracle on the GPU machine's host cores, on bounded samples.
+    """The oracle on the host cores of the machine, on bounded samples.
 
     * The reported workload: the full per-space work (downfolded Hamiltonian,
       CAS eigenproblem, cluster analysis) of the first m spaces, scaled by K,
